@@ -1,0 +1,168 @@
+"""Seeded synthetic camera data for the SDA fingerprint path.
+
+Frames follow the sensor output model of Sec. II-A, Eq. (1): the recorded
+image is the clean scene plus the scene modulated by the multiplicative PRNU
+factor K plus additive noise, then rounded (half to even) and clipped to the
+8-bit range.  Nothing here denoises, averages or correlates: this module only
+makes inputs.  It is shared by the tests, the benchmark and the CPU oracle's
+callers, and it contains none of the fingerprint method's arithmetic.
+
+Streams: every draw comes from ``numpy.random.Generator(Philox)`` keyed by a
+master seed and a tuple of integers (config, camera, frame, ...), so any
+frame of any synthetic camera can be regenerated on its own.
+
+The device variant (``video_frames_torch``) draws its noise with torch's
+generator on the GPU; it follows the same recipe but not the same random
+stream, and callers that need an oracle result on it read its frames back.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+MASTER_SEED = 190904573
+
+# Config ids used as the first stream key.
+CFG_TINY, CFG_VIDEO, CFG_BATCH, CFG_DIFF, CFG_STILL, CFG_TEST = 0, 1, 2, 3, 4, 99
+
+
+def rng(*keys: int) -> np.random.Generator:
+    """Independent generator for the stream named by ``keys``."""
+    ss = np.random.SeedSequence([MASTER_SEED, *[int(k) & 0xFFFFFFFF for k in keys]])
+    return np.random.Generator(np.random.Philox(ss))
+
+
+def gaussian_blur(x: np.ndarray, sigma: float) -> np.ndarray:
+    """Gaussian low-pass of a 2-D field (reflect boundary, 4-sigma support)."""
+    from scipy.ndimage import gaussian_filter
+
+    return gaussian_filter(x, sigma=sigma, mode="reflect", truncate=4.0)
+
+
+def camera_prnu(shape, std: float, *keys: int) -> np.ndarray:
+    """PRNU factor K ~ N(0, std^2), one value per sensor element (and channel)."""
+    return rng(*keys).normal(0.0, std, size=shape)
+
+
+def flat_scene(H: int, W: int, g: np.random.Generator, sigma: float = 8.0) -> np.ndarray:
+    """Uniform[40,220] field blurred with sigma px: a nearly flat scene (std ~2 DN)."""
+    return gaussian_blur(g.uniform(40.0, 220.0, size=(H, W)), sigma)
+
+
+def stretch(x: np.ndarray, lo: float = 40.0, hi: float = 220.0) -> np.ndarray:
+    """Affine re-stretch of a field to [lo, hi]."""
+    mn, mx = float(x.min()), float(x.max())
+    if mx <= mn:
+        return np.full_like(x, 0.5 * (lo + hi))
+    return lo + (hi - lo) * (x - mn) / (mx - mn)
+
+
+def textured_scene(H: int, W: int, g: np.random.Generator, sigma: float = 8.0) -> np.ndarray:
+    """Blurred uniform field re-stretched to [40,220]: a textured scene."""
+    return stretch(flat_scene(H, W, g, sigma))
+
+
+def quantize_u8(x: np.ndarray) -> np.ndarray:
+    """Round half to even, clip to [0,255], store as uint8."""
+    return np.clip(np.rint(x), 0, 255).astype(np.uint8)
+
+
+def sensor_frame(I0: np.ndarray, K: np.ndarray, noise_std: float, g: np.random.Generator,
+                 quantize: bool = True) -> np.ndarray:
+    """I = I0 + I0*K + psi with psi ~ N(0, noise_std^2) (Sec. II-A, Eq. (1))."""
+    I = I0 * (1.0 + K) + g.normal(0.0, noise_std, size=I0.shape)
+    return quantize_u8(I) if quantize else I
+
+
+def tiny_camera(cam: int, n_frames: int, H: int = 256, W: int = 256, k_std: float = 0.02,
+                noise_std: float = 2.0, textured: bool = False, cfg: int = CFG_TINY,
+                first_frame: int = 0):
+    """Grayscale camera of the tiny workload.
+
+    Returns (frames uint8 [n][H][W][1], K float64 [H][W]).  Each frame has a new
+    scene: Uniform[40,220] blurred with sigma = 8 px (flat), or the same field
+    re-stretched to [40,220] (textured variant).
+    """
+    K = camera_prnu((H, W), k_std, cfg, cam, 0xC0FFEE)
+    out = np.empty((n_frames, H, W, 1), np.uint8)
+    for i in range(n_frames):
+        g = rng(cfg, cam, 1 + first_frame + i)
+        I0 = textured_scene(H, W, g) if textured else flat_scene(H, W, g)
+        out[i, :, :, 0] = sensor_frame(I0, K, noise_std, g)
+    return out, K
+
+
+def video_texture(H: int, W: int, C: int, *keys: int) -> np.ndarray:
+    """Per-camera base texture, twice the frame size, per channel: U[0,1] blurred
+    with sigma = 2 px and stretched to [40,220].  Shape [2H][2W][C]."""
+    g = rng(*keys)
+    tex = np.empty((2 * H, 2 * W, C))
+    for c in range(C):
+        tex[:, :, c] = stretch(gaussian_blur(g.uniform(0.0, 1.0, size=(2 * H, 2 * W)), 2.0))
+    return tex
+
+
+def crop_walk(n: int, H: int, W: int, g: np.random.Generator, step: float = 3.0):
+    """Random-walk integer crop offsets inside a [2H][2W] texture."""
+    y, x = H // 2, W // 2
+    offs = np.empty((n, 2), np.int64)
+    for i in range(n):
+        y = int(np.clip(round(y + g.normal(0.0, step)), 0, H))
+        x = int(np.clip(round(x + g.normal(0.0, step)), 0, W))
+        offs[i] = (y, x)
+    return offs
+
+
+def video_camera(cam: int, n_frames: int, H: int, W: int, C: int = 3, k_std: float = 0.01,
+                 noise_std: float = 2.0, cfg: int = CFG_VIDEO, first_frame: int = 0):
+    """Video-shaped camera: frames are random-walk crops of a per-camera texture
+    with a per-frame brightness jitter U[0.7,1.3], PRNU and N(0, 2^2) noise.
+
+    Returns (frames uint8 [n][H][W][C], K float64 [H][W][C]).
+    """
+    K = camera_prnu((H, W, C), k_std, cfg, cam, 0xC0FFEE)
+    tex = video_texture(H, W, C, cfg, cam, 0x7E7)
+    offs = crop_walk(first_frame + n_frames, H, W, rng(cfg, cam, 0x3A1C))[first_frame:]
+    out = np.empty((n_frames, H, W, C), np.uint8)
+    for i in range(n_frames):
+        g = rng(cfg, cam, 1 + first_frame + i)
+        b = g.uniform(0.7, 1.3)
+        y, x = offs[i]
+        I0 = b * tex[y:y + H, x:x + W, :]
+        out[i] = sensor_frame(I0, K, noise_std, g)
+    return out, K
+
+
+def video_frames_torch(cam: int, n_frames: int, H: int, W: int, C: int = 3, k_std: float = 0.01,
+                       noise_std: float = 2.0, device="cuda", cfg: int = CFG_VIDEO, out=None,
+                       first_frame: int = 0):
+    """Same recipe as :func:`video_camera`, drawn on the device for large volumes.
+
+    Texture, K, offsets and brightness come from the numpy streams above; the
+    per-pixel noise is drawn with a seeded torch generator on ``device``.
+    Returns a uint8 tensor [n][H][W][C] on ``device`` (written into ``out`` if
+    given) and K as float64 numpy.
+    """
+    import torch
+
+    K = camera_prnu((H, W, C), k_std, cfg, cam, 0xC0FFEE)
+    tex = torch.from_numpy(video_texture(H, W, C, cfg, cam, 0x7E7)).to(device=device, dtype=torch.float32)
+    offs = crop_walk(first_frame + n_frames, H, W, rng(cfg, cam, 0x3A1C))[first_frame:]
+    bright = rng(cfg, cam, 0xB16).uniform(0.7, 1.3, size=first_frame + n_frames)[first_frame:]
+    Kt = torch.from_numpy(K).to(device=device, dtype=torch.float32)
+    gen = torch.Generator(device=device)
+    gen.manual_seed((MASTER_SEED * 1000003 + cfg * 7919 + cam * 104729 + first_frame) % (2**63))
+    if out is None:
+        out = torch.empty((n_frames, H, W, C), dtype=torch.uint8, device=device)
+    noise = torch.empty((H, W, C), dtype=torch.float32, device=device)
+    for i in range(n_frames):
+        y, x = int(offs[i, 0]), int(offs[i, 1])
+        I0 = tex[y:y + H, x:x + W, :] * float(bright[i])
+        noise.normal_(0.0, noise_std, generator=gen)
+        I = I0 * (1.0 + Kt) + noise
+        out[i] = torch.round(I).clamp_(0, 255).to(torch.uint8)
+    return out, K
+
+
+def random_field(shape, *keys: int, std: float = 1.0) -> np.ndarray:
+    """White Gaussian field (for correlation tests)."""
+    return rng(*keys).normal(0.0, std, size=shape)
