@@ -1,0 +1,207 @@
+/*
+ * prnu.h -- C ABI of the MI355X (gfx950) camera-fingerprint library.
+ *
+ * The library computes the fingerprint-extraction path of "Camera Fingerprint
+ * Extraction via Spatial Domain Averaged Frames" (Taspinar, Mohanty, Memon,
+ * arXiv 1909.04573):
+ *
+ *   spatial-domain averaged (SDA) frames            (Sec. III-B, SDA-frame mean)
+ *   -> noise residual W = I - F(I), F a 4-level     (Sec. II-A, Eq. (1) and the
+ *      wavelet denoiser with local Wiener shrinkage  residual definition; Sec. IV
+ *                                                     names the wavelet denoiser)
+ *   -> MLE fingerprint K = sum W*I / sum I^2        (Sec. III-A MLE; Sec. III-B,
+ *                                                     SDA form of the MLE)
+ *   -> zero-mean, luma, DFT-domain Wiener filtering
+ *   -> PCE / NCC of query residuals vs fingerprints (Sec. II-A correlation step;
+ *                                                     Sec. IV, PCE threshold 60)
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Array arguments are DEVICE pointers owned by the caller (row-major,
+ *    planes contiguous).  The library never allocates device memory and keeps
+ *    no device state between calls; every scratch byte comes from the caller's
+ *    workspace `ws` of at least the size the matching *_workspace_size call
+ *    reports.  The workspace must be 256-byte aligned.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  Every
+ *    call only enqueues work on it; results are valid once the stream has
+ *    been synchronised.  Calls on different streams with different
+ *    workspaces may run concurrently.
+ *  - All arguments are checked on the host before anything is enqueued; on
+ *    any error nothing is enqueued and the status says why:
+ *        PRNU_OK             success
+ *        PRNU_E_INVAL        null pointer, bad size, bad mode or flag
+ *        PRNU_E_UNSUPPORTED  valid but not implemented (e.g. FFT size with a
+ *                            prime factor above 5, filter length)
+ *        PRNU_E_WORKSPACE    workspace too small or misaligned
+ *        PRNU_E_HIP          a HIP launch failed (the HIP error string is kept)
+ *    prnu_last_error() returns a thread-local text for the last failure.
+ *  - Frames are stored [n][H][W][C] (C = 1 or 3 channels, interleaved), with
+ *    element type PRNU_U8, PRNU_BF16 or PRNU_F32.  Planar float data is
+ *    [plane][H][W].
+ *  - Readings where the paper is silent: periodised orthonormal Daubechies
+ *    DWT after symmetric padding to a multiple of 16; Wiener windows 3,5,7,9
+ *    with zero extension; the approximation band is kept by F, so the
+ *    residual's approximation band is zero; a last SDA group with fewer than
+ *    `group` frames is averaged over its own count.
+ */
+#ifndef PRNU_H
+#define PRNU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PRNU_OK 0
+#define PRNU_E_INVAL (-1)
+#define PRNU_E_UNSUPPORTED (-2)
+#define PRNU_E_WORKSPACE (-3)
+#define PRNU_E_HIP (-4)
+
+/* frame element types */
+#define PRNU_U8 0
+#define PRNU_BF16 1
+#define PRNU_F32 2
+
+/* MLE accumulator storage (A = sum W*I, B = sum I^2), see
+ * prnu_fingerprint_accumulate */
+#define PRNU_ACC_F64 0       /* double A[C][H][W], double B[C][H][W]          */
+#define PRNU_ACC_KAHAN_F32 1 /* float A[2][C][H][W]: value plane then         */
+                             /* compensation plane (value = [0] + [1]); same B */
+#define PRNU_ACC_F32 2       /* float A[C][H][W], float B[C][H][W]            */
+
+/* post-processing flags (finalize and query residuals) */
+#define PRNU_ZM 1     /* per channel: subtract row means, then column means   */
+#define PRNU_LUMA 2   /* C = 3: combine channels 0.299 R + 0.587 G + 0.114 B  */
+#define PRNU_WIENER 4 /* DFT-domain Wiener filtering of each output plane     */
+
+/* PCE peak location */
+#define PRNU_PEAK_FIXED_00 0 /* aligned verification: peak is C(0,0)          */
+#define PRNU_PEAK_ARGMAX 1   /* shift search: first maximum, row-major order   */
+
+typedef struct prnu_denoise_params {
+    float sigma0;          /* std of the noise the Wiener step assumes (grey levels) */
+    int levels;            /* wavelet levels, 1..4 (padding is always to 16)          */
+    int taps;              /* Daubechies filter length: 8 or 16 ("db8" = 16)          */
+    float level_weight[4]; /* level l (finest = 0) uses noise variance                */
+                           /* level_weight[l] * sigma0^2; all 1 for the plain method */
+} prnu_denoise_params;
+
+typedef struct prnu_pce_params {
+    int peak_mode; /* PRNU_PEAK_FIXED_00 or PRNU_PEAK_ARGMAX                       */
+    int nbhd;      /* odd side of the block around the peak left out of the energy */
+} prnu_pce_params;
+
+/* Text of the last error on this thread ("" if none). */
+const char *prnu_last_error(void);
+/* Library version string. */
+const char *prnu_version(void);
+/* sigma0 = 3, 4 levels, 16 taps, weights 1. */
+void prnu_default_denoise_params(prnu_denoise_params *p);
+
+/* Host-only: the Daubechies low-pass filter the kernels use, h[0..taps-1]
+ * (extremal phase, sum = sqrt(2)), computed by spectral factorisation in long
+ * double.  taps in {2,4,...,20}.  Enqueues nothing. */
+int prnu_filter_coefficients(int taps, double *h);
+
+/* ---------------------------------------------------------------------------
+ * SDA frames (Sec. III-B: the mean of d consecutive frames).
+ *
+ * frames  [n_frames][H][W][C] of `dtype`.
+ * group   d >= 1: group i holds frames i*d .. min((i+1)*d, n_frames) - 1;
+ *         g = ceil(n_frames / d) groups.
+ * sums    PRNU_U8 only (else must be NULL), nullable: uint32 [g][C][H][W],
+ *         exact integer sums (n_frames <= 16843009 so 255*d fits).
+ * means   nullable: float [g][C][H][W] = sum / count, correctly rounded
+ *         (U8: the exact integer sum divided once; BF16/F32: sum in double).
+ * At least one of sums/means must be given.
+ */
+int prnu_sda_average(const void *frames, int dtype, int n_frames, int H, int W, int C, int group,
+                     uint32_t *sums, float *means, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Noise residual W = I - F(I) of float planes (Sec. II-A; denoiser of Sec. IV).
+ *
+ * img    float [n_img][H][W] (grey levels), H, W >= 16.
+ * resid  float [n_img][H][W] output (may not alias img).
+ */
+int prnu_denoise_residual_workspace_size(int n_img, int H, int W, const prnu_denoise_params *p,
+                                         size_t *bytes);
+int prnu_denoise_residual(const float *img, int n_img, int H, int W, const prnu_denoise_params *p,
+                          float *resid, void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Fused SDA -> residual -> MLE accumulation (Sec. III-B: the SDA frames are
+ * denoised and combined with the MLE; group = 1 is the conventional
+ * per-frame estimator of Sec. III-A).
+ *
+ * frames   [n_frames][H][W][C] of `dtype`; SDA groups of `group` frames are
+ *          formed inside this call (the last may be shorter).
+ * A, B     accumulators in the layout of `acc_mode` (see PRNU_ACC_*), per
+ *          channel: A += sum_i W_i * I_i, B += sum_i I_i^2 over this call's SDA
+ *          frames I_i.  The caller zeroes them once; calling again with more
+ *          frames continues the same sums (streaming / resume).
+ */
+int prnu_fingerprint_accumulate_workspace_size(int n_frames, int H, int W, int C, int group,
+                                               const prnu_denoise_params *p, size_t *bytes);
+int prnu_fingerprint_accumulate(const void *frames, int dtype, int n_frames, int H, int W, int C,
+                                int group, const prnu_denoise_params *p, int acc_mode, void *A,
+                                void *B, void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Fingerprint finalisation: K = A / B per channel (0 where B = 0), then the
+ * post-processing `flags` (PRNU_ZM, PRNU_LUMA, PRNU_WIENER) in that order.
+ *
+ * K         float output: [H][W] when C = 1 or PRNU_LUMA is set, else [C][H][W].
+ * sigma_wf  std of the DFT-Wiener noise; < 0 uses the population std of the
+ *           field being filtered.
+ * PRNU_WIENER needs H and W free of prime factors above 5.
+ */
+int prnu_fingerprint_finalize_workspace_size(int C, int H, int W, int flags, size_t *bytes);
+int prnu_fingerprint_finalize(const void *A, const void *B, int acc_mode, int C, int H, int W,
+                              int flags, float sigma_wf, float *K, void *ws, size_t ws_bytes,
+                              void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Query residuals (Sec. II-A: the query's noise residual, to be correlated
+ * with a fingerprint).  Each frame's channels are denoised, then the same
+ * post-processing as prnu_fingerprint_finalize is applied.
+ *
+ * frames  [n][H][W][C] of `dtype`.
+ * Wq      float [n][H][W] (C = 1 or PRNU_LUMA) else [n][C][H][W].
+ * Iq      nullable float [n][H][W]: the frame's luma (C = 3) or plane (C = 1),
+ *         the intensity that modulates the fingerprint in the matched statistic.
+ */
+int prnu_query_residual_workspace_size(int n, int H, int W, int C, const prnu_denoise_params *p,
+                                       int flags, size_t *bytes);
+int prnu_query_residual(const void *frames, int dtype, int n, int H, int W, int C,
+                        const prnu_denoise_params *p, int flags, float *Wq, float *Iq, void *ws,
+                        size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * PCE / NCC matching (Sec. II-A correlation; Sec. IV uses PCE > 60).
+ *
+ * For every pair (q, j):  x = X[q] - mean,  y = Y'[q][j] - mean, where
+ * Y'[q][j] = modulate[q] * Y[j] elementwise when `modulate` is given (the
+ * query intensity times the fingerprint), else Y[j];
+ * C(s) = sum_t x(t + s) y(t) (circular);  peak p per `peak_mode`;
+ * energy = mean of C(s)^2 over the shifts outside the nbhd x nbhd block
+ * centred on p;  pce = sign(C(p)) C(p)^2 / energy;  ncc = C(0) / (|x| |y|).
+ *
+ * X         float [nx][h][w];  Y float [ny][h][w];  modulate nullable [nx][h][w].
+ * pce       double [nx][ny] output;  ncc nullable double [nx][ny];
+ * peak      nullable int32 [nx][ny][2] (row, col) of the peak.
+ * h, w > nbhd, both free of prime factors above 5 (else PRNU_E_UNSUPPORTED).
+ */
+int prnu_pce_match_workspace_size(int nx, int ny, int h, int w, int modulated, size_t *bytes);
+int prnu_pce_match(const float *X, int nx, const float *Y, int ny, int h, int w,
+                   const float *modulate, const prnu_pce_params *pp, double *pce, double *ncc,
+                   int32_t *peak, void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PRNU_H */

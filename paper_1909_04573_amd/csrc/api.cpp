@@ -1,0 +1,592 @@
+// C ABI of the fingerprint library: host-side validation, workspace carving
+// and the launch sequences of every entry point.  Nothing here allocates
+// device memory; every buffer comes from the caller.
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <climits>
+
+#include "internal.h"
+
+namespace prnu {
+
+static thread_local char g_err[512];
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+int fail(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+namespace {
+
+#define PRNU_HIP(expr)                                                                       \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(PRNU_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+    } while (0)
+
+#define PRNU_TRY(expr)                  \
+    do {                                \
+        int rc_ = (expr);               \
+        if (rc_ != PRNU_OK) return rc_; \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int64_t kBatchPixels = 48ll << 20;  // planes x padded pixels per denoise batch
+constexpr int kMaxFramesPerMle = 8;          // SDA frames folded per accumulator update
+constexpr int kMaxDim = 1 << 15;
+
+// Bump allocator over the caller's workspace; with base == nullptr it only
+// measures, so size queries and calls carve identically.
+struct Carver {
+    char *base;
+    size_t off = 0;
+    explicit Carver(void *b) : base(static_cast<char *>(b)) {}
+    template <class T>
+    T *take(size_t count) {
+        off = (off + kAlign - 1) / kAlign * kAlign;
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+int check_ws(const Carver &cv, void *ws, size_t ws_bytes, const char *fn) {
+    if (!ws) return fail(PRNU_E_WORKSPACE, "%s: null workspace", fn);
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign)
+        return fail(PRNU_E_WORKSPACE, "%s: workspace must be %zu-byte aligned", fn, kAlign);
+    if (ws_bytes < cv.off)
+        return fail(PRNU_E_WORKSPACE, "%s: workspace of %zu bytes, %zu needed", fn, ws_bytes, cv.off);
+    return PRNU_OK;
+}
+
+int check_dims(int H, int W, const char *fn) {
+    if (H < 16 || W < 16 || H > kMaxDim || W > kMaxDim)
+        return fail(PRNU_E_INVAL, "%s: H and W must be in [16, %d] (got %d x %d)", fn, kMaxDim, H, W);
+    return PRNU_OK;
+}
+
+int check_frames(const void *frames, int dtype, int n, int C, const char *fn) {
+    if (!frames) return fail(PRNU_E_INVAL, "%s: null frames", fn);
+    if (dtype != PRNU_U8 && dtype != PRNU_BF16 && dtype != PRNU_F32)
+        return fail(PRNU_E_INVAL, "%s: unknown dtype %d", fn, dtype);
+    if (n < 1) return fail(PRNU_E_INVAL, "%s: need at least one frame (got %d)", fn, n);
+    if (C != 1 && C != 3) return fail(PRNU_E_INVAL, "%s: C must be 1 or 3 (got %d)", fn, C);
+    return PRNU_OK;
+}
+
+int check_params(const prnu_denoise_params *p, const char *fn) {
+    if (!p) return fail(PRNU_E_INVAL, "%s: null denoise params", fn);
+    if (!std::isfinite(p->sigma0) || p->sigma0 < 0.f)
+        return fail(PRNU_E_INVAL, "%s: sigma0 must be finite and >= 0", fn);
+    if (p->levels < 1 || p->levels > 4) return fail(PRNU_E_INVAL, "%s: levels must be 1..4", fn);
+    if (p->taps != 8 && p->taps != 16)
+        return fail(PRNU_E_UNSUPPORTED, "%s: taps must be 8 or 16 (got %d)", fn, p->taps);
+    for (int l = 0; l < 4; ++l)
+        if (!std::isfinite(p->level_weight[l]) || p->level_weight[l] < 0.f)
+            return fail(PRNU_E_INVAL, "%s: level_weight must be finite and >= 0", fn);
+    return PRNU_OK;
+}
+
+int check_flags(int flags, const char *fn) {
+    if (flags & ~(PRNU_ZM | PRNU_LUMA | PRNU_WIENER)) return fail(PRNU_E_INVAL, "%s: unknown flags", fn);
+    return PRNU_OK;
+}
+
+size_t elem_bytes(int dtype) { return dtype == PRNU_U8 ? 1 : dtype == PRNU_BF16 ? 2 : 4; }
+
+// ---- the wavelet pyramid of a batch of planes --------------------------------
+struct Pyramid {
+    float *lvl[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+};
+
+void carve_pyramid(Carver &cv, int planes, int H, int W, int levels, Pyramid *py) {
+    const int Hp = padded(H), Wp = padded(W);
+    for (int l = 1; l <= levels; ++l) py->lvl[l] = cv.take<float>((size_t)planes * level_floats(Hp, Wp, l));
+}
+
+int batch_planes(int n, int H, int W) {
+    const int64_t px = (int64_t)padded(H) * padded(W);
+    int64_t nb = kBatchPixels / px;
+    if (nb < 1) nb = 1;
+    if (nb > n) nb = n;
+    return (int)nb;
+}
+
+// Forward levels 1..L (with shrinkage) and inverse levels L..2; the caller
+// runs inverse level 1 with its epilogue.
+int run_pyramid(const Filter &f, const prnu_denoise_params *p, const float *src, int planes, int H,
+                int W, const Pyramid &py, hipStream_t s) {
+    const int Hp = padded(H), Wp = padded(W), L = p->levels;
+    const float s0 = p->sigma0 * p->sigma0;
+    for (int l = 1; l <= L; ++l) {
+        const float s2 = p->level_weight[l - 1] * s0;
+        if (l == 1) {
+            PRNU_HIP(launch_dwt_fwd(p->taps, f, src, (int64_t)H * W, H, W, Hp, Wp, pad_before(H),
+                                    pad_before(W), py.lvl[1], planes, s2, L > 1, s));
+        } else {
+            const int nr = Hp >> (l - 1), nc = Wp >> (l - 1);
+            PRNU_HIP(launch_dwt_fwd(p->taps, f, py.lvl[l - 1], (int64_t)level_floats(Hp, Wp, l - 1), nr,
+                                    nc, nr, nc, 0, 0, py.lvl[l], planes, s2, l < L, s));
+        }
+    }
+    for (int l = L; l >= 2; --l)
+        PRNU_HIP(launch_dwt_inv(p->taps, f, py.lvl[l], Hp >> l, Wp >> l, l == L, planes, INV_PLANE,
+                                py.lvl[l - 1], 0, 0, 0, 0, s));
+    return PRNU_OK;
+}
+
+// ---- post-processing chain (zero-mean, luma, DFT Wiener) --------------------
+struct PostWs {
+    double *zm = nullptr;
+    float *tmp = nullptr;
+    float2 *Z = nullptr, *G = nullptr, *tw_h = nullptr, *tw_w = nullptr;
+    double *var = nullptr, *red = nullptr;
+};
+
+void carve_post(Carver &cv, int C, int H, int W, int flags, PostWs *pw) {
+    const int nout = (C == 3 && (flags & PRNU_LUMA)) ? 1 : C;
+    pw->zm = cv.take<double>(zm_scratch_doubles(C, H, W));
+    if (flags & PRNU_WIENER) {
+        const size_t N = (size_t)H * W;
+        pw->tmp = cv.take<float>((size_t)nout * N);
+        pw->Z = cv.take<float2>((size_t)nout * N);
+        pw->G = cv.take<float2>((size_t)nout * N);
+        pw->tw_h = cv.take<float2>((size_t)H);
+        pw->tw_w = cv.take<float2>((size_t)W);
+        pw->var = cv.take<double>((size_t)nout);
+        pw->red = cv.take<double>(reduce_scratch_doubles(nout, (int64_t)N));
+    }
+}
+
+int check_fft_dims(int H, int W, const char *fn, FftPlan *ph, FftPlan *pw) {
+    if (!make_fft_plan(H, ph) || !make_fft_plan(W, pw))
+        return fail(PRNU_E_UNSUPPORTED, "%s: DFT sizes need prime factors <= 5 and <= 8704 (got %d x %d)",
+                    fn, H, W);
+    return PRNU_OK;
+}
+
+int run_post(const float *in, int C, int H, int W, int flags, float sigma_wf, float *out,
+             const PostWs &pw, bool twiddles_ready, hipStream_t s) {
+    const int nout = (C == 3 && (flags & PRNU_LUMA)) ? 1 : C;
+    const bool wf = (flags & PRNU_WIENER) != 0;
+    float *dst = wf ? pw.tmp : out;
+    PRNU_HIP(launch_zero_mean(in, C, H, W, (flags & PRNU_ZM) != 0, C == 3 && (flags & PRNU_LUMA), dst,
+                              pw.zm, s));
+    if (!wf) return PRNU_OK;
+    FftPlan ph, pwl;
+    PRNU_TRY(check_fft_dims(H, W, "post", &ph, &pwl));
+    const int64_t N = (int64_t)H * W;
+    if (!twiddles_ready) {
+        PRNU_HIP(launch_twiddles(H, pw.tw_h, s));
+        PRNU_HIP(launch_twiddles(W, pw.tw_w, s));
+    }
+    if (sigma_wf < 0.f) PRNU_HIP(launch_plane_variance(dst, nout, N, pw.var, pw.red, s));
+    PRNU_HIP(launch_real_to_complex(dst, nout, N, pw.Z, s));
+    PRNU_HIP(launch_fft2(pw.Z, nout, H, W, ph, pwl, pw.tw_h, pw.tw_w, -1, s));
+    PRNU_HIP(launch_spectral_wiener(pw.Z, nout, H, W, pw.var, sigma_wf < 0.f ? -1.f : sigma_wf * sigma_wf,
+                                    pw.G, s));
+    PRNU_HIP(launch_fft2(pw.G, nout, H, W, ph, pwl, pw.tw_h, pw.tw_w, +1, s));
+    PRNU_HIP(launch_complex_real(pw.G, nout, N, (float)(1.0 / (double)N), out, s));
+    return PRNU_OK;
+}
+
+// ---- entry point plans ---------------------------------------------------
+int plan_denoise(Carver &cv, int n_img, int H, int W, const prnu_denoise_params *p, Pyramid *py,
+                 int *nb) {
+    *nb = batch_planes(n_img, H, W);
+    carve_pyramid(cv, *nb, H, W, p->levels, py);
+    return PRNU_OK;
+}
+
+int frames_per_batch(int g, int H, int W, int C) {
+    const int64_t px = (int64_t)C * padded(H) * padded(W);
+    int64_t nb = kBatchPixels / px;
+    if (nb < 1) nb = 1;
+    if (nb > kMaxFramesPerMle) nb = kMaxFramesPerMle;
+    if (nb > g) nb = g;
+    return (int)nb;
+}
+
+struct AccPlan {
+    int nb;
+    float *means;
+    Pyramid py;
+};
+
+void plan_accumulate(Carver &cv, int n_frames, int H, int W, int C, int group,
+                     const prnu_denoise_params *p, AccPlan *ap) {
+    const int g = (n_frames + group - 1) / group;
+    ap->nb = frames_per_batch(g, H, W, C);
+    ap->means = cv.take<float>((size_t)ap->nb * C * H * W);
+    carve_pyramid(cv, ap->nb * C, H, W, p->levels, &ap->py);
+}
+
+struct QueryPlan {
+    int nb;
+    float *means, *resid;
+    Pyramid py;
+    PostWs post;
+};
+
+void plan_query(Carver &cv, int n, int H, int W, int C, const prnu_denoise_params *p, int flags,
+                QueryPlan *qp) {
+    qp->nb = frames_per_batch(n, H, W, C);
+    qp->means = cv.take<float>((size_t)qp->nb * C * H * W);
+    qp->resid = cv.take<float>((size_t)qp->nb * C * H * W);
+    carve_pyramid(cv, qp->nb * C, H, W, p->levels, &qp->py);
+    carve_post(cv, C, H, W, flags, &qp->post);
+}
+
+constexpr int64_t kPceChunkBytes = 512ll << 20;
+
+struct PcePlan {
+    int P;
+    float2 *tw_h, *tw_w, *Xs, *Ys, *Z;
+    double *xmean, *xn2, *ymean, *yn2, *spart;
+    void *ppart;
+};
+
+void plan_pce(Carver &cv, int nx, int ny, int h, int w, bool modulated, PcePlan *pp) {
+    const int64_t N = (int64_t)h * w;
+    const int64_t npairs = (int64_t)nx * ny;
+    int64_t P = kPceChunkBytes / (N * (int64_t)sizeof(float2));
+    if (P < 1) P = 1;
+    if (P > 64) P = 64;
+    if (P > npairs) P = npairs;
+    pp->P = (int)P;
+    pp->tw_h = cv.take<float2>((size_t)h);
+    pp->tw_w = cv.take<float2>((size_t)w);
+    pp->Xs = cv.take<float2>((size_t)nx * N);
+    pp->Ys = modulated ? nullptr : cv.take<float2>((size_t)ny * N);
+    pp->Z = cv.take<float2>((size_t)P * N);
+    pp->xmean = cv.take<double>((size_t)nx);
+    pp->xn2 = cv.take<double>((size_t)nx);
+    const int ycount = modulated ? (int)P : ny;
+    pp->ymean = cv.take<double>((size_t)ycount);
+    pp->yn2 = cv.take<double>((size_t)ycount);
+    int mx = nx > ny ? nx : ny;
+    if ((int)P > mx) mx = (int)P;
+    pp->spart = cv.take<double>(stats_part_doubles(mx));
+    pp->ppart = cv.take<char>(pce_part_bytes((int)P));
+}
+
+
+}  // namespace
+}  // namespace prnu
+
+using namespace prnu;
+
+extern "C" {
+
+const char *prnu_last_error(void) { return g_err; }
+
+const char *prnu_version(void) { return "prnu-mi355x 0.1 (gfx950)"; }
+
+void prnu_default_denoise_params(prnu_denoise_params *p) {
+    if (!p) return;
+    p->sigma0 = 3.0f;
+    p->levels = 4;
+    p->taps = 16;
+    for (int l = 0; l < 4; ++l) p->level_weight[l] = 1.0f;
+}
+
+int prnu_sda_average(const void *frames, int dtype, int n_frames, int H, int W, int C, int group,
+                     uint32_t *sums, float *means, void *stream) {
+    const char *fn = "prnu_sda_average";
+    set_error("");
+    PRNU_TRY(check_frames(frames, dtype, n_frames, C, fn));
+    if (H < 1 || W < 1 || H > kMaxDim || W > kMaxDim) return fail(PRNU_E_INVAL, "%s: bad H x W", fn);
+    if (group < 1) return fail(PRNU_E_INVAL, "%s: group must be >= 1", fn);
+    if (!sums && !means) return fail(PRNU_E_INVAL, "%s: need sums or means", fn);
+    if (sums && dtype != PRNU_U8) return fail(PRNU_E_INVAL, "%s: integer sums need u8 frames", fn);
+    if (n_frames > 16843009) return fail(PRNU_E_INVAL, "%s: too many frames for u32 sums", fn);
+    const int g = (n_frames + group - 1) / group;
+    PRNU_HIP(launch_sda(frames, dtype, n_frames, H, W, C, group, 0, g, sums, means, (hipStream_t)stream));
+    return PRNU_OK;
+}
+
+int prnu_denoise_residual_workspace_size(int n_img, int H, int W, const prnu_denoise_params *p,
+                                         size_t *bytes) {
+    const char *fn = "prnu_denoise_residual_workspace_size";
+    set_error("");
+    if (!bytes) return fail(PRNU_E_INVAL, "%s: null output", fn);
+    if (n_img < 1) return fail(PRNU_E_INVAL, "%s: n_img must be >= 1", fn);
+    PRNU_TRY(check_dims(H, W, fn));
+    PRNU_TRY(check_params(p, fn));
+    Carver cv(nullptr);
+    Pyramid py;
+    int nb;
+    plan_denoise(cv, n_img, H, W, p, &py, &nb);
+    *bytes = cv.off;
+    return PRNU_OK;
+}
+
+int prnu_denoise_residual(const float *img, int n_img, int H, int W, const prnu_denoise_params *p,
+                          float *resid, void *ws, size_t ws_bytes, void *stream) {
+    const char *fn = "prnu_denoise_residual";
+    set_error("");
+    if (!img || !resid) return fail(PRNU_E_INVAL, "%s: null pointer", fn);
+    if (img == resid) return fail(PRNU_E_INVAL, "%s: resid may not alias img", fn);
+    if (n_img < 1) return fail(PRNU_E_INVAL, "%s: n_img must be >= 1", fn);
+    PRNU_TRY(check_dims(H, W, fn));
+    PRNU_TRY(check_params(p, fn));
+    Carver cv(nullptr);
+    Pyramid py;
+    int nb;
+    plan_denoise(cv, n_img, H, W, p, &py, &nb);
+    PRNU_TRY(check_ws(cv, ws, ws_bytes, fn));
+    Carver real(ws);
+    plan_denoise(real, n_img, H, W, p, &py, &nb);
+    Filter f;
+    make_filter(p->taps, &f);
+    hipStream_t s = (hipStream_t)stream;
+    const int Hp = padded(H), Wp = padded(W);
+    const int64_t plane = (int64_t)H * W;
+    for (int b0 = 0; b0 < n_img; b0 += nb) {
+        const int n = n_img - b0 < nb ? n_img - b0 : nb;
+        PRNU_TRY(run_pyramid(f, p, img + b0 * plane, n, H, W, py, s));
+        PRNU_HIP(launch_dwt_inv(p->taps, f, py.lvl[1], Hp / 2, Wp / 2, p->levels == 1, n, INV_RESID,
+                                resid + b0 * plane, H, W, pad_before(H), pad_before(W), s));
+    }
+    return PRNU_OK;
+}
+
+int prnu_fingerprint_accumulate_workspace_size(int n_frames, int H, int W, int C, int group,
+                                               const prnu_denoise_params *p, size_t *bytes) {
+    const char *fn = "prnu_fingerprint_accumulate_workspace_size";
+    set_error("");
+    if (!bytes) return fail(PRNU_E_INVAL, "%s: null output", fn);
+    if (n_frames < 1 || group < 1) return fail(PRNU_E_INVAL, "%s: n_frames and group must be >= 1", fn);
+    if (C != 1 && C != 3) return fail(PRNU_E_INVAL, "%s: C must be 1 or 3", fn);
+    PRNU_TRY(check_dims(H, W, fn));
+    PRNU_TRY(check_params(p, fn));
+    Carver cv(nullptr);
+    AccPlan ap;
+    plan_accumulate(cv, n_frames, H, W, C, group, p, &ap);
+    *bytes = cv.off;
+    return PRNU_OK;
+}
+
+int prnu_fingerprint_accumulate(const void *frames, int dtype, int n_frames, int H, int W, int C,
+                                int group, const prnu_denoise_params *p, int acc_mode, void *A, void *B,
+                                void *ws, size_t ws_bytes, void *stream) {
+    const char *fn = "prnu_fingerprint_accumulate";
+    set_error("");
+    PRNU_TRY(check_frames(frames, dtype, n_frames, C, fn));
+    PRNU_TRY(check_dims(H, W, fn));
+    PRNU_TRY(check_params(p, fn));
+    if (group < 1) return fail(PRNU_E_INVAL, "%s: group must be >= 1", fn);
+    if (acc_mode != PRNU_ACC_F64 && acc_mode != PRNU_ACC_KAHAN_F32 && acc_mode != PRNU_ACC_F32)
+        return fail(PRNU_E_INVAL, "%s: unknown acc_mode %d", fn, acc_mode);
+    if (!A || !B) return fail(PRNU_E_INVAL, "%s: null accumulator", fn);
+    if (n_frames > 16843009) return fail(PRNU_E_INVAL, "%s: too many frames", fn);
+    Carver cv(nullptr);
+    AccPlan ap;
+    plan_accumulate(cv, n_frames, H, W, C, group, p, &ap);
+    PRNU_TRY(check_ws(cv, ws, ws_bytes, fn));
+    Carver real(ws);
+    plan_accumulate(real, n_frames, H, W, C, group, p, &ap);
+    Filter f;
+    make_filter(p->taps, &f);
+    hipStream_t s = (hipStream_t)stream;
+    const int g = (n_frames + group - 1) / group;
+    const int Hp = padded(H), Wp = padded(W);
+    for (int g0 = 0; g0 < g; g0 += ap.nb) {
+        const int g1 = g0 + ap.nb < g ? g0 + ap.nb : g;
+        const int nb = g1 - g0;
+        PRNU_HIP(launch_sda(frames, dtype, n_frames, H, W, C, group, g0, g1, nullptr, ap.means, s));
+        PRNU_TRY(run_pyramid(f, p, ap.means, nb * C, H, W, ap.py, s));
+        PRNU_HIP(launch_dwt_inv_mle(p->taps, f, ap.py.lvl[1], Hp / 2, Wp / 2, p->levels == 1, nb, C,
+                                    ap.means, H, W, pad_before(H), pad_before(W), acc_mode, A, B, s));
+    }
+    return PRNU_OK;
+}
+
+int prnu_fingerprint_finalize_workspace_size(int C, int H, int W, int flags, size_t *bytes) {
+    const char *fn = "prnu_fingerprint_finalize_workspace_size";
+    set_error("");
+    if (!bytes) return fail(PRNU_E_INVAL, "%s: null output", fn);
+    if (C != 1 && C != 3) return fail(PRNU_E_INVAL, "%s: C must be 1 or 3", fn);
+    if (H < 1 || W < 1 || H > kMaxDim || W > kMaxDim) return fail(PRNU_E_INVAL, "%s: bad H x W", fn);
+    PRNU_TRY(check_flags(flags, fn));
+    Carver cv(nullptr);
+    cv.take<float>((size_t)C * H * W);
+    PostWs pw;
+    carve_post(cv, C, H, W, flags, &pw);
+    *bytes = cv.off;
+    return PRNU_OK;
+}
+
+int prnu_fingerprint_finalize(const void *A, const void *B, int acc_mode, int C, int H, int W, int flags,
+                              float sigma_wf, float *K, void *ws, size_t ws_bytes, void *stream) {
+    const char *fn = "prnu_fingerprint_finalize";
+    set_error("");
+    if (!A || !B || !K) return fail(PRNU_E_INVAL, "%s: null pointer", fn);
+    if (C != 1 && C != 3) return fail(PRNU_E_INVAL, "%s: C must be 1 or 3", fn);
+    if (H < 1 || W < 1 || H > kMaxDim || W > kMaxDim) return fail(PRNU_E_INVAL, "%s: bad H x W", fn);
+    if (acc_mode != PRNU_ACC_F64 && acc_mode != PRNU_ACC_KAHAN_F32 && acc_mode != PRNU_ACC_F32)
+        return fail(PRNU_E_INVAL, "%s: unknown acc_mode %d", fn, acc_mode);
+    PRNU_TRY(check_flags(flags, fn));
+    if (!std::isfinite(sigma_wf)) return fail(PRNU_E_INVAL, "%s: sigma_wf must be finite", fn);
+    if (flags & PRNU_WIENER) {
+        FftPlan a, b;
+        PRNU_TRY(check_fft_dims(H, W, fn, &a, &b));
+    }
+    Carver cv(nullptr);
+    cv.take<float>((size_t)C * H * W);
+    PostWs pw;
+    carve_post(cv, C, H, W, flags, &pw);
+    PRNU_TRY(check_ws(cv, ws, ws_bytes, fn));
+    Carver real(ws);
+    float *Kc = real.take<float>((size_t)C * H * W);
+    carve_post(real, C, H, W, flags, &pw);
+    hipStream_t s = (hipStream_t)stream;
+    PRNU_HIP(launch_ratio(A, B, acc_mode, (int64_t)C * H * W, Kc, s));
+    return run_post(Kc, C, H, W, flags, sigma_wf, K, pw, false, s);
+}
+
+int prnu_query_residual_workspace_size(int n, int H, int W, int C, const prnu_denoise_params *p, int flags,
+                                       size_t *bytes) {
+    const char *fn = "prnu_query_residual_workspace_size";
+    set_error("");
+    if (!bytes) return fail(PRNU_E_INVAL, "%s: null output", fn);
+    if (n < 1) return fail(PRNU_E_INVAL, "%s: n must be >= 1", fn);
+    if (C != 1 && C != 3) return fail(PRNU_E_INVAL, "%s: C must be 1 or 3", fn);
+    PRNU_TRY(check_dims(H, W, fn));
+    PRNU_TRY(check_params(p, fn));
+    PRNU_TRY(check_flags(flags, fn));
+    Carver cv(nullptr);
+    QueryPlan qp;
+    plan_query(cv, n, H, W, C, p, flags, &qp);
+    *bytes = cv.off;
+    return PRNU_OK;
+}
+
+int prnu_query_residual(const void *frames, int dtype, int n, int H, int W, int C,
+                        const prnu_denoise_params *p, int flags, float *Wq, float *Iq, void *ws,
+                        size_t ws_bytes, void *stream) {
+    const char *fn = "prnu_query_residual";
+    set_error("");
+    PRNU_TRY(check_frames(frames, dtype, n, C, fn));
+    PRNU_TRY(check_dims(H, W, fn));
+    PRNU_TRY(check_params(p, fn));
+    PRNU_TRY(check_flags(flags, fn));
+    if (!Wq) return fail(PRNU_E_INVAL, "%s: null Wq", fn);
+    if (flags & PRNU_WIENER) {
+        FftPlan a, b;
+        PRNU_TRY(check_fft_dims(H, W, fn, &a, &b));
+    }
+    Carver cv(nullptr);
+    QueryPlan qp;
+    plan_query(cv, n, H, W, C, p, flags, &qp);
+    PRNU_TRY(check_ws(cv, ws, ws_bytes, fn));
+    Carver real(ws);
+    plan_query(real, n, H, W, C, p, flags, &qp);
+    Filter f;
+    make_filter(p->taps, &f);
+    hipStream_t s = (hipStream_t)stream;
+    const int Hp = padded(H), Wp = padded(W);
+    const int64_t plane = (int64_t)H * W;
+    const int nout = (C == 3 && (flags & PRNU_LUMA)) ? 1 : C;
+    bool tw_ready = false;
+    for (int f0 = 0; f0 < n; f0 += qp.nb) {
+        const int f1 = f0 + qp.nb < n ? f0 + qp.nb : n;
+        const int nb = f1 - f0;
+        PRNU_HIP(launch_sda(frames, dtype, n, H, W, C, 1, f0, f1, nullptr, qp.means, s));
+        PRNU_TRY(run_pyramid(f, p, qp.means, nb * C, H, W, qp.py, s));
+        PRNU_HIP(launch_dwt_inv(p->taps, f, qp.py.lvl[1], Hp / 2, Wp / 2, p->levels == 1, nb * C, INV_RESID,
+                                qp.resid, H, W, pad_before(H), pad_before(W), s));
+        for (int k = 0; k < nb; ++k) {
+            PRNU_TRY(run_post(qp.resid + (int64_t)k * C * plane, C, H, W, flags, -1.f,
+                              Wq + (int64_t)(f0 + k) * nout * plane, qp.post, tw_ready, s));
+            tw_ready = (flags & PRNU_WIENER) != 0;
+        }
+        if (Iq) {
+            const char *fb = static_cast<const char *>(frames) + (size_t)f0 * plane * C * elem_bytes(dtype);
+            PRNU_HIP(launch_luma_frames(fb, dtype, nb, H, W, C, Iq + (int64_t)f0 * plane, s));
+        }
+    }
+    return PRNU_OK;
+}
+
+int prnu_pce_match_workspace_size(int nx, int ny, int h, int w, int modulated, size_t *bytes) {
+    const char *fn = "prnu_pce_match_workspace_size";
+    set_error("");
+    if (!bytes) return fail(PRNU_E_INVAL, "%s: null output", fn);
+    if (nx < 1 || ny < 1 || h < 1 || w < 1) return fail(PRNU_E_INVAL, "%s: bad sizes", fn);
+    if ((int64_t)h * w > (int64_t)INT_MAX) return fail(PRNU_E_INVAL, "%s: surface too large", fn);
+    Carver cv(nullptr);
+    PcePlan pp;
+    plan_pce(cv, nx, ny, h, w, modulated != 0, &pp);
+    *bytes = cv.off;
+    return PRNU_OK;
+}
+
+int prnu_pce_match(const float *X, int nx, const float *Y, int ny, int h, int w, const float *modulate,
+                   const prnu_pce_params *pp_, double *pce, double *ncc, int32_t *peak, void *ws,
+                   size_t ws_bytes, void *stream) {
+    const char *fn = "prnu_pce_match";
+    set_error("");
+    if (!X || !Y || !pce || !pp_) return fail(PRNU_E_INVAL, "%s: null pointer", fn);
+    if (nx < 1 || ny < 1) return fail(PRNU_E_INVAL, "%s: nx and ny must be >= 1", fn);
+    if (pp_->peak_mode != PRNU_PEAK_FIXED_00 && pp_->peak_mode != PRNU_PEAK_ARGMAX)
+        return fail(PRNU_E_INVAL, "%s: unknown peak mode", fn);
+    if (pp_->nbhd < 1 || !(pp_->nbhd & 1)) return fail(PRNU_E_INVAL, "%s: nbhd must be odd and >= 1", fn);
+    if (h <= pp_->nbhd || w <= pp_->nbhd)
+        return fail(PRNU_E_INVAL, "%s: h and w must exceed nbhd (got %d x %d, nbhd %d)", fn, h, w, pp_->nbhd);
+    if ((int64_t)h * w > (int64_t)INT_MAX) return fail(PRNU_E_INVAL, "%s: surface too large", fn);
+    FftPlan ph, pw;
+    PRNU_TRY(check_fft_dims(h, w, fn, &ph, &pw));
+    const bool modulated = modulate != nullptr;
+    Carver cv(nullptr);
+    PcePlan pl;
+    plan_pce(cv, nx, ny, h, w, modulated, &pl);
+    PRNU_TRY(check_ws(cv, ws, ws_bytes, fn));
+    Carver real(ws);
+    plan_pce(real, nx, ny, h, w, modulated, &pl);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t N = (int64_t)h * w;
+    PRNU_HIP(launch_twiddles(h, pl.tw_h, s));
+    PRNU_HIP(launch_twiddles(w, pl.tw_w, s));
+    // query spectra
+    PRNU_HIP(launch_pair_stats(X, nullptr, INT_MAX, 0, nx, N, pl.xmean, pl.xn2, pl.spart, s));
+    PRNU_HIP(launch_pair_center(X, nullptr, INT_MAX, 0, nx, N, pl.xmean, pl.Xs, s));
+    PRNU_HIP(launch_fft2(pl.Xs, nx, h, w, ph, pw, pl.tw_h, pl.tw_w, -1, s));
+    if (!modulated) {
+        PRNU_HIP(launch_pair_stats(Y, nullptr, INT_MAX, 0, ny, N, pl.ymean, pl.yn2, pl.spart, s));
+        PRNU_HIP(launch_pair_center(Y, nullptr, INT_MAX, 0, ny, N, pl.ymean, pl.Ys, s));
+        PRNU_HIP(launch_fft2(pl.Ys, ny, h, w, ph, pw, pl.tw_h, pl.tw_w, -1, s));
+    }
+    const int64_t npairs = (int64_t)nx * ny;
+    for (int64_t p0 = 0; p0 < npairs; p0 += pl.P) {
+        const int n = (int)(npairs - p0 < pl.P ? npairs - p0 : pl.P);
+        if (modulated) {
+            PRNU_HIP(launch_pair_stats(Y, modulate, ny, (int)p0, n, N, pl.ymean, pl.yn2, pl.spart, s));
+            PRNU_HIP(launch_pair_center(Y, modulate, ny, (int)p0, n, N, pl.ymean, pl.Z, s));
+            PRNU_HIP(launch_fft2(pl.Z, n, h, w, ph, pw, pl.tw_h, pl.tw_w, -1, s));
+            PRNU_HIP(launch_cross(pl.Xs, nullptr, ny, (int)p0, n, N, pl.Z, s));
+        } else {
+            PRNU_HIP(launch_cross(pl.Xs, pl.Ys, ny, (int)p0, n, N, pl.Z, s));
+        }
+        PRNU_HIP(launch_fft2(pl.Z, n, h, w, ph, pw, pl.tw_h, pl.tw_w, +1, s));
+        PRNU_HIP(launch_pce_reduce(pl.Z, n, h, w, pp_->nbhd, pp_->peak_mode, pl.xn2, pl.yn2, !modulated, ny,
+                                   (int)p0, pce, ncc, peak, pl.ppart, s));
+    }
+    return PRNU_OK;
+}
+
+}  // extern "C"

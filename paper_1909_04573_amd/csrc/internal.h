@@ -1,0 +1,132 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "prnu.h"
+
+namespace prnu {
+
+// ---- errors ----------------------------------------------------------------
+void set_error(const char *fmt, ...);
+int fail(int code, const char *fmt, ...);
+
+// ---- filters ---------------------------------------------------------------
+constexpr int kMaxTaps = 16;
+// Low-pass h and quadrature-mirror high-pass g = (-1)^k h[L-1-k], rounded to
+// float; passed to kernels by value so the taps live in scalar registers.
+struct Filter {
+    float h[kMaxTaps];
+    float g[kMaxTaps];
+};
+// Daubechies extremal-phase low-pass, long-double spectral factorisation.
+bool daubechies_lowpass(int taps, long double *h);
+bool make_filter(int taps, Filter *f);
+
+// ---- geometry --------------------------------------------------------------
+constexpr int kPadMult = 16;
+inline int pad_before(int n) { return ((kPadMult - n % kPadMult) % kPadMult) / 2; }
+inline int padded(int n) { return n + (kPadMult - n % kPadMult) % kPadMult; }
+
+// Per-level pyramid buffer: [planes][4][hl][wl], subband 0 = approximation
+// (later the partial reconstruction), 1 = lh, 2 = hl, 3 = hh.
+inline size_t level_floats(int Hp, int Wp, int lvl) {
+    return (size_t)4 * (size_t)(Hp >> lvl) * (size_t)(Wp >> lvl);
+}
+
+// ---- kernel launchers (all enqueue on `s`, return the launch status) -------
+// SDA: groups [g0, g1) of `group` frames; outputs indexed from g0.
+hipError_t launch_sda(const void *frames, int dtype, int n_frames, int H, int W, int C, int group,
+                      int g0, int g1, uint32_t *sums, float *means, hipStream_t s);
+
+// Forward level with fused Wiener shrinkage.  src plane p at src + p*src_stride,
+// stored src_rows x src_cols; the level input is the n_r x n_c plane obtained
+// by symmetric padding with (off_r, off_c) samples before (level 1) or the
+// plane itself (off = 0, n = stored size).  out: [planes][4][n_r/2][n_c/2].
+hipError_t launch_dwt_fwd(int taps, const Filter &f, const float *src, int64_t src_stride,
+                          int src_rows, int src_cols, int n_r, int n_c, int off_r, int off_c,
+                          float *out, int planes, float s2, bool write_ll, hipStream_t s);
+
+enum InvEpilogue { INV_PLANE = 0, INV_RESID = 1, INV_MLE = 2 };
+
+// Inverse level: reads lvl = [planes][4][hk][wk] (subband 0 ignored when
+// zero_approx) and writes the 2hk x 2wk plane into
+//   INV_PLANE: out [planes][4][2hk][2wk] subband 0,
+//   INV_RESID: out [planes][H][W] cropped at (off_r, off_c).
+hipError_t launch_dwt_inv(int taps, const Filter &f, const float *lvl, int hk, int wk,
+                          bool zero_approx, int planes, int epi, float *out, int H, int W,
+                          int off_r, int off_c, hipStream_t s);
+
+// Inverse level 1 with the MLE epilogue: planes are [nb][C]; for every channel
+// c and pixel, A[c] += sum_f W_f * I_f and B[c] += sum_f I_f^2 where I_f is
+// means[f][c] ([nb][C][H][W]).
+hipError_t launch_dwt_inv_mle(int taps, const Filter &f, const float *lvl, int hk, int wk,
+                              bool zero_approx, int nb, int C, const float *means, int H, int W,
+                              int off_r, int off_c, int acc_mode, void *A, void *B, hipStream_t s);
+
+// ---- post-processing -------------------------------------------------------
+// K[c] = A[c] / B[c] (0 where B = 0) as float [C][H][W].
+hipError_t launch_ratio(const void *A, const void *B, int acc_mode, int64_t n, float *K,
+                        hipStream_t s);
+// Zero-mean per plane and optional luma.  in: [C][H][W]; out: [1][H][W] with
+// luma else [C][H][W].  rowpart/colpart: double scratch of zm_scratch_doubles.
+size_t zm_scratch_doubles(int C, int H, int W);
+hipError_t launch_zero_mean(const float *in, int C, int H, int W, bool zm, bool luma, float *out,
+                            double *scratch, hipStream_t s);
+// Convert planes [n][H][W] (n planes) u8/bf16/f32 interleaved frames -> luma.
+hipError_t launch_luma_frames(const void *frames, int dtype, int n, int H, int W, int C,
+                              float *out, hipStream_t s);
+
+// ---- FFT -------------------------------------------------------------------
+struct FftPlan {
+    int n;            // length
+    int nrad;         // number of passes
+    int rad[16];      // radices, each in {2,3,4,5}
+    int nvec;         // vectors per workgroup
+};
+bool make_fft_plan(int n, FftPlan *p);
+size_t fft_twiddle_floats(int n);  // complex table of n entries, 2 floats each
+hipError_t launch_twiddles(int n, float2 *tw, hipStream_t s);
+// In-place 2-D complex FFT on `batch` planes [h][w] (plane stride h*w).
+// dir = -1 forward, +1 inverse (unnormalised).
+hipError_t launch_fft2(float2 *data, int batch, int h, int w, const FftPlan &ph,
+                       const FftPlan &pw, const float2 *tw_h, const float2 *tw_w, int dir,
+                       hipStream_t s);
+
+// ---- reductions and Wiener in the DFT domain --------------------------------
+// Per-plane population variance of float planes [n][N] -> double var[n];
+// scratch: reduce_scratch_doubles(n, N).
+size_t reduce_scratch_doubles(int n, int64_t N);
+hipError_t launch_plane_variance(const float *x, int n, int64_t N, double *var, double *scratch,
+                                 hipStream_t s);
+// Real planes [n][h][w] -> complex [n][h][w] (imaginary part 0).
+hipError_t launch_real_to_complex(const float *x, int n, int64_t N, float2 *z, hipStream_t s);
+// G = F * rho with rho the Wiener residual factor of |F|/sqrt(hw); noise
+// variance var[p] (per plane, device) or sigma2 >= 0 (host constant).
+hipError_t launch_spectral_wiener(const float2 *F, int n, int h, int w, const double *var,
+                                  float sigma2, float2 *G, hipStream_t s);
+// out[p][i] = Re(z[p][i]) * scale
+hipError_t launch_complex_real(const float2 *z, int n, int64_t N, float scale, float *out,
+                               hipStream_t s);
+
+// ---- PCE -------------------------------------------------------------------
+// Chunk plane p (0 <= p < n) is Y[(p0+p) % ny], times mod[(p0+p) / ny] when mod
+// is given.  Plain planes: mod = nullptr and ny > p0 + n.
+size_t pce_part_bytes(int npairs);
+size_t stats_part_doubles(int n);
+hipError_t launch_pair_stats(const float *Y, const float *mod, int ny, int p0, int n, int64_t N,
+                             double *mean, double *nrm2, double *part, hipStream_t s);
+hipError_t launch_pair_center(const float *Y, const float *mod, int ny, int p0, int n, int64_t N,
+                              const double *mean, float2 *z, hipStream_t s);
+// z[p] = Xs[q] * conj(Ycache ? Ycache[j] : z[p]) with q = (p0+p)/ny, j = (p0+p)%ny.
+hipError_t launch_cross(const float2 *Xs, const float2 *Ycache, int ny, int p0, int n, int64_t N,
+                        float2 *z, hipStream_t s);
+// Reduce the n surfaces z[p] (real part = N * C) into pce/ncc/peak[p0 + p].
+hipError_t launch_pce_reduce(const float2 *z, int n, int h, int w, int nbhd, int peak_mode,
+                             const double *xn2, const double *yn2, bool yn2_by_j, int ny, int p0,
+                             double *pce, double *ncc, int32_t *peak, void *part, hipStream_t s);
+
+}  // namespace prnu

@@ -1,0 +1,244 @@
+// NCC / PCE of query residuals against fingerprints (Sec. II-A: the query's
+// residual is correlated with the fingerprint; Sec. IV: PCE above 60 means
+// "same camera").
+//
+// Per pair p = (q, j) of a chunk: y = modulate[q] * Y[j] (or Y[j]) is centred
+// and transformed, its spectrum is multiplied into X^[q] * conj(Y^), and the
+// inverse transform gives N * C(s).  The surface is reduced in two fixed-order
+// stages: per-block partials (sum of C^2 in double, first maximum), then one
+// block per pair adds the partials, subtracts the nbhd x nbhd block around the
+// peak from the energy and forms PCE and NCC.
+
+#include <cfloat>
+#include <climits>
+
+#include "internal.h"
+
+namespace prnu {
+namespace {
+
+constexpr int NT = 256;
+constexpr int RB = 64;  // reduction blocks per plane
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NT / 64; ++k) r += sh[k];
+    __syncthreads();
+    return r;
+}
+
+// plane p of the chunk: y = Y[(p0+p) % ny] times modulate[(p0+p) / ny] if given.
+struct PairSel {
+    const float *Y;
+    const float *mod;
+    int ny;
+    int p0;
+    __device__ __forceinline__ void planes(int64_t N, const float *&y, const float *&m) const {
+        const int pid = p0 + (int)blockIdx.y;
+        y = Y + (int64_t)(pid % ny) * N;
+        m = mod ? mod + (int64_t)(pid / ny) * N : nullptr;
+    }
+};
+
+// pass 0: partial sums of y; pass 1: partial sums of (y - mean)^2
+__global__ __launch_bounds__(NT) void stats_partial(PairSel sel, int64_t N, const double *__restrict__ mean,
+                                                    double *__restrict__ part) {
+    __shared__ double sh[NT / 64];
+    const float *y, *m;
+    sel.planes(N, y, m);
+    const double mu = mean ? mean[blockIdx.y] : 0.0;
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < N; i += (int64_t)RB * NT) {
+        const float v = m ? m[i] * y[i] : y[i];
+        const double d = (double)v - mu;
+        s += mean ? d * d : d;
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.y * RB + blockIdx.x] = s;
+}
+
+__global__ void stats_finish(const double *__restrict__ part, int n, double scale, double *__restrict__ out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    double s = 0.0;
+    for (int k = 0; k < RB; ++k) s += part[(int64_t)p * RB + k];
+    out[p] = s * scale;
+}
+
+__global__ __launch_bounds__(NT) void center_complex(PairSel sel, int64_t N, const double *__restrict__ mean,
+                                                     float2 *__restrict__ z) {
+    const float *y, *m;
+    sel.planes(N, y, m);
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (i >= N) return;
+    const float v = m ? m[i] * y[i] : y[i];
+    z[(int64_t)blockIdx.y * N + i] = make_float2((float)((double)v - mean[blockIdx.y]), 0.f);
+}
+
+// z[p] = X^[q] * conj(S), S = z[p] (in place) or Ycache[j].
+__global__ __launch_bounds__(NT) void cross_spectrum(const float2 *__restrict__ Xs, const float2 *Ycache,
+                                                     int ny, int p0, int64_t N, float2 *z) {
+    const int pid = p0 + (int)blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (i >= N) return;
+    const float2 a = Xs[(int64_t)(pid / ny) * N + i];
+    const float2 b = Ycache ? Ycache[(int64_t)(pid % ny) * N + i] : z[(int64_t)blockIdx.y * N + i];
+    // a * conj(b)
+    z[(int64_t)blockIdx.y * N + i] = make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+
+struct PcePart {
+    double e2;   // sum of v^2
+    float vmax;  // first maximum of v
+    int imax;
+};
+
+__global__ __launch_bounds__(NT) void pce_partial(const float2 *__restrict__ z, int64_t N,
+                                                  PcePart *__restrict__ part) {
+    __shared__ double sh[NT / 64];
+    __shared__ float sv[NT];
+    __shared__ int si[NT];
+    const float2 *zp = z + (int64_t)blockIdx.y * N;
+    double e = 0.0;
+    float best = -FLT_MAX;
+    int bi = INT_MAX;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < N; i += (int64_t)RB * NT) {
+        const float v = zp[i].x;
+        e += (double)v * (double)v;
+        if (v > best || (v == best && (int)i < bi)) {
+            best = v;
+            bi = (int)i;
+        }
+    }
+    sv[threadIdx.x] = best;
+    si[threadIdx.x] = bi;
+    e = block_sum(e, sh);  // contains barriers
+    for (int st = NT / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            const float ov = sv[threadIdx.x + st];
+            const int oi = si[threadIdx.x + st];
+            if (ov > sv[threadIdx.x] || (ov == sv[threadIdx.x] && oi < si[threadIdx.x])) {
+                sv[threadIdx.x] = ov;
+                si[threadIdx.x] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.y * RB + blockIdx.x] = {e, sv[0], si[0]};
+}
+
+__global__ __launch_bounds__(NT) void pce_finish(const float2 *__restrict__ z, int h, int w, int nbhd,
+                                                 int peak_mode, const PcePart *__restrict__ part,
+                                                 const double *__restrict__ xn2, const double *__restrict__ yn2,
+                                                 int yn2_by_j, int ny, int p0, double *__restrict__ pce,
+                                                 double *__restrict__ ncc, int32_t *__restrict__ peak) {
+    __shared__ double sh[NT / 64];
+    __shared__ int s_peak;
+    __shared__ double s_tot;
+    const int p = blockIdx.x;
+    const int pid = p0 + p;
+    const int64_t N = (int64_t)h * w;
+    const float2 *zp = z + (int64_t)p * N;
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        float best = -FLT_MAX;
+        int bi = INT_MAX;
+        for (int k = 0; k < RB; ++k) {
+            const PcePart q = part[(int64_t)p * RB + k];
+            tot += q.e2;
+            if (q.vmax > best || (q.vmax == best && q.imax < bi)) {
+                best = q.vmax;
+                bi = q.imax;
+            }
+        }
+        s_tot = tot;
+        if (bi < 0 || (int64_t)bi >= N) bi = 0;  // no comparable value (e.g. all NaN)
+        s_peak = peak_mode == PRNU_PEAK_ARGMAX ? bi : 0;
+    }
+    __syncthreads();
+    const int pk = s_peak;
+    const int py = pk / w, px = pk - (pk / w) * w;
+    const int r = nbhd / 2;
+    double e = 0.0;
+    for (int t = threadIdx.x; t < nbhd * nbhd; t += NT) {
+        const int dy = t / nbhd - r, dx = t % nbhd - r;
+        const int yy = ((py + dy) % h + h) % h, xx = ((px + dx) % w + w) % w;
+        const double v = zp[(int64_t)yy * w + xx].x;
+        e += v * v;
+    }
+    e = block_sum(e, sh);
+    if (threadIdx.x == 0) {
+        const double invN = 1.0 / (double)N;
+        const double cp = (double)zp[pk].x * invN;
+        const double energy = (s_tot - e) * invN * invN / (double)(N - (int64_t)nbhd * nbhd);
+        const double val = energy > 0.0 ? (cp >= 0.0 ? 1.0 : -1.0) * cp * cp / energy : 0.0;
+        const int q = pid / ny, j = pid % ny;
+        pce[pid] = val;
+        if (ncc) {
+            const double c0 = (double)zp[0].x * invN;
+            const double den = sqrt(xn2[q] * yn2[yn2_by_j ? j : p]);
+            ncc[pid] = den > 0.0 ? c0 / den : 0.0;
+        }
+        if (peak) {
+            peak[2 * (int64_t)pid] = py;
+            peak[2 * (int64_t)pid + 1] = px;
+        }
+    }
+}
+
+inline unsigned blocks(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
+
+}  // namespace
+
+size_t pce_part_bytes(int npairs) { return (size_t)npairs * RB * sizeof(PcePart); }
+size_t stats_part_doubles(int n) { return (size_t)n * RB; }
+
+// Means and centred squared norms of the chunk's planes (pairs p0 .. p0+n-1,
+// or plain planes when mod == nullptr and ny >= p0 + n).
+hipError_t launch_pair_stats(const float *Y, const float *mod, int ny, int p0, int n, int64_t N,
+                             double *mean, double *nrm2, double *part, hipStream_t s) {
+    PairSel sel{Y, mod, ny, p0};
+    dim3 g(RB, (unsigned)n);
+    stats_partial<<<g, NT, 0, s>>>(sel, N, nullptr, part);
+    stats_finish<<<(n + 63) / 64, 64, 0, s>>>(part, n, 1.0 / (double)N, mean);
+    stats_partial<<<g, NT, 0, s>>>(sel, N, mean, part);
+    stats_finish<<<(n + 63) / 64, 64, 0, s>>>(part, n, 1.0, nrm2);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_center(const float *Y, const float *mod, int ny, int p0, int n, int64_t N,
+                              const double *mean, float2 *z, hipStream_t s) {
+    PairSel sel{Y, mod, ny, p0};
+    center_complex<<<dim3(blocks(N), (unsigned)n), NT, 0, s>>>(sel, N, mean, z);
+    return hipGetLastError();
+}
+
+hipError_t launch_cross(const float2 *Xs, const float2 *Ycache, int ny, int p0, int n, int64_t N,
+                        float2 *z, hipStream_t s) {
+    cross_spectrum<<<dim3(blocks(N), (unsigned)n), NT, 0, s>>>(Xs, Ycache, ny, p0, N, z);
+    return hipGetLastError();
+}
+
+hipError_t launch_pce_reduce(const float2 *z, int n, int h, int w, int nbhd, int peak_mode,
+                             const double *xn2, const double *yn2, bool yn2_by_j, int ny, int p0,
+                             double *pce, double *ncc, int32_t *peak, void *part, hipStream_t s) {
+    const int64_t N = (int64_t)h * w;
+    PcePart *pp = static_cast<PcePart *>(part);
+    pce_partial<<<dim3(RB, (unsigned)n), NT, 0, s>>>(z, N, pp);
+    pce_finish<<<(unsigned)n, NT, 0, s>>>(z, h, w, nbhd, peak_mode, pp, xn2, yn2,
+                                                yn2_by_j ? 1 : 0, ny, p0, pce, ncc, peak);
+    return hipGetLastError();
+}
+
+}  // namespace prnu

@@ -1,0 +1,307 @@
+// Fingerprint finalisation kernels: the MLE ratio K = A / B (Sec. III-A/B),
+// per-channel zero-mean (row means, then column means), ITU-R BT.601 luma,
+// per-plane variance, and the DFT-domain Wiener step applied to |F|/sqrt(N).
+//
+// All reductions are two-stage with a fixed order (per-block partials in
+// double, then one block combining them), so results are deterministic.
+
+#include "internal.h"
+#include "wiener_dev.h"
+
+namespace prnu {
+namespace {
+
+constexpr int NT = 256;
+constexpr float kLuma[3] = {0.299f, 0.587f, 0.114f};
+
+__device__ __forceinline__ float bf16f(uint16_t v) { return __uint_as_float((uint32_t)v << 16); }
+
+template <int ACC>
+__global__ __launch_bounds__(NT) void ratio_kernel(const void *__restrict__ Av, const void *__restrict__ Bv,
+                                                   int64_t n, float *__restrict__ K) {
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (i >= n) return;
+    double a, b;
+    if (ACC == PRNU_ACC_F64) {
+        a = static_cast<const double *>(Av)[i];
+        b = static_cast<const double *>(Bv)[i];
+    } else if (ACC == PRNU_ACC_F32) {
+        a = static_cast<const float *>(Av)[i];
+        b = static_cast<const float *>(Bv)[i];
+    } else {  // value + compensation planes
+        const float *A = static_cast<const float *>(Av);
+        const float *B = static_cast<const float *>(Bv);
+        a = (double)A[i] + (double)A[i + n];
+        b = (double)B[i] + (double)B[i + n];
+    }
+    K[i] = b > 0.0 ? (float)(a / b) : 0.f;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Block-wide sum in a fixed order; result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) r += sh[k];
+    __syncthreads();
+    return r;
+}
+
+// Row means: one wave per row of a plane.  rm[c*H + r] = mean of row r.
+__global__ __launch_bounds__(NT) void row_mean_kernel(const float *__restrict__ x, int rows, int W,
+                                                      double *__restrict__ rm) {
+    const int row = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= rows) return;
+    const float *p = x + (int64_t)row * W;
+    double s = 0.0;
+    for (int i = lane; i < W; i += 64) s += (double)p[i];
+    s = wave_sum(s);
+    if (lane == 0) rm[row] = s / (double)W;
+}
+
+// Column partial sums over chunks of RCH rows: colpart[c][chunk][col].
+constexpr int RCH = 64;
+__global__ __launch_bounds__(NT) void col_part_kernel(const float *__restrict__ x, int H, int W,
+                                                      double *__restrict__ colpart) {
+    const int col = blockIdx.x * NT + threadIdx.x;
+    const int chunk = blockIdx.y, c = blockIdx.z;
+    if (col >= W) return;
+    const int nch = gridDim.y;
+    const float *p = x + (int64_t)c * H * W;
+    const int r0 = chunk * RCH, r1 = min(H, r0 + RCH);
+    double s = 0.0;
+    for (int r = r0; r < r1; ++r) s += (double)p[(int64_t)r * W + col];
+    colpart[((int64_t)c * nch + chunk) * W + col] = s;
+}
+
+// adj[c][col] = column mean of the plane minus the mean of its row means.
+__global__ __launch_bounds__(NT) void col_finish_kernel(const double *__restrict__ colpart, int nch,
+                                                        const double *__restrict__ rm, int H, int W,
+                                                        double *__restrict__ adj) {
+    __shared__ double sh[NT / 64];
+    __shared__ double mu;
+    const int c = blockIdx.y;
+    double s = 0.0;
+    for (int r = threadIdx.x; r < H; r += NT) s += rm[(int64_t)c * H + r];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) mu = s / (double)H;
+    __syncthreads();
+    const int col = blockIdx.x * NT + threadIdx.x;
+    if (col >= W) return;
+    double t = 0.0;
+    for (int k = 0; k < nch; ++k) t += colpart[((int64_t)c * nch + k) * W + col];
+    adj[(int64_t)c * W + col] = t / (double)H - mu;
+}
+
+// out = x - rm[r] - adj[col] per channel, then luma (optional).
+__global__ __launch_bounds__(NT) void zm_apply_kernel(const float *__restrict__ x, int C, int H, int W,
+                                                      const double *__restrict__ rm,
+                                                      const double *__restrict__ adj, int luma,
+                                                      float *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int64_t N = (int64_t)H * W;
+    if (i >= N) return;
+    const int r = (int)(i / W), col = (int)(i - (int64_t)r * W);
+    if (luma) {
+        double acc = 0.0;
+        for (int c = 0; c < C; ++c) {
+            double v = (double)x[c * N + i];
+            if (rm) v -= rm[(int64_t)c * H + r] + adj[(int64_t)c * W + col];
+            acc += (double)kLuma[c] * v;
+        }
+        out[i] = (float)acc;
+    } else {
+        for (int c = 0; c < C; ++c) {
+            double v = (double)x[c * N + i];
+            if (rm) v -= rm[(int64_t)c * H + r] + adj[(int64_t)c * W + col];
+            out[c * N + i] = (float)v;
+        }
+    }
+}
+
+template <int DT>
+__global__ __launch_bounds__(NT) void luma_frames_kernel(const void *__restrict__ frames, int64_t npx,
+                                                         int C, float *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int f = blockIdx.y;
+    if (i >= npx) return;
+    const int64_t e = ((int64_t)f * npx + i) * C;
+    float v[3];
+    for (int c = 0; c < C; ++c) {
+        if (DT == PRNU_U8) v[c] = (float)static_cast<const uint8_t *>(frames)[e + c];
+        else if (DT == PRNU_BF16) v[c] = bf16f(static_cast<const uint16_t *>(frames)[e + c]);
+        else v[c] = static_cast<const float *>(frames)[e + c];
+    }
+    float r;
+    if (C == 3) r = (float)((double)kLuma[0] * v[0] + (double)kLuma[1] * v[1] + (double)kLuma[2] * v[2]);
+    else r = v[0];
+    out[(int64_t)f * npx + i] = r;
+}
+
+// ---- per-plane sums: partials[p][blk] -------------------------------------
+constexpr int RBLK = 64;  // blocks per plane
+
+__global__ __launch_bounds__(NT) void plane_partial_kernel(const float *__restrict__ x, int64_t N,
+                                                           const double *__restrict__ mean,
+                                                           double *__restrict__ part) {
+    __shared__ double sh[NT / 64];
+    const int p = blockIdx.y;
+    const float *xp = x + (int64_t)p * N;
+    const double mu = mean ? mean[p] : 0.0;
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < N; i += (int64_t)RBLK * NT) {
+        const double v = (double)xp[i] - mu;
+        s += mean ? v * v : v;
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) part[(int64_t)p * RBLK + blockIdx.x] = s;
+}
+
+__global__ void plane_finish_kernel(const double *__restrict__ part, int n, int64_t N,
+                                    double *__restrict__ out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    double s = 0.0;
+    for (int k = 0; k < RBLK; ++k) s += part[(int64_t)p * RBLK + k];
+    out[p] = s / (double)N;
+}
+
+__global__ __launch_bounds__(NT) void r2c_kernel(const float *__restrict__ x, int64_t n,
+                                                 float2 *__restrict__ z) {
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (i < n) z[i] = make_float2(x[i], 0.f);
+}
+
+__global__ __launch_bounds__(NT) void c2r_kernel(const float2 *__restrict__ z, int64_t n, float scale,
+                                                 float *__restrict__ x) {
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (i < n) x[i] = z[i].x * scale;
+}
+
+// DFT-domain Wiener: tile of T x T bins with a 4-bin margin; q = |F|^2 / N
+// (zero outside the array), G = F * rho.
+constexpr int WT = 32, WH = 4, WNC = WT + 2 * WH, WNCS = WNC + 1;
+__global__ __launch_bounds__(NT) void spectral_wiener_kernel(const float2 *__restrict__ F, int h, int w,
+                                                             const double *__restrict__ var,
+                                                             float sigma2, int tiles_c,
+                                                             float2 *__restrict__ G) {
+    __shared__ float q[WNC * WNCS];
+    const int p = blockIdx.y;
+    const int tr = blockIdx.x / tiles_c, tc = blockIdx.x - (blockIdx.x / tiles_c) * tiles_c;
+    const int r0 = tr * WT - WH, c0 = tc * WT - WH;
+    const int64_t N = (int64_t)h * w;
+    const float2 *Fp = F + (int64_t)p * N;
+    float2 *Gp = G + (int64_t)p * N;
+    const float invN = (float)(1.0 / (double)N);
+    for (int e = threadIdx.x; e < WNC * WNC; e += NT) {
+        const int i = e / WNC, j = e - (e / WNC) * WNC;
+        const int gr = r0 + i, gc = c0 + j;
+        float v = 0.f;
+        if (gr >= 0 && gr < h && gc >= 0 && gc < w) {
+            const float2 z = Fp[(int64_t)gr * w + gc];
+            v = (z.x * z.x + z.y * z.y) * invN;
+        }
+        q[i * WNCS + j] = v;
+    }
+    __syncthreads();
+    const float s2 = sigma2 >= 0.f ? sigma2 : (float)var[p];
+    if (threadIdx.x < 2 * WT) {
+        const int half = threadIdx.x / WT, kcl = threadIdx.x & (WT - 1);
+        const int gc = tc * WT + kcl;
+        auto load = [&](int r, int c) { return q[r * WNCS + c]; };
+        auto emit = [&](int ko, float rho) {
+            const int gr = r0 + ko;
+            if (gr < h && gc < w) {
+                const float2 z = Fp[(int64_t)gr * w + gc];
+                Gp[(int64_t)gr * w + gc] = make_float2(z.x * rho, z.y * rho);
+            }
+        };
+        wiener_column<WT / 2>(half * (WT / 2), kcl, s2, load, emit);
+    }
+}
+
+inline unsigned blocks(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
+
+}  // namespace
+
+hipError_t launch_ratio(const void *A, const void *B, int acc_mode, int64_t n, float *K, hipStream_t s) {
+    if (acc_mode == PRNU_ACC_F64) ratio_kernel<PRNU_ACC_F64><<<blocks(n), NT, 0, s>>>(A, B, n, K);
+    else if (acc_mode == PRNU_ACC_F32) ratio_kernel<PRNU_ACC_F32><<<blocks(n), NT, 0, s>>>(A, B, n, K);
+    else ratio_kernel<PRNU_ACC_KAHAN_F32><<<blocks(n), NT, 0, s>>>(A, B, n, K);
+    return hipGetLastError();
+}
+
+size_t zm_scratch_doubles(int C, int H, int W) {
+    const int nch = (H + RCH - 1) / RCH;
+    return (size_t)C * H + (size_t)C * nch * W + (size_t)C * W;
+}
+
+hipError_t launch_zero_mean(const float *in, int C, int H, int W, bool zm, bool luma, float *out,
+                            double *scratch, hipStream_t s) {
+    const int nch = (H + RCH - 1) / RCH;
+    double *rm = scratch;
+    double *colpart = rm + (size_t)C * H;
+    double *adj = colpart + (size_t)C * nch * W;
+    if (zm) {
+        row_mean_kernel<<<(unsigned)((C * H + 3) / 4), NT, 0, s>>>(in, C * H, W, rm);
+        col_part_kernel<<<dim3(blocks(W), nch, C), NT, 0, s>>>(in, H, W, colpart);
+        col_finish_kernel<<<dim3(blocks(W), C), NT, 0, s>>>(colpart, nch, rm, H, W, adj);
+    }
+    zm_apply_kernel<<<blocks((int64_t)H * W), NT, 0, s>>>(in, C, H, W, zm ? rm : nullptr, adj,
+                                                          luma ? 1 : 0, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_luma_frames(const void *frames, int dtype, int n, int H, int W, int C, float *out,
+                              hipStream_t s) {
+    const int64_t npx = (int64_t)H * W;
+    dim3 g(blocks(npx), (unsigned)n);
+    if (dtype == PRNU_U8) luma_frames_kernel<PRNU_U8><<<g, NT, 0, s>>>(frames, npx, C, out);
+    else if (dtype == PRNU_BF16) luma_frames_kernel<PRNU_BF16><<<g, NT, 0, s>>>(frames, npx, C, out);
+    else luma_frames_kernel<PRNU_F32><<<g, NT, 0, s>>>(frames, npx, C, out);
+    return hipGetLastError();
+}
+
+size_t reduce_scratch_doubles(int n, int64_t) { return (size_t)n * RBLK + (size_t)n; }
+
+hipError_t launch_plane_variance(const float *x, int n, int64_t N, double *var, double *scratch,
+                                 hipStream_t s) {
+    double *part = scratch;
+    double *mean = scratch + (size_t)n * RBLK;
+    dim3 g(RBLK, (unsigned)n);
+    plane_partial_kernel<<<g, NT, 0, s>>>(x, N, nullptr, part);
+    plane_finish_kernel<<<(n + 63) / 64, 64, 0, s>>>(part, n, N, mean);
+    plane_partial_kernel<<<g, NT, 0, s>>>(x, N, mean, part);
+    plane_finish_kernel<<<(n + 63) / 64, 64, 0, s>>>(part, n, N, var);
+    return hipGetLastError();
+}
+
+hipError_t launch_real_to_complex(const float *x, int n, int64_t N, float2 *z, hipStream_t s) {
+    r2c_kernel<<<blocks((int64_t)n * N), NT, 0, s>>>(x, (int64_t)n * N, z);
+    return hipGetLastError();
+}
+
+hipError_t launch_complex_real(const float2 *z, int n, int64_t N, float scale, float *out, hipStream_t s) {
+    c2r_kernel<<<blocks((int64_t)n * N), NT, 0, s>>>(z, (int64_t)n * N, scale, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_spectral_wiener(const float2 *F, int n, int h, int w, const double *var, float sigma2,
+                                  float2 *G, hipStream_t s) {
+    const int tr = (h + WT - 1) / WT, tc = (w + WT - 1) / WT;
+    spectral_wiener_kernel<<<dim3((unsigned)(tr * tc), (unsigned)n), NT, 0, s>>>(F, h, w, var, sigma2,
+                                                                                  tc, G);
+    return hipGetLastError();
+}
+
+}  // namespace prnu

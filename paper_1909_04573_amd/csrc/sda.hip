@@ -1,0 +1,141 @@
+// Spatial-domain averaged frames (Sec. III-B): the mean of d consecutive frames.
+//
+// One thread owns 4 consecutive pixels of all C interleaved channels (4*C
+// bytes of a u8 frame: one dword per channel-quad, so a wave reads a
+// contiguous 256*C-byte span per frame) and walks the frames of its group,
+// accumulating exact integer sums (u8) or double sums (bf16/f32).  It writes
+// the de-interleaved planes: the sum (u8 only) and the correctly rounded
+// float mean sum / count.  Grid: x = pixel quads, y = group.
+
+#include <hip/hip_bf16.h>
+
+#include "internal.h"
+
+namespace prnu {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ float bf16_to_float(uint16_t v) {
+    return __uint_as_float((uint32_t)v << 16);
+}
+
+template <int C>
+__global__ __launch_bounds__(kThreads) void sda_u8_quads(const uint8_t *__restrict__ frames,
+                                                         int64_t npx, int n_frames, int group,
+                                                         int g0, uint32_t *__restrict__ sums,
+                                                         float *__restrict__ means) {
+    const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;  // pixel quad
+    if (q * 4 >= npx) return;
+    const int gi = g0 + blockIdx.y;
+    const int f0 = gi * group;
+    const int cnt = min(group, n_frames - f0);
+    uint32_t acc[4 * C];
+#pragma unroll
+    for (int k = 0; k < 4 * C; ++k) acc[k] = 0;
+    const int64_t frame_bytes = npx * C;
+    const uint32_t *base = reinterpret_cast<const uint32_t *>(frames + (int64_t)f0 * frame_bytes) + q * C;
+    const int64_t fstride = frame_bytes / 4;
+    int f = 0;
+    for (; f + 4 <= cnt; f += 4) {
+        uint32_t w[4][C];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int k = 0; k < C; ++k) w[u][k] = __builtin_nontemporal_load(base + (f + u) * fstride + k);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int k = 0; k < C; ++k)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[4 * k + b] += (w[u][k] >> (8 * b)) & 0xFFu;
+    }
+    for (; f < cnt; ++f) {
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            uint32_t w = __builtin_nontemporal_load(base + f * fstride + k);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[4 * k + b] += (w >> (8 * b)) & 0xFFu;
+        }
+    }
+    // byte e = 4k+b of the quad is pixel e / C, channel e % C
+    const int64_t gbase = (int64_t)blockIdx.y * C * npx;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        uint32_t s[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) s[p] = acc[p * C + c];
+        const int64_t o = gbase + (int64_t)c * npx + q * 4;
+        if (sums) *reinterpret_cast<uint4 *>(sums + o) = make_uint4(s[0], s[1], s[2], s[3]);
+        if (means) {
+            const float fc = (float)cnt;
+            *reinterpret_cast<float4 *>(means + o) =
+                make_float4((float)s[0] / fc, (float)s[1] / fc, (float)s[2] / fc, (float)s[3] / fc);
+        }
+    }
+}
+
+// Generic path: one thread per pixel, any layout / alignment / dtype.
+template <int DT>
+__global__ __launch_bounds__(kThreads) void sda_generic(const void *__restrict__ frames, int64_t npx,
+                                                        int C, int n_frames, int group, int g0,
+                                                        uint32_t *__restrict__ sums,
+                                                        float *__restrict__ means) {
+    const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (p >= npx) return;
+    const int gi = g0 + blockIdx.y;
+    const int f0 = gi * group;
+    const int cnt = min(group, n_frames - f0);
+    const int64_t gbase = (int64_t)blockIdx.y * C * npx;
+    for (int c = 0; c < C; ++c) {
+        if (DT == PRNU_U8) {
+            const uint8_t *fr = static_cast<const uint8_t *>(frames);
+            uint32_t s = 0;
+            for (int f = 0; f < cnt; ++f) s += fr[((int64_t)(f0 + f) * npx + p) * C + c];
+            if (sums) sums[gbase + (int64_t)c * npx + p] = s;
+            if (means) means[gbase + (int64_t)c * npx + p] = (float)s / (float)cnt;
+        } else {
+            double s = 0.0;
+            for (int f = 0; f < cnt; ++f) {
+                const int64_t e = ((int64_t)(f0 + f) * npx + p) * C + c;
+                if (DT == PRNU_BF16)
+                    s += (double)bf16_to_float(static_cast<const uint16_t *>(frames)[e]);
+                else
+                    s += (double)static_cast<const float *>(frames)[e];
+            }
+            if (means) means[gbase + (int64_t)c * npx + p] = (float)(s / (double)cnt);
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_sda(const void *frames, int dtype, int n_frames, int H, int W, int C, int group,
+                      int g0, int g1, uint32_t *sums, float *means, hipStream_t s) {
+    const int64_t npx = (int64_t)H * W;
+    const int ng = g1 - g0;
+    if (ng <= 0) return hipSuccess;
+    const bool quad_ok = dtype == PRNU_U8 && (npx % 4) == 0 &&
+                         (reinterpret_cast<uintptr_t>(frames) % 4) == 0 &&
+                         (sums == nullptr || reinterpret_cast<uintptr_t>(sums) % 16 == 0) &&
+                         (means == nullptr || reinterpret_cast<uintptr_t>(means) % 16 == 0);
+    if (quad_ok && (C == 1 || C == 3)) {
+        dim3 grid((unsigned)((npx / 4 + kThreads - 1) / kThreads), (unsigned)ng);
+        const uint8_t *fr = static_cast<const uint8_t *>(frames);
+        if (C == 1)
+            sda_u8_quads<1><<<grid, kThreads, 0, s>>>(fr, npx, n_frames, group, g0, sums, means);
+        else
+            sda_u8_quads<3><<<grid, kThreads, 0, s>>>(fr, npx, n_frames, group, g0, sums, means);
+    } else {
+        dim3 grid((unsigned)((npx + kThreads - 1) / kThreads), (unsigned)ng);
+        if (dtype == PRNU_U8)
+            sda_generic<PRNU_U8><<<grid, kThreads, 0, s>>>(frames, npx, C, n_frames, group, g0, sums, means);
+        else if (dtype == PRNU_BF16)
+            sda_generic<PRNU_BF16><<<grid, kThreads, 0, s>>>(frames, npx, C, n_frames, group, g0, sums, means);
+        else
+            sda_generic<PRNU_F32><<<grid, kThreads, 0, s>>>(frames, npx, C, n_frames, group, g0, sums, means);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace prnu

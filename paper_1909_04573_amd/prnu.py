@@ -1,0 +1,280 @@
+"""Python binding of libprnu.so (ctypes; argument marshalling only).
+
+Every function passes device pointers of torch tensors, the current HIP
+stream and a workspace tensor to the C ABI declared in include/prnu.h; all
+computation happens in the library's HIP kernels.  The library must have been
+built (``python -m paper_1909_04573_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libprnu.so")
+
+PRNU_OK, PRNU_E_INVAL, PRNU_E_UNSUPPORTED, PRNU_E_WORKSPACE, PRNU_E_HIP = 0, -1, -2, -3, -4
+U8, BF16, F32 = 0, 1, 2
+ACC_F64, ACC_KAHAN_F32, ACC_F32 = 0, 1, 2
+ZM, LUMA, WIENER = 1, 2, 4
+PEAK_FIXED_00, PEAK_ARGMAX = 0, 1
+
+_DT = {torch.uint8: U8, torch.bfloat16: BF16, torch.float32: F32}
+
+# Every symbol the header declares (checked by the CPU test suite).
+EXPORTS = (
+    "prnu_last_error", "prnu_version", "prnu_default_denoise_params", "prnu_filter_coefficients",
+    "prnu_sda_average",
+    "prnu_denoise_residual_workspace_size", "prnu_denoise_residual",
+    "prnu_fingerprint_accumulate_workspace_size", "prnu_fingerprint_accumulate",
+    "prnu_fingerprint_finalize_workspace_size", "prnu_fingerprint_finalize",
+    "prnu_query_residual_workspace_size", "prnu_query_residual",
+    "prnu_pce_match_workspace_size", "prnu_pce_match",
+)
+
+
+class PrnuError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libprnu error {code}: {msg}")
+        self.code = code
+
+
+class DenoiseParams(ctypes.Structure):
+    _fields_ = [("sigma0", ctypes.c_float), ("levels", ctypes.c_int), ("taps", ctypes.c_int),
+                ("level_weight", ctypes.c_float * 4)]
+
+
+class PceParams(ctypes.Structure):
+    _fields_ = [("peak_mode", ctypes.c_int), ("nbhd", ctypes.c_int)]
+
+
+_lib = None
+_P, _I, _F, _S = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_size_t
+_DP = ctypes.POINTER(DenoiseParams)
+
+
+def lib() -> ctypes.CDLL:
+    """Load libprnu.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1909_04573_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    L.prnu_last_error.restype = ctypes.c_char_p
+    L.prnu_version.restype = ctypes.c_char_p
+    L.prnu_default_denoise_params.argtypes = [_DP]
+    L.prnu_filter_coefficients.argtypes = [_I, ctypes.POINTER(ctypes.c_double)]
+    L.prnu_sda_average.argtypes = [_P, _I, _I, _I, _I, _I, _I, _P, _P, _P]
+    L.prnu_denoise_residual_workspace_size.argtypes = [_I, _I, _I, _DP, ctypes.POINTER(_S)]
+    L.prnu_denoise_residual.argtypes = [_P, _I, _I, _I, _DP, _P, _P, _S, _P]
+    L.prnu_fingerprint_accumulate_workspace_size.argtypes = [_I, _I, _I, _I, _I, _DP, ctypes.POINTER(_S)]
+    L.prnu_fingerprint_accumulate.argtypes = [_P, _I, _I, _I, _I, _I, _I, _DP, _I, _P, _P, _P, _S, _P]
+    L.prnu_fingerprint_finalize_workspace_size.argtypes = [_I, _I, _I, _I, ctypes.POINTER(_S)]
+    L.prnu_fingerprint_finalize.argtypes = [_P, _P, _I, _I, _I, _I, _I, _F, _P, _P, _S, _P]
+    L.prnu_query_residual_workspace_size.argtypes = [_I, _I, _I, _I, _DP, _I, ctypes.POINTER(_S)]
+    L.prnu_query_residual.argtypes = [_P, _I, _I, _I, _I, _I, _DP, _I, _P, _P, _P, _S, _P]
+    L.prnu_pce_match_workspace_size.argtypes = [_I, _I, _I, _I, _I, ctypes.POINTER(_S)]
+    L.prnu_pce_match.argtypes = [_P, _I, _P, _I, _I, _I, _P, ctypes.POINTER(PceParams), _P, _P, _P, _P,
+                                 _S, _P]
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != PRNU_OK:
+        raise PrnuError(rc, lib().prnu_last_error().decode())
+
+
+def denoise_params(sigma0: float = 3.0, levels: int = 4, taps: int = 16, level_weight=(1, 1, 1, 1)):
+    p = DenoiseParams()
+    p.sigma0, p.levels, p.taps = float(sigma0), int(levels), int(taps)
+    for i in range(4):
+        p.level_weight[i] = float(level_weight[i])
+    return p
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(dev):
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _cuda(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _frames(frames: torch.Tensor):
+    _cuda(frames, "frames")
+    if frames.dtype not in _DT:
+        raise ValueError("frames must be uint8, bfloat16 or float32")
+    if frames.dim() == 3:
+        frames = frames.unsqueeze(-1)
+    if frames.dim() != 4:
+        raise ValueError("frames must be [n][H][W] or [n][H][W][C]")
+    n, H, W, C = frames.shape
+    return frames, _DT[frames.dtype], n, H, W, C
+
+
+def workspace(nbytes: int, device) -> torch.Tensor:
+    ws = torch.empty(max(int(nbytes), 256) + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + max(int(nbytes), 256)]
+
+
+def version() -> str:
+    return lib().prnu_version().decode()
+
+
+def filter_coefficients(taps: int):
+    """Host-side Daubechies low-pass filter used by the kernels (float64 list)."""
+    buf = (ctypes.c_double * taps)()
+    _check(lib().prnu_filter_coefficients(taps, buf))
+    return list(buf)
+
+
+def sda_average(frames: torch.Tensor, group: int, want_sums: bool = True, want_means: bool = True):
+    """SDA frames: returns (sums int64 [g][C][H][W] or None, means f32 [g][C][H][W] or None)."""
+    frames, dt, n, H, W, C = _frames(frames)
+    g = (n + group - 1) // group
+    dev = frames.device
+    sums = torch.empty((g, C, H, W), dtype=torch.int32, device=dev) if want_sums and dt == U8 else None
+    means = torch.empty((g, C, H, W), dtype=torch.float32, device=dev) if want_means else None
+    _check(lib().prnu_sda_average(_ptr(frames), dt, n, H, W, C, int(group), _ptr(sums), _ptr(means),
+                                  _stream(dev)))
+    if sums is not None:
+        sums = sums.to(torch.int64) & 0xFFFFFFFF
+    return sums, means
+
+
+def denoise_residual(img: torch.Tensor, params: DenoiseParams | None = None) -> torch.Tensor:
+    """W = I - F(I) of float planes [n][H][W] (or [H][W])."""
+    _cuda(img, "img")
+    if img.dtype != torch.float32:
+        raise ValueError("img must be float32")
+    squeeze = img.dim() == 2
+    x = img.unsqueeze(0) if squeeze else img
+    n, H, W = x.shape
+    p = params or denoise_params()
+    nbytes = _S()
+    _check(lib().prnu_denoise_residual_workspace_size(n, H, W, ctypes.byref(p), ctypes.byref(nbytes)))
+    ws = workspace(nbytes.value, x.device)
+    out = torch.empty_like(x)
+    _check(lib().prnu_denoise_residual(_ptr(x), n, H, W, ctypes.byref(p), _ptr(out), _ptr(ws),
+                                       ws.numel(), _stream(x.device)))
+    return out[0] if squeeze else out
+
+
+def new_accumulators(C: int, H: int, W: int, acc_mode: int = ACC_F64, device="cuda"):
+    """Zeroed (A, B) accumulators in the layout of ``acc_mode``."""
+    if acc_mode == ACC_F64:
+        shape, dt = (C, H, W), torch.float64
+    elif acc_mode == ACC_KAHAN_F32:
+        shape, dt = (2, C, H, W), torch.float32
+    else:
+        shape, dt = (C, H, W), torch.float32
+    return torch.zeros(shape, dtype=dt, device=device), torch.zeros(shape, dtype=dt, device=device)
+
+
+def fingerprint_accumulate(frames: torch.Tensor, group: int, A: torch.Tensor, B: torch.Tensor,
+                           params: DenoiseParams | None = None, acc_mode: int = ACC_F64,
+                           ws: torch.Tensor | None = None):
+    """A += sum W*I, B += sum I^2 over the SDA frames of ``frames`` (in place)."""
+    frames, dt, n, H, W, C = _frames(frames)
+    _cuda(A, "A")
+    _cuda(B, "B")
+    p = params or denoise_params()
+    nbytes = _S()
+    _check(lib().prnu_fingerprint_accumulate_workspace_size(n, H, W, C, int(group), ctypes.byref(p),
+                                                            ctypes.byref(nbytes)))
+    if ws is None or ws.numel() < nbytes.value:
+        ws = workspace(nbytes.value, frames.device)
+    _check(lib().prnu_fingerprint_accumulate(_ptr(frames), dt, n, H, W, C, int(group), ctypes.byref(p),
+                                             int(acc_mode), _ptr(A), _ptr(B), _ptr(ws), ws.numel(),
+                                             _stream(frames.device)))
+    return A, B
+
+
+def fingerprint_accumulate_workspace_size(n, H, W, C, group, params: DenoiseParams | None = None) -> int:
+    p = params or denoise_params()
+    nbytes = _S()
+    _check(lib().prnu_fingerprint_accumulate_workspace_size(n, H, W, C, int(group), ctypes.byref(p),
+                                                            ctypes.byref(nbytes)))
+    return nbytes.value
+
+
+def fingerprint_finalize(A: torch.Tensor, B: torch.Tensor, acc_mode: int = ACC_F64,
+                         flags: int = ZM | LUMA | WIENER, sigma_wf: float = -1.0) -> torch.Tensor:
+    """K = A/B then zero-mean / luma / DFT Wiener per ``flags``."""
+    _cuda(A, "A")
+    _cuda(B, "B")
+    shape = A.shape[-3:]
+    C, H, W = int(shape[0]), int(shape[1]), int(shape[2])
+    nbytes = _S()
+    _check(lib().prnu_fingerprint_finalize_workspace_size(C, H, W, int(flags), ctypes.byref(nbytes)))
+    ws = workspace(nbytes.value, A.device)
+    nout = 1 if (C == 3 and flags & LUMA) else C
+    K = torch.empty((nout, H, W) if nout > 1 else (H, W), dtype=torch.float32, device=A.device)
+    _check(lib().prnu_fingerprint_finalize(_ptr(A), _ptr(B), int(acc_mode), C, H, W, int(flags),
+                                           float(sigma_wf), _ptr(K), _ptr(ws), ws.numel(), _stream(A.device)))
+    return K
+
+
+def query_residual(frames: torch.Tensor, params: DenoiseParams | None = None,
+                   flags: int = ZM | LUMA | WIENER, want_intensity: bool = True):
+    """Residuals of query frames, post-processed like fingerprints; and their luma."""
+    frames, dt, n, H, W, C = _frames(frames)
+    p = params or denoise_params()
+    nbytes = _S()
+    _check(lib().prnu_query_residual_workspace_size(n, H, W, C, ctypes.byref(p), int(flags),
+                                                    ctypes.byref(nbytes)))
+    ws = workspace(nbytes.value, frames.device)
+    nout = 1 if (C == 3 and flags & LUMA) else C
+    Wq = torch.empty((n, nout, H, W) if nout > 1 else (n, H, W), dtype=torch.float32, device=frames.device)
+    Iq = torch.empty((n, H, W), dtype=torch.float32, device=frames.device) if want_intensity else None
+    _check(lib().prnu_query_residual(_ptr(frames), dt, n, H, W, C, ctypes.byref(p), int(flags), _ptr(Wq),
+                                     _ptr(Iq), _ptr(ws), ws.numel(), _stream(frames.device)))
+    return Wq, Iq
+
+
+def pce_match(X: torch.Tensor, Y: torch.Tensor, modulate: torch.Tensor | None = None,
+              peak_mode: int = PEAK_FIXED_00, nbhd: int = 11, want_ncc: bool = True,
+              want_peak: bool = True):
+    """PCE [nx][ny] (float64), NCC and peak (row, col) of every (query, fingerprint) pair."""
+    _cuda(X, "X")
+    _cuda(Y, "Y")
+    if X.dtype != torch.float32 or Y.dtype != torch.float32:
+        raise ValueError("X and Y must be float32")
+    if X.dim() == 2:
+        X = X.unsqueeze(0)
+    if Y.dim() == 2:
+        Y = Y.unsqueeze(0)
+    nx, h, w = X.shape
+    ny = Y.shape[0]
+    if tuple(Y.shape[1:]) != (h, w):
+        raise ValueError("X and Y planes differ in size")
+    if modulate is not None:
+        _cuda(modulate, "modulate")
+        if modulate.dim() == 2:
+            modulate = modulate.unsqueeze(0)
+        if tuple(modulate.shape) != (nx, h, w) or modulate.dtype != torch.float32:
+            raise ValueError("modulate must be float32 [nx][h][w]")
+    nbytes = _S()
+    _check(lib().prnu_pce_match_workspace_size(nx, ny, h, w, int(modulate is not None), ctypes.byref(nbytes)))
+    ws = workspace(nbytes.value, X.device)
+    pp = PceParams(int(peak_mode), int(nbhd))
+    dev = X.device
+    pce = torch.empty((nx, ny), dtype=torch.float64, device=dev)
+    ncc = torch.empty((nx, ny), dtype=torch.float64, device=dev) if want_ncc else None
+    peak = torch.empty((nx, ny, 2), dtype=torch.int32, device=dev) if want_peak else None
+    _check(lib().prnu_pce_match(_ptr(X), nx, _ptr(Y), ny, h, w, _ptr(modulate), ctypes.byref(pp), _ptr(pce),
+                                _ptr(ncc), _ptr(peak), _ptr(ws), ws.numel(), _stream(dev)))
+    return pce, ncc, peak
