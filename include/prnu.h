@@ -200,6 +200,20 @@ int prnu_pce_match(const float *X, int nx, const float *Y, int ny, int h, int w,
                    const float *modulate, const prnu_pce_params *pp, double *pce, double *ncc,
                    int32_t *peak, void *ws, size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Kernel timing (measurement aid, off by default).
+ *
+ * prnu_timing_enable(1) discards earlier records and brackets every later
+ * kernel launch with a pair of HIP events on the launch's stream; (0) stops.
+ * prnu_timing_report() waits for the recorded events and writes one line per
+ * kernel name: "name<TAB>launches<TAB>total_ms<TAB>algorithmic_bytes", where
+ * the bytes are what the algorithm must read once and write once for those
+ * launches.  `needed` (nullable) receives the text size including the NUL;
+ * PRNU_E_INVAL if `len` is too small (the text is truncated).
+ */
+int prnu_timing_enable(int on);
+int prnu_timing_report(char *buf, size_t len, size_t *needed);
+
 #ifdef __cplusplus
 }
 #endif

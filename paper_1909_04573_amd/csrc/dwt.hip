@@ -431,6 +431,9 @@ hipError_t launch_dwt_fwd(int taps, const Filter &f, const float *src, int64_t s
     const int hk = n_r / 2, wk = n_c / 2;
     const int tr = (int)ceil_div(hk, T), tc = (int)ceil_div(wk, T);
     dim3 grid((unsigned)(tr * tc), (unsigned)planes);
+    const double bytes = (double)planes * 4.0 *
+                         ((double)src_rows * src_cols + (write_ll ? 4.0 : 3.0) * (double)hk * wk);
+    KernelTimer kt(taps == 16 ? "dwt_fwd_wiener<16>" : "dwt_fwd_wiener<8>", bytes, s);
     if (taps == 16)
         dwt_fwd_wiener<16><<<grid, NT, 0, s>>>(src, src_stride, src_rows, src_cols, n_r, n_c, off_r,
                                                off_c, out, s2, tc, write_ll ? 1 : 0, f);
@@ -446,6 +449,11 @@ hipError_t launch_dwt_inv(int taps, const Filter &f, const float *lvl, int hk, i
     const int tr = (int)ceil_div(hk, T), tc = (int)ceil_div(wk, T);
     dim3 grid((unsigned)(tr * tc), (unsigned)planes);
     const int za = zero_approx ? 1 : 0;
+    const double outpx = epi == INV_PLANE ? 4.0 * hk * wk : (double)H * W;
+    const double bytes = (double)planes * 4.0 * ((zero_approx ? 3.0 : 4.0) * (double)hk * wk + outpx);
+    static const char *names[2][2] = {{"dwt_inv<8,plane>", "dwt_inv<8,resid>"},
+                                      {"dwt_inv<16,plane>", "dwt_inv<16,resid>"}};
+    KernelTimer kt(names[taps == 16][epi == INV_PLANE ? 0 : 1], bytes, s);
 #define PRNU_INV(TP, EP)                                                                        \
     dwt_inv<TP, EP><<<grid, NT, 0, s>>>(lvl, hk, wk, za, tc, out, H, W, off_r, off_c, f)
     if (taps == 16) {
@@ -463,6 +471,10 @@ hipError_t launch_dwt_inv_mle(int taps, const Filter &f, const float *lvl, int h
     const int tr = (int)ceil_div(hk, T), tc = (int)ceil_div(wk, T);
     dim3 grid((unsigned)(tr * tc), (unsigned)C);
     const int za = zero_approx ? 1 : 0;
+    const double accb = acc_mode == PRNU_ACC_F32 ? 16.0 : 32.0;  // A and B, read + write
+    const double bytes = (double)nb * C * 4.0 * ((zero_approx ? 3.0 : 4.0) * (double)hk * wk + (double)H * W) +
+                         (double)C * H * W * accb;
+    KernelTimer kt(taps == 16 ? "dwt_inv_mle<16>" : "dwt_inv_mle<8>", bytes, s);
 #define PRNU_MLE(TP, AC)                                                                          \
     dwt_inv_mle<TP, AC><<<grid, NT, 0, s>>>(lvl, hk, wk, za, tc, nb, C, means, H, W, off_r, off_c, \
                                             A, B, f)

@@ -200,14 +200,21 @@ hipError_t launch_fft2(float2 *data, int batch, int h, int w, const FftPlan &ph,
                        const float2 *tw_h, const float2 *tw_w, int dir, hipStream_t s) {
     const float sigma = dir < 0 ? -1.f : 1.f;
     const int64_t plane = (int64_t)h * w;
+    const double bytes = 16.0 * (double)batch * plane;  // read + write every complex element
     // rows: h vectors of length w
     dim3 gr((unsigned)((h + pw.nvec - 1) / pw.nvec), (unsigned)batch);
-    fft_1d<<<gr, FNT, 0, s>>>(data, w, h, 1, w, plane, pw, tw_w, sigma);
+    {
+        KernelTimer kt("fft_1d", bytes, s);
+        fft_1d<<<gr, FNT, 0, s>>>(data, w, h, 1, w, plane, pw, tw_w, sigma);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // columns: w vectors of length h
     dim3 gc((unsigned)((w + ph.nvec - 1) / ph.nvec), (unsigned)batch);
-    fft_1d<<<gc, FNT, 0, s>>>(data, h, w, w, 1, plane, ph, tw_h, sigma);
+    {
+        KernelTimer kt("fft_1d", bytes, s);
+        fft_1d<<<gc, FNT, 0, s>>>(data, h, w, w, 1, plane, ph, tw_h, sigma);
+    }
     return hipGetLastError();
 }
 

@@ -14,6 +14,17 @@ namespace prnu {
 void set_error(const char *fmt, ...);
 int fail(int code, const char *fmt, ...);
 
+// ---- optional kernel timing (see prnu_timing_enable) ----------------------
+class KernelTimer {
+   public:
+    KernelTimer(const char *name, double bytes, hipStream_t s);
+    ~KernelTimer();
+
+   private:
+    long idx_;
+    hipStream_t s_;
+};
+
 // ---- filters ---------------------------------------------------------------
 constexpr int kMaxTaps = 16;
 // Low-pass h and quadrature-mirror high-pass g = (-1)^k h[L-1-k], rounded to

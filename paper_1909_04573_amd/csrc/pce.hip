@@ -210,6 +210,7 @@ hipError_t launch_pair_stats(const float *Y, const float *mod, int ny, int p0, i
                              double *mean, double *nrm2, double *part, hipStream_t s) {
     PairSel sel{Y, mod, ny, p0};
     dim3 g(RB, (unsigned)n);
+    KernelTimer kt("pair_stats", 2.0 * (double)n * N * (mod ? 8.0 : 4.0), s);
     stats_partial<<<g, NT, 0, s>>>(sel, N, nullptr, part);
     stats_finish<<<(n + 63) / 64, 64, 0, s>>>(part, n, 1.0 / (double)N, mean);
     stats_partial<<<g, NT, 0, s>>>(sel, N, mean, part);
@@ -220,12 +221,14 @@ hipError_t launch_pair_stats(const float *Y, const float *mod, int ny, int p0, i
 hipError_t launch_pair_center(const float *Y, const float *mod, int ny, int p0, int n, int64_t N,
                               const double *mean, float2 *z, hipStream_t s) {
     PairSel sel{Y, mod, ny, p0};
+    KernelTimer kt("center_complex", (double)n * N * ((mod ? 8.0 : 4.0) + 8.0), s);
     center_complex<<<dim3(blocks(N), (unsigned)n), NT, 0, s>>>(sel, N, mean, z);
     return hipGetLastError();
 }
 
 hipError_t launch_cross(const float2 *Xs, const float2 *Ycache, int ny, int p0, int n, int64_t N,
                         float2 *z, hipStream_t s) {
+    KernelTimer kt("cross_spectrum", (double)n * N * 24.0, s);
     cross_spectrum<<<dim3(blocks(N), (unsigned)n), NT, 0, s>>>(Xs, Ycache, ny, p0, N, z);
     return hipGetLastError();
 }
@@ -235,6 +238,7 @@ hipError_t launch_pce_reduce(const float2 *z, int n, int h, int w, int nbhd, int
                              double *pce, double *ncc, int32_t *peak, void *part, hipStream_t s) {
     const int64_t N = (int64_t)h * w;
     PcePart *pp = static_cast<PcePart *>(part);
+    KernelTimer kt("pce_reduce", (double)n * N * 8.0, s);
     pce_partial<<<dim3(RB, (unsigned)n), NT, 0, s>>>(z, N, pp);
     pce_finish<<<(unsigned)n, NT, 0, s>>>(z, h, w, nbhd, peak_mode, pp, xn2, yn2,
                                                 yn2_by_j ? 1 : 0, ny, p0, pce, ncc, peak);

@@ -235,6 +235,7 @@ inline unsigned blocks(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
 }  // namespace
 
 hipError_t launch_ratio(const void *A, const void *B, int acc_mode, int64_t n, float *K, hipStream_t s) {
+    KernelTimer kt("ratio", (double)n * ((acc_mode == PRNU_ACC_F32 ? 8.0 : 16.0) + 4.0), s);
     if (acc_mode == PRNU_ACC_F64) ratio_kernel<PRNU_ACC_F64><<<blocks(n), NT, 0, s>>>(A, B, n, K);
     else if (acc_mode == PRNU_ACC_F32) ratio_kernel<PRNU_ACC_F32><<<blocks(n), NT, 0, s>>>(A, B, n, K);
     else ratio_kernel<PRNU_ACC_KAHAN_F32><<<blocks(n), NT, 0, s>>>(A, B, n, K);
@@ -252,6 +253,8 @@ hipError_t launch_zero_mean(const float *in, int C, int H, int W, bool zm, bool 
     double *rm = scratch;
     double *colpart = rm + (size_t)C * H;
     double *adj = colpart + (size_t)C * nch * W;
+    const int nout = luma ? 1 : C;
+    KernelTimer kt("zero_mean", (double)H * W * 4.0 * (C * (zm ? 3.0 : 1.0) + nout), s);
     if (zm) {
         row_mean_kernel<<<(unsigned)((C * H + 3) / 4), NT, 0, s>>>(in, C * H, W, rm);
         col_part_kernel<<<dim3(blocks(W), nch, C), NT, 0, s>>>(in, H, W, colpart);
@@ -266,6 +269,7 @@ hipError_t launch_luma_frames(const void *frames, int dtype, int n, int H, int W
                               hipStream_t s) {
     const int64_t npx = (int64_t)H * W;
     dim3 g(blocks(npx), (unsigned)n);
+    KernelTimer kt("luma_frames", (double)n * npx * (C * (dtype == PRNU_U8 ? 1.0 : dtype == PRNU_BF16 ? 2.0 : 4.0) + 4.0), s);
     if (dtype == PRNU_U8) luma_frames_kernel<PRNU_U8><<<g, NT, 0, s>>>(frames, npx, C, out);
     else if (dtype == PRNU_BF16) luma_frames_kernel<PRNU_BF16><<<g, NT, 0, s>>>(frames, npx, C, out);
     else luma_frames_kernel<PRNU_F32><<<g, NT, 0, s>>>(frames, npx, C, out);
@@ -279,6 +283,7 @@ hipError_t launch_plane_variance(const float *x, int n, int64_t N, double *var, 
     double *part = scratch;
     double *mean = scratch + (size_t)n * RBLK;
     dim3 g(RBLK, (unsigned)n);
+    KernelTimer kt("plane_variance", 8.0 * (double)n * N, s);
     plane_partial_kernel<<<g, NT, 0, s>>>(x, N, nullptr, part);
     plane_finish_kernel<<<(n + 63) / 64, 64, 0, s>>>(part, n, N, mean);
     plane_partial_kernel<<<g, NT, 0, s>>>(x, N, mean, part);
@@ -287,11 +292,13 @@ hipError_t launch_plane_variance(const float *x, int n, int64_t N, double *var, 
 }
 
 hipError_t launch_real_to_complex(const float *x, int n, int64_t N, float2 *z, hipStream_t s) {
+    KernelTimer kt("real_to_complex", 12.0 * (double)n * N, s);
     r2c_kernel<<<blocks((int64_t)n * N), NT, 0, s>>>(x, (int64_t)n * N, z);
     return hipGetLastError();
 }
 
 hipError_t launch_complex_real(const float2 *z, int n, int64_t N, float scale, float *out, hipStream_t s) {
+    KernelTimer kt("complex_real", 12.0 * (double)n * N, s);
     c2r_kernel<<<blocks((int64_t)n * N), NT, 0, s>>>(z, (int64_t)n * N, scale, out);
     return hipGetLastError();
 }
@@ -299,6 +306,7 @@ hipError_t launch_complex_real(const float2 *z, int n, int64_t N, float scale, f
 hipError_t launch_spectral_wiener(const float2 *F, int n, int h, int w, const double *var, float sigma2,
                                   float2 *G, hipStream_t s) {
     const int tr = (h + WT - 1) / WT, tc = (w + WT - 1) / WT;
+    KernelTimer kt("spectral_wiener", 16.0 * (double)n * h * w, s);
     spectral_wiener_kernel<<<dim3((unsigned)(tr * tc), (unsigned)n), NT, 0, s>>>(F, h, w, var, sigma2,
                                                                                   tc, G);
     return hipGetLastError();

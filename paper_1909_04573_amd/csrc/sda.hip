@@ -115,6 +115,10 @@ hipError_t launch_sda(const void *frames, int dtype, int n_frames, int H, int W,
     const int64_t npx = (int64_t)H * W;
     const int ng = g1 - g0;
     if (ng <= 0) return hipSuccess;
+    const int64_t nread = (int64_t)min(n_frames, g1 * group) - (int64_t)g0 * group;
+    const double esz = dtype == PRNU_U8 ? 1.0 : dtype == PRNU_BF16 ? 2.0 : 4.0;
+    const double bytes = (double)nread * npx * C * esz +
+                         (double)ng * C * npx * ((sums ? 4.0 : 0.0) + (means ? 4.0 : 0.0));
     const bool quad_ok = dtype == PRNU_U8 && (npx % 4) == 0 &&
                          (reinterpret_cast<uintptr_t>(frames) % 4) == 0 &&
                          (sums == nullptr || reinterpret_cast<uintptr_t>(sums) % 16 == 0) &&
@@ -122,12 +126,14 @@ hipError_t launch_sda(const void *frames, int dtype, int n_frames, int H, int W,
     if (quad_ok && (C == 1 || C == 3)) {
         dim3 grid((unsigned)((npx / 4 + kThreads - 1) / kThreads), (unsigned)ng);
         const uint8_t *fr = static_cast<const uint8_t *>(frames);
+        KernelTimer kt(C == 1 ? "sda_u8_quads<1>" : "sda_u8_quads<3>", bytes, s);
         if (C == 1)
             sda_u8_quads<1><<<grid, kThreads, 0, s>>>(fr, npx, n_frames, group, g0, sums, means);
         else
             sda_u8_quads<3><<<grid, kThreads, 0, s>>>(fr, npx, n_frames, group, g0, sums, means);
     } else {
         dim3 grid((unsigned)((npx + kThreads - 1) / kThreads), (unsigned)ng);
+        KernelTimer kt("sda_generic", bytes, s);
         if (dtype == PRNU_U8)
             sda_generic<PRNU_U8><<<grid, kThreads, 0, s>>>(frames, npx, C, n_frames, group, g0, sums, means);
         else if (dtype == PRNU_BF16)

@@ -32,6 +32,7 @@ EXPORTS = (
     "prnu_fingerprint_finalize_workspace_size", "prnu_fingerprint_finalize",
     "prnu_query_residual_workspace_size", "prnu_query_residual",
     "prnu_pce_match_workspace_size", "prnu_pce_match",
+    "prnu_timing_enable", "prnu_timing_report",
 )
 
 
@@ -79,6 +80,8 @@ def lib() -> ctypes.CDLL:
     L.prnu_pce_match_workspace_size.argtypes = [_I, _I, _I, _I, _I, ctypes.POINTER(_S)]
     L.prnu_pce_match.argtypes = [_P, _I, _P, _I, _I, _I, _P, ctypes.POINTER(PceParams), _P, _P, _P, _P,
                                  _S, _P]
+    L.prnu_timing_enable.argtypes = [_I]
+    L.prnu_timing_report.argtypes = [ctypes.c_char_p, _S, ctypes.POINTER(_S)]
     _lib = L
     return L
 
@@ -212,8 +215,9 @@ def fingerprint_accumulate_workspace_size(n, H, W, C, group, params: DenoisePara
 
 
 def fingerprint_finalize(A: torch.Tensor, B: torch.Tensor, acc_mode: int = ACC_F64,
-                         flags: int = ZM | LUMA | WIENER, sigma_wf: float = -1.0) -> torch.Tensor:
-    """K = A/B then zero-mean / luma / DFT Wiener per ``flags``."""
+                         flags: int = ZM | LUMA | WIENER, sigma_wf: float = -1.0,
+                         out: torch.Tensor | None = None) -> torch.Tensor:
+    """K = A/B then zero-mean / luma / DFT Wiener per ``flags`` (into ``out`` if given)."""
     _cuda(A, "A")
     _cuda(B, "B")
     shape = A.shape[-3:]
@@ -222,7 +226,14 @@ def fingerprint_finalize(A: torch.Tensor, B: torch.Tensor, acc_mode: int = ACC_F
     _check(lib().prnu_fingerprint_finalize_workspace_size(C, H, W, int(flags), ctypes.byref(nbytes)))
     ws = workspace(nbytes.value, A.device)
     nout = 1 if (C == 3 and flags & LUMA) else C
-    K = torch.empty((nout, H, W) if nout > 1 else (H, W), dtype=torch.float32, device=A.device)
+    shape = (nout, H, W) if nout > 1 else (H, W)
+    if out is not None:
+        _cuda(out, "out")
+        if tuple(out.shape) != shape or out.dtype != torch.float32:
+            raise ValueError(f"out must be float32 {shape}")
+        K = out
+    else:
+        K = torch.empty(shape, dtype=torch.float32, device=A.device)
     _check(lib().prnu_fingerprint_finalize(_ptr(A), _ptr(B), int(acc_mode), C, H, W, int(flags),
                                            float(sigma_wf), _ptr(K), _ptr(ws), ws.numel(), _stream(A.device)))
     return K
@@ -278,3 +289,21 @@ def pce_match(X: torch.Tensor, Y: torch.Tensor, modulate: torch.Tensor | None = 
     _check(lib().prnu_pce_match(_ptr(X), nx, _ptr(Y), ny, h, w, _ptr(modulate), ctypes.byref(pp), _ptr(pce),
                                 _ptr(ncc), _ptr(peak), _ptr(ws), ws.numel(), _stream(dev)))
     return pce, ncc, peak
+
+
+def timing_enable(on: bool = True):
+    """Start (or stop) bracketing every kernel launch with HIP events."""
+    _check(lib().prnu_timing_enable(1 if on else 0))
+
+
+def timing_report() -> dict:
+    """{kernel name: (launches, total ms, algorithmic bytes)} since timing_enable."""
+    need = _S()
+    _check(lib().prnu_timing_report(None, 0, ctypes.byref(need)))
+    buf = ctypes.create_string_buffer(need.value + 64)
+    _check(lib().prnu_timing_report(buf, len(buf), None))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, n, ms, b = line.split("\t")
+        out[name] = (int(n), float(ms), float(b))
+    return out
