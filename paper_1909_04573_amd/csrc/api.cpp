@@ -157,9 +157,9 @@ struct PostWs {
     double *var = nullptr, *red = nullptr;
 };
 
-void carve_post(Carver &cv, int C, int H, int W, int flags, PostWs *pw) {
-    const int nout = (C == 3 && (flags & PRNU_LUMA)) ? 1 : C;
-    pw->zm = cv.take<double>(zm_scratch_doubles(C, H, W));
+void carve_post(Carver &cv, int nf, int C, int H, int W, int flags, PostWs *pw) {
+    const int nout = nf * ((C == 3 && (flags & PRNU_LUMA)) ? 1 : C);
+    pw->zm = cv.take<double>(zm_scratch_doubles(nf, C, H, W));
     if (flags & PRNU_WIENER) {
         const size_t N = (size_t)H * W;
         pw->tmp = cv.take<float>((size_t)nout * N);
@@ -174,17 +174,19 @@ void carve_post(Carver &cv, int C, int H, int W, int flags, PostWs *pw) {
 
 int check_fft_dims(int H, int W, const char *fn, FftPlan *ph, FftPlan *pw) {
     if (!make_fft_plan(H, ph) || !make_fft_plan(W, pw))
-        return fail(PRNU_E_UNSUPPORTED, "%s: DFT sizes need prime factors <= 5 and <= 8704 (got %d x %d)",
+        return fail(PRNU_E_UNSUPPORTED, "%s: DFT sizes need prime factors <= 5 and <= 5120 (got %d x %d)",
                     fn, H, W);
     return PRNU_OK;
 }
 
-int run_post(const float *in, int C, int H, int W, int flags, float sigma_wf, float *out,
+// Post-processing of nf frames of C planes [nf][C][H][W] into
+// out [nf][nout][H][W]; every output plane gets its own Wiener variance.
+int run_post(const float *in, int nf, int C, int H, int W, int flags, float sigma_wf, float *out,
              const PostWs &pw, bool twiddles_ready, hipStream_t s) {
-    const int nout = (C == 3 && (flags & PRNU_LUMA)) ? 1 : C;
+    const int nout = nf * ((C == 3 && (flags & PRNU_LUMA)) ? 1 : C);
     const bool wf = (flags & PRNU_WIENER) != 0;
     float *dst = wf ? pw.tmp : out;
-    PRNU_HIP(launch_zero_mean(in, C, H, W, (flags & PRNU_ZM) != 0, C == 3 && (flags & PRNU_LUMA), dst,
+    PRNU_HIP(launch_zero_mean(in, nf, C, H, W, (flags & PRNU_ZM) != 0, C == 3 && (flags & PRNU_LUMA), dst,
                               pw.zm, s));
     if (!wf) return PRNU_OK;
     FftPlan ph, pwl;
@@ -248,7 +250,7 @@ void plan_query(Carver &cv, int n, int H, int W, int C, const prnu_denoise_param
     qp->means = cv.take<float>((size_t)qp->nb * C * H * W);
     qp->resid = cv.take<float>((size_t)qp->nb * C * H * W);
     carve_pyramid(cv, qp->nb * C, H, W, p->levels, &qp->py);
-    carve_post(cv, C, H, W, flags, &qp->post);
+    carve_post(cv, qp->nb, C, H, W, flags, &qp->post);
 }
 
 constexpr int64_t kPceChunkBytes = 512ll << 20;
@@ -258,7 +260,53 @@ struct PcePlan {
     float2 *tw_h, *tw_w, *Xs, *Ys, *Z;
     double *xmean, *xn2, *ymean, *yn2, *spart;
     void *ppart;
+    // fixed-peak fast path
+    bool fast = false;
+    int Mc = 0;
+    float2 *tw_half = nullptr;
+    float *Px = nullptr, *Py = nullptr;
+    double *dpart = nullptr, *cpart = nullptr;
 };
+
+bool pce_fast_ok(int h, int w, int peak_mode, int nbhd) {
+    FftPlan a, b;
+    return peak_mode == PRNU_PEAK_FIXED_00 && nbhd <= 11 && (w % 2) == 0 && make_fft_plan(h, &a) &&
+           make_fft_plan(w / 2, &b) && make_fft_plan(w, &b);
+}
+
+void plan_pce_fast(Carver &cv, int nx, int ny, int h, int w, bool modulated, PcePlan *pp) {
+    const int64_t N = (int64_t)h * w;
+    const int Mc = w / 2 + 1;
+    const int64_t S = (int64_t)h * Mc;
+    const int64_t npairs = (int64_t)nx * ny;
+    int64_t P = kPceChunkBytes / (S * (int64_t)sizeof(float2));
+    if (P < 1) P = 1;
+    if (P > 64) P = 64;
+    if (P > npairs) P = npairs;
+    int64_t Pq = P;  // planes per chunk when preparing the query / fingerprint spectra
+    pp->fast = true;
+    pp->P = (int)P;
+    pp->Mc = Mc;
+    pp->tw_h = cv.take<float2>((size_t)h);
+    pp->tw_w = cv.take<float2>((size_t)w);
+    pp->tw_half = cv.take<float2>((size_t)(w / 2));
+    pp->Px = cv.take<float>((size_t)nx * S);
+    pp->Py = modulated ? nullptr : cv.take<float>((size_t)ny * S);
+    pp->Z = cv.take<float2>((size_t)(P > Pq ? P : Pq) * S);
+    pp->xmean = cv.take<double>((size_t)nx);
+    pp->xn2 = cv.take<double>((size_t)nx);
+    pp->ymean = cv.take<double>((size_t)ny);
+    pp->yn2 = cv.take<double>((size_t)ny);
+    int mx = nx > ny ? nx : ny;
+    pp->spart = cv.take<double>(stats_part_doubles(mx));
+    pp->dpart = cv.take<double>(pce_direct_part_doubles((int)P, h, w));
+    FftPlan ph;
+    make_fft_plan(h, &ph);
+    const int ncb = fft_cols_power_blocks(Mc, ph);
+    const int nsb = ncb > pce_dot_blocks() ? ncb : pce_dot_blocks();
+    pp->cpart = cv.take<double>((size_t)P * nsb);
+    (void)N;
+}
 
 void plan_pce(Carver &cv, int nx, int ny, int h, int w, bool modulated, PcePlan *pp) {
     const int64_t N = (int64_t)h * w;
@@ -284,6 +332,57 @@ void plan_pce(Carver &cv, int nx, int ny, int h, int w, bool modulated, PcePlan 
     pp->ppart = cv.take<char>(pce_part_bytes((int)P));
 }
 
+
+// Fixed-peak PCE: C(0) and the shifts around it are direct sums; the total
+// energy of the surface is (1/N) sum_k |X_k|^2 |Y_k|^2 (Parseval), so no
+// inverse transform is needed.
+int pce_fixed_fast(const float *X, int nx, const float *Y, int ny, int h, int w, const float *mod, int nbhd,
+                   double *pce, double *ncc, int32_t *peak, const PcePlan &pl, hipStream_t s) {
+    const int64_t N = (int64_t)h * w;
+    const int Mc = pl.Mc;
+    FftPlan ph, phalf;
+    make_fft_plan(h, &ph);
+    make_fft_plan(w / 2, &phalf);
+    PRNU_HIP(launch_twiddles(h, pl.tw_h, s));
+    PRNU_HIP(launch_twiddles(w, pl.tw_w, s));
+    PRNU_HIP(launch_twiddles(w / 2, pl.tw_half, s));
+    // query statistics and power spectra |X^|^2 of the centred queries
+    PRNU_HIP(launch_pair_stats(X, nullptr, INT_MAX, 0, nx, N, pl.xmean, pl.xn2, pl.spart, s));
+    const int64_t S = (int64_t)h * Mc;
+    for (int q0 = 0; q0 < nx; q0 += pl.P) {
+        const int n = nx - q0 < pl.P ? nx - q0 : pl.P;
+        PRNU_HIP(launch_rfft_rows(X, nullptr, INT_MAX, q0, n, pl.xmean + q0, h, w, phalf, pl.tw_half, pl.tw_w,
+                                  pl.Z, s));
+        PRNU_HIP(launch_fft_cols_power(pl.Z, n, h, Mc, ph, pl.tw_h, nullptr, 1, 0, pl.Px + q0 * S, nullptr, s));
+    }
+    if (!mod) {
+        for (int j0 = 0; j0 < ny; j0 += pl.P) {
+            const int n = ny - j0 < pl.P ? ny - j0 : pl.P;
+            PRNU_HIP(launch_rfft_rows(Y, nullptr, INT_MAX, j0, n, nullptr, h, w, phalf, pl.tw_half, pl.tw_w,
+                                      pl.Z, s));
+            PRNU_HIP(launch_fft_cols_power(pl.Z, n, h, Mc, ph, pl.tw_h, nullptr, 1, 0, pl.Py + j0 * S, nullptr,
+                                           s));
+        }
+    }
+    const int64_t npairs = (int64_t)nx * ny;
+    const int nbd = pce_direct_blocks(h, w);
+    for (int64_t p0 = 0; p0 < npairs; p0 += pl.P) {
+        const int n = (int)(npairs - p0 < pl.P ? npairs - p0 : pl.P);
+        int nbs;
+        if (mod) {
+            PRNU_HIP(launch_rfft_rows(Y, mod, ny, (int)p0, n, nullptr, h, w, phalf, pl.tw_half, pl.tw_w, pl.Z, s));
+            PRNU_HIP(launch_fft_cols_power(pl.Z, n, h, Mc, ph, pl.tw_h, pl.Px, ny, (int)p0, nullptr, pl.cpart, s));
+            nbs = fft_cols_power_blocks(Mc, ph);
+        } else {
+            PRNU_HIP(launch_power_dot(pl.Px, pl.Py, ny, (int)p0, n, h, Mc, pl.cpart, s));
+            nbs = pce_dot_blocks();
+        }
+        PRNU_HIP(launch_pce_direct(X, pl.xmean, Y, mod, ny, (int)p0, n, h, w, pl.dpart, s));
+        PRNU_HIP(launch_pce_finish_fixed(pl.dpart, nbd, pl.cpart, nbs, n, h, w, nbhd, pl.xn2, ny, (int)p0, pce, ncc,
+                                         peak, s));
+    }
+    return PRNU_OK;
+}
 
 }  // namespace
 }  // namespace prnu
@@ -426,7 +525,7 @@ int prnu_fingerprint_finalize_workspace_size(int C, int H, int W, int flags, siz
     Carver cv(nullptr);
     cv.take<float>((size_t)C * H * W);
     PostWs pw;
-    carve_post(cv, C, H, W, flags, &pw);
+    carve_post(cv, 1, C, H, W, flags, &pw);
     *bytes = cv.off;
     return PRNU_OK;
 }
@@ -449,14 +548,14 @@ int prnu_fingerprint_finalize(const void *A, const void *B, int acc_mode, int C,
     Carver cv(nullptr);
     cv.take<float>((size_t)C * H * W);
     PostWs pw;
-    carve_post(cv, C, H, W, flags, &pw);
+    carve_post(cv, 1, C, H, W, flags, &pw);
     PRNU_TRY(check_ws(cv, ws, ws_bytes, fn));
     Carver real(ws);
     float *Kc = real.take<float>((size_t)C * H * W);
-    carve_post(real, C, H, W, flags, &pw);
+    carve_post(real, 1, C, H, W, flags, &pw);
     hipStream_t s = (hipStream_t)stream;
     PRNU_HIP(launch_ratio(A, B, acc_mode, (int64_t)C * H * W, Kc, s));
-    return run_post(Kc, C, H, W, flags, sigma_wf, K, pw, false, s);
+    return run_post(Kc, 1, C, H, W, flags, sigma_wf, K, pw, false, s);
 }
 
 int prnu_query_residual_workspace_size(int n, int H, int W, int C, const prnu_denoise_params *p, int flags,
@@ -510,11 +609,9 @@ int prnu_query_residual(const void *frames, int dtype, int n, int H, int W, int 
         PRNU_TRY(run_pyramid(f, p, qp.means, nb * C, H, W, qp.py, s));
         PRNU_HIP(launch_dwt_inv(p->taps, f, qp.py.lvl[1], Hp / 2, Wp / 2, p->levels == 1, nb * C, INV_RESID,
                                 qp.resid, H, W, pad_before(H), pad_before(W), s));
-        for (int k = 0; k < nb; ++k) {
-            PRNU_TRY(run_post(qp.resid + (int64_t)k * C * plane, C, H, W, flags, -1.f,
-                              Wq + (int64_t)(f0 + k) * nout * plane, qp.post, tw_ready, s));
-            tw_ready = (flags & PRNU_WIENER) != 0;
-        }
+        PRNU_TRY(run_post(qp.resid, nb, C, H, W, flags, -1.f, Wq + (int64_t)f0 * nout * plane, qp.post,
+                          tw_ready, s));
+        tw_ready = (flags & PRNU_WIENER) != 0;
         if (Iq) {
             const char *fb = static_cast<const char *>(frames) + (size_t)f0 * plane * C * elem_bytes(dtype);
             PRNU_HIP(launch_luma_frames(fb, dtype, nb, H, W, C, Iq + (int64_t)f0 * plane, s));
@@ -529,10 +626,17 @@ int prnu_pce_match_workspace_size(int nx, int ny, int h, int w, int modulated, s
     if (!bytes) return fail(PRNU_E_INVAL, "%s: null output", fn);
     if (nx < 1 || ny < 1 || h < 1 || w < 1) return fail(PRNU_E_INVAL, "%s: bad sizes", fn);
     if ((int64_t)h * w > (int64_t)INT_MAX) return fail(PRNU_E_INVAL, "%s: surface too large", fn);
+    // the size covers both the shift-search path and the fixed-peak path
     Carver cv(nullptr);
     PcePlan pp;
     plan_pce(cv, nx, ny, h, w, modulated != 0, &pp);
-    *bytes = cv.off;
+    size_t need = cv.off;
+    if (pce_fast_ok(h, w, PRNU_PEAK_FIXED_00, 11)) {
+        Carver cf(nullptr);
+        plan_pce_fast(cf, nx, ny, h, w, modulated != 0, &pp);
+        if (cf.off > need) need = cf.off;
+    }
+    *bytes = need;
     return PRNU_OK;
 }
 
@@ -552,14 +656,23 @@ int prnu_pce_match(const float *X, int nx, const float *Y, int ny, int h, int w,
     FftPlan ph, pw;
     PRNU_TRY(check_fft_dims(h, w, fn, &ph, &pw));
     const bool modulated = modulate != nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t N = (int64_t)h * w;
+    if (pce_fast_ok(h, w, pp_->peak_mode, pp_->nbhd)) {
+        Carver cv(nullptr);
+        PcePlan pl;
+        plan_pce_fast(cv, nx, ny, h, w, modulated, &pl);
+        PRNU_TRY(check_ws(cv, ws, ws_bytes, fn));
+        Carver real(ws);
+        plan_pce_fast(real, nx, ny, h, w, modulated, &pl);
+        return pce_fixed_fast(X, nx, Y, ny, h, w, modulate, pp_->nbhd, pce, ncc, peak, pl, s);
+    }
     Carver cv(nullptr);
     PcePlan pl;
     plan_pce(cv, nx, ny, h, w, modulated, &pl);
     PRNU_TRY(check_ws(cv, ws, ws_bytes, fn));
     Carver real(ws);
     plan_pce(real, nx, ny, h, w, modulated, &pl);
-    hipStream_t s = (hipStream_t)stream;
-    const int64_t N = (int64_t)h * w;
     PRNU_HIP(launch_twiddles(h, pl.tw_h, s));
     PRNU_HIP(launch_twiddles(w, pl.tw_w, s));
     // query spectra

@@ -32,10 +32,11 @@ constexpr int NT = 256;   // threads per workgroup
 
 template <int TAPS>
 struct FwdGeom {
-    static constexpr int NC = T + 2 * HALO;       // coefficients per side incl. margin
-    static constexpr int NCS = NC + 1;            // LDS row stride
-    static constexpr int IN = 2 * NC + TAPS - 2;  // input samples per side
-    static constexpr int INS = IN + 1;
+    static constexpr int NC = T + 2 * HALO;       // coefficients per side incl. margin (40)
+    static constexpr int IN = 2 * NC + TAPS - 2;  // input samples per side (94 for 16 taps)
+    static constexpr int INS = (IN + 3) / 4 * 4;  // LDS row stride, 16-byte aligned rows
+    static constexpr int QSZ = 3 * NC * NC + 3 * T * T;  // masked squares + core coefficients
+    static constexpr int TILE = IN * INS > QSZ ? IN * INS : QSZ;
 };
 
 template <int TAPS>
@@ -62,11 +63,10 @@ __global__ __launch_bounds__(NT) void dwt_fwd_wiener(const float *__restrict__ s
                                                      int off_r, int off_c, float *__restrict__ out,
                                                      float s2, int tiles_c, int write_ll, Filter f) {
     using G = FwdGeom<TAPS>;
-    constexpr int IN = G::IN, INS = G::INS, NC = G::NC, NCS = G::NCS;
-    static_assert(3 * NC * NCS <= IN * INS, "detail bands must fit in the input tile");
-    __shared__ float tile[IN * INS];  // input samples, later the 3 detail bands
-    __shared__ float rlo[IN * NCS];
-    __shared__ float rhi[IN * NCS];
+    constexpr int IN = G::IN, INS = G::INS, NC = G::NC;
+    __shared__ __align__(16) float tile[G::TILE];  // input samples; later squares + core coefficients
+    __shared__ __align__(16) float rlo[IN * NC];
+    __shared__ __align__(16) float rhi[IN * NC];
     __shared__ int rmap[IN];
     __shared__ int cmap[IN];
 
@@ -84,83 +84,135 @@ __global__ __launch_bounds__(NT) void dwt_fwd_wiener(const float *__restrict__ s
         cmap[tid - IN] = map_index(2 * (k0c - HALO) + tid - IN, n_c, off_c, src_cols);
     __syncthreads();
 
-    for (int e = tid; e < IN * IN; e += NT) {
-        const int i = e / IN, j = e - (e / IN) * IN;
-        tile[i * INS + j] = sp[(int64_t)rmap[i] * src_cols + cmap[j]];
+    // Stage the input tile: pairs of contiguous samples where the tile's columns
+    // need neither the periodic wrap nor the reflection, single samples otherwise.
+    const int c_src0 = 2 * (k0c - HALO) - off_c;
+    const bool cfast = c_src0 >= 0 && c_src0 + IN <= src_cols && (c_src0 & 1) == 0 && (src_cols & 1) == 0 &&
+                       (src_stride & 1) == 0;
+    if (cfast) {
+        constexpr int IN2 = IN / 2;
+        for (int e = tid; e < IN * IN2; e += NT) {
+            const int i = e / IN2, j2 = e - (e / IN2) * IN2;
+            const float2 v = *reinterpret_cast<const float2 *>(sp + (int64_t)rmap[i] * src_cols + c_src0 + 2 * j2);
+            *reinterpret_cast<float2 *>(&tile[i * INS + 2 * j2]) = v;
+        }
+    } else {
+        for (int e = tid; e < IN * IN; e += NT) {
+            const int i = e / IN, j = e - (e / IN) * IN;
+            tile[i * INS + j] = sp[(int64_t)rmap[i] * src_cols + cmap[j]];
+        }
     }
     __syncthreads();
 
-    // Rows: lo/hi along axis 1, four coefficients per item.
+    // Rows: lo/hi along axis 1, four coefficients per item, 16-byte LDS traffic.
     constexpr int NQ = NC / 4;
+    constexpr int NX = TAPS + 8;  // TAPS + 6 samples, rounded up to whole float4s
     for (int it = tid; it < IN * NQ; it += NT) {
         const int i = it / NQ, kq = it - (it / NQ) * NQ;
-        const float *row = &tile[i * INS + 8 * kq];
-        float x[TAPS + 6];
+        const float4 *row = reinterpret_cast<const float4 *>(&tile[i * INS + 8 * kq]);
+        float x[NX];
 #pragma unroll
-        for (int t = 0; t < TAPS + 6; ++t) x[t] = row[t];
+        for (int t = 0; t < NX / 4; ++t) {
+            const float4 v = row[t];
+            x[4 * t] = v.x;
+            x[4 * t + 1] = v.y;
+            x[4 * t + 2] = v.z;
+            x[4 * t + 3] = v.w;
+        }
+        float lo[4], hi[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            float lo = 0.f, hi = 0.f;
+            lo[u] = 0.f;
+            hi[u] = 0.f;
 #pragma unroll
             for (int j = 0; j < TAPS; ++j) {
-                lo = fmaf(f.h[j], x[2 * u + j], lo);
-                hi = fmaf(f.g[j], x[2 * u + j], hi);
+                lo[u] = fmaf(f.h[j], x[2 * u + j], lo[u]);
+                hi[u] = fmaf(f.g[j], x[2 * u + j], hi[u]);
             }
-            rlo[i * NCS + 4 * kq + u] = lo;
-            rhi[i * NCS + 4 * kq + u] = hi;
         }
+        *reinterpret_cast<float4 *>(&rlo[i * NC + 4 * kq]) = make_float4(lo[0], lo[1], lo[2], lo[3]);
+        *reinterpret_cast<float4 *>(&rhi[i * NC + 4 * kq]) = make_float4(hi[0], hi[1], hi[2], hi[3]);
     }
     __syncthreads();
 
-    // Columns: the four subbands, two coefficients per item.
-    float *det = tile;  // [3][NC][NCS]: lh, hl, hh
-    constexpr int NP = NC / 2;
-    for (int it = tid; it < NC * NP; it += NT) {
-        const int kp = it / NC, kc = it - (it / NC) * NC;
-        float xl[TAPS + 2], xh[TAPS + 2];
+    // Columns: a quad of coefficient columns by a pair of coefficient rows per
+    // item.  Every detail coefficient's square goes to q (zero outside the
+    // band: the Wiener windows' zero extension); the core coefficients to cb.
+    float *qb = tile;                // [3][NC][NC]
+    float *cb = tile + 3 * NC * NC;  // [3][T][T]
+    const int gr0 = k0r - HALO, gc0 = k0c - HALO;
+    for (int it = tid; it < NQ * (NC / 2); it += NT) {
+        const int cq = it % NQ, kp = it / NQ;
+        bool cv[4];
 #pragma unroll
-        for (int t = 0; t < TAPS + 2; ++t) {
-            xl[t] = rlo[(4 * kp + t) * NCS + kc];
-            xh[t] = rhi[(4 * kp + t) * NCS + kc];
-        }
+        for (int c = 0; c < 4; ++c) cv[c] = gc0 + 4 * cq + c >= 0 && gc0 + 4 * cq + c < wk;
+        const bool core_c = cq >= HALO / 4 && cq < (HALO + T) / 4;
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            float ll = 0.f, hl = 0.f, lh = 0.f, hh = 0.f;
+        for (int pass = 0; pass < 2; ++pass) {
+            const float *rb = pass == 0 ? rlo : rhi;
+            float4 xv[TAPS + 2];
 #pragma unroll
-            for (int j = 0; j < TAPS; ++j) {
-                ll = fmaf(f.h[j], xl[2 * u + j], ll);
-                hl = fmaf(f.g[j], xl[2 * u + j], hl);
-                lh = fmaf(f.h[j], xh[2 * u + j], lh);
-                hh = fmaf(f.g[j], xh[2 * u + j], hh);
-            }
-            const int kr = 2 * kp + u;
-            det[0 * NC * NCS + kr * NCS + kc] = lh;
-            det[1 * NC * NCS + kr * NCS + kc] = hl;
-            det[2 * NC * NCS + kr * NCS + kc] = hh;
-            if (write_ll && kr >= HALO && kr < HALO + T && kc >= HALO && kc < HALO + T) {
-                const int gr = k0r + kr - HALO, gc = k0c + kc - HALO;
-                if (gr < hk && gc < wk) op[(int64_t)gr * wk + gc] = ll;
+            for (int t = 0; t < TAPS + 2; ++t) xv[t] = *reinterpret_cast<const float4 *>(&rb[(4 * kp + t) * NC + 4 * cq]);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                float a[4] = {0.f, 0.f, 0.f, 0.f}, d[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int j = 0; j < TAPS; ++j) {
+                    const float4 v = xv[2 * u + j];
+                    a[0] = fmaf(f.h[j], v.x, a[0]);
+                    a[1] = fmaf(f.h[j], v.y, a[1]);
+                    a[2] = fmaf(f.h[j], v.z, a[2]);
+                    a[3] = fmaf(f.h[j], v.w, a[3]);
+                    d[0] = fmaf(f.g[j], v.x, d[0]);
+                    d[1] = fmaf(f.g[j], v.y, d[1]);
+                    d[2] = fmaf(f.g[j], v.z, d[2]);
+                    d[3] = fmaf(f.g[j], v.w, d[3]);
+                }
+                const int kr = 2 * kp + u;
+                const bool rv = gr0 + kr >= 0 && gr0 + kr < hk;
+                const bool core = core_c && kr >= HALO && kr < HALO + T;
+                // pass 0 (row low-pass): a = ll, d = hl (band 2); pass 1: a = lh (band 1), d = hh (band 3)
+                if (pass == 0) {
+                    if (write_ll && core) {
+                        const int gr = gr0 + kr;
+                        if (gr < hk)
+#pragma unroll
+                            for (int c = 0; c < 4; ++c)
+                                if (cv[c]) op[(int64_t)gr * wk + gc0 + 4 * cq + c] = a[c];
+                    }
+                } else {
+                    *reinterpret_cast<float4 *>(&qb[(0 * NC + kr) * NC + 4 * cq]) =
+                        make_float4(rv && cv[0] ? a[0] * a[0] : 0.f, rv && cv[1] ? a[1] * a[1] : 0.f,
+                                    rv && cv[2] ? a[2] * a[2] : 0.f, rv && cv[3] ? a[3] * a[3] : 0.f);
+                    if (core)
+                        *reinterpret_cast<float4 *>(&cb[(0 * T + kr - HALO) * T + 4 * cq - HALO]) =
+                            make_float4(a[0], a[1], a[2], a[3]);
+                }
+                const int sb = pass == 0 ? 1 : 2;  // hl -> band index 1 of q/cb, hh -> 2
+                *reinterpret_cast<float4 *>(&qb[(sb * NC + kr) * NC + 4 * cq]) =
+                    make_float4(rv && cv[0] ? d[0] * d[0] : 0.f, rv && cv[1] ? d[1] * d[1] : 0.f,
+                                rv && cv[2] ? d[2] * d[2] : 0.f, rv && cv[3] ? d[3] * d[3] : 0.f);
+                if (core)
+                    *reinterpret_cast<float4 *>(&cb[(sb * T + kr - HALO) * T + 4 * cq - HALO]) =
+                        make_float4(d[0], d[1], d[2], d[3]);
             }
         }
     }
     __syncthreads();
 
     // Wiener shrinkage of the T x T core of each detail band: one thread per
-    // (band, core column, half of the core rows).
+    // (band, core column, half of the core rows).  Band s of q/cb is lh, hl,
+    // hh for s = 0, 1, 2, stored as subbands 1, 2, 3.
     if (tid < 3 * 2 * T) {
         const int s = tid / (2 * T), half = (tid / T) & 1, kcl = tid & (T - 1);
-        const float *D = det + s * NC * NCS;
-        const int gr0 = k0r - HALO, gc0 = k0c - HALO;
+        const float *Q = qb + s * NC * NC;
+        const float *Cc = cb + s * T * T;
         float *ob = op + (int64_t)(s + 1) * band;
         const int gco = k0c + kcl;
-        auto load = [&](int kr, int kc) {
-            const int gr = gr0 + kr, gc = gc0 + kc;
-            const float c = D[kr * NCS + kc];
-            return (gr >= 0 && gr < hk && gc >= 0 && gc < wk) ? c * c : 0.f;
-        };
+        auto load = [&](int kr, int kc) { return Q[kr * NC + kc]; };
         auto emit = [&](int ko, float rho) {
             const int gro = gr0 + ko;
-            if (gro < hk && gco < wk) ob[(int64_t)gro * wk + gco] = D[ko * NCS + kcl + HALO] * rho;
+            if (gro < hk && gco < wk) ob[(int64_t)gro * wk + gco] = Cc[(ko - HALO) * T + kcl] * rho;
         };
         wiener_column<T / 2>(half * (T / 2), kcl, s2, load, emit);
     }

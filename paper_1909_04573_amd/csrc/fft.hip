@@ -1,165 +1,151 @@
-// Mixed-radix complex FFT for gfx950 (radices 2, 3, 4, 5), used by the
-// DFT-domain Wiener step and by the PCE correlation surfaces.
+// Mixed-radix FFTs for gfx950 (radices 2, 3, 4, 5), used by the DFT-domain
+// Wiener step and by PCE.
 //
 // A workgroup transforms `nvec` vectors of length N held in LDS as
 // buf[n * nvec + v].  Each pass is a Stockham (self-sorting) step: with Ns the
 // product of the radices already applied, butterfly j (k = j mod Ns) reads
 // x[j + r N/R] for r < R, multiplies by the twiddle W_N^{k r N/(Ns R)},
-// does an R-point DFT and writes y[(j / Ns) Ns R + k + r Ns].  Every thread
-// keeps its butterflies' values in registers across one barrier, so the
-// pass runs in place in a single LDS buffer.  Twiddles W_N^k = exp(-2 pi i k/N)
-// are rounded to float from double-precision sincospi once per size.
+// does an R-point DFT and writes y[(j / Ns) Ns R + k + r Ns].  Passes
+// ping-pong between two LDS buffers, so each thread only holds one
+// butterfly's values at a time.  Twiddles W_N^k = exp(-2 pi i k / N) are
+// rounded to float from double-precision sincospi once per size.
 //
-// 2-D transforms are a pass along rows (vectors = rows) and a pass along
-// columns (vectors = columns, coalesced across the nvec neighbouring columns).
+// Kernels:
+//   fft_1d          complex transform of rows or columns, in place in HBM
+//   rfft_rows       real rows (optionally scaled elementwise by a second
+//                   field) -> half spectrum of w/2+1 bins, through one
+//                   complex transform of length w/2
+//   fft_cols_power  column transform of half spectra; the epilogue either
+//                   stores |Y_k|^2 or reduces sum_k |X_k|^2 |Y_k|^2 over the
+//                   full (Hermitian) spectrum without the DC bin
 
 #include <cmath>
 
+#include "fft_dev.h"
 #include "internal.h"
 
 namespace prnu {
 namespace {
-
-constexpr int FNT = 256;
-constexpr int LDS_CAP = 8704;  // complex elements per workgroup (68 KiB)
-
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-// sigma * i * z
-__device__ __forceinline__ float2 cmuli(float2 z, float sigma) { return make_float2(-sigma * z.y, sigma * z.x); }
-__device__ __forceinline__ float2 cscale(float2 z, float s) { return make_float2(z.x * s, z.y * s); }
-
-// R-point DFT in place, y_k = sum_r x_r exp(sigma 2 pi i r k / R).
-template <int R>
-__device__ __forceinline__ void dft(float2 *x, float sigma);
-
-template <>
-__device__ __forceinline__ void dft<2>(float2 *x, float) {
-    const float2 a = x[0], b = x[1];
-    x[0] = cadd(a, b);
-    x[1] = csub(a, b);
-}
-
-template <>
-__device__ __forceinline__ void dft<3>(float2 *x, float sigma) {
-    constexpr float S3 = 0.866025403784438646763723170752936f;  // sin(2 pi / 3)
-    const float2 t1 = cadd(x[1], x[2]), t2 = csub(x[1], x[2]);
-    const float2 m = csub(x[0], cscale(t1, 0.5f));
-    const float2 s = cmuli(cscale(t2, S3), sigma);
-    x[0] = cadd(x[0], t1);
-    x[1] = cadd(m, s);
-    x[2] = csub(m, s);
-}
-
-template <>
-__device__ __forceinline__ void dft<4>(float2 *x, float sigma) {
-    const float2 a = cadd(x[0], x[2]), b = csub(x[0], x[2]);
-    const float2 c = cadd(x[1], x[3]), d = cmuli(csub(x[1], x[3]), sigma);
-    x[0] = cadd(a, c);
-    x[2] = csub(a, c);
-    x[1] = cadd(b, d);
-    x[3] = csub(b, d);
-}
-
-template <>
-__device__ __forceinline__ void dft<5>(float2 *x, float sigma) {
-    constexpr float C1 = 0.309016994374947424102293417182819f;   // cos(2 pi / 5)
-    constexpr float C2 = -0.809016994374947424102293417182819f;  // cos(4 pi / 5)
-    constexpr float S1 = 0.951056516295153572116439333379382f;   // sin(2 pi / 5)
-    constexpr float S2 = 0.587785252292473129168705954639073f;   // sin(4 pi / 5)
-    const float2 t1 = cadd(x[1], x[4]), t2 = cadd(x[2], x[3]);
-    const float2 t3 = csub(x[1], x[4]), t4 = csub(x[2], x[3]);
-    const float2 a1 = cadd(x[0], cadd(cscale(t1, C1), cscale(t2, C2)));
-    const float2 a2 = cadd(x[0], cadd(cscale(t1, C2), cscale(t2, C1)));
-    const float2 b1 = cmuli(cadd(cscale(t3, S1), cscale(t4, S2)), sigma);
-    const float2 b2 = cmuli(csub(cscale(t3, S2), cscale(t4, S1)), sigma);
-    x[0] = cadd(x[0], cadd(t1, t2));
-    x[1] = cadd(a1, b1);
-    x[4] = csub(a1, b1);
-    x[2] = cadd(a2, b2);
-    x[3] = csub(a2, b2);
-}
-
-template <int R>
-struct MaxB {
-    static constexpr int v = (LDS_CAP / R + FNT - 1) / FNT;
-};
-
-template <int R>
-__device__ __forceinline__ void stockham_pass(float2 *buf, int N, int nvec, int Ns,
-                                              const float2 *__restrict__ tw, float sigma) {
-    constexpr int MB = MaxB<R>::v;
-    const int nb = (N / R) * nvec;
-    const int NR = N / R;
-    const int tws = N / (Ns * R);
-    float2 v[MB][R];
-    int dst[MB];
-#pragma unroll
-    for (int b = 0; b < MB; ++b) {
-        const int idx = threadIdx.x + b * FNT;
-        if (idx < nb) {
-            const int vv = idx % nvec, j = idx / nvec;
-            const int k = j % Ns;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                float2 x = buf[(j + r * NR) * nvec + vv];
-                if (r > 0) {
-                    float2 w = tw[k * r * tws];
-                    w.y *= -sigma;  // table holds exp(-2 pi i k / N); inverse uses the conjugate
-                    x = cmul(x, make_float2(w.x, w.y));
-                }
-                v[b][r] = x;
-            }
-            dft<R>(v[b], sigma);
-            dst[b] = ((j / Ns) * Ns * R + k) * nvec + vv;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int b = 0; b < MB; ++b) {
-        const int idx = threadIdx.x + b * FNT;
-        if (idx < nb) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) buf[dst[b] + r * Ns * nvec] = v[b][r];
-        }
-    }
-    __syncthreads();
-}
 
 // One batch of 1-D transforms: vectors v0 .. v0+nvec-1 of `count`, element n
 // of vector v at base[v * vs + n * es].
 __global__ __launch_bounds__(FNT) void fft_1d(float2 *__restrict__ data, int N, int count, int64_t es,
                                               int64_t vs, int64_t plane_stride, FftPlan plan,
                                               const float2 *__restrict__ tw, float sigma) {
-    __shared__ float2 buf[LDS_CAP];
+    __shared__ float2 lds[2 * FCAP];
     const int nvec = plan.nvec;
     const int v0 = blockIdx.x * nvec;
     float2 *base = data + (int64_t)blockIdx.y * plane_stride;
     const int tot = N * nvec;
+    float2 *b0 = lds, *b1 = lds + FCAP;
     for (int e = threadIdx.x; e < tot; e += FNT) {
-        const int v = e % nvec, n = e / nvec;
-        buf[e] = (v0 + v < count) ? base[(int64_t)(v0 + v) * vs + (int64_t)n * es] : make_float2(0.f, 0.f);
+        const int v = e & (nvec - 1), n = e >> plan.lvec;
+        b0[e] = (v0 + v < count) ? base[(int64_t)(v0 + v) * vs + (int64_t)n * es] : make_float2(0.f, 0.f);
     }
     __syncthreads();
-    int Ns = 1;
-    for (int p = 0; p < plan.nrad; ++p) {
-        const int R = plan.rad[p];
-        if (R == 4)
-            stockham_pass<4>(buf, N, nvec, Ns, tw, sigma);
-        else if (R == 2)
-            stockham_pass<2>(buf, N, nvec, Ns, tw, sigma);
-        else if (R == 3)
-            stockham_pass<3>(buf, N, nvec, Ns, tw, sigma);
-        else
-            stockham_pass<5>(buf, N, nvec, Ns, tw, sigma);
-        Ns *= R;
-    }
+    const float2 *res = fft_lds(b0, b1, plan, tw, sigma);
     for (int e = threadIdx.x; e < tot; e += FNT) {
-        const int v = e % nvec, n = e / nvec;
-        if (v0 + v < count) base[(int64_t)(v0 + v) * vs + (int64_t)n * es] = buf[e];
+        const int v = e & (nvec - 1), n = e >> plan.lvec;
+        if (v0 + v < count) base[(int64_t)(v0 + v) * vs + (int64_t)n * es] = res[e];
+    }
+}
+
+// Real rows -> half spectra.  Plane p of the batch is y = Y[(p0+p) % ny]
+// (times mod[(p0+p) / ny] if given, minus `mean[p]` if given).  Row r, bins
+// k = 0 .. w/2 at out[p][r][k] (row stride w/2 + 1).
+__global__ __launch_bounds__(FNT) void rfft_rows(const float *__restrict__ Y, const float *__restrict__ mod,
+                                                 int ny, int p0, const double *__restrict__ mean, int h,
+                                                 int w, FftPlan plan, const float2 *__restrict__ tw_half,
+                                                 const float2 *__restrict__ tw_full, float2 *__restrict__ out) {
+    __shared__ float2 lds[2 * FCAP];
+    const int M = w / 2;
+    const int nvec = plan.nvec;
+    const int r0 = blockIdx.x * nvec;
+    const int pid = p0 + (int)blockIdx.y;
+    const int64_t N = (int64_t)h * w;
+    const float *yp = Y + (int64_t)(pid % ny) * N;
+    const float *mp = mod ? mod + (int64_t)(pid / ny) * N : nullptr;
+    const float mu = mean ? (float)mean[blockIdx.y] : 0.f;
+    float2 *b0 = lds, *b1 = lds + FCAP;
+    const int tot = M * nvec;
+    for (int e = threadIdx.x; e < tot; e += FNT) {
+        const int v = e & (nvec - 1), n = e >> plan.lvec;
+        float2 z = make_float2(0.f, 0.f);
+        if (r0 + v < h) {
+            const int64_t o = (int64_t)(r0 + v) * w + 2 * n;
+            float a = yp[o], b = yp[o + 1];
+            if (mp) {
+                a *= mp[o];
+                b *= mp[o + 1];
+            }
+            z = make_float2(a - mu, b - mu);
+        }
+        b0[e] = z;
+    }
+    __syncthreads();
+    const float2 *res = fft_lds(b0, b1, plan, tw_half, -1.f);
+    // Split the even/odd-sample spectra: Y[k] = E[k] + W_w^k O[k].
+    float2 *op = out + (int64_t)blockIdx.y * h * (M + 1);
+    const int tot2 = (M + 1) * nvec;
+    for (int e = threadIdx.x; e < tot2; e += FNT) {
+        const int v = e % nvec, k = e / nvec;
+        if (r0 + v >= h) continue;
+        const float2 zk = res[(k % M) * nvec + v];
+        const float2 zm = res[((M - k) % M) * nvec + v];
+        // E = (zk + conj zm) / 2 ; O = (zk - conj zm) / (2i)
+        const float2 E = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+        const float2 O = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+        const float2 t = tw_full[k];  // exp(-2 pi i k / w), k <= w/2
+        const float2 tO = cmul(t, O);
+        op[(int64_t)(r0 + v) * (M + 1) + k] = make_float2(E.x + tO.x, E.y + tO.y);
+    }
+}
+
+// Column transforms of half spectra [p][h][Mc] (Mc = w/2 + 1).
+//   POWER_STORE: Pout[p][k] = |S_k|^2 (DC bin 0)
+//   POWER_DOT:   part[p][blockIdx.x] = sum_k wgt(k) Px[q][k] |S_k|^2 over the
+//                strip (wgt = 1 on the first and the Nyquist column, 2 between;
+//                DC bin excluded), q = (p0 + p) / ny.
+template <bool DOT>
+__global__ __launch_bounds__(FNT) void fft_cols_power(const float2 *__restrict__ S, int h, int Mc, FftPlan plan,
+                                                      const float2 *__restrict__ tw, const float *__restrict__ Px,
+                                                      int ny, int p0, float *__restrict__ Pout,
+                                                      double *__restrict__ part) {
+    __shared__ float2 lds[2 * FCAP];
+    const int nvec = plan.nvec;
+    const int c0 = blockIdx.x * nvec;
+    const int64_t plane = (int64_t)h * Mc;
+    const float2 *sp = S + (int64_t)blockIdx.y * plane;
+    float2 *b0 = lds, *b1 = lds + FCAP;
+    const int tot = h * nvec;
+    for (int e = threadIdx.x; e < tot; e += FNT) {
+        const int v = e & (nvec - 1), n = e >> plan.lvec;
+        b0[e] = (c0 + v < Mc) ? sp[(int64_t)n * Mc + c0 + v] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    const float2 *res = fft_lds(b0, b1, plan, tw, -1.f);
+    const int pid = p0 + (int)blockIdx.y;
+    double acc = 0.0;
+    const float *pq = DOT ? Px + (int64_t)(pid / ny) * plane : nullptr;
+    for (int e = threadIdx.x; e < tot; e += FNT) {
+        const int v = e & (nvec - 1), n = e >> plan.lvec;
+        const int col = c0 + v;
+        if (col >= Mc) continue;
+        const float2 z = res[e];
+        float pw = z.x * z.x + z.y * z.y;
+        if (n == 0 && col == 0) pw = 0.f;
+        if (DOT) {
+            const float wgt = (col == 0 || col == Mc - 1) ? 1.f : 2.f;
+            acc += (double)(wgt * pw) * (double)pq[(int64_t)n * Mc + col];
+        } else {
+            Pout[(int64_t)blockIdx.y * plane + (int64_t)n * Mc + col] = pw;
+        }
+    }
+    if (DOT) {
+        // the buffer not holding the result is free for the reduction
+        double *red = reinterpret_cast<double *>(res == b0 ? b1 : b0);
+        acc = block_sum_f64(acc, red);
+        if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = acc;
     }
 }
 
@@ -174,7 +160,7 @@ __global__ void twiddle_kernel(int n, float2 *tw) {
 }  // namespace
 
 bool make_fft_plan(int n, FftPlan *p) {
-    if (n < 1 || n > LDS_CAP) return false;
+    if (n < 1 || n > FCAP) return false;
     int m = n, k = 0;
     while (m % 4 == 0 && k < 16) { p->rad[k++] = 4; m /= 4; }
     while (m % 2 == 0 && k < 16) { p->rad[k++] = 2; m /= 2; }
@@ -183,9 +169,13 @@ bool make_fft_plan(int n, FftPlan *p) {
     if (m != 1) return false;
     p->n = n;
     p->nrad = k;
-    int nv = 16;
-    while (nv > 1 && n * nv > LDS_CAP) nv /= 2;
+    int nv = 16, lv = 4;
+    while (nv > 1 && n * nv > FCAP) {
+        nv /= 2;
+        --lv;
+    }
     p->nvec = nv;
+    p->lvec = lv;
     return true;
 }
 
@@ -214,6 +204,32 @@ hipError_t launch_fft2(float2 *data, int batch, int h, int w, const FftPlan &ph,
     {
         KernelTimer kt("fft_1d", bytes, s);
         fft_1d<<<gc, FNT, 0, s>>>(data, h, w, w, 1, plane, ph, tw_h, sigma);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_rfft_rows(const float *Y, const float *mod, int ny, int p0, int n, const double *mean,
+                            int h, int w, const FftPlan &phalf, const float2 *tw_half, const float2 *tw_full,
+                            float2 *out, hipStream_t s) {
+    const double bytes = (double)n * h * ((mod ? 8.0 : 4.0) * w + 8.0 * (w / 2 + 1));
+    KernelTimer kt("rfft_rows", bytes, s);
+    dim3 g((unsigned)((h + phalf.nvec - 1) / phalf.nvec), (unsigned)n);
+    rfft_rows<<<g, FNT, 0, s>>>(Y, mod, ny, p0, mean, h, w, phalf, tw_half, tw_full, out);
+    return hipGetLastError();
+}
+
+int fft_cols_power_blocks(int Mc, const FftPlan &ph) { return (Mc + ph.nvec - 1) / ph.nvec; }
+
+hipError_t launch_fft_cols_power(const float2 *S, int n, int h, int Mc, const FftPlan &ph, const float2 *tw_h,
+                                 const float *Px, int ny, int p0, float *Pout, double *part, hipStream_t s) {
+    const double bytes = (double)n * h * Mc * (8.0 + 4.0);
+    dim3 g((unsigned)fft_cols_power_blocks(Mc, ph), (unsigned)n);
+    if (Px) {
+        KernelTimer kt("fft_cols_power_dot", bytes, s);
+        fft_cols_power<true><<<g, FNT, 0, s>>>(S, h, Mc, ph, tw_h, Px, ny, p0, nullptr, part);
+    } else {
+        KernelTimer kt("fft_cols_power_store", bytes, s);
+        fft_cols_power<false><<<g, FNT, 0, s>>>(S, h, Mc, ph, tw_h, nullptr, ny, p0, Pout, nullptr);
     }
     return hipGetLastError();
 }

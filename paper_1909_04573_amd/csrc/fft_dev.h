@@ -1,0 +1,156 @@
+// Device helpers of the mixed-radix Stockham FFT (see fft.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace prnu {
+
+constexpr int FNT = 256;    // threads per FFT workgroup
+constexpr int FCAP = 5120;  // complex elements per LDS buffer (two buffers: 80 KiB)
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// sigma * i * z
+__device__ __forceinline__ float2 cmuli(float2 z, float sigma) { return make_float2(-sigma * z.y, sigma * z.x); }
+__device__ __forceinline__ float2 cscale(float2 z, float s) { return make_float2(z.x * s, z.y * s); }
+
+// R-point DFT in place, y_k = sum_r x_r exp(sigma 2 pi i r k / R).
+template <int R>
+__device__ __forceinline__ void dft(float2 *x, float sigma);
+
+template <>
+__device__ __forceinline__ void dft<2>(float2 *x, float) {
+    const float2 a = x[0], b = x[1];
+    x[0] = cadd(a, b);
+    x[1] = csub(a, b);
+}
+
+template <>
+__device__ __forceinline__ void dft<3>(float2 *x, float sigma) {
+    constexpr float S3 = 0.866025403784438646763723170752936f;  // sin(2 pi / 3)
+    const float2 t1 = cadd(x[1], x[2]), t2 = csub(x[1], x[2]);
+    const float2 m = csub(x[0], cscale(t1, 0.5f));
+    const float2 s = cmuli(cscale(t2, S3), sigma);
+    x[0] = cadd(x[0], t1);
+    x[1] = cadd(m, s);
+    x[2] = csub(m, s);
+}
+
+template <>
+__device__ __forceinline__ void dft<4>(float2 *x, float sigma) {
+    const float2 a = cadd(x[0], x[2]), b = csub(x[0], x[2]);
+    const float2 c = cadd(x[1], x[3]), d = cmuli(csub(x[1], x[3]), sigma);
+    x[0] = cadd(a, c);
+    x[2] = csub(a, c);
+    x[1] = cadd(b, d);
+    x[3] = csub(b, d);
+}
+
+template <>
+__device__ __forceinline__ void dft<5>(float2 *x, float sigma) {
+    constexpr float C1 = 0.309016994374947424102293417182819f;   // cos(2 pi / 5)
+    constexpr float C2 = -0.809016994374947424102293417182819f;  // cos(4 pi / 5)
+    constexpr float S1 = 0.951056516295153572116439333379382f;   // sin(2 pi / 5)
+    constexpr float S2 = 0.587785252292473129168705954639073f;   // sin(4 pi / 5)
+    const float2 t1 = cadd(x[1], x[4]), t2 = cadd(x[2], x[3]);
+    const float2 t3 = csub(x[1], x[4]), t4 = csub(x[2], x[3]);
+    const float2 a1 = cadd(x[0], cadd(cscale(t1, C1), cscale(t2, C2)));
+    const float2 a2 = cadd(x[0], cadd(cscale(t1, C2), cscale(t2, C1)));
+    const float2 b1 = cmuli(cadd(cscale(t3, S1), cscale(t4, S2)), sigma);
+    const float2 b2 = cmuli(csub(cscale(t3, S2), cscale(t4, S1)), sigma);
+    x[0] = cadd(x[0], cadd(t1, t2));
+    x[1] = cadd(a1, b1);
+    x[4] = csub(a1, b1);
+    x[2] = cadd(a2, b2);
+    x[3] = csub(a2, b2);
+}
+
+// Exact j / d for 0 <= j < 2^20 and d >= 1 (float estimate plus correction).
+__device__ __forceinline__ int udiv_small(int j, int d, float inv_d) {
+    int q = (int)((float)j * inv_d);
+    if (q * d > j) --q;
+    if ((q + 1) * d <= j) ++q;
+    return q;
+}
+
+template <int R>
+__device__ __forceinline__ void stockham_pass(const float2 *__restrict__ src, float2 *__restrict__ dst, int N,
+                                              int nvec, int lvec, int Ns, const float2 *__restrict__ tw,
+                                              float sigma) {
+    const int NR = N / R;
+    const int nb = NR * nvec;
+    const int tws = N / (Ns * R);
+    const float inv_ns = 1.0f / (float)Ns;
+    for (int idx = threadIdx.x; idx < nb; idx += FNT) {
+        const int vv = idx & (nvec - 1), j = idx >> lvec;
+        const int jq = udiv_small(j, Ns, inv_ns);
+        const int k = j - jq * Ns;
+        float2 v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            float2 x = src[(j + r * NR) * nvec + vv];
+            if (r > 0) {
+                float2 w = tw[k * r * tws];
+                w.y *= -sigma;  // table holds exp(-2 pi i k / N); the inverse uses its conjugate
+                x = cmul(x, w);
+            }
+            v[r] = x;
+        }
+        dft<R>(v, sigma);
+        const int d0 = (jq * Ns * R + k) * nvec + vv;
+#pragma unroll
+        for (int r = 0; r < R; ++r) dst[d0 + r * Ns * nvec] = v[r];
+    }
+    __syncthreads();
+}
+
+// Transform the nvec vectors in b0 (layout [n][nvec]); returns the buffer
+// holding the result (b0 or b1).
+__device__ __forceinline__ const float2 *fft_lds(float2 *b0, float2 *b1, const FftPlan &plan,
+                                                 const float2 *__restrict__ tw, float sigma) {
+    float2 *src = b0, *dst = b1;
+    int Ns = 1;
+    for (int p = 0; p < plan.nrad; ++p) {
+        const int R = plan.rad[p];
+        if (R == 4)
+            stockham_pass<4>(src, dst, plan.n, plan.nvec, plan.lvec, Ns, tw, sigma);
+        else if (R == 2)
+            stockham_pass<2>(src, dst, plan.n, plan.nvec, plan.lvec, Ns, tw, sigma);
+        else if (R == 3)
+            stockham_pass<3>(src, dst, plan.n, plan.nvec, plan.lvec, Ns, tw, sigma);
+        else
+            stockham_pass<5>(src, dst, plan.n, plan.nvec, plan.lvec, Ns, tw, sigma);
+        float2 *t = src;
+        src = dst;
+        dst = t;
+        Ns *= R;
+    }
+    return src;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Block-wide sum in a fixed order; the result is valid in thread 0.  Every
+// thread of the block must call it.
+__device__ __forceinline__ double block_sum_f64(double v, double *sh) {
+    v = wave_sum_f64(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) r += sh[k];
+    __syncthreads();
+    return r;
+}
+
+}  // namespace prnu

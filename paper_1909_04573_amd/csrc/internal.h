@@ -84,8 +84,9 @@ hipError_t launch_ratio(const void *A, const void *B, int acc_mode, int64_t n, f
                         hipStream_t s);
 // Zero-mean per plane and optional luma.  in: [C][H][W]; out: [1][H][W] with
 // luma else [C][H][W].  rowpart/colpart: double scratch of zm_scratch_doubles.
-size_t zm_scratch_doubles(int C, int H, int W);
-hipError_t launch_zero_mean(const float *in, int C, int H, int W, bool zm, bool luma, float *out,
+// nf frames of C planes: in [nf][C][H][W] -> out [nf][luma ? 1 : C][H][W].
+size_t zm_scratch_doubles(int nf, int C, int H, int W);
+hipError_t launch_zero_mean(const float *in, int nf, int C, int H, int W, bool zm, bool luma, float *out,
                             double *scratch, hipStream_t s);
 // Convert planes [n][H][W] (n planes) u8/bf16/f32 interleaved frames -> luma.
 hipError_t launch_luma_frames(const void *frames, int dtype, int n, int H, int W, int C,
@@ -93,10 +94,11 @@ hipError_t launch_luma_frames(const void *frames, int dtype, int n, int H, int W
 
 // ---- FFT -------------------------------------------------------------------
 struct FftPlan {
-    int n;            // length
-    int nrad;         // number of passes
-    int rad[16];      // radices, each in {2,3,4,5}
-    int nvec;         // vectors per workgroup
+    int n;        // length
+    int nrad;     // number of passes
+    int rad[16];  // radices, each in {2,3,4,5}
+    int nvec;     // vectors per workgroup (power of two)
+    int lvec;     // log2(nvec)
 };
 bool make_fft_plan(int n, FftPlan *p);
 size_t fft_twiddle_floats(int n);  // complex table of n entries, 2 floats each
@@ -106,6 +108,19 @@ hipError_t launch_twiddles(int n, float2 *tw, hipStream_t s);
 hipError_t launch_fft2(float2 *data, int batch, int h, int w, const FftPlan &ph,
                        const FftPlan &pw, const float2 *tw_h, const float2 *tw_w, int dir,
                        hipStream_t s);
+
+// Real rows -> half spectra [n][h][w/2+1] (w even, phalf planned for w/2).
+// Plane p is Y[(p0+p) % ny], times mod[(p0+p) / ny] when mod is given, minus
+// mean[p] when mean is given.  tw_half: table for w/2; tw_full: table for w.
+hipError_t launch_rfft_rows(const float *Y, const float *mod, int ny, int p0, int n, const double *mean,
+                            int h, int w, const FftPlan &phalf, const float2 *tw_half, const float2 *tw_full,
+                            float2 *out, hipStream_t s);
+// Column transforms of half spectra S [n][h][Mc]: with Px, reduce
+// sum wgt*Px[(p0+p)/ny]*|S|^2 (DC excluded) into part[p][blocks]; else
+// store |S|^2 into Pout [n][h][Mc].
+int fft_cols_power_blocks(int Mc, const FftPlan &ph);
+hipError_t launch_fft_cols_power(const float2 *S, int n, int h, int Mc, const FftPlan &ph, const float2 *tw_h,
+                                 const float *Px, int ny, int p0, float *Pout, double *part, hipStream_t s);
 
 // ---- reductions and Wiener in the DFT domain --------------------------------
 // Per-plane population variance of float planes [n][N] -> double var[n];
@@ -139,5 +154,19 @@ hipError_t launch_cross(const float2 *Xs, const float2 *Ycache, int ny, int p0, 
 hipError_t launch_pce_reduce(const float2 *z, int n, int h, int w, int nbhd, int peak_mode,
                              const double *xn2, const double *yn2, bool yn2_by_j, int ny, int p0,
                              double *pce, double *ncc, int32_t *peak, void *part, hipStream_t s);
+
+// Fixed-peak fast path: direct sums of the (2*5+1)^2 shifts around 0 plus
+// sum y, sum y^2, sum xc per pair (part [n][pce_direct_blocks][124] doubles);
+// the spectral energy term comes from fft_cols_power or power_dot.
+int pce_direct_blocks(int h, int w);
+size_t pce_direct_part_doubles(int npairs, int h, int w);
+int pce_dot_blocks();
+hipError_t launch_pce_direct(const float *X, const double *xmean, const float *Y, const float *mod, int ny,
+                             int p0, int n, int h, int w, double *part, hipStream_t s);
+hipError_t launch_power_dot(const float *Px, const float *Py, int ny, int p0, int n, int h, int Mc,
+                            double *part, hipStream_t s);
+hipError_t launch_pce_finish_fixed(const double *dpart, int nblk_d, const double *spart, int nblk_s, int n,
+                                   int h, int w, int nbhd, const double *xn2, int ny, int p0, double *pce,
+                                   double *ncc, int32_t *peak, hipStream_t s);
 
 }  // namespace prnu

@@ -197,6 +197,167 @@ __global__ __launch_bounds__(NT) void pce_finish(const float2 *__restrict__ z, i
     }
 }
 
+// ---- fixed-peak fast path ---------------------------------------------------
+// C(s) for the (2*DRAD+1)^2 shifts around 0, computed directly:
+//   D(s) = sum_t xc(t + s) y(t),  xc = X[q] - mean[q] (circular in t + s),
+// with y = mod[q] * Y[j] (or Y[j]); plus sum y, sum y^2 and sum xc.
+// A thread owns 4 consecutive pixels of a 16 x 64 tile; the centred x tile
+// with a DRAD halo sits in LDS; the 121 sums stay in registers across the
+// block's tiles and are reduced once per block.
+constexpr int DRAD = 5;
+constexpr int DNS = 2 * DRAD + 1;
+constexpr int DSTAT = DNS * DNS + 3;  // D(s), sum y, sum y^2, sum xc
+constexpr int DTY = 16, DTX = 64;
+constexpr int XTH = DTY + 2 * DRAD, XTW = DTX + 2 * DRAD, XTWS = 76;
+
+__global__ __launch_bounds__(NT) void pce_direct(const float *__restrict__ X, const double *__restrict__ xmean,
+                                                 PairSel sel, int h, int w, int tiles_x, int ntiles,
+                                                 double *__restrict__ part) {
+    __shared__ float xs[XTH * XTWS];
+    __shared__ float red[NT / 64][DSTAT];
+    const int64_t N = (int64_t)h * w;
+    const int pid = sel.p0 + (int)blockIdx.y;
+    const int q = pid / sel.ny;
+    const float *xp = X + (int64_t)q * N;
+    const float mux = (float)xmean[q];
+    const float *yp = sel.Y + (int64_t)(pid % sel.ny) * N;
+    const float *mp = sel.mod ? sel.mod + (int64_t)q * N : nullptr;
+    const int tid = threadIdx.x;
+    const int ty = tid >> 4, tq = tid & 15;
+    float acc[DNS][DNS];
+#pragma unroll
+    for (int a = 0; a < DNS; ++a)
+#pragma unroll
+        for (int b = 0; b < DNS; ++b) acc[a][b] = 0.f;
+    float sy = 0.f, syy = 0.f, sx = 0.f;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int ty0 = (tile / tiles_x) * DTY, tx0 = (tile % tiles_x) * DTX;
+        __syncthreads();
+        for (int e = tid; e < XTH * XTW; e += NT) {
+            const int i = e / XTW, jj = e - (e / XTW) * XTW;
+            int gr = (ty0 - DRAD + i) % h;
+            gr = gr < 0 ? gr + h : gr;
+            int gc = (tx0 - DRAD + jj) % w;
+            gc = gc < 0 ? gc + w : gc;
+            xs[i * XTWS + jj] = xp[(int64_t)gr * w + gc] - mux;
+        }
+        __syncthreads();
+        const int gy = ty0 + ty, gx = tx0 + 4 * tq;
+        float yv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            float v = 0.f;
+            if (gy < h && gx + u < w) {
+                const int64_t o = (int64_t)gy * w + gx + u;
+                v = mp ? mp[o] * yp[o] : yp[o];
+                sx += xs[(ty + DRAD) * XTWS + 4 * tq + u + DRAD];
+            }
+            yv[u] = v;
+            sy += v;
+            syy = fmaf(v, v, syy);
+        }
+#pragma unroll
+        for (int dy = 0; dy < DNS; ++dy) {
+            const float *row = &xs[(ty + dy) * XTWS + 4 * tq];
+            float xr[4 + 2 * DRAD];
+#pragma unroll
+            for (int t = 0; t < 4 + 2 * DRAD; ++t) xr[t] = row[t];
+#pragma unroll
+            for (int dx = 0; dx < DNS; ++dx)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[dy][dx] = fmaf(xr[u + dx], yv[u], acc[dy][dx]);
+        }
+    }
+    // block reduction: wave shuffles, then across the waves in fixed order
+    const int lane = tid & 63, wv = tid >> 6;
+    auto wsum = [](float v) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        return v;
+    };
+#pragma unroll
+    for (int a = 0; a < DNS; ++a)
+#pragma unroll
+        for (int b = 0; b < DNS; ++b) {
+            const float v = wsum(acc[a][b]);
+            if (lane == 0) red[wv][a * DNS + b] = v;
+        }
+    {
+        const float v0 = wsum(sy), v1 = wsum(syy), v2 = wsum(sx);
+        if (lane == 0) {
+            red[wv][DNS * DNS] = v0;
+            red[wv][DNS * DNS + 1] = v1;
+            red[wv][DNS * DNS + 2] = v2;
+        }
+    }
+    __syncthreads();
+    if (tid < DSTAT) {
+        double t = 0.0;
+        for (int k = 0; k < NT / 64; ++k) t += (double)red[k][tid];
+        part[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * DSTAT + tid] = t;
+    }
+}
+
+// part[p][blk] = sum over the half spectrum of wgt * Px[q] * Py[j] (DC excluded).
+__global__ __launch_bounds__(NT) void power_dot(const float *__restrict__ Px, const float *__restrict__ Py,
+                                                int ny, int p0, int h, int Mc, double *__restrict__ part) {
+    __shared__ double sh[NT / 64];
+    const int pid = p0 + (int)blockIdx.y;
+    const int64_t M = (int64_t)h * Mc;
+    const float *a = Px + (int64_t)(pid / ny) * M;
+    const float *b = Py + (int64_t)(pid % ny) * M;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < M; i += (int64_t)gridDim.x * NT) {
+        const int col = (int)(i % Mc);
+        const float wgt = (col == 0 || col == Mc - 1) ? 1.f : 2.f;
+        acc += (i == 0) ? 0.0 : (double)(wgt * a[i] * b[i]);
+    }
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = acc;
+}
+
+__global__ void pce_finish_fixed(const double *__restrict__ dpart, int nblk_d, const double *__restrict__ spart,
+                                 int nblk_s, int64_t N, int nbhd, const double *__restrict__ xn2, int ny, int p0,
+                                 double *__restrict__ pce, double *__restrict__ ncc,
+                                 int32_t *__restrict__ peak) {
+    __shared__ double st[DSTAT];
+    const int p = blockIdx.x;
+    const int pid = p0 + p;
+    for (int t = threadIdx.x; t < DSTAT; t += blockDim.x) {
+        double s = 0.0;
+        for (int b = 0; b < nblk_d; ++b) s += dpart[((int64_t)p * nblk_d + b) * DSTAT + t];
+        st[t] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double dot = 0.0;
+    for (int b = 0; b < nblk_s; ++b) dot += spart[(int64_t)p * nblk_s + b];
+    const double dN = (double)N;
+    const double sy = st[DNS * DNS], syy = st[DNS * DNS + 1], sx = st[DNS * DNS + 2];
+    const double muy = sy / dN;
+    const int r = nbhd / 2;
+    double n11 = 0.0;
+    for (int dy = -r; dy <= r; ++dy)
+        for (int dx = -r; dx <= r; ++dx) {
+            const double c = st[(dy + DRAD) * DNS + (dx + DRAD)] - muy * sx;
+            n11 += c * c;
+        }
+    const double c0 = st[DRAD * DNS + DRAD] - muy * sx;
+    const double total = dot / dN;
+    const double energy = (total - n11) / (dN - (double)nbhd * nbhd);
+    pce[pid] = energy > 0.0 ? (c0 >= 0.0 ? 1.0 : -1.0) * c0 * c0 / energy : 0.0;
+    if (ncc) {
+        const int q = pid / ny;
+        const double yn = syy - sy * sy / dN;
+        const double den = sqrt(xn2[q] * (yn > 0.0 ? yn : 0.0));
+        ncc[pid] = den > 0.0 ? c0 / den : 0.0;
+    }
+    if (peak) {
+        peak[2 * (int64_t)pid] = 0;
+        peak[2 * (int64_t)pid + 1] = 0;
+    }
+}
+
 inline unsigned blocks(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
 
 }  // namespace
@@ -242,6 +403,46 @@ hipError_t launch_pce_reduce(const float2 *z, int n, int h, int w, int nbhd, int
     pce_partial<<<dim3(RB, (unsigned)n), NT, 0, s>>>(z, N, pp);
     pce_finish<<<(unsigned)n, NT, 0, s>>>(z, h, w, nbhd, peak_mode, pp, xn2, yn2,
                                                 yn2_by_j ? 1 : 0, ny, p0, pce, ncc, peak);
+    return hipGetLastError();
+}
+
+}  // namespace prnu
+
+namespace prnu {
+
+int pce_direct_blocks(int h, int w) {
+    const int tiles = ((h + DTY - 1) / DTY) * ((w + DTX - 1) / DTX);
+    int nb = (tiles + 31) / 32;
+    return nb < 1 ? 1 : nb;
+}
+size_t pce_direct_part_doubles(int npairs, int h, int w) {
+    return (size_t)npairs * pce_direct_blocks(h, w) * DSTAT;
+}
+int pce_dot_blocks() { return 64; }
+
+hipError_t launch_pce_direct(const float *X, const double *xmean, const float *Y, const float *mod, int ny,
+                             int p0, int n, int h, int w, double *part, hipStream_t s) {
+    const int tiles_x = (w + DTX - 1) / DTX;
+    const int ntiles = tiles_x * ((h + DTY - 1) / DTY);
+    PairSel sel{Y, mod, ny, p0};
+    KernelTimer kt("pce_direct", (double)n * h * w * (mod ? 12.0 : 8.0), s);
+    pce_direct<<<dim3((unsigned)pce_direct_blocks(h, w), (unsigned)n), NT, 0, s>>>(X, xmean, sel, h, w,
+                                                                                  tiles_x, ntiles, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_power_dot(const float *Px, const float *Py, int ny, int p0, int n, int h, int Mc,
+                            double *part, hipStream_t s) {
+    KernelTimer kt("power_dot", (double)n * h * Mc * 8.0, s);
+    power_dot<<<dim3((unsigned)pce_dot_blocks(), (unsigned)n), NT, 0, s>>>(Px, Py, ny, p0, h, Mc, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_pce_finish_fixed(const double *dpart, int nblk_d, const double *spart, int nblk_s, int n,
+                                   int h, int w, int nbhd, const double *xn2, int ny, int p0, double *pce,
+                                   double *ncc, int32_t *peak, hipStream_t s) {
+    pce_finish_fixed<<<(unsigned)n, 64, 0, s>>>(dpart, nblk_d, spart, nblk_s, (int64_t)h * w, nbhd, xn2, ny, p0,
+                                                pce, ncc, peak);
     return hipGetLastError();
 }
 

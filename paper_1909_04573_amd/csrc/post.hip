@@ -111,6 +111,13 @@ __global__ __launch_bounds__(NT) void zm_apply_kernel(const float *__restrict__ 
     const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
     const int64_t N = (int64_t)H * W;
     if (i >= N) return;
+    const int f = blockIdx.y;  // frame: planes f*C .. f*C + C-1
+    x += (int64_t)f * C * N;
+    out += (int64_t)f * (luma ? 1 : C) * N;
+    if (rm) {
+        rm += (int64_t)f * C * H;
+        adj += (int64_t)f * C * W;
+    }
     const int r = (int)(i / W), col = (int)(i - (int64_t)r * W);
     if (luma) {
         double acc = 0.0;
@@ -242,26 +249,28 @@ hipError_t launch_ratio(const void *A, const void *B, int acc_mode, int64_t n, f
     return hipGetLastError();
 }
 
-size_t zm_scratch_doubles(int C, int H, int W) {
+size_t zm_scratch_doubles(int nf, int C, int H, int W) {
     const int nch = (H + RCH - 1) / RCH;
-    return (size_t)C * H + (size_t)C * nch * W + (size_t)C * W;
+    const size_t P = (size_t)nf * C;
+    return P * H + P * nch * W + P * W;
 }
 
-hipError_t launch_zero_mean(const float *in, int C, int H, int W, bool zm, bool luma, float *out,
+hipError_t launch_zero_mean(const float *in, int nf, int C, int H, int W, bool zm, bool luma, float *out,
                             double *scratch, hipStream_t s) {
     const int nch = (H + RCH - 1) / RCH;
+    const int P = nf * C;
     double *rm = scratch;
-    double *colpart = rm + (size_t)C * H;
-    double *adj = colpart + (size_t)C * nch * W;
+    double *colpart = rm + (size_t)P * H;
+    double *adj = colpart + (size_t)P * nch * W;
     const int nout = luma ? 1 : C;
-    KernelTimer kt("zero_mean", (double)H * W * 4.0 * (C * (zm ? 3.0 : 1.0) + nout), s);
+    KernelTimer kt("zero_mean", (double)nf * H * W * 4.0 * (C * (zm ? 3.0 : 1.0) + nout), s);
     if (zm) {
-        row_mean_kernel<<<(unsigned)((C * H + 3) / 4), NT, 0, s>>>(in, C * H, W, rm);
-        col_part_kernel<<<dim3(blocks(W), nch, C), NT, 0, s>>>(in, H, W, colpart);
-        col_finish_kernel<<<dim3(blocks(W), C), NT, 0, s>>>(colpart, nch, rm, H, W, adj);
+        row_mean_kernel<<<(unsigned)((P * H + 3) / 4), NT, 0, s>>>(in, P * H, W, rm);
+        col_part_kernel<<<dim3(blocks(W), nch, P), NT, 0, s>>>(in, H, W, colpart);
+        col_finish_kernel<<<dim3(blocks(W), P), NT, 0, s>>>(colpart, nch, rm, H, W, adj);
     }
-    zm_apply_kernel<<<blocks((int64_t)H * W), NT, 0, s>>>(in, C, H, W, zm ? rm : nullptr, adj,
-                                                          luma ? 1 : 0, out);
+    zm_apply_kernel<<<dim3(blocks((int64_t)H * W), nf), NT, 0, s>>>(in, C, H, W, zm ? rm : nullptr, adj,
+                                                                    luma ? 1 : 0, out);
     return hipGetLastError();
 }
 

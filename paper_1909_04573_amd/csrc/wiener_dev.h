@@ -4,7 +4,8 @@
 // extension), the noise variance s2 and the centred windows w = 3, 5, 7, 9:
 //     m_w  = (1/w^2) * sum of q over the w x w window
 //     var  = min_w max(0, m_w - s2)
-//     rho  = s2 / (var + s2)            (0 when the denominator is 0)
+//     rho  = s2 / (var + s2)            (0 when the denominator is 0;
+//                                        hardware reciprocal, <= 1 ulp)
 // The caller multiplies its coefficient by rho: the noise part of it.
 //
 // One thread walks down one column of the tile core: every row's 3/5/7/9-wide
@@ -52,7 +53,7 @@ __device__ __forceinline__ void wiener_column(int r0, int c, float s2, Load load
             est = fminf(est, fmaxf(0.f, v7 * (1.f / 49.f) - s2));
             est = fminf(est, fmaxf(0.f, v9 * (1.f / 81.f) - s2));
             const float den = est + s2;
-            emit(row - 4, den > 0.f ? s2 / den : 0.f);
+            emit(row - 4, den > 0.f ? s2 * __builtin_amdgcn_rcpf(den) : 0.f);
         }
     }
 }

@@ -237,7 +237,8 @@ def _pce_ref(X, Y, mod, mode):
 
 @pytest.mark.parametrize("h,w,mode,modulated", [
     (64, 80, 0, False), (64, 80, 1, True), (120, 160, 0, True), (256, 256, 1, False),
-    (30, 36, 1, True), (1080, 1920, 0, True)])
+    (30, 36, 1, True), (45, 75, 0, True), (36, 50, 0, False), (1080, 1920, 0, True),
+    (1080, 1920, 0, False)])
 def test_pce_match(dev, h, w, mode, modulated):
     _log(f"pce {h}x{w} mode={mode} modulated={modulated}")
     g = synth.rng(synth.CFG_TEST, 5400 + h)
@@ -267,6 +268,26 @@ def test_pce_match(dev, h, w, mode, modulated):
     assert pce[0, 0] > 60
     if mode == 1:
         assert tuple(peak[1, 1]) == ((-5) % h, (-9) % w)
+
+
+def test_pce_fixed_peak_offsets_and_nbhd(dev):
+    """Fixed-peak path with fields far from zero mean and a 7x7 neighbourhood."""
+    g = synth.rng(synth.CFG_TEST, 5600)
+    h, w = 72, 96
+    X = (g.normal(0, 1, size=(2, h, w)) + 50.0).astype(np.float32)
+    Y = (g.normal(0, 1, size=(2, h, w)) - 20.0).astype(np.float32)
+    Y[1] = (0.5 * (X[1] - 50.0) + g.normal(0, 1, size=(h, w)) + 3.0).astype(np.float32)
+    mod = g.uniform(0.5, 2.0, size=(2, h, w)).astype(np.float32)
+    for m in (None, mod):
+        for nb in (7, 11):
+            pce, ncc, _ = prnu.pce_match(up(X, dev), up(Y, dev), up(m, dev) if m is not None else None, nbhd=nb)
+            pce, ncc = down(pce), down(ncc)
+            for q in range(2):
+                for j in range(2):
+                    y = Y[j].astype(np.float64) * (m[q] if m is not None else 1.0)
+                    r = correlate.pce(X[q].astype(np.float64), y, correlate.PEAK_FIXED_00, nbhd=nb)
+                    assert_pce(pce[q, j], r["pce"], what=f"pce[{q},{j}] nbhd={nb}")
+                    assert abs(ncc[q, j] - r["ncc"]) < 1e-5
 
 
 def test_pce_nbhd_and_wrap(dev):
