@@ -53,6 +53,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
+    ap.add_argument("--workload", choices=["video", "stills-precision"], default="video",
+                    help="video: the headline benchmark; stills-precision: the accumulator/storage "
+                         "precision report on 4000x3000 BF16 stills")
+    ap.add_argument("--stills", type=int, default=200)
     return ap.parse_args()
 
 
@@ -88,6 +92,9 @@ def main():
               "the fingerprint path shards by camera with no communication, see the design notes.",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "stills-precision":
+        return precision_main(args)
 
     import numpy as np
     import torch
@@ -318,6 +325,107 @@ def cpu_baseline(frames, queries, ncam, nq, H, W, C, dev, p):
     err = {"fingerprint_rel_l2": k_rel, "fingerprint_max_rel": k_max, "pce_gpu": [float(x) for x in g],
            "pce_oracle": [float(x) for x in ref], "pce_rel_err": pce_rel}
     return cpu, err
+
+
+def precision_main(args):
+    """Precision report on the stills workload: 2 cameras x N 4000x3000
+    grayscale stills with 8x8 block-quantisation noise, stored as BF16,
+    filtered in FP32.  For SDA depths 1 and 10 and each accumulator mode
+    (FP64, compensated FP32, plain FP32) the fingerprints and the PCEs of two
+    held-out stills per camera are compared with the FP64-accumulated ones
+    (accumulation error); the FP64 path on unrounded FP32 frames gives the
+    storage error; the FP64 oracle on a bounded sample of the same BF16-decoded
+    stills gives the compute error of the FP32 filtering."""
+    import numpy as np
+    import torch
+
+    import synth
+    from oracle import correlate, pipeline
+    from paper_1909_04573_amd import prnu
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    prnu.lib()
+    H, W, ncam, n, nq = 3000, 4000, 2, args.stills, 2
+    log(f"generating {ncam} cameras x {n + nq} stills {W}x{H} (block-quantised) on device")
+    f32 = []
+    for c in range(ncam):
+        f, _ = synth.still_frames_torch(c, n + nq, H, W, device=dev)
+        f32.append(f)
+    bf = [f.to(torch.bfloat16) for f in f32]
+    torch.cuda.synchronize()
+    modes = {"f64": prnu.ACC_F64, "kahan_f32": prnu.ACC_KAHAN_F32, "f32": prnu.ACC_F32}
+    flags = prnu.ZM | prnu.WIENER
+    stream = torch.cuda.current_stream(dev)
+    res = {}
+    for d in (1, 10):
+        Ks, P, T = {}, {}, {}
+        for name, mode in list(modes.items()) + [("f64_unrounded", prnu.ACC_F64)]:
+            src = f32 if name == "f64_unrounded" else bf
+            K = torch.empty((ncam, H, W), dtype=torch.float32, device=dev)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for c in range(ncam):
+                A, B = prnu.new_accumulators(1, H, W, mode, device=dev)
+                prnu.fingerprint_accumulate(src[c][:n], d, A, B, acc_mode=mode)
+                prnu.fingerprint_finalize(A, B, mode, flags=flags, out=K[c])
+            e1.record(stream)
+            q = torch.cat([src[c][n:n + nq] for c in range(ncam)]).contiguous()
+            Wq, Iq = prnu.query_residual(q, flags=flags)
+            pce, _, _ = prnu.pce_match(Wq, K, modulate=Iq)
+            torch.cuda.synchronize()
+            Ks[name], P[name] = K.cpu().numpy().astype(np.float64), pce.cpu().numpy()
+            T[name] = e0.elapsed_time(e1)
+            log(f"d={d} {name}: {T[name]:.1f} ms for {ncam} fingerprints")
+        ref, pref = Ks["f64"], P["f64"]
+        row = {}
+        for name in Ks:
+            dk = Ks[name] - ref
+            row[name] = {
+                "fingerprint_rel_l2_vs_f64": float(np.linalg.norm(dk) / np.linalg.norm(ref)),
+                "fingerprint_max_rel_vs_f64": float(np.abs(dk).max() / np.abs(ref).max()),
+                "pce_max_rel_vs_f64": float(np.max(np.abs(P[name] - pref) / np.maximum(np.abs(pref), 1.0))),
+                "stills_per_s": ncam * n / (T[name] / 1e3),
+                "matched_pce": [float(P[name][c * nq + k, c]) for c in range(ncam) for k in range(nq)],
+            }
+        res[str(d)] = row
+    # compute error of the FP32 filtering: oracle on a bounded sample
+    ns, ds = min(20, n), 10
+    log(f"oracle: camera 0, {ns} BF16-decoded stills at d={ds}, one query")
+    dec = bf[0][:ns].float().cpu().numpy().astype(np.float64)
+    unr = f32[0][:ns].cpu().numpy().astype(np.float64)
+    qd = bf[0][n:n + 1].float().cpu().numpy().astype(np.float64)[0]
+    qu = f32[0][n:n + 1].cpu().numpy().astype(np.float64)[0]
+    t0 = time.perf_counter()
+    Kr = pipeline.finalize(*pipeline.fingerprint_accumulate(dec, ds), pipeline.FIN_ZM | pipeline.FIN_WIENER)
+    Wr, Ir = pipeline.query_residual(qd, flags=pipeline.FIN_ZM | pipeline.FIN_WIENER)
+    pr = correlate.pce(Wr, Ir * Kr)["pce"]
+    t_or = time.perf_counter() - t0
+    Ku = pipeline.finalize(*pipeline.fingerprint_accumulate(unr, ds), pipeline.FIN_ZM | pipeline.FIN_WIENER)
+    Wu, Iu = pipeline.query_residual(qu, flags=pipeline.FIN_ZM | pipeline.FIN_WIENER)
+    pu = correlate.pce(Wu, Iu * Ku)["pce"]
+    sample = {}
+    for name, mode in modes.items():
+        A, B = prnu.new_accumulators(1, H, W, mode, device=dev)
+        prnu.fingerprint_accumulate(bf[0][:ns].contiguous(), ds, A, B, acc_mode=mode)
+        K = prnu.fingerprint_finalize(A, B, mode, flags=flags)
+        Wq, Iq = prnu.query_residual(bf[0][n:n + 1].contiguous(), flags=flags)
+        pce, _, _ = prnu.pce_match(Wq, K.unsqueeze(0), modulate=Iq)
+        torch.cuda.synchronize()
+        Kg = K.cpu().numpy().astype(np.float64)
+        g = float(pce.cpu().numpy()[0, 0])
+        sample[name] = {"fingerprint_rel_l2_vs_oracle": float(np.linalg.norm(Kg - Kr) / np.linalg.norm(Kr)),
+                        "fingerprint_max_rel_vs_oracle": float(np.abs(Kg - Kr).max() / np.abs(Kr).max()),
+                        "pce_gpu": g, "pce_oracle": pr, "pce_rel_vs_oracle": abs(g - pr) / max(abs(pr), 1.0)}
+    storage = {"fingerprint_rel_l2_bf16_vs_unrounded": float(np.linalg.norm(Kr - Ku) / np.linalg.norm(Ku)),
+               "pce_bf16": pr, "pce_unrounded": pu}
+    out = {"metric": "fingerprint and PCE error vs FP64 per precision variant, 4000x3000 BF16 stills",
+           "workload": f"stills 4000x3000 gray, {ncam} cameras x {n} stills (+{nq} queries each), block-quantised, "
+                       "BF16 storage, FP32 filtering; ZM + DFT Wiener; PCE fixed (0,0)",
+           "gpu_variants_vs_gpu_f64": res,
+           "oracle_sample": {"sample": f"camera 0, {ns} stills at d={ds} + 1 query, FP64 NumPy, {t_or:.1f} s",
+                             "compute_error": sample, "storage_error": storage}}
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -166,3 +166,81 @@ def video_frames_torch(cam: int, n_frames: int, H: int, W: int, C: int = 3, k_st
 def random_field(shape, *keys: int, std: float = 1.0) -> np.ndarray:
     """White Gaussian field (for correlation tests)."""
     return rng(*keys).normal(0.0, std, size=shape)
+
+
+# ---------------------------------------------------------------- stills with block-DCT quantisation
+def dct8_matrix() -> np.ndarray:
+    """Orthonormal 8-point DCT-II matrix D (rows = frequencies)."""
+    D = np.zeros((8, 8))
+    for u in range(8):
+        a = np.sqrt(1.0 / 8.0) if u == 0 else np.sqrt(2.0 / 8.0)
+        for x in range(8):
+            D[u, x] = a * np.cos((2 * x + 1) * u * np.pi / 16.0)
+    return D
+
+
+def quant_table() -> np.ndarray:
+    """Synthetic quantisation steps q(u, v) = 2 + u + v (not JPEG's table)."""
+    u = np.arange(8)
+    return 2.0 + u[:, None] + u[None, :]
+
+
+def block_quantise(I: np.ndarray) -> np.ndarray:
+    """8x8 block DCT-II, rounding of every coefficient to a multiple of
+    q(u, v), inverse DCT, clip to [0, 255] (H and W multiples of 8)."""
+    H, W = I.shape
+    D, Q = dct8_matrix(), quant_table()
+    B = I.reshape(H // 8, 8, W // 8, 8).transpose(0, 2, 1, 3)
+    C = D @ B @ D.T
+    C = np.rint(C / Q) * Q
+    R = (D.T @ C @ D).transpose(0, 2, 1, 3).reshape(H, W)
+    return np.clip(R, 0.0, 255.0)
+
+
+def still_camera(cam: int, n: int, H: int, W: int, k_std: float = 0.005, noise_std: float = 2.0,
+                 cfg: int = CFG_STILL, first_frame: int = 0):
+    """Grayscale stills: a new blurred texture per still (U[0,1] blurred with
+    sigma 2 px, stretched to [40,220]), PRNU, N(0, 2^2) noise, 8x8 block
+    quantisation noise.  Returns (float64 frames [n][H][W][1] before storage
+    rounding, K)."""
+    K = camera_prnu((H, W), k_std, cfg, cam, 0xC0FFEE)
+    out = np.empty((n, H, W, 1))
+    for i in range(n):
+        g = rng(cfg, cam, 1 + first_frame + i)
+        I0 = stretch(gaussian_blur(g.uniform(0.0, 1.0, size=(H, W)), 2.0))
+        out[i, :, :, 0] = block_quantise(sensor_frame(I0, K, noise_std, g, quantize=False))
+    return out, K
+
+
+def still_frames_torch(cam: int, n: int, H: int, W: int, k_std: float = 0.005, noise_std: float = 2.0,
+                       device="cuda", cfg: int = CFG_STILL, first_frame: int = 0):
+    """Device version of :func:`still_camera` (same recipe, torch's RNG for the
+    per-pixel draws).  Returns float32 frames [n][H][W][1] before storage
+    rounding, and K (float64 numpy)."""
+    import torch
+
+    K = camera_prnu((H, W), k_std, cfg, cam, 0xC0FFEE)
+    Kt = torch.from_numpy(K).to(device=device, dtype=torch.float32)
+    gen = torch.Generator(device=device)
+    gen.manual_seed((MASTER_SEED * 7 + cfg * 7919 + cam * 104729 + first_frame) % (2**63))
+    D = torch.from_numpy(dct8_matrix()).to(device=device, dtype=torch.float32)
+    DT = torch.from_numpy(np.ascontiguousarray(dct8_matrix().T)).to(device=device, dtype=torch.float32)
+    Q = torch.from_numpy(quant_table()).to(device=device, dtype=torch.float32)
+    r = 8
+    x = torch.arange(-r, r + 1, device=device, dtype=torch.float32)
+    kern = torch.exp(-0.5 * (x / 2.0) ** 2)
+    kern = kern / kern.sum()
+    out = torch.empty((n, H, W, 1), dtype=torch.float32, device=device)
+    for i in range(n):
+        u = torch.rand((1, 1, H, W), generator=gen, device=device)
+        u = torch.nn.functional.pad(u, (r, r, r, r), mode="reflect")
+        u = torch.nn.functional.conv2d(u, kern.view(1, 1, 1, -1))
+        u = torch.nn.functional.conv2d(u, kern.view(1, 1, -1, 1))[0, 0]
+        I0 = 40.0 + 180.0 * (u - u.min()) / (u.max() - u.min())
+        I = I0 * (1.0 + Kt) + noise_std * torch.randn((H, W), generator=gen, device=device)
+        B = I.reshape(H // 8, 8, W // 8, 8).permute(0, 2, 1, 3)
+        B = B.contiguous()
+        C = torch.round(torch.matmul(torch.matmul(D, B), DT) / Q) * Q
+        R = torch.matmul(torch.matmul(DT, C.contiguous()), D)
+        out[i, :, :, 0] = R.permute(0, 2, 1, 3).reshape(H, W).clamp_(0.0, 255.0)
+    return out, K
