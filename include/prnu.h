@@ -201,6 +201,55 @@ int prnu_pce_match(const float *X, int nx, const float *Y, int ny, int h, int w,
                    int32_t *peak, void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Post-processing of given planes (the chain prnu_fingerprint_finalize applies
+ * after the ratio): zero-mean per plane, BT.601 luma of channel triples,
+ * DFT-domain Wiener.  planes [n][C][H][W] -> out [n][C or 1][H][W] (no alias).
+ * Zero-mean is linear and self-adjoint, so the same call applies its adjoint.
+ */
+int prnu_postprocess_workspace_size(int n, int C, int H, int W, int flags, size_t *bytes);
+int prnu_postprocess(const float *planes, int n, int C, int H, int W, int flags, float sigma_wf, float *out,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Adjoint of the residual with respect to the shrinkage noise variances
+ * s_l = level_weight[l] * sigma0^2 (the denoiser's parameters; Sec. II-A
+ * residual, Sec. IV denoiser).  Per detail coefficient c with smallest window
+ * mean m of c^2, the residual coefficient is c s / max(s, m), so
+ * dr/ds = c / m where m > s and 0 elsewhere.
+ *
+ * prnu_denoise_residual_ckpt: as prnu_denoise_residual, and also stores those
+ *   sensitivities: ckpt [n_img][prnu_denoise_ckpt_floats] float, per plane
+ *   level 1's [3][Hp/2][Wp/2] (bands lh, hl, hh), then level 2, ... where
+ *   Hp, Wp are H, W padded to multiples of 16.
+ * prnu_denoise_residual_vjp: given dL/dW for n planes (plane p at
+ *   gW + p * gW_plane_stride; stride 0 broadcasts one plane), optionally
+ *   multiplied elementwise by mul[p] ([n][H][W]) and divided by div ([H][W],
+ *   0 where div <= 0) -- the MLE's dK/dW_i = I_i / sum I^2 --, adds
+ *   dL/ds_l summed over the planes to dLds[l] (device doubles, `levels` of them).
+ */
+int prnu_denoise_ckpt_floats(int H, int W, int levels, size_t *floats);
+int prnu_denoise_residual_ckpt(const float *img, int n_img, int H, int W, const prnu_denoise_params *p,
+                               float *resid, float *ckpt, void *ws, size_t ws_bytes, void *stream);
+int prnu_denoise_residual_vjp_workspace_size(int n, int H, int W, const prnu_denoise_params *p,
+                                             size_t *bytes);
+int prnu_denoise_residual_vjp(const float *gW, int64_t gW_plane_stride, const float *mul, const float *div,
+                              int n, int H, int W, const prnu_denoise_params *p, const float *ckpt,
+                              double *dLds, void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Adjoint of the fixed-peak PCE (Sec. IV statistic) for a weighted sum
+ * L = sum_{q,j} weights[q][j] * PCE(X[q], Y'[q][j]) with Y' as in
+ * prnu_pce_match: gX [nx][h][w] = dL/dX, gY [ny][h][w] = dL/dY (the
+ * modulation folded in), both overwritten; pce (nullable) [nx][ny] receives
+ * the PCE values.  weights: device doubles [nx][ny].  h, w > nbhd,
+ * prime factors <= 5.
+ */
+int prnu_pce_vjp_workspace_size(int nx, int ny, int h, int w, size_t *bytes);
+int prnu_pce_vjp(const float *X, int nx, const float *Y, int ny, int h, int w, const float *modulate,
+                 int nbhd, const double *weights, double *pce, float *gX, float *gY, void *ws,
+                 size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Kernel timing (measurement aid, off by default).
  *
  * prnu_timing_enable(1) discards earlier records and brackets every later

@@ -128,19 +128,29 @@ int batch_planes(int n, int H, int W) {
 
 // Forward levels 1..L (with shrinkage) and inverse levels L..2; the caller
 // runs inverse level 1 with its epilogue.
+// Sensitivity checkpoint layout per plane: level 1 [3][Hp/2][Wp/2], then level 2, ...
+size_t ckpt_level_offset(int H, int W, int lvl) {
+    const int Hp = padded(H), Wp = padded(W);
+    size_t off = 0;
+    for (int l = 1; l < lvl; ++l) off += (size_t)3 * (Hp >> l) * (Wp >> l);
+    return off;
+}
+
 int run_pyramid(const Filter &f, const prnu_denoise_params *p, const float *src, int planes, int H,
-                int W, const Pyramid &py, hipStream_t s) {
+                int W, const Pyramid &py, hipStream_t s, float *ckpt = nullptr) {
     const int Hp = padded(H), Wp = padded(W), L = p->levels;
     const float s0 = p->sigma0 * p->sigma0;
+    const int64_t cstride = (int64_t)ckpt_level_offset(H, W, L + 1);
     for (int l = 1; l <= L; ++l) {
         const float s2 = p->level_weight[l - 1] * s0;
+        float *ck = ckpt ? ckpt + ckpt_level_offset(H, W, l) : nullptr;
         if (l == 1) {
             PRNU_HIP(launch_dwt_fwd(p->taps, f, src, (int64_t)H * W, H, W, Hp, Wp, pad_before(H),
-                                    pad_before(W), py.lvl[1], planes, s2, L > 1, s));
+                                    pad_before(W), py.lvl[1], planes, s2, L > 1, s, ck, cstride));
         } else {
             const int nr = Hp >> (l - 1), nc = Wp >> (l - 1);
             PRNU_HIP(launch_dwt_fwd(p->taps, f, py.lvl[l - 1], (int64_t)level_floats(Hp, Wp, l - 1), nr,
-                                    nc, nr, nc, 0, 0, py.lvl[l], planes, s2, l < L, s));
+                                    nc, nr, nc, 0, 0, py.lvl[l], planes, s2, l < L, s, ck, cstride));
         }
     }
     for (int l = L; l >= 2; --l)
@@ -333,6 +343,49 @@ void plan_pce(Carver &cv, int nx, int ny, int h, int w, bool modulated, PcePlan 
 }
 
 
+struct VjpPlan {
+    int nb;
+    float *ll[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    double *part;
+};
+
+void plan_vjp(Carver &cv, int n, int H, int W, const prnu_denoise_params *p, VjpPlan *vp) {
+    vp->nb = batch_planes(n, H, W);
+    const int Hp = padded(H), Wp = padded(W);
+    for (int l = 1; l < p->levels; ++l) vp->ll[l] = cv.take<float>((size_t)vp->nb * (Hp >> l) * (Wp >> l));
+    vp->part = cv.take<double>((size_t)vp->nb * dwt_vjp_tiles(Hp / 2, Wp / 2));
+}
+
+struct PvjpPlan {
+    int P;
+    float2 *tw_h, *tw_w, *Xs, *V, *Z, *T1, *T2;
+    double *xmean, *xn2, *ymean, *yn2, *spart;
+    void *coef;
+};
+
+void plan_pvjp(Carver &cv, int nx, int ny, int h, int w, PvjpPlan *pl) {
+    const int64_t N = (int64_t)h * w;
+    const int64_t npairs = (int64_t)nx * ny;
+    int64_t P = kPceChunkBytes / (4 * N * (int64_t)sizeof(float2));
+    if (P < 1) P = 1;
+    if (P > 64) P = 64;
+    if (P > npairs) P = npairs;
+    pl->P = (int)P;
+    pl->tw_h = cv.take<float2>((size_t)h);
+    pl->tw_w = cv.take<float2>((size_t)w);
+    pl->Xs = cv.take<float2>((size_t)nx * N);
+    pl->V = cv.take<float2>((size_t)P * N);
+    pl->Z = cv.take<float2>((size_t)P * N);
+    pl->T1 = cv.take<float2>((size_t)P * N);
+    pl->T2 = cv.take<float2>((size_t)P * N);
+    pl->xmean = cv.take<double>((size_t)nx);
+    pl->xn2 = cv.take<double>((size_t)nx);
+    pl->ymean = cv.take<double>((size_t)P);
+    pl->yn2 = cv.take<double>((size_t)P);
+    pl->spart = cv.take<double>(stats_part_doubles(nx > (int)P ? nx : (int)P));
+    pl->coef = cv.take<char>(pvjp_coef_bytes((int)P));
+}
+
 // Fixed-peak PCE: C(0) and the shifts around it are direct sums; the total
 // energy of the surface is (1/N) sum_k |X_k|^2 |Y_k|^2 (Parseval), so no
 // inverse transform is needed.
@@ -434,9 +487,31 @@ int prnu_denoise_residual_workspace_size(int n_img, int H, int W, const prnu_den
     return PRNU_OK;
 }
 
+static int denoise_impl(const char *fn, const float *img, int n_img, int H, int W, const prnu_denoise_params *p,
+                        float *resid, float *ckpt, void *ws, size_t ws_bytes, void *stream);
+
 int prnu_denoise_residual(const float *img, int n_img, int H, int W, const prnu_denoise_params *p,
                           float *resid, void *ws, size_t ws_bytes, void *stream) {
-    const char *fn = "prnu_denoise_residual";
+    return denoise_impl("prnu_denoise_residual", img, n_img, H, W, p, resid, nullptr, ws, ws_bytes, stream);
+}
+
+int prnu_denoise_ckpt_floats(int H, int W, int levels, size_t *floats) {
+    set_error("");
+    if (!floats) return fail(PRNU_E_INVAL, "prnu_denoise_ckpt_floats: null output");
+    if (H < 16 || W < 16 || H > kMaxDim || W > kMaxDim || levels < 1 || levels > 4)
+        return fail(PRNU_E_INVAL, "prnu_denoise_ckpt_floats: bad size or levels");
+    *floats = ckpt_level_offset(H, W, levels + 1);
+    return PRNU_OK;
+}
+
+int prnu_denoise_residual_ckpt(const float *img, int n_img, int H, int W, const prnu_denoise_params *p,
+                               float *resid, float *ckpt, void *ws, size_t ws_bytes, void *stream) {
+    if (!ckpt) return fail(PRNU_E_INVAL, "prnu_denoise_residual_ckpt: null checkpoint");
+    return denoise_impl("prnu_denoise_residual_ckpt", img, n_img, H, W, p, resid, ckpt, ws, ws_bytes, stream);
+}
+
+static int denoise_impl(const char *fn, const float *img, int n_img, int H, int W, const prnu_denoise_params *p,
+                        float *resid, float *ckpt, void *ws, size_t ws_bytes, void *stream) {
     set_error("");
     if (!img || !resid) return fail(PRNU_E_INVAL, "%s: null pointer", fn);
     if (img == resid) return fail(PRNU_E_INVAL, "%s: resid may not alias img", fn);
@@ -455,9 +530,10 @@ int prnu_denoise_residual(const float *img, int n_img, int H, int W, const prnu_
     hipStream_t s = (hipStream_t)stream;
     const int Hp = padded(H), Wp = padded(W);
     const int64_t plane = (int64_t)H * W;
+    const size_t cplane = ckpt_level_offset(H, W, p->levels + 1);
     for (int b0 = 0; b0 < n_img; b0 += nb) {
         const int n = n_img - b0 < nb ? n_img - b0 : nb;
-        PRNU_TRY(run_pyramid(f, p, img + b0 * plane, n, H, W, py, s));
+        PRNU_TRY(run_pyramid(f, p, img + b0 * plane, n, H, W, py, s, ckpt ? ckpt + (size_t)b0 * cplane : nullptr));
         PRNU_HIP(launch_dwt_inv(p->taps, f, py.lvl[1], Hp / 2, Wp / 2, p->levels == 1, n, INV_RESID,
                                 resid + b0 * plane, H, W, pad_before(H), pad_before(W), s));
     }
@@ -700,6 +776,152 @@ int prnu_pce_match(const float *X, int nx, const float *Y, int ny, int h, int w,
                                    (int)p0, pce, ncc, peak, pl.ppart, s));
     }
     return PRNU_OK;
+}
+
+int prnu_denoise_residual_vjp_workspace_size(int n, int H, int W, const prnu_denoise_params *p, size_t *bytes) {
+    const char *fn = "prnu_denoise_residual_vjp_workspace_size";
+    set_error("");
+    if (!bytes) return fail(PRNU_E_INVAL, "%s: null output", fn);
+    if (n < 1) return fail(PRNU_E_INVAL, "%s: n must be >= 1", fn);
+    PRNU_TRY(check_dims(H, W, fn));
+    PRNU_TRY(check_params(p, fn));
+    Carver cv(nullptr);
+    VjpPlan vp;
+    plan_vjp(cv, n, H, W, p, &vp);
+    *bytes = cv.off;
+    return PRNU_OK;
+}
+
+int prnu_denoise_residual_vjp(const float *gW, int64_t gW_plane_stride, const float *mul, const float *div, int n,
+                              int H, int W, const prnu_denoise_params *p, const float *ckpt, double *dLds, void *ws,
+                              size_t ws_bytes, void *stream) {
+    const char *fn = "prnu_denoise_residual_vjp";
+    set_error("");
+    if (!gW || !ckpt || !dLds) return fail(PRNU_E_INVAL, "%s: null pointer", fn);
+    if (n < 1) return fail(PRNU_E_INVAL, "%s: n must be >= 1", fn);
+    if (gW_plane_stride < 0) return fail(PRNU_E_INVAL, "%s: negative plane stride", fn);
+    PRNU_TRY(check_dims(H, W, fn));
+    PRNU_TRY(check_params(p, fn));
+    Carver cv(nullptr);
+    VjpPlan vp;
+    plan_vjp(cv, n, H, W, p, &vp);
+    PRNU_TRY(check_ws(cv, ws, ws_bytes, fn));
+    Carver real(ws);
+    plan_vjp(real, n, H, W, p, &vp);
+    Filter f;
+    make_filter(p->taps, &f);
+    hipStream_t s = (hipStream_t)stream;
+    const int Hp = padded(H), Wp = padded(W), L = p->levels;
+    const int64_t plane = (int64_t)H * W;
+    const int64_t cplane = (int64_t)ckpt_level_offset(H, W, L + 1);
+    for (int b0 = 0; b0 < n; b0 += vp.nb) {
+        const int nb = n - b0 < vp.nb ? n - b0 : vp.nb;
+        for (int l = 1; l <= L; ++l) {
+            const int nr = Hp >> (l - 1), nc = Wp >> (l - 1);
+            const float *ck = ckpt + (int64_t)b0 * cplane + ckpt_level_offset(H, W, l);
+            float *llo = l < L ? vp.ll[l] : nullptr;
+            const int tiles = dwt_vjp_tiles(nr / 2, nc / 2);
+            if (l == 1)
+                PRNU_HIP(launch_dwt_vjp(p->taps, f, gW + b0 * gW_plane_stride, gW_plane_stride, H, W,
+                                        mul ? mul + b0 * plane : nullptr, plane, div, Hp, Wp, pad_before(H),
+                                        pad_before(W), llo, ck, cplane, nb, vp.part, s));
+            else
+                PRNU_HIP(launch_dwt_vjp(p->taps, f, vp.ll[l - 1], (int64_t)nr * nc, nr, nc, nullptr, 0, nullptr, nr,
+                                        nc, 0, 0, llo, ck, cplane, nb, vp.part, s));
+            PRNU_HIP(launch_vjp_finish(vp.part, (int64_t)nb * tiles, dLds + (l - 1), s));
+        }
+    }
+    return PRNU_OK;
+}
+
+int prnu_pce_vjp_workspace_size(int nx, int ny, int h, int w, size_t *bytes) {
+    const char *fn = "prnu_pce_vjp_workspace_size";
+    set_error("");
+    if (!bytes) return fail(PRNU_E_INVAL, "%s: null output", fn);
+    if (nx < 1 || ny < 1 || h < 1 || w < 1) return fail(PRNU_E_INVAL, "%s: bad sizes", fn);
+    Carver cv(nullptr);
+    PvjpPlan pl;
+    plan_pvjp(cv, nx, ny, h, w, &pl);
+    *bytes = cv.off;
+    return PRNU_OK;
+}
+
+int prnu_pce_vjp(const float *X, int nx, const float *Y, int ny, int h, int w, const float *modulate, int nbhd,
+                 const double *weights, double *pce, float *gX, float *gY, void *ws, size_t ws_bytes, void *stream) {
+    const char *fn = "prnu_pce_vjp";
+    set_error("");
+    if (!X || !Y || !weights || !gX || !gY) return fail(PRNU_E_INVAL, "%s: null pointer", fn);
+    if (nx < 1 || ny < 1) return fail(PRNU_E_INVAL, "%s: nx and ny must be >= 1", fn);
+    if (nbhd < 1 || !(nbhd & 1)) return fail(PRNU_E_INVAL, "%s: nbhd must be odd and >= 1", fn);
+    if (h <= nbhd || w <= nbhd) return fail(PRNU_E_INVAL, "%s: h and w must exceed nbhd", fn);
+    if ((int64_t)h * w > (int64_t)INT_MAX) return fail(PRNU_E_INVAL, "%s: surface too large", fn);
+    FftPlan ph, pw;
+    PRNU_TRY(check_fft_dims(h, w, fn, &ph, &pw));
+    Carver cv(nullptr);
+    PvjpPlan pl;
+    plan_pvjp(cv, nx, ny, h, w, &pl);
+    PRNU_TRY(check_ws(cv, ws, ws_bytes, fn));
+    Carver real(ws);
+    plan_pvjp(real, nx, ny, h, w, &pl);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t N = (int64_t)h * w;
+    PRNU_HIP(launch_fill_zero(gX, (int64_t)nx * N, s));
+    PRNU_HIP(launch_fill_zero(gY, (int64_t)ny * N, s));
+    PRNU_HIP(launch_twiddles(h, pl.tw_h, s));
+    PRNU_HIP(launch_twiddles(w, pl.tw_w, s));
+    PRNU_HIP(launch_pair_stats(X, nullptr, INT_MAX, 0, nx, N, pl.xmean, pl.xn2, pl.spart, s));
+    PRNU_HIP(launch_pair_center(X, nullptr, INT_MAX, 0, nx, N, pl.xmean, pl.Xs, s));
+    PRNU_HIP(launch_fft2(pl.Xs, nx, h, w, ph, pw, pl.tw_h, pl.tw_w, -1, s));
+    const int64_t npairs = (int64_t)nx * ny;
+    for (int64_t p0 = 0; p0 < npairs; p0 += pl.P) {
+        const int n = (int)(npairs - p0 < pl.P ? npairs - p0 : pl.P);
+        PRNU_HIP(launch_pair_stats(Y, modulate, ny, (int)p0, n, N, pl.ymean, pl.yn2, pl.spart, s));
+        PRNU_HIP(launch_pair_center(Y, modulate, ny, (int)p0, n, N, pl.ymean, pl.V, s));
+        PRNU_HIP(launch_fft2(pl.V, n, h, w, ph, pw, pl.tw_h, pl.tw_w, -1, s));
+        PRNU_HIP(hipMemcpyAsync(pl.Z, pl.V, (size_t)n * N * sizeof(float2), hipMemcpyDeviceToDevice, s));
+        PRNU_HIP(launch_cross(pl.Xs, nullptr, ny, (int)p0, n, N, pl.Z, s));
+        PRNU_HIP(launch_fft2(pl.Z, n, h, w, ph, pw, pl.tw_h, pl.tw_w, +1, s));
+        PRNU_HIP(launch_pvjp(pl.Z, pl.V, pl.T1, pl.T2, pl.Xs, n, h, w, nbhd, ny, (int)p0, ph, pw, pl.tw_h, pl.tw_w,
+                             pl.coef, weights, modulate, pce, gX, gY, s));
+    }
+    return PRNU_OK;
+}
+
+int prnu_postprocess_workspace_size(int n, int C, int H, int W, int flags, size_t *bytes) {
+    const char *fn = "prnu_postprocess_workspace_size";
+    set_error("");
+    if (!bytes) return fail(PRNU_E_INVAL, "%s: null output", fn);
+    if (n < 1 || (C != 1 && C != 3)) return fail(PRNU_E_INVAL, "%s: bad n or C", fn);
+    if (H < 1 || W < 1 || H > kMaxDim || W > kMaxDim) return fail(PRNU_E_INVAL, "%s: bad H x W", fn);
+    PRNU_TRY(check_flags(flags, fn));
+    Carver cv(nullptr);
+    PostWs pw;
+    carve_post(cv, n, C, H, W, flags, &pw);
+    *bytes = cv.off;
+    return PRNU_OK;
+}
+
+int prnu_postprocess(const float *planes, int n, int C, int H, int W, int flags, float sigma_wf, float *out,
+                     void *ws, size_t ws_bytes, void *stream) {
+    const char *fn = "prnu_postprocess";
+    set_error("");
+    if (!planes || !out) return fail(PRNU_E_INVAL, "%s: null pointer", fn);
+    if (planes == out) return fail(PRNU_E_INVAL, "%s: out may not alias planes", fn);
+    if (n < 1 || (C != 1 && C != 3)) return fail(PRNU_E_INVAL, "%s: bad n or C", fn);
+    if (H < 1 || W < 1 || H > kMaxDim || W > kMaxDim) return fail(PRNU_E_INVAL, "%s: bad H x W", fn);
+    PRNU_TRY(check_flags(flags, fn));
+    if (!std::isfinite(sigma_wf)) return fail(PRNU_E_INVAL, "%s: sigma_wf must be finite", fn);
+    if (flags & PRNU_WIENER) {
+        FftPlan a, b;
+        PRNU_TRY(check_fft_dims(H, W, fn, &a, &b));
+    }
+    Carver cv(nullptr);
+    PostWs pw;
+    carve_post(cv, n, C, H, W, flags, &pw);
+    PRNU_TRY(check_ws(cv, ws, ws_bytes, fn));
+    Carver real(ws);
+    carve_post(real, n, C, H, W, flags, &pw);
+    return run_post(planes, n, C, H, W, flags, sigma_wf, out, pw, false, (hipStream_t)stream);
 }
 
 }  // extern "C"

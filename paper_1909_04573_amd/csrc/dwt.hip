@@ -61,7 +61,8 @@ template <int TAPS>
 __global__ __launch_bounds__(NT) void dwt_fwd_wiener(const float *__restrict__ src, int64_t src_stride,
                                                      int src_rows, int src_cols, int n_r, int n_c,
                                                      int off_r, int off_c, float *__restrict__ out,
-                                                     float s2, int tiles_c, int write_ll, Filter f) {
+                                                     float s2, int tiles_c, int write_ll, Filter f,
+                                                     float *__restrict__ ckpt, int64_t ckpt_stride) {
     using G = FwdGeom<TAPS>;
     constexpr int IN = G::IN, INS = G::INS, NC = G::NC;
     __shared__ __align__(16) float tile[G::TILE];  // input samples; later squares + core coefficients
@@ -209,10 +210,16 @@ __global__ __launch_bounds__(NT) void dwt_fwd_wiener(const float *__restrict__ s
         const float *Cc = cb + s * T * T;
         float *ob = op + (int64_t)(s + 1) * band;
         const int gco = k0c + kcl;
+        float *cp = ckpt ? ckpt + (int64_t)blockIdx.y * ckpt_stride + (int64_t)s * band : nullptr;
         auto load = [&](int kr, int kc) { return Q[kr * NC + kc]; };
-        auto emit = [&](int ko, float rho) {
+        auto emit = [&](int ko, float rho, float den) {
             const int gro = gr0 + ko;
-            if (gro < hk && gco < wk) ob[(int64_t)gro * wk + gco] = Cc[(ko - HALO) * T + kcl] * rho;
+            if (gro < hk && gco < wk) {
+                const float c = Cc[(ko - HALO) * T + kcl];
+                ob[(int64_t)gro * wk + gco] = c * rho;
+                // sensitivity dr/ds = c / m where the window mean m exceeds s2, else 0
+                if (cp) cp[(int64_t)gro * wk + gco] = den > s2 ? c * __builtin_amdgcn_rcpf(den) : 0.f;
+            }
         };
         wiener_column<T / 2>(half * (T / 2), kcl, s2, load, emit);
     }
@@ -479,7 +486,8 @@ inline unsigned ceil_div(int a, int b) { return (unsigned)((a + b - 1) / b); }
 
 hipError_t launch_dwt_fwd(int taps, const Filter &f, const float *src, int64_t src_stride,
                           int src_rows, int src_cols, int n_r, int n_c, int off_r, int off_c,
-                          float *out, int planes, float s2, bool write_ll, hipStream_t s) {
+                          float *out, int planes, float s2, bool write_ll, hipStream_t s, float *ckpt,
+                          int64_t ckpt_stride) {
     const int hk = n_r / 2, wk = n_c / 2;
     const int tr = (int)ceil_div(hk, T), tc = (int)ceil_div(wk, T);
     dim3 grid((unsigned)(tr * tc), (unsigned)planes);
@@ -488,10 +496,10 @@ hipError_t launch_dwt_fwd(int taps, const Filter &f, const float *src, int64_t s
     KernelTimer kt(taps == 16 ? "dwt_fwd_wiener<16>" : "dwt_fwd_wiener<8>", bytes, s);
     if (taps == 16)
         dwt_fwd_wiener<16><<<grid, NT, 0, s>>>(src, src_stride, src_rows, src_cols, n_r, n_c, off_r,
-                                               off_c, out, s2, tc, write_ll ? 1 : 0, f);
+                                               off_c, out, s2, tc, write_ll ? 1 : 0, f, ckpt, ckpt_stride);
     else
         dwt_fwd_wiener<8><<<grid, NT, 0, s>>>(src, src_stride, src_rows, src_cols, n_r, n_c, off_r,
-                                              off_c, out, s2, tc, write_ll ? 1 : 0, f);
+                                              off_c, out, s2, tc, write_ll ? 1 : 0, f, ckpt, ckpt_stride);
     return hipGetLastError();
 }
 

@@ -57,9 +57,13 @@ hipError_t launch_sda(const void *frames, int dtype, int n_frames, int H, int W,
 // stored src_rows x src_cols; the level input is the n_r x n_c plane obtained
 // by symmetric padding with (off_r, off_c) samples before (level 1) or the
 // plane itself (off = 0, n = stored size).  out: [planes][4][n_r/2][n_c/2].
+// ckpt (nullable): per plane (stride ckpt_stride) the level's [3][n_r/2][n_c/2]
+// sensitivities c/m of the detail coefficients whose window mean m exceeds s2
+// (0 elsewhere), in subband order lh, hl, hh.
 hipError_t launch_dwt_fwd(int taps, const Filter &f, const float *src, int64_t src_stride,
                           int src_rows, int src_cols, int n_r, int n_c, int off_r, int off_c,
-                          float *out, int planes, float s2, bool write_ll, hipStream_t s);
+                          float *out, int planes, float s2, bool write_ll, hipStream_t s,
+                          float *ckpt = nullptr, int64_t ckpt_stride = 0);
 
 enum InvEpilogue { INV_PLANE = 0, INV_RESID = 1, INV_MLE = 2 };
 
@@ -168,5 +172,27 @@ hipError_t launch_power_dot(const float *Px, const float *Py, int ny, int p0, in
 hipError_t launch_pce_finish_fixed(const double *dpart, int nblk_d, const double *spart, int nblk_s, int n,
                                    int h, int w, int nbhd, const double *xn2, int ny, int p0, double *pce,
                                    double *ncc, int32_t *peak, hipStream_t s);
+
+// ---- adjoint -------------------------------------------------------------------
+// Gradient analysis of one level: src planes (stride src_stride, stored
+// src_rows x src_cols; level 1 is zero-embedded into the padded n_r x n_c
+// frame at (off_r, off_c) and optionally scaled by mul (per plane) / div
+// (shared)), approximation to ll_out [planes][n_r/2][n_c/2] (nullable), the
+// detail bands dotted with ckpt ([3][n_r/2][n_c/2] per plane) into
+// part[planes][dwt_vjp_tiles].
+int dwt_vjp_tiles(int hk, int wk);
+hipError_t launch_dwt_vjp(int taps, const Filter &f, const float *src, int64_t src_stride, int src_rows,
+                          int src_cols, const float *mul, int64_t mul_stride, const float *div, int n_r, int n_c,
+                          int off_r, int off_c, float *ll_out, const float *ckpt, int64_t ckpt_stride, int planes,
+                          double *part, hipStream_t s);
+hipError_t launch_vjp_finish(const double *part, int64_t n, double *out, hipStream_t s);
+size_t pvjp_coef_bytes(int n);
+// PCE adjoint of a chunk of n pairs; Z holds the unnormalised inverse
+// transform of X^ conj(V) (N * C), V the transforms of the centred y's.
+hipError_t launch_pvjp(float2 *Z, float2 *V, float2 *T1, float2 *T2, const float2 *Xs, int n, int h, int w,
+                       int nbhd, int ny, int p0, const FftPlan &ph, const FftPlan &pw, const float2 *tw_h,
+                       const float2 *tw_w, void *coef, const double *wts, const float *mod, double *pce, float *gX,
+                       float *gY, hipStream_t s);
+hipError_t launch_fill_zero(float *x, int64_t n, hipStream_t s);
 
 }  // namespace prnu

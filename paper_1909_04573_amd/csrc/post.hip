@@ -226,7 +226,7 @@ __global__ __launch_bounds__(NT) void spectral_wiener_kernel(const float2 *__res
         const int half = threadIdx.x / WT, kcl = threadIdx.x & (WT - 1);
         const int gc = tc * WT + kcl;
         auto load = [&](int r, int c) { return q[r * WNCS + c]; };
-        auto emit = [&](int ko, float rho) {
+        auto emit = [&](int ko, float rho, float) {
             const int gr = r0 + ko;
             if (gr < h && gc < w) {
                 const float2 z = Fp[(int64_t)gr * w + gc];

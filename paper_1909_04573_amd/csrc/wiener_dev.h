@@ -19,8 +19,9 @@
 namespace prnu {
 
 // load(row, col) returns q at tile position (row, col); rows r0 .. r0+NROWS+7
-// and columns c .. c+8 are read; emit(row, rho) receives the factor of the
-// coefficient at (row, c + 4) for rows r0+4 .. r0+NROWS+3.
+// and columns c .. c+8 are read; emit(row, rho, den) receives the factor of
+// the coefficient at (row, c + 4) for rows r0+4 .. r0+NROWS+3, and
+// den = var + s2 (the smallest window mean when it exceeds s2).
 template <int NROWS, typename Load, typename Emit>
 __device__ __forceinline__ void wiener_column(int r0, int c, float s2, Load load, Emit emit) {
     float h3[9], h5[9], h7[9], h9[9];
@@ -53,7 +54,7 @@ __device__ __forceinline__ void wiener_column(int r0, int c, float s2, Load load
             est = fminf(est, fmaxf(0.f, v7 * (1.f / 49.f) - s2));
             est = fminf(est, fmaxf(0.f, v9 * (1.f / 81.f) - s2));
             const float den = est + s2;
-            emit(row - 4, den > 0.f ? s2 * __builtin_amdgcn_rcpf(den) : 0.f);
+            emit(row - 4, den > 0.f ? s2 * __builtin_amdgcn_rcpf(den) : 0.f, den);
         }
     }
 }

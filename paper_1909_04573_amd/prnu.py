@@ -33,6 +33,10 @@ EXPORTS = (
     "prnu_query_residual_workspace_size", "prnu_query_residual",
     "prnu_pce_match_workspace_size", "prnu_pce_match",
     "prnu_timing_enable", "prnu_timing_report",
+    "prnu_postprocess_workspace_size", "prnu_postprocess",
+    "prnu_denoise_ckpt_floats", "prnu_denoise_residual_ckpt",
+    "prnu_denoise_residual_vjp_workspace_size", "prnu_denoise_residual_vjp",
+    "prnu_pce_vjp_workspace_size", "prnu_pce_vjp",
 )
 
 
@@ -80,6 +84,14 @@ def lib() -> ctypes.CDLL:
     L.prnu_pce_match_workspace_size.argtypes = [_I, _I, _I, _I, _I, ctypes.POINTER(_S)]
     L.prnu_pce_match.argtypes = [_P, _I, _P, _I, _I, _I, _P, ctypes.POINTER(PceParams), _P, _P, _P, _P,
                                  _S, _P]
+    L.prnu_postprocess_workspace_size.argtypes = [_I, _I, _I, _I, _I, ctypes.POINTER(_S)]
+    L.prnu_postprocess.argtypes = [_P, _I, _I, _I, _I, _I, _F, _P, _P, _S, _P]
+    L.prnu_denoise_ckpt_floats.argtypes = [_I, _I, _I, ctypes.POINTER(_S)]
+    L.prnu_denoise_residual_ckpt.argtypes = [_P, _I, _I, _I, _DP, _P, _P, _P, _S, _P]
+    L.prnu_denoise_residual_vjp_workspace_size.argtypes = [_I, _I, _I, _DP, ctypes.POINTER(_S)]
+    L.prnu_denoise_residual_vjp.argtypes = [_P, ctypes.c_int64, _P, _P, _I, _I, _I, _DP, _P, _P, _P, _S, _P]
+    L.prnu_pce_vjp_workspace_size.argtypes = [_I, _I, _I, _I, ctypes.POINTER(_S)]
+    L.prnu_pce_vjp.argtypes = [_P, _I, _P, _I, _I, _I, _P, _I, _P, _P, _P, _P, _P, _S, _P]
     L.prnu_timing_enable.argtypes = [_I]
     L.prnu_timing_report.argtypes = [ctypes.c_char_p, _S, ctypes.POINTER(_S)]
     _lib = L
@@ -307,3 +319,79 @@ def timing_report() -> dict:
         name, n, ms, b = line.split("\t")
         out[name] = (int(n), float(ms), float(b))
     return out
+
+
+def postprocess(planes: torch.Tensor, C: int = 1, flags: int = ZM, sigma_wf: float = -1.0) -> torch.Tensor:
+    """Zero-mean / luma / DFT-Wiener of planes [n][C][H][W] (or [n][H][W] for C = 1)."""
+    _cuda(planes, "planes")
+    if planes.dtype != torch.float32:
+        raise ValueError("planes must be float32")
+    H, W = int(planes.shape[-2]), int(planes.shape[-1])
+    n = planes.numel() // (C * H * W)
+    nbytes = _S()
+    _check(lib().prnu_postprocess_workspace_size(n, C, H, W, int(flags), ctypes.byref(nbytes)))
+    ws = workspace(nbytes.value, planes.device)
+    nout = 1 if (C == 3 and flags & LUMA) else C
+    out = torch.empty((n, nout, H, W) if nout > 1 else (n, H, W), dtype=torch.float32, device=planes.device)
+    _check(lib().prnu_postprocess(_ptr(planes), n, C, H, W, int(flags), float(sigma_wf), _ptr(out), _ptr(ws),
+                                  ws.numel(), _stream(planes.device)))
+    return out
+
+
+def denoise_residual_ckpt(img: torch.Tensor, params: DenoiseParams | None = None):
+    """Residuals of planes [n][H][W] and the shrinkage sensitivities the adjoint needs."""
+    _cuda(img, "img")
+    if img.dtype != torch.float32 or img.dim() != 3:
+        raise ValueError("img must be float32 [n][H][W]")
+    n, H, W = img.shape
+    p = params or denoise_params()
+    per = _S()
+    _check(lib().prnu_denoise_ckpt_floats(H, W, p.levels, ctypes.byref(per)))
+    nbytes = _S()
+    _check(lib().prnu_denoise_residual_workspace_size(n, H, W, ctypes.byref(p), ctypes.byref(nbytes)))
+    ws = workspace(nbytes.value, img.device)
+    out = torch.empty_like(img)
+    ckpt = torch.empty((n, per.value), dtype=torch.float32, device=img.device)
+    _check(lib().prnu_denoise_residual_ckpt(_ptr(img), n, H, W, ctypes.byref(p), _ptr(out), _ptr(ckpt), _ptr(ws),
+                                            ws.numel(), _stream(img.device)))
+    return out, ckpt
+
+
+def denoise_residual_vjp(gW: torch.Tensor, ckpt: torch.Tensor, params: DenoiseParams | None = None,
+                         mul: torch.Tensor | None = None, div: torch.Tensor | None = None,
+                         dLds: torch.Tensor | None = None) -> torch.Tensor:
+    """dL/ds_l (float64 [levels]) summed over n planes; gW is [n][H][W] or one
+    [H][W] plane broadcast over n = ckpt.shape[0] planes, scaled by mul/div."""
+    _cuda(gW, "gW")
+    _cuda(ckpt, "ckpt")
+    p = params or denoise_params()
+    n = int(ckpt.shape[0])
+    H, W = int(gW.shape[-2]), int(gW.shape[-1])
+    stride = 0 if gW.dim() == 2 else H * W
+    if gW.dim() == 3 and gW.shape[0] != n:
+        raise ValueError("gW and ckpt disagree on the number of planes")
+    nbytes = _S()
+    _check(lib().prnu_denoise_residual_vjp_workspace_size(n, H, W, ctypes.byref(p), ctypes.byref(nbytes)))
+    ws = workspace(nbytes.value, gW.device)
+    if dLds is None:
+        dLds = torch.zeros(p.levels, dtype=torch.float64, device=gW.device)
+    _check(lib().prnu_denoise_residual_vjp(_ptr(gW), stride, _ptr(mul), _ptr(div), n, H, W, ctypes.byref(p),
+                                           _ptr(ckpt), _ptr(dLds), _ptr(ws), ws.numel(), _stream(gW.device)))
+    return dLds
+
+
+def pce_vjp(X: torch.Tensor, Y: torch.Tensor, weights: torch.Tensor, modulate: torch.Tensor | None = None,
+            nbhd: int = 11):
+    """(PCE [nx][ny], dL/dX, dL/dY) for L = sum weights * PCE, fixed peak."""
+    for t, name in ((X, "X"), (Y, "Y"), (weights, "weights")):
+        _cuda(t, name)
+    nx, h, w = X.shape
+    ny = Y.shape[0]
+    nbytes = _S()
+    _check(lib().prnu_pce_vjp_workspace_size(nx, ny, h, w, ctypes.byref(nbytes)))
+    ws = workspace(nbytes.value, X.device)
+    pce = torch.empty((nx, ny), dtype=torch.float64, device=X.device)
+    gX, gY = torch.empty_like(X), torch.empty_like(Y)
+    _check(lib().prnu_pce_vjp(_ptr(X), nx, _ptr(Y), ny, h, w, _ptr(modulate), int(nbhd), _ptr(weights), _ptr(pce),
+                              _ptr(gX), _ptr(gY), _ptr(ws), ws.numel(), _stream(X.device)))
+    return pce, gX, gY
