@@ -19,9 +19,10 @@
  * --------------------------------
  *  - Array arguments are DEVICE pointers owned by the caller (row-major,
  *    planes contiguous).  The library never allocates device memory and keeps
- *    no device state between calls; every scratch byte comes from the caller's
- *    workspace `ws` of at least the size the matching *_workspace_size call
- *    reports.  The workspace must be 256-byte aligned.
+ *    no device state between calls (a prnu_batch object owns its HIP graph);
+ *    every scratch byte comes from the caller's workspace `ws` of at least the
+ *    size the matching *_workspace_size call reports.  The workspace must be
+ *    256-byte aligned.
  *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  Every
  *    call only enqueues work on it; results are valid once the stream has
  *    been synchronised.  Calls on different streams with different
@@ -248,6 +249,91 @@ int prnu_pce_vjp_workspace_size(int nx, int ny, int h, int w, size_t *bytes);
 int prnu_pce_vjp(const float *X, int nx, const float *Y, int ny, int h, int w, const float *modulate,
                  int nbhd, const double *weights, double *pce, float *gX, float *gY, void *ws,
                  size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched fingerprint accumulation: many cameras of different sizes, frame
+ * counts and SDA group lengths in one sequence of persistent launches (the
+ * SDA -> residual -> MLE chain of prnu_fingerprint_accumulate, Sec. III-B,
+ * for every camera at once).
+ *
+ * Each camera's SDA groups are split into jobs; jobs are packed into rounds
+ * whose means and wavelet pyramids fit `round_bytes` (0 = 8 GiB), at most one
+ * job per camera per round.  A round is one launch per stage over all its
+ * jobs: SDA means, forward levels 1..L, inverse levels L..2, and inverse
+ * level 1 with the MLE fold; the level launches are persistent work queues
+ * whose workgroups take (camera, plane, tile) items from a counter.
+ *
+ * prnu_camera   frames [n_frames][H][W][C] of the batch's dtype; A, B that
+ *               camera's accumulators in the acc_mode layout (as
+ *               prnu_fingerprint_accumulate).  The A and B areas of all
+ *               cameras must be pairwise disjoint.
+ * prnu_batch_create  validates, packs the rounds, writes the work tables into
+ *               `ws` (enqueued on `stream`, then waits for that stream), and
+ *               with PRNU_BATCH_GRAPH captures the whole sequence as one HIP
+ *               graph.  The cameras' buffers and `ws` must stay valid and
+ *               untouched while the object lives.  With PRNU_BATCH_ZERO_ACC
+ *               every launch first zeroes all A and B (with a fill kernel).
+ * prnu_batch_launch  enqueues the sequence (one graph launch with
+ *               PRNU_BATCH_GRAPH) on `stream`; launches of one object must not
+ *               overlap.
+ * prnu_batch_info_get  rounds, launches, SDA frames and denoised padded
+ *               pixels of the batch.
+ * prnu_fingerprint_batch  create (without graph) + launch + destroy.
+ */
+typedef struct prnu_camera {
+    const void *frames;
+    int n_frames, H, W, C, group;
+    void *A, *B;
+} prnu_camera;
+
+typedef struct prnu_batch_info {
+    int rounds;             /* rounds of the schedule                        */
+    int launches;           /* kernel launches per prnu_batch_launch         */
+    int64_t jobs;           /* (camera, run of SDA groups) jobs              */
+    int64_t sda_frames;     /* SDA frames formed and denoised                */
+    int64_t padded_pixels;  /* sum over SDA frames of C * Hp * Wp            */
+    int64_t input_bytes;    /* frame bytes read                              */
+} prnu_batch_info;
+
+typedef struct prnu_batch prnu_batch;
+
+#define PRNU_BATCH_ZERO_ACC 1
+#define PRNU_BATCH_GRAPH 2
+
+int prnu_batch_workspace_size(const prnu_camera *cams, int n_cams, const prnu_denoise_params *p,
+                              size_t round_bytes, size_t *bytes);
+int prnu_batch_create(const prnu_camera *cams, int n_cams, int dtype, const prnu_denoise_params *p, int acc_mode,
+                      int flags, size_t round_bytes, void *ws, size_t ws_bytes, void *stream, prnu_batch **out);
+int prnu_batch_launch(prnu_batch *b, void *stream);
+int prnu_batch_info_get(const prnu_batch *b, prnu_batch_info *info);
+int prnu_batch_destroy(prnu_batch *b);
+int prnu_fingerprint_batch(const prnu_camera *cams, int n_cams, int dtype, const prnu_denoise_params *p,
+                           int acc_mode, size_t round_bytes, void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Tile shapes of the wavelet level kernels (host state, process-wide).
+ *
+ * A forward level with shrinkage, an inverse level, or inverse level 1 with
+ * the MLE fold (kind PRNU_TILE_FWD / _INV / _MLE) works on square tiles of
+ * `tile` subband coefficients per side, 16 or 32 (default 32), chosen per
+ * filter length and subband size hk x wk; the Wiener margin around a forward
+ * tile is fixed at 4 coefficients by the largest (9 x 9) window.
+ * prnu_set_tile: tile 16 or 32, 0 restores the default.
+ * prnu_autotune: for frames of H x W x C and the denoiser `p`, times both
+ *   tiles of every forward level, inverse level 2..L and the MLE fold on
+ *   synthetic planes in `ws` (events on `stream`, waits for them; not under
+ *   graph capture) and keeps the faster; `tiles` (nullable, 12 ints) receives
+ *   the choices: [0..3] forward levels 1..4, [4..7] inverse levels 1..4
+ *   ([4], level 1, is the MLE fold's), [8] the MLE fold; unused entries 0.
+ */
+#define PRNU_TILE_FWD 0
+#define PRNU_TILE_INV 1
+#define PRNU_TILE_MLE 2
+int prnu_get_tile(int kind, int taps, int hk, int wk);
+int prnu_set_tile(int kind, int taps, int hk, int wk, int tile);
+int prnu_autotune_workspace_size(int H, int W, int C, const prnu_denoise_params *p, size_t *bytes);
+int prnu_autotune(int H, int W, int C, const prnu_denoise_params *p, void *ws, size_t ws_bytes, void *stream,
+                  int *tiles);
 
 /* ---------------------------------------------------------------------------
  * Kernel timing (measurement aid, off by default).

@@ -2,23 +2,32 @@
 // with F the locally adaptive wavelet denoiser named in Sec. IV.
 //
 // Forward level (analysis + Wiener shrinkage, one launch per level):
-//   a workgroup owns a T x T tile of every subband.  It stages the
-//   (2(T+2*HALO)+L-2)^2 input samples the tile and a HALO-wide Wiener margin
-//   need into LDS (periodic wrap, plus symmetric padding at level 1), filters
-//   rows then columns in LDS with register-blocked taps held in scalar
-//   registers, keeps the three detail subbands of the (T+2*HALO)^2 region in
-//   LDS, and shrinks the T x T core:
-//       var = min_{w=3,5,7,9} max(0, box_w(c^2)/w^2 - s2)   (zero outside the band)
+//   a workgroup owns a TT x TT tile of every subband (TT = 16 or 32).  It
+//   stages the (2(TT+2*HALO)+L-2)^2 input samples the tile and a HALO-wide
+//   Wiener margin need into LDS (periodic wrap, plus symmetric padding at
+//   level 1), filters rows then columns in LDS with register-blocked taps held
+//   in scalar registers, keeps the squares of the three detail bands over the
+//   (TT+2*HALO)^2 region (zero outside the band) in LDS, and shrinks the core:
+//       var = min_{w=3,5,7,9} max(0, box_w(c^2)/w^2 - s2)
 //       r   = c * s2 / (var + s2)
 //   It writes the approximation (input of the next level) and the residual
 //   detail coefficients r; the shrunk coefficients never touch HBM.
 //
-// Inverse level (synthesis): a workgroup owns a 2T x 2T output tile, stages
-//   the (T+L/2-1)^2 coefficients of the four subbands it needs, synthesises
+// Inverse level (synthesis): a workgroup owns a 2TT x 2TT output tile, stages
+//   the (TT+L/2-1)^2 coefficients of the four subbands it needs, synthesises
 //   columns then rows in LDS and either stores the plane (next level up),
 //   stores the cropped residual, or (level 1 of the fingerprint path) folds
 //   the MLE sums  A += W*I, B += I^2  over a batch of SDA frames in registers
 //   before one read-modify-write of the accumulators.
+//
+// Each level body is a device function of (tile, plane) working in an LDS
+// area handed to it, so the per-plane kernels (tile and plane from blockIdx)
+// and the batched work-queue kernels (planes of many cameras of different
+// sizes in one launch) run the same code.
+
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "internal.h"
 #include "wiener_dev.h"
@@ -26,24 +35,29 @@
 namespace prnu {
 namespace {
 
-constexpr int T = 32;     // subband coefficients per tile side
-constexpr int HALO = 4;   // half of the largest Wiener window (9)
-constexpr int NT = 256;   // threads per workgroup
+constexpr int HALO = 4;  // half of the largest Wiener window (9)
+constexpr int NT = 256;  // threads per workgroup
 
-template <int TAPS>
+template <int TAPS, int TT>
 struct FwdGeom {
-    static constexpr int NC = T + 2 * HALO;       // coefficients per side incl. margin (40)
-    static constexpr int IN = 2 * NC + TAPS - 2;  // input samples per side (94 for 16 taps)
-    static constexpr int INS = (IN + 3) / 4 * 4;  // LDS row stride, 16-byte aligned rows
-    static constexpr int QSZ = 3 * NC * NC + 3 * T * T;  // masked squares + core coefficients
+    static constexpr int NC = TT + 2 * HALO;              // coefficients per side incl. margin
+    static constexpr int IN = 2 * NC + TAPS - 2;          // input samples per side
+    static constexpr int INS = (IN + 3) / 4 * 4;          // LDS row stride, 16-byte aligned rows
+    static constexpr int QSZ = 3 * NC * NC + 3 * TT * TT;  // masked squares + core coefficients
     static constexpr int TILE = IN * INS > QSZ ? IN * INS : QSZ;
+    static constexpr int RL = IN * NC;                    // one row-filtered band
+    static constexpr int LDS = TILE + 2 * RL + 2 * IN;    // floats; the two index maps at the end
+    static_assert(TILE % 4 == 0 && RL % 4 == 0 && NC % 4 == 0, "16-byte aligned LDS areas");
 };
 
-template <int TAPS>
+template <int TAPS, int TT>
 struct InvGeom {
-    static constexpr int NK = T + TAPS / 2 - 1;  // coefficients per side
+    static constexpr int NK = TT + TAPS / 2 - 1;  // coefficients per side
     static constexpr int NKS = NK + 1;
-    static constexpr int NO = 2 * T;             // outputs per side
+    static constexpr int NO = 2 * TT;             // outputs per side
+    static constexpr int SB = 4 * NK * NKS;
+    static constexpr int L1 = NO * NKS;
+    static constexpr int LDS = SB + 2 * L1 + 2 * NK;
 };
 
 // Periodic wrap into [0, n), then symmetric (edge-including) reflection of
@@ -57,50 +71,49 @@ __device__ __forceinline__ int map_index(int p, int n, int off, int stored) {
     return q;
 }
 
-template <int TAPS>
-__global__ __launch_bounds__(NT) void dwt_fwd_wiener(const float *__restrict__ src, int64_t src_stride,
-                                                     int src_rows, int src_cols, int n_r, int n_c,
-                                                     int off_r, int off_c, float *__restrict__ out,
-                                                     float s2, int tiles_c, int write_ll, Filter f,
-                                                     float *__restrict__ ckpt, int64_t ckpt_stride) {
-    using G = FwdGeom<TAPS>;
+// ---------------------------------------------------------------------------
+// Forward level body: subband tile `tile` of plane `plane`.
+template <int TAPS, int TT>
+__device__ __forceinline__ void fwd_body(const FwdArgs &a, int tile, int plane, float *lds, const Filter &f) {
+    using G = FwdGeom<TAPS, TT>;
     constexpr int IN = G::IN, INS = G::INS, NC = G::NC;
-    __shared__ __align__(16) float tile[G::TILE];  // input samples; later squares + core coefficients
-    __shared__ __align__(16) float rlo[IN * NC];
-    __shared__ __align__(16) float rhi[IN * NC];
-    __shared__ int rmap[IN];
-    __shared__ int cmap[IN];
+    float *tbuf = lds;           // input samples; later squares + core coefficients
+    float *rlo = lds + G::TILE;  // row low-pass
+    float *rhi = rlo + G::RL;    // row high-pass
+    int *rmap = reinterpret_cast<int *>(rhi + G::RL);
+    int *cmap = rmap + IN;
 
-    const int hk = n_r >> 1, wk = n_c >> 1;
-    const int tr = blockIdx.x / tiles_c, tc = blockIdx.x - (blockIdx.x / tiles_c) * tiles_c;
-    const int k0r = tr * T, k0c = tc * T;
-    const float *sp = src + (int64_t)blockIdx.y * src_stride;
-    float *op = out + (int64_t)blockIdx.y * 4 * hk * wk;
+    const int hk = a.n_r >> 1, wk = a.n_c >> 1;
+    const int tr = tile / a.tiles_c, tc = tile - (tile / a.tiles_c) * a.tiles_c;
+    const int k0r = tr * TT, k0c = tc * TT;
+    const float *sp = a.src + (int64_t)plane * a.src_stride;
+    float *op = a.out + (int64_t)plane * 4 * hk * wk;
     const int64_t band = (int64_t)hk * wk;
     const int tid = threadIdx.x;
 
     if (tid < IN)
-        rmap[tid] = map_index(2 * (k0r - HALO) + tid, n_r, off_r, src_rows);
+        rmap[tid] = map_index(2 * (k0r - HALO) + tid, a.n_r, a.off_r, a.src_rows);
     else if (tid < 2 * IN)
-        cmap[tid - IN] = map_index(2 * (k0c - HALO) + tid - IN, n_c, off_c, src_cols);
+        cmap[tid - IN] = map_index(2 * (k0c - HALO) + tid - IN, a.n_c, a.off_c, a.src_cols);
     __syncthreads();
 
-    // Stage the input tile: pairs of contiguous samples where the tile's columns
-    // need neither the periodic wrap nor the reflection, single samples otherwise.
-    const int c_src0 = 2 * (k0c - HALO) - off_c;
-    const bool cfast = c_src0 >= 0 && c_src0 + IN <= src_cols && (c_src0 & 1) == 0 && (src_cols & 1) == 0 &&
-                       (src_stride & 1) == 0;
+    // Stage the input tile: pairs of contiguous samples where the tile's
+    // columns need neither the periodic wrap nor the reflection, single
+    // samples otherwise.
+    const int c_src0 = 2 * (k0c - HALO) - a.off_c;
+    const bool cfast = c_src0 >= 0 && c_src0 + IN <= a.src_cols && (c_src0 & 1) == 0 && (a.src_cols & 1) == 0 &&
+                       (a.src_stride & 1) == 0;
     if (cfast) {
         constexpr int IN2 = IN / 2;
         for (int e = tid; e < IN * IN2; e += NT) {
             const int i = e / IN2, j2 = e - (e / IN2) * IN2;
-            const float2 v = *reinterpret_cast<const float2 *>(sp + (int64_t)rmap[i] * src_cols + c_src0 + 2 * j2);
-            *reinterpret_cast<float2 *>(&tile[i * INS + 2 * j2]) = v;
+            const float2 v = *reinterpret_cast<const float2 *>(sp + (int64_t)rmap[i] * a.src_cols + c_src0 + 2 * j2);
+            *reinterpret_cast<float2 *>(&tbuf[i * INS + 2 * j2]) = v;
         }
     } else {
         for (int e = tid; e < IN * IN; e += NT) {
             const int i = e / IN, j = e - (e / IN) * IN;
-            tile[i * INS + j] = sp[(int64_t)rmap[i] * src_cols + cmap[j]];
+            tbuf[i * INS + j] = sp[(int64_t)rmap[i] * a.src_cols + cmap[j]];
         }
     }
     __syncthreads();
@@ -110,7 +123,7 @@ __global__ __launch_bounds__(NT) void dwt_fwd_wiener(const float *__restrict__ s
     constexpr int NX = TAPS + 8;  // TAPS + 6 samples, rounded up to whole float4s
     for (int it = tid; it < IN * NQ; it += NT) {
         const int i = it / NQ, kq = it - (it / NQ) * NQ;
-        const float4 *row = reinterpret_cast<const float4 *>(&tile[i * INS + 8 * kq]);
+        const float4 *row = reinterpret_cast<const float4 *>(&tbuf[i * INS + 8 * kq]);
         float x[NX];
 #pragma unroll
         for (int t = 0; t < NX / 4; ++t) {
@@ -139,104 +152,116 @@ __global__ __launch_bounds__(NT) void dwt_fwd_wiener(const float *__restrict__ s
     // Columns: a quad of coefficient columns by a pair of coefficient rows per
     // item.  Every detail coefficient's square goes to q (zero outside the
     // band: the Wiener windows' zero extension); the core coefficients to cb.
-    float *qb = tile;                // [3][NC][NC]
-    float *cb = tile + 3 * NC * NC;  // [3][T][T]
+    float *qb = tbuf;                // [3][NC][NC]
+    float *cb = tbuf + 3 * NC * NC;  // [3][TT][TT]
     const int gr0 = k0r - HALO, gc0 = k0c - HALO;
     for (int it = tid; it < NQ * (NC / 2); it += NT) {
         const int cq = it % NQ, kp = it / NQ;
         bool cv[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) cv[c] = gc0 + 4 * cq + c >= 0 && gc0 + 4 * cq + c < wk;
-        const bool core_c = cq >= HALO / 4 && cq < (HALO + T) / 4;
+        const bool core_c = cq >= HALO / 4 && cq < (HALO + TT) / 4;
 #pragma unroll
         for (int pass = 0; pass < 2; ++pass) {
             const float *rb = pass == 0 ? rlo : rhi;
             float4 xv[TAPS + 2];
 #pragma unroll
-            for (int t = 0; t < TAPS + 2; ++t) xv[t] = *reinterpret_cast<const float4 *>(&rb[(4 * kp + t) * NC + 4 * cq]);
+            for (int t = 0; t < TAPS + 2; ++t)
+                xv[t] = *reinterpret_cast<const float4 *>(&rb[(4 * kp + t) * NC + 4 * cq]);
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
-                float a[4] = {0.f, 0.f, 0.f, 0.f}, d[4] = {0.f, 0.f, 0.f, 0.f};
+                float lo4[4] = {0.f, 0.f, 0.f, 0.f}, hi4[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int j = 0; j < TAPS; ++j) {
                     const float4 v = xv[2 * u + j];
-                    a[0] = fmaf(f.h[j], v.x, a[0]);
-                    a[1] = fmaf(f.h[j], v.y, a[1]);
-                    a[2] = fmaf(f.h[j], v.z, a[2]);
-                    a[3] = fmaf(f.h[j], v.w, a[3]);
-                    d[0] = fmaf(f.g[j], v.x, d[0]);
-                    d[1] = fmaf(f.g[j], v.y, d[1]);
-                    d[2] = fmaf(f.g[j], v.z, d[2]);
-                    d[3] = fmaf(f.g[j], v.w, d[3]);
+                    lo4[0] = fmaf(f.h[j], v.x, lo4[0]);
+                    lo4[1] = fmaf(f.h[j], v.y, lo4[1]);
+                    lo4[2] = fmaf(f.h[j], v.z, lo4[2]);
+                    lo4[3] = fmaf(f.h[j], v.w, lo4[3]);
+                    hi4[0] = fmaf(f.g[j], v.x, hi4[0]);
+                    hi4[1] = fmaf(f.g[j], v.y, hi4[1]);
+                    hi4[2] = fmaf(f.g[j], v.z, hi4[2]);
+                    hi4[3] = fmaf(f.g[j], v.w, hi4[3]);
                 }
                 const int kr = 2 * kp + u;
                 const bool rv = gr0 + kr >= 0 && gr0 + kr < hk;
-                const bool core = core_c && kr >= HALO && kr < HALO + T;
-                // pass 0 (row low-pass): a = ll, d = hl (band 2); pass 1: a = lh (band 1), d = hh (band 3)
+                const bool core = core_c && kr >= HALO && kr < HALO + TT;
+                // pass 0 (row low-pass): lo4 = ll, hi4 = hl (q band 1);
+                // pass 1 (row high-pass): lo4 = lh (q band 0), hi4 = hh (q band 2)
                 if (pass == 0) {
-                    if (write_ll && core) {
+                    if (a.write_ll && core) {
                         const int gr = gr0 + kr;
                         if (gr < hk)
 #pragma unroll
                             for (int c = 0; c < 4; ++c)
-                                if (cv[c]) op[(int64_t)gr * wk + gc0 + 4 * cq + c] = a[c];
+                                if (cv[c]) op[(int64_t)gr * wk + gc0 + 4 * cq + c] = lo4[c];
                     }
                 } else {
                     *reinterpret_cast<float4 *>(&qb[(0 * NC + kr) * NC + 4 * cq]) =
-                        make_float4(rv && cv[0] ? a[0] * a[0] : 0.f, rv && cv[1] ? a[1] * a[1] : 0.f,
-                                    rv && cv[2] ? a[2] * a[2] : 0.f, rv && cv[3] ? a[3] * a[3] : 0.f);
+                        make_float4(rv && cv[0] ? lo4[0] * lo4[0] : 0.f, rv && cv[1] ? lo4[1] * lo4[1] : 0.f,
+                                    rv && cv[2] ? lo4[2] * lo4[2] : 0.f, rv && cv[3] ? lo4[3] * lo4[3] : 0.f);
                     if (core)
-                        *reinterpret_cast<float4 *>(&cb[(0 * T + kr - HALO) * T + 4 * cq - HALO]) =
-                            make_float4(a[0], a[1], a[2], a[3]);
+                        *reinterpret_cast<float4 *>(&cb[(0 * TT + kr - HALO) * TT + 4 * cq - HALO]) =
+                            make_float4(lo4[0], lo4[1], lo4[2], lo4[3]);
                 }
-                const int sb = pass == 0 ? 1 : 2;  // hl -> band index 1 of q/cb, hh -> 2
+                const int sb = pass == 0 ? 1 : 2;
                 *reinterpret_cast<float4 *>(&qb[(sb * NC + kr) * NC + 4 * cq]) =
-                    make_float4(rv && cv[0] ? d[0] * d[0] : 0.f, rv && cv[1] ? d[1] * d[1] : 0.f,
-                                rv && cv[2] ? d[2] * d[2] : 0.f, rv && cv[3] ? d[3] * d[3] : 0.f);
+                    make_float4(rv && cv[0] ? hi4[0] * hi4[0] : 0.f, rv && cv[1] ? hi4[1] * hi4[1] : 0.f,
+                                rv && cv[2] ? hi4[2] * hi4[2] : 0.f, rv && cv[3] ? hi4[3] * hi4[3] : 0.f);
                 if (core)
-                    *reinterpret_cast<float4 *>(&cb[(sb * T + kr - HALO) * T + 4 * cq - HALO]) =
-                        make_float4(d[0], d[1], d[2], d[3]);
+                    *reinterpret_cast<float4 *>(&cb[(sb * TT + kr - HALO) * TT + 4 * cq - HALO]) =
+                        make_float4(hi4[0], hi4[1], hi4[2], hi4[3]);
             }
         }
     }
     __syncthreads();
 
-    // Wiener shrinkage of the T x T core of each detail band: one thread per
+    // Wiener shrinkage of the TT x TT core of each detail band: one thread per
     // (band, core column, half of the core rows).  Band s of q/cb is lh, hl,
     // hh for s = 0, 1, 2, stored as subbands 1, 2, 3.
-    if (tid < 3 * 2 * T) {
-        const int s = tid / (2 * T), half = (tid / T) & 1, kcl = tid & (T - 1);
+    if (tid < 3 * 2 * TT) {
+        const int s = tid / (2 * TT), half = (tid / TT) & 1, kcl = tid & (TT - 1);
         const float *Q = qb + s * NC * NC;
-        const float *Cc = cb + s * T * T;
+        const float *Cc = cb + s * TT * TT;
         float *ob = op + (int64_t)(s + 1) * band;
+        float *cp = a.ckpt ? a.ckpt + (int64_t)plane * a.ckpt_stride + (int64_t)s * band : nullptr;
         const int gco = k0c + kcl;
-        float *cp = ckpt ? ckpt + (int64_t)blockIdx.y * ckpt_stride + (int64_t)s * band : nullptr;
+        const float s2 = a.s2;
         auto load = [&](int kr, int kc) { return Q[kr * NC + kc]; };
         auto emit = [&](int ko, float rho, float den) {
             const int gro = gr0 + ko;
             if (gro < hk && gco < wk) {
-                const float c = Cc[(ko - HALO) * T + kcl];
+                const float c = Cc[(ko - HALO) * TT + kcl];
                 ob[(int64_t)gro * wk + gco] = c * rho;
                 // sensitivity dr/ds = c / m where the window mean m exceeds s2, else 0
                 if (cp) cp[(int64_t)gro * wk + gco] = den > s2 ? c * __builtin_amdgcn_rcpf(den) : 0.f;
             }
         };
-        wiener_column<T / 2>(half * (T / 2), kcl, s2, load, emit);
+        wiener_column<TT / 2>(half * (TT / 2), kcl, s2, load, emit);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Inverse level.
-
-template <int TAPS>
-__device__ __forceinline__ void inv_load(const float *__restrict__ lp, int hk, int wk, int k0r,
-                                         int k0c, bool zero_approx, float *sb, int *rmap,
-                                         int *cmap) {
-    using G = InvGeom<TAPS>;
-    constexpr int NK = G::NK, NKS = G::NKS;
+// Inverse level pieces.
+template <int TAPS, int TT>
+__device__ __forceinline__ void inv_maps(int hk, int wk, int k0r, int k0c, int *rmap, int *cmap) {
+    constexpr int NK = InvGeom<TAPS, TT>::NK, HT = TAPS / 2;
     const int tid = threadIdx.x;
+    if (tid < NK) {
+        int k = (k0r - (HT - 1) + tid) % hk;
+        rmap[tid] = k < 0 ? k + hk : k;
+    } else if (tid < 2 * NK) {
+        int k = (k0c - (HT - 1) + tid - NK) % wk;
+        cmap[tid - NK] = k < 0 ? k + wk : k;
+    }
+}
+
+template <int TAPS, int TT>
+__device__ __forceinline__ void inv_load(const float *__restrict__ lp, int hk, int wk, bool zero_approx, float *sb,
+                                         const int *rmap, const int *cmap) {
+    constexpr int NK = InvGeom<TAPS, TT>::NK, NKS = InvGeom<TAPS, TT>::NKS;
     const int64_t band = (int64_t)hk * wk;
-    for (int e = tid; e < 4 * NK * NK; e += NT) {
+    for (int e = threadIdx.x; e < 4 * NK * NK; e += NT) {
         const int s = e / (NK * NK);
         const int rem = e - s * NK * NK;
         const int kr = rem / NK, kc = rem - (rem / NK) * NK;
@@ -246,14 +271,12 @@ __device__ __forceinline__ void inv_load(const float *__restrict__ lp, int hk, i
     }
 }
 
-// Columns (axis 0): lo1/hi1[n][kc] for the 2T output rows.
-template <int TAPS>
+// Columns (axis 0): lo1/hi1[n][kc] for the 2TT output rows.
+template <int TAPS, int TT>
 __device__ __forceinline__ void inv_cols(const float *sb, float *lo1, float *hi1, const Filter &f) {
-    using G = InvGeom<TAPS>;
-    constexpr int NK = G::NK, NKS = G::NKS, HT = TAPS / 2;
-    const int tid = threadIdx.x;
+    constexpr int NK = InvGeom<TAPS, TT>::NK, NKS = InvGeom<TAPS, TT>::NKS, HT = TAPS / 2;
     // item: column kc, quad of output rows n = 4pp .. 4pp+3 (coefficient rows 2pp .. 2pp+HT)
-    for (int it = tid; it < NK * (T / 2); it += NT) {
+    for (int it = threadIdx.x; it < NK * (TT / 2); it += NT) {
         const int pp = it / NK, kc = it - (it / NK) * NK;
         float a[HT + 1], lh[HT + 1], hl[HT + 1], hh[HT + 1];
 #pragma unroll
@@ -284,11 +307,10 @@ __device__ __forceinline__ void inv_cols(const float *sb, float *lo1, float *hi1
 }
 
 // Rows (axis 1): four consecutive outputs x[n][4mq .. 4mq+3].
-template <int TAPS>
-__device__ __forceinline__ void inv_row_quad(const float *lo1, const float *hi1, int n, int mq,
-                                             const Filter &f, float out[4]) {
-    using G = InvGeom<TAPS>;
-    constexpr int NKS = G::NKS, HT = TAPS / 2;
+template <int TAPS, int TT>
+__device__ __forceinline__ void inv_row_quad(const float *lo1, const float *hi1, int n, int mq, const Filter &f,
+                                             float out[4]) {
+    constexpr int NKS = InvGeom<TAPS, TT>::NKS, HT = TAPS / 2;
     float l[HT + 1], h[HT + 1];
 #pragma unroll
     for (int t = 0; t <= HT; ++t) {
@@ -309,38 +331,26 @@ __device__ __forceinline__ void inv_row_quad(const float *lo1, const float *hi1,
         }
 }
 
-template <int TAPS, int EPI>
-__global__ __launch_bounds__(NT) void dwt_inv(const float *__restrict__ lvl, int hk, int wk,
-                                              int zero_approx, int tiles_c, float *__restrict__ out,
-                                              int H, int W, int off_r, int off_c, Filter f) {
-    using G = InvGeom<TAPS>;
-    constexpr int NK = G::NK, NKS = G::NKS, NO = G::NO, HT = TAPS / 2;
-    __shared__ float sb[4 * NK * NKS];
-    __shared__ float lo1[NO * NKS];
-    __shared__ float hi1[NO * NKS];
-    __shared__ int rmap[NK];
-    __shared__ int cmap[NK];
-    const int tid = threadIdx.x;
-    const int tr = blockIdx.x / tiles_c, tc = blockIdx.x - (blockIdx.x / tiles_c) * tiles_c;
-    const int k0r = tr * T, k0c = tc * T;
-    if (tid < NK) {
-        int k = (k0r - (HT - 1) + tid) % hk;
-        rmap[tid] = k < 0 ? k + hk : k;
-    } else if (tid < 2 * NK) {
-        int k = (k0c - (HT - 1) + tid - NK) % wk;
-        cmap[tid - NK] = k < 0 ? k + wk : k;
-    }
+template <int TAPS, int TT, int EPI>
+__device__ __forceinline__ void inv_body(const InvArgs &a, int tile, int plane, float *lds, const Filter &f) {
+    using G = InvGeom<TAPS, TT>;
+    constexpr int NO = G::NO;
+    float *sb = lds, *lo1 = lds + G::SB, *hi1 = lo1 + G::L1;
+    int *rmap = reinterpret_cast<int *>(hi1 + G::L1);
+    int *cmap = rmap + G::NK;
+    const int tr = tile / a.tiles_c, tc = tile - (tile / a.tiles_c) * a.tiles_c;
+    const int k0r = tr * TT, k0c = tc * TT;
+    inv_maps<TAPS, TT>(a.hk, a.wk, k0r, k0c, rmap, cmap);
     __syncthreads();
-    const float *lp = lvl + (int64_t)blockIdx.y * 4 * hk * wk;
-    inv_load<TAPS>(lp, hk, wk, k0r, k0c, zero_approx != 0, sb, rmap, cmap);
+    inv_load<TAPS, TT>(a.lvl + (int64_t)plane * 4 * a.hk * a.wk, a.hk, a.wk, a.zero_approx != 0, sb, rmap, cmap);
     __syncthreads();
-    inv_cols<TAPS>(sb, lo1, hi1, f);
+    inv_cols<TAPS, TT>(sb, lo1, hi1, f);
     __syncthreads();
-    const int nr = 2 * hk, nc = 2 * wk;
-    for (int it = tid; it < NO * (NO / 4); it += NT) {
+    const int nr = 2 * a.hk, nc = 2 * a.wk;
+    for (int it = threadIdx.x; it < NO * (NO / 4); it += NT) {
         const int n = it / (NO / 4), mq = it - (it / (NO / 4)) * (NO / 4);
         float x[4];
-        inv_row_quad<TAPS>(lo1, hi1, n, mq, f, x);
+        inv_row_quad<TAPS, TT>(lo1, hi1, n, mq, f, x);
         const int gr = 2 * k0r + n;
         if (gr >= nr) continue;
 #pragma unroll
@@ -348,45 +358,33 @@ __global__ __launch_bounds__(NT) void dwt_inv(const float *__restrict__ lvl, int
             const int gc = 2 * k0c + 4 * mq + u;
             if (gc >= nc) continue;
             if (EPI == INV_PLANE) {
-                out[(int64_t)blockIdx.y * 4 * nr * nc + (int64_t)gr * nc + gc] = x[u];
+                a.out[(int64_t)plane * 4 * nr * nc + (int64_t)gr * nc + gc] = x[u];
             } else {
-                const int y = gr - off_r, xx = gc - off_c;
-                if (y >= 0 && y < H && xx >= 0 && xx < W)
-                    out[(int64_t)blockIdx.y * H * W + (int64_t)y * W + xx] = x[u];
+                const int y = gr - a.off_r, xx = gc - a.off_c;
+                if (y >= 0 && y < a.H && xx >= 0 && xx < a.W)
+                    a.out[(int64_t)plane * a.H * a.W + (int64_t)y * a.W + xx] = x[u];
             }
         }
     }
 }
 
-// Level 1 with the MLE epilogue over nb SDA frames of one channel.
-template <int TAPS, int ACC>
-__global__ __launch_bounds__(NT) void dwt_inv_mle(const float *__restrict__ lvl, int hk, int wk,
-                                                  int zero_approx, int tiles_c, int nb, int C,
-                                                  const float *__restrict__ means, int H, int W,
-                                                  int off_r, int off_c, void *__restrict__ Av,
-                                                  void *__restrict__ Bv, Filter f) {
-    using G = InvGeom<TAPS>;
-    constexpr int NK = G::NK, NKS = G::NKS, NO = G::NO, HT = TAPS / 2;
-    constexpr int ITEMS = NO * (NO / 4) / NT;  // 4
+// Level 1 with the MLE epilogue over the a.nb SDA frames of channel c
+// (planes [nb][C], means [nb][C][H][W]).
+template <int TAPS, int TT, int ACC>
+__device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, float *lds, const Filter &f) {
+    using G = InvGeom<TAPS, TT>;
+    constexpr int NO = G::NO;
+    constexpr int ITEMS = NO * (NO / 4) / NT;  // row quads per thread: 4 (TT = 32) or 1 (TT = 16)
     static_assert(NO * (NO / 4) == ITEMS * NT, "items per thread");
-    __shared__ float sb[4 * NK * NKS];
-    __shared__ float lo1[NO * NKS];
-    __shared__ float hi1[NO * NKS];
-    __shared__ int rmap[NK];
-    __shared__ int cmap[NK];
+    float *sb = lds, *lo1 = lds + G::SB, *hi1 = lo1 + G::L1;
+    int *rmap = reinterpret_cast<int *>(hi1 + G::L1);
+    int *cmap = rmap + G::NK;
     const int tid = threadIdx.x;
-    const int c = blockIdx.y;
-    const int tr = blockIdx.x / tiles_c, tc = blockIdx.x - (blockIdx.x / tiles_c) * tiles_c;
-    const int k0r = tr * T, k0c = tc * T;
-    if (tid < NK) {
-        int k = (k0r - (HT - 1) + tid) % hk;
-        rmap[tid] = k < 0 ? k + hk : k;
-    } else if (tid < 2 * NK) {
-        int k = (k0c - (HT - 1) + tid - NK) % wk;
-        cmap[tid - NK] = k < 0 ? k + wk : k;
-    }
+    const int tr = tile / a.tiles_c, tc = tile - (tile / a.tiles_c) * a.tiles_c;
+    const int k0r = tr * TT, k0c = tc * TT;
+    const int H = a.H, W = a.W, C = a.C;
+    inv_maps<TAPS, TT>(a.hk, a.wk, k0r, k0c, rmap, cmap);
     const int64_t npx = (int64_t)H * W;
-    // per-thread partial sums: ITEMS row quads of 4 pixels
     double sa[ITEMS][4], sbb[ITEMS][4];  // ACC_F64 partials
     float ka[ITEMS][4], kc_[ITEMS][4];   // float partial of A (+ compensation for KAHAN)
     float kb[ITEMS][4], kbc[ITEMS][4];   // ... and of B
@@ -398,24 +396,24 @@ __global__ __launch_bounds__(NT) void dwt_inv_mle(const float *__restrict__ lvl,
             sbb[k][u] = 0.0;
             ka[k][u] = kc_[k][u] = kb[k][u] = kbc[k][u] = 0.f;
         }
-    for (int fr = 0; fr < nb; ++fr) {
+    for (int fr = 0; fr < a.nb; ++fr) {
         __syncthreads();  // maps ready / previous frame's LDS reads done
-        const float *lp = lvl + (int64_t)(fr * C + c) * 4 * hk * wk;
-        inv_load<TAPS>(lp, hk, wk, k0r, k0c, zero_approx != 0, sb, rmap, cmap);
+        inv_load<TAPS, TT>(a.lvl + (int64_t)(fr * C + c) * 4 * a.hk * a.wk, a.hk, a.wk, a.zero_approx != 0, sb,
+                           rmap, cmap);
         __syncthreads();
-        inv_cols<TAPS>(sb, lo1, hi1, f);
+        inv_cols<TAPS, TT>(sb, lo1, hi1, f);
         __syncthreads();
-        const float *Ip = means + (int64_t)(fr * C + c) * npx;
+        const float *Ip = a.means + (int64_t)(fr * C + c) * npx;
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
             const int it = tid + k * NT;
             const int n = it / (NO / 4), mq = it - (it / (NO / 4)) * (NO / 4);
             float x[4];
-            inv_row_quad<TAPS>(lo1, hi1, n, mq, f, x);
-            const int y = 2 * k0r + n - off_r;
+            inv_row_quad<TAPS, TT>(lo1, hi1, n, mq, f, x);
+            const int y = 2 * k0r + n - a.off_r;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int xx = 2 * k0c + 4 * mq + u - off_c;
+                const int xx = 2 * k0c + 4 * mq + u - a.off_c;
                 if (y >= 0 && y < H && xx >= 0 && xx < W) {
                     const float I = Ip[(int64_t)y * W + xx];
                     if (ACC == PRNU_ACC_KAHAN_F32) {
@@ -445,27 +443,27 @@ __global__ __launch_bounds__(NT) void dwt_inv_mle(const float *__restrict__ lvl,
     for (int k = 0; k < ITEMS; ++k) {
         const int it = tid + k * NT;
         const int n = it / (NO / 4), mq = it - (it / (NO / 4)) * (NO / 4);
-        const int y = 2 * k0r + n - off_r;
+        const int y = 2 * k0r + n - a.off_r;
         if (y < 0 || y >= H) continue;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int xx = 2 * k0c + 4 * mq + u - off_c;
+            const int xx = 2 * k0c + 4 * mq + u - a.off_c;
             if (xx < 0 || xx >= W) continue;
             const int64_t o = (int64_t)c * npx + (int64_t)y * W + xx;
             if (ACC == PRNU_ACC_F64) {
-                double *A = static_cast<double *>(Av);
-                double *B = static_cast<double *>(Bv);
+                double *A = static_cast<double *>(a.A);
+                double *B = static_cast<double *>(a.B);
                 A[o] += sa[k][u];
                 B[o] += sbb[k][u];
             } else if (ACC == PRNU_ACC_F32) {
-                float *A = static_cast<float *>(Av);
-                float *B = static_cast<float *>(Bv);
+                float *A = static_cast<float *>(a.A);
+                float *B = static_cast<float *>(a.B);
                 A[o] += ka[k][u];
                 B[o] += kb[k][u];
             } else {
                 // value plane [0], compensation plane [1]
-                float *A = static_cast<float *>(Av);
-                float *B = static_cast<float *>(Bv);
+                float *A = static_cast<float *>(a.A);
+                float *B = static_cast<float *>(a.B);
                 const int64_t cs = (int64_t)C * npx;
                 float s = A[o], t = s + ka[k][u], z = t - s;
                 A[o + cs] += kc_[k][u] + ((s - (t - z)) + (ka[k][u] - z));
@@ -480,75 +478,287 @@ __global__ __launch_bounds__(NT) void dwt_inv_mle(const float *__restrict__ lvl,
     }
 }
 
-inline unsigned ceil_div(int a, int b) { return (unsigned)((a + b - 1) / b); }
+// ---------------------------------------------------------------------------
+// Per-plane kernels.
+template <int TAPS, int TT>
+__global__ __launch_bounds__(NT) void dwt_fwd_wiener(FwdArgs a, Filter f) {
+    __shared__ __align__(16) float lds[FwdGeom<TAPS, TT>::LDS];
+    fwd_body<TAPS, TT>(a, blockIdx.x, blockIdx.y, lds, f);
+}
+
+template <int TAPS, int TT, int EPI>
+__global__ __launch_bounds__(NT) void dwt_inv(InvArgs a, Filter f) {
+    __shared__ __align__(16) float lds[InvGeom<TAPS, TT>::LDS];
+    inv_body<TAPS, TT, EPI>(a, blockIdx.x, blockIdx.y, lds, f);
+}
+
+template <int TAPS, int TT, int ACC>
+__global__ __launch_bounds__(NT) void dwt_inv_mle(MleArgs a, Filter f) {
+    __shared__ __align__(16) float lds[InvGeom<TAPS, TT>::LDS];
+    mle_body<TAPS, TT, ACC>(a, blockIdx.x, blockIdx.y, lds, f);
+}
+
+// ---------------------------------------------------------------------------
+// Work-queue kernels: a persistent grid takes virtual blocks from a counter;
+// virtual block vb belongs to the last descriptor whose block0 <= vb (binary
+// search; block0 ascending, first 0) and is (tile, plane) of that level, tile
+// fastest.  Every workgroup leaves once the counter has passed `total`, so
+// the grid drains whatever its size; the host keeps total + grid < 2^31.
+template <typename D>
+__device__ __forceinline__ int find_desc(const D *__restrict__ d, int nd, int vb) {
+    int lo = 0, hi = nd - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d[mid].block0 <= vb)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// One thread takes the next virtual block for the workgroup (vector atomic on
+// the global counter), the barrier publishes it through LDS.
+__device__ __forceinline__ int next_block(int *ctr, int *slot) {
+    __syncthreads();  // the previous block's LDS use is over
+    if (threadIdx.x == 0) *slot = atomicAdd(ctr, 1);
+    __syncthreads();
+    return *slot;
+}
+
+template <int TAPS, int TT>
+__global__ __launch_bounds__(NT) void dwt_fwd_multi(const FwdDesc *__restrict__ d, int nd, int total, int *ctr,
+                                                    Filter f) {
+    __shared__ __align__(16) float lds[FwdGeom<TAPS, TT>::LDS];
+    __shared__ int slot;
+    for (;;) {
+        const int vb = next_block(ctr, &slot);
+        if (vb >= total) break;
+        const FwdDesc &D = d[find_desc(d, nd, vb)];
+        const int local = vb - (int)D.block0;
+        fwd_body<TAPS, TT>(D.a, local % D.tiles, local / D.tiles, lds, f);
+    }
+}
+
+template <int TAPS, int TT>
+__global__ __launch_bounds__(NT) void dwt_inv_multi(const InvDesc *__restrict__ d, int nd, int total, int *ctr,
+                                                    Filter f) {
+    __shared__ __align__(16) float lds[InvGeom<TAPS, TT>::LDS];
+    __shared__ int slot;
+    for (;;) {
+        const int vb = next_block(ctr, &slot);
+        if (vb >= total) break;
+        const InvDesc &D = d[find_desc(d, nd, vb)];
+        const int local = vb - (int)D.block0;
+        inv_body<TAPS, TT, INV_PLANE>(D.a, local % D.tiles, local / D.tiles, lds, f);
+    }
+}
+
+template <int TAPS, int TT, int ACC>
+__global__ __launch_bounds__(NT) void dwt_mle_multi(const MleDesc *__restrict__ d, int nd, int total, int *ctr,
+                                                    Filter f) {
+    __shared__ __align__(16) float lds[InvGeom<TAPS, TT>::LDS];
+    __shared__ int slot;
+    for (;;) {
+        const int vb = next_block(ctr, &slot);
+        if (vb >= total) break;
+        const MleDesc &D = d[find_desc(d, nd, vb)];
+        const int local = vb - (int)D.block0;
+        mle_body<TAPS, TT, ACC>(D.a, local % D.tiles, local / D.tiles, lds, f);
+    }
+}
+
+__global__ void zero_ints(int *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+// Grey levels in [40, 220] from an integer hash of the index (timing input).
+__global__ void fill_pattern(float *x, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t h = (uint32_t)i * 2654435761u;
+    h ^= h >> 15;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    x[i] = 40.f + (float)(h & 0xFFFFu) * (180.f / 65535.f);
+}
+
+inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+std::mutex g_tile_mu;
+std::map<std::tuple<int, int, int, int>, int> g_tile;
+
+template <typename K>
+int occupancy_of(K kernel) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, NT, 0) != hipSuccess || n < 1) n = 1;
+    return n;
+}
 
 }  // namespace
 
-hipError_t launch_dwt_fwd(int taps, const Filter &f, const float *src, int64_t src_stride,
-                          int src_rows, int src_cols, int n_r, int n_c, int off_r, int off_c,
-                          float *out, int planes, float s2, bool write_ll, hipStream_t s, float *ckpt,
-                          int64_t ckpt_stride) {
+int tile_choice(int kind, int taps, int hk, int wk) {
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    auto it = g_tile.find(std::make_tuple(kind, taps, hk, wk));
+    return it == g_tile.end() ? 32 : it->second;
+}
+
+void set_tile_choice(int kind, int taps, int hk, int wk, int tt) {
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    g_tile[std::make_tuple(kind, taps, hk, wk)] = tt == 16 ? 16 : 32;
+}
+
+hipError_t launch_dwt_fwd(int taps, const Filter &f, const float *src, int64_t src_stride, int src_rows,
+                          int src_cols, int n_r, int n_c, int off_r, int off_c, float *out, int planes, float s2,
+                          bool write_ll, hipStream_t s, float *ckpt, int64_t ckpt_stride) {
     const int hk = n_r / 2, wk = n_c / 2;
-    const int tr = (int)ceil_div(hk, T), tc = (int)ceil_div(wk, T);
-    dim3 grid((unsigned)(tr * tc), (unsigned)planes);
+    const int tt = tile_choice(TK_FWD, taps, hk, wk);
+    FwdArgs a{src, src_stride, src_rows, src_cols, n_r, n_c, off_r, off_c, out, s2,
+              ceil_div(wk, tt), write_ll ? 1 : 0, ckpt, ckpt_stride};
+    dim3 grid((unsigned)tiles_for(tt, hk, wk), (unsigned)planes);
     const double bytes = (double)planes * 4.0 *
                          ((double)src_rows * src_cols + (write_ll ? 4.0 : 3.0) * (double)hk * wk);
     KernelTimer kt(taps == 16 ? "dwt_fwd_wiener<16>" : "dwt_fwd_wiener<8>", bytes, s);
-    if (taps == 16)
-        dwt_fwd_wiener<16><<<grid, NT, 0, s>>>(src, src_stride, src_rows, src_cols, n_r, n_c, off_r,
-                                               off_c, out, s2, tc, write_ll ? 1 : 0, f, ckpt, ckpt_stride);
-    else
-        dwt_fwd_wiener<8><<<grid, NT, 0, s>>>(src, src_stride, src_rows, src_cols, n_r, n_c, off_r,
-                                              off_c, out, s2, tc, write_ll ? 1 : 0, f, ckpt, ckpt_stride);
+    if (taps == 16) {
+        if (tt == 16) dwt_fwd_wiener<16, 16><<<grid, NT, 0, s>>>(a, f);
+        else dwt_fwd_wiener<16, 32><<<grid, NT, 0, s>>>(a, f);
+    } else {
+        if (tt == 16) dwt_fwd_wiener<8, 16><<<grid, NT, 0, s>>>(a, f);
+        else dwt_fwd_wiener<8, 32><<<grid, NT, 0, s>>>(a, f);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_dwt_inv(int taps, const Filter &f, const float *lvl, int hk, int wk,
-                          bool zero_approx, int planes, int epi, float *out, int H, int W,
-                          int off_r, int off_c, hipStream_t s) {
-    const int tr = (int)ceil_div(hk, T), tc = (int)ceil_div(wk, T);
-    dim3 grid((unsigned)(tr * tc), (unsigned)planes);
-    const int za = zero_approx ? 1 : 0;
+hipError_t launch_dwt_inv(int taps, const Filter &f, const float *lvl, int hk, int wk, bool zero_approx, int planes,
+                          int epi, float *out, int H, int W, int off_r, int off_c, hipStream_t s) {
+    const int tt = tile_choice(TK_INV, taps, hk, wk);
+    InvArgs a{lvl, hk, wk, zero_approx ? 1 : 0, ceil_div(wk, tt), out, H, W, off_r, off_c};
+    dim3 grid((unsigned)tiles_for(tt, hk, wk), (unsigned)planes);
     const double outpx = epi == INV_PLANE ? 4.0 * hk * wk : (double)H * W;
     const double bytes = (double)planes * 4.0 * ((zero_approx ? 3.0 : 4.0) * (double)hk * wk + outpx);
     static const char *names[2][2] = {{"dwt_inv<8,plane>", "dwt_inv<8,resid>"},
                                       {"dwt_inv<16,plane>", "dwt_inv<16,resid>"}};
     KernelTimer kt(names[taps == 16][epi == INV_PLANE ? 0 : 1], bytes, s);
-#define PRNU_INV(TP, EP)                                                                        \
-    dwt_inv<TP, EP><<<grid, NT, 0, s>>>(lvl, hk, wk, za, tc, out, H, W, off_r, off_c, f)
+#define PRNU_INV(TP, T_)                                                  \
+    do {                                                                  \
+        if (epi == INV_PLANE) dwt_inv<TP, T_, INV_PLANE><<<grid, NT, 0, s>>>(a, f); \
+        else dwt_inv<TP, T_, INV_RESID><<<grid, NT, 0, s>>>(a, f);        \
+    } while (0)
     if (taps == 16) {
-        if (epi == INV_PLANE) PRNU_INV(16, INV_PLANE); else PRNU_INV(16, INV_RESID);
+        if (tt == 16) PRNU_INV(16, 16); else PRNU_INV(16, 32);
     } else {
-        if (epi == INV_PLANE) PRNU_INV(8, INV_PLANE); else PRNU_INV(8, INV_RESID);
+        if (tt == 16) PRNU_INV(8, 16); else PRNU_INV(8, 32);
     }
 #undef PRNU_INV
     return hipGetLastError();
 }
 
-hipError_t launch_dwt_inv_mle(int taps, const Filter &f, const float *lvl, int hk, int wk,
-                              bool zero_approx, int nb, int C, const float *means, int H, int W,
-                              int off_r, int off_c, int acc_mode, void *A, void *B, hipStream_t s) {
-    const int tr = (int)ceil_div(hk, T), tc = (int)ceil_div(wk, T);
-    dim3 grid((unsigned)(tr * tc), (unsigned)C);
-    const int za = zero_approx ? 1 : 0;
+hipError_t launch_dwt_inv_mle(int taps, const Filter &f, const float *lvl, int hk, int wk, bool zero_approx, int nb,
+                              int C, const float *means, int H, int W, int off_r, int off_c, int acc_mode, void *A,
+                              void *B, hipStream_t s) {
+    const int tt = tile_choice(TK_MLE, taps, hk, wk);
+    MleArgs a{lvl, hk, wk, zero_approx ? 1 : 0, ceil_div(wk, tt), nb, C, means, H, W, off_r, off_c, A, B};
+    dim3 grid((unsigned)tiles_for(tt, hk, wk), (unsigned)C);
     const double accb = acc_mode == PRNU_ACC_F32 ? 16.0 : 32.0;  // A and B, read + write
     const double bytes = (double)nb * C * 4.0 * ((zero_approx ? 3.0 : 4.0) * (double)hk * wk + (double)H * W) +
                          (double)C * H * W * accb;
     KernelTimer kt(taps == 16 ? "dwt_inv_mle<16>" : "dwt_inv_mle<8>", bytes, s);
-#define PRNU_MLE(TP, AC)                                                                          \
-    dwt_inv_mle<TP, AC><<<grid, NT, 0, s>>>(lvl, hk, wk, za, tc, nb, C, means, H, W, off_r, off_c, \
-                                            A, B, f)
+#define PRNU_MLE(TP, T_)                                                                            \
+    do {                                                                                            \
+        if (acc_mode == PRNU_ACC_F64) dwt_inv_mle<TP, T_, PRNU_ACC_F64><<<grid, NT, 0, s>>>(a, f);  \
+        else if (acc_mode == PRNU_ACC_KAHAN_F32)                                                    \
+            dwt_inv_mle<TP, T_, PRNU_ACC_KAHAN_F32><<<grid, NT, 0, s>>>(a, f);                      \
+        else dwt_inv_mle<TP, T_, PRNU_ACC_F32><<<grid, NT, 0, s>>>(a, f);                           \
+    } while (0)
     if (taps == 16) {
-        if (acc_mode == PRNU_ACC_F64) PRNU_MLE(16, PRNU_ACC_F64);
-        else if (acc_mode == PRNU_ACC_KAHAN_F32) PRNU_MLE(16, PRNU_ACC_KAHAN_F32);
-        else PRNU_MLE(16, PRNU_ACC_F32);
+        if (tt == 16) PRNU_MLE(16, 16); else PRNU_MLE(16, 32);
     } else {
-        if (acc_mode == PRNU_ACC_F64) PRNU_MLE(8, PRNU_ACC_F64);
-        else if (acc_mode == PRNU_ACC_KAHAN_F32) PRNU_MLE(8, PRNU_ACC_KAHAN_F32);
-        else PRNU_MLE(8, PRNU_ACC_F32);
+        if (tt == 16) PRNU_MLE(8, 16); else PRNU_MLE(8, 32);
     }
 #undef PRNU_MLE
     return hipGetLastError();
+}
+
+hipError_t launch_fwd_multi(int taps, int tt, const Filter &f, const FwdDesc *d, int nd, int total, int *ctr,
+                            int grid, hipStream_t s) {
+    if (total <= 0 || nd <= 0) return hipSuccess;
+    if (taps == 16) {
+        if (tt == 16) dwt_fwd_multi<16, 16><<<grid, NT, 0, s>>>(d, nd, total, ctr, f);
+        else dwt_fwd_multi<16, 32><<<grid, NT, 0, s>>>(d, nd, total, ctr, f);
+    } else {
+        if (tt == 16) dwt_fwd_multi<8, 16><<<grid, NT, 0, s>>>(d, nd, total, ctr, f);
+        else dwt_fwd_multi<8, 32><<<grid, NT, 0, s>>>(d, nd, total, ctr, f);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_inv_multi(int taps, int tt, const Filter &f, const InvDesc *d, int nd, int total, int *ctr,
+                            int grid, hipStream_t s) {
+    if (total <= 0 || nd <= 0) return hipSuccess;
+    if (taps == 16) {
+        if (tt == 16) dwt_inv_multi<16, 16><<<grid, NT, 0, s>>>(d, nd, total, ctr, f);
+        else dwt_inv_multi<16, 32><<<grid, NT, 0, s>>>(d, nd, total, ctr, f);
+    } else {
+        if (tt == 16) dwt_inv_multi<8, 16><<<grid, NT, 0, s>>>(d, nd, total, ctr, f);
+        else dwt_inv_multi<8, 32><<<grid, NT, 0, s>>>(d, nd, total, ctr, f);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_mle_multi(int taps, int tt, int acc_mode, const Filter &f, const MleDesc *d, int nd, int total,
+                            int *ctr, int grid, hipStream_t s) {
+    if (total <= 0 || nd <= 0) return hipSuccess;
+#define PRNU_MM(TP, T_)                                                                                  \
+    do {                                                                                                 \
+        if (acc_mode == PRNU_ACC_F64)                                                                    \
+            dwt_mle_multi<TP, T_, PRNU_ACC_F64><<<grid, NT, 0, s>>>(d, nd, total, ctr, f);               \
+        else if (acc_mode == PRNU_ACC_KAHAN_F32)                                                         \
+            dwt_mle_multi<TP, T_, PRNU_ACC_KAHAN_F32><<<grid, NT, 0, s>>>(d, nd, total, ctr, f);         \
+        else                                                                                             \
+            dwt_mle_multi<TP, T_, PRNU_ACC_F32><<<grid, NT, 0, s>>>(d, nd, total, ctr, f);               \
+    } while (0)
+    if (taps == 16) {
+        if (tt == 16) PRNU_MM(16, 16); else PRNU_MM(16, 32);
+    } else {
+        if (tt == 16) PRNU_MM(8, 16); else PRNU_MM(8, 32);
+    }
+#undef PRNU_MM
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_ints(int *p, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    zero_ints<<<(n + 255) / 256, 256, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_pattern(float *x, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    fill_pattern<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, n);
+    return hipGetLastError();
+}
+
+int fwd_multi_occupancy(int taps, int tt) {
+    if (taps == 16) return tt == 16 ? occupancy_of(dwt_fwd_multi<16, 16>) : occupancy_of(dwt_fwd_multi<16, 32>);
+    return tt == 16 ? occupancy_of(dwt_fwd_multi<8, 16>) : occupancy_of(dwt_fwd_multi<8, 32>);
+}
+int inv_multi_occupancy(int taps, int tt) {
+    if (taps == 16) return tt == 16 ? occupancy_of(dwt_inv_multi<16, 16>) : occupancy_of(dwt_inv_multi<16, 32>);
+    return tt == 16 ? occupancy_of(dwt_inv_multi<8, 16>) : occupancy_of(dwt_inv_multi<8, 32>);
+}
+int mle_multi_occupancy(int taps, int tt, int acc_mode) {
+#define PRNU_OCC(TP, T_)                                                                              \
+    return acc_mode == PRNU_ACC_F64 ? occupancy_of(dwt_mle_multi<TP, T_, PRNU_ACC_F64>)               \
+           : acc_mode == PRNU_ACC_KAHAN_F32 ? occupancy_of(dwt_mle_multi<TP, T_, PRNU_ACC_KAHAN_F32>) \
+                                            : occupancy_of(dwt_mle_multi<TP, T_, PRNU_ACC_F32>)
+    if (taps == 16) {
+        if (tt == 16) PRNU_OCC(16, 16);
+        PRNU_OCC(16, 32);
+    }
+    if (tt == 16) PRNU_OCC(8, 16);
+    PRNU_OCC(8, 32);
+#undef PRNU_OCC
 }
 
 }  // namespace prnu

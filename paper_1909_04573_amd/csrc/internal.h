@@ -48,6 +48,63 @@ inline size_t level_floats(int Hp, int Wp, int lvl) {
     return (size_t)4 * (size_t)(Hp >> lvl) * (size_t)(Wp >> lvl);
 }
 
+// ---- per-launch argument blocks (shared by the per-plane and the batched,
+// work-queue launches; passed by value) --------------------------------------
+struct FwdArgs {
+    const float *src;
+    int64_t src_stride;
+    int src_rows, src_cols, n_r, n_c, off_r, off_c;
+    float *out;
+    float s2;
+    int tiles_c;
+    int write_ll;
+    float *ckpt;
+    int64_t ckpt_stride;
+};
+struct InvArgs {
+    const float *lvl;
+    int hk, wk, zero_approx, tiles_c;
+    float *out;
+    int H, W, off_r, off_c;
+};
+struct MleArgs {
+    const float *lvl;
+    int hk, wk, zero_approx, tiles_c, nb, C;
+    const float *means;
+    int H, W, off_r, off_c;
+    void *A, *B;
+};
+// One entry of a batched launch: `blocks` virtual workgroups starting at block0.
+struct FwdDesc {
+    FwdArgs a;
+    int tt, tiles, planes, pad;
+    int64_t block0;
+};
+struct InvDesc {
+    InvArgs a;
+    int tt, tiles, planes, pad;
+    int64_t block0;
+};
+struct MleDesc {
+    MleArgs a;
+    int tt, tiles, pad0, pad1;
+    int64_t block0;
+};
+struct SdaDesc {
+    const void *frames;
+    int64_t npx;
+    int dtype, n_frames, C, group, g0, ng, quad, bpg;
+    float *means;
+    int64_t block0;
+};
+
+// Tile side (16 or 32 subband coefficients) per kernel kind and level size;
+// 32 unless prnu_autotune measured otherwise.
+enum TileKind { TK_FWD = 0, TK_INV = 1, TK_MLE = 2 };
+int tile_choice(int kind, int taps, int hk, int wk);
+void set_tile_choice(int kind, int taps, int hk, int wk, int tt);
+inline int tiles_for(int tt, int hk, int wk) { return ((hk + tt - 1) / tt) * ((wk + tt - 1) / tt); }
+
 // ---- kernel launchers (all enqueue on `s`, return the launch status) -------
 // SDA: groups [g0, g1) of `group` frames; outputs indexed from g0.
 hipError_t launch_sda(const void *frames, int dtype, int n_frames, int H, int W, int C, int group,
@@ -81,6 +138,30 @@ hipError_t launch_dwt_inv(int taps, const Filter &f, const float *lvl, int hk, i
 hipError_t launch_dwt_inv_mle(int taps, const Filter &f, const float *lvl, int hk, int wk,
                               bool zero_approx, int nb, int C, const float *means, int H, int W,
                               int off_r, int off_c, int acc_mode, void *A, void *B, hipStream_t s);
+
+// Batched (work-queue) launches of one tile size tt: every workgroup of a
+// grid of `grid` takes virtual blocks from *ctr until `total`; *ctr must be
+// zero at launch, total + grid < 2^31.  Descriptors: block0 ascending from 0,
+// each covering tiles x planes (or tiles x C for the MLE) virtual blocks.
+hipError_t launch_fwd_multi(int taps, int tt, const Filter &f, const FwdDesc *d, int nd, int total, int *ctr,
+                            int grid, hipStream_t s);
+hipError_t launch_inv_multi(int taps, int tt, const Filter &f, const InvDesc *d, int nd, int total, int *ctr,
+                            int grid, hipStream_t s);
+hipError_t launch_mle_multi(int taps, int tt, int acc_mode, const Filter &f, const MleDesc *d, int nd, int total,
+                            int *ctr, int grid, hipStream_t s);
+hipError_t launch_zero_ints(int *p, int n, hipStream_t s);
+hipError_t launch_fill_pattern(float *x, int64_t n, hipStream_t s);
+// Resident workgroups per CU of each batched kernel (for the persistent grid).
+int fwd_multi_occupancy(int taps, int tt);
+int inv_multi_occupancy(int taps, int tt);
+int mle_multi_occupancy(int taps, int tt, int acc_mode);
+
+// Batched SDA means (no sums): a 1-D grid of `total` blocks over the
+// descriptors; quad = sda_quad_ok(...) for the descriptor's buffers, bpg =
+// sda_blocks_per_group(quad, npx), means [ng][C][H][W] of groups g0 .. g0+ng-1.
+bool sda_quad_ok(const void *frames, int dtype, int64_t npx, int C, const void *sums, const void *means);
+int sda_blocks_per_group(bool quad, int64_t npx);
+hipError_t launch_sda_multi(const SdaDesc *d, int nd, int64_t total, hipStream_t s);
 
 // ---- post-processing -------------------------------------------------------
 // K[c] = A[c] / B[c] (0 where B = 0) as float [C][H][W].

@@ -20,14 +20,13 @@ __device__ __forceinline__ float bf16_to_float(uint16_t v) {
     return __uint_as_float((uint32_t)v << 16);
 }
 
+// u8 body: pixel quad block `bx` of absolute group gi, written as output group go.
 template <int C>
-__global__ __launch_bounds__(kThreads) void sda_u8_quads(const uint8_t *__restrict__ frames,
-                                                         int64_t npx, int n_frames, int group,
-                                                         int g0, uint32_t *__restrict__ sums,
-                                                         float *__restrict__ means) {
-    const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;  // pixel quad
+__device__ __forceinline__ void sda_u8_body(const uint8_t *__restrict__ frames, int64_t npx, int n_frames, int group,
+                                            int gi, int go, int64_t bx, uint32_t *__restrict__ sums,
+                                            float *__restrict__ means) {
+    const int64_t q = bx * kThreads + threadIdx.x;  // pixel quad
     if (q * 4 >= npx) return;
-    const int gi = g0 + blockIdx.y;
     const int f0 = gi * group;
     const int cnt = min(group, n_frames - f0);
     uint32_t acc[4 * C];
@@ -59,7 +58,7 @@ __global__ __launch_bounds__(kThreads) void sda_u8_quads(const uint8_t *__restri
         }
     }
     // byte e = 4k+b of the quad is pixel e / C, channel e % C
-    const int64_t gbase = (int64_t)blockIdx.y * C * npx;
+    const int64_t gbase = (int64_t)go * C * npx;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         uint32_t s[4];
@@ -75,18 +74,16 @@ __global__ __launch_bounds__(kThreads) void sda_u8_quads(const uint8_t *__restri
     }
 }
 
-// Generic path: one thread per pixel, any layout / alignment / dtype.
+// Generic body: one thread per pixel, any layout / alignment / dtype.
 template <int DT>
-__global__ __launch_bounds__(kThreads) void sda_generic(const void *__restrict__ frames, int64_t npx,
-                                                        int C, int n_frames, int group, int g0,
-                                                        uint32_t *__restrict__ sums,
-                                                        float *__restrict__ means) {
-    const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+__device__ __forceinline__ void sda_generic_body(const void *__restrict__ frames, int64_t npx, int C, int n_frames,
+                                                 int group, int gi, int go, int64_t bx,
+                                                 uint32_t *__restrict__ sums, float *__restrict__ means) {
+    const int64_t p = bx * kThreads + threadIdx.x;
     if (p >= npx) return;
-    const int gi = g0 + blockIdx.y;
     const int f0 = gi * group;
     const int cnt = min(group, n_frames - f0);
-    const int64_t gbase = (int64_t)blockIdx.y * C * npx;
+    const int64_t gbase = (int64_t)go * C * npx;
     for (int c = 0; c < C; ++c) {
         if (DT == PRNU_U8) {
             const uint8_t *fr = static_cast<const uint8_t *>(frames);
@@ -108,7 +105,74 @@ __global__ __launch_bounds__(kThreads) void sda_generic(const void *__restrict__
     }
 }
 
+template <int C>
+__global__ __launch_bounds__(kThreads) void sda_u8_quads(const uint8_t *__restrict__ frames, int64_t npx,
+                                                         int n_frames, int group, int g0,
+                                                         uint32_t *__restrict__ sums, float *__restrict__ means) {
+    sda_u8_body<C>(frames, npx, n_frames, group, g0 + (int)blockIdx.y, (int)blockIdx.y, blockIdx.x, sums, means);
+}
+
+template <int DT>
+__global__ __launch_bounds__(kThreads) void sda_generic(const void *__restrict__ frames, int64_t npx, int C,
+                                                        int n_frames, int group, int g0,
+                                                        uint32_t *__restrict__ sums, float *__restrict__ means) {
+    sda_generic_body<DT>(frames, npx, C, n_frames, group, g0 + (int)blockIdx.y, (int)blockIdx.y, blockIdx.x, sums,
+                         means);
+}
+
+// Batched SDA: block b of the 1-D grid belongs to the last descriptor with
+// block0 <= b (block0 ascending, first 0); within it, block (b - block0) is
+// pixel block (b - block0) % bpg of output group (b - block0) / bpg.
+__global__ __launch_bounds__(kThreads) void sda_multi(const SdaDesc *__restrict__ d, int nd) {
+    const int64_t vb = blockIdx.x;
+    int lo = 0, hi = nd - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d[mid].block0 <= vb)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const SdaDesc D = d[lo];
+    const int64_t local = vb - D.block0;
+    const int go = (int)(local / D.bpg);
+    const int64_t bx = local - (int64_t)go * D.bpg;
+    if (go >= D.ng) return;
+    const int gi = D.g0 + go;
+    if (D.quad) {
+        const uint8_t *fr = static_cast<const uint8_t *>(D.frames);
+        if (D.C == 3)
+            sda_u8_body<3>(fr, D.npx, D.n_frames, D.group, gi, go, bx, nullptr, D.means);
+        else
+            sda_u8_body<1>(fr, D.npx, D.n_frames, D.group, gi, go, bx, nullptr, D.means);
+    } else if (D.dtype == PRNU_U8) {
+        sda_generic_body<PRNU_U8>(D.frames, D.npx, D.C, D.n_frames, D.group, gi, go, bx, nullptr, D.means);
+    } else if (D.dtype == PRNU_BF16) {
+        sda_generic_body<PRNU_BF16>(D.frames, D.npx, D.C, D.n_frames, D.group, gi, go, bx, nullptr, D.means);
+    } else {
+        sda_generic_body<PRNU_F32>(D.frames, D.npx, D.C, D.n_frames, D.group, gi, go, bx, nullptr, D.means);
+    }
+}
+
 }  // namespace
+
+bool sda_quad_ok(const void *frames, int dtype, int64_t npx, int C, const void *sums, const void *means) {
+    return dtype == PRNU_U8 && (C == 1 || C == 3) && (npx % 4) == 0 &&
+           (reinterpret_cast<uintptr_t>(frames) % 4) == 0 &&
+           (sums == nullptr || reinterpret_cast<uintptr_t>(sums) % 16 == 0) &&
+           (means == nullptr || reinterpret_cast<uintptr_t>(means) % 16 == 0);
+}
+
+int sda_blocks_per_group(bool quad, int64_t npx) {
+    return (int)(((quad ? npx / 4 : npx) + kThreads - 1) / kThreads);
+}
+
+hipError_t launch_sda_multi(const SdaDesc *d, int nd, int64_t total, hipStream_t s) {
+    if (total <= 0 || nd <= 0) return hipSuccess;
+    if (total > 0x7fffffff) return hipErrorInvalidValue;
+    sda_multi<<<(unsigned)total, kThreads, 0, s>>>(d, nd);
+    return hipGetLastError();
+}
 
 hipError_t launch_sda(const void *frames, int dtype, int n_frames, int H, int W, int C, int group,
                       int g0, int g1, uint32_t *sums, float *means, hipStream_t s) {
@@ -119,11 +183,7 @@ hipError_t launch_sda(const void *frames, int dtype, int n_frames, int H, int W,
     const double esz = dtype == PRNU_U8 ? 1.0 : dtype == PRNU_BF16 ? 2.0 : 4.0;
     const double bytes = (double)nread * npx * C * esz +
                          (double)ng * C * npx * ((sums ? 4.0 : 0.0) + (means ? 4.0 : 0.0));
-    const bool quad_ok = dtype == PRNU_U8 && (npx % 4) == 0 &&
-                         (reinterpret_cast<uintptr_t>(frames) % 4) == 0 &&
-                         (sums == nullptr || reinterpret_cast<uintptr_t>(sums) % 16 == 0) &&
-                         (means == nullptr || reinterpret_cast<uintptr_t>(means) % 16 == 0);
-    if (quad_ok && (C == 1 || C == 3)) {
+    if (sda_quad_ok(frames, dtype, npx, C, sums, means)) {
         dim3 grid((unsigned)((npx / 4 + kThreads - 1) / kThreads), (unsigned)ng);
         const uint8_t *fr = static_cast<const uint8_t *>(frames);
         KernelTimer kt(C == 1 ? "sda_u8_quads<1>" : "sda_u8_quads<3>", bytes, s);

@@ -50,6 +50,8 @@ void recycle_all() {
 KernelTimer::KernelTimer(const char *name, double bytes, hipStream_t s) : idx_(-1), s_(s) {
     std::lock_guard<std::mutex> lk(g_mu);
     if (!g_on) return;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return;
     hipEvent_t a = get_event(), b = get_event();
     if (!a || !b) return;
     if (hipEventRecord(a, s) != hipSuccess) return;

@@ -37,7 +37,12 @@ EXPORTS = (
     "prnu_denoise_ckpt_floats", "prnu_denoise_residual_ckpt",
     "prnu_denoise_residual_vjp_workspace_size", "prnu_denoise_residual_vjp",
     "prnu_pce_vjp_workspace_size", "prnu_pce_vjp",
+    "prnu_batch_workspace_size", "prnu_batch_create", "prnu_batch_launch", "prnu_batch_info_get",
+    "prnu_batch_destroy", "prnu_fingerprint_batch",
+    "prnu_get_tile", "prnu_set_tile", "prnu_autotune_workspace_size", "prnu_autotune",
 )
+TILE_FWD, TILE_INV, TILE_MLE = 0, 1, 2
+BATCH_ZERO_ACC, BATCH_GRAPH = 1, 2
 
 
 class PrnuError(RuntimeError):
@@ -53,6 +58,18 @@ class DenoiseParams(ctypes.Structure):
 
 class PceParams(ctypes.Structure):
     _fields_ = [("peak_mode", ctypes.c_int), ("nbhd", ctypes.c_int)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("frames", ctypes.c_void_p), ("n_frames", ctypes.c_int), ("H", ctypes.c_int),
+                ("W", ctypes.c_int), ("C", ctypes.c_int), ("group", ctypes.c_int),
+                ("A", ctypes.c_void_p), ("B", ctypes.c_void_p)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int), ("launches", ctypes.c_int), ("jobs", ctypes.c_int64),
+                ("sda_frames", ctypes.c_int64), ("padded_pixels", ctypes.c_int64),
+                ("input_bytes", ctypes.c_int64)]
 
 
 _lib = None
@@ -92,6 +109,17 @@ def lib() -> ctypes.CDLL:
     L.prnu_denoise_residual_vjp.argtypes = [_P, ctypes.c_int64, _P, _P, _I, _I, _I, _DP, _P, _P, _P, _S, _P]
     L.prnu_pce_vjp_workspace_size.argtypes = [_I, _I, _I, _I, ctypes.POINTER(_S)]
     L.prnu_pce_vjp.argtypes = [_P, _I, _P, _I, _I, _I, _P, _I, _P, _P, _P, _P, _P, _S, _P]
+    _CP = ctypes.POINTER(Camera)
+    L.prnu_batch_workspace_size.argtypes = [_CP, _I, _DP, _S, ctypes.POINTER(_S)]
+    L.prnu_batch_create.argtypes = [_CP, _I, _I, _DP, _I, _I, _S, _P, _S, _P, ctypes.POINTER(_P)]
+    L.prnu_batch_launch.argtypes = [_P, _P]
+    L.prnu_batch_info_get.argtypes = [_P, ctypes.POINTER(BatchInfo)]
+    L.prnu_batch_destroy.argtypes = [_P]
+    L.prnu_fingerprint_batch.argtypes = [_CP, _I, _I, _DP, _I, _S, _P, _S, _P]
+    L.prnu_get_tile.argtypes = [_I, _I, _I, _I]
+    L.prnu_set_tile.argtypes = [_I, _I, _I, _I, _I]
+    L.prnu_autotune_workspace_size.argtypes = [_I, _I, _I, _DP, ctypes.POINTER(_S)]
+    L.prnu_autotune.argtypes = [_I, _I, _I, _DP, _P, _S, _P, ctypes.POINTER(_I)]
     L.prnu_timing_enable.argtypes = [_I]
     L.prnu_timing_report.argtypes = [ctypes.c_char_p, _S, ctypes.POINTER(_S)]
     _lib = L
@@ -395,3 +423,108 @@ def pce_vjp(X: torch.Tensor, Y: torch.Tensor, weights: torch.Tensor, modulate: t
     _check(lib().prnu_pce_vjp(_ptr(X), nx, _ptr(Y), ny, h, w, _ptr(modulate), int(nbhd), _ptr(weights), _ptr(pce),
                               _ptr(gX), _ptr(gY), _ptr(ws), ws.numel(), _stream(X.device)))
     return pce, gX, gY
+
+
+# ---------------------------------------------------------------------------
+# Batched accumulation over many cameras and the tile autotuner.
+
+def _cameras(cams):
+    """cams: sequence of (frames [n][H][W] or [n][H][W][C], group, A, B); one dtype."""
+    arr = (Camera * len(cams))()
+    dts = set()
+    dev = None
+    for i, (frames, group, A, B) in enumerate(cams):
+        frames, dt, n, H, W, C = _frames(frames)
+        _cuda(A, "A")
+        _cuda(B, "B")
+        dts.add(dt)
+        dev = frames.device
+        arr[i] = Camera(frames.data_ptr(), n, H, W, C, int(group), A.data_ptr(), B.data_ptr())
+    if len(dts) != 1:
+        raise ValueError("all cameras of a batch must share one frame dtype")
+    return arr, dts.pop(), dev
+
+
+def batch_workspace_size(cams, params: DenoiseParams | None = None, round_bytes: int = 0) -> int:
+    arr, _, _ = _cameras(cams)
+    p = params or denoise_params()
+    nbytes = _S()
+    _check(lib().prnu_batch_workspace_size(arr, len(cams), ctypes.byref(p), int(round_bytes),
+                                           ctypes.byref(nbytes)))
+    return nbytes.value
+
+
+class Batch:
+    """A planned batch (prnu_batch_create): ``launch()`` enqueues the whole
+    schedule on the current stream (one graph launch with BATCH_GRAPH)."""
+
+    def __init__(self, cams, params: DenoiseParams | None = None, acc_mode: int = ACC_F64,
+                 flags: int = BATCH_GRAPH | BATCH_ZERO_ACC, round_bytes: int = 0, ws: torch.Tensor | None = None):
+        self._h = None
+        arr, dt, dev = _cameras(cams)
+        p = params or denoise_params()
+        nbytes = _S()
+        _check(lib().prnu_batch_workspace_size(arr, len(cams), ctypes.byref(p), int(round_bytes),
+                                               ctypes.byref(nbytes)))
+        if ws is None or ws.numel() < nbytes.value:
+            ws = workspace(nbytes.value, dev)
+        self.ws, self.device, self.cams = ws, dev, list(cams)  # keep the buffers alive
+        h = ctypes.c_void_p()
+        _check(lib().prnu_batch_create(arr, len(cams), dt, ctypes.byref(p), int(acc_mode), int(flags),
+                                       int(round_bytes), _ptr(ws), ws.numel(), _stream(dev), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self):
+        _check(lib().prnu_batch_launch(self._h, _stream(self.device)))
+
+    def info(self) -> dict:
+        bi = BatchInfo()
+        _check(lib().prnu_batch_info_get(self._h, ctypes.byref(bi)))
+        return {k: getattr(bi, k) for k, _ in BatchInfo._fields_}
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            torch.cuda.synchronize(self.device)
+            _check(lib().prnu_batch_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fingerprint_batch(cams, params: DenoiseParams | None = None, acc_mode: int = ACC_F64, round_bytes: int = 0,
+                      ws: torch.Tensor | None = None):
+    """A += sum W*I, B += sum I^2 for every camera of ``cams`` (one schedule, no graph)."""
+    arr, dt, dev = _cameras(cams)
+    p = params or denoise_params()
+    nbytes = _S()
+    _check(lib().prnu_batch_workspace_size(arr, len(cams), ctypes.byref(p), int(round_bytes),
+                                           ctypes.byref(nbytes)))
+    if ws is None or ws.numel() < nbytes.value:
+        ws = workspace(nbytes.value, dev)
+    _check(lib().prnu_fingerprint_batch(arr, len(cams), dt, ctypes.byref(p), int(acc_mode), int(round_bytes),
+                                        _ptr(ws), ws.numel(), _stream(dev)))
+
+
+def get_tile(kind: int, taps: int, hk: int, wk: int) -> int:
+    return int(lib().prnu_get_tile(int(kind), int(taps), int(hk), int(wk)))
+
+
+def set_tile(kind: int, taps: int, hk: int, wk: int, tile: int):
+    _check(lib().prnu_set_tile(int(kind), int(taps), int(hk), int(wk), int(tile)))
+
+
+def autotune(H: int, W: int, C: int = 1, params: DenoiseParams | None = None, device="cuda"):
+    """Times both tile sizes of every level kernel for H x W x C frames and keeps
+    the faster; returns the 12 choices (forward 1..4, inverse 1..4, MLE)."""
+    p = params or denoise_params()
+    nbytes = _S()
+    _check(lib().prnu_autotune_workspace_size(int(H), int(W), int(C), ctypes.byref(p), ctypes.byref(nbytes)))
+    dev = torch.device(device)
+    ws = workspace(nbytes.value, dev)
+    out = (ctypes.c_int * 12)()
+    _check(lib().prnu_autotune(int(H), int(W), int(C), ctypes.byref(p), _ptr(ws), ws.numel(), _stream(dev), out))
+    return list(out)

@@ -244,3 +244,21 @@ def still_frames_torch(cam: int, n: int, H: int, W: int, k_std: float = 0.005, n
         R = torch.matmul(torch.matmul(DT, C.contiguous()), D)
         out[i, :, :, 0] = R.permute(0, 2, 1, 3).reshape(H, W).clamp_(0.0, 255.0)
     return out, K
+
+
+def patch_camera(cam: int, n: int, H: int = 512, W: int = 512, k_std: float = 0.015, kappa: float = 0.03,
+                 cfg: int = CFG_DIFF, first_frame: int = 0):
+    """Float patches for the differentiable workload: random-walk crops of a
+    per-camera texture (as for video), PRNU K ~ N(0, k_std^2) and signal-
+    dependent noise of variance kappa * I0 (about 2 DN at I0 = 130).
+    Returns (float64 patches [n][H][W], K)."""
+    K = camera_prnu((H, W), k_std, cfg, cam, 0xC0FFEE)
+    tex = video_texture(H, W, 1, cfg, cam, 0x7E7)[:, :, 0]
+    offs = crop_walk(first_frame + n, H, W, rng(cfg, cam, 0x3A1C), step=16.0)[first_frame:]
+    out = np.empty((n, H, W))
+    for i in range(n):
+        g = rng(cfg, cam, 1 + first_frame + i)
+        y, x = offs[i]
+        I0 = tex[y:y + H, x:x + W]
+        out[i] = I0 * (1.0 + K) + g.normal(0.0, 1.0, size=I0.shape) * np.sqrt(kappa * I0)
+    return out, K

@@ -1,0 +1,249 @@
+"""GPU parity of the batched path: cameras of uneven size, channel count,
+frame count and SDA group length accumulated by one schedule of persistent
+work-queue launches (optionally one HIP graph), against the FP64 oracle and
+against the per-camera entry point; both tile sizes; graph replays."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import pipeline
+from parity import assert_scaled
+
+torch = pytest.importorskip("torch")
+from paper_1909_04573_amd import prnu  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+# (n_frames, H, W, C, group): ragged sizes, a short last group, many groups
+CAMS = [(10, 72, 104, 3, 4), (9, 64, 80, 1, 3), (40, 48, 48, 1, 2), (8, 256, 256, 1, 1), (5, 24, 40, 1, 5),
+        (7, 40, 136, 1, 3)]
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    prnu.lib()
+    return torch.device("cuda:0")
+
+
+def up(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def down(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _frames(k, n, H, W, C):
+    if C == 1:
+        fr, _ = synth.tiny_camera(40 + k, n, H, W, cfg=synth.CFG_TEST)
+    else:
+        fr, _ = synth.video_camera(40 + k, n, H, W, C, cfg=synth.CFG_TEST)
+    return fr
+
+
+@pytest.fixture(scope="module")
+def data():
+    frames = [_frames(k, *c[:4]) for k, c in enumerate(CAMS)]
+    refs = [pipeline.fingerprint_accumulate(fr, c[4]) for fr, c in zip(frames, CAMS)]
+    return frames, refs
+
+
+def _cams(frames, dev, mode=prnu.ACC_F64, dtype=torch.uint8):
+    out = []
+    for fr, (n, H, W, C, d) in zip(frames, CAMS):
+        t = up(fr, dev)
+        if dtype != torch.uint8:
+            t = t.to(dtype).contiguous()
+        A, B = prnu.new_accumulators(C, H, W, mode, device=dev)
+        out.append((t, d, A, B))
+    return out
+
+
+def _combine(t, mode):
+    a = down(t)
+    if mode == prnu.ACC_KAHAN_F32:
+        return a[0].astype(np.float64) + a[1]
+    return a.astype(np.float64)
+
+
+def _check_oracle(cams, refs, mode=prnu.ACC_F64, what=""):
+    for k, ((_, _, A, B), (Ar, Br)) in enumerate(zip(cams, refs)):
+        a, b = _combine(A, mode), _combine(B, mode)
+        assert_scaled(a, Ar, what=f"A cam{k} {what}")
+        assert_scaled(b, Br, rtol=1e-6 if mode == prnu.ACC_F32 else 1e-7, what=f"B cam{k} {what}")
+
+
+@pytest.mark.parametrize("how", ["graph", "oneshot", "rounds"])
+def test_batch_matches_oracle(dev, data, how):
+    _log(f"batch vs oracle ({how})")
+    frames, refs = data
+    cams = _cams(frames, dev)
+    if how == "graph":
+        b = prnu.Batch(cams, flags=prnu.BATCH_GRAPH)
+        b.launch()
+        info = b.info()
+        b.close()
+        assert info["rounds"] >= 1 and info["sda_frames"] == sum(-(-n // d) for n, *_, d in CAMS)
+    elif how == "oneshot":
+        prnu.fingerprint_batch(cams)
+    else:  # a budget of ~64 KiB: every round takes only a few groups
+        b = prnu.Batch(cams, flags=prnu.BATCH_GRAPH, round_bytes=64 << 10)
+        b.launch()
+        info = b.info()
+        b.close()
+        assert info["rounds"] > 5, info
+    _check_oracle(cams, refs, what=how)
+
+
+def test_batch_equals_per_camera_path(dev, data):
+    _log("batch vs per-camera entry point")
+    frames, _ = data
+    cams = _cams(frames, dev)
+    prnu.fingerprint_batch(cams)
+    for k, ((t, d, A, B), (n, H, W, C, _)) in enumerate(zip(cams, CAMS)):
+        A1, B1 = prnu.new_accumulators(C, H, W, device=dev)
+        prnu.fingerprint_accumulate(t, d, A1, B1)
+        a, a1 = down(A), down(A1)
+        # same residuals; only the grouping of the FP64 sums may differ
+        np.testing.assert_allclose(a, a1, rtol=0, atol=1e-12 * np.abs(a1).max(), err_msg=f"A cam{k}")
+        np.testing.assert_allclose(down(B), down(B1), rtol=1e-15, atol=0, err_msg=f"B cam{k}")
+
+
+def _all_geometries(taps=16, levels=4):
+    geo = set()
+    for _, H, W, _, _ in CAMS:
+        Hp, Wp = -(-H // 16) * 16, -(-W // 16) * 16
+        for l in range(1, levels + 1):
+            geo.add((Hp >> l, Wp >> l))
+    return geo
+
+
+@pytest.mark.parametrize("tile", [16, 32])
+def test_batch_tile_sizes(dev, data, tile):
+    _log(f"batch and per-camera path with {tile}x{tile} tiles")
+    frames, refs = data
+    geo = _all_geometries()
+    try:
+        for kind in (prnu.TILE_FWD, prnu.TILE_INV, prnu.TILE_MLE):
+            for hk, wk in geo:
+                prnu.set_tile(kind, 16, hk, wk, tile)
+        cams = _cams(frames, dev)
+        b = prnu.Batch(cams)
+        b.launch()
+        b.close()
+        _check_oracle(cams, refs, what=f"tile {tile}")
+        for k, ((t, d, _, _), (n, H, W, C, _), (Ar, Br)) in enumerate(zip(cams, CAMS, refs)):
+            A1, B1 = prnu.new_accumulators(C, H, W, device=dev)
+            prnu.fingerprint_accumulate(t, d, A1, B1)
+            assert_scaled(down(A1), Ar, what=f"per-camera A cam{k} tile {tile}")
+        img = frames[3][:2, :, :, 0].astype(np.float32)
+        got = down(prnu.denoise_residual(up(img, dev)))
+        for i in range(2):
+            assert_scaled(got[i], pipeline.denoise_residual(img[i].astype(np.float64)), what=f"W tile {tile}")
+    finally:
+        for kind in (prnu.TILE_FWD, prnu.TILE_INV, prnu.TILE_MLE):
+            for hk, wk in geo:
+                prnu.set_tile(kind, 16, hk, wk, 0)
+
+
+def test_mixed_tile_sizes_in_one_stage(dev, data):
+    """Cameras whose levels use different tile sizes share every stage (one
+    launch per tile size)."""
+    _log("batch with mixed tile sizes")
+    frames, refs = data
+    geo = sorted(_all_geometries())
+    try:
+        for i, (hk, wk) in enumerate(geo):
+            for kind in (prnu.TILE_FWD, prnu.TILE_INV, prnu.TILE_MLE):
+                prnu.set_tile(kind, 16, hk, wk, 16 if (i + kind) % 2 else 32)
+        cams = _cams(frames, dev)
+        b = prnu.Batch(cams)
+        b.launch()
+        b.close()
+        _check_oracle(cams, refs, what="mixed tiles")
+    finally:
+        for hk, wk in geo:
+            for kind in (prnu.TILE_FWD, prnu.TILE_INV, prnu.TILE_MLE):
+                prnu.set_tile(kind, 16, hk, wk, 0)
+
+
+def test_graph_replays(dev, data):
+    """Replays of the captured graph (accumulators zeroed inside it) give the
+    same bits each time, with eager library and torch work in between."""
+    _log("graph replays")
+    frames, refs = data
+    cams = _cams(frames, dev)
+    b = prnu.Batch(cams, flags=prnu.BATCH_GRAPH | prnu.BATCH_ZERO_ACC)
+    first = None
+    for rep in range(3):
+        b.launch()
+        got = [(down(A).copy(), down(B).copy()) for _, _, A, B in cams]
+        if first is None:
+            first = got
+            _check_oracle(cams, refs, what="replay 0")
+        else:
+            for k, ((a, bb), (a0, b0)) in enumerate(zip(got, first)):
+                np.testing.assert_array_equal(a, a0, err_msg=f"A cam{k} replay {rep}")
+                np.testing.assert_array_equal(bb, b0, err_msg=f"B cam{k} replay {rep}")
+        # eager work between replays: a per-camera accumulate and a torch reduction
+        t, d, _, _ = cams[1]
+        A1, B1 = prnu.new_accumulators(1, CAMS[1][1], CAMS[1][2], device=dev)
+        prnu.fingerprint_accumulate(t, d, A1, B1)
+        _ = float(A1.abs().sum())
+    b.close()
+
+
+@pytest.mark.parametrize("mode", [prnu.ACC_KAHAN_F32, prnu.ACC_F32])
+def test_batch_accumulator_modes(dev, data, mode):
+    _log(f"batch accumulator mode {mode}")
+    frames, refs = data
+    cams = _cams(frames, dev, mode)
+    b = prnu.Batch(cams, acc_mode=mode)
+    b.launch()
+    b.close()
+    _check_oracle(cams, refs, mode, what=f"mode {mode}")
+
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32])
+def test_batch_float_frames(dev, data, dtype):
+    """u8 grey levels stored as bf16 / f32 are exact: the generic SDA path must
+    give the u8 result."""
+    _log(f"batch {dtype} frames")
+    frames, refs = data
+    cams = _cams(frames, dev, dtype=dtype)
+    prnu.fingerprint_batch(cams)
+    _check_oracle(cams, refs, what=str(dtype))
+
+
+def test_autotune_then_batch(dev, data):
+    _log("autotune")
+    frames, refs = data
+    n, H, W, C, d = CAMS[3]
+    tiles = prnu.autotune(H, W, C)
+    assert all(t in (16, 32) for t in tiles[0:4]), tiles
+    assert all(t in (16, 32) for t in tiles[5:8]) and tiles[8] in (16, 32), tiles
+    try:
+        cams = _cams(frames, dev)
+        prnu.fingerprint_batch(cams)
+        _check_oracle(cams, refs, what="autotuned")
+    finally:
+        for kind in (prnu.TILE_FWD, prnu.TILE_INV, prnu.TILE_MLE):
+            for hk, wk in _all_geometries():
+                prnu.set_tile(kind, 16, hk, wk, 0)
+
+
+def test_batch_rejects_overlapping_accumulators(dev, data):
+    frames, _ = data
+    cams = _cams(frames[:2], dev)
+    t0, d0, A0, B0 = cams[0]
+    cams[1] = (cams[1][0], cams[1][1], A0, cams[1][3])  # camera 1 writes camera 0's A
+    with pytest.raises(prnu.PrnuError, match="overlap"):
+        prnu.fingerprint_batch(cams)
