@@ -26,6 +26,7 @@ struct prnu_batch {
         int *ctr = nullptr;
         float *fill = nullptr;
         int64_t nfill = 0;
+        double bytes = 0;  // algorithmic bytes (inputs read once, outputs written once)
     };
     std::vector<Launch> launches;
     prnu::Filter f;
@@ -253,6 +254,11 @@ int build(const prnu_camera *cams, int n, int dtype, const prnu_denoise_params *
             }
             if (blk > 0x7fffffff) return fail(PRNU_E_INVAL, "prnu_batch: round of %lld SDA blocks", (long long)blk);
             Launch la{};
+            for (int k = 0; k < nj; ++k) {
+                const prnu_camera &c = cams[r[k].cam];
+                const int64_t nread = std::min(c.n_frames, (r[k].g0 + r[k].ng) * c.group) - r[k].g0 * c.group;
+                la.bytes += (double)nread * c.H * c.W * c.C * elem_bytes(dtype) + 4.0 * r[k].ng * c.C * c.H * c.W;
+            }
             la.kind = Launch::SDA;
             la.desc = ws + toff;
             la.nd = nj;
@@ -274,13 +280,14 @@ int build(const prnu_camera *cams, int n, int dtype, const prnu_denoise_params *
                 char *tab = blob->data() + toff;
                 int nd = 0;
                 int64_t blk = 0;
+                double bytes = 0;
                 for (int k = 0; k < nj; ++k) {
                     const prnu_camera &c = cams[r[k].cam];
                     const int Hp = padded(c.H), Wp = padded(c.W);
                     const int hk = Hp >> level, wk = Wp >> level;
                     if (stage_tt(kind_tk, taps, hk, wk) != tt || nd == cnt) continue;
                     const int tiles = tiles_for(tt, hk, wk);
-                    const int planes = make(k, tt, tab + nd * dsz, blk);
+                    const int planes = make(k, tt, tab + nd * dsz, blk, &bytes);
                     blk += (int64_t)tiles * planes;
                     ++nd;
                 }
@@ -294,6 +301,7 @@ int build(const prnu_camera *cams, int n, int dtype, const prnu_denoise_params *
                 la.nd = nd;
                 la.total = blk;
                 la.ctr = ctr + ci++;
+                la.bytes = bytes;
                 const int occ = kind == Launch::FWD   ? fwd_multi_occupancy(taps, tt)
                                 : kind == Launch::INV ? inv_multi_occupancy(taps, tt)
                                                       : mle_multi_occupancy(taps, tt, acc_mode);
@@ -305,7 +313,7 @@ int build(const prnu_camera *cams, int n, int dtype, const prnu_denoise_params *
         };
         for (int l = 1; l <= lv; ++l) {
             const float s2 = p->level_weight[l - 1] * s0;
-            auto mk = [&](int k, int tt, char *dst, int64_t blk0) {
+            auto mk = [&](int k, int tt, char *dst, int64_t blk0, double *bytes) {
                 const prnu_camera &c = cams[r[k].cam];
                 const int Hp = padded(c.H), Wp = padded(c.W);
                 const int planes = r[k].ng * c.C;
@@ -323,12 +331,14 @@ int build(const prnu_camera *cams, int n, int dtype, const prnu_denoise_params *
                 d.planes = planes;
                 d.block0 = blk0;
                 std::memcpy(dst, &d, sizeof d);
+                *bytes += 4.0 * planes *
+                          ((double)d.a.src_rows * d.a.src_cols + (d.a.write_ll ? 4.0 : 3.0) * (Hp >> l) * (Wp >> l));
                 return planes;
             };
             PRNU_TRY(emit_stage(mk, sizeof(FwdDesc), TK_FWD, l, Launch::FWD));
         }
         for (int l = lv; l >= 2; --l) {
-            auto mk = [&](int k, int tt, char *dst, int64_t blk0) {
+            auto mk = [&](int k, int tt, char *dst, int64_t blk0, double *bytes) {
                 const prnu_camera &c = cams[r[k].cam];
                 const int Hp = padded(c.H), Wp = padded(c.W);
                 const int planes = r[k].ng * c.C;
@@ -340,12 +350,13 @@ int build(const prnu_camera *cams, int n, int dtype, const prnu_denoise_params *
                 d.planes = planes;
                 d.block0 = blk0;
                 std::memcpy(dst, &d, sizeof d);
+                *bytes += 4.0 * planes * ((l == lv ? 3.0 : 4.0) + 4.0) * hk * wk;
                 return planes;
             };
             PRNU_TRY(emit_stage(mk, sizeof(InvDesc), TK_INV, l, Launch::INV));
         }
         {
-            auto mk = [&](int k, int tt, char *dst, int64_t blk0) {
+            auto mk = [&](int k, int tt, char *dst, int64_t blk0, double *bytes) {
                 const prnu_camera &c = cams[r[k].cam];
                 const int Hp = padded(c.H), Wp = padded(c.W);
                 const int hk = Hp >> 1, wk = Wp >> 1;
@@ -356,6 +367,9 @@ int build(const prnu_camera *cams, int n, int dtype, const prnu_denoise_params *
                 d.tiles = tiles_for(tt, hk, wk);
                 d.block0 = blk0;
                 std::memcpy(dst, &d, sizeof d);
+                const double accb = acc_mode == PRNU_ACC_F32 ? 16.0 : 32.0;  // A and B, read + write
+                *bytes += 4.0 * r[k].ng * c.C * ((lv == 1 ? 3.0 : 4.0) * hk * wk + (double)c.H * c.W) +
+                          accb * c.C * c.H * c.W;
                 return c.C;
             };
             PRNU_TRY(emit_stage(mk, sizeof(MleDesc), TK_MLE, 1, Launch::MLE));
@@ -371,26 +385,38 @@ int build(const prnu_camera *cams, int n, int dtype, const prnu_denoise_params *
 
 int enqueue(const prnu_batch *b, hipStream_t s) {
     using Launch = prnu_batch::Launch;
+    static const char *fwd_names[2] = {"batch_fwd_wiener<16>", "batch_fwd_wiener<32>"};
+    static const char *inv_names[2] = {"batch_inv<16>", "batch_inv<32>"};
+    static const char *mle_names[2] = {"batch_inv_mle<16>", "batch_inv_mle<32>"};
     for (const Launch &la : b->launches) {
         hipError_t e = hipSuccess;
+        const int t32 = la.tt == 32;
         switch (la.kind) {
             case Launch::ZERO_CTR: e = launch_zero_ints(la.ctr, (int)la.total, s); break;
             case Launch::ZERO_ACC: e = launch_fill_zero(la.fill, la.nfill, s); break;
-            case Launch::SDA:
+            case Launch::SDA: {
+                KernelTimer kt("batch_sda", la.bytes, s);
                 e = launch_sda_multi(static_cast<const SdaDesc *>(la.desc), la.nd, la.total, s);
                 break;
-            case Launch::FWD:
+            }
+            case Launch::FWD: {
+                KernelTimer kt(fwd_names[t32], la.bytes, s);
                 e = launch_fwd_multi(b->taps, la.tt, b->f, static_cast<const FwdDesc *>(la.desc), la.nd,
                                      (int)la.total, la.ctr, la.grid, s);
                 break;
-            case Launch::INV:
+            }
+            case Launch::INV: {
+                KernelTimer kt(inv_names[t32], la.bytes, s);
                 e = launch_inv_multi(b->taps, la.tt, b->f, static_cast<const InvDesc *>(la.desc), la.nd,
                                      (int)la.total, la.ctr, la.grid, s);
                 break;
-            case Launch::MLE:
+            }
+            case Launch::MLE: {
+                KernelTimer kt(mle_names[t32], la.bytes, s);
                 e = launch_mle_multi(b->taps, la.tt, b->acc_mode, b->f, static_cast<const MleDesc *>(la.desc), la.nd,
                                      (int)la.total, la.ctr, la.grid, s);
                 break;
+            }
         }
         if (e != hipSuccess) return fail(PRNU_E_HIP, "prnu_batch: launch failed: %s", hipGetErrorString(e));
     }
