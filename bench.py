@@ -53,11 +53,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
-    ap.add_argument("--workload", choices=["video", "stills-precision", "batched"], default="video",
+    ap.add_argument("--workload", choices=["video", "stills-precision", "batched", "diff"], default="video",
                     help="video: the headline benchmark; stills-precision: the accumulator/storage "
                          "precision report on 4000x3000 BF16 stills; batched: 64 grayscale cameras of "
                          "uneven resolution, frame count and SDA depth in one graph launch, then a 64x64 "
-                         "PCE matrix of 512x512 fingerprint crops")
+                         "PCE matrix of 512x512 fingerprint crops; diff: loss and gradient of the matched-"
+                         "minus-unmatched PCE gap w.r.t. the denoiser parameters (256 patches of 512x512)")
     ap.add_argument("--batch-cams", type=int, default=64)
     ap.add_argument("--round-gib", type=float, default=24.0,
                     help="batched: memory budget of one round's SDA means and wavelet pyramids")
@@ -102,6 +103,8 @@ def main():
         return precision_main(args)
     if args.workload == "batched":
         return batched_main(args)
+    if args.workload == "diff":
+        return diff_main(args)
 
     import numpy as np
     import torch
@@ -636,6 +639,129 @@ def batched_main(args):
             "kernels_one_pass": kernels,
             "gpu_vs_fp64_oracle": err,
         },
+    }
+    print(json.dumps(out), flush=True)
+
+
+
+def diff_main(args):
+    """Differentiation workload: 8 cameras x 32 float patches of 512x512 (24
+    per camera at SDA depth 8 for the fingerprints, 8 single-patch queries);
+    one step is the matched-minus-unmatched PCE gap and its gradient with
+    respect to (sigma0, 4 level weights) through the hand-written adjoint
+    (forward with checkpoints, PCE adjoint, zero-mean and MLE adjoints,
+    residual adjoint).  A short normalised gradient ascent follows."""
+    import numpy as np
+    import torch
+
+    import synth
+    from oracle import adjoint
+    from paper_1909_04573_amd import autograd, prnu
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    prnu.lib()
+    ncam, nfp, nq, H, W, d = 8, 24, 8, 512, 512, 8
+    cams, qs, qc = [], [], []
+    for c in range(ncam):
+        pch, _ = synth.patch_camera(c, nfp + nq, H, W)
+        cams.append(pch[:nfp])
+        qs.extend(pch[nfp:])
+        qc.extend([c] * nq)
+    cams_np, qs_np = np.stack(cams), np.stack(qs)
+    cams_t = torch.from_numpy(cams_np.astype(np.float32)).to(dev)
+    qs_t = torch.from_numpy(qs_np.astype(np.float32)).to(dev)
+    theta0 = torch.tensor([3.0, 1.0, 1.0, 1.0, 1.0], dtype=torch.float64)
+
+    def run_step():
+        th = theta0.clone().requires_grad_(True)
+        L = autograd.pce_gap(th, cams_t, qs_t, qc, d=d)
+        L.backward()
+        return float(L.detach()), th.grad.clone()
+
+    for i in range(args.warmup):
+        log(f"warmup step {i + 1}/{args.warmup}")
+        run_step()
+    torch.cuda.synchronize()
+    prnu.timing_enable(True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        L, g = run_step()
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    timing = prnu.timing_report()
+    prnu.timing_enable(False)
+    log(f"timed {args.steps} steps: {ms_per_step:.1f} ms/step, loss {L:.4f}, grad {g.tolist()}")
+    patches = ncam * (nfp + nq)
+    value = patches * H * W / (ms_per_step / 1e3) / 1e6
+    dom = max(timing.items(), key=lambda kv: kv[1][1])
+    name, (launches, kms, kbytes) = dom
+    achieved = (kbytes / launches) / (kms / launches / 1e3) / 1e9
+    roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "launches": launches, "avg_launch_us": round(kms / launches * 1e3, 2),
+                "algorithmic_bytes_per_launch": round(kbytes / launches)}
+    kernels = {k: {"launches": n, "ms_per_step": ms / args.steps, "avg_us": ms / n * 1e3,
+                   "gbs": (b / (ms / 1e3) / 1e9) if ms > 0 else None}
+               for k, (n, ms, b) in sorted(timing.items(), key=lambda kv: -kv[1][1])}
+    # short ascent (untimed)
+    theta = theta0.clone()
+    gaps = []
+    for _ in range(6):
+        th = theta.clone().requires_grad_(True)
+        Lf = autograd.pce_gap(th, cams_t, qs_t, qc, d=d)
+        Lf.backward()
+        gaps.append(float(Lf.detach()))
+        theta = (theta + 0.05 * th.grad / th.grad.norm()).clamp(min=0.05)
+    # oracle: loss and gradient on a bounded sample (2 cameras, 8 + 2 patches each)
+    cpu, err = None, None
+    if not args.no_cpu_baseline:
+        sc, sf, sq = 2, 8, 2
+        c32 = [cams_np[c, :sf].astype(np.float32).astype(np.float64) for c in range(sc)]
+        q_idx = [c * nq + k for c in range(sc) for k in range(sq)]
+        q32 = qs_np[q_idx].astype(np.float32).astype(np.float64)
+        qcs = [qc[i] for i in q_idx]
+        log("oracle: gap loss and gradient on 2 cameras x (8 + 2) patches")
+        t1 = time.perf_counter()
+        Lr, gr, _ = adjoint.gap_loss(theta0.numpy(), c32, q32, qcs, d=d)
+        t_or = time.perf_counter() - t1
+        th = theta0.clone().requires_grad_(True)
+        Ls = autograd.pce_gap(th, torch.from_numpy(np.stack(c32).astype(np.float32)).to(dev),
+                              torch.from_numpy(q32.astype(np.float32)).to(dev), qcs, d=d)
+        Ls.backward()
+        gs = th.grad.numpy()
+        npx = (sc * sf + len(q_idx)) * H * W
+        cpu = {"value": round(npx / t_or / 1e6, 4), "unit": "Mpix/s", "cores": 1, "kind": "oracle",
+               "sample": f"2 cameras x ({sf} patches at depth {d} + {sq} queries) of 512x512: loss and "
+                         f"gradient, FP64 NumPy, {t_or:.1f} s",
+               "host": host_cpu_model(), "host_cpu_count": os.cpu_count()}
+        err = {"loss_gpu": float(Ls.detach()), "loss_oracle": float(Lr),
+               "loss_rel_err": float(abs(float(Ls.detach()) - Lr) / abs(Lr)),
+               "grad_gpu": gs.tolist(), "grad_oracle": gr.tolist(),
+               "grad_max_rel_err": float(np.abs(gs - gr).max() / np.abs(gr).max())}
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"differentiation: {ncam} cameras x {nfp + nq} patches {W}x{H} f32 ({nfp} at SDA depth {d} "
+                        f"per fingerprint, {nq} queries), loss = mean matched - mean unmatched PCE, gradient "
+                        "w.r.t. sigma0 and 4 level weights (forward + adjoint per step)",
+            "patches": patches, "pairs": ncam * nq * ncam,
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "detail": {"loss": L, "grad": g.tolist(), "gradient_evals_per_s": 1e3 / ms_per_step,
+                   "ascent_gaps": gaps, "kernels": kernels, "gpu_vs_fp64_oracle": err},
     }
     print(json.dumps(out), flush=True)
 
