@@ -19,6 +19,7 @@
 
 #include "fft_dev.h"
 #include "internal.h"
+#include "stage_dev.h"
 
 namespace prnu {
 namespace {
@@ -66,21 +67,24 @@ __global__ __launch_bounds__(NT) void dwt_vjp(const float *__restrict__ src, int
     else if (tid < 2 * IN)
         cmap[tid - IN] = map_zero(2 * k0c + tid - IN, n_c, off_c, src_cols);
     __syncthreads();
-    for (int e = tid; e < IN * IN; e += NT) {
-        const int i = e / IN, j = e - (e / IN) * IN;
-        const int r = rmap[i], c = cmap[j];
-        float v = 0.f;
-        if (r >= 0 && c >= 0) {
-            const int64_t o = (int64_t)r * src_cols + c;
-            v = sp[o];
-            if (mp) v *= mp[o];
-            if (div) {
-                const float d = div[o];
-                v = d > 0.f ? v / d : 0.f;
+    staged_copy<NT, 8, float>(
+        tid, IN * IN,
+        [&](int e) {
+            const int i = e / IN, j = e - (e / IN) * IN;
+            const int r = rmap[i], c = cmap[j];
+            float v = 0.f;
+            if (r >= 0 && c >= 0) {
+                const int64_t o = (int64_t)r * src_cols + c;
+                v = sp[o];
+                if (mp) v *= mp[o];
+                if (div) {
+                    const float d = div[o];
+                    v = d > 0.f ? v / d : 0.f;
+                }
             }
-        }
-        tile[i * INS + j] = v;
-    }
+            return v;
+        },
+        [&](int e, float v) { tile[(e / IN) * INS + e - (e / IN) * IN] = v; });
     __syncthreads();
     constexpr int NQ = NC / 4;
     for (int it = tid; it < IN * NQ; it += NT) {

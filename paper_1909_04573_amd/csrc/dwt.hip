@@ -30,6 +30,7 @@
 #include <tuple>
 
 #include "internal.h"
+#include "stage_dev.h"
 #include "wiener_dev.h"
 
 namespace prnu {
@@ -60,6 +61,15 @@ struct InvGeom {
     static constexpr int LDS = SB + 2 * L1 + 2 * NK;
 };
 
+// The thread index as a value the compiler cannot hoist out of a persistent
+// loop: the per-thread index arithmetic of a level body is recomputed for
+// every tile instead of being kept live in registers across tiles.
+__device__ __forceinline__ int opaque_tid() {
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
 // Periodic wrap into [0, n), then symmetric (edge-including) reflection of
 // the padded index into the stored [0, stored) range.
 __device__ __forceinline__ int map_index(int p, int n, int off, int stored) {
@@ -86,10 +96,10 @@ __device__ __forceinline__ void fwd_body(const FwdArgs &a, int tile, int plane, 
     const int hk = a.n_r >> 1, wk = a.n_c >> 1;
     const int tr = tile / a.tiles_c, tc = tile - (tile / a.tiles_c) * a.tiles_c;
     const int k0r = tr * TT, k0c = tc * TT;
-    const float *sp = a.src + (int64_t)plane * a.src_stride;
-    float *op = a.out + (int64_t)plane * 4 * hk * wk;
+    const PRNU_GLOBAL float *sp = gmem(a.src) + (int64_t)plane * a.src_stride;
+    PRNU_GLOBAL float *op = gmem(a.out) + (int64_t)plane * 4 * hk * wk;
     const int64_t band = (int64_t)hk * wk;
-    const int tid = threadIdx.x;
+    const int tid = opaque_tid();
 
     if (tid < IN)
         rmap[tid] = map_index(2 * (k0r - HALO) + tid, a.n_r, a.off_r, a.src_rows);
@@ -99,21 +109,49 @@ __device__ __forceinline__ void fwd_body(const FwdArgs &a, int tile, int plane, 
 
     // Stage the input tile: pairs of contiguous samples where the tile's
     // columns need neither the periodic wrap nor the reflection, single
-    // samples otherwise.
+    // samples otherwise.  Every load of a thread is issued before the first
+    // LDS store, so the whole tile is in flight at once.
     const int c_src0 = 2 * (k0c - HALO) - a.off_c;
     const bool cfast = c_src0 >= 0 && c_src0 + IN <= a.src_cols && (c_src0 & 1) == 0 && (a.src_cols & 1) == 0 &&
                        (a.src_stride & 1) == 0;
     if (cfast) {
         constexpr int IN2 = IN / 2;
-        for (int e = tid; e < IN * IN2; e += NT) {
-            const int i = e / IN2, j2 = e - (e / IN2) * IN2;
-            const float2 v = *reinterpret_cast<const float2 *>(sp + (int64_t)rmap[i] * a.src_cols + c_src0 + 2 * j2);
-            *reinterpret_cast<float2 *>(&tbuf[i * INS + 2 * j2]) = v;
+        constexpr int E = IN * IN2, K = (E + NT - 1) / NT;
+        float2 v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int e = tid + k * NT;
+            if (e < E) {
+                const int i = e / IN2, j2 = e - (e / IN2) * IN2;
+                v[k] = ld2(sp + (int64_t)rmap[i] * a.src_cols + c_src0 + 2 * j2);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int e = tid + k * NT;
+            if (e < E) {
+                const int i = e / IN2, j2 = e - (e / IN2) * IN2;
+                *reinterpret_cast<float2 *>(&tbuf[i * INS + 2 * j2]) = v[k];
+            }
         }
     } else {
-        for (int e = tid; e < IN * IN; e += NT) {
-            const int i = e / IN, j = e - (e / IN) * IN;
-            tbuf[i * INS + j] = sp[(int64_t)rmap[i] * a.src_cols + cmap[j]];
+        constexpr int E = IN * IN, K = (E + NT - 1) / NT;
+        float v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int e = tid + k * NT;
+            if (e < E) {
+                const int i = e / IN, j = e - (e / IN) * IN;
+                v[k] = sp[(int64_t)rmap[i] * a.src_cols + cmap[j]];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int e = tid + k * NT;
+            if (e < E) {
+                const int i = e / IN, j = e - (e / IN) * IN;
+                tbuf[i * INS + j] = v[k];
+            }
         }
     }
     __syncthreads();
@@ -223,8 +261,8 @@ __device__ __forceinline__ void fwd_body(const FwdArgs &a, int tile, int plane, 
         const int s = tid / (2 * TT), half = (tid / TT) & 1, kcl = tid & (TT - 1);
         const float *Q = qb + s * NC * NC;
         const float *Cc = cb + s * TT * TT;
-        float *ob = op + (int64_t)(s + 1) * band;
-        float *cp = a.ckpt ? a.ckpt + (int64_t)plane * a.ckpt_stride + (int64_t)s * band : nullptr;
+        PRNU_GLOBAL float *ob = op + (int64_t)(s + 1) * band;
+        PRNU_GLOBAL float *cp = a.ckpt ? gmem(a.ckpt) + (int64_t)plane * a.ckpt_stride + (int64_t)s * band : nullptr;
         const int gco = k0c + kcl;
         const float s2 = a.s2;
         auto load = [&](int kr, int kc) { return Q[kr * NC + kc]; };
@@ -244,9 +282,8 @@ __device__ __forceinline__ void fwd_body(const FwdArgs &a, int tile, int plane, 
 // ---------------------------------------------------------------------------
 // Inverse level pieces.
 template <int TAPS, int TT>
-__device__ __forceinline__ void inv_maps(int hk, int wk, int k0r, int k0c, int *rmap, int *cmap) {
+__device__ __forceinline__ void inv_maps(int tid, int hk, int wk, int k0r, int k0c, int *rmap, int *cmap) {
     constexpr int NK = InvGeom<TAPS, TT>::NK, HT = TAPS / 2;
-    const int tid = threadIdx.x;
     if (tid < NK) {
         int k = (k0r - (HT - 1) + tid) % hk;
         rmap[tid] = k < 0 ? k + hk : k;
@@ -256,27 +293,49 @@ __device__ __forceinline__ void inv_maps(int hk, int wk, int k0r, int k0c, int *
     }
 }
 
+// Stages the (TT+L/2-1)^2 coefficients of the four subbands (subband 0 as
+// zeros with zero_approx); a thread issues its loads in batches of up to 12
+// before storing them, so a batch is in flight at once.
 template <int TAPS, int TT>
-__device__ __forceinline__ void inv_load(const float *__restrict__ lp, int hk, int wk, bool zero_approx, float *sb,
-                                         const int *rmap, const int *cmap) {
+__device__ __forceinline__ void inv_load(int tid, const float *__restrict__ lpp, int hk, int wk, bool zero_approx,
+                                         float *sb, const int *rmap, const int *cmap) {
+    const PRNU_GLOBAL float *lp = gmem(lpp);
     constexpr int NK = InvGeom<TAPS, TT>::NK, NKS = InvGeom<TAPS, TT>::NKS;
+    constexpr int E = 4 * NK * NK, K = (E + NT - 1) / NT, KB = K < 12 ? K : 12;
     const int64_t band = (int64_t)hk * wk;
-    for (int e = threadIdx.x; e < 4 * NK * NK; e += NT) {
-        const int s = e / (NK * NK);
-        const int rem = e - s * NK * NK;
-        const int kr = rem / NK, kc = rem - (rem / NK) * NK;
-        float v = 0.f;
-        if (!(s == 0 && zero_approx)) v = lp[s * band + (int64_t)rmap[kr] * wk + cmap[kc]];
-        sb[(s * NK + kr) * NKS + kc] = v;
+#pragma unroll
+    for (int k0 = 0; k0 < K; k0 += KB) {
+        float v[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const int e = tid + (k0 + k) * NT;
+            v[k] = 0.f;
+            if (k0 + k < K && e < E) {
+                const int s = e / (NK * NK);
+                const int rem = e - s * NK * NK;
+                const int kr = rem / NK, kc = rem - (rem / NK) * NK;
+                if (!(s == 0 && zero_approx)) v[k] = lp[s * band + (int64_t)rmap[kr] * wk + cmap[kc]];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const int e = tid + (k0 + k) * NT;
+            if (k0 + k < K && e < E) {
+                const int s = e / (NK * NK);
+                const int rem = e - s * NK * NK;
+                const int kr = rem / NK, kc = rem - (rem / NK) * NK;
+                sb[(s * NK + kr) * NKS + kc] = v[k];
+            }
+        }
     }
 }
 
 // Columns (axis 0): lo1/hi1[n][kc] for the 2TT output rows.
 template <int TAPS, int TT>
-__device__ __forceinline__ void inv_cols(const float *sb, float *lo1, float *hi1, const Filter &f) {
+__device__ __forceinline__ void inv_cols(int tid, const float *sb, float *lo1, float *hi1, const Filter &f) {
     constexpr int NK = InvGeom<TAPS, TT>::NK, NKS = InvGeom<TAPS, TT>::NKS, HT = TAPS / 2;
     // item: column kc, quad of output rows n = 4pp .. 4pp+3 (coefficient rows 2pp .. 2pp+HT)
-    for (int it = threadIdx.x; it < NK * (TT / 2); it += NT) {
+    for (int it = tid; it < NK * (TT / 2); it += NT) {
         const int pp = it / NK, kc = it - (it / NK) * NK;
         float a[HT + 1], lh[HT + 1], hl[HT + 1], hh[HT + 1];
 #pragma unroll
@@ -338,16 +397,19 @@ __device__ __forceinline__ void inv_body(const InvArgs &a, int tile, int plane, 
     float *sb = lds, *lo1 = lds + G::SB, *hi1 = lo1 + G::L1;
     int *rmap = reinterpret_cast<int *>(hi1 + G::L1);
     int *cmap = rmap + G::NK;
+    const int tid = opaque_tid();
     const int tr = tile / a.tiles_c, tc = tile - (tile / a.tiles_c) * a.tiles_c;
     const int k0r = tr * TT, k0c = tc * TT;
-    inv_maps<TAPS, TT>(a.hk, a.wk, k0r, k0c, rmap, cmap);
+    inv_maps<TAPS, TT>(tid, a.hk, a.wk, k0r, k0c, rmap, cmap);
     __syncthreads();
-    inv_load<TAPS, TT>(a.lvl + (int64_t)plane * 4 * a.hk * a.wk, a.hk, a.wk, a.zero_approx != 0, sb, rmap, cmap);
+    inv_load<TAPS, TT>(tid, a.lvl + (int64_t)plane * 4 * a.hk * a.wk, a.hk, a.wk, a.zero_approx != 0, sb, rmap,
+                       cmap);
     __syncthreads();
-    inv_cols<TAPS, TT>(sb, lo1, hi1, f);
+    inv_cols<TAPS, TT>(tid, sb, lo1, hi1, f);
     __syncthreads();
     const int nr = 2 * a.hk, nc = 2 * a.wk;
-    for (int it = threadIdx.x; it < NO * (NO / 4); it += NT) {
+    PRNU_GLOBAL float *out = gmem(a.out);
+    for (int it = tid; it < NO * (NO / 4); it += NT) {
         const int n = it / (NO / 4), mq = it - (it / (NO / 4)) * (NO / 4);
         float x[4];
         inv_row_quad<TAPS, TT>(lo1, hi1, n, mq, f, x);
@@ -358,11 +420,11 @@ __device__ __forceinline__ void inv_body(const InvArgs &a, int tile, int plane, 
             const int gc = 2 * k0c + 4 * mq + u;
             if (gc >= nc) continue;
             if (EPI == INV_PLANE) {
-                a.out[(int64_t)plane * 4 * nr * nc + (int64_t)gr * nc + gc] = x[u];
+                out[(int64_t)plane * 4 * nr * nc + (int64_t)gr * nc + gc] = x[u];
             } else {
                 const int y = gr - a.off_r, xx = gc - a.off_c;
                 if (y >= 0 && y < a.H && xx >= 0 && xx < a.W)
-                    a.out[(int64_t)plane * a.H * a.W + (int64_t)y * a.W + xx] = x[u];
+                    out[(int64_t)plane * a.H * a.W + (int64_t)y * a.W + xx] = x[u];
             }
         }
     }
@@ -379,11 +441,11 @@ __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, floa
     float *sb = lds, *lo1 = lds + G::SB, *hi1 = lo1 + G::L1;
     int *rmap = reinterpret_cast<int *>(hi1 + G::L1);
     int *cmap = rmap + G::NK;
-    const int tid = threadIdx.x;
+    const int tid = opaque_tid();
     const int tr = tile / a.tiles_c, tc = tile - (tile / a.tiles_c) * a.tiles_c;
     const int k0r = tr * TT, k0c = tc * TT;
     const int H = a.H, W = a.W, C = a.C;
-    inv_maps<TAPS, TT>(a.hk, a.wk, k0r, k0c, rmap, cmap);
+    inv_maps<TAPS, TT>(tid, a.hk, a.wk, k0r, k0c, rmap, cmap);
     const int64_t npx = (int64_t)H * W;
     double sa[ITEMS][4], sbb[ITEMS][4];  // ACC_F64 partials
     float ka[ITEMS][4], kc_[ITEMS][4];   // float partial of A (+ compensation for KAHAN)
@@ -397,13 +459,29 @@ __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, floa
             ka[k][u] = kc_[k][u] = kb[k][u] = kbc[k][u] = 0.f;
         }
     for (int fr = 0; fr < a.nb; ++fr) {
+        // this frame's SDA means, loaded ahead of the subband staging (kept
+        // in registers only where a thread owns a single row quad)
+        const PRNU_GLOBAL float *Ip = gmem(a.means) + (int64_t)(fr * C + c) * npx;
+        constexpr int PF = ITEMS == 1 ? 1 : 0;
+        float Iv[PF ? ITEMS : 1][4];
+#pragma unroll
+        for (int k = 0; k < (PF ? ITEMS : 0); ++k) {
+            const int it = tid + k * NT;
+            const int n = it / (NO / 4), mq = it - (it / (NO / 4)) * (NO / 4);
+            const int y = 2 * k0r + n - a.off_r;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int xx = 2 * k0c + 4 * mq + u - a.off_c;
+                Iv[k][u] = (y >= 0 && y < H && xx >= 0 && xx < W) ? Ip[(int64_t)y * W + xx] : 0.f;
+            }
+        }
         __syncthreads();  // maps ready / previous frame's LDS reads done
-        inv_load<TAPS, TT>(a.lvl + (int64_t)(fr * C + c) * 4 * a.hk * a.wk, a.hk, a.wk, a.zero_approx != 0, sb,
-                           rmap, cmap);
+        const int tf = opaque_tid();  // index arithmetic per frame, not live across the frame loop
+        inv_load<TAPS, TT>(tf, a.lvl + (int64_t)(fr * C + c) * 4 * a.hk * a.wk, a.hk, a.wk, a.zero_approx != 0,
+                           sb, rmap, cmap);
         __syncthreads();
-        inv_cols<TAPS, TT>(sb, lo1, hi1, f);
+        inv_cols<TAPS, TT>(tf, sb, lo1, hi1, f);
         __syncthreads();
-        const float *Ip = a.means + (int64_t)(fr * C + c) * npx;
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
             const int it = tid + k * NT;
@@ -415,7 +493,7 @@ __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, floa
             for (int u = 0; u < 4; ++u) {
                 const int xx = 2 * k0c + 4 * mq + u - a.off_c;
                 if (y >= 0 && y < H && xx >= 0 && xx < W) {
-                    const float I = Ip[(int64_t)y * W + xx];
+                    const float I = PF ? Iv[PF ? k : 0][u] : Ip[(int64_t)y * W + xx];
                     if (ACC == PRNU_ACC_KAHAN_F32) {
                         // two-sum accumulation of W*I and I*I
                         const float pa = x[u] * I, pb = I * I;
@@ -451,19 +529,19 @@ __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, floa
             if (xx < 0 || xx >= W) continue;
             const int64_t o = (int64_t)c * npx + (int64_t)y * W + xx;
             if (ACC == PRNU_ACC_F64) {
-                double *A = static_cast<double *>(a.A);
-                double *B = static_cast<double *>(a.B);
+                PRNU_GLOBAL double *A = gmem(static_cast<double *>(a.A));
+                PRNU_GLOBAL double *B = gmem(static_cast<double *>(a.B));
                 A[o] += sa[k][u];
                 B[o] += sbb[k][u];
             } else if (ACC == PRNU_ACC_F32) {
-                float *A = static_cast<float *>(a.A);
-                float *B = static_cast<float *>(a.B);
+                PRNU_GLOBAL float *A = gmem(static_cast<float *>(a.A));
+                PRNU_GLOBAL float *B = gmem(static_cast<float *>(a.B));
                 A[o] += ka[k][u];
                 B[o] += kb[k][u];
             } else {
                 // value plane [0], compensation plane [1]
-                float *A = static_cast<float *>(a.A);
-                float *B = static_cast<float *>(a.B);
+                PRNU_GLOBAL float *A = gmem(static_cast<float *>(a.A));
+                PRNU_GLOBAL float *B = gmem(static_cast<float *>(a.B));
                 const int64_t cs = (int64_t)C * npx;
                 float s = A[o], t = s + ka[k][u], z = t - s;
                 A[o + cs] += kc_[k][u] + ((s - (t - z)) + (ka[k][u] - z));
@@ -523,7 +601,7 @@ __device__ __forceinline__ int next_block(int *ctr, int *slot) {
     __syncthreads();  // the previous block's LDS use is over
     if (threadIdx.x == 0) *slot = atomicAdd(ctr, 1);
     __syncthreads();
-    return *slot;
+    return __builtin_amdgcn_readfirstlane(*slot);  // uniform: descriptor fields go to scalar registers
 }
 
 template <int TAPS, int TT>

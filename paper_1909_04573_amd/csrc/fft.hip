@@ -23,6 +23,7 @@
 
 #include "fft_dev.h"
 #include "internal.h"
+#include "stage_dev.h"
 
 namespace prnu {
 namespace {
@@ -38,10 +39,13 @@ __global__ __launch_bounds__(FNT) void fft_1d(float2 *__restrict__ data, int N, 
     float2 *base = data + (int64_t)blockIdx.y * plane_stride;
     const int tot = N * nvec;
     float2 *b0 = lds, *b1 = lds + FCAP;
-    for (int e = threadIdx.x; e < tot; e += FNT) {
-        const int v = e & (nvec - 1), n = e >> plan.lvec;
-        b0[e] = (v0 + v < count) ? base[(int64_t)(v0 + v) * vs + (int64_t)n * es] : make_float2(0.f, 0.f);
-    }
+    staged_copy<FNT, 8, float2>(
+        threadIdx.x, tot,
+        [&](int e) {
+            const int v = e & (nvec - 1), n = e >> plan.lvec;
+            return (v0 + v < count) ? base[(int64_t)(v0 + v) * vs + (int64_t)n * es] : make_float2(0.f, 0.f);
+        },
+        [&](int e, float2 z) { b0[e] = z; });
     __syncthreads();
     const float2 *res = fft_lds(b0, b1, plan, tw, sigma);
     for (int e = threadIdx.x; e < tot; e += FNT) {
@@ -68,20 +72,23 @@ __global__ __launch_bounds__(FNT) void rfft_rows(const float *__restrict__ Y, co
     const float mu = mean ? (float)mean[blockIdx.y] : 0.f;
     float2 *b0 = lds, *b1 = lds + FCAP;
     const int tot = M * nvec;
-    for (int e = threadIdx.x; e < tot; e += FNT) {
-        const int v = e & (nvec - 1), n = e >> plan.lvec;
-        float2 z = make_float2(0.f, 0.f);
-        if (r0 + v < h) {
-            const int64_t o = (int64_t)(r0 + v) * w + 2 * n;
-            float a = yp[o], b = yp[o + 1];
-            if (mp) {
-                a *= mp[o];
-                b *= mp[o + 1];
+    staged_copy<FNT, 8, float2>(
+        threadIdx.x, tot,
+        [&](int e) {
+            const int v = e & (nvec - 1), n = e >> plan.lvec;
+            float2 z = make_float2(0.f, 0.f);
+            if (r0 + v < h) {
+                const int64_t o = (int64_t)(r0 + v) * w + 2 * n;
+                float a = yp[o], b = yp[o + 1];
+                if (mp) {
+                    a *= mp[o];
+                    b *= mp[o + 1];
+                }
+                z = make_float2(a - mu, b - mu);
             }
-            z = make_float2(a - mu, b - mu);
-        }
-        b0[e] = z;
-    }
+            return z;
+        },
+        [&](int e, float2 z) { b0[e] = z; });
     __syncthreads();
     const float2 *res = fft_lds(b0, b1, plan, tw_half, -1.f);
     // Split the even/odd-sample spectra: Y[k] = E[k] + W_w^k O[k].
@@ -118,27 +125,44 @@ __global__ __launch_bounds__(FNT) void fft_cols_power(const float2 *__restrict__
     const float2 *sp = S + (int64_t)blockIdx.y * plane;
     float2 *b0 = lds, *b1 = lds + FCAP;
     const int tot = h * nvec;
-    for (int e = threadIdx.x; e < tot; e += FNT) {
-        const int v = e & (nvec - 1), n = e >> plan.lvec;
-        b0[e] = (c0 + v < Mc) ? sp[(int64_t)n * Mc + c0 + v] : make_float2(0.f, 0.f);
-    }
+    staged_copy<FNT, 8, float2>(
+        threadIdx.x, tot,
+        [&](int e) {
+            const int v = e & (nvec - 1), n = e >> plan.lvec;
+            return (c0 + v < Mc) ? sp[(int64_t)n * Mc + c0 + v] : make_float2(0.f, 0.f);
+        },
+        [&](int e, float2 z) { b0[e] = z; });
     __syncthreads();
     const float2 *res = fft_lds(b0, b1, plan, tw, -1.f);
     const int pid = p0 + (int)blockIdx.y;
     double acc = 0.0;
     const float *pq = DOT ? Px + (int64_t)(pid / ny) * plane : nullptr;
-    for (int e = threadIdx.x; e < tot; e += FNT) {
-        const int v = e & (nvec - 1), n = e >> plan.lvec;
-        const int col = c0 + v;
-        if (col >= Mc) continue;
-        const float2 z = res[e];
-        float pw = z.x * z.x + z.y * z.y;
-        if (n == 0 && col == 0) pw = 0.f;
+    constexpr int KB = 8;  // the power weights of KB elements are loaded before they are used
+    for (int e0 = threadIdx.x; e0 < tot; e0 += KB * FNT) {
+        float px[KB];
         if (DOT) {
-            const float wgt = (col == 0 || col == Mc - 1) ? 1.f : 2.f;
-            acc += (double)(wgt * pw) * (double)pq[(int64_t)n * Mc + col];
-        } else {
-            Pout[(int64_t)blockIdx.y * plane + (int64_t)n * Mc + col] = pw;
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                const int e = e0 + k * FNT;
+                const int v = e & (nvec - 1), n = e >> plan.lvec;
+                px[k] = (e < tot && c0 + v < Mc) ? pq[(int64_t)n * Mc + c0 + v] : 0.f;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const int e = e0 + k * FNT;
+            const int v = e & (nvec - 1), n = e >> plan.lvec;
+            const int col = c0 + v;
+            if (e >= tot || col >= Mc) continue;
+            const float2 z = res[e];
+            float pw = z.x * z.x + z.y * z.y;
+            if (n == 0 && col == 0) pw = 0.f;
+            if (DOT) {
+                const float wgt = (col == 0 || col == Mc - 1) ? 1.f : 2.f;
+                acc += (double)(wgt * pw) * (double)px[k];
+            } else {
+                Pout[(int64_t)blockIdx.y * plane + (int64_t)n * Mc + col] = pw;
+            }
         }
     }
     if (DOT) {

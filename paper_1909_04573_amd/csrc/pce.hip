@@ -13,6 +13,7 @@
 #include <climits>
 
 #include "internal.h"
+#include "stage_dev.h"
 
 namespace prnu {
 namespace {
@@ -233,14 +234,17 @@ __global__ __launch_bounds__(NT) void pce_direct(const float *__restrict__ X, co
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int ty0 = (tile / tiles_x) * DTY, tx0 = (tile % tiles_x) * DTX;
         __syncthreads();
-        for (int e = tid; e < XTH * XTW; e += NT) {
-            const int i = e / XTW, jj = e - (e / XTW) * XTW;
-            int gr = (ty0 - DRAD + i) % h;
-            gr = gr < 0 ? gr + h : gr;
-            int gc = (tx0 - DRAD + jj) % w;
-            gc = gc < 0 ? gc + w : gc;
-            xs[i * XTWS + jj] = xp[(int64_t)gr * w + gc] - mux;
-        }
+        staged_copy<NT, 4, float>(
+            tid, XTH * XTW,
+            [&](int e) {
+                const int i = e / XTW, jj = e - (e / XTW) * XTW;
+                int gr = (ty0 - DRAD + i) % h;
+                gr = gr < 0 ? gr + h : gr;
+                int gc = (tx0 - DRAD + jj) % w;
+                gc = gc < 0 ? gc + w : gc;
+                return xp[(int64_t)gr * w + gc] - mux;
+            },
+            [&](int e, float v) { xs[(e / XTW) * XTWS + e - (e / XTW) * XTW] = v; });
         __syncthreads();
         const int gy = ty0 + ty, gx = tx0 + 4 * tq;
         float yv[4];

@@ -6,6 +6,7 @@
 // double, then one block combining them), so results are deterministic.
 
 #include "internal.h"
+#include "stage_dev.h"
 #include "wiener_dev.h"
 
 namespace prnu {
@@ -210,16 +211,19 @@ __global__ __launch_bounds__(NT) void spectral_wiener_kernel(const float2 *__res
     const float2 *Fp = F + (int64_t)p * N;
     float2 *Gp = G + (int64_t)p * N;
     const float invN = (float)(1.0 / (double)N);
-    for (int e = threadIdx.x; e < WNC * WNC; e += NT) {
-        const int i = e / WNC, j = e - (e / WNC) * WNC;
-        const int gr = r0 + i, gc = c0 + j;
-        float v = 0.f;
-        if (gr >= 0 && gr < h && gc >= 0 && gc < w) {
-            const float2 z = Fp[(int64_t)gr * w + gc];
-            v = (z.x * z.x + z.y * z.y) * invN;
-        }
-        q[i * WNCS + j] = v;
-    }
+    staged_copy<NT, 8, float>(
+        threadIdx.x, WNC * WNC,
+        [&](int e) {
+            const int i = e / WNC, j = e - (e / WNC) * WNC;
+            const int gr = r0 + i, gc = c0 + j;
+            float v = 0.f;
+            if (gr >= 0 && gr < h && gc >= 0 && gc < w) {
+                const float2 z = Fp[(int64_t)gr * w + gc];
+                v = (z.x * z.x + z.y * z.y) * invN;
+            }
+            return v;
+        },
+        [&](int e, float v) { q[(e / WNC) * WNCS + e - (e / WNC) * WNC] = v; });
     __syncthreads();
     const float s2 = sigma2 >= 0.f ? sigma2 : (float)var[p];
     if (threadIdx.x < 2 * WT) {

@@ -10,6 +10,7 @@
 #include <hip/hip_bf16.h>
 
 #include "internal.h"
+#include "stage_dev.h"
 
 namespace prnu {
 namespace {
@@ -33,7 +34,8 @@ __device__ __forceinline__ void sda_u8_body(const uint8_t *__restrict__ frames, 
 #pragma unroll
     for (int k = 0; k < 4 * C; ++k) acc[k] = 0;
     const int64_t frame_bytes = npx * C;
-    const uint32_t *base = reinterpret_cast<const uint32_t *>(frames + (int64_t)f0 * frame_bytes) + q * C;
+    const PRNU_GLOBAL uint32_t *base =
+        gmem(reinterpret_cast<const uint32_t *>(frames + (int64_t)f0 * frame_bytes)) + q * C;
     const int64_t fstride = frame_bytes / 4;
     int f = 0;
     for (; f + 4 <= cnt; f += 4) {
@@ -65,11 +67,10 @@ __device__ __forceinline__ void sda_u8_body(const uint8_t *__restrict__ frames, 
 #pragma unroll
         for (int p = 0; p < 4; ++p) s[p] = acc[p * C + c];
         const int64_t o = gbase + (int64_t)c * npx + q * 4;
-        if (sums) *reinterpret_cast<uint4 *>(sums + o) = make_uint4(s[0], s[1], s[2], s[3]);
+        if (sums) st4<uint32_t>(gmem(sums) + o, s[0], s[1], s[2], s[3]);
         if (means) {
             const float fc = (float)cnt;
-            *reinterpret_cast<float4 *>(means + o) =
-                make_float4((float)s[0] / fc, (float)s[1] / fc, (float)s[2] / fc, (float)s[3] / fc);
+            st4<float>(gmem(means) + o, (float)s[0] / fc, (float)s[1] / fc, (float)s[2] / fc, (float)s[3] / fc);
         }
     }
 }
@@ -86,21 +87,21 @@ __device__ __forceinline__ void sda_generic_body(const void *__restrict__ frames
     const int64_t gbase = (int64_t)go * C * npx;
     for (int c = 0; c < C; ++c) {
         if (DT == PRNU_U8) {
-            const uint8_t *fr = static_cast<const uint8_t *>(frames);
+            const PRNU_GLOBAL uint8_t *fr = gmem(static_cast<const uint8_t *>(frames));
             uint32_t s = 0;
             for (int f = 0; f < cnt; ++f) s += fr[((int64_t)(f0 + f) * npx + p) * C + c];
-            if (sums) sums[gbase + (int64_t)c * npx + p] = s;
-            if (means) means[gbase + (int64_t)c * npx + p] = (float)s / (float)cnt;
+            if (sums) gmem(sums)[gbase + (int64_t)c * npx + p] = s;
+            if (means) gmem(means)[gbase + (int64_t)c * npx + p] = (float)s / (float)cnt;
         } else {
             double s = 0.0;
             for (int f = 0; f < cnt; ++f) {
                 const int64_t e = ((int64_t)(f0 + f) * npx + p) * C + c;
                 if (DT == PRNU_BF16)
-                    s += (double)bf16_to_float(static_cast<const uint16_t *>(frames)[e]);
+                    s += (double)bf16_to_float(gmem(static_cast<const uint16_t *>(frames))[e]);
                 else
-                    s += (double)static_cast<const float *>(frames)[e];
+                    s += (double)gmem(static_cast<const float *>(frames))[e];
             }
-            if (means) means[gbase + (int64_t)c * npx + p] = (float)(s / (double)cnt);
+            if (means) gmem(means)[gbase + (int64_t)c * npx + p] = (float)(s / (double)cnt);
         }
     }
 }

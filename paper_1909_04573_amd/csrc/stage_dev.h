@@ -1,0 +1,56 @@
+// Device helpers for global-memory access.
+//
+// staged_copy: cooperative staging of global data into LDS.  Thread `tid` of
+// a group of NTH threads handles elements tid, tid + NTH, ... of `count`; it
+// issues up to KB loads before storing them, so a batch of global loads is in
+// flight at once instead of one load per round trip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace prnu {
+
+// Global-memory views of caller pointers.  Pointers the work-queue kernels
+// read from their descriptor tables would otherwise be accessed with flat
+// instructions, whose completion shares a wait counter with LDS reads and so
+// serialises a tile's loads behind its LDS index look-ups.
+#define PRNU_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ PRNU_GLOBAL T *gmem(T *p) {
+    return (PRNU_GLOBAL T *)p;
+}
+template <typename T>
+__device__ __forceinline__ const PRNU_GLOBAL T *gmem(const T *p) {
+    return (const PRNU_GLOBAL T *)p;
+}
+// Two consecutive floats (8-byte aligned) in one load.
+__device__ __forceinline__ float2 ld2(const PRNU_GLOBAL float *p) {
+    typedef float v2 __attribute__((ext_vector_type(2)));
+    const v2 t = *(const PRNU_GLOBAL v2 *)p;
+    return make_float2(t.x, t.y);
+}
+// Four consecutive 32-bit values (16-byte aligned) in one store.
+template <typename T>
+__device__ __forceinline__ void st4(PRNU_GLOBAL T *p, T a, T b, T c, T d) {
+    typedef T v4 __attribute__((ext_vector_type(4)));
+    *(PRNU_GLOBAL v4 *)p = v4{a, b, c, d};
+}
+
+template <int NTH, int KB, typename T, typename Load, typename Store>
+__device__ __forceinline__ void staged_copy(int tid, int count, Load load, Store store) {
+    for (int e0 = tid; e0 < count; e0 += KB * NTH) {
+        T v[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const int e = e0 + k * NTH;
+            if (e < count) v[k] = load(e);
+        }
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const int e = e0 + k * NTH;
+            if (e < count) store(e, v[k]);
+        }
+    }
+}
+
+}  // namespace prnu
