@@ -131,6 +131,8 @@ def main():
     log(f"inputs ready in {time.time() - t0:.1f} s ({frames.numel() / 1e9:.2f} GB frames)")
 
     p = prnu.denoise_params()
+    tiles = prnu.autotune(H, W, C, p, device=dev)  # tile side per level kernel, timed on this GPU
+    log(f"autotuned tiles: {tiles}")
     A, B = prnu.new_accumulators(C, H, W, device=dev)
     ws = prnu.workspace(max(prnu.fingerprint_accumulate_workspace_size(nfp, H, W, C, d, p) for d in depths), dev)
     K = {d: torch.empty((ncam, H, W), dtype=torch.float32, device=dev) for d in depths}
@@ -282,6 +284,7 @@ def main():
             "query_residual_ms": stage_ms("query"),
             "per_depth": per_depth,
             "kernels": kernels,
+            "tiles": tiles,
             "gpu_vs_fp64_oracle": err,
             "paper_context": "Table IV (single-threaded MATLAB, Xeon E5-2687W v2): SDA-50 is 29.3x, "
                              "SDA-10 9.9x faster than all-frames; not this hardware",

@@ -8,7 +8,9 @@
 // does an R-point DFT and writes y[(j / Ns) Ns R + k + r Ns].  Passes
 // ping-pong between two LDS buffers, so each thread only holds one
 // butterfly's values at a time.  Twiddles W_N^k = exp(-2 pi i k / N) are
-// rounded to float from double-precision sincospi once per size.
+// rounded to float from double-precision sincospi once per size and staged
+// into LDS with the data, so a pass touches no global memory.  LDS is sized
+// per launch: two data buffers of N * nvec plus the twiddle table(s).
 //
 // Kernels:
 //   fft_1d          complex transform of rows or columns, in place in HBM
@@ -33,12 +35,13 @@ namespace {
 __global__ __launch_bounds__(FNT) void fft_1d(float2 *__restrict__ data, int N, int count, int64_t es,
                                               int64_t vs, int64_t plane_stride, FftPlan plan,
                                               const float2 *__restrict__ tw, float sigma) {
-    __shared__ float2 lds[2 * FCAP];
+    extern __shared__ float2 smem[];
     const int nvec = plan.nvec;
     const int v0 = blockIdx.x * nvec;
     float2 *base = data + (int64_t)blockIdx.y * plane_stride;
     const int tot = N * nvec;
-    float2 *b0 = lds, *b1 = lds + FCAP;
+    float2 *b0 = smem, *b1 = smem + tot, *twl = smem + 2 * tot;
+    staged_copy<FNT, 4, float2>(threadIdx.x, N, [&](int e) { return tw[e]; }, [&](int e, float2 z) { twl[e] = z; });
     staged_copy<FNT, 8, float2>(
         threadIdx.x, tot,
         [&](int e) {
@@ -47,7 +50,7 @@ __global__ __launch_bounds__(FNT) void fft_1d(float2 *__restrict__ data, int N, 
         },
         [&](int e, float2 z) { b0[e] = z; });
     __syncthreads();
-    const float2 *res = fft_lds(b0, b1, plan, tw, sigma);
+    const float2 *res = fft_lds(b0, b1, plan, twl, sigma);
     for (int e = threadIdx.x; e < tot; e += FNT) {
         const int v = e & (nvec - 1), n = e >> plan.lvec;
         if (v0 + v < count) base[(int64_t)(v0 + v) * vs + (int64_t)n * es] = res[e];
@@ -61,7 +64,7 @@ __global__ __launch_bounds__(FNT) void rfft_rows(const float *__restrict__ Y, co
                                                  int ny, int p0, const double *__restrict__ mean, int h,
                                                  int w, FftPlan plan, const float2 *__restrict__ tw_half,
                                                  const float2 *__restrict__ tw_full, float2 *__restrict__ out) {
-    __shared__ float2 lds[2 * FCAP];
+    extern __shared__ float2 smem[];
     const int M = w / 2;
     const int nvec = plan.nvec;
     const int r0 = blockIdx.x * nvec;
@@ -70,8 +73,12 @@ __global__ __launch_bounds__(FNT) void rfft_rows(const float *__restrict__ Y, co
     const float *yp = Y + (int64_t)(pid % ny) * N;
     const float *mp = mod ? mod + (int64_t)(pid / ny) * N : nullptr;
     const float mu = mean ? (float)mean[blockIdx.y] : 0.f;
-    float2 *b0 = lds, *b1 = lds + FCAP;
     const int tot = M * nvec;
+    float2 *b0 = smem, *b1 = smem + tot, *twh = smem + 2 * tot, *twf = twh + M;
+    staged_copy<FNT, 4, float2>(threadIdx.x, M, [&](int e) { return tw_half[e]; },
+                                [&](int e, float2 z) { twh[e] = z; });
+    staged_copy<FNT, 4, float2>(threadIdx.x, M + 1, [&](int e) { return tw_full[e]; },
+                                [&](int e, float2 z) { twf[e] = z; });
     staged_copy<FNT, 8, float2>(
         threadIdx.x, tot,
         [&](int e) {
@@ -90,7 +97,7 @@ __global__ __launch_bounds__(FNT) void rfft_rows(const float *__restrict__ Y, co
         },
         [&](int e, float2 z) { b0[e] = z; });
     __syncthreads();
-    const float2 *res = fft_lds(b0, b1, plan, tw_half, -1.f);
+    const float2 *res = fft_lds(b0, b1, plan, twh, -1.f);
     // Split the even/odd-sample spectra: Y[k] = E[k] + W_w^k O[k].
     float2 *op = out + (int64_t)blockIdx.y * h * (M + 1);
     const int tot2 = (M + 1) * nvec;
@@ -102,8 +109,7 @@ __global__ __launch_bounds__(FNT) void rfft_rows(const float *__restrict__ Y, co
         // E = (zk + conj zm) / 2 ; O = (zk - conj zm) / (2i)
         const float2 E = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
         const float2 O = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
-        const float2 t = tw_full[k];  // exp(-2 pi i k / w), k <= w/2
-        const float2 tO = cmul(t, O);
+        const float2 tO = cmul(twf[k], O);  // exp(-2 pi i k / w), k <= w/2
         op[(int64_t)(r0 + v) * (M + 1) + k] = make_float2(E.x + tO.x, E.y + tO.y);
     }
 }
@@ -118,13 +124,14 @@ __global__ __launch_bounds__(FNT) void fft_cols_power(const float2 *__restrict__
                                                       const float2 *__restrict__ tw, const float *__restrict__ Px,
                                                       int ny, int p0, float *__restrict__ Pout,
                                                       double *__restrict__ part) {
-    __shared__ float2 lds[2 * FCAP];
+    extern __shared__ float2 smem[];
     const int nvec = plan.nvec;
     const int c0 = blockIdx.x * nvec;
     const int64_t plane = (int64_t)h * Mc;
     const float2 *sp = S + (int64_t)blockIdx.y * plane;
-    float2 *b0 = lds, *b1 = lds + FCAP;
     const int tot = h * nvec;
+    float2 *b0 = smem, *b1 = smem + tot, *twl = smem + 2 * tot;
+    staged_copy<FNT, 4, float2>(threadIdx.x, h, [&](int e) { return tw[e]; }, [&](int e, float2 z) { twl[e] = z; });
     staged_copy<FNT, 8, float2>(
         threadIdx.x, tot,
         [&](int e) {
@@ -133,7 +140,7 @@ __global__ __launch_bounds__(FNT) void fft_cols_power(const float2 *__restrict__
         },
         [&](int e, float2 z) { b0[e] = z; });
     __syncthreads();
-    const float2 *res = fft_lds(b0, b1, plan, tw, -1.f);
+    const float2 *res = fft_lds(b0, b1, plan, twl, -1.f);
     const int pid = p0 + (int)blockIdx.y;
     double acc = 0.0;
     const float *pq = DOT ? Px + (int64_t)(pid / ny) * plane : nullptr;
@@ -205,6 +212,19 @@ bool make_fft_plan(int n, FftPlan *p) {
 
 size_t fft_twiddle_floats(int n) { return (size_t)2 * n; }
 
+// Dynamic LDS of a transform workgroup: two data buffers and `tw` twiddles
+// (at most 2 * 5120 + 5121 complex values, 123 KB).
+unsigned fft_lds_bytes(const FftPlan &p, int tw) {
+    return (unsigned)(sizeof(float2) * ((size_t)2 * p.n * p.nvec + (size_t)tw));
+}
+
+// Allows a kernel the dynamic LDS of its launch.
+template <typename K>
+hipError_t allow_lds(K kernel, unsigned bytes) {
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
+
 hipError_t launch_twiddles(int n, float2 *tw, hipStream_t s) {
     twiddle_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, tw);
     return hipGetLastError();
@@ -219,7 +239,10 @@ hipError_t launch_fft2(float2 *data, int batch, int h, int w, const FftPlan &ph,
     dim3 gr((unsigned)((h + pw.nvec - 1) / pw.nvec), (unsigned)batch);
     {
         KernelTimer kt("fft_1d", bytes, s);
-        fft_1d<<<gr, FNT, 0, s>>>(data, w, h, 1, w, plane, pw, tw_w, sigma);
+        const unsigned lds = fft_lds_bytes(pw, pw.n);
+        hipError_t e = allow_lds(fft_1d, lds);
+        if (e != hipSuccess) return e;
+        fft_1d<<<gr, FNT, lds, s>>>(data, w, h, 1, w, plane, pw, tw_w, sigma);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -227,7 +250,10 @@ hipError_t launch_fft2(float2 *data, int batch, int h, int w, const FftPlan &ph,
     dim3 gc((unsigned)((w + ph.nvec - 1) / ph.nvec), (unsigned)batch);
     {
         KernelTimer kt("fft_1d", bytes, s);
-        fft_1d<<<gc, FNT, 0, s>>>(data, h, w, w, 1, plane, ph, tw_h, sigma);
+        const unsigned lds = fft_lds_bytes(ph, ph.n);
+        e = allow_lds(fft_1d, lds);
+        if (e != hipSuccess) return e;
+        fft_1d<<<gc, FNT, lds, s>>>(data, h, w, w, 1, plane, ph, tw_h, sigma);
     }
     return hipGetLastError();
 }
@@ -238,7 +264,10 @@ hipError_t launch_rfft_rows(const float *Y, const float *mod, int ny, int p0, in
     const double bytes = (double)n * h * ((mod ? 8.0 : 4.0) * w + 8.0 * (w / 2 + 1));
     KernelTimer kt("rfft_rows", bytes, s);
     dim3 g((unsigned)((h + phalf.nvec - 1) / phalf.nvec), (unsigned)n);
-    rfft_rows<<<g, FNT, 0, s>>>(Y, mod, ny, p0, mean, h, w, phalf, tw_half, tw_full, out);
+    const unsigned lds = fft_lds_bytes(phalf, 2 * phalf.n + 1);
+    const hipError_t e = allow_lds(rfft_rows, lds);
+    if (e != hipSuccess) return e;
+    rfft_rows<<<g, FNT, lds, s>>>(Y, mod, ny, p0, mean, h, w, phalf, tw_half, tw_full, out);
     return hipGetLastError();
 }
 
@@ -248,12 +277,17 @@ hipError_t launch_fft_cols_power(const float2 *S, int n, int h, int Mc, const Ff
                                  const float *Px, int ny, int p0, float *Pout, double *part, hipStream_t s) {
     const double bytes = (double)n * h * Mc * (8.0 + 4.0);
     dim3 g((unsigned)fft_cols_power_blocks(Mc, ph), (unsigned)n);
+    const unsigned lds = fft_lds_bytes(ph, ph.n);
     if (Px) {
+        const hipError_t e = allow_lds(fft_cols_power<true>, lds);
+        if (e != hipSuccess) return e;
         KernelTimer kt("fft_cols_power_dot", bytes, s);
-        fft_cols_power<true><<<g, FNT, 0, s>>>(S, h, Mc, ph, tw_h, Px, ny, p0, nullptr, part);
+        fft_cols_power<true><<<g, FNT, lds, s>>>(S, h, Mc, ph, tw_h, Px, ny, p0, nullptr, part);
     } else {
+        const hipError_t e = allow_lds(fft_cols_power<false>, lds);
+        if (e != hipSuccess) return e;
         KernelTimer kt("fft_cols_power_store", bytes, s);
-        fft_cols_power<false><<<g, FNT, 0, s>>>(S, h, Mc, ph, tw_h, nullptr, ny, p0, Pout, nullptr);
+        fft_cols_power<false><<<g, FNT, lds, s>>>(S, h, Mc, ph, tw_h, nullptr, ny, p0, Pout, nullptr);
     }
     return hipGetLastError();
 }
