@@ -107,7 +107,7 @@ void carve_post(Carver &cv, int nf, int C, int H, int W, int flags, PostWs *pw) 
 }
 
 int check_fft_dims(int H, int W, const char *fn, FftPlan *ph, FftPlan *pw) {
-    if (!make_fft_plan(H, ph) || !make_fft_plan(W, pw))
+    if (!make_fft_plan(H, ph, true) || !make_fft_plan(W, pw))
         return fail(PRNU_E_UNSUPPORTED, "%s: DFT sizes need prime factors <= 5 and <= 5120 (got %d x %d)",
                     fn, H, W);
     return PRNU_OK;
@@ -235,7 +235,7 @@ void plan_pce_fast(Carver &cv, int nx, int ny, int h, int w, bool modulated, Pce
     pp->spart = cv.take<double>(stats_part_doubles(mx));
     pp->dpart = cv.take<double>(pce_direct_part_doubles((int)P, h, w));
     FftPlan ph;
-    make_fft_plan(h, &ph);
+    make_fft_plan(h, &ph, true);
     const int ncb = fft_cols_power_blocks(Mc, ph);
     const int nsb = ncb > pce_dot_blocks() ? ncb : pce_dot_blocks();
     pp->cpart = cv.take<double>((size_t)P * nsb);
@@ -318,7 +318,7 @@ int pce_fixed_fast(const float *X, int nx, const float *Y, int ny, int h, int w,
     const int64_t N = (int64_t)h * w;
     const int Mc = pl.Mc;
     FftPlan ph, phalf;
-    make_fft_plan(h, &ph);
+    make_fft_plan(h, &ph, true);
     make_fft_plan(w / 2, &phalf);
     PRNU_HIP(launch_twiddles(h, pl.tw_h, s));
     PRNU_HIP(launch_twiddles(w, pl.tw_w, s));

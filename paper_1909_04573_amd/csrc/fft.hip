@@ -190,7 +190,7 @@ __global__ void twiddle_kernel(int n, float2 *tw) {
 
 }  // namespace
 
-bool make_fft_plan(int n, FftPlan *p) {
+bool make_fft_plan(int n, FftPlan *p, bool columns) {
     if (n < 1 || n > FCAP) return false;
     int m = n, k = 0;
     while (m % 4 == 0 && k < 16) { p->rad[k++] = 4; m /= 4; }
@@ -200,8 +200,11 @@ bool make_fft_plan(int n, FftPlan *p) {
     if (m != 1) return false;
     p->n = n;
     p->nrad = k;
+    // Column transforms read nvec adjacent complex values per row: they keep
+    // up to twice as many vectors per workgroup for longer contiguous reads.
+    const int target = columns ? 2 * FVEC : FVEC;
     int nv = 16, lv = 4;
-    while (nv > 1 && n * nv > FCAP) {
+    while (nv > 1 && n * nv > target) {
         nv /= 2;
         --lv;
     }
@@ -213,7 +216,7 @@ bool make_fft_plan(int n, FftPlan *p) {
 size_t fft_twiddle_floats(int n) { return (size_t)2 * n; }
 
 // Dynamic LDS of a transform workgroup: two data buffers and `tw` twiddles
-// (at most 2 * 5120 + 5121 complex values, 123 KB).
+// (at most 2 * 5120 + 5121 complex values, 123 KB, for one vector of 5120).
 unsigned fft_lds_bytes(const FftPlan &p, int tw) {
     return (unsigned)(sizeof(float2) * ((size_t)2 * p.n * p.nvec + (size_t)tw));
 }

@@ -8,7 +8,8 @@
 namespace prnu {
 
 constexpr int FNT = 256;    // threads per FFT workgroup
-constexpr int FCAP = 5120;  // complex elements per LDS buffer (two buffers: 80 KiB)
+constexpr int FCAP = 5120;  // longest transform
+constexpr int FVEC = 2560;  // vectors per workgroup: as many as keep nvec * N within this
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -82,29 +83,43 @@ template <int R>
 __device__ __forceinline__ void stockham_pass(const float2 *__restrict__ src, float2 *__restrict__ dst, int N,
                                               int nvec, int lvec, int Ns, const float2 *__restrict__ tw,
                                               float sigma) {
+    // KB butterflies per thread per batch: their LDS reads are issued together
+    constexpr int KB = R == 5 ? 3 : 4;
     const int NR = N / R;
     const int nb = NR * nvec;
     const int tws = N / (Ns * R);
     const float inv_ns = 1.0f / (float)Ns;
-    for (int idx = threadIdx.x; idx < nb; idx += FNT) {
-        const int vv = idx & (nvec - 1), j = idx >> lvec;
-        const int jq = udiv_small(j, Ns, inv_ns);
-        const int k = j - jq * Ns;
-        float2 v[R];
+    for (int idx0 = threadIdx.x; idx0 < nb; idx0 += KB * FNT) {
+        float2 v[KB][R];
+        int kk[KB], d0[KB];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            float2 x = src[(j + r * NR) * nvec + vv];
-            if (r > 0) {
-                float2 w = tw[k * r * tws];
-                w.y *= -sigma;  // table holds exp(-2 pi i k / N); the inverse uses its conjugate
-                x = cmul(x, w);
+        for (int b = 0; b < KB; ++b) {
+            const int idx = idx0 + b * FNT;
+            if (idx < nb) {
+                const int vv = idx & (nvec - 1), j = idx >> lvec;
+                const int jq = udiv_small(j, Ns, inv_ns);
+                const int k = j - jq * Ns;
+                kk[b] = k;
+                d0[b] = (jq * Ns * R + k) * nvec + vv;
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[b][r] = src[(j + r * NR) * nvec + vv];
             }
-            v[r] = x;
         }
-        dft<R>(v, sigma);
-        const int d0 = (jq * Ns * R + k) * nvec + vv;
 #pragma unroll
-        for (int r = 0; r < R; ++r) dst[d0 + r * Ns * nvec] = v[r];
+        for (int b = 0; b < KB; ++b) {
+            const int idx = idx0 + b * FNT;
+            if (idx < nb) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    float2 w = tw[kk[b] * r * tws];
+                    w.y *= -sigma;  // table holds exp(-2 pi i k / N); the inverse uses its conjugate
+                    v[b][r] = cmul(v[b][r], w);
+                }
+                dft<R>(v[b], sigma);
+#pragma unroll
+                for (int r = 0; r < R; ++r) dst[d0[b] + r * Ns * nvec] = v[b][r];
+            }
+        }
     }
     __syncthreads();
 }

@@ -185,7 +185,8 @@ struct FftPlan {
     int nvec;     // vectors per workgroup (power of two)
     int lvec;     // log2(nvec)
 };
-bool make_fft_plan(int n, FftPlan *p);
+// columns: a plan for strided (column) vectors, which groups more vectors.
+bool make_fft_plan(int n, FftPlan *p, bool columns = false);
 size_t fft_twiddle_floats(int n);  // complex table of n entries, 2 floats each
 hipError_t launch_twiddles(int n, float2 *tw, hipStream_t s);
 // In-place 2-D complex FFT on `batch` planes [h][w] (plane stride h*w).
