@@ -208,6 +208,19 @@ bool pce_fast_ok(int h, int w, int peak_mode, int nbhd) {
            make_fft_plan(w / 2, &b) && make_fft_plan(w, &b);
 }
 
+// Fingerprints per query from which the matrix-core direct sums pay off.
+constexpr int kMfmaMinFingerprints = 3;
+constexpr int64_t kMfmaPartDoubles = 8ll << 20;  // direct-sum partials per query chunk (64 MiB)
+
+// Queries per chunk of the matrix-core direct sums.
+int mfma_query_chunk(int nx, int ny, int nblk) {
+    int64_t qc = kMfmaPartDoubles / ((int64_t)ny * nblk * kPceDirectStats);
+    if (qc < 1) qc = 1;
+    if (qc > nx) qc = nx;
+    if (qc > 65535) qc = 65535;
+    return (int)qc;
+}
+
 void plan_pce_fast(Carver &cv, int nx, int ny, int h, int w, bool modulated, PcePlan *pp) {
     const int64_t N = (int64_t)h * w;
     const int Mc = w / 2 + 1;
@@ -233,7 +246,13 @@ void plan_pce_fast(Carver &cv, int nx, int ny, int h, int w, bool modulated, Pce
     pp->yn2 = cv.take<double>((size_t)ny);
     int mx = nx > ny ? nx : ny;
     pp->spart = cv.take<double>(stats_part_doubles(mx));
-    pp->dpart = cv.take<double>(pce_direct_part_doubles((int)P, h, w));
+    size_t dpart = pce_direct_part_doubles((int)P, h, w);
+    if (ny >= kMfmaMinFingerprints) {
+        const int nbm = pce_mfma_blocks(nx, ny, h, w);
+        const size_t m = (size_t)mfma_query_chunk(nx, ny, nbm) * ny * nbm * kPceDirectStats;
+        if (m > dpart) dpart = m;
+    }
+    pp->dpart = cv.take<double>(dpart);
     FftPlan ph;
     make_fft_plan(h, &ph, true);
     const int ncb = fft_cols_power_blocks(Mc, ph);
@@ -341,19 +360,42 @@ int pce_fixed_fast(const float *X, int nx, const float *Y, int ny, int h, int w,
                                            s));
         }
     }
+    // energy of the pairs p0 .. p0+n-1 into cpart; returns the partials per pair
+    auto energy = [&](int64_t p0, int n, int *nbs) -> int {
+        if (mod) {
+            PRNU_HIP(launch_rfft_rows(Y, mod, ny, (int)p0, n, nullptr, h, w, phalf, pl.tw_half, pl.tw_w, pl.Z, s));
+            PRNU_HIP(launch_fft_cols_power(pl.Z, n, h, Mc, ph, pl.tw_h, pl.Px, ny, (int)p0, nullptr, pl.cpart, s));
+            *nbs = fft_cols_power_blocks(Mc, ph);
+        } else {
+            PRNU_HIP(launch_power_dot(pl.Px, pl.Py, ny, (int)p0, n, h, Mc, pl.cpart, s));
+            *nbs = pce_dot_blocks();
+        }
+        return PRNU_OK;
+    };
+    if (ny >= kMfmaMinFingerprints) {
+        // direct sums of every fingerprint of a chunk of queries on the matrix cores
+        const int nbm = pce_mfma_blocks(nx, ny, h, w);
+        const int qc = mfma_query_chunk(nx, ny, nbm);
+        for (int q0 = 0; q0 < nx; q0 += qc) {
+            const int nq = nx - q0 < qc ? nx - q0 : qc;
+            PRNU_HIP(launch_pce_direct_mfma(X, pl.xmean, Y, mod, ny, q0, nq, h, w, nbm, pl.dpart, s));
+            const int64_t pa = (int64_t)q0 * ny, pb = (int64_t)(q0 + nq) * ny;
+            for (int64_t p0 = pa; p0 < pb; p0 += pl.P) {
+                const int n = (int)(pb - p0 < pl.P ? pb - p0 : pl.P);
+                int nbs = 0;
+                PRNU_TRY(energy(p0, n, &nbs));
+                PRNU_HIP(launch_pce_finish_fixed(pl.dpart + (p0 - pa) * nbm * kPceDirectStats, nbm, pl.cpart, nbs, n,
+                                                 h, w, nbhd, pl.xn2, ny, (int)p0, pce, ncc, peak, s));
+            }
+        }
+        return PRNU_OK;
+    }
     const int64_t npairs = (int64_t)nx * ny;
     const int nbd = pce_direct_blocks(h, w);
     for (int64_t p0 = 0; p0 < npairs; p0 += pl.P) {
         const int n = (int)(npairs - p0 < pl.P ? npairs - p0 : pl.P);
-        int nbs;
-        if (mod) {
-            PRNU_HIP(launch_rfft_rows(Y, mod, ny, (int)p0, n, nullptr, h, w, phalf, pl.tw_half, pl.tw_w, pl.Z, s));
-            PRNU_HIP(launch_fft_cols_power(pl.Z, n, h, Mc, ph, pl.tw_h, pl.Px, ny, (int)p0, nullptr, pl.cpart, s));
-            nbs = fft_cols_power_blocks(Mc, ph);
-        } else {
-            PRNU_HIP(launch_power_dot(pl.Px, pl.Py, ny, (int)p0, n, h, Mc, pl.cpart, s));
-            nbs = pce_dot_blocks();
-        }
+        int nbs = 0;
+        PRNU_TRY(energy(p0, n, &nbs));
         PRNU_HIP(launch_pce_direct(X, pl.xmean, Y, mod, ny, (int)p0, n, h, w, pl.dpart, s));
         PRNU_HIP(launch_pce_finish_fixed(pl.dpart, nbd, pl.cpart, nbs, n, h, w, nbhd, pl.xn2, ny, (int)p0, pce, ncc,
                                          peak, s));

@@ -208,6 +208,7 @@ __global__ __launch_bounds__(NT) void pce_finish(const float2 *__restrict__ z, i
 constexpr int DRAD = 5;
 constexpr int DNS = 2 * DRAD + 1;
 constexpr int DSTAT = DNS * DNS + 3;  // D(s), sum y, sum y^2, sum xc
+static_assert(DSTAT == kPceDirectStats, "partial layout shared with the host plan");
 constexpr int DTY = 16, DTX = 64;
 constexpr int XTH = DTY + 2 * DRAD, XTW = DTX + 2 * DRAD, XTWS = 76;
 
@@ -299,6 +300,176 @@ __global__ __launch_bounds__(NT) void pce_direct(const float *__restrict__ X, co
         double t = 0.0;
         for (int k = 0; k < NT / 64; ++k) t += (double)red[k][tid];
         part[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * DSTAT + tid] = t;
+    }
+}
+
+// ---- fixed-peak direct sums on the matrix cores ------------------------------
+// For one query q and 16 fingerprints j0 .. j0+15 the 121 shifted sums are
+// one product D[s][j] = sum_t xc(t + s) y_j(t) whose inner dimension runs over
+// the pixels t.  v_mfma_f32_16x16x4f32 multiplies 16 shifts x 4 pixels (A:
+// the centred query tile in LDS, read through per-lane shift offsets) by
+// 4 pixels x 16 fingerprints (B: the modulated fingerprint tile in LDS); eight
+// such products per pixel quad cover 128 rows: the 121 shifts, an all-ones row
+// (giving sum y) and 6 unused rows.  Lane layout (checked on the device):
+// A[i][k] and B[k][n] at lane 16 k + i / 16 k + n, C[4 (l / 16) + r][l % 16]
+// in slot r of lane l.  Each tile's fp32 products are added to FP64
+// accumulators; sum y^2 and sum xc are plain FP64 sums.
+constexpr int MTY = 8, MTX = 64;                              // pixel tile
+constexpr int MXH = MTY + 2 * DRAD, MXW = MTX + 2 * DRAD, MXWS = 76;  // query tile with the shift halo
+constexpr int MNJ = 16, MNS = 8;                              // fingerprints, shift blocks of 16
+constexpr int MYS = MTY * MTX + 4;                            // fingerprint stride in LDS (bank offset 4)
+constexpr int MONES = DNS * DNS;                              // row 121: all ones
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(NT) void pce_direct_mfma(const float *__restrict__ X, const double *__restrict__ xmean,
+                                                      const float *__restrict__ Y, const float *__restrict__ mod,
+                                                      int ny, int q0, int h, int w, int tiles_x, int ntiles,
+                                                      double *__restrict__ part) {
+    __shared__ float xs[MXH * MXWS];
+    __shared__ __align__(16) float ys[MNJ * MYS];  // reused for the FP64 reduction (32 KB)
+    __shared__ double sred[NT / 64];
+    const int q = q0 + (int)blockIdx.y;
+    const int j0 = (int)blockIdx.z * MNJ;
+    const int nblk = gridDim.x, blk = blockIdx.x;
+    const int64_t N = (int64_t)h * w;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const float *xp = X + (int64_t)q * N;
+    const float mux = (float)xmean[q];
+    const float *mp = mod ? mod + (int64_t)q * N : nullptr;
+    // A operand: row i = lane % 16 of shift block sb is shift m = 16 sb + i (rows past the
+    // ones row read shift (0,0) and are dropped), column k = lane / 16 is pixel k of the quad
+    int aoff[MNS];
+#pragma unroll
+    for (int sb = 0; sb < MNS; ++sb) {
+        const int m = 16 * sb + (lane & 15);
+        const int mm = m < DNS * DNS ? m : (DNS * DNS) / 2;
+        aoff[sb] = (mm / DNS) * MXWS + (mm % DNS) + (lane >> 4);
+    }
+    const bool ones_lane = (lane & 15) == MONES - 16 * (MNS - 1);
+    const int boff = (lane & 15) * MYS + (lane >> 4);  // B: fingerprint n = lane % 16, pixel k = lane / 16
+    // staging of the fingerprint tile: thread -> fingerprint sn, columns sc + 16 u
+    const int sn = tid >> 4, sc = tid & 15;
+    const float *yp = j0 + sn < ny ? Y + (int64_t)(j0 + sn) * N : nullptr;
+    double acc[MNS][4];
+#pragma unroll
+    for (int sb = 0; sb < MNS; ++sb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[sb][r] = 0.0;
+    double syy = 0.0, sx = 0.0;
+    for (int tile = blk; tile < ntiles; tile += nblk) {
+        const int ty0 = (tile / tiles_x) * MTY, tx0 = (tile % tiles_x) * MTX;
+        __syncthreads();  // previous tile's LDS reads are done
+        staged_copy<NT, 8, float>(
+            tid, MXH * MXW,
+            [&](int e) {
+                const int i = e / MXW, jj = e - (e / MXW) * MXW;
+                int gr = (ty0 - DRAD + i) % h;
+                gr = gr < 0 ? gr + h : gr;
+                int gc = (tx0 - DRAD + jj) % w;
+                gc = gc < 0 ? gc + w : gc;
+                return xp[(int64_t)gr * w + gc] - mux;
+            },
+            [&](int e, float v) { xs[(e / MXW) * MXWS + e - (e / MXW) * MXW] = v; });
+        float ssq = 0.f;
+#pragma unroll
+        for (int b0 = 0; b0 < 32; b0 += 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int kk = b0 + u, r = kk >> 2, c = sc + 16 * (kk & 3);
+                const int gy = ty0 + r, gx = tx0 + c;
+                float y = 0.f;
+                if (yp && gy < h && gx < w) {
+                    const int64_t o = (int64_t)gy * w + gx;
+                    y = mp ? mp[o] * yp[o] : yp[o];
+                }
+                v[u] = y;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int kk = b0 + u, r = kk >> 2, c = sc + 16 * (kk & 3);
+                ys[sn * MYS + r * MTX + c] = v[u];
+                ssq = fmaf(v[u], v[u], ssq);
+            }
+        }
+        syy += (double)ssq;
+        __syncthreads();
+        // sum of the centred query over this tile's pixels inside the image
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int t = tid + u * NT, r = t / MTX, c = t % MTX;
+            if (ty0 + r < h && tx0 + c < w) sx += (double)xs[(r + DRAD) * MXWS + c + DRAD];
+        }
+        // wave wv: pixel rows 2 wv, 2 wv + 1, sixteen quads each
+        v4f cacc[MNS];
+#pragma unroll
+        for (int sb = 0; sb < MNS; ++sb) cacc[sb] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int g = 0; g < 32; ++g) {
+            const int r = 2 * wv + (g >> 4), c4 = (g & 15) * 4;
+            const float b = ys[boff + r * MTX + c4];
+            const int xb = r * MXWS + c4;
+#pragma unroll
+            for (int sb = 0; sb < MNS; ++sb) {
+                float a = xs[xb + aoff[sb]];
+                if (sb == MNS - 1 && ones_lane) a = 1.f;
+                cacc[sb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, cacc[sb], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int sb = 0; sb < MNS; ++sb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[sb][r] += (double)cacc[sb][r];
+    }
+    // reduce the four waves' accumulators in a fixed order (waves 2, 3 into 0, 1; then 1 into 0)
+    double *dred = reinterpret_cast<double *>(ys);  // [2][64][32]
+    __syncthreads();
+    if (wv >= 2) {
+#pragma unroll
+        for (int sb = 0; sb < MNS; ++sb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) dred[((wv - 2) * 64 + lane) * 32 + sb * 4 + r] = acc[sb][r];
+    }
+    __syncthreads();
+    if (wv < 2) {
+#pragma unroll
+        for (int sb = 0; sb < MNS; ++sb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[sb][r] += dred[(wv * 64 + lane) * 32 + sb * 4 + r];
+    }
+    __syncthreads();
+    if (wv == 1) {
+#pragma unroll
+        for (int sb = 0; sb < MNS; ++sb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) dred[lane * 32 + sb * 4 + r] = acc[sb][r];
+    }
+    __syncthreads();
+    const int64_t prow = (int64_t)(q - q0) * ny;
+    if (wv == 0) {
+        const int n = lane & 15;
+        if (j0 + n < ny) {
+            double *dst = part + ((prow + j0 + n) * nblk + blk) * DSTAT;
+#pragma unroll
+            for (int sb = 0; sb < MNS; ++sb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int m = 16 * sb + 4 * (lane >> 4) + r;
+                    if (m <= MONES) dst[m] = acc[sb][r] + dred[lane * 32 + sb * 4 + r];
+                }
+        }
+    }
+    // sum y^2 per fingerprint: the 16 staging threads of each fingerprint (a fixed shuffle tree)
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) syy += __shfl_xor(syy, o, 16);
+    if (sc == 0 && j0 + sn < ny) part[((prow + j0 + sn) * nblk + blk) * DSTAT + MONES + 1] = syy;
+    // sum xc, the same for every fingerprint
+    sx = wave_sum(sx);
+    if (lane == 0) sred[wv] = sx;
+    __syncthreads();
+    if (tid < MNJ && j0 + tid < ny) {
+        double t = 0.0;
+        for (int k = 0; k < NT / 64; ++k) t += sred[k];
+        part[((prow + j0 + tid) * nblk + blk) * DSTAT + MONES + 2] = t;
     }
 }
 
@@ -431,6 +602,29 @@ hipError_t launch_pce_direct(const float *X, const double *xmean, const float *Y
     PairSel sel{Y, mod, ny, p0};
     KernelTimer kt("pce_direct", (double)n * h * w * (mod ? 12.0 : 8.0), s);
     pce_direct<<<dim3((unsigned)pce_direct_blocks(h, w), (unsigned)n), NT, 0, s>>>(X, xmean, sel, h, w,
+                                                                                  tiles_x, ntiles, part);
+    return hipGetLastError();
+}
+
+int pce_mfma_tiles(int h, int w) { return ((h + MTY - 1) / MTY) * ((w + MTX - 1) / MTX); }
+
+int pce_mfma_blocks(int nq, int ny, int h, int w) {
+    const int64_t groups = (int64_t)nq * ((ny + MNJ - 1) / MNJ);
+    int64_t nb = (2048 + groups - 1) / groups;  // about eight workgroups per CU in all
+    const int tiles = pce_mfma_tiles(h, w);
+    if (nb > 64) nb = 64;
+    if (nb > tiles) nb = tiles;
+    return nb < 1 ? 1 : (int)nb;
+}
+
+hipError_t launch_pce_direct_mfma(const float *X, const double *xmean, const float *Y, const float *mod, int ny,
+                                  int q0, int nq, int h, int w, int nblk, double *part, hipStream_t s) {
+    const int tiles_x = (w + MTX - 1) / MTX;
+    const int ntiles = pce_mfma_tiles(h, w);
+    const int ng = (ny + MNJ - 1) / MNJ;
+    // algorithmic bytes: every query pixel once, every fingerprint (and modulation) pixel once per query
+    KernelTimer kt("pce_direct_mfma", (double)nq * h * w * (4.0 + ny * (mod ? 8.0 : 4.0)), s);
+    pce_direct_mfma<<<dim3((unsigned)nblk, (unsigned)nq, (unsigned)ng), NT, 0, s>>>(X, xmean, Y, mod, ny, q0, h, w,
                                                                                   tiles_x, ntiles, part);
     return hipGetLastError();
 }

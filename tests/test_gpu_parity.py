@@ -270,6 +270,56 @@ def test_pce_match(dev, h, w, mode, modulated):
         assert tuple(peak[1, 1]) == ((-5) % h, (-9) % w)
 
 
+@pytest.mark.parametrize("nx,ny,h,w,modulated", [
+    (3, 16, 36, 150, True), (2, 17, 40, 64, False), (1, 33, 24, 200, True), (4, 5, 72, 96, False)])
+def test_pce_fixed_many_fingerprints(dev, nx, ny, h, w, modulated):
+    """Fixed-peak PCE with three or more fingerprints per query (the direct sums
+    then run on the matrix cores in groups of 16, ragged tiles)."""
+    _log(f"pce many fingerprints nx={nx} ny={ny} {h}x{w} modulated={modulated}")
+    g = synth.rng(synth.CFG_TEST, 5700 + ny)
+    X = g.normal(0, 1, size=(nx, h, w)).astype(np.float32)
+    Y = g.normal(0, 1, size=(ny, h, w)).astype(np.float32)
+    for q in range(nx):
+        Y[(3 * q) % ny] = (0.4 * X[q] + g.normal(0, 1, size=(h, w))).astype(np.float32)
+    mod = g.uniform(50, 200, size=(nx, h, w)).astype(np.float32) if modulated else None
+    pce, ncc, _ = prnu.pce_match(up(X, dev), up(Y, dev), up(mod, dev) if modulated else None, peak_mode=0)
+    rp, rn, _, _ = _pce_ref(X.astype(np.float64), Y.astype(np.float64),
+                            mod.astype(np.float64) if modulated else None, 0)
+    pce, ncc = down(pce), down(ncc)
+    np.testing.assert_allclose(ncc, rn, rtol=0, atol=1e-5)
+    for q in range(nx):
+        for j in range(ny):
+            assert_pce(pce[q, j], rp[q, j], what=f"pce[{q},{j}]")
+        assert pce[q, (3 * q) % ny] > 60
+
+
+def test_pce_fixed_query_chunks(dev):
+    """Enough pairs that the direct sums run in several chunks of queries."""
+    _log("pce query chunks")
+    g = synth.rng(synth.CFG_TEST, 5800)
+    nx, ny, h, w = 300, 256, 16, 20
+    X = g.normal(0, 1, size=(nx, h, w)).astype(np.float32)
+    Y = g.normal(0, 1, size=(ny, h, w)).astype(np.float32)
+    pce, _, _ = prnu.pce_match(up(X, dev), up(Y, dev), None, peak_mode=0, want_ncc=False, want_peak=False)
+    pce = down(pce)
+    # oracle via the FFT of every pair (fixed peak at (0,0), 11x11 excluded)
+    Xc = X.astype(np.float64) - X.mean(axis=(1, 2), keepdims=True)
+    Yc = Y.astype(np.float64) - Y.mean(axis=(1, 2), keepdims=True)
+    FX, FY = np.fft.fft2(Xc), np.fft.fft2(Yc)
+    sel = [q for q in range(0, nx, 7)] + [nx - 1]
+    for q in sel:
+        C = np.real(np.fft.ifft2(FX[q][None] * np.conj(FY)))  # [ny][h][w]
+        c0 = C[:, 0, 0]
+        Ct = C.copy()
+        rows = [d % h for d in range(-5, 6)]
+        cols = [d % w for d in range(-5, 6)]
+        Ct[:, np.array(rows)[:, None], np.array(cols)[None, :]] = 0.0
+        E = (Ct ** 2).sum(axis=(1, 2)) / (h * w - 121)
+        ref = np.sign(c0) * c0 * c0 / E
+        for j in range(ny):
+            assert_pce(pce[q, j], ref[j], what=f"pce[{q},{j}]")
+
+
 def test_pce_fixed_peak_offsets_and_nbhd(dev):
     """Fixed-peak path with fields far from zero mean and a 7x7 neighbourhood."""
     g = synth.rng(synth.CFG_TEST, 5600)
