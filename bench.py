@@ -53,7 +53,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
-    ap.add_argument("--workload", choices=["video", "stills-precision", "batched", "diff"], default="video",
+    ap.add_argument("--workload", choices=["video", "stills-precision", "batched", "diff", "copy-calibration"],
+                    default="video",
                     help="video: the headline benchmark; stills-precision: the accumulator/storage "
                          "precision report on 4000x3000 BF16 stills; batched: 64 grayscale cameras of "
                          "uneven resolution, frame count and SDA depth in one graph launch, then a 64x64 "
@@ -105,6 +106,8 @@ def main():
         return batched_main(args)
     if args.workload == "diff":
         return diff_main(args)
+    if args.workload == "copy-calibration":
+        return copy_main(args)
 
     import numpy as np
     import torch
@@ -768,6 +771,30 @@ def diff_main(args):
                    "ascent_gaps": gaps, "kernels": kernels, "gpu_vs_fp64_oracle": err},
     }
     print(json.dumps(out), flush=True)
+
+
+
+def copy_main(args):
+    """Three plain device copies of 1 GiB (the reference kernel for the HBM
+    byte counters: each copy reads 1 GiB and writes 1 GiB)."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    n = 1 << 28  # 1 GiB of float32
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        t.append(e0.elapsed_time(e1))
+    gbs = [2.0 * n * 4 / (ms / 1e3) / 1e9 for ms in t]
+    print(json.dumps({"workload": "copy-calibration", "bytes_read": n * 4, "bytes_written": n * 4,
+                      "ms": t, "gbs": gbs}), flush=True)
 
 
 if __name__ == "__main__":
