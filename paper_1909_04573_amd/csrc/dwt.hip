@@ -70,6 +70,24 @@ __device__ __forceinline__ int opaque_tid() {
     return t;
 }
 
+// Workgroups are dispatched to the XCDs (each with its own L2) round robin in
+// the order of their linear index.  Renumbering them so that XCD x takes the
+// x-th contiguous range of virtual blocks keeps neighbouring tiles, which
+// read overlapping input halos, in the same L2.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_order(int lin, int total) {
+    const int q = total / NXCD, r = total - (total / NXCD) * NXCD;
+    const int x = lin % NXCD, slot = lin / NXCD;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + slot;
+}
+// (tile, plane) of this workgroup of a grid (tiles, planes) in that order.
+__device__ __forceinline__ void grid_tile(int &tile, int &plane) {
+    const int tiles = (int)gridDim.x;
+    const int v = xcd_order((int)(blockIdx.x + blockIdx.y * gridDim.x), (int)(gridDim.x * gridDim.y));
+    plane = v / tiles;
+    tile = v - plane * tiles;
+}
+
 // Periodic wrap into [0, n), then symmetric (edge-including) reflection of
 // the padded index into the stored [0, stored) range.
 __device__ __forceinline__ int map_index(int p, int n, int off, int stored) {
@@ -561,19 +579,25 @@ __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, floa
 template <int TAPS, int TT>
 __global__ __launch_bounds__(NT) void dwt_fwd_wiener(FwdArgs a, Filter f) {
     __shared__ __align__(16) float lds[FwdGeom<TAPS, TT>::LDS];
-    fwd_body<TAPS, TT>(a, blockIdx.x, blockIdx.y, lds, f);
+    int tile, plane;
+    grid_tile(tile, plane);
+    fwd_body<TAPS, TT>(a, tile, plane, lds, f);
 }
 
 template <int TAPS, int TT, int EPI>
 __global__ __launch_bounds__(NT) void dwt_inv(InvArgs a, Filter f) {
     __shared__ __align__(16) float lds[InvGeom<TAPS, TT>::LDS];
-    inv_body<TAPS, TT, EPI>(a, blockIdx.x, blockIdx.y, lds, f);
+    int tile, plane;
+    grid_tile(tile, plane);
+    inv_body<TAPS, TT, EPI>(a, tile, plane, lds, f);
 }
 
 template <int TAPS, int TT, int ACC>
 __global__ __launch_bounds__(NT) void dwt_inv_mle(MleArgs a, Filter f) {
     __shared__ __align__(16) float lds[InvGeom<TAPS, TT>::LDS];
-    mle_body<TAPS, TT, ACC>(a, blockIdx.x, blockIdx.y, lds, f);
+    int tile, c;
+    grid_tile(tile, c);
+    mle_body<TAPS, TT, ACC>(a, tile, c, lds, f);
 }
 
 // ---------------------------------------------------------------------------
