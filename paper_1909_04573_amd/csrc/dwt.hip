@@ -70,24 +70,6 @@ __device__ __forceinline__ int opaque_tid() {
     return t;
 }
 
-// Workgroups are dispatched to the XCDs (each with its own L2) round robin in
-// the order of their linear index.  Renumbering them so that XCD x takes the
-// x-th contiguous range of virtual blocks keeps neighbouring tiles, which
-// read overlapping input halos, in the same L2.
-constexpr int NXCD = 8;
-__device__ __forceinline__ int xcd_order(int lin, int total) {
-    const int q = total / NXCD, r = total - (total / NXCD) * NXCD;
-    const int x = lin % NXCD, slot = lin / NXCD;
-    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + slot;
-}
-// (tile, plane) of this workgroup of a grid (tiles, planes) in that order.
-__device__ __forceinline__ void grid_tile(int &tile, int &plane) {
-    const int tiles = (int)gridDim.x;
-    const int v = xcd_order((int)(blockIdx.x + blockIdx.y * gridDim.x), (int)(gridDim.x * gridDim.y));
-    plane = v / tiles;
-    tile = v - plane * tiles;
-}
-
 // Periodic wrap into [0, n), then symmetric (edge-including) reflection of
 // the padded index into the stored [0, stored) range.
 __device__ __forceinline__ int map_index(int p, int n, int off, int stored) {

@@ -36,9 +36,11 @@ __global__ __launch_bounds__(FNT) void fft_1d(float2 *__restrict__ data, int N, 
                                               int64_t vs, int64_t plane_stride, FftPlan plan,
                                               const float2 *__restrict__ tw, float sigma) {
     extern __shared__ float2 smem[];
+    int blk, pl;
+    grid_tile(blk, pl);  // neighbouring vector groups on one XCD: they share cache lines
     const int nvec = plan.nvec;
-    const int v0 = blockIdx.x * nvec;
-    float2 *base = data + (int64_t)blockIdx.y * plane_stride;
+    const int v0 = blk * nvec;
+    float2 *base = data + (int64_t)pl * plane_stride;
     const int tot = N * nvec;
     float2 *b0 = smem, *b1 = smem + tot, *twl = smem + 2 * tot;
     staged_copy<FNT, 4, float2>(threadIdx.x, N, [&](int e) { return tw[e]; }, [&](int e, float2 z) { twl[e] = z; });
@@ -125,10 +127,12 @@ __global__ __launch_bounds__(FNT) void fft_cols_power(const float2 *__restrict__
                                                       int ny, int p0, float *__restrict__ Pout,
                                                       double *__restrict__ part) {
     extern __shared__ float2 smem[];
+    int blk, pl;
+    grid_tile(blk, pl);  // neighbouring column groups on one XCD: they share cache lines
     const int nvec = plan.nvec;
-    const int c0 = blockIdx.x * nvec;
+    const int c0 = blk * nvec;
     const int64_t plane = (int64_t)h * Mc;
-    const float2 *sp = S + (int64_t)blockIdx.y * plane;
+    const float2 *sp = S + (int64_t)pl * plane;
     const int tot = h * nvec;
     float2 *b0 = smem, *b1 = smem + tot, *twl = smem + 2 * tot;
     staged_copy<FNT, 4, float2>(threadIdx.x, h, [&](int e) { return tw[e]; }, [&](int e, float2 z) { twl[e] = z; });
@@ -141,7 +145,7 @@ __global__ __launch_bounds__(FNT) void fft_cols_power(const float2 *__restrict__
         [&](int e, float2 z) { b0[e] = z; });
     __syncthreads();
     const float2 *res = fft_lds(b0, b1, plan, twl, -1.f);
-    const int pid = p0 + (int)blockIdx.y;
+    const int pid = p0 + pl;
     double acc = 0.0;
     const float *pq = DOT ? Px + (int64_t)(pid / ny) * plane : nullptr;
     constexpr int KB = 8;  // the power weights of KB elements are loaded before they are used
@@ -168,7 +172,7 @@ __global__ __launch_bounds__(FNT) void fft_cols_power(const float2 *__restrict__
                 const float wgt = (col == 0 || col == Mc - 1) ? 1.f : 2.f;
                 acc += (double)(wgt * pw) * (double)px[k];
             } else {
-                Pout[(int64_t)blockIdx.y * plane + (int64_t)n * Mc + col] = pw;
+                Pout[(int64_t)pl * plane + (int64_t)n * Mc + col] = pw;
             }
         }
     }
@@ -176,7 +180,7 @@ __global__ __launch_bounds__(FNT) void fft_cols_power(const float2 *__restrict__
         // the buffer not holding the result is free for the reduction
         double *red = reinterpret_cast<double *>(res == b0 ? b1 : b0);
         acc = block_sum_f64(acc, red);
-        if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = acc;
+        if (threadIdx.x == 0) part[(int64_t)pl * gridDim.x + blk] = acc;
     }
 }
 

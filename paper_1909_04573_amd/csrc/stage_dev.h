@@ -36,6 +36,24 @@ __device__ __forceinline__ void st4(PRNU_GLOBAL T *p, T a, T b, T c, T d) {
     *(PRNU_GLOBAL v4 *)p = v4{a, b, c, d};
 }
 
+// Workgroups are dispatched to the XCDs (each with its own L2) round robin in
+// the order of their linear index.  Renumbering them so that XCD x takes the
+// x-th contiguous range of virtual blocks keeps neighbouring tiles, which
+// read overlapping input halos, in the same L2.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_order(int lin, int total) {
+    const int q = total / NXCD, r = total - (total / NXCD) * NXCD;
+    const int x = lin % NXCD, slot = lin / NXCD;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + slot;
+}
+// (tile, plane) of this workgroup of a grid (tiles, planes) in that order.
+__device__ __forceinline__ void grid_tile(int &tile, int &plane) {
+    const int tiles = (int)gridDim.x;
+    const int v = xcd_order((int)(blockIdx.x + blockIdx.y * gridDim.x), (int)(gridDim.x * gridDim.y));
+    plane = v / tiles;
+    tile = v - plane * tiles;
+}
+
 template <int NTH, int KB, typename T, typename Load, typename Store>
 __device__ __forceinline__ void staged_copy(int tid, int count, Load load, Store store) {
     for (int e0 = tid; e0 < count; e0 += KB * NTH) {
