@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--depths", type=str, default="1,10,20,50")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--curve-step", type=int, default=25,
+                    help="video: frame-count grid of the conventional accuracy curve (0: skip it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
     ap.add_argument("--workload", choices=["video", "stills-precision", "batched", "diff", "copy-calibration"],
@@ -222,6 +224,49 @@ def main():
             "unmatched_abs_pce_max": float(np.abs(pce[mask]).max()) if mask.any() else None,
         }
 
+    # ---------------------------------------------------------------- equal-accuracy speedup
+    # Conventional fingerprints (d = 1) from the first n frames, n on a grid;
+    # the frame count at which their mean matched PCE reaches SDA-d's at all
+    # frames prices SDA at equal accuracy: t_conv(n) / t_SDA(all frames),
+    # with t_conv(n) = n times the measured per-frame cost at d = 1 (every
+    # frame is denoised, so the cost is linear in n).  Untimed.
+    equal_pce = None
+    if 1 in depths and args.curve_step > 0:
+        log("equal-accuracy curve: conventional fingerprints from the first n frames")
+        ns = list(range(args.curve_step, nfp + 1, args.curve_step))
+        if not ns or ns[-1] != nfp:
+            ns.append(nfp)
+        Kc = torch.empty((len(ns) * ncam, H, W), dtype=torch.float32, device=dev)
+        for c in range(ncam):
+            A.zero_()
+            B.zero_()
+            prev = 0
+            for k, nn in enumerate(ns):
+                prnu.fingerprint_accumulate(frames[c, prev:nn], 1, A, B, p, ws=ws)
+                prnu.fingerprint_finalize(A, B, out=Kc[k * ncam + c])
+                prev = nn
+        Wq, Iq = prnu.query_residual(queries, p)
+        pc, _, _ = prnu.pce_match(Wq, Kc, modulate=Iq, want_ncc=False, want_peak=False)
+        pc = pc.cpu().numpy()
+        cam_of_q = np.repeat(np.arange(ncam), nq)
+        rows = np.arange(len(cam_of_q))
+        curve = [float(pc[rows, k * ncam + cam_of_q].mean()) for k in range(len(ns))]
+        t_frame = stage_ms(("fp", 1)) / nfp  # ms per frame, all cameras, d = 1
+        for d in depths:
+            if d == 1:
+                continue
+            target = per_depth[str(d)]["matched_pce_mean"]
+            n_eq = None
+            for k, v in enumerate(curve):
+                if v >= target:
+                    n0, v0 = (ns[k - 1], curve[k - 1]) if k > 0 else (0, 0.0)
+                    n_eq = n0 + (ns[k] - n0) * (target - v0) / (v - v0) if v > v0 else float(ns[k])
+                    break
+            per_depth[str(d)]["equal_pce_conventional_frames"] = None if n_eq is None else round(n_eq, 1)
+            per_depth[str(d)]["speedup_equal_pce"] = (
+                None if n_eq is None else n_eq * t_frame / stage_ms(("fp", d)))
+        equal_pce = {"frames": ns, "conventional_matched_pce_mean": curve}
+
     # ---------------------------------------------------------------- roofline
     dom = max(timing.items(), key=lambda kv: kv[1][1])
     name, (launches, kms, kbytes) = dom
@@ -254,7 +299,7 @@ def main():
     cpu = None
     err = None
     if not args.no_cpu_baseline:
-        cpu, err = cpu_baseline(frames, queries, ncam, nq, H, W, C, dev, p)
+        cpu, err = cpu_baseline(frames, queries, ncam, nq, nfp, depths, H, W, C, dev, p)
 
     out = {
         "metric": METRIC,
@@ -287,6 +332,7 @@ def main():
             "pce_ms": stage_ms("pce"),
             "pce_pairs_per_s": ncam * nq * ncam * len(depths) / (stage_ms("pce") / 1e3),
             "per_depth": per_depth,
+            "equal_pce_curve": equal_pce,
             "kernels": kernels,
             "tiles": tiles,
             "gpu_vs_fp64_oracle": err,
@@ -297,49 +343,110 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(frames, queries, ncam, nq, H, W, C, dev, p):
-    """Oracle on a bounded sample: camera 0's first 100 frames at SDA depth
-    50 (2 SDA frames, 6 plane denoises), finalisation, two query residuals
-    (one matched, one from camera 1) and their two PCEs.  The GPU path runs the
-    same sample through the C ABI; its errors against the oracle are returned."""
+def _oracle_plane(args):
+    """Worker of the oracle's process-pool run: residual and MLE terms of one
+    plane (float64), as the oracle computes them for an SDA frame."""
+    from oracle import pipeline
+
+    I, kind = args
+    Wr = pipeline.denoise_residual(I)
+    return float((Wr * I).sum()) if kind == "sda" else float(Wr.sum())
+
+
+def cpu_baseline(frames, queries, ncam, nq, nfp, depths, H, W, C, dev, p):
+    """Oracle on a bounded sample: camera 0's first 200 frames at SDA depth
+    25 (8 SDA frames, 24 plane denoises), finalisation, four query residuals
+    (two matched, two from camera 1) and their PCEs, in one process.  The
+    stage times give the paper's linear cost model t(m, d) = m*t_avg +
+    ceil(m/d)*t_den (per camera, C planes per SDA frame), which extrapolates
+    the oracle's time for one full step of this workload.  The same plane
+    denoises are then timed in a process pool over the host's cores.  The GPU
+    path runs the sample through the C ABI; its errors against the oracle are
+    returned."""
+    import concurrent.futures
+    import multiprocessing
+
     import numpy as np
     import torch
 
-    from oracle import correlate, pipeline
+    from oracle import correlate, pipeline, sda
     from paper_1909_04573_amd import prnu
 
-    n, d = min(100, frames.shape[1]), 50
+    n, d = min(200, frames.shape[1]), 25
     fr = frames[0, :n].cpu().numpy()
-    qi = [0, nq] if ncam > 1 else [0]
+    qi = [0, 1, nq, nq + 1] if ncam > 1 else [0, 1]
     qs = queries[qi].cpu().numpy()
     log("cpu baseline: running the oracle on the sample")
     t0 = time.perf_counter()
-    Kr = pipeline.camera_fingerprint(fr, d)
+    means = sda.sda_means(fr, d)  # [g][C][H][W]
+    t1 = time.perf_counter()
+    g = means.shape[0]
+    A = np.zeros((C, H, W))
+    B = np.zeros((C, H, W))
+    for i in range(g):
+        for c in range(C):
+            I = means[i, c]
+            Wr = pipeline.denoise_residual(I)
+            A[c] += Wr * I
+            B[c] += I * I
+    t2 = time.perf_counter()
+    Kr = pipeline.finalize(A, B)
+    t3 = time.perf_counter()
     ref = []
     for q in qs:
         Wr, Ir = pipeline.query_residual(q)
         ref.append(correlate.pce(Wr, Ir * Kr)["pce"])
-    t_cpu = time.perf_counter() - t0
-    planes = (math.ceil(n / d) + len(qs)) * C
+    t4 = time.perf_counter()
+    t_cpu = t4 - t0
+    planes = (g + len(qs)) * C
     value = planes * H * W / t_cpu / 1e6
-    log(f"cpu baseline: {t_cpu:.1f} s")
+    t_avg = (t1 - t0) / n  # per input frame (all channels)
+    t_den = (t2 - t1) / (g * C)  # per plane: residual + MLE terms
+    t_fin = t3 - t2
+    t_q = (t4 - t3) / len(qs)  # residual of C planes, post-processing, one PCE
+    step = sum(ncam * (nfp * t_avg + math.ceil(nfp / dd) * C * t_den + t_fin) for dd in depths)
+    step += ncam * nq * t_q
+    log(f"cpu baseline: {t_cpu:.1f} s in one process")
+
+    # the same plane work in a process pool (fresh interpreters: the parent holds the GPU)
+    workers = max(1, min(16, os.cpu_count() or 1))
+    jobs = [(means[i, c], "sda") for i in range(g) for c in range(C)]
+    jobs += [(np.ascontiguousarray(q[:, :, c], dtype=np.float64), "query") for q in qs for c in range(C)]
+    ctx = multiprocessing.get_context("spawn")
+    with concurrent.futures.ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as pool:
+        list(pool.map(_oracle_plane, jobs[:workers]))  # start-up and imports, untimed
+        tp = time.perf_counter()
+        list(pool.map(_oracle_plane, jobs))
+        t_pool = time.perf_counter() - tp
+    log(f"cpu baseline: {len(jobs)} plane denoises in {t_pool:.1f} s on {workers} processes")
+
     # the same sample on the GPU
-    A, B = prnu.new_accumulators(C, H, W, device=dev)
-    prnu.fingerprint_accumulate(frames[0, :n], d, A, B, p)
-    K = prnu.fingerprint_finalize(A, B)
+    Ag, Bg = prnu.new_accumulators(C, H, W, device=dev)
+    prnu.fingerprint_accumulate(frames[0, :n], d, Ag, Bg, p)
+    K = prnu.fingerprint_finalize(Ag, Bg)
     Wq, Iq = prnu.query_residual(queries[qi].contiguous(), p)
     pce, _, _ = prnu.pce_match(Wq, K.unsqueeze(0), modulate=Iq)
     torch.cuda.synchronize()
     Kg = K.cpu().numpy()
-    g = pce.cpu().numpy()[:, 0]
+    gp = pce.cpu().numpy()[:, 0]
     k_rel = float(np.linalg.norm(Kg - Kr) / np.linalg.norm(Kr))
     k_max = float(np.abs(Kg - Kr).max() / np.abs(Kr).max())
-    pce_rel = [float(abs(a - b) / max(abs(b), 1.0)) for a, b in zip(g, ref)]
+    pce_rel = [float(abs(a - b) / max(abs(b), 1.0)) for a, b in zip(gp, ref)]
     cpu = {"value": round(value, 3), "unit": "Mpix/s", "cores": 1, "kind": "oracle",
-           "sample": f"camera 0, {n} frames of {W}x{H}x{C} at SDA depth {d} ({math.ceil(n / d)} SDA frames) "
+           "sample": f"camera 0, {n} frames of {W}x{H}x{C} at SDA depth {d} ({g} SDA frames) "
                      f"+ {len(qs)} query residuals + {len(qs)} PCEs, FP64 NumPy, {t_cpu:.1f} s",
-           "host": host_cpu_model(), "host_cpu_count": os.cpu_count()}
-    err = {"fingerprint_rel_l2": k_rel, "fingerprint_max_rel": k_max, "pce_gpu": [float(x) for x in g],
+           "host": host_cpu_model(), "host_cpu_count": os.cpu_count(),
+           "linear_model": {"t_avg_ms_per_frame": round(t_avg * 1e3, 3),
+                            "t_den_ms_per_plane": round(t_den * 1e3, 1),
+                            "t_finalize_ms": round(t_fin * 1e3, 1),
+                            "t_query_ms": round(t_q * 1e3, 1),
+                            "extrapolated_step_s": round(step, 1),
+                            "note": "oracle time of one full step from m*t_avg + ceil(m/d)*C*t_den + "
+                                    "t_finalize per camera and depth, plus t_query per query"},
+           "pool": {"cores": workers, "planes": len(jobs), "seconds": round(t_pool, 2),
+                    "value": round(len(jobs) * H * W / t_pool / 1e6, 3), "unit": "Mpix/s",
+                    "note": "plane denoises of the sample spread over a process pool"}}
+    err = {"fingerprint_rel_l2": k_rel, "fingerprint_max_rel": k_max, "pce_gpu": [float(x) for x in gp],
            "pce_oracle": [float(x) for x in ref], "pce_rel_err": pce_rel}
     return cpu, err
 

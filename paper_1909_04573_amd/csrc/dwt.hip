@@ -38,6 +38,10 @@ namespace {
 
 constexpr int HALO = 4;  // half of the largest Wiener window (9)
 constexpr int NT = 256;  // threads per workgroup
+// Forward-level workgroups with 32 x 32 tiles are LDS-limited to two per CU;
+// twice the threads give the CU more waves to hide load and LDS latency.
+constexpr int FWD_NT32 = 512;
+constexpr int fwd_nt(int tt) { return tt == 32 ? FWD_NT32 : NT; }
 
 template <int TAPS, int TT>
 struct FwdGeom {
@@ -86,6 +90,7 @@ __device__ __forceinline__ int map_index(int p, int n, int off, int stored) {
 template <int TAPS, int TT>
 __device__ __forceinline__ void fwd_body(const FwdArgs &a, int tile, int plane, float *lds, const Filter &f) {
     using G = FwdGeom<TAPS, TT>;
+    constexpr int NTH = fwd_nt(TT);
     constexpr int IN = G::IN, INS = G::INS, NC = G::NC;
     float *tbuf = lds;           // input samples; later squares + core coefficients
     float *rlo = lds + G::TILE;  // row low-pass
@@ -116,11 +121,11 @@ __device__ __forceinline__ void fwd_body(const FwdArgs &a, int tile, int plane, 
                        (a.src_stride & 1) == 0;
     if (cfast) {
         constexpr int IN2 = IN / 2;
-        constexpr int E = IN * IN2, K = (E + NT - 1) / NT;
+        constexpr int E = IN * IN2, K = (E + NTH - 1) / NTH;
         float2 v[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const int e = tid + k * NT;
+            const int e = tid + k * NTH;
             if (e < E) {
                 const int i = e / IN2, j2 = e - (e / IN2) * IN2;
                 v[k] = ld2(sp + (int64_t)rmap[i] * a.src_cols + c_src0 + 2 * j2);
@@ -128,18 +133,18 @@ __device__ __forceinline__ void fwd_body(const FwdArgs &a, int tile, int plane, 
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const int e = tid + k * NT;
+            const int e = tid + k * NTH;
             if (e < E) {
                 const int i = e / IN2, j2 = e - (e / IN2) * IN2;
                 *reinterpret_cast<float2 *>(&tbuf[i * INS + 2 * j2]) = v[k];
             }
         }
     } else {
-        constexpr int E = IN * IN, K = (E + NT - 1) / NT;
+        constexpr int E = IN * IN, K = (E + NTH - 1) / NTH;
         float v[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const int e = tid + k * NT;
+            const int e = tid + k * NTH;
             if (e < E) {
                 const int i = e / IN, j = e - (e / IN) * IN;
                 v[k] = sp[(int64_t)rmap[i] * a.src_cols + cmap[j]];
@@ -147,7 +152,7 @@ __device__ __forceinline__ void fwd_body(const FwdArgs &a, int tile, int plane, 
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const int e = tid + k * NT;
+            const int e = tid + k * NTH;
             if (e < E) {
                 const int i = e / IN, j = e - (e / IN) * IN;
                 tbuf[i * INS + j] = v[k];
@@ -159,7 +164,7 @@ __device__ __forceinline__ void fwd_body(const FwdArgs &a, int tile, int plane, 
     // Rows: lo/hi along axis 1, four coefficients per item, 16-byte LDS traffic.
     constexpr int NQ = NC / 4;
     constexpr int NX = TAPS + 8;  // TAPS + 6 samples, rounded up to whole float4s
-    for (int it = tid; it < IN * NQ; it += NT) {
+    for (int it = tid; it < IN * NQ; it += NTH) {
         const int i = it / NQ, kq = it - (it / NQ) * NQ;
         const float4 *row = reinterpret_cast<const float4 *>(&tbuf[i * INS + 8 * kq]);
         float x[NX];
@@ -193,7 +198,7 @@ __device__ __forceinline__ void fwd_body(const FwdArgs &a, int tile, int plane, 
     float *qb = tbuf;                // [3][NC][NC]
     float *cb = tbuf + 3 * NC * NC;  // [3][TT][TT]
     const int gr0 = k0r - HALO, gc0 = k0c - HALO;
-    for (int it = tid; it < NQ * (NC / 2); it += NT) {
+    for (int it = tid; it < NQ * (NC / 2); it += NTH) {
         const int cq = it % NQ, kp = it / NQ;
         bool cv[4];
 #pragma unroll
@@ -559,7 +564,7 @@ __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, floa
 // ---------------------------------------------------------------------------
 // Per-plane kernels.
 template <int TAPS, int TT>
-__global__ __launch_bounds__(NT) void dwt_fwd_wiener(FwdArgs a, Filter f) {
+__global__ __launch_bounds__(fwd_nt(TT)) void dwt_fwd_wiener(FwdArgs a, Filter f) {
     __shared__ __align__(16) float lds[FwdGeom<TAPS, TT>::LDS];
     int tile, plane;
     grid_tile(tile, plane);
@@ -611,7 +616,7 @@ __device__ __forceinline__ int next_block(int *ctr, int *slot) {
 }
 
 template <int TAPS, int TT>
-__global__ __launch_bounds__(NT) void dwt_fwd_multi(const FwdDesc *__restrict__ d, int nd, int total, int *ctr,
+__global__ __launch_bounds__(fwd_nt(TT)) void dwt_fwd_multi(const FwdDesc *__restrict__ d, int nd, int total, int *ctr,
                                                     Filter f) {
     __shared__ __align__(16) float lds[FwdGeom<TAPS, TT>::LDS];
     __shared__ int slot;
@@ -674,9 +679,9 @@ std::mutex g_tile_mu;
 std::map<std::tuple<int, int, int, int>, int> g_tile;
 
 template <typename K>
-int occupancy_of(K kernel) {
+int occupancy_of(K kernel, int threads = NT) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, NT, 0) != hipSuccess || n < 1) n = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, threads, 0) != hipSuccess || n < 1) n = 1;
     return n;
 }
 
@@ -705,11 +710,11 @@ hipError_t launch_dwt_fwd(int taps, const Filter &f, const float *src, int64_t s
                          ((double)src_rows * src_cols + (write_ll ? 4.0 : 3.0) * (double)hk * wk);
     KernelTimer kt(taps == 16 ? "dwt_fwd_wiener<16>" : "dwt_fwd_wiener<8>", bytes, s);
     if (taps == 16) {
-        if (tt == 16) dwt_fwd_wiener<16, 16><<<grid, NT, 0, s>>>(a, f);
-        else dwt_fwd_wiener<16, 32><<<grid, NT, 0, s>>>(a, f);
+        if (tt == 16) dwt_fwd_wiener<16, 16><<<grid, fwd_nt(16), 0, s>>>(a, f);
+        else dwt_fwd_wiener<16, 32><<<grid, fwd_nt(32), 0, s>>>(a, f);
     } else {
-        if (tt == 16) dwt_fwd_wiener<8, 16><<<grid, NT, 0, s>>>(a, f);
-        else dwt_fwd_wiener<8, 32><<<grid, NT, 0, s>>>(a, f);
+        if (tt == 16) dwt_fwd_wiener<8, 16><<<grid, fwd_nt(16), 0, s>>>(a, f);
+        else dwt_fwd_wiener<8, 32><<<grid, fwd_nt(32), 0, s>>>(a, f);
     }
     return hipGetLastError();
 }
@@ -768,11 +773,11 @@ hipError_t launch_fwd_multi(int taps, int tt, const Filter &f, const FwdDesc *d,
                             int grid, hipStream_t s) {
     if (total <= 0 || nd <= 0) return hipSuccess;
     if (taps == 16) {
-        if (tt == 16) dwt_fwd_multi<16, 16><<<grid, NT, 0, s>>>(d, nd, total, ctr, f);
-        else dwt_fwd_multi<16, 32><<<grid, NT, 0, s>>>(d, nd, total, ctr, f);
+        if (tt == 16) dwt_fwd_multi<16, 16><<<grid, fwd_nt(16), 0, s>>>(d, nd, total, ctr, f);
+        else dwt_fwd_multi<16, 32><<<grid, fwd_nt(32), 0, s>>>(d, nd, total, ctr, f);
     } else {
-        if (tt == 16) dwt_fwd_multi<8, 16><<<grid, NT, 0, s>>>(d, nd, total, ctr, f);
-        else dwt_fwd_multi<8, 32><<<grid, NT, 0, s>>>(d, nd, total, ctr, f);
+        if (tt == 16) dwt_fwd_multi<8, 16><<<grid, fwd_nt(16), 0, s>>>(d, nd, total, ctr, f);
+        else dwt_fwd_multi<8, 32><<<grid, fwd_nt(32), 0, s>>>(d, nd, total, ctr, f);
     }
     return hipGetLastError();
 }
@@ -824,8 +829,10 @@ hipError_t launch_fill_pattern(float *x, int64_t n, hipStream_t s) {
 }
 
 int fwd_multi_occupancy(int taps, int tt) {
-    if (taps == 16) return tt == 16 ? occupancy_of(dwt_fwd_multi<16, 16>) : occupancy_of(dwt_fwd_multi<16, 32>);
-    return tt == 16 ? occupancy_of(dwt_fwd_multi<8, 16>) : occupancy_of(dwt_fwd_multi<8, 32>);
+    if (taps == 16)
+        return tt == 16 ? occupancy_of(dwt_fwd_multi<16, 16>, fwd_nt(16))
+                        : occupancy_of(dwt_fwd_multi<16, 32>, fwd_nt(32));
+    return tt == 16 ? occupancy_of(dwt_fwd_multi<8, 16>, fwd_nt(16)) : occupancy_of(dwt_fwd_multi<8, 32>, fwd_nt(32));
 }
 int inv_multi_occupancy(int taps, int tt) {
     if (taps == 16) return tt == 16 ? occupancy_of(dwt_inv_multi<16, 16>) : occupancy_of(dwt_inv_multi<16, 32>);
