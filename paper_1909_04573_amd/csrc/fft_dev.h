@@ -7,7 +7,7 @@
 
 namespace prnu {
 
-constexpr int FNT = 256;    // threads per FFT workgroup
+constexpr int FNT = 512;    // threads per FFT workgroup (LDS allows two or three per CU; 8 waves each hide LDS latency)
 constexpr int FCAP = 5120;  // longest transform
 constexpr int FVEC = 2560;  // vectors per workgroup: as many as keep nvec * N within this
 
