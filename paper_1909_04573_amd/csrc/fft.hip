@@ -32,13 +32,17 @@ namespace {
 
 // One batch of 1-D transforms: vectors v0 .. v0+nvec-1 of `count`, element n
 // of vector v at base[v * vs + n * es].
-__global__ __launch_bounds__(FNT) void fft_1d(float2 *__restrict__ data, int N, int count, int64_t es,
+// FN, FV: length and vectors per workgroup fixed at compile time (FN = 0: the
+// runtime plan).
+template <int FN, int FV>
+__global__ __launch_bounds__(FNT) void fft_1d(float2 *__restrict__ data, int Nrt, int count, int64_t es,
                                               int64_t vs, int64_t plane_stride, FftPlan plan,
                                               const float2 *__restrict__ tw, float sigma) {
     extern __shared__ float2 smem[];
     int blk, pl;
     grid_tile(blk, pl);  // neighbouring vector groups on one XCD: they share cache lines
-    const int nvec = plan.nvec;
+    const int N = FN ? FN : Nrt;
+    const int nvec = FN ? FV : plan.nvec, lvec = FN ? ilog2c(FV) : plan.lvec;
     const int v0 = blk * nvec;
     float2 *base = data + (int64_t)pl * plane_stride;
     const int tot = N * nvec;
@@ -47,14 +51,14 @@ __global__ __launch_bounds__(FNT) void fft_1d(float2 *__restrict__ data, int N, 
     staged_copy<FNT, 8, float2>(
         threadIdx.x, tot,
         [&](int e) {
-            const int v = e & (nvec - 1), n = e >> plan.lvec;
+            const int v = e & (nvec - 1), n = e >> lvec;
             return (v0 + v < count) ? base[(int64_t)(v0 + v) * vs + (int64_t)n * es] : make_float2(0.f, 0.f);
         },
         [&](int e, float2 z) { b0[e] = z; });
     __syncthreads();
-    const float2 *res = fft_lds(b0, b1, plan, twl, sigma);
+    const float2 *res = fft_run<FN, FV>(b0, b1, plan, twl, sigma);
     for (int e = threadIdx.x; e < tot; e += FNT) {
-        const int v = e & (nvec - 1), n = e >> plan.lvec;
+        const int v = e & (nvec - 1), n = e >> lvec;
         if (v0 + v < count) base[(int64_t)(v0 + v) * vs + (int64_t)n * es] = res[e];
     }
 }
@@ -62,13 +66,15 @@ __global__ __launch_bounds__(FNT) void fft_1d(float2 *__restrict__ data, int N, 
 // Real rows -> half spectra.  Plane p of the batch is y = Y[(p0+p) % ny]
 // (times mod[(p0+p) / ny] if given, minus `mean[p]` if given).  Row r, bins
 // k = 0 .. w/2 at out[p][r][k] (row stride w/2 + 1).
+template <int FN, int FV>
 __global__ __launch_bounds__(FNT) void rfft_rows(const float *__restrict__ Y, const float *__restrict__ mod,
                                                  int ny, int p0, const double *__restrict__ mean, int h,
-                                                 int w, FftPlan plan, const float2 *__restrict__ tw_half,
+                                                 int wrt, FftPlan plan, const float2 *__restrict__ tw_half,
                                                  const float2 *__restrict__ tw_full, float2 *__restrict__ out) {
     extern __shared__ float2 smem[];
+    const int w = FN ? 2 * FN : wrt;
     const int M = w / 2;
-    const int nvec = plan.nvec;
+    const int nvec = FN ? FV : plan.nvec, lvec = FN ? ilog2c(FV) : plan.lvec;
     const int r0 = blockIdx.x * nvec;
     const int pid = p0 + (int)blockIdx.y;
     const int64_t N = (int64_t)h * w;
@@ -84,7 +90,7 @@ __global__ __launch_bounds__(FNT) void rfft_rows(const float *__restrict__ Y, co
     staged_copy<FNT, 8, float2>(
         threadIdx.x, tot,
         [&](int e) {
-            const int v = e & (nvec - 1), n = e >> plan.lvec;
+            const int v = e & (nvec - 1), n = e >> lvec;
             float2 z = make_float2(0.f, 0.f);
             if (r0 + v < h) {
                 const int64_t o = (int64_t)(r0 + v) * w + 2 * n;
@@ -99,7 +105,7 @@ __global__ __launch_bounds__(FNT) void rfft_rows(const float *__restrict__ Y, co
         },
         [&](int e, float2 z) { b0[e] = z; });
     __syncthreads();
-    const float2 *res = fft_lds(b0, b1, plan, twh, -1.f);
+    const float2 *res = fft_run<FN, FV>(b0, b1, plan, twh, -1.f);
     // Split the even/odd-sample spectra: Y[k] = E[k] + W_w^k O[k].
     float2 *op = out + (int64_t)blockIdx.y * h * (M + 1);
     const int tot2 = (M + 1) * nvec;
@@ -121,15 +127,16 @@ __global__ __launch_bounds__(FNT) void rfft_rows(const float *__restrict__ Y, co
 //   POWER_DOT:   part[p][blockIdx.x] = sum_k wgt(k) Px[q][k] |S_k|^2 over the
 //                strip (wgt = 1 on the first and the Nyquist column, 2 between;
 //                DC bin excluded), q = (p0 + p) / ny.
-template <bool DOT>
-__global__ __launch_bounds__(FNT) void fft_cols_power(const float2 *__restrict__ S, int h, int Mc, FftPlan plan,
+template <bool DOT, int FN, int FV>
+__global__ __launch_bounds__(FNT) void fft_cols_power(const float2 *__restrict__ S, int hrt, int Mc, FftPlan plan,
                                                       const float2 *__restrict__ tw, const float *__restrict__ Px,
                                                       int ny, int p0, float *__restrict__ Pout,
                                                       double *__restrict__ part) {
     extern __shared__ float2 smem[];
     int blk, pl;
     grid_tile(blk, pl);  // neighbouring column groups on one XCD: they share cache lines
-    const int nvec = plan.nvec;
+    const int h = FN ? FN : hrt;
+    const int nvec = FN ? FV : plan.nvec, lvec = FN ? ilog2c(FV) : plan.lvec;
     const int c0 = blk * nvec;
     const int64_t plane = (int64_t)h * Mc;
     const float2 *sp = S + (int64_t)pl * plane;
@@ -139,12 +146,12 @@ __global__ __launch_bounds__(FNT) void fft_cols_power(const float2 *__restrict__
     staged_copy<FNT, 8, float2>(
         threadIdx.x, tot,
         [&](int e) {
-            const int v = e & (nvec - 1), n = e >> plan.lvec;
+            const int v = e & (nvec - 1), n = e >> lvec;
             return (c0 + v < Mc) ? sp[(int64_t)n * Mc + c0 + v] : make_float2(0.f, 0.f);
         },
         [&](int e, float2 z) { b0[e] = z; });
     __syncthreads();
-    const float2 *res = fft_lds(b0, b1, plan, twl, -1.f);
+    const float2 *res = fft_run<FN, FV>(b0, b1, plan, twl, -1.f);
     const int pid = p0 + pl;
     double acc = 0.0;
     const float *pq = DOT ? Px + (int64_t)(pid / ny) * plane : nullptr;
@@ -155,14 +162,14 @@ __global__ __launch_bounds__(FNT) void fft_cols_power(const float2 *__restrict__
 #pragma unroll
             for (int k = 0; k < KB; ++k) {
                 const int e = e0 + k * FNT;
-                const int v = e & (nvec - 1), n = e >> plan.lvec;
+                const int v = e & (nvec - 1), n = e >> lvec;
                 px[k] = (e < tot && c0 + v < Mc) ? pq[(int64_t)n * Mc + c0 + v] : 0.f;
             }
         }
 #pragma unroll
         for (int k = 0; k < KB; ++k) {
             const int e = e0 + k * FNT;
-            const int v = e & (nvec - 1), n = e >> plan.lvec;
+            const int v = e & (nvec - 1), n = e >> lvec;
             const int col = c0 + v;
             if (e >= tot || col >= Mc) continue;
             const float2 z = res[e];
@@ -232,6 +239,39 @@ hipError_t allow_lds(K kernel, unsigned bytes) {
                                (int)bytes);
 }
 
+// Lengths with compile-time transforms, each with the vector count its plan
+// gets: full rows, half rows and columns of 1920x1080, 1280x720, 3840x2160
+// and 512x512 planes.  Every other length runs the runtime plan.
+using Fft1dKernel = decltype(&fft_1d<0, 0>);
+using RowsKernel = decltype(&rfft_rows<0, 0>);
+using ColsKernel = decltype(&fft_cols_power<true, 0, 0>);
+
+static Fft1dKernel pick_fft_1d(const FftPlan &p) {
+#define PRNU_CASE(N, V) \
+    if (p.n == N && p.nvec == V) return fft_1d<N, V>;
+    PRNU_CASE(1920, 1) PRNU_CASE(1080, 4) PRNU_CASE(1280, 2) PRNU_CASE(720, 4) PRNU_CASE(3840, 1)
+    PRNU_CASE(2160, 2) PRNU_CASE(512, 4) PRNU_CASE(512, 8)
+#undef PRNU_CASE
+    return fft_1d<0, 0>;
+}
+
+static RowsKernel pick_rfft_rows(const FftPlan &p) {
+#define PRNU_CASE(N, V) \
+    if (p.n == N && p.nvec == V) return rfft_rows<N, V>;
+    PRNU_CASE(960, 2) PRNU_CASE(640, 4) PRNU_CASE(1920, 1) PRNU_CASE(256, 8)
+#undef PRNU_CASE
+    return rfft_rows<0, 0>;
+}
+
+template <bool DOT>
+static ColsKernel pick_fft_cols(const FftPlan &p) {
+#define PRNU_CASE(N, V) \
+    if (p.n == N && p.nvec == V) return fft_cols_power<DOT, N, V>;
+    PRNU_CASE(1080, 4) PRNU_CASE(720, 4) PRNU_CASE(2160, 2) PRNU_CASE(512, 8)
+#undef PRNU_CASE
+    return fft_cols_power<DOT, 0, 0>;
+}
+
 hipError_t launch_twiddles(int n, float2 *tw, hipStream_t s) {
     twiddle_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, tw);
     return hipGetLastError();
@@ -247,9 +287,10 @@ hipError_t launch_fft2(float2 *data, int batch, int h, int w, const FftPlan &ph,
     {
         KernelTimer kt("fft_1d", bytes, s);
         const unsigned lds = fft_lds_bytes(pw, pw.n);
-        hipError_t e = allow_lds(fft_1d, lds);
+        const Fft1dKernel k = pick_fft_1d(pw);
+        hipError_t e = allow_lds(k, lds);
         if (e != hipSuccess) return e;
-        fft_1d<<<gr, FNT, lds, s>>>(data, w, h, 1, w, plane, pw, tw_w, sigma);
+        k<<<gr, FNT, lds, s>>>(data, w, h, 1, w, plane, pw, tw_w, sigma);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -258,9 +299,10 @@ hipError_t launch_fft2(float2 *data, int batch, int h, int w, const FftPlan &ph,
     {
         KernelTimer kt("fft_1d", bytes, s);
         const unsigned lds = fft_lds_bytes(ph, ph.n);
-        e = allow_lds(fft_1d, lds);
+        const Fft1dKernel k = pick_fft_1d(ph);
+        e = allow_lds(k, lds);
         if (e != hipSuccess) return e;
-        fft_1d<<<gc, FNT, lds, s>>>(data, h, w, w, 1, plane, ph, tw_h, sigma);
+        k<<<gc, FNT, lds, s>>>(data, h, w, w, 1, plane, ph, tw_h, sigma);
     }
     return hipGetLastError();
 }
@@ -272,9 +314,10 @@ hipError_t launch_rfft_rows(const float *Y, const float *mod, int ny, int p0, in
     KernelTimer kt("rfft_rows", bytes, s);
     dim3 g((unsigned)((h + phalf.nvec - 1) / phalf.nvec), (unsigned)n);
     const unsigned lds = fft_lds_bytes(phalf, 2 * phalf.n + 1);
-    const hipError_t e = allow_lds(rfft_rows, lds);
+    const RowsKernel k = pick_rfft_rows(phalf);
+    const hipError_t e = allow_lds(k, lds);
     if (e != hipSuccess) return e;
-    rfft_rows<<<g, FNT, lds, s>>>(Y, mod, ny, p0, mean, h, w, phalf, tw_half, tw_full, out);
+    k<<<g, FNT, lds, s>>>(Y, mod, ny, p0, mean, h, w, phalf, tw_half, tw_full, out);
     return hipGetLastError();
 }
 
@@ -286,15 +329,17 @@ hipError_t launch_fft_cols_power(const float2 *S, int n, int h, int Mc, const Ff
     dim3 g((unsigned)fft_cols_power_blocks(Mc, ph), (unsigned)n);
     const unsigned lds = fft_lds_bytes(ph, ph.n);
     if (Px) {
-        const hipError_t e = allow_lds(fft_cols_power<true>, lds);
+        const ColsKernel k = pick_fft_cols<true>(ph);
+        const hipError_t e = allow_lds(k, lds);
         if (e != hipSuccess) return e;
         KernelTimer kt("fft_cols_power_dot", bytes, s);
-        fft_cols_power<true><<<g, FNT, lds, s>>>(S, h, Mc, ph, tw_h, Px, ny, p0, nullptr, part);
+        k<<<g, FNT, lds, s>>>(S, h, Mc, ph, tw_h, Px, ny, p0, nullptr, part);
     } else {
-        const hipError_t e = allow_lds(fft_cols_power<false>, lds);
+        const ColsKernel k = pick_fft_cols<false>(ph);
+        const hipError_t e = allow_lds(k, lds);
         if (e != hipSuccess) return e;
         KernelTimer kt("fft_cols_power_store", bytes, s);
-        fft_cols_power<false><<<g, FNT, lds, s>>>(S, h, Mc, ph, tw_h, nullptr, ny, p0, Pout, nullptr);
+        k<<<g, FNT, lds, s>>>(S, h, Mc, ph, tw_h, nullptr, ny, p0, Pout, nullptr);
     }
     return hipGetLastError();
 }

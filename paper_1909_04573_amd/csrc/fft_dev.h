@@ -148,6 +148,94 @@ __device__ __forceinline__ const float2 *fft_lds(float2 *b0, float2 *b1, const F
     return src;
 }
 
+// ---------------------------------------------------------------------------
+// The same transform for a length N and vector count NV fixed at compile
+// time: every loop bound, index division and twiddle stride is a constant, so
+// the per-butterfly index arithmetic of the passes folds away.  Radices are
+// taken in the order make_fft_plan uses (fours, a two, threes, fives).
+struct Radices {
+    int n;
+    int r[16];
+};
+constexpr Radices radices_of(int N) {
+    Radices L{0, {}};
+    int m = N;
+    while (m % 4 == 0 && L.n < 16) { L.r[L.n++] = 4; m /= 4; }
+    while (m % 2 == 0 && L.n < 16) { L.r[L.n++] = 2; m /= 2; }
+    while (m % 3 == 0 && L.n < 16) { L.r[L.n++] = 3; m /= 3; }
+    while (m % 5 == 0 && L.n < 16) { L.r[L.n++] = 5; m /= 5; }
+    return L;
+}
+constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
+
+template <int N, int R, int NS, int NV>
+__device__ __forceinline__ void stockham_fixed(const float2 *__restrict__ src, float2 *__restrict__ dst,
+                                               const float2 *__restrict__ tw, float sigma) {
+    constexpr int NR = N / R, NB = NR * NV, TWS = N / (NS * R);
+    constexpr int ITER = (NB + FNT - 1) / FNT;
+    constexpr int KB = R == 5 ? 3 : 4;
+#pragma unroll
+    for (int i0 = 0; i0 < ITER; i0 += KB) {
+        float2 v[KB][R];
+        unsigned kk[KB], d0[KB];
+#pragma unroll
+        for (int b = 0; b < KB; ++b) {
+            const int i = i0 + b;
+            const unsigned idx = threadIdx.x + (unsigned)(i * FNT);
+            if (i < ITER && ((i + 1) * FNT <= NB || idx < (unsigned)NB)) {
+                const unsigned vv = idx % NV, j = idx / NV;
+                const unsigned k = j % NS, jq = j / NS;
+                kk[b] = k;
+                d0[b] = (jq * (NS * R) + k) * NV + vv;
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[b][r] = src[(j + r * NR) * NV + vv];
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < KB; ++b) {
+            const int i = i0 + b;
+            const unsigned idx = threadIdx.x + (unsigned)(i * FNT);
+            if (i < ITER && ((i + 1) * FNT <= NB || idx < (unsigned)NB)) {
+                if (NS > 1) {  // the first pass has k = 0: unit twiddles
+#pragma unroll
+                    for (int r = 1; r < R; ++r) {
+                        float2 w = tw[kk[b] * (r * TWS)];
+                        w.y *= -sigma;
+                        v[b][r] = cmul(v[b][r], w);
+                    }
+                }
+                dft<R>(v[b], sigma);
+#pragma unroll
+                for (int r = 0; r < R; ++r) dst[d0[b] + r * NS * NV] = v[b][r];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <int N, int NV, int P = 0, int NS = 1>
+__device__ __forceinline__ const float2 *fft_fixed(float2 *src, float2 *dst, const float2 *__restrict__ tw,
+                                                   float sigma) {
+    constexpr Radices L = radices_of(N);
+    if constexpr (P == L.n) {
+        return src;
+    } else {
+        constexpr int R = L.r[P];
+        stockham_fixed<N, R, NS, NV>(src, dst, tw, sigma);
+        return fft_fixed<N, NV, P + 1, NS * R>(dst, src, tw, sigma);
+    }
+}
+
+// Runtime plan for N = 0, the compile-time passes otherwise.
+template <int N, int NV>
+__device__ __forceinline__ const float2 *fft_run(float2 *b0, float2 *b1, const FftPlan &plan,
+                                                 const float2 *__restrict__ tw, float sigma) {
+    if constexpr (N == 0)
+        return fft_lds(b0, b1, plan, tw, sigma);
+    else
+        return fft_fixed<N, NV>(b0, b1, tw, sigma);
+}
+
 __device__ __forceinline__ double wave_sum_f64(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

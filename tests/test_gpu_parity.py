@@ -293,6 +293,30 @@ def test_pce_fixed_many_fingerprints(dev, nx, ny, h, w, modulated):
         assert pce[q, (3 * q) % ny] > 60
 
 
+@pytest.mark.parametrize("h,w", [(512, 512), (720, 1280), (2160, 3840)])
+def test_compiled_transform_sizes(dev, h, w):
+    """Frame sizes whose row, half-row and column transforms run compile-time
+    kernels (1080x1920 is covered above): fixed-peak PCE of one modulated
+    query against three fingerprints, and the DFT-domain Wiener of one plane."""
+    _log(f"compiled transform sizes {h}x{w}")
+    g = synth.rng(synth.CFG_TEST, 5900 + h)
+    X = g.normal(0, 1, size=(1, h, w)).astype(np.float32)
+    Y = g.normal(0, 1, size=(3, h, w)).astype(np.float32)
+    Y[1] = (0.2 * X[0] + g.normal(0, 1, size=(h, w))).astype(np.float32)
+    mod = g.uniform(50, 200, size=(1, h, w)).astype(np.float32)
+    pce, _, _ = prnu.pce_match(up(X, dev), up(Y, dev), up(mod, dev), peak_mode=0, want_ncc=False,
+                               want_peak=False)
+    pce = down(pce)
+    for j in range(3):
+        r = correlate.pce(X[0].astype(np.float64), Y[j].astype(np.float64) * mod[0], correlate.PEAK_FIXED_00)
+        assert_pce(pce[0, j], r["pce"], what=f"pce[0,{j}] {h}x{w}")
+    assert pce[0, 1] > 60
+    B = g.uniform(1e4, 6e4, size=(1, h, w))
+    A = B * g.normal(0, 0.01, size=(1, h, w))
+    K = down(prnu.fingerprint_finalize(up(A, dev), up(B, dev), flags=prnu.ZM | prnu.WIENER))
+    assert_scaled(K, pipeline.finalize(A, B, pipeline.FIN_ZM | pipeline.FIN_WIENER), what=f"K {h}x{w}")
+
+
 def test_pce_fixed_query_chunks(dev):
     """Enough pairs that the direct sums run in several chunks of queries."""
     _log("pce query chunks")
