@@ -326,18 +326,22 @@ __global__ __launch_bounds__(NT) void pce_direct_mfma(const float *__restrict__ 
                                                       int ny, int q0, int h, int w, int tiles_x, int ntiles,
                                                       double *__restrict__ part) {
     __shared__ float xs[MXH * MXWS];
+    __shared__ float ms[MTY * MTX];                // modulation per tile pixel, 0 outside the image
     __shared__ __align__(16) float ys[MNJ * MYS];  // reused for the FP64 reduction (32 KB)
     __shared__ double sred[NT / 64];
+    __shared__ double yred[NT / 64][MNJ];
     const int q = q0 + (int)blockIdx.y;
     const int j0 = (int)blockIdx.z * MNJ;
     const int nblk = gridDim.x, blk = blockIdx.x;
     const int64_t N = (int64_t)h * w;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const float *xp = X + (int64_t)q * N;
+    const PRNU_GLOBAL float *xp = gmem(X) + (int64_t)q * N;
     const float mux = (float)xmean[q];
-    const float *mp = mod ? mod + (int64_t)q * N : nullptr;
+    const PRNU_GLOBAL float *mp = mod ? gmem(mod) + (int64_t)q * N : nullptr;
     // A operand: row i = lane % 16 of shift block sb is shift m = 16 sb + i (rows past the
-    // ones row read shift (0,0) and are dropped), column k = lane / 16 is pixel k of the quad
+    // ones row read shift (0,0) and are dropped), column k = lane / 16 is pixel k of the quad.
+    // The modulation belongs to the pixel t, so it scales A: xc(t + s) * mod(t); the
+    // fingerprint tile (B) is then the same for every query.
     int aoff[MNS];
 #pragma unroll
     for (int sb = 0; sb < MNS; ++sb) {
@@ -349,51 +353,65 @@ __global__ __launch_bounds__(NT) void pce_direct_mfma(const float *__restrict__ 
     const int boff = (lane & 15) * MYS + (lane >> 4);  // B: fingerprint n = lane % 16, pixel k = lane / 16
     // staging of the fingerprint tile: thread -> fingerprint sn, columns sc + 16 u
     const int sn = tid >> 4, sc = tid & 15;
-    const float *yp = j0 + sn < ny ? Y + (int64_t)(j0 + sn) * N : nullptr;
+    const PRNU_GLOBAL float *yp = j0 + sn < ny ? gmem(Y) + (int64_t)(j0 + sn) * N : nullptr;
     double acc[MNS][4];
 #pragma unroll
     for (int sb = 0; sb < MNS; ++sb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[sb][r] = 0.0;
     double syy = 0.0, sx = 0.0;
-    for (int tile = blk; tile < ntiles; tile += nblk) {
+
+    // The next tile's global loads are issued before the current tile's
+    // products and land in registers while the matrix cores run.
+    constexpr int KX = (MXH * MXW + NT - 1) / NT, KM = MTY * MTX / NT, KY = MTY * MTX * MNJ / NT;
+    static_assert(KM * NT == MTY * MTX && KY * NT == MTY * MTX * MNJ, "tile staging");
+    float rx[KX], rm[KM], ry[KY];
+    auto fetch = [&](int tile) {
         const int ty0 = (tile / tiles_x) * MTY, tx0 = (tile % tiles_x) * MTX;
-        __syncthreads();  // previous tile's LDS reads are done
-        staged_copy<NT, 8, float>(
-            tid, MXH * MXW,
-            [&](int e) {
+#pragma unroll
+        for (int k = 0; k < KX; ++k) {
+            const int e = tid + k * NT;
+            rx[k] = 0.f;
+            if (e < MXH * MXW) {
                 const int i = e / MXW, jj = e - (e / MXW) * MXW;
                 int gr = (ty0 - DRAD + i) % h;
                 gr = gr < 0 ? gr + h : gr;
                 int gc = (tx0 - DRAD + jj) % w;
                 gc = gc < 0 ? gc + w : gc;
-                return xp[(int64_t)gr * w + gc] - mux;
-            },
-            [&](int e, float v) { xs[(e / MXW) * MXWS + e - (e / MXW) * MXW] = v; });
-        float ssq = 0.f;
-#pragma unroll
-        for (int b0 = 0; b0 < 32; b0 += 8) {
-            float v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int kk = b0 + u, r = kk >> 2, c = sc + 16 * (kk & 3);
-                const int gy = ty0 + r, gx = tx0 + c;
-                float y = 0.f;
-                if (yp && gy < h && gx < w) {
-                    const int64_t o = (int64_t)gy * w + gx;
-                    y = mp ? mp[o] * yp[o] : yp[o];
-                }
-                v[u] = y;
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int kk = b0 + u, r = kk >> 2, c = sc + 16 * (kk & 3);
-                ys[sn * MYS + r * MTX + c] = v[u];
-                ssq = fmaf(v[u], v[u], ssq);
+                rx[k] = xp[(int64_t)gr * w + gc];
             }
         }
-        syy += (double)ssq;
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            const int e = tid + k * NT, gy = ty0 + e / MTX, gx = tx0 + e % MTX;
+            const bool in = gy < h && gx < w;
+            rm[k] = in ? (mp ? mp[(int64_t)gy * w + gx] : 1.f) : 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < KY; ++k) {
+            const int r = k >> 2, c = sc + 16 * (k & 3), gy = ty0 + r, gx = tx0 + c;
+            ry[k] = (yp && gy < h && gx < w) ? yp[(int64_t)gy * w + gx] : 0.f;
+        }
+    };
+    auto put = [&]() {
+#pragma unroll
+        for (int k = 0; k < KX; ++k) {
+            const int e = tid + k * NT;
+            if (e < MXH * MXW) xs[(e / MXW) * MXWS + e - (e / MXW) * MXW] = rx[k] - mux;
+        }
+#pragma unroll
+        for (int k = 0; k < KM; ++k) ms[tid + k * NT] = rm[k];
+#pragma unroll
+        for (int k = 0; k < KY; ++k) ys[sn * MYS + (k >> 2) * MTX + sc + 16 * (k & 3)] = ry[k];
+    };
+
+    if (blk < ntiles) fetch(blk);
+    for (int tile = blk; tile < ntiles; tile += nblk) {
+        const int ty0 = (tile / tiles_x) * MTY, tx0 = (tile % tiles_x) * MTX;
+        __syncthreads();  // previous tile's LDS reads are done
+        put();
         __syncthreads();
+        if (tile + nblk < ntiles) fetch(tile + nblk);
         // sum of the centred query over this tile's pixels inside the image
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
@@ -404,17 +422,22 @@ __global__ __launch_bounds__(NT) void pce_direct_mfma(const float *__restrict__ 
         v4f cacc[MNS];
 #pragma unroll
         for (int sb = 0; sb < MNS; ++sb) cacc[sb] = v4f{0.f, 0.f, 0.f, 0.f};
+        float ssq = 0.f;
         for (int g = 0; g < 32; ++g) {
             const int r = 2 * wv + (g >> 4), c4 = (g & 15) * 4;
             const float b = ys[boff + r * MTX + c4];
+            const float m = ms[r * MTX + c4 + (lane >> 4)];
+            const float mb = m * b;
+            ssq = fmaf(mb, mb, ssq);
             const int xb = r * MXWS + c4;
 #pragma unroll
             for (int sb = 0; sb < MNS; ++sb) {
-                float a = xs[xb + aoff[sb]];
-                if (sb == MNS - 1 && ones_lane) a = 1.f;
+                float a = xs[xb + aoff[sb]] * m;
+                if (sb == MNS - 1 && ones_lane) a = m;
                 cacc[sb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, cacc[sb], 0, 0, 0);
             }
         }
+        syy += (double)ssq;
 #pragma unroll
         for (int sb = 0; sb < MNS; ++sb)
 #pragma unroll
@@ -458,17 +481,22 @@ __global__ __launch_bounds__(NT) void pce_direct_mfma(const float *__restrict__ 
                 }
         }
     }
-    // sum y^2 per fingerprint: the 16 staging threads of each fingerprint (a fixed shuffle tree)
-#pragma unroll
-    for (int o = 8; o > 0; o >>= 1) syy += __shfl_xor(syy, o, 16);
-    if (sc == 0 && j0 + sn < ny) part[((prow + j0 + sn) * nblk + blk) * DSTAT + MONES + 1] = syy;
+    // sum y^2 per fingerprint n = lane % 16: the four lanes of n in each wave (a
+    // fixed shuffle tree), then the four waves in order
+    syy += __shfl_xor(syy, 16, 64);
+    syy += __shfl_xor(syy, 32, 64);
+    if (lane < MNJ) yred[wv][lane] = syy;
     // sum xc, the same for every fingerprint
     sx = wave_sum(sx);
     if (lane == 0) sred[wv] = sx;
     __syncthreads();
     if (tid < MNJ && j0 + tid < ny) {
-        double t = 0.0;
-        for (int k = 0; k < NT / 64; ++k) t += sred[k];
+        double t = 0.0, u = 0.0;
+        for (int k = 0; k < NT / 64; ++k) {
+            t += sred[k];
+            u += yred[k][tid];
+        }
+        part[((prow + j0 + tid) * nblk + blk) * DSTAT + MONES + 1] = u;
         part[((prow + j0 + tid) * nblk + blk) * DSTAT + MONES + 2] = t;
     }
 }
