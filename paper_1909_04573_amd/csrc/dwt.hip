@@ -299,39 +299,47 @@ __device__ __forceinline__ void inv_maps(int tid, int hk, int wk, int k0r, int k
 }
 
 // Stages the (TT+L/2-1)^2 coefficients of the four subbands (subband 0 as
-// zeros with zero_approx); a thread issues its loads in batches of up to 12
-// before storing them, so a batch is in flight at once.
+// zeros with zero_approx).  Threads form 32 columns x (NT/32) rows: a thread
+// looks up its column offsets and its row offsets once and then reads the
+// same positions of every subband, so each load costs one address add; a
+// wave's lanes read consecutive columns of two rows.  Loads are issued for
+// two subbands at a time before their LDS stores.
 template <int TAPS, int TT>
 __device__ __forceinline__ void inv_load(int tid, const float *__restrict__ lpp, int hk, int wk, bool zero_approx,
                                          float *sb, const int *rmap, const int *cmap) {
     const PRNU_GLOBAL float *lp = gmem(lpp);
     constexpr int NK = InvGeom<TAPS, TT>::NK, NKS = InvGeom<TAPS, TT>::NKS;
-    constexpr int E = 4 * NK * NK, K = (E + NT - 1) / NT, KB = K < 12 ? K : 12;
+    constexpr int CX = 32, RY = NT / CX;
+    constexpr int NCG = (NK + CX - 1) / CX, NRG = (NK + RY - 1) / RY;
+    const int tx = tid % CX, ty = tid / CX;
     const int64_t band = (int64_t)hk * wk;
+    int coff[NCG], roff[NRG];
 #pragma unroll
-    for (int k0 = 0; k0 < K; k0 += KB) {
-        float v[KB];
+    for (int g = 0; g < NCG; ++g) coff[g] = tx + g * CX < NK ? cmap[tx + g * CX] : 0;
 #pragma unroll
-        for (int k = 0; k < KB; ++k) {
-            const int e = tid + (k0 + k) * NT;
-            v[k] = 0.f;
-            if (k0 + k < K && e < E) {
-                const int s = e / (NK * NK);
-                const int rem = e - s * NK * NK;
-                const int kr = rem / NK, kc = rem - (rem / NK) * NK;
-                if (!(s == 0 && zero_approx)) v[k] = lp[s * band + (int64_t)rmap[kr] * wk + cmap[kc]];
-            }
-        }
+    for (int i = 0; i < NRG; ++i) roff[i] = ty + i * RY < NK ? rmap[ty + i * RY] * wk : 0;
 #pragma unroll
-        for (int k = 0; k < KB; ++k) {
-            const int e = tid + (k0 + k) * NT;
-            if (k0 + k < K && e < E) {
-                const int s = e / (NK * NK);
-                const int rem = e - s * NK * NK;
-                const int kr = rem / NK, kc = rem - (rem / NK) * NK;
-                sb[(s * NK + kr) * NKS + kc] = v[k];
-            }
-        }
+    for (int s0 = 0; s0 < 4; s0 += 2) {
+        float v[2][NRG][NCG];
+#pragma unroll
+        for (int ds = 0; ds < 2; ++ds)
+#pragma unroll
+            for (int i = 0; i < NRG; ++i)
+#pragma unroll
+                for (int g = 0; g < NCG; ++g) {
+                    const int sbd = s0 + ds;
+                    v[ds][i][g] = 0.f;
+                    if (ty + i * RY < NK && tx + g * CX < NK && !(sbd == 0 && zero_approx))
+                        v[ds][i][g] = lp[sbd * band + roff[i] + coff[g]];
+                }
+#pragma unroll
+        for (int ds = 0; ds < 2; ++ds)
+#pragma unroll
+            for (int i = 0; i < NRG; ++i)
+#pragma unroll
+                for (int g = 0; g < NCG; ++g)
+                    if (ty + i * RY < NK && tx + g * CX < NK)
+                        sb[((s0 + ds) * NK + ty + i * RY) * NKS + tx + g * CX] = v[ds][i][g];
     }
 }
 
