@@ -114,50 +114,50 @@ __device__ __forceinline__ void fwd_body(const FwdArgs &a, int tile, int plane, 
 
     // Stage the input tile: pairs of contiguous samples where the tile's
     // columns need neither the periodic wrap nor the reflection, single
-    // samples otherwise.  Every load of a thread is issued before the first
-    // LDS store, so the whole tile is in flight at once.
+    // samples otherwise.  Threads form CX columns x RY rows; a thread looks up
+    // its column offsets once and one row offset per row it reads, so each
+    // load costs an address add.  Every load of a thread is issued before the
+    // first LDS store, so the whole tile is in flight at once.
     const int c_src0 = 2 * (k0c - HALO) - a.off_c;
     const bool cfast = c_src0 >= 0 && c_src0 + IN <= a.src_cols && (c_src0 & 1) == 0 && (a.src_cols & 1) == 0 &&
                        (a.src_stride & 1) == 0;
     if (cfast) {
-        constexpr int IN2 = IN / 2;
-        constexpr int E = IN * IN2, K = (E + NTH - 1) / NTH;
-        float2 v[K];
+        constexpr int IN2 = IN / 2, CX = IN2 <= 32 ? 32 : 64, RY = NTH / CX, NRG = (IN + RY - 1) / RY;
+        const int tx = tid % CX, ty = tid / CX;
+        const PRNU_GLOBAL float *cp0 = sp + c_src0 + 2 * tx;
+        float2 v[NRG];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int e = tid + k * NTH;
-            if (e < E) {
-                const int i = e / IN2, j2 = e - (e / IN2) * IN2;
-                v[k] = ld2(sp + (int64_t)rmap[i] * a.src_cols + c_src0 + 2 * j2);
-            }
+        for (int i = 0; i < NRG; ++i) {
+            const int r = ty + i * RY;
+            if (tx < IN2 && r < IN) v[i] = ld2(cp0 + (int64_t)rmap[r] * a.src_cols);
         }
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int e = tid + k * NTH;
-            if (e < E) {
-                const int i = e / IN2, j2 = e - (e / IN2) * IN2;
-                *reinterpret_cast<float2 *>(&tbuf[i * INS + 2 * j2]) = v[k];
-            }
+        for (int i = 0; i < NRG; ++i) {
+            const int r = ty + i * RY;
+            if (tx < IN2 && r < IN) *reinterpret_cast<float2 *>(&tbuf[r * INS + 2 * tx]) = v[i];
         }
     } else {
-        constexpr int E = IN * IN, K = (E + NTH - 1) / NTH;
-        float v[K];
+        constexpr int CX = 32, RY = NTH / CX, NCG = (IN + CX - 1) / CX, NRG = (IN + RY - 1) / RY;
+        const int tx = tid % CX, ty = tid / CX;
+        int coff[NCG];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int e = tid + k * NTH;
-            if (e < E) {
-                const int i = e / IN, j = e - (e / IN) * IN;
-                v[k] = sp[(int64_t)rmap[i] * a.src_cols + cmap[j]];
-            }
+        for (int g = 0; g < NCG; ++g) coff[g] = tx + g * CX < IN ? cmap[tx + g * CX] : 0;
+        float v[NRG][NCG];
+#pragma unroll
+        for (int i = 0; i < NRG; ++i) {
+            const int r = ty + i * RY;
+            const PRNU_GLOBAL float *rp = sp + (int64_t)(r < IN ? rmap[r] : 0) * a.src_cols;
+#pragma unroll
+            for (int g = 0; g < NCG; ++g)
+                if (r < IN && tx + g * CX < IN) v[i][g] = rp[coff[g]];
         }
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int e = tid + k * NTH;
-            if (e < E) {
-                const int i = e / IN, j = e - (e / IN) * IN;
-                tbuf[i * INS + j] = v[k];
+        for (int i = 0; i < NRG; ++i)
+#pragma unroll
+            for (int g = 0; g < NCG; ++g) {
+                const int r = ty + i * RY;
+                if (r < IN && tx + g * CX < IN) tbuf[r * INS + tx + g * CX] = v[i][g];
             }
-        }
     }
     __syncthreads();
 
