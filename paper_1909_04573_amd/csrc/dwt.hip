@@ -42,6 +42,9 @@ constexpr int NT = 256;  // threads per workgroup
 // twice the threads give the CU more waves to hide load and LDS latency.
 constexpr int FWD_NT32 = 512;
 constexpr int fwd_nt(int tt) { return tt == 32 ? FWD_NT32 : NT; }
+// The same for the inverse levels (32 x 32 tiles: three workgroups per CU).
+constexpr int INV_NT32 = 512;
+constexpr int inv_nt(int tt) { return tt == 32 ? INV_NT32 : NT; }
 
 template <int TAPS, int TT>
 struct FwdGeom {
@@ -299,7 +302,7 @@ __device__ __forceinline__ void inv_maps(int tid, int hk, int wk, int k0r, int k
 }
 
 // Stages the (TT+L/2-1)^2 coefficients of the four subbands (subband 0 as
-// zeros with zero_approx).  Threads form 32 columns x (NT/32) rows: a thread
+// zeros with zero_approx).  Threads form 32 columns x (threads/32) rows: a thread
 // looks up its column offsets and its row offsets once and then reads the
 // same positions of every subband, so each load costs one address add; a
 // wave's lanes read consecutive columns of two rows.  Loads are issued for
@@ -309,7 +312,7 @@ __device__ __forceinline__ void inv_load(int tid, const float *__restrict__ lpp,
                                          float *sb, const int *rmap, const int *cmap) {
     const PRNU_GLOBAL float *lp = gmem(lpp);
     constexpr int NK = InvGeom<TAPS, TT>::NK, NKS = InvGeom<TAPS, TT>::NKS;
-    constexpr int CX = 32, RY = NT / CX;
+    constexpr int CX = 32, RY = inv_nt(TT) / CX;
     constexpr int NCG = (NK + CX - 1) / CX, NRG = (NK + RY - 1) / RY;
     const int tx = tid % CX, ty = tid / CX;
     const int64_t band = (int64_t)hk * wk;
@@ -348,7 +351,7 @@ template <int TAPS, int TT>
 __device__ __forceinline__ void inv_cols(int tid, const float *sb, float *lo1, float *hi1, const Filter &f) {
     constexpr int NK = InvGeom<TAPS, TT>::NK, NKS = InvGeom<TAPS, TT>::NKS, HT = TAPS / 2;
     // item: column kc, quad of output rows n = 4pp .. 4pp+3 (coefficient rows 2pp .. 2pp+HT)
-    for (int it = tid; it < NK * (TT / 2); it += NT) {
+    for (int it = tid; it < NK * (TT / 2); it += inv_nt(TT)) {
         const int pp = it / NK, kc = it - (it / NK) * NK;
         float a[HT + 1], lh[HT + 1], hl[HT + 1], hh[HT + 1];
 #pragma unroll
@@ -422,7 +425,7 @@ __device__ __forceinline__ void inv_body(const InvArgs &a, int tile, int plane, 
     __syncthreads();
     const int nr = 2 * a.hk, nc = 2 * a.wk;
     PRNU_GLOBAL float *out = gmem(a.out);
-    for (int it = tid; it < NO * (NO / 4); it += NT) {
+    for (int it = tid; it < NO * (NO / 4); it += inv_nt(TT)) {
         const int n = it / (NO / 4), mq = it - (it / (NO / 4)) * (NO / 4);
         float x[4];
         inv_row_quad<TAPS, TT>(lo1, hi1, n, mq, f, x);
@@ -449,8 +452,8 @@ template <int TAPS, int TT, int ACC>
 __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, float *lds, const Filter &f) {
     using G = InvGeom<TAPS, TT>;
     constexpr int NO = G::NO;
-    constexpr int ITEMS = NO * (NO / 4) / NT;  // row quads per thread: 4 (TT = 32) or 1 (TT = 16)
-    static_assert(NO * (NO / 4) == ITEMS * NT, "items per thread");
+    constexpr int ITEMS = NO * (NO / 4) / inv_nt(TT);  // row quads per thread
+    static_assert(NO * (NO / 4) == ITEMS * inv_nt(TT), "items per thread");
     float *sb = lds, *lo1 = lds + G::SB, *hi1 = lo1 + G::L1;
     int *rmap = reinterpret_cast<int *>(hi1 + G::L1);
     int *cmap = rmap + G::NK;
@@ -479,7 +482,7 @@ __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, floa
         float Iv[PF ? ITEMS : 1][4];
 #pragma unroll
         for (int k = 0; k < (PF ? ITEMS : 0); ++k) {
-            const int it = tid + k * NT;
+            const int it = tid + k * inv_nt(TT);
             const int n = it / (NO / 4), mq = it - (it / (NO / 4)) * (NO / 4);
             const int y = 2 * k0r + n - a.off_r;
 #pragma unroll
@@ -497,7 +500,7 @@ __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, floa
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
-            const int it = tid + k * NT;
+            const int it = tid + k * inv_nt(TT);
             const int n = it / (NO / 4), mq = it - (it / (NO / 4)) * (NO / 4);
             float x[4];
             inv_row_quad<TAPS, TT>(lo1, hi1, n, mq, f, x);
@@ -532,7 +535,7 @@ __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, floa
     // one read-modify-write of the accumulators per pixel
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
-        const int it = tid + k * NT;
+        const int it = tid + k * inv_nt(TT);
         const int n = it / (NO / 4), mq = it - (it / (NO / 4)) * (NO / 4);
         const int y = 2 * k0r + n - a.off_r;
         if (y < 0 || y >= H) continue;
@@ -580,7 +583,7 @@ __global__ __launch_bounds__(fwd_nt(TT)) void dwt_fwd_wiener(FwdArgs a, Filter f
 }
 
 template <int TAPS, int TT, int EPI>
-__global__ __launch_bounds__(NT) void dwt_inv(InvArgs a, Filter f) {
+__global__ __launch_bounds__(inv_nt(TT)) void dwt_inv(InvArgs a, Filter f) {
     __shared__ __align__(16) float lds[InvGeom<TAPS, TT>::LDS];
     int tile, plane;
     grid_tile(tile, plane);
@@ -588,7 +591,7 @@ __global__ __launch_bounds__(NT) void dwt_inv(InvArgs a, Filter f) {
 }
 
 template <int TAPS, int TT, int ACC>
-__global__ __launch_bounds__(NT) void dwt_inv_mle(MleArgs a, Filter f) {
+__global__ __launch_bounds__(inv_nt(TT)) void dwt_inv_mle(MleArgs a, Filter f) {
     __shared__ __align__(16) float lds[InvGeom<TAPS, TT>::LDS];
     int tile, c;
     grid_tile(tile, c);
@@ -638,7 +641,7 @@ __global__ __launch_bounds__(fwd_nt(TT)) void dwt_fwd_multi(const FwdDesc *__res
 }
 
 template <int TAPS, int TT>
-__global__ __launch_bounds__(NT) void dwt_inv_multi(const InvDesc *__restrict__ d, int nd, int total, int *ctr,
+__global__ __launch_bounds__(inv_nt(TT)) void dwt_inv_multi(const InvDesc *__restrict__ d, int nd, int total, int *ctr,
                                                     Filter f) {
     __shared__ __align__(16) float lds[InvGeom<TAPS, TT>::LDS];
     __shared__ int slot;
@@ -652,7 +655,7 @@ __global__ __launch_bounds__(NT) void dwt_inv_multi(const InvDesc *__restrict__ 
 }
 
 template <int TAPS, int TT, int ACC>
-__global__ __launch_bounds__(NT) void dwt_mle_multi(const MleDesc *__restrict__ d, int nd, int total, int *ctr,
+__global__ __launch_bounds__(inv_nt(TT)) void dwt_mle_multi(const MleDesc *__restrict__ d, int nd, int total, int *ctr,
                                                     Filter f) {
     __shared__ __align__(16) float lds[InvGeom<TAPS, TT>::LDS];
     __shared__ int slot;
@@ -739,8 +742,8 @@ hipError_t launch_dwt_inv(int taps, const Filter &f, const float *lvl, int hk, i
     KernelTimer kt(names[taps == 16][epi == INV_PLANE ? 0 : 1], bytes, s);
 #define PRNU_INV(TP, T_)                                                  \
     do {                                                                  \
-        if (epi == INV_PLANE) dwt_inv<TP, T_, INV_PLANE><<<grid, NT, 0, s>>>(a, f); \
-        else dwt_inv<TP, T_, INV_RESID><<<grid, NT, 0, s>>>(a, f);        \
+        if (epi == INV_PLANE) dwt_inv<TP, T_, INV_PLANE><<<grid, inv_nt(T_), 0, s>>>(a, f); \
+        else dwt_inv<TP, T_, INV_RESID><<<grid, inv_nt(T_), 0, s>>>(a, f);        \
     } while (0)
     if (taps == 16) {
         if (tt == 16) PRNU_INV(16, 16); else PRNU_INV(16, 32);
@@ -763,10 +766,10 @@ hipError_t launch_dwt_inv_mle(int taps, const Filter &f, const float *lvl, int h
     KernelTimer kt(taps == 16 ? "dwt_inv_mle<16>" : "dwt_inv_mle<8>", bytes, s);
 #define PRNU_MLE(TP, T_)                                                                            \
     do {                                                                                            \
-        if (acc_mode == PRNU_ACC_F64) dwt_inv_mle<TP, T_, PRNU_ACC_F64><<<grid, NT, 0, s>>>(a, f);  \
+        if (acc_mode == PRNU_ACC_F64) dwt_inv_mle<TP, T_, PRNU_ACC_F64><<<grid, inv_nt(T_), 0, s>>>(a, f);  \
         else if (acc_mode == PRNU_ACC_KAHAN_F32)                                                    \
-            dwt_inv_mle<TP, T_, PRNU_ACC_KAHAN_F32><<<grid, NT, 0, s>>>(a, f);                      \
-        else dwt_inv_mle<TP, T_, PRNU_ACC_F32><<<grid, NT, 0, s>>>(a, f);                           \
+            dwt_inv_mle<TP, T_, PRNU_ACC_KAHAN_F32><<<grid, inv_nt(T_), 0, s>>>(a, f);                      \
+        else dwt_inv_mle<TP, T_, PRNU_ACC_F32><<<grid, inv_nt(T_), 0, s>>>(a, f);                           \
     } while (0)
     if (taps == 16) {
         if (tt == 16) PRNU_MLE(16, 16); else PRNU_MLE(16, 32);
@@ -794,11 +797,11 @@ hipError_t launch_inv_multi(int taps, int tt, const Filter &f, const InvDesc *d,
                             int grid, hipStream_t s) {
     if (total <= 0 || nd <= 0) return hipSuccess;
     if (taps == 16) {
-        if (tt == 16) dwt_inv_multi<16, 16><<<grid, NT, 0, s>>>(d, nd, total, ctr, f);
-        else dwt_inv_multi<16, 32><<<grid, NT, 0, s>>>(d, nd, total, ctr, f);
+        if (tt == 16) dwt_inv_multi<16, 16><<<grid, inv_nt(16), 0, s>>>(d, nd, total, ctr, f);
+        else dwt_inv_multi<16, 32><<<grid, inv_nt(32), 0, s>>>(d, nd, total, ctr, f);
     } else {
-        if (tt == 16) dwt_inv_multi<8, 16><<<grid, NT, 0, s>>>(d, nd, total, ctr, f);
-        else dwt_inv_multi<8, 32><<<grid, NT, 0, s>>>(d, nd, total, ctr, f);
+        if (tt == 16) dwt_inv_multi<8, 16><<<grid, inv_nt(16), 0, s>>>(d, nd, total, ctr, f);
+        else dwt_inv_multi<8, 32><<<grid, inv_nt(32), 0, s>>>(d, nd, total, ctr, f);
     }
     return hipGetLastError();
 }
@@ -809,11 +812,11 @@ hipError_t launch_mle_multi(int taps, int tt, int acc_mode, const Filter &f, con
 #define PRNU_MM(TP, T_)                                                                                  \
     do {                                                                                                 \
         if (acc_mode == PRNU_ACC_F64)                                                                    \
-            dwt_mle_multi<TP, T_, PRNU_ACC_F64><<<grid, NT, 0, s>>>(d, nd, total, ctr, f);               \
+            dwt_mle_multi<TP, T_, PRNU_ACC_F64><<<grid, inv_nt(T_), 0, s>>>(d, nd, total, ctr, f);               \
         else if (acc_mode == PRNU_ACC_KAHAN_F32)                                                         \
-            dwt_mle_multi<TP, T_, PRNU_ACC_KAHAN_F32><<<grid, NT, 0, s>>>(d, nd, total, ctr, f);         \
+            dwt_mle_multi<TP, T_, PRNU_ACC_KAHAN_F32><<<grid, inv_nt(T_), 0, s>>>(d, nd, total, ctr, f);         \
         else                                                                                             \
-            dwt_mle_multi<TP, T_, PRNU_ACC_F32><<<grid, NT, 0, s>>>(d, nd, total, ctr, f);               \
+            dwt_mle_multi<TP, T_, PRNU_ACC_F32><<<grid, inv_nt(T_), 0, s>>>(d, nd, total, ctr, f);               \
     } while (0)
     if (taps == 16) {
         if (tt == 16) PRNU_MM(16, 16); else PRNU_MM(16, 32);
@@ -843,14 +846,16 @@ int fwd_multi_occupancy(int taps, int tt) {
     return tt == 16 ? occupancy_of(dwt_fwd_multi<8, 16>, fwd_nt(16)) : occupancy_of(dwt_fwd_multi<8, 32>, fwd_nt(32));
 }
 int inv_multi_occupancy(int taps, int tt) {
-    if (taps == 16) return tt == 16 ? occupancy_of(dwt_inv_multi<16, 16>) : occupancy_of(dwt_inv_multi<16, 32>);
-    return tt == 16 ? occupancy_of(dwt_inv_multi<8, 16>) : occupancy_of(dwt_inv_multi<8, 32>);
+    if (taps == 16)
+        return tt == 16 ? occupancy_of(dwt_inv_multi<16, 16>, inv_nt(16))
+                        : occupancy_of(dwt_inv_multi<16, 32>, inv_nt(32));
+    return tt == 16 ? occupancy_of(dwt_inv_multi<8, 16>, inv_nt(16)) : occupancy_of(dwt_inv_multi<8, 32>, inv_nt(32));
 }
 int mle_multi_occupancy(int taps, int tt, int acc_mode) {
 #define PRNU_OCC(TP, T_)                                                                              \
-    return acc_mode == PRNU_ACC_F64 ? occupancy_of(dwt_mle_multi<TP, T_, PRNU_ACC_F64>)               \
-           : acc_mode == PRNU_ACC_KAHAN_F32 ? occupancy_of(dwt_mle_multi<TP, T_, PRNU_ACC_KAHAN_F32>) \
-                                            : occupancy_of(dwt_mle_multi<TP, T_, PRNU_ACC_F32>)
+    return acc_mode == PRNU_ACC_F64 ? occupancy_of(dwt_mle_multi<TP, T_, PRNU_ACC_F64>, inv_nt(T_))          \
+           : acc_mode == PRNU_ACC_KAHAN_F32 ? occupancy_of(dwt_mle_multi<TP, T_, PRNU_ACC_KAHAN_F32>, inv_nt(T_)) \
+                                            : occupancy_of(dwt_mle_multi<TP, T_, PRNU_ACC_F32>, inv_nt(T_))
     if (taps == 16) {
         if (tt == 16) PRNU_OCC(16, 16);
         PRNU_OCC(16, 32);
