@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--depths", type=str, default="1,10,20,50")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tiles", type=str, default="auto",
+                    help="video: 'auto' (time both tile sizes per level kernel) or the 12 values autotune "
+                         "reports, e.g. to profile the configuration a bench run chose")
     ap.add_argument("--curve-step", type=int, default=25,
                     help="video: frame-count grid of the conventional accuracy curve (0: skip it)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -136,8 +139,13 @@ def main():
     log(f"inputs ready in {time.time() - t0:.1f} s ({frames.numel() / 1e9:.2f} GB frames)")
 
     p = prnu.denoise_params()
-    tiles = prnu.autotune(H, W, C, p, device=dev)  # tile side per level kernel, timed on this GPU
-    log(f"autotuned tiles: {tiles}")
+    if args.tiles == "auto":
+        tiles = prnu.autotune(H, W, C, p, device=dev)  # tile side per level kernel, timed on this GPU
+        log(f"autotuned tiles: {tiles}")
+    else:
+        tiles = [int(x) for x in args.tiles.split(",")]
+        prnu.set_tiles(H, W, tiles)
+        log(f"tiles as given: {tiles}")
     A, B = prnu.new_accumulators(C, H, W, device=dev)
     ws = prnu.workspace(max(prnu.fingerprint_accumulate_workspace_size(nfp, H, W, C, d, p) for d in depths), dev)
     Kall = torch.empty((len(depths) * ncam, H, W), dtype=torch.float32, device=dev)

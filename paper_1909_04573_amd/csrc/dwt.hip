@@ -301,50 +301,55 @@ __device__ __forceinline__ void inv_maps(int tid, int hk, int wk, int k0r, int k
     }
 }
 
-// Stages the (TT+L/2-1)^2 coefficients of the four subbands (subband 0 as
-// zeros with zero_approx).  Threads form 32 columns x (threads/32) rows: a thread
-// looks up its column offsets and its row offsets once and then reads the
-// same positions of every subband, so each load costs one address add; a
-// wave's lanes read consecutive columns of two rows.  Loads are issued for
-// two subbands at a time before their LDS stores.
+// Staging of the (TT+L/2-1)^2 coefficients of the four subbands (subband 0
+// as zeros with zero_approx).  Threads form 32 columns x (threads/32) rows: a
+// thread looks up its column and row offsets once (they are the same for
+// every plane of a level) and then reads the same positions of every
+// subband, so each load costs one address add; a wave's lanes read
+// consecutive columns of two rows.  fetch() issues a plane's loads into
+// registers, put() stores them to LDS, so a caller can have the next plane's
+// loads in flight while it works on the current one.
 template <int TAPS, int TT>
-__device__ __forceinline__ void inv_load(int tid, const float *__restrict__ lpp, int hk, int wk, bool zero_approx,
-                                         float *sb, const int *rmap, const int *cmap) {
-    const PRNU_GLOBAL float *lp = gmem(lpp);
-    constexpr int NK = InvGeom<TAPS, TT>::NK, NKS = InvGeom<TAPS, TT>::NKS;
-    constexpr int CX = 32, RY = inv_nt(TT) / CX;
-    constexpr int NCG = (NK + CX - 1) / CX, NRG = (NK + RY - 1) / RY;
-    const int tx = tid % CX, ty = tid / CX;
-    const int64_t band = (int64_t)hk * wk;
-    int coff[NCG], roff[NRG];
+struct InvStage {
+    static constexpr int NK = InvGeom<TAPS, TT>::NK, NKS = InvGeom<TAPS, TT>::NKS;
+    static constexpr int CX = 32, RY = inv_nt(TT) / CX;
+    static constexpr int NCG = (NK + CX - 1) / CX, NRG = (NK + RY - 1) / RY;
+    int tx, ty, coff[NCG], roff[NRG];
+    float v[4][NRG][NCG];
+
+    // rmap/cmap must be in LDS (after the barrier that follows inv_maps)
+    __device__ __forceinline__ void offsets(int tid, int wk, const int *rmap, const int *cmap) {
+        tx = tid % CX;
+        ty = tid / CX;
 #pragma unroll
-    for (int g = 0; g < NCG; ++g) coff[g] = tx + g * CX < NK ? cmap[tx + g * CX] : 0;
+        for (int g = 0; g < NCG; ++g) coff[g] = tx + g * CX < NK ? cmap[tx + g * CX] : 0;
 #pragma unroll
-    for (int i = 0; i < NRG; ++i) roff[i] = ty + i * RY < NK ? rmap[ty + i * RY] * wk : 0;
+        for (int i = 0; i < NRG; ++i) roff[i] = ty + i * RY < NK ? rmap[ty + i * RY] * wk : 0;
+    }
+    __device__ __forceinline__ void fetch(const float *__restrict__ lpp, int64_t band, bool zero_approx) {
+        const PRNU_GLOBAL float *lp = gmem(lpp);
 #pragma unroll
-    for (int s0 = 0; s0 < 4; s0 += 2) {
-        float v[2][NRG][NCG];
-#pragma unroll
-        for (int ds = 0; ds < 2; ++ds)
+        for (int sbd = 0; sbd < 4; ++sbd)
 #pragma unroll
             for (int i = 0; i < NRG; ++i)
 #pragma unroll
                 for (int g = 0; g < NCG; ++g) {
-                    const int sbd = s0 + ds;
-                    v[ds][i][g] = 0.f;
+                    v[sbd][i][g] = 0.f;
                     if (ty + i * RY < NK && tx + g * CX < NK && !(sbd == 0 && zero_approx))
-                        v[ds][i][g] = lp[sbd * band + roff[i] + coff[g]];
+                        v[sbd][i][g] = lp[sbd * band + roff[i] + coff[g]];
                 }
+    }
+    __device__ __forceinline__ void put(float *sb) const {
 #pragma unroll
-        for (int ds = 0; ds < 2; ++ds)
+        for (int sbd = 0; sbd < 4; ++sbd)
 #pragma unroll
             for (int i = 0; i < NRG; ++i)
 #pragma unroll
                 for (int g = 0; g < NCG; ++g)
                     if (ty + i * RY < NK && tx + g * CX < NK)
-                        sb[((s0 + ds) * NK + ty + i * RY) * NKS + tx + g * CX] = v[ds][i][g];
+                        sb[(sbd * NK + ty + i * RY) * NKS + tx + g * CX] = v[sbd][i][g];
     }
-}
+};
 
 // Columns (axis 0): lo1/hi1[n][kc] for the 2TT output rows.
 template <int TAPS, int TT>
@@ -418,8 +423,12 @@ __device__ __forceinline__ void inv_body(const InvArgs &a, int tile, int plane, 
     const int k0r = tr * TT, k0c = tc * TT;
     inv_maps<TAPS, TT>(tid, a.hk, a.wk, k0r, k0c, rmap, cmap);
     __syncthreads();
-    inv_load<TAPS, TT>(tid, a.lvl + (int64_t)plane * 4 * a.hk * a.wk, a.hk, a.wk, a.zero_approx != 0, sb, rmap,
-                       cmap);
+    {
+        InvStage<TAPS, TT> st;
+        st.offsets(tid, a.wk, rmap, cmap);
+        st.fetch(a.lvl + (int64_t)plane * 4 * a.hk * a.wk, (int64_t)a.hk * a.wk, a.zero_approx != 0);
+        st.put(sb);
+    }
     __syncthreads();
     inv_cols<TAPS, TT>(tid, sb, lo1, hi1, f);
     __syncthreads();
@@ -474,6 +483,12 @@ __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, floa
             sbb[k][u] = 0.0;
             ka[k][u] = kc_[k][u] = kb[k][u] = kbc[k][u] = 0.f;
         }
+    // subband loads of frame fr + 1 are in flight while frame fr is transformed
+    __syncthreads();  // maps ready
+    InvStage<TAPS, TT> st;
+    st.offsets(tid, a.wk, rmap, cmap);
+    const int64_t band = (int64_t)a.hk * a.wk;
+    st.fetch(a.lvl + (int64_t)c * 4 * band, band, a.zero_approx != 0);
     for (int fr = 0; fr < a.nb; ++fr) {
         // this frame's SDA means, loaded ahead of the subband staging (kept
         // in registers only where a thread owns a single row quad)
@@ -491,11 +506,11 @@ __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, floa
                 Iv[k][u] = (y >= 0 && y < H && xx >= 0 && xx < W) ? Ip[(int64_t)y * W + xx] : 0.f;
             }
         }
-        __syncthreads();  // maps ready / previous frame's LDS reads done
-        const int tf = opaque_tid();  // index arithmetic per frame, not live across the frame loop
-        inv_load<TAPS, TT>(tf, a.lvl + (int64_t)(fr * C + c) * 4 * a.hk * a.wk, a.hk, a.wk, a.zero_approx != 0,
-                           sb, rmap, cmap);
+        __syncthreads();  // previous frame's LDS reads done
+        st.put(sb);
         __syncthreads();
+        if (fr + 1 < a.nb) st.fetch(a.lvl + (int64_t)((fr + 1) * C + c) * 4 * band, band, a.zero_approx != 0);
+        const int tf = opaque_tid();  // index arithmetic per frame, not live across the frame loop
         inv_cols<TAPS, TT>(tf, sb, lo1, hi1, f);
         __syncthreads();
 #pragma unroll

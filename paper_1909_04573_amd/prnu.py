@@ -517,6 +517,20 @@ def set_tile(kind: int, taps: int, hk: int, wk: int, tile: int):
     _check(lib().prnu_set_tile(int(kind), int(taps), int(hk), int(wk), int(tile)))
 
 
+def set_tiles(H: int, W: int, tiles, taps: int = 16, levels: int = 4):
+    """Applies a list in autotune's layout (forward 1..4, -, inverse 2..4, MLE)
+    to the level geometries of H x W frames; 0 entries are left as they are."""
+    Hp, Wp = -(-int(H) // 16) * 16, -(-int(W) // 16) * 16
+    for l in range(1, levels + 1):
+        if tiles[l - 1]:
+            set_tile(TILE_FWD, taps, Hp >> l, Wp >> l, tiles[l - 1])
+    for l in range(2, levels + 1):
+        if tiles[4 + l - 1]:
+            set_tile(TILE_INV, taps, Hp >> l, Wp >> l, tiles[4 + l - 1])
+    if tiles[8]:
+        set_tile(TILE_MLE, taps, Hp >> 1, Wp >> 1, tiles[8])
+
+
 def autotune(H: int, W: int, C: int = 1, params: DenoiseParams | None = None, device="cuda"):
     """Times both tile sizes of every level kernel for H x W x C frames and keeps
     the faster; returns the 12 choices (forward 1..4, inverse 1..4, MLE)."""

@@ -133,3 +133,19 @@ def test_autotune_workspace(lib):
     assert lib.prnu_autotune_workspace_size(1080, 1920, 2, ctypes.byref(p), ctypes.byref(n)) == prnu.PRNU_E_INVAL
     assert lib.prnu_autotune(1080, 1920, 1, ctypes.byref(p), ctypes.c_void_p(0x40000000), 16, None, None) == \
         prnu.PRNU_E_WORKSPACE
+
+
+def test_set_tiles_layout(lib):
+    """set_tiles applies autotune's layout: forward levels 1..4, inverse 2..4, MLE."""
+    tiles = [16, 32, 16, 32, 0, 32, 16, 32, 16, 0, 0, 0]
+    try:
+        prnu.set_tiles(1080, 1920, tiles)
+        Hp, Wp = 1088, 1920
+        assert [prnu.get_tile(prnu.TILE_FWD, 16, Hp >> l, Wp >> l) for l in range(1, 5)] == tiles[0:4]
+        assert [prnu.get_tile(prnu.TILE_INV, 16, Hp >> l, Wp >> l) for l in range(2, 5)] == tiles[5:8]
+        assert prnu.get_tile(prnu.TILE_MLE, 16, Hp >> 1, Wp >> 1) == 16
+        assert prnu.get_tile(prnu.TILE_INV, 16, Hp >> 1, Wp >> 1) == 32  # untouched: entry 4 is unused
+    finally:
+        for l in range(1, 5):
+            for kind in (prnu.TILE_FWD, prnu.TILE_INV, prnu.TILE_MLE):
+                prnu.set_tile(kind, 16, 1088 >> l, 1920 >> l, 0)
