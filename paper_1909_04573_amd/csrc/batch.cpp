@@ -181,13 +181,6 @@ Layout plan_layout(const prnu_camera *cams, int n, const prnu_denoise_params *p,
     return L;
 }
 
-int device_cus() {
-    int dev = 0, n = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 256;
-    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) return 256;
-    return n;
-}
-
 // Builds the tables (host blob mirrored at ws) and the launch list.
 int build(const prnu_camera *cams, int n, int dtype, const prnu_denoise_params *p, int acc_mode, int flags,
           const Layout &L, char *ws, std::vector<char> *blob, prnu_batch *b) {

@@ -89,80 +89,104 @@ __device__ __forceinline__ int map_index(int p, int n, int off, int stored) {
 }
 
 // ---------------------------------------------------------------------------
-// Forward level body: subband tile `tile` of plane `plane`.
+// Forward level: staging of a tile's input samples.  maps() writes the
+// periodic/reflected source row and column of every tile sample to LDS;
+// fetch() issues the tile's global loads into registers (pairs of contiguous
+// samples where the tile's columns need neither the periodic wrap nor the
+// reflection, single samples otherwise); put() stores them to LDS.  Threads
+// form CX columns x RY rows: a thread looks up its column offsets once and one
+// row offset per row it reads, so each load costs an address add, and every
+// load of a thread is issued before the first LDS store.  Splitting fetch and
+// put keeps the register staging separate from the LDS layout.
 template <int TAPS, int TT>
-__device__ __forceinline__ void fwd_body(const FwdArgs &a, int tile, int plane, float *lds, const Filter &f) {
+struct FwdStage {
+    using G = FwdGeom<TAPS, TT>;
+    static constexpr int NTH = fwd_nt(TT), IN = G::IN, INS = G::INS, IN2 = IN / 2;
+    static constexpr int CXF = IN2 <= 32 ? 32 : 64, RYF = NTH / CXF, NRGF = (IN + RYF - 1) / RYF;
+    static constexpr int CXS = 32, RYS = NTH / CXS, NCGS = (IN + CXS - 1) / CXS, NRGS = (IN + RYS - 1) / RYS;
+    static constexpr int NV = 2 * NRGF > NRGS * NCGS ? 2 * NRGF : NRGS * NCGS;
+    float v[NV];
+    bool fast;
+
+    static __device__ __forceinline__ void maps(const FwdArgs &a, int tile, int tid, int *rmap, int *cmap) {
+        const int tr = tile / a.tiles_c, tc = tile - (tile / a.tiles_c) * a.tiles_c;
+        if (tid < IN)
+            rmap[tid] = map_index(2 * (tr * TT - HALO) + tid, a.n_r, a.off_r, a.src_rows);
+        else if (tid < 2 * IN)
+            cmap[tid - IN] = map_index(2 * (tc * TT - HALO) + tid - IN, a.n_c, a.off_c, a.src_cols);
+    }
+    __device__ __forceinline__ void fetch(const FwdArgs &a, int tile, int plane, int tid, const int *rmap,
+                                          const int *cmap) {
+        const int tc = tile - (tile / a.tiles_c) * a.tiles_c;
+        const PRNU_GLOBAL float *sp = gmem(a.src) + (int64_t)plane * a.src_stride;
+        const int c_src0 = 2 * (tc * TT - HALO) - a.off_c;
+        fast = c_src0 >= 0 && c_src0 + IN <= a.src_cols && (c_src0 & 1) == 0 && (a.src_cols & 1) == 0 &&
+               (a.src_stride & 1) == 0;
+        if (fast) {
+            const int tx = tid % CXF, ty = tid / CXF;
+            const PRNU_GLOBAL float *cp0 = sp + c_src0 + 2 * tx;
+#pragma unroll
+            for (int i = 0; i < NRGF; ++i) {
+                const int r = ty + i * RYF;
+                if (tx < IN2 && r < IN) {
+                    const float2 t = ld2(cp0 + (int64_t)rmap[r] * a.src_cols);
+                    v[2 * i] = t.x;
+                    v[2 * i + 1] = t.y;
+                }
+            }
+        } else {
+            const int tx = tid % CXS, ty = tid / CXS;
+            int coff[NCGS];
+#pragma unroll
+            for (int g = 0; g < NCGS; ++g) coff[g] = tx + g * CXS < IN ? cmap[tx + g * CXS] : 0;
+#pragma unroll
+            for (int i = 0; i < NRGS; ++i) {
+                const int r = ty + i * RYS;
+                const PRNU_GLOBAL float *rp = sp + (int64_t)(r < IN ? rmap[r] : 0) * a.src_cols;
+#pragma unroll
+                for (int g = 0; g < NCGS; ++g)
+                    if (r < IN && tx + g * CXS < IN) v[i * NCGS + g] = rp[coff[g]];
+            }
+        }
+    }
+    __device__ __forceinline__ void put(float *tbuf, int tid) const {
+        if (fast) {
+            const int tx = tid % CXF, ty = tid / CXF;
+#pragma unroll
+            for (int i = 0; i < NRGF; ++i) {
+                const int r = ty + i * RYF;
+                if (tx < IN2 && r < IN)
+                    *reinterpret_cast<float2 *>(&tbuf[r * INS + 2 * tx]) = make_float2(v[2 * i], v[2 * i + 1]);
+            }
+        } else {
+            const int tx = tid % CXS, ty = tid / CXS;
+#pragma unroll
+            for (int i = 0; i < NRGS; ++i)
+#pragma unroll
+                for (int g = 0; g < NCGS; ++g) {
+                    const int r = ty + i * RYS;
+                    if (r < IN && tx + g * CXS < IN) tbuf[r * INS + tx + g * CXS] = v[i * NCGS + g];
+                }
+        }
+    }
+};
+
+// Forward level work on a staged tile (`tile` of plane `plane`, input samples
+// in LDS): row pass, column pass, Wiener shrinkage of the detail bands.
+template <int TAPS, int TT>
+__device__ __forceinline__ void fwd_compute(const FwdArgs &a, int tile, int plane, float *lds, const Filter &f) {
     using G = FwdGeom<TAPS, TT>;
     constexpr int NTH = fwd_nt(TT);
     constexpr int IN = G::IN, INS = G::INS, NC = G::NC;
     float *tbuf = lds;           // input samples; later squares + core coefficients
     float *rlo = lds + G::TILE;  // row low-pass
     float *rhi = rlo + G::RL;    // row high-pass
-    int *rmap = reinterpret_cast<int *>(rhi + G::RL);
-    int *cmap = rmap + IN;
-
     const int hk = a.n_r >> 1, wk = a.n_c >> 1;
     const int tr = tile / a.tiles_c, tc = tile - (tile / a.tiles_c) * a.tiles_c;
     const int k0r = tr * TT, k0c = tc * TT;
-    const PRNU_GLOBAL float *sp = gmem(a.src) + (int64_t)plane * a.src_stride;
     PRNU_GLOBAL float *op = gmem(a.out) + (int64_t)plane * 4 * hk * wk;
     const int64_t band = (int64_t)hk * wk;
     const int tid = opaque_tid();
-
-    if (tid < IN)
-        rmap[tid] = map_index(2 * (k0r - HALO) + tid, a.n_r, a.off_r, a.src_rows);
-    else if (tid < 2 * IN)
-        cmap[tid - IN] = map_index(2 * (k0c - HALO) + tid - IN, a.n_c, a.off_c, a.src_cols);
-    __syncthreads();
-
-    // Stage the input tile: pairs of contiguous samples where the tile's
-    // columns need neither the periodic wrap nor the reflection, single
-    // samples otherwise.  Threads form CX columns x RY rows; a thread looks up
-    // its column offsets once and one row offset per row it reads, so each
-    // load costs an address add.  Every load of a thread is issued before the
-    // first LDS store, so the whole tile is in flight at once.
-    const int c_src0 = 2 * (k0c - HALO) - a.off_c;
-    const bool cfast = c_src0 >= 0 && c_src0 + IN <= a.src_cols && (c_src0 & 1) == 0 && (a.src_cols & 1) == 0 &&
-                       (a.src_stride & 1) == 0;
-    if (cfast) {
-        constexpr int IN2 = IN / 2, CX = IN2 <= 32 ? 32 : 64, RY = NTH / CX, NRG = (IN + RY - 1) / RY;
-        const int tx = tid % CX, ty = tid / CX;
-        const PRNU_GLOBAL float *cp0 = sp + c_src0 + 2 * tx;
-        float2 v[NRG];
-#pragma unroll
-        for (int i = 0; i < NRG; ++i) {
-            const int r = ty + i * RY;
-            if (tx < IN2 && r < IN) v[i] = ld2(cp0 + (int64_t)rmap[r] * a.src_cols);
-        }
-#pragma unroll
-        for (int i = 0; i < NRG; ++i) {
-            const int r = ty + i * RY;
-            if (tx < IN2 && r < IN) *reinterpret_cast<float2 *>(&tbuf[r * INS + 2 * tx]) = v[i];
-        }
-    } else {
-        constexpr int CX = 32, RY = NTH / CX, NCG = (IN + CX - 1) / CX, NRG = (IN + RY - 1) / RY;
-        const int tx = tid % CX, ty = tid / CX;
-        int coff[NCG];
-#pragma unroll
-        for (int g = 0; g < NCG; ++g) coff[g] = tx + g * CX < IN ? cmap[tx + g * CX] : 0;
-        float v[NRG][NCG];
-#pragma unroll
-        for (int i = 0; i < NRG; ++i) {
-            const int r = ty + i * RY;
-            const PRNU_GLOBAL float *rp = sp + (int64_t)(r < IN ? rmap[r] : 0) * a.src_cols;
-#pragma unroll
-            for (int g = 0; g < NCG; ++g)
-                if (r < IN && tx + g * CX < IN) v[i][g] = rp[coff[g]];
-        }
-#pragma unroll
-        for (int i = 0; i < NRG; ++i)
-#pragma unroll
-            for (int g = 0; g < NCG; ++g) {
-                const int r = ty + i * RY;
-                if (r < IN && tx + g * CX < IN) tbuf[r * INS + tx + g * CX] = v[i][g];
-            }
-    }
-    __syncthreads();
 
     // Rows: lo/hi along axis 1, four coefficients per item, 16-byte LDS traffic.
     constexpr int NQ = NC / 4;
@@ -285,6 +309,22 @@ __device__ __forceinline__ void fwd_body(const FwdArgs &a, int tile, int plane, 
         };
         wiener_column<TT / 2>(half * (TT / 2), kcl, s2, load, emit);
     }
+}
+
+// Forward level body: subband tile `tile` of plane `plane`.
+template <int TAPS, int TT>
+__device__ __forceinline__ void fwd_body(const FwdArgs &a, int tile, int plane, float *lds, const Filter &f) {
+    using G = FwdGeom<TAPS, TT>;
+    int *rmap = reinterpret_cast<int *>(lds + G::TILE + 2 * G::RL);
+    int *cmap = rmap + G::IN;
+    const int tid = opaque_tid();
+    FwdStage<TAPS, TT>::maps(a, tile, tid, rmap, cmap);
+    __syncthreads();
+    FwdStage<TAPS, TT> st;
+    st.fetch(a, tile, plane, tid, rmap, cmap);
+    st.put(lds, tid);
+    __syncthreads();
+    fwd_compute<TAPS, TT>(a, tile, plane, lds, f);
 }
 
 // ---------------------------------------------------------------------------
@@ -712,6 +752,20 @@ int occupancy_of(K kernel, int threads = NT) {
 }
 
 }  // namespace
+
+int device_cus() {
+    static std::mutex mu;
+    static std::map<int, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 256;
+    cache[dev] = n;
+    return n;
+}
 
 int tile_choice(int kind, int taps, int hk, int wk) {
     std::lock_guard<std::mutex> lk(g_tile_mu);

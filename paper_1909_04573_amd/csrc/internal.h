@@ -153,6 +153,8 @@ hipError_t launch_zero_ints(int *p, int n, hipStream_t s);
 hipError_t launch_fill_pattern(float *x, int64_t n, hipStream_t s);
 // Resident workgroups per CU of each batched kernel (for the persistent grid).
 int fwd_multi_occupancy(int taps, int tt);
+// compute units of the current device (cached per device)
+int device_cus();
 int inv_multi_occupancy(int taps, int tt);
 int mle_multi_occupancy(int taps, int tt, int acc_mode);
 
