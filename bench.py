@@ -12,12 +12,19 @@ HBM before timing.  One step is one pass of the whole path:
   pce_match of the 200 queries against the 16 fingerprints (4 per depth)
 
 The printed JSON line's value is the step's denoised Mpix/s (every SDA frame
-and query plane that went through the denoiser); fingerprints/s, input Mpix/s
-and the SDA-vs-per-frame speedup per depth are in "detail".  The roofline
-entry is the dominant kernel's algorithmic bytes over its event-timed launch
-durations in the timed region; cpu_baseline times the FP64 oracle on a
-bounded sample of the same workload and also gives the GPU path's error
-against it.
+and query plane that went through the denoiser), timed over K steps between
+two events; fingerprints/s, input Mpix/s, the SDA-vs-per-frame speedup per
+depth at equal frames and at equal mean matched PCE are in "detail".  A
+second pass of the same K steps brackets every kernel launch with events: the
+roofline entry is the dominant kernel's algorithmic arithmetic (or bytes, for
+a kernel limited by HBM) over its average launch duration there, beside the
+calibrated HBM counter traffic while the kernel sources match the profiled
+ones.  cpu_baseline times the FP64 oracle on a bounded sample of the same
+workload and also gives the GPU path's error against it.
+
+Other workloads (--workload): batched, diff, stills-precision and
+copy-calibration (plain 1 GiB device copies, the reference for the HBM byte
+counters).
 """
 from __future__ import annotations
 
@@ -36,6 +43,13 @@ if ROOT not in sys.path:
 
 METRIC = "denoised Mpix/s & fingerprints/s, SDA vs per-frame, 1080p video; PCE err vs FP64"
 HBM_PEAK_GBS = 8000.0
+# FP32 vector arithmetic without packed-FP32 instructions (the build disables
+# them): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
+VALU_PEAK_TFLOPS = 78.6
+MFMA_F32_PEAK_TFLOPS = 157.3  # dense FP32 matrix cores
+# kernels limited by their arithmetic (measured: VALU or matrix-core issue, not HBM)
+ALU_KERNELS = ("dwt_fwd_wiener", "dwt_inv", "batch_fwd_wiener", "batch_inv", "dwt_mle", "batch_inv_mle")
+MFMA_KERNELS = ("pce_direct_mfma",)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -56,8 +70,6 @@ def parse():
                          "reports, e.g. to profile the configuration a bench run chose")
     ap.add_argument("--curve-step", type=int, default=25,
                     help="video: frame-count grid of the conventional accuracy curve (0: skip it)")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain 1 GiB device copy (reference for HBM counters)")
     ap.add_argument("--workload", choices=["video", "stills-precision", "batched", "diff", "copy-calibration"],
                     default="video",
                     help="video: the headline benchmark; stills-precision: the accumulator/storage "
@@ -85,6 +97,41 @@ def host_cpu_model() -> str:
     except OSError:
         pass
     return platform.machine()
+
+
+def roofline_block(timing, steps, use_traffic=True):
+    """Roofline entry of the dominant kernel (largest total time) and the
+    per-kernel table, from prnu.timing_report() over `steps` steps."""
+    name, (launches, kms, kbytes, kflops) = max(timing.items(), key=lambda kv: kv[1][1])
+    dur = kms / launches / 1e3  # seconds per launch
+    gbs = kbytes / launches / dur / 1e9
+    bound = "hbm"
+    if kflops > 0 and name.startswith(MFMA_KERNELS):
+        bound = "mfma"
+    elif kflops > 0 and name.startswith(ALU_KERNELS):
+        bound = "alu"
+    if bound == "hbm":
+        achieved, peak, unit = gbs, HBM_PEAK_GBS, "GB/s"
+    else:
+        achieved = kflops / launches / dur / 1e12
+        peak, unit = (MFMA_F32_PEAK_TFLOPS if bound == "mfma" else VALU_PEAK_TFLOPS), "TFLOP/s"
+    traffic = None
+    if use_traffic and os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            tr = json.load(fh)
+        rec = tr.get(name)
+        if rec and rec.get("source_hash") == kernel_source_hash():
+            traffic = rec.get("bytes_per_launch")
+    roof = {"bound": bound, "kernel": name, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+            "frac": round(achieved / peak, 4), "traffic": traffic, "launches": launches,
+            "avg_launch_us": round(dur * 1e6, 2), "algorithmic_bytes_per_launch": round(kbytes / launches),
+            "algorithmic_flops_per_launch": round(kflops / launches), "hbm_gbs": round(gbs, 1),
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    kernels = {k: {"launches": n, "ms_per_step": ms / steps, "avg_us": ms / n * 1e3,
+                   "gbs": (b / (ms / 1e3) / 1e9) if ms > 0 else None,
+                   "tflops": (fl / (ms / 1e3) / 1e12) if ms > 0 and fl > 0 else None}
+               for k, (n, ms, b, fl) in sorted(timing.items(), key=lambda kv: -kv[1][1])}
+    return roof, kernels
 
 
 def kernel_source_hash() -> str:
@@ -285,32 +332,7 @@ def main():
         equal_pce = {"frames": ns, "conventional_matched_pce_mean": curve}
 
     # ---------------------------------------------------------------- roofline
-    dom = max(timing.items(), key=lambda kv: kv[1][1])
-    name, (launches, kms, kbytes) = dom
-    achieved = (kbytes / launches) / (kms / launches / 1e3) / 1e9
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as fh:
-            tr = json.load(fh)
-        rec = tr.get(name)
-        if rec and rec.get("source_hash") == kernel_source_hash():
-            traffic = rec.get("bytes_per_launch")
-    roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "launches": launches, "avg_launch_us": round(kms / launches * 1e3, 2),
-                "algorithmic_bytes_per_launch": round(kbytes / launches)}
-    kernels = {k: {"launches": n, "ms_per_step": ms / args.steps, "avg_us": ms / n * 1e3,
-                   "gbs": (b / (ms / 1e3) / 1e9) if ms > 0 else None}
-               for k, (n, ms, b) in sorted(timing.items(), key=lambda kv: -kv[1][1])}
-
-    if args.copy_calibration:
-        n = 1 << 28  # 1 GiB of float32
-        src = torch.ones(n, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log("copy calibration: 3 x 1 GiB device copies done")
+    roofline, kernels = roofline_block(timing, args.steps)
 
     # ---------------------------------------------------------------- oracle baseline
     cpu = None
@@ -677,15 +699,7 @@ def batched_main(args):
     timing = prnu.timing_report()
     prnu.timing_enable(False)
     plain.close()
-    dom = max(timing.items(), key=lambda kv: kv[1][1])
-    name, (launches, kms, kbytes) = dom
-    achieved = (kbytes / launches) / (kms / launches / 1e3) / 1e9
-    roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "launches": launches, "avg_launch_us": round(kms / launches * 1e3, 2),
-                "algorithmic_bytes_per_launch": round(kbytes / launches)}
-    kernels = {k: {"launches": n, "ms": ms, "avg_us": ms / n * 1e3, "gbs": (b / (ms / 1e3) / 1e9) if ms > 0 else None}
-               for k, (n, ms, b) in sorted(timing.items(), key=lambda kv: -kv[1][1])}
+    roofline, kernels = roofline_block(timing, 1, use_traffic=False)
 
     # PCE matrix summary
     _, pce_t, peak_t = recs[-1]
@@ -826,16 +840,7 @@ def diff_main(args):
     log(f"timed {args.steps} steps: {ms_per_step:.1f} ms/step, loss {L:.4f}, grad {g.tolist()}")
     patches = ncam * (nfp + nq)
     value = patches * H * W / (ms_per_step / 1e3) / 1e6
-    dom = max(timing.items(), key=lambda kv: kv[1][1])
-    name, (launches, kms, kbytes) = dom
-    achieved = (kbytes / launches) / (kms / launches / 1e3) / 1e9
-    roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "launches": launches, "avg_launch_us": round(kms / launches * 1e3, 2),
-                "algorithmic_bytes_per_launch": round(kbytes / launches)}
-    kernels = {k: {"launches": n, "ms_per_step": ms / args.steps, "avg_us": ms / n * 1e3,
-                   "gbs": (b / (ms / 1e3) / 1e9) if ms > 0 else None}
-               for k, (n, ms, b) in sorted(timing.items(), key=lambda kv: -kv[1][1])}
+    roofline, kernels = roofline_block(timing, args.steps, use_traffic=False)
     # short ascent (untimed)
     theta = theta0.clone()
     gaps = []
@@ -848,12 +853,12 @@ def diff_main(args):
     # oracle: loss and gradient on a bounded sample (2 cameras, 8 + 2 patches each)
     cpu, err = None, None
     if not args.no_cpu_baseline:
-        sc, sf, sq = 2, 8, 2
+        sc, sf, sq = ncam, nfp, nq  # the whole workload: about 10-15 s of FP64 NumPy on one core
         c32 = [cams_np[c, :sf].astype(np.float32).astype(np.float64) for c in range(sc)]
         q_idx = [c * nq + k for c in range(sc) for k in range(sq)]
         q32 = qs_np[q_idx].astype(np.float32).astype(np.float64)
         qcs = [qc[i] for i in q_idx]
-        log("oracle: gap loss and gradient on 2 cameras x (8 + 2) patches")
+        log(f"oracle: gap loss and gradient on {sc} cameras x ({sf} + {sq}) patches")
         t1 = time.perf_counter()
         Lr, gr, _ = adjoint.gap_loss(theta0.numpy(), c32, q32, qcs, d=d)
         t_or = time.perf_counter() - t1
@@ -864,8 +869,8 @@ def diff_main(args):
         gs = th.grad.numpy()
         npx = (sc * sf + len(q_idx)) * H * W
         cpu = {"value": round(npx / t_or / 1e6, 4), "unit": "Mpix/s", "cores": 1, "kind": "oracle",
-               "sample": f"2 cameras x ({sf} patches at depth {d} + {sq} queries) of 512x512: loss and "
-                         f"gradient, FP64 NumPy, {t_or:.1f} s",
+               "sample": f"{sc} cameras x ({sf} patches at depth {d} + {sq} queries) of 512x512 (the whole "
+                         f"step): loss and gradient, FP64 NumPy, {t_or:.1f} s",
                "host": host_cpu_model(), "host_cpu_count": os.cpu_count()}
         err = {"loss_gpu": float(Ls.detach()), "loss_oracle": float(Lr),
                "loss_rel_err": float(abs(float(Ls.detach()) - Lr) / abs(Lr)),

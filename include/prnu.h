@@ -341,9 +341,10 @@ int prnu_autotune(int H, int W, int C, const prnu_denoise_params *p, void *ws, s
  * prnu_timing_enable(1) discards earlier records and brackets every later
  * kernel launch with a pair of HIP events on the launch's stream; (0) stops.
  * prnu_timing_report() waits for the recorded events and writes one line per
- * kernel name: "name<TAB>launches<TAB>total_ms<TAB>algorithmic_bytes", where
- * the bytes are what the algorithm must read once and write once for those
- * launches.  `needed` (nullable) receives the text size including the NUL;
+ * kernel name: "name<TAB>launches<TAB>total_ms<TAB>algorithmic_bytes<TAB>
+ * algorithmic_flops", where the bytes are what the algorithm must read once
+ * and write once for those launches and the flops its arithmetic (0 for pure
+ * data movement).  `needed` (nullable) receives the text size including the NUL;
  * PRNU_E_INVAL if `len` is too small (the text is truncated).
  */
 int prnu_timing_enable(int on);

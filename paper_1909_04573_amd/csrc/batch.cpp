@@ -27,6 +27,7 @@ struct prnu_batch {
         float *fill = nullptr;
         int64_t nfill = 0;
         double bytes = 0;  // algorithmic bytes (inputs read once, outputs written once)
+        double flops = 0;  // algorithmic arithmetic
     };
     std::vector<Launch> launches;
     prnu::Filter f;
@@ -273,14 +274,14 @@ int build(const prnu_camera *cams, int n, int dtype, const prnu_denoise_params *
                 char *tab = blob->data() + toff;
                 int nd = 0;
                 int64_t blk = 0;
-                double bytes = 0;
+                double bytes = 0, flops = 0;
                 for (int k = 0; k < nj; ++k) {
                     const prnu_camera &c = cams[r[k].cam];
                     const int Hp = padded(c.H), Wp = padded(c.W);
                     const int hk = Hp >> level, wk = Wp >> level;
                     if (stage_tt(kind_tk, taps, hk, wk) != tt || nd == cnt) continue;
                     const int tiles = tiles_for(tt, hk, wk);
-                    const int planes = make(k, tt, tab + nd * dsz, blk, &bytes);
+                    const int planes = make(k, tt, tab + nd * dsz, blk, &bytes, &flops);
                     blk += (int64_t)tiles * planes;
                     ++nd;
                 }
@@ -295,6 +296,7 @@ int build(const prnu_camera *cams, int n, int dtype, const prnu_denoise_params *
                 la.total = blk;
                 la.ctr = ctr + ci++;
                 la.bytes = bytes;
+                la.flops = flops;
                 const int occ = kind == Launch::FWD   ? fwd_multi_occupancy(taps, tt)
                                 : kind == Launch::INV ? inv_multi_occupancy(taps, tt)
                                                       : mle_multi_occupancy(taps, tt, acc_mode);
@@ -306,7 +308,7 @@ int build(const prnu_camera *cams, int n, int dtype, const prnu_denoise_params *
         };
         for (int l = 1; l <= lv; ++l) {
             const float s2 = p->level_weight[l - 1] * s0;
-            auto mk = [&](int k, int tt, char *dst, int64_t blk0, double *bytes) {
+            auto mk = [&](int k, int tt, char *dst, int64_t blk0, double *bytes, double *flops) {
                 const prnu_camera &c = cams[r[k].cam];
                 const int Hp = padded(c.H), Wp = padded(c.W);
                 const int planes = r[k].ng * c.C;
@@ -326,12 +328,13 @@ int build(const prnu_camera *cams, int n, int dtype, const prnu_denoise_params *
                 std::memcpy(dst, &d, sizeof d);
                 *bytes += 4.0 * planes *
                           ((double)d.a.src_rows * d.a.src_cols + (d.a.write_ll ? 4.0 : 3.0) * (Hp >> l) * (Wp >> l));
+                *flops += (double)planes * d.a.n_r * d.a.n_c * fwd_flops_per_px(taps);
                 return planes;
             };
             PRNU_TRY(emit_stage(mk, sizeof(FwdDesc), TK_FWD, l, Launch::FWD));
         }
         for (int l = lv; l >= 2; --l) {
-            auto mk = [&](int k, int tt, char *dst, int64_t blk0, double *bytes) {
+            auto mk = [&](int k, int tt, char *dst, int64_t blk0, double *bytes, double *flops) {
                 const prnu_camera &c = cams[r[k].cam];
                 const int Hp = padded(c.H), Wp = padded(c.W);
                 const int planes = r[k].ng * c.C;
@@ -344,12 +347,13 @@ int build(const prnu_camera *cams, int n, int dtype, const prnu_denoise_params *
                 d.block0 = blk0;
                 std::memcpy(dst, &d, sizeof d);
                 *bytes += 4.0 * planes * ((l == lv ? 3.0 : 4.0) + 4.0) * hk * wk;
+                *flops += (double)planes * 4.0 * hk * wk * inv_flops_per_px(taps);
                 return planes;
             };
             PRNU_TRY(emit_stage(mk, sizeof(InvDesc), TK_INV, l, Launch::INV));
         }
         {
-            auto mk = [&](int k, int tt, char *dst, int64_t blk0, double *bytes) {
+            auto mk = [&](int k, int tt, char *dst, int64_t blk0, double *bytes, double *flops) {
                 const prnu_camera &c = cams[r[k].cam];
                 const int Hp = padded(c.H), Wp = padded(c.W);
                 const int hk = Hp >> 1, wk = Wp >> 1;
@@ -363,6 +367,7 @@ int build(const prnu_camera *cams, int n, int dtype, const prnu_denoise_params *
                 const double accb = acc_mode == PRNU_ACC_F32 ? 16.0 : 32.0;  // A and B, read + write
                 *bytes += 4.0 * r[k].ng * c.C * ((lv == 1 ? 3.0 : 4.0) * hk * wk + (double)c.H * c.W) +
                           accb * c.C * c.H * c.W;
+                *flops += (double)r[k].ng * c.C * (4.0 * hk * wk * inv_flops_per_px(taps) + 4.0 * c.H * c.W);
                 return c.C;
             };
             PRNU_TRY(emit_stage(mk, sizeof(MleDesc), TK_MLE, 1, Launch::MLE));
@@ -393,19 +398,19 @@ int enqueue(const prnu_batch *b, hipStream_t s) {
                 break;
             }
             case Launch::FWD: {
-                KernelTimer kt(fwd_names[t32], la.bytes, s);
+                KernelTimer kt(fwd_names[t32], la.bytes, s, la.flops);
                 e = launch_fwd_multi(b->taps, la.tt, b->f, static_cast<const FwdDesc *>(la.desc), la.nd,
                                      (int)la.total, la.ctr, la.grid, s);
                 break;
             }
             case Launch::INV: {
-                KernelTimer kt(inv_names[t32], la.bytes, s);
+                KernelTimer kt(inv_names[t32], la.bytes, s, la.flops);
                 e = launch_inv_multi(b->taps, la.tt, b->f, static_cast<const InvDesc *>(la.desc), la.nd,
                                      (int)la.total, la.ctr, la.grid, s);
                 break;
             }
             case Launch::MLE: {
-                KernelTimer kt(mle_names[t32], la.bytes, s);
+                KernelTimer kt(mle_names[t32], la.bytes, s, la.flops);
                 e = launch_mle_multi(b->taps, la.tt, b->acc_mode, b->f, static_cast<const MleDesc *>(la.desc), la.nd,
                                      (int)la.total, la.ctr, la.grid, s);
                 break;

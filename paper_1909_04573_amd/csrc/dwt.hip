@@ -788,7 +788,8 @@ hipError_t launch_dwt_fwd(int taps, const Filter &f, const float *src, int64_t s
     dim3 grid((unsigned)tiles_for(tt, hk, wk), (unsigned)planes);
     const double bytes = (double)planes * 4.0 *
                          ((double)src_rows * src_cols + (write_ll ? 4.0 : 3.0) * (double)hk * wk);
-    KernelTimer kt(taps == 16 ? "dwt_fwd_wiener<16>" : "dwt_fwd_wiener<8>", bytes, s);
+    KernelTimer kt(taps == 16 ? "dwt_fwd_wiener<16>" : "dwt_fwd_wiener<8>", bytes, s,
+                   (double)planes * n_r * n_c * fwd_flops_per_px(taps));
     if (taps == 16) {
         if (tt == 16) dwt_fwd_wiener<16, 16><<<grid, fwd_nt(16), 0, s>>>(a, f);
         else dwt_fwd_wiener<16, 32><<<grid, fwd_nt(32), 0, s>>>(a, f);
@@ -808,7 +809,8 @@ hipError_t launch_dwt_inv(int taps, const Filter &f, const float *lvl, int hk, i
     const double bytes = (double)planes * 4.0 * ((zero_approx ? 3.0 : 4.0) * (double)hk * wk + outpx);
     static const char *names[2][2] = {{"dwt_inv<8,plane>", "dwt_inv<8,resid>"},
                                       {"dwt_inv<16,plane>", "dwt_inv<16,resid>"}};
-    KernelTimer kt(names[taps == 16][epi == INV_PLANE ? 0 : 1], bytes, s);
+    KernelTimer kt(names[taps == 16][epi == INV_PLANE ? 0 : 1], bytes, s,
+                   (double)planes * 4.0 * hk * wk * inv_flops_per_px(taps));
 #define PRNU_INV(TP, T_)                                                  \
     do {                                                                  \
         if (epi == INV_PLANE) dwt_inv<TP, T_, INV_PLANE><<<grid, inv_nt(T_), 0, s>>>(a, f); \
@@ -832,7 +834,8 @@ hipError_t launch_dwt_inv_mle(int taps, const Filter &f, const float *lvl, int h
     const double accb = acc_mode == PRNU_ACC_F32 ? 16.0 : 32.0;  // A and B, read + write
     const double bytes = (double)nb * C * 4.0 * ((zero_approx ? 3.0 : 4.0) * (double)hk * wk + (double)H * W) +
                          (double)C * H * W * accb;
-    KernelTimer kt(taps == 16 ? "dwt_inv_mle<16>" : "dwt_inv_mle<8>", bytes, s);
+    KernelTimer kt(taps == 16 ? "dwt_inv_mle<16>" : "dwt_inv_mle<8>", bytes, s,
+                   (double)nb * C * (4.0 * hk * wk * inv_flops_per_px(taps) + 4.0 * H * W));
 #define PRNU_MLE(TP, T_)                                                                            \
     do {                                                                                            \
         if (acc_mode == PRNU_ACC_F64) dwt_inv_mle<TP, T_, PRNU_ACC_F64><<<grid, inv_nt(T_), 0, s>>>(a, f);  \

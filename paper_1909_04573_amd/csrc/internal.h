@@ -17,7 +17,9 @@ int fail(int code, const char *fmt, ...);
 // ---- optional kernel timing (see prnu_timing_enable) ----------------------
 class KernelTimer {
    public:
-    KernelTimer(const char *name, double bytes, hipStream_t s);
+    // bytes: what the algorithm reads once and writes once; flops: its
+    // arithmetic (0 where a launch is pure data movement)
+    KernelTimer(const char *name, double bytes, hipStream_t s, double flops = 0.0);
     ~KernelTimer();
 
    private:
@@ -155,6 +157,11 @@ hipError_t launch_fill_pattern(float *x, int64_t n, hipStream_t s);
 int fwd_multi_occupancy(int taps, int tt);
 // compute units of the current device (cached per device)
 int device_cus();
+// Algorithmic arithmetic of a wavelet level, per pixel of the level's input
+// (analysis) or output (synthesis): 2 TAPS flops per pass and direction; the
+// Wiener shrinkage adds 36 per detail coefficient (3 of every 4 coefficients).
+inline double fwd_flops_per_px(int taps) { return 4.0 * taps + 0.75 * 36.0; }
+inline double inv_flops_per_px(int taps) { return 4.0 * taps; }
 int inv_multi_occupancy(int taps, int tt);
 int mle_multi_occupancy(int taps, int tt, int acc_mode);
 

@@ -651,7 +651,8 @@ hipError_t launch_pce_direct_mfma(const float *X, const double *xmean, const flo
     const int ntiles = pce_mfma_tiles(h, w);
     const int ng = (ny + MNJ - 1) / MNJ;
     // algorithmic bytes: every query pixel once, every fingerprint (and modulation) pixel once per query
-    KernelTimer kt("pce_direct_mfma", (double)nq * h * w * (4.0 + ny * (mod ? 8.0 : 4.0)), s);
+    KernelTimer kt("pce_direct_mfma", (double)nq * h * w * (4.0 + ny * (mod ? 8.0 : 4.0)), s,
+                   2.0 * (DNS * DNS + 1) * (double)nq * ny * h * w);  // 121 shifted sums and the plain sum
     pce_direct_mfma<<<dim3((unsigned)nblk, (unsigned)nq, (unsigned)ng), NT, 0, s>>>(X, xmean, Y, mod, ny, q0, h, w,
                                                                                   tiles_x, ntiles, part);
     return hipGetLastError();

@@ -17,7 +17,7 @@ namespace {
 
 struct Rec {
     const char *name;
-    double bytes;
+    double bytes, flops;
     hipEvent_t a, b;
 };
 
@@ -47,7 +47,7 @@ void recycle_all() {
 
 }  // namespace
 
-KernelTimer::KernelTimer(const char *name, double bytes, hipStream_t s) : idx_(-1), s_(s) {
+KernelTimer::KernelTimer(const char *name, double bytes, hipStream_t s, double flops) : idx_(-1), s_(s) {
     std::lock_guard<std::mutex> lk(g_mu);
     if (!g_on) return;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -55,7 +55,7 @@ KernelTimer::KernelTimer(const char *name, double bytes, hipStream_t s) : idx_(-
     hipEvent_t a = get_event(), b = get_event();
     if (!a || !b) return;
     if (hipEventRecord(a, s) != hipSuccess) return;
-    g_recs.push_back({name, bytes, a, b});
+    g_recs.push_back({name, bytes, flops, a, b});
     idx_ = (long)g_recs.size() - 1;
 }
 
@@ -81,7 +81,7 @@ extern "C" int prnu_timing_report(char *buf, size_t len, size_t *needed) {
     std::lock_guard<std::mutex> lk(prnu::g_mu);
     struct Agg {
         long n = 0;
-        double ms = 0.0, bytes = 0.0;
+        double ms = 0.0, bytes = 0.0, flops = 0.0;
     };
     std::map<std::string, Agg> agg;
     for (auto &r : prnu::g_recs) {
@@ -94,12 +94,13 @@ extern "C" int prnu_timing_report(char *buf, size_t len, size_t *needed) {
         g.n += 1;
         g.ms += ms;
         g.bytes += r.bytes;
+        g.flops += r.flops;
     }
     std::string out;
     char line[256];
     for (auto &kv : agg) {
-        snprintf(line, sizeof(line), "%s\t%ld\t%.6f\t%.0f\n", kv.first.c_str(), kv.second.n, kv.second.ms,
-                 kv.second.bytes);
+        snprintf(line, sizeof(line), "%s\t%ld\t%.6f\t%.0f\t%.0f\n", kv.first.c_str(), kv.second.n, kv.second.ms,
+                 kv.second.bytes, kv.second.flops);
         out += line;
     }
     if (needed) *needed = out.size() + 1;

@@ -337,15 +337,15 @@ def timing_enable(on: bool = True):
 
 
 def timing_report() -> dict:
-    """{kernel name: (launches, total ms, algorithmic bytes)} since timing_enable."""
+    """{kernel name: (launches, total ms, algorithmic bytes, algorithmic flops)} since timing_enable."""
     need = _S()
     _check(lib().prnu_timing_report(None, 0, ctypes.byref(need)))
     buf = ctypes.create_string_buffer(need.value + 64)
     _check(lib().prnu_timing_report(buf, len(buf), None))
     out = {}
     for line in buf.value.decode().splitlines():
-        name, n, ms, b = line.split("\t")
-        out[name] = (int(n), float(ms), float(b))
+        name, n, ms, b, fl = line.split("\t")
+        out[name] = (int(n), float(ms), float(b), float(fl))
     return out
 
 
