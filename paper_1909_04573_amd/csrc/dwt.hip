@@ -42,6 +42,8 @@ constexpr int NT = 256;  // threads per workgroup
 // twice the threads give the CU more waves to hide load and LDS latency.
 constexpr int FWD_NT32 = 512;
 constexpr int fwd_nt(int tt) { return tt == 32 ? FWD_NT32 : NT; }
+// Row parts per core column in the forward level's Wiener stage.
+constexpr int WIENER_SPLIT = 4;
 // The same for the inverse levels (32 x 32 tiles: three workgroups per CU).
 constexpr int INV_NT32 = 512;
 constexpr int inv_nt(int tt) { return tt == 32 ? INV_NT32 : NT; }
@@ -287,10 +289,12 @@ __device__ __forceinline__ void fwd_compute(const FwdArgs &a, int tile, int plan
     __syncthreads();
 
     // Wiener shrinkage of the TT x TT core of each detail band: one thread per
-    // (band, core column, half of the core rows).  Band s of q/cb is lh, hl,
-    // hh for s = 0, 1, 2, stored as subbands 1, 2, 3.
-    if (tid < 3 * 2 * TT) {
-        const int s = tid / (2 * TT), half = (tid / TT) & 1, kcl = tid & (TT - 1);
+    // (band, core column, WS-th part of the core rows), WS as large as the
+    // workgroup's threads allow up to four.  Band s of q/cb is lh, hl, hh for
+    // s = 0, 1, 2, stored as subbands 1, 2, 3.
+    constexpr int WS = WIENER_SPLIT * 3 * TT <= NTH ? WIENER_SPLIT : 2;
+    if (tid < 3 * WS * TT) {
+        const int s = tid / (WS * TT), part = (tid / TT) % WS, kcl = tid & (TT - 1);
         const float *Q = qb + s * NC * NC;
         const float *Cc = cb + s * TT * TT;
         PRNU_GLOBAL float *ob = op + (int64_t)(s + 1) * band;
@@ -307,7 +311,7 @@ __device__ __forceinline__ void fwd_compute(const FwdArgs &a, int tile, int plan
                 if (cp) cp[(int64_t)gro * wk + gco] = den > s2 ? c * __builtin_amdgcn_rcpf(den) : 0.f;
             }
         };
-        wiener_column<TT / 2>(half * (TT / 2), kcl, s2, load, emit);
+        wiener_column<TT / WS>(part * (TT / WS), kcl, s2, load, emit);
     }
 }
 
