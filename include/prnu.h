@@ -182,6 +182,23 @@ int prnu_query_residual(const void *frames, int dtype, int n, int H, int W, int 
                         size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Block gather for the block-wise PCE protocol (Sec. IV: each fingerprint
+ * and each test residual is divided into disjoint 500 x 500 blocks and
+ * corresponding blocks are correlated).
+ *
+ * src: n planes [n][H][W] fp32 (device); out: device buffer of
+ * (H/b)*(W/b)*n*b*b floats, written block-major:
+ *   out[k][p][r][c] = src[p][(k / nbc)*b + r][(k % nbc)*b + c],
+ *   nbc = W / b, k < (H / b) * nbc,
+ * so the n planes of block k are one contiguous [n][b][b] batch for
+ * prnu_pce_match.  Rows and columns past the last whole block are unused.
+ * PRNU_E_INVAL for null pointers, n < 1, H or W outside [1, 32768],
+ * b outside [1, min(H, W)], or more than 2^31 - 1 block-planes.  Enqueued on
+ * `stream`; nothing is allocated.
+ */
+int prnu_extract_blocks(const float *src, int n, int H, int W, int b, float *out, void *stream);
+
+/* ---------------------------------------------------------------------------
  * PCE / NCC matching (Sec. II-A correlation; Sec. IV uses PCE > 60).
  *
  * For every pair (q, j):  x = X[q] - mean,  y = Y'[q][j] - mean, where

@@ -77,3 +77,19 @@ def pce(X: np.ndarray, Y: np.ndarray, peak_mode: int = PEAK_FIXED_00, nbhd: int 
     ncc = float(C[0, 0]) / (nx * ny) if nx > 0 and ny > 0 else 0.0
     val = np.sign(cp) * cp * cp / energy if energy > 0 else 0.0
     return {"pce": float(val), "ncc": ncc, "peak": (py, px), "cpeak": cp, "energy": energy}
+
+
+def blocks(X: np.ndarray, b: int) -> list:
+    """The disjoint b x b blocks of a plane in row-major block order (Sec. IV
+    divides fingerprints and test residuals into 500 x 500 blocks); rows and
+    columns past the last whole block are not used."""
+    X = np.asarray(X)
+    h, w = X.shape
+    return [X[r * b:(r + 1) * b, c * b:(c + 1) * b] for r in range(h // b) for c in range(w // b)]
+
+
+def pce_blocks(X: np.ndarray, Y: np.ndarray, b: int, nbhd: int = 11) -> np.ndarray:
+    """Block-wise fixed-peak PCE of a query residual X against a fingerprint
+    term Y (Sec. IV): block k of X correlated with block k of Y, each block a
+    field of its own (zero-mean, circular).  Returns one PCE per block."""
+    return np.array([pce(x, y, PEAK_FIXED_00, nbhd)["pce"] for x, y in zip(blocks(X, b), blocks(Y, b))])

@@ -662,6 +662,19 @@ int prnu_query_residual(const void *frames, int dtype, int n, int H, int W, int 
     return PRNU_OK;
 }
 
+int prnu_extract_blocks(const float *src, int n, int H, int W, int b, float *out, void *stream) {
+    const char *fn = "prnu_extract_blocks";
+    set_error("");
+    if (!src || !out) return fail(PRNU_E_INVAL, "%s: null pointer", fn);
+    if (n < 1) return fail(PRNU_E_INVAL, "%s: n must be >= 1", fn);
+    if (H < 1 || W < 1 || H > kMaxDim || W > kMaxDim) return fail(PRNU_E_INVAL, "%s: bad H x W", fn);
+    if (b < 1 || b > H || b > W) return fail(PRNU_E_INVAL, "%s: block side must be in [1, min(H, W)]", fn);
+    if ((int64_t)(H / b) * (W / b) * n > 0x7fffffff)
+        return fail(PRNU_E_INVAL, "%s: too many blocks x planes", fn);
+    PRNU_HIP(launch_extract_blocks(src, n, H, W, b, out, (hipStream_t)stream));
+    return PRNU_OK;
+}
+
 int prnu_pce_match_workspace_size(int nx, int ny, int h, int w, int modulated, size_t *bytes) {
     const char *fn = "prnu_pce_match_workspace_size";
     set_error("");

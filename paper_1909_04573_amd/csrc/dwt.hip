@@ -550,7 +550,10 @@ __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, floa
                 Iv[k][u] = (y >= 0 && y < H && xx >= 0 && xx < W) ? Ip[(int64_t)y * W + xx] : 0.f;
             }
         }
-        __syncthreads();  // previous frame's LDS reads done
+        // The previous frame's column pass finished reading sb before the
+        // barrier that precedes its row pass, and this frame's column pass
+        // writes lo1/hi1 only after the next barrier, which every thread
+        // reaches after its row pass: one barrier per hand-over suffices.
         st.put(sb);
         __syncthreads();
         if (fr + 1 < a.nb) st.fetch(a.lvl + (int64_t)((fr + 1) * C + c) * 4 * band, band, a.zero_approx != 0);

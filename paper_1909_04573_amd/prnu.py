@@ -31,7 +31,7 @@ EXPORTS = (
     "prnu_fingerprint_accumulate_workspace_size", "prnu_fingerprint_accumulate",
     "prnu_fingerprint_finalize_workspace_size", "prnu_fingerprint_finalize",
     "prnu_query_residual_workspace_size", "prnu_query_residual",
-    "prnu_pce_match_workspace_size", "prnu_pce_match",
+    "prnu_pce_match_workspace_size", "prnu_pce_match", "prnu_extract_blocks",
     "prnu_timing_enable", "prnu_timing_report",
     "prnu_postprocess_workspace_size", "prnu_postprocess",
     "prnu_denoise_ckpt_floats", "prnu_denoise_residual_ckpt",
@@ -101,6 +101,7 @@ def lib() -> ctypes.CDLL:
     L.prnu_pce_match_workspace_size.argtypes = [_I, _I, _I, _I, _I, ctypes.POINTER(_S)]
     L.prnu_pce_match.argtypes = [_P, _I, _P, _I, _I, _I, _P, ctypes.POINTER(PceParams), _P, _P, _P, _P,
                                  _S, _P]
+    L.prnu_extract_blocks.argtypes = [_P, _I, _I, _I, _I, _P, _P]
     L.prnu_postprocess_workspace_size.argtypes = [_I, _I, _I, _I, _I, ctypes.POINTER(_S)]
     L.prnu_postprocess.argtypes = [_P, _I, _I, _I, _I, _I, _F, _P, _P, _S, _P]
     L.prnu_denoise_ckpt_floats.argtypes = [_I, _I, _I, ctypes.POINTER(_S)]
@@ -329,6 +330,39 @@ def pce_match(X: torch.Tensor, Y: torch.Tensor, modulate: torch.Tensor | None = 
     _check(lib().prnu_pce_match(_ptr(X), nx, _ptr(Y), ny, h, w, _ptr(modulate), ctypes.byref(pp), _ptr(pce),
                                 _ptr(ncc), _ptr(peak), _ptr(ws), ws.numel(), _stream(dev)))
     return pce, ncc, peak
+
+
+def extract_blocks(x: torch.Tensor, b: int) -> torch.Tensor:
+    """Disjoint b x b blocks of planes [n][H][W] (or [H][W]), block-major
+    [(H//b)*(W//b)][n][b][b]; rows and columns past the last whole block are
+    not used."""
+    _cuda(x, "x")
+    if x.dtype != torch.float32:
+        raise ValueError("x must be float32")
+    if x.dim() == 2:
+        x = x.unsqueeze(0)
+    x = x.contiguous()
+    n, H, W = (int(v) for v in x.shape)
+    nb = (H // b) * (W // b) if b > 0 else 0
+    out = torch.empty((max(nb, 1), n, max(b, 1), max(b, 1)), dtype=torch.float32, device=x.device)
+    _check(lib().prnu_extract_blocks(_ptr(x), n, H, W, int(b), _ptr(out), _stream(x.device)))
+    return out
+
+
+def pce_blocks(X: torch.Tensor, Y: torch.Tensor, modulate: torch.Tensor | None = None, b: int = 500,
+               nbhd: int = 11):
+    """Block-wise fixed-peak PCE: query planes X [nx][H][W] against fingerprints
+    Y [ny][H][W] (optionally X's modulation [nx][H][W]), block k of a query
+    against block k of each fingerprint.  Returns float64 [nblocks][nx][ny]."""
+    Xb = extract_blocks(X, b)
+    Yb = extract_blocks(Y, b)
+    Mb = extract_blocks(modulate, b) if modulate is not None else None
+    out = []
+    for k in range(Xb.shape[0]):
+        p, _, _ = pce_match(Xb[k], Yb[k], Mb[k] if Mb is not None else None, peak_mode=PEAK_FIXED_00, nbhd=nbhd,
+                            want_ncc=False, want_peak=False)
+        out.append(p)
+    return torch.stack(out)
 
 
 def timing_enable(on: bool = True):

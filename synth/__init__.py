@@ -22,7 +22,7 @@ import numpy as np
 MASTER_SEED = 190904573
 
 # Config ids used as the first stream key.
-CFG_TINY, CFG_VIDEO, CFG_BATCH, CFG_DIFF, CFG_STILL, CFG_TEST = 0, 1, 2, 3, 4, 99
+CFG_TINY, CFG_VIDEO, CFG_BATCH, CFG_DIFF, CFG_STILL, CFG_EVAL, CFG_TEST = 0, 1, 2, 3, 4, 5, 99
 
 
 def rng(*keys: int) -> np.random.Generator:
@@ -261,4 +261,39 @@ def patch_camera(cam: int, n: int, H: int = 512, W: int = 512, k_std: float = 0.
         y, x = offs[i]
         I0 = tex[y:y + H, x:x + W]
         out[i] = I0 * (1.0 + K) + g.normal(0.0, 1.0, size=I0.shape) * np.sqrt(kappa * I0)
+    return out, K
+
+
+def eval_frames_torch(cam: int, n: int, H: int, W: int, kind: str = "flat", k_std: float = 0.0008,
+                      noise_std: float = 2.0, device="cuda", cfg: int = CFG_EVAL, first_frame: int = 0):
+    """Gray images for the attribution protocol (flat vs textured scenes),
+    drawn on the device.  'flat': a smooth field per image (a 9 x 16 grid of
+    U[100, 160] values, bicubic-upsampled); 'textured': a new texture per image
+    (U[0,1] blurred with sigma 2 px, stretched to [40, 220]).  PRNU
+    K ~ N(0, k_std^2) per camera, N(0, noise_std^2) noise, rint, clip.
+    Returns (uint8 [n][H][W][1] on device, K float64 [H][W])."""
+    import torch
+
+    K = camera_prnu((H, W), k_std, cfg, cam, 0xC0FFEE)
+    Kt = torch.from_numpy(K).to(device=device, dtype=torch.float32)
+    gen = torch.Generator(device=device)
+    gen.manual_seed((MASTER_SEED * 11 + cfg * 7919 + cam * 104729 + first_frame * 31 +
+                     (0 if kind == "flat" else 17)) % (2**63))
+    r = 8
+    x = torch.arange(-r, r + 1, device=device, dtype=torch.float32)
+    kern = torch.exp(-0.5 * (x / 2.0) ** 2)
+    kern = kern / kern.sum()
+    out = torch.empty((n, H, W, 1), dtype=torch.uint8, device=device)
+    for i in range(n):
+        if kind == "flat":
+            grid = 100.0 + 60.0 * torch.rand((1, 1, 9, 16), generator=gen, device=device)
+            I0 = torch.nn.functional.interpolate(grid, size=(H, W), mode="bicubic", align_corners=False)[0, 0]
+        else:
+            u = torch.rand((1, 1, H, W), generator=gen, device=device)
+            u = torch.nn.functional.pad(u, (r, r, r, r), mode="reflect")
+            u = torch.nn.functional.conv2d(u, kern.view(1, 1, 1, -1))
+            u = torch.nn.functional.conv2d(u, kern.view(1, 1, -1, 1))[0, 0]
+            I0 = 40.0 + 180.0 * (u - u.min()) / (u.max() - u.min())
+        I = I0 * (1.0 + Kt) + noise_std * torch.randn((H, W), generator=gen, device=device)
+        out[i, :, :, 0] = torch.round(I).clamp_(0, 255).to(torch.uint8)
     return out, K

@@ -120,3 +120,17 @@ def test_validation_rejects_before_enqueue(lib):
     assert "peak mode" in lib.prnu_last_error().decode()
     assert lib.prnu_query_residual(fake, 0, 1, 64, 64, 3, P, 16, fake, None, fake, 1 << 30,
                                    None) == prnu.PRNU_E_INVAL
+
+
+def test_extract_blocks_validation(lib):
+    fake = ctypes.c_void_p(0x1000)
+    ok = (fake, 2, 64, 80, 16, fake, None)
+    bad = [
+        (None, 2, 64, 80, 16, fake, None), (fake, 2, 64, 80, 16, None, None), (fake, 0, 64, 80, 16, fake, None),
+        (fake, 2, 0, 80, 16, fake, None), (fake, 2, 64, 80, 0, fake, None), (fake, 2, 64, 80, 65, fake, None),
+        (fake, 2, 64, 1 << 16, 16, fake, None),
+    ]
+    for args in bad:
+        assert lib.prnu_extract_blocks(*args) == prnu.PRNU_E_INVAL, args
+    assert "prnu_extract_blocks" in lib.prnu_last_error().decode()
+    assert len(ok) == 7

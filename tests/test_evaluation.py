@@ -1,0 +1,36 @@
+"""CPU checks of the attribution statistics (TPR / FPR at the PCE threshold
+of 60, ROC and its area) against hand-computed cases."""
+import numpy as np
+import pytest
+
+from paper_1909_04573_amd import evaluation as ev
+
+
+def test_rates_at_threshold():
+    assert ev.tpr([10, 61, 60, 200]) == 0.5  # strictly above 60
+    assert ev.fpr([0, 5, 70]) == pytest.approx(1 / 3)
+    assert ev.tpr([1, 2, 3], thr=1.5) == pytest.approx(2 / 3)
+
+
+def test_roc_hand_case():
+    f, t = ev.roc([5, 3], [4, 1])
+    # thresholds 5, 4, 3, 1 (descending): (0,.5) (.5,.5) (.5,1) (1,1)
+    np.testing.assert_allclose(f, [0, 0, 0.5, 0.5, 1.0])
+    np.testing.assert_allclose(t, [0, 0.5, 0.5, 1.0, 1.0])
+
+
+def test_auc_is_the_area_under_roc_and_a_rank_probability():
+    g = np.random.default_rng(3)
+    m = g.normal(2.0, 1.0, 200)
+    u = g.normal(0.0, 1.0, 300)
+    f, t = ev.roc(m, u)
+    area = float(np.sum((f[1:] - f[:-1]) * (t[1:] + t[:-1]) / 2))
+    assert ev.auc(m, u) == pytest.approx(area, abs=1e-12)
+    brute = np.mean(m[:, None] > u[None, :]) + 0.5 * np.mean(m[:, None] == u[None, :])
+    assert ev.auc(m, u) == pytest.approx(brute, abs=1e-12)
+
+
+def test_auc_extremes_and_ties():
+    assert ev.auc([3, 4], [1, 2]) == 1.0
+    assert ev.auc([1, 2], [3, 4]) == 0.0
+    assert ev.auc([1, 1], [1, 1]) == 0.5

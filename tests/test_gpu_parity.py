@@ -317,6 +317,43 @@ def test_compiled_transform_sizes(dev, h, w):
     assert_scaled(K, pipeline.finalize(A, B, pipeline.FIN_ZM | pipeline.FIN_WIENER), what=f"K {h}x{w}")
 
 
+@pytest.mark.parametrize("n,H,W,b", [(3, 37, 53, 16), (2, 1080, 1920, 500), (1, 64, 64, 64), (4, 20, 30, 1)])
+def test_extract_blocks_exact(dev, n, H, W, b):
+    """Block gather of the block-wise protocol: bit-exact copies, block-major."""
+    _log(f"extract blocks n={n} {H}x{W} b={b}")
+    g = synth.rng(synth.CFG_TEST, 6000 + H)
+    x = g.normal(0, 1, size=(n, H, W)).astype(np.float32)
+    got = down(prnu.extract_blocks(up(x, dev), b))
+    ref = np.stack([np.stack(correlate.blocks(x[p], b)) for p in range(n)], axis=1)
+    assert got.shape == ref.shape
+    np.testing.assert_array_equal(got, ref)
+
+
+def test_pce_blocks_vs_oracle(dev):
+    """Block-wise fixed-peak PCE (block k of each query against block k of each
+    fingerprint, query intensity x fingerprint) against the oracle; the pairs
+    that share noise in some blocks stand out only there."""
+    _log("block-wise PCE")
+    g = synth.rng(synth.CFG_TEST, 6100)
+    nx, ny, H, W, b = 2, 3, 600, 1100, 250
+    X = g.normal(0, 1, size=(nx, H, W)).astype(np.float32)
+    Y = g.normal(0, 1, size=(ny, H, W)).astype(np.float32)
+    mod = g.uniform(50, 200, size=(nx, H, W)).astype(np.float32)
+    for blk in (2, 5):  # query 0 and fingerprint 1 share noise in blocks 2 and 5
+        r, c = divmod(blk, W // b)
+        sl = (slice(r * b, (r + 1) * b), slice(c * b, (c + 1) * b))
+        Y[1][sl] = (0.3 * X[0][sl] / mod[0][sl] * 100 + g.normal(0, 1, size=(b, b))).astype(np.float32)
+    got = down(prnu.pce_blocks(up(X, dev), up(Y, dev), up(mod, dev), b))
+    assert got.shape == ((H // b) * (W // b), nx, ny)
+    for q in range(nx):
+        for j in range(ny):
+            ref = correlate.pce_blocks(X[q].astype(np.float64), Y[j].astype(np.float64) * mod[q], b)
+            for k in range(len(ref)):
+                assert_pce(got[k, q, j], ref[k], what=f"block {k} pce[{q},{j}]")
+    assert got[2, 0, 1] > 60 and got[5, 0, 1] > 60
+    assert abs(got[0, 0, 1]) < 60
+
+
 def test_pce_fixed_query_chunks(dev):
     """Enough pairs that the direct sums run in several chunks of queries."""
     _log("pce query chunks")

@@ -138,3 +138,38 @@ def test_matched_tiny_camera_above_threshold():
     Wu, Iu = pipeline.query_residual(other[0])
     assert correlate.pce(Wq, Iq * K)["pce"] > 60
     assert abs(correlate.pce(Wu, Iu * K)["pce"]) < 60
+
+
+# ------------------------------------------------------------------ block-wise PCE (Sec. IV protocol)
+def test_blocks_partition():
+    X = np.arange(7 * 11, dtype=np.float64).reshape(7, 11)
+    bl = correlate.blocks(X, 3)
+    assert len(bl) == 2 * 3
+    # row-major block order, remainder rows/columns dropped
+    np.testing.assert_array_equal(bl[0], X[0:3, 0:3])
+    np.testing.assert_array_equal(bl[2], X[0:3, 6:9])
+    np.testing.assert_array_equal(bl[4], X[3:6, 3:6])
+    assert sum(b.size for b in bl) == 6 * 9
+
+
+def test_pce_blocks_locates_a_planted_block():
+    """A fingerprint term that shares noise with the query in one block only
+    gives a large PCE there and chi-square-sized values elsewhere."""
+    g = np.random.default_rng(11)
+    b = 64
+    X = g.normal(0, 1, size=(2 * b, 3 * b))
+    Y = g.normal(0, 1, size=X.shape)
+    Y[b:2 * b, b:2 * b] = X[b:2 * b, b:2 * b] + 0.5 * g.normal(0, 1, size=(b, b))  # block 4
+    p = correlate.pce_blocks(X, Y, b)
+    assert p.shape == (6,)
+    assert p[4] > 1000
+    assert np.all(np.abs(np.delete(p, 4)) < 30)
+
+
+def test_pce_blocks_one_block_is_the_whole_field():
+    g = np.random.default_rng(12)
+    X = g.normal(0, 1, size=(48, 48))
+    Y = 0.3 * X + g.normal(0, 1, size=X.shape)
+    p = correlate.pce_blocks(X, Y, 48)
+    assert p.shape == (1,)
+    assert p[0] == correlate.pce(X, Y, correlate.PEAK_FIXED_00)["pce"]
