@@ -965,18 +965,25 @@ def eval_main(args):
         qcam = np.repeat(np.arange(ncam), nq)
 
         def fingerprints(select, d):
-            """K [ncam][H][W] from frames[c][select] at SDA depth d; time in ms."""
+            """K [ncam][H][W] from frames[c][select] at SDA depth d; times in ms
+            of the accumulation (SDA + denoise + MLE) and of the whole call."""
             K = torch.empty((ncam, H, W), dtype=torch.float32, device=dev)
-
-            def run():
-                for c in range(ncam):
-                    A.zero_()
-                    B.zero_()
-                    fr = frames[c, select]
-                    prnu.fingerprint_accumulate(fr if fr.is_contiguous() else fr.contiguous(), d, A, B, p, ws=ws)
-                    prnu.fingerprint_finalize(A, B, out=K[c])
-            _, ms = timed(run)
-            return K, ms
+            sel = [frames[c, select] for c in range(ncam)]
+            sel = [f if f.is_contiguous() else f.contiguous() for f in sel]
+            ev_a = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in sel]
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for c in range(ncam):
+                A.zero_()
+                B.zero_()
+                ev_a[c][0].record(stream)
+                prnu.fingerprint_accumulate(sel[c], d, A, B, p, ws=ws)
+                ev_a[c][1].record(stream)
+                prnu.fingerprint_finalize(A, B, out=K[c])
+            e1.record(stream)
+            torch.cuda.synchronize()
+            acc_ms = sum(a.elapsed_time(z) for a, z in ev_a)
+            return K, (acc_ms, e0.elapsed_time(e1))
 
         variants = {}
         for n in conv_ns:
@@ -987,25 +994,55 @@ def eval_main(args):
         if kind == "textured":
             for d in t2_ds:
                 variants[f"table2-sda{d}-50"] = fingerprints(slice(0, 50), d)
-        out = {}
-        for name, (K, ms_fp) in variants.items():
+        def block_stats(K):
             P, ms_pce = timed(lambda: prnu.pce_blocks(Wq, K, Iq, b))
             P = P.cpu().numpy()  # [nblocks][nq_total][ncam]
             matched = P[:, np.arange(len(qcam)), qcam]
             mask = np.ones(P.shape[1:], dtype=bool)
             mask[np.arange(len(qcam)), qcam] = False
-            unmatched = P[:, mask]
+            return P, matched, P[:, mask], ms_pce
+
+        out = {}
+        for name, (K, ms_fp) in variants.items():
+            P, matched, unmatched, ms_pce = block_stats(K)
             f, t = ev.roc(matched, unmatched)
             idx = np.unique(np.linspace(0, len(f) - 1, 25).astype(int))
             out[name] = {"tpr": ev.tpr(matched), "fpr": ev.fpr(unmatched), "auc": ev.auc(matched, unmatched),
                          "matched_pce_median": float(np.median(matched)),
                          "unmatched_abs_pce_max": float(np.abs(unmatched).max()),
-                         "fingerprint_ms": round(ms_fp, 2), "block_pce_ms": round(ms_pce, 2),
+                         "accumulate_ms": round(ms_fp[0], 2), "fingerprint_ms": round(ms_fp[1], 2),
+                         "block_pce_ms": round(ms_pce, 2),
                          "block_pairs": int(P.size),
                          "roc": {"fpr": [round(float(x), 4) for x in f[idx]],
                                  "tpr": [round(float(x), 4) for x in t[idx]]}}
             log(f"{kind} {name}: TPR {out[name]['tpr']:.3f} AUC {out[name]['auc']:.4f}")
         result["kinds"][kind] = out
+        if kind == "textured":
+            # fingerprint equivalence: the fewest images m an SDA-d fingerprint
+            # needs to reach the TPR of a conventional fingerprint of n images
+            eq_n = [n for n in (40, 50, 60, 80, 100) if n <= nfp]
+            eq_m = [m for m in (50, 75, 100, 125, 150, 175, 200) if m <= nfp]
+            conv = {}
+            for n in eq_n:
+                K, ms = fingerprints(slice(0, n), 1)
+                conv[n] = (ev.tpr(block_stats(K)[1]), ms)
+            eqv = {"conventional": {str(n): {"tpr": t, "accumulate_ms": round(ms[0], 2),
+                                             "fingerprint_ms": round(ms[1], 2)} for n, (t, ms) in conv.items()}}
+            for d in (5, 10):
+                sda = {}
+                for m in eq_m:
+                    K, ms = fingerprints(slice(0, m), d)
+                    sda[m] = (ev.tpr(block_stats(K)[1]), ms)
+                rows = {}
+                for n, (tn, msn) in conv.items():
+                    m_eq = next((m for m in eq_m if sda[m][0] >= tn), None)
+                    rows[str(n)] = {"sda_images": m_eq, "ratio_m_over_n": None if m_eq is None else m_eq / n,
+                                    "denoise_ratio": None if m_eq is None else round(n / math.ceil(m_eq / d), 2),
+                                    "speedup_accumulate": None if m_eq is None else round(msn[0] / sda[m_eq][1][0], 2),
+                                    "speedup_with_finalize": None if m_eq is None else round(msn[1] / sda[m_eq][1][1], 2)}
+                eqv[f"sda{d}"] = {"tpr_by_images": {str(m): v[0] for m, v in sda.items()}, "equivalent": rows}
+            result["equivalence_textured"] = eqv
+            log(f"equivalence: {json.dumps(eqv)}")
         if sample is None:
             # oracle check of the block PCEs on one query against two fingerprints
             from oracle import correlate
@@ -1020,6 +1057,24 @@ def eval_main(args):
         del frames, queries, Wq, Iq, variants
         torch.cuda.empty_cache()
     result["gpu_vs_fp64_oracle"] = sample
+
+    # variance model of Sec. III-B: residual W = I K + psi + xi, psi the noise
+    # term (averaged down by SDA) and xi the scene term; both variances from
+    # R images of one scene, then the bound m <= n (s1 + d s2) / (s1 + s2)
+    R = 16
+    model = {}
+    for kind in ("flat", "textured"):
+        fr, I0, K = synth.eval_scene_realizations(0, R, H, W, kind, device=dev)
+        Wr = prnu.denoise_residual(fr.to(torch.float32), p).double()
+        mean = Wr.mean(0)
+        s1 = float(((Wr - mean) ** 2).sum(0).mean() / (R - 1))
+        prnu_term = I0.double() * torch.from_numpy(K).to(dev)
+        s2 = max(float(((mean - prnu_term) ** 2).mean()) - s1 / R, 0.0)
+        model[kind] = {"sigma1_sq": s1, "sigma2_sq": s2,
+                       "bound_ratio": {str(d): (s1 + d * s2) / (s1 + s2) for d in (5, 10, 25, 50)}}
+        del fr, Wr
+    result["variance_model"] = model
+    log(f"variance model: {json.dumps(model)}")
     print(json.dumps(result), flush=True)
 
 

@@ -264,36 +264,68 @@ def patch_camera(cam: int, n: int, H: int = 512, W: int = 512, k_std: float = 0.
     return out, K
 
 
-def eval_frames_torch(cam: int, n: int, H: int, W: int, kind: str = "flat", k_std: float = 0.0008,
-                      noise_std: float = 2.0, device="cuda", cfg: int = CFG_EVAL, first_frame: int = 0):
-    """Gray images for the attribution protocol (flat vs textured scenes),
-    drawn on the device.  'flat': a smooth field per image (a 9 x 16 grid of
-    U[100, 160] values, bicubic-upsampled); 'textured': a new texture per image
-    (U[0,1] blurred with sigma 2 px, stretched to [40, 220]).  PRNU
-    K ~ N(0, k_std^2) per camera, N(0, noise_std^2) noise, rint, clip.
-    Returns (uint8 [n][H][W][1] on device, K float64 [H][W])."""
+def _eval_scene(gen, H: int, W: int, kind: str, device):
+    """One scene of the attribution generator: 'flat' = a 9 x 16 grid of
+    U[100, 160] values, bicubic-upsampled; 'textured' = U[0,1] blurred with
+    sigma 2 px, stretched to [40, 220]."""
     import torch
 
-    K = camera_prnu((H, W), k_std, cfg, cam, 0xC0FFEE)
-    Kt = torch.from_numpy(K).to(device=device, dtype=torch.float32)
-    gen = torch.Generator(device=device)
-    gen.manual_seed((MASTER_SEED * 11 + cfg * 7919 + cam * 104729 + first_frame * 31 +
-                     (0 if kind == "flat" else 17)) % (2**63))
+    if kind == "flat":
+        grid = 100.0 + 60.0 * torch.rand((1, 1, 9, 16), generator=gen, device=device)
+        return torch.nn.functional.interpolate(grid, size=(H, W), mode="bicubic", align_corners=False)[0, 0]
     r = 8
     x = torch.arange(-r, r + 1, device=device, dtype=torch.float32)
     kern = torch.exp(-0.5 * (x / 2.0) ** 2)
     kern = kern / kern.sum()
+    u = torch.rand((1, 1, H, W), generator=gen, device=device)
+    u = torch.nn.functional.pad(u, (r, r, r, r), mode="reflect")
+    u = torch.nn.functional.conv2d(u, kern.view(1, 1, 1, -1))
+    u = torch.nn.functional.conv2d(u, kern.view(1, 1, -1, 1))[0, 0]
+    return 40.0 + 180.0 * (u - u.min()) / (u.max() - u.min())
+
+
+def _eval_generator(cam: int, cfg: int, first_frame: int, kind: str, device):
+    import torch
+
+    gen = torch.Generator(device=device)
+    gen.manual_seed((MASTER_SEED * 11 + cfg * 7919 + cam * 104729 + first_frame * 31 +
+                     (0 if kind == "flat" else 17)) % (2**63))
+    return gen
+
+
+def eval_frames_torch(cam: int, n: int, H: int, W: int, kind: str = "flat", k_std: float = 0.0008,
+                      noise_std: float = 2.0, device="cuda", cfg: int = CFG_EVAL, first_frame: int = 0):
+    """Gray images for the attribution protocol (flat vs textured scenes, a
+    new scene per image), drawn on the device: PRNU K ~ N(0, k_std^2) per
+    camera, N(0, noise_std^2) noise, rint, clip.  Returns (uint8 [n][H][W][1]
+    on device, K float64 [H][W])."""
+    import torch
+
+    K = camera_prnu((H, W), k_std, cfg, cam, 0xC0FFEE)
+    Kt = torch.from_numpy(K).to(device=device, dtype=torch.float32)
+    gen = _eval_generator(cam, cfg, first_frame, kind, device)
     out = torch.empty((n, H, W, 1), dtype=torch.uint8, device=device)
     for i in range(n):
-        if kind == "flat":
-            grid = 100.0 + 60.0 * torch.rand((1, 1, 9, 16), generator=gen, device=device)
-            I0 = torch.nn.functional.interpolate(grid, size=(H, W), mode="bicubic", align_corners=False)[0, 0]
-        else:
-            u = torch.rand((1, 1, H, W), generator=gen, device=device)
-            u = torch.nn.functional.pad(u, (r, r, r, r), mode="reflect")
-            u = torch.nn.functional.conv2d(u, kern.view(1, 1, 1, -1))
-            u = torch.nn.functional.conv2d(u, kern.view(1, 1, -1, 1))[0, 0]
-            I0 = 40.0 + 180.0 * (u - u.min()) / (u.max() - u.min())
+        I0 = _eval_scene(gen, H, W, kind, device)
         I = I0 * (1.0 + Kt) + noise_std * torch.randn((H, W), generator=gen, device=device)
         out[i, :, :, 0] = torch.round(I).clamp_(0, 255).to(torch.uint8)
     return out, K
+
+
+def eval_scene_realizations(cam: int, R: int, H: int, W: int, kind: str = "textured", k_std: float = 0.0008,
+                            noise_std: float = 2.0, device="cuda", cfg: int = CFG_EVAL):
+    """R images of ONE scene of the attribution generator (same I0 and K,
+    independent noise), to separate the residual's noise term from its scene
+    term.  Returns (uint8 [R][H][W] on device, I0 float32 [H][W] on device,
+    K float64 [H][W])."""
+    import torch
+
+    K = camera_prnu((H, W), k_std, cfg, cam, 0xC0FFEE)
+    Kt = torch.from_numpy(K).to(device=device, dtype=torch.float32)
+    gen = _eval_generator(cam, cfg, 1 << 20, kind, device)
+    I0 = _eval_scene(gen, H, W, kind, device)
+    out = torch.empty((R, H, W), dtype=torch.uint8, device=device)
+    for i in range(R):
+        I = I0 * (1.0 + Kt) + noise_std * torch.randn((H, W), generator=gen, device=device)
+        out[i] = torch.round(I).clamp_(0, 255).to(torch.uint8)
+    return out, I0, K
