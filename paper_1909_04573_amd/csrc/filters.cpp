@@ -100,15 +100,28 @@ bool daubechies_lowpass(int taps, long double *h) {
     return true;
 }
 
+// The root finding costs milliseconds of host time, so each filter length is
+// built once per process and copied out afterwards.
 bool make_filter(int taps, Filter *f) {
     if (taps != 8 && taps != 16) return false;
-    long double h[20];
-    if (!daubechies_lowpass(taps, h)) return false;
-    std::memset(f, 0, sizeof(*f));
-    for (int k = 0; k < taps; ++k) {
-        f->h[k] = (float)h[k];
-        f->g[k] = (float)((k & 1 ? -1.0L : 1.0L) * h[taps - 1 - k]);
+    static std::mutex mu;
+    static Filter cache[2];
+    static bool ready[2] = {false, false};
+    const int slot = taps == 16;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ready[slot]) {
+        long double h[20];
+        if (!daubechies_lowpass(taps, h)) return false;
+        Filter t;
+        std::memset(&t, 0, sizeof(t));
+        for (int k = 0; k < taps; ++k) {
+            t.h[k] = (float)h[k];
+            t.g[k] = (float)((k & 1 ? -1.0L : 1.0L) * h[taps - 1 - k]);
+        }
+        cache[slot] = t;
+        ready[slot] = true;
     }
+    *f = cache[slot];
     return true;
 }
 
