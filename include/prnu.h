@@ -198,6 +198,21 @@ int prnu_query_residual(const void *frames, int dtype, int n, int H, int W, int 
  */
 int prnu_extract_blocks(const float *src, int n, int H, int W, int b, float *out, void *stream);
 
+/* Bilinear resampling for mixed-media matching (Sec. V-D: the query image is
+ * resized and cropped to the geometry of the video fingerprint before its
+ * PRNU is matched).
+ *
+ * src [n][H][W] fp32 and out [n][oh][ow] fp32, device buffers:
+ *   out[p][y][x] = bilinear(src[p], (y + oy + 0.5)/scale - 0.5, (x + ox + 0.5)/scale - 0.5)
+ * pixel-centre convention, sample coordinates clamped to the plane (edge
+ * replication); scale = output size / input size; (oy, ox) is a crop offset
+ * in output pixels.  PRNU_E_INVAL for null pointers, n outside [1, 65535],
+ * sizes outside [1, 32768], a scale that is not finite and positive, or
+ * negative offsets.  Enqueued on `stream`; nothing is allocated.
+ */
+int prnu_resample_bilinear(const float *src, int n, int H, int W, double scale, int oy, int ox, int oh, int ow,
+                           float *out, void *stream);
+
 /* ---------------------------------------------------------------------------
  * PCE / NCC matching (Sec. II-A correlation; Sec. IV uses PCE > 60).
  *

@@ -675,6 +675,20 @@ int prnu_extract_blocks(const float *src, int n, int H, int W, int b, float *out
     return PRNU_OK;
 }
 
+int prnu_resample_bilinear(const float *src, int n, int H, int W, double scale, int oy, int ox, int oh, int ow,
+                           float *out, void *stream) {
+    const char *fn = "prnu_resample_bilinear";
+    set_error("");
+    if (!src || !out) return fail(PRNU_E_INVAL, "%s: null pointer", fn);
+    if (n < 1 || n > 65535) return fail(PRNU_E_INVAL, "%s: n must be in [1, 65535]", fn);
+    if (H < 1 || W < 1 || H > kMaxDim || W > kMaxDim) return fail(PRNU_E_INVAL, "%s: bad H x W", fn);
+    if (oh < 1 || ow < 1 || oh > kMaxDim || ow > kMaxDim) return fail(PRNU_E_INVAL, "%s: bad output size", fn);
+    if (!std::isfinite(scale) || scale <= 0.0) return fail(PRNU_E_INVAL, "%s: scale must be finite and > 0", fn);
+    if (oy < 0 || ox < 0 || oy > kMaxDim || ox > kMaxDim) return fail(PRNU_E_INVAL, "%s: bad crop offset", fn);
+    PRNU_HIP(launch_resample_bilinear(src, n, H, W, scale, oy, ox, oh, ow, out, (hipStream_t)stream));
+    return PRNU_OK;
+}
+
 int prnu_pce_match_workspace_size(int nx, int ny, int h, int w, int modulated, size_t *bytes) {
     const char *fn = "prnu_pce_match_workspace_size";
     set_error("");

@@ -227,6 +227,10 @@ hipError_t launch_plane_variance(const float *x, int n, int64_t N, double *var, 
 hipError_t launch_real_to_complex(const float *x, int n, int64_t N, float2 *z, hipStream_t s);
 // G = F * rho with rho the Wiener residual factor of |F|/sqrt(hw); noise
 // variance var[p] (per plane, device) or sigma2 >= 0 (host constant).
+// Bilinear resampling of n planes [n][H][W] to [n][oh][ow] (pixel centres,
+// scale = output / input size, crop offset (oy, ox) in output pixels).
+hipError_t launch_resample_bilinear(const float *src, int n, int H, int W, double scale, int oy, int ox, int oh,
+                                    int ow, float *out, hipStream_t s);
 // Disjoint b x b blocks of n planes [n][H][W], block-major [k][n][b][b].
 hipError_t launch_extract_blocks(const float *src, int n, int H, int W, int b, float *out, hipStream_t s);
 hipError_t launch_spectral_wiener(const float2 *F, int n, int h, int w, const double *var,

@@ -31,7 +31,7 @@ EXPORTS = (
     "prnu_fingerprint_accumulate_workspace_size", "prnu_fingerprint_accumulate",
     "prnu_fingerprint_finalize_workspace_size", "prnu_fingerprint_finalize",
     "prnu_query_residual_workspace_size", "prnu_query_residual",
-    "prnu_pce_match_workspace_size", "prnu_pce_match", "prnu_extract_blocks",
+    "prnu_pce_match_workspace_size", "prnu_pce_match", "prnu_extract_blocks", "prnu_resample_bilinear",
     "prnu_timing_enable", "prnu_timing_report",
     "prnu_postprocess_workspace_size", "prnu_postprocess",
     "prnu_denoise_ckpt_floats", "prnu_denoise_residual_ckpt",
@@ -102,6 +102,7 @@ def lib() -> ctypes.CDLL:
     L.prnu_pce_match.argtypes = [_P, _I, _P, _I, _I, _I, _P, ctypes.POINTER(PceParams), _P, _P, _P, _P,
                                  _S, _P]
     L.prnu_extract_blocks.argtypes = [_P, _I, _I, _I, _I, _P, _P]
+    L.prnu_resample_bilinear.argtypes = [_P, _I, _I, _I, ctypes.c_double, _I, _I, _I, _I, _P, _P]
     L.prnu_postprocess_workspace_size.argtypes = [_I, _I, _I, _I, _I, ctypes.POINTER(_S)]
     L.prnu_postprocess.argtypes = [_P, _I, _I, _I, _I, _I, _F, _P, _P, _S, _P]
     L.prnu_denoise_ckpt_floats.argtypes = [_I, _I, _I, ctypes.POINTER(_S)]
@@ -347,6 +348,24 @@ def extract_blocks(x: torch.Tensor, b: int) -> torch.Tensor:
     out = torch.empty((max(nb, 1), n, max(b, 1), max(b, 1)), dtype=torch.float32, device=x.device)
     _check(lib().prnu_extract_blocks(_ptr(x), n, H, W, int(b), _ptr(out), _stream(x.device)))
     return out
+
+
+def resample_bilinear(x: torch.Tensor, scale: float, out_h: int, out_w: int, oy: int = 0,
+                      ox: int = 0) -> torch.Tensor:
+    """Planes [n][H][W] (or [H][W]) resampled by `scale` (pixel centres, edges
+    clamped) into [n][out_h][out_w], starting at output pixel (oy, ox)."""
+    _cuda(x, "x")
+    if x.dtype != torch.float32:
+        raise ValueError("x must be float32")
+    squeeze = x.dim() == 2
+    if squeeze:
+        x = x.unsqueeze(0)
+    x = x.contiguous()
+    n, H, W = (int(v) for v in x.shape)
+    out = torch.empty((n, int(out_h), int(out_w)), dtype=torch.float32, device=x.device)
+    _check(lib().prnu_resample_bilinear(_ptr(x), n, H, W, float(scale), int(oy), int(ox), int(out_h), int(out_w),
+                                        _ptr(out), _stream(x.device)))
+    return out[0] if squeeze else out
 
 
 def pce_blocks(X: torch.Tensor, Y: torch.Tensor, modulate: torch.Tensor | None = None, b: int = 500,

@@ -329,3 +329,36 @@ def eval_scene_realizations(cam: int, R: int, H: int, W: int, kind: str = "textu
         I = I0 * (1.0 + Kt) + noise_std * torch.randn((H, W), generator=gen, device=device)
         out[i] = torch.round(I).clamp_(0, 255).to(torch.uint8)
     return out, I0, K
+
+
+def mixed_media_camera_torch(cam: int, n_video: int, n_still: int, Hs: int = 2250, Ws: int = 4000,
+                             oy: int = 0, ox: int = 0, Hv: int = 1080, Wv: int = 1920, k_std: float = 0.001,
+                             noise_std: float = 2.0, video_noise: float = 1.0, device="cuda",
+                             cfg: int = CFG_EVAL):
+    """A camera that records full-resolution stills and half-resolution video.
+
+    The sensor has PRNU K ~ N(0, k_std^2) at Hs x Ws.  A still is a textured
+    scene at sensor resolution (as in eval_frames_torch) times (1 + K) plus
+    N(0, noise_std^2), rounded.  A video frame is a sensor frame (same model)
+    reduced 2 x 2 (the in-camera downscale by 0.5, pixel centres), cropped at
+    (oy, ox) to Hv x Wv, plus N(0, video_noise^2), rounded.  Returns (video
+    uint8 [n_video][Hv][Wv][1], stills uint8 [n_still][Hs][Ws][1], K float64
+    [Hs][Ws]) with the frames on `device`."""
+    import torch
+
+    K = camera_prnu((Hs, Ws), k_std, cfg, cam, 0x5E45)
+    Kt = torch.from_numpy(K).to(device=device, dtype=torch.float32)
+    gen = _eval_generator(cam, cfg, 1 << 21, "textured", device)
+    video = torch.empty((n_video, Hv, Wv, 1), dtype=torch.uint8, device=device)
+    stills = torch.empty((n_still, Hs, Ws, 1), dtype=torch.uint8, device=device)
+    for i in range(n_video):
+        S = _eval_scene(gen, Hs, Ws, "textured", device) * (1.0 + Kt)
+        S = S + noise_std * torch.randn((Hs, Ws), generator=gen, device=device)
+        half = S[: Hs // 2 * 2, : Ws // 2 * 2].reshape(Hs // 2, 2, Ws // 2, 2).mean(dim=(1, 3))
+        v = half[oy:oy + Hv, ox:ox + Wv] + video_noise * torch.randn((Hv, Wv), generator=gen, device=device)
+        video[i, :, :, 0] = torch.round(v).clamp_(0, 255).to(torch.uint8)
+    for i in range(n_still):
+        S = _eval_scene(gen, Hs, Ws, "textured", device) * (1.0 + Kt)
+        S = S + noise_std * torch.randn((Hs, Ws), generator=gen, device=device)
+        stills[i, :, :, 0] = torch.round(S).clamp_(0, 255).to(torch.uint8)
+    return video, stills, K

@@ -134,3 +134,15 @@ def test_extract_blocks_validation(lib):
         assert lib.prnu_extract_blocks(*args) == prnu.PRNU_E_INVAL, args
     assert "prnu_extract_blocks" in lib.prnu_last_error().decode()
     assert len(ok) == 7
+
+
+def test_resample_validation(lib):
+    fake = ctypes.c_void_p(0x1000)
+    bad = [
+        (None, 1, 8, 8, 0.5, 0, 0, 4, 4, fake, None), (fake, 1, 8, 8, 0.5, 0, 0, 4, 4, None, None),
+        (fake, 0, 8, 8, 0.5, 0, 0, 4, 4, fake, None), (fake, 1, 8, 8, 0.0, 0, 0, 4, 4, fake, None),
+        (fake, 1, 8, 8, float("nan"), 0, 0, 4, 4, fake, None), (fake, 1, 8, 8, 0.5, -1, 0, 4, 4, fake, None),
+        (fake, 1, 8, 8, 0.5, 0, 0, 0, 4, fake, None), (fake, 1, 0, 8, 0.5, 0, 0, 4, 4, fake, None),
+    ]
+    for args in bad:
+        assert lib.prnu_resample_bilinear(*args) == prnu.PRNU_E_INVAL, args

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import correlate, pipeline, sda
+from oracle import correlate, pipeline, resample, sda
 from parity import RTOL, assert_pce, assert_scaled
 
 torch = pytest.importorskip("torch")
@@ -352,6 +352,21 @@ def test_pce_blocks_vs_oracle(dev):
                 assert_pce(got[k, q, j], ref[k], what=f"block {k} pce[{q},{j}]")
     assert got[2, 0, 1] > 60 and got[5, 0, 1] > 60
     assert abs(got[0, 0, 1]) < 60
+
+
+@pytest.mark.parametrize("n,H,W,scale,oh,ow,oy,ox", [
+    (2, 64, 96, 0.5, 32, 48, 0, 0), (1, 37, 53, 1.37, 60, 70, 3, 5), (3, 120, 200, 0.73, 80, 140, 2, 1),
+    (1, 2200, 3900, 0.5, 1080, 1920, 37, 61), (1, 17, 19, 2.0, 40, 40, 0, 0)])
+def test_resample_bilinear_vs_oracle(dev, n, H, W, scale, oh, ow, oy, ox):
+    """Resizing and cropping of a query for mixed-media matching: downsampling,
+    upsampling, crop offsets and clamped edges against the oracle."""
+    _log(f"resample {n}x{H}x{W} scale {scale} -> {oh}x{ow} at ({oy},{ox})")
+    g = synth.rng(synth.CFG_TEST, 6200 + H)
+    x = g.normal(0, 1, size=(n, H, W)).astype(np.float32)
+    got = down(prnu.resample_bilinear(up(x, dev), scale, oh, ow, oy, ox))
+    for p in range(n):
+        ref = resample.bilinear(x[p].astype(np.float64), scale, oh, ow, oy, ox)
+        np.testing.assert_allclose(got[p], ref, rtol=0, atol=2e-6 * np.abs(ref).max())
 
 
 def test_pce_fixed_query_chunks(dev):
