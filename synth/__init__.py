@@ -362,3 +362,37 @@ def mixed_media_camera_torch(cam: int, n_video: int, n_still: int, Hs: int = 225
         S = S + noise_std * torch.randn((Hs, Ws), generator=gen, device=device)
         stills[i, :, :, 0] = torch.round(S).clamp_(0, 255).to(torch.uint8)
     return video, stills, K
+
+
+def stabilized_video_torch(cam: int, vid: int, n: int, H: int = 1080, W: int = 1920, k_std: float = 0.0004,
+                           p_still: float = 0.3, max_shift: int = 8, noise_std: float = 2.0, device="cuda",
+                           cfg: int = CFG_EVAL):
+    """A digitally stabilised gray video: the scene is a random-walk crop of a
+    per-video texture (as in the video generator); each frame's sensor
+    pattern reaches the output translated by the stabiliser, by (0, 0) with
+    probability p_still and otherwise by an integer shift uniform in
+    [-max_shift, max_shift]^2 (a translation-only stand-in for the in-camera
+    warps).  I = I0 (1 + K shifted) + N(0, noise_std^2), rounded.  Returns
+    (uint8 [n][H][W][1] on device, K float64 [H][W], shifts int [n][2])."""
+    import torch
+
+    K = camera_prnu((H, W), k_std, cfg, cam, 0x57AB)
+    Kt = torch.from_numpy(K).to(device=device, dtype=torch.float32)
+    g = rng(cfg, cam, 0x57AB, vid)
+    tex = torch.from_numpy(stretch(gaussian_blur(g.uniform(0.0, 1.0, size=(2 * H, 2 * W)), 2.0))).to(
+        device=device, dtype=torch.float32)
+    offs = crop_walk(n, H, W, g)
+    bright = g.uniform(0.7, 1.3, size=n)
+    still = g.uniform(size=n) < p_still
+    shifts = g.integers(-max_shift, max_shift + 1, size=(n, 2))
+    shifts[still] = 0
+    gen = torch.Generator(device=device)
+    gen.manual_seed((MASTER_SEED * 17 + cfg * 7919 + cam * 104729 + vid * 131) % (2**63))
+    out = torch.empty((n, H, W, 1), dtype=torch.uint8, device=device)
+    for i in range(n):
+        y, x = int(offs[i, 0]), int(offs[i, 1])
+        Ks = torch.roll(Kt, shifts=(int(shifts[i, 0]), int(shifts[i, 1])), dims=(0, 1))
+        I = tex[y:y + H, x:x + W] * float(bright[i]) * (1.0 + Ks)
+        I = I + noise_std * torch.randn((H, W), generator=gen, device=device)
+        out[i, :, :, 0] = torch.round(I).clamp_(0, 255).to(torch.uint8)
+    return out, K, shifts
