@@ -38,13 +38,15 @@ namespace {
 
 constexpr int HALO = 4;  // half of the largest Wiener window (9)
 constexpr int NT = 256;  // threads per workgroup
-// Forward-level workgroups with 32 x 32 tiles are LDS-limited to two per CU;
-// twice the threads give the CU more waves to hide load and LDS latency.
+// Forward-level workgroups with 32 x 32 tiles take 36 KB of LDS (four per
+// CU); 512 threads give each of them eight waves.
 constexpr int FWD_NT32 = 512;
 constexpr int fwd_nt(int tt) { return tt == 32 ? FWD_NT32 : NT; }
-// Row parts per core column in the forward level's Wiener stage.
-constexpr int WIENER_SPLIT = 4;
-// The same for the inverse levels (32 x 32 tiles: three workgroups per CU).
+// Row parts per core column in the forward level's Wiener stage: each part
+// re-reads eight halo rows, so few long parts beat many short ones once other
+// workgroups on the CU cover the idle threads.
+constexpr int WIENER_SPLIT = 2;
+// Inverse levels with 32 x 32 tiles: three workgroups per CU, 512 threads each.
 constexpr int INV_NT32 = 512;
 constexpr int inv_nt(int tt) { return tt == 32 ? INV_NT32 : NT; }
 
@@ -54,9 +56,12 @@ struct FwdGeom {
     static constexpr int IN = 2 * NC + TAPS - 2;          // input samples per side
     static constexpr int INS = (IN + 3) / 4 * 4;          // LDS row stride, 16-byte aligned rows
     static constexpr int QSZ = 3 * NC * NC + 3 * TT * TT;  // masked squares + core coefficients
-    static constexpr int TILE = IN * INS > QSZ ? IN * INS : QSZ;
     static constexpr int RL = IN * NC;                    // one row-filtered band
-    static constexpr int LDS = TILE + 2 * RL + 2 * IN;    // floats; the two index maps at the end
+    // One area holds, in turn, the input samples, the two row-filtered bands
+    // and the squares + core coefficients: each pass keeps its results in
+    // registers until every thread has read its inputs.
+    static constexpr int TILE = IN * INS > QSZ ? (IN * INS > 2 * RL ? IN * INS : 2 * RL) : (QSZ > 2 * RL ? QSZ : 2 * RL);
+    static constexpr int LDS = TILE + 2 * IN;             // floats; the two index maps at the end
     static_assert(TILE % 4 == 0 && RL % 4 == 0 && NC % 4 == 0, "16-byte aligned LDS areas");
 };
 
@@ -180,9 +185,9 @@ __device__ __forceinline__ void fwd_compute(const FwdArgs &a, int tile, int plan
     using G = FwdGeom<TAPS, TT>;
     constexpr int NTH = fwd_nt(TT);
     constexpr int IN = G::IN, INS = G::INS, NC = G::NC;
-    float *tbuf = lds;           // input samples; later squares + core coefficients
-    float *rlo = lds + G::TILE;  // row low-pass
-    float *rhi = rlo + G::RL;    // row high-pass
+    float *tbuf = lds;             // input samples, then the row bands, then squares + core coefficients
+    float *rlo = lds;              // row low-pass
+    float *rhi = lds + G::RL;      // row high-pass
     const int hk = a.n_r >> 1, wk = a.n_c >> 1;
     const int tr = tile / a.tiles_c, tc = tile - (tile / a.tiles_c) * a.tiles_c;
     const int k0r = tr * TT, k0c = tc * TT;
@@ -193,106 +198,132 @@ __device__ __forceinline__ void fwd_compute(const FwdArgs &a, int tile, int plan
     // Rows: lo/hi along axis 1, four coefficients per item, 16-byte LDS traffic.
     constexpr int NQ = NC / 4;
     constexpr int NX = TAPS + 8;  // TAPS + 6 samples, rounded up to whole float4s
-    for (int it = tid; it < IN * NQ; it += NTH) {
-        const int i = it / NQ, kq = it - (it / NQ) * NQ;
-        const float4 *row = reinterpret_cast<const float4 *>(&tbuf[i * INS + 8 * kq]);
-        float x[NX];
+    constexpr int RITEMS = IN * NQ, RIT = (RITEMS + NTH - 1) / NTH;
+    float rl[RIT][4], rh[RIT][4];
 #pragma unroll
-        for (int t = 0; t < NX / 4; ++t) {
-            const float4 v = row[t];
-            x[4 * t] = v.x;
-            x[4 * t + 1] = v.y;
-            x[4 * t + 2] = v.z;
-            x[4 * t + 3] = v.w;
-        }
-        float lo[4], hi[4];
+    for (int k = 0; k < RIT; ++k) {
+        const int it = tid + k * NTH;
+        if (it < RITEMS) {
+            const int i = it / NQ, kq = it - (it / NQ) * NQ;
+            const float4 *row = reinterpret_cast<const float4 *>(&tbuf[i * INS + 8 * kq]);
+            float x[NX];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            lo[u] = 0.f;
-            hi[u] = 0.f;
+            for (int t = 0; t < NX / 4; ++t) {
+                const float4 v = row[t];
+                x[4 * t] = v.x;
+                x[4 * t + 1] = v.y;
+                x[4 * t + 2] = v.z;
+                x[4 * t + 3] = v.w;
+            }
 #pragma unroll
-            for (int j = 0; j < TAPS; ++j) {
-                lo[u] = fmaf(f.h[j], x[2 * u + j], lo[u]);
-                hi[u] = fmaf(f.g[j], x[2 * u + j], hi[u]);
+            for (int u = 0; u < 4; ++u) {
+                rl[k][u] = 0.f;
+                rh[k][u] = 0.f;
+#pragma unroll
+                for (int j = 0; j < TAPS; ++j) {
+                    rl[k][u] = fmaf(f.h[j], x[2 * u + j], rl[k][u]);
+                    rh[k][u] = fmaf(f.g[j], x[2 * u + j], rh[k][u]);
+                }
             }
         }
-        *reinterpret_cast<float4 *>(&rlo[i * NC + 4 * kq]) = make_float4(lo[0], lo[1], lo[2], lo[3]);
-        *reinterpret_cast<float4 *>(&rhi[i * NC + 4 * kq]) = make_float4(hi[0], hi[1], hi[2], hi[3]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < RIT; ++k) {
+        const int it = tid + k * NTH;
+        if (it < RITEMS) {
+            const int i = it / NQ, kq = it - (it / NQ) * NQ;
+            *reinterpret_cast<float4 *>(&rlo[i * NC + 4 * kq]) = make_float4(rl[k][0], rl[k][1], rl[k][2], rl[k][3]);
+            *reinterpret_cast<float4 *>(&rhi[i * NC + 4 * kq]) = make_float4(rh[k][0], rh[k][1], rh[k][2], rh[k][3]);
+        }
     }
     __syncthreads();
 
-    // Columns: a quad of coefficient columns by a pair of coefficient rows per
-    // item.  Every detail coefficient's square goes to q (zero outside the
-    // band: the Wiener windows' zero extension); the core coefficients to cb.
+    // Columns: a pair of coefficient columns by a pair of coefficient rows of
+    // one row band per item.  Every detail coefficient's square goes to q
+    // (zero outside the band: the Wiener windows' zero extension); the core
+    // coefficients to cb.  Row band 0 (low-pass) gives ll (stored at once)
+    // and hl (q band 1); row band 1 gives lh (q band 0) and hh (q band 2).
     float *qb = tbuf;                // [3][NC][NC]
     float *cb = tbuf + 3 * NC * NC;  // [3][TT][TT]
     const int gr0 = k0r - HALO, gc0 = k0c - HALO;
-    for (int it = tid; it < NQ * (NC / 2); it += NTH) {
-        const int cq = it % NQ, kp = it / NQ;
-        bool cv[4];
+    constexpr int NP = NC / 2;
+    constexpr int CITEMS = 2 * NP * NP, CIT = (CITEMS + NTH - 1) / NTH;
+    float cl[CIT][2][2], ch[CIT][2][2];  // [item][row][column]
 #pragma unroll
-        for (int c = 0; c < 4; ++c) cv[c] = gc0 + 4 * cq + c >= 0 && gc0 + 4 * cq + c < wk;
-        const bool core_c = cq >= HALO / 4 && cq < (HALO + TT) / 4;
-#pragma unroll
-        for (int pass = 0; pass < 2; ++pass) {
+    for (int k = 0; k < CIT; ++k) {
+        const int it = tid + k * NTH;
+        if (it < CITEMS) {
+            const int cp = it % NP, kp = (it / NP) % NP, pass = it / (NP * NP);
             const float *rb = pass == 0 ? rlo : rhi;
-            float4 xv[TAPS + 2];
+            float2 xv[TAPS + 2];
 #pragma unroll
             for (int t = 0; t < TAPS + 2; ++t)
-                xv[t] = *reinterpret_cast<const float4 *>(&rb[(4 * kp + t) * NC + 4 * cq]);
+                xv[t] = *reinterpret_cast<const float2 *>(&rb[(4 * kp + t) * NC + 2 * cp]);
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
-                float lo4[4] = {0.f, 0.f, 0.f, 0.f}, hi4[4] = {0.f, 0.f, 0.f, 0.f};
+                float l0 = 0.f, l1 = 0.f, h0 = 0.f, h1 = 0.f;
 #pragma unroll
                 for (int j = 0; j < TAPS; ++j) {
-                    const float4 v = xv[2 * u + j];
-                    lo4[0] = fmaf(f.h[j], v.x, lo4[0]);
-                    lo4[1] = fmaf(f.h[j], v.y, lo4[1]);
-                    lo4[2] = fmaf(f.h[j], v.z, lo4[2]);
-                    lo4[3] = fmaf(f.h[j], v.w, lo4[3]);
-                    hi4[0] = fmaf(f.g[j], v.x, hi4[0]);
-                    hi4[1] = fmaf(f.g[j], v.y, hi4[1]);
-                    hi4[2] = fmaf(f.g[j], v.z, hi4[2]);
-                    hi4[3] = fmaf(f.g[j], v.w, hi4[3]);
+                    const float2 v = xv[2 * u + j];
+                    l0 = fmaf(f.h[j], v.x, l0);
+                    l1 = fmaf(f.h[j], v.y, l1);
+                    h0 = fmaf(f.g[j], v.x, h0);
+                    h1 = fmaf(f.g[j], v.y, h1);
                 }
+                cl[k][u][0] = l0;
+                cl[k][u][1] = l1;
+                ch[k][u][0] = h0;
+                ch[k][u][1] = h1;
+                const int kr = 2 * kp + u;
+                const bool core = cp >= HALO / 2 && cp < (HALO + TT) / 2 && kr >= HALO && kr < HALO + TT;
+                if (pass == 0 && a.write_ll && core) {
+                    const int gr = gr0 + kr, gc = gc0 + 2 * cp;
+                    if (gr < hk) {
+                        if (gc < wk) op[(int64_t)gr * wk + gc] = l0;
+                        if (gc + 1 < wk) op[(int64_t)gr * wk + gc + 1] = l1;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < CIT; ++k) {
+        const int it = tid + k * NTH;
+        if (it < CITEMS) {
+            const int cp = it % NP, kp = (it / NP) % NP, pass = it / (NP * NP);
+            const bool cv0 = gc0 + 2 * cp >= 0 && gc0 + 2 * cp < wk;
+            const bool cv1 = gc0 + 2 * cp + 1 >= 0 && gc0 + 2 * cp + 1 < wk;
+            const bool core_c = cp >= HALO / 2 && cp < (HALO + TT) / 2;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
                 const int kr = 2 * kp + u;
                 const bool rv = gr0 + kr >= 0 && gr0 + kr < hk;
                 const bool core = core_c && kr >= HALO && kr < HALO + TT;
-                // pass 0 (row low-pass): lo4 = ll, hi4 = hl (q band 1);
-                // pass 1 (row high-pass): lo4 = lh (q band 0), hi4 = hh (q band 2)
-                if (pass == 0) {
-                    if (a.write_ll && core) {
-                        const int gr = gr0 + kr;
-                        if (gr < hk)
-#pragma unroll
-                            for (int c = 0; c < 4; ++c)
-                                if (cv[c]) op[(int64_t)gr * wk + gc0 + 4 * cq + c] = lo4[c];
-                    }
-                } else {
-                    *reinterpret_cast<float4 *>(&qb[(0 * NC + kr) * NC + 4 * cq]) =
-                        make_float4(rv && cv[0] ? lo4[0] * lo4[0] : 0.f, rv && cv[1] ? lo4[1] * lo4[1] : 0.f,
-                                    rv && cv[2] ? lo4[2] * lo4[2] : 0.f, rv && cv[3] ? lo4[3] * lo4[3] : 0.f);
+                auto put = [&](int sb, float c0, float c1) {
+                    *reinterpret_cast<float2 *>(&qb[(sb * NC + kr) * NC + 2 * cp]) =
+                        make_float2(rv && cv0 ? c0 * c0 : 0.f, rv && cv1 ? c1 * c1 : 0.f);
                     if (core)
-                        *reinterpret_cast<float4 *>(&cb[(0 * TT + kr - HALO) * TT + 4 * cq - HALO]) =
-                            make_float4(lo4[0], lo4[1], lo4[2], lo4[3]);
+                        *reinterpret_cast<float2 *>(&cb[(sb * TT + kr - HALO) * TT + 2 * cp - HALO]) =
+                            make_float2(c0, c1);
+                };
+                if (pass == 0) {
+                    put(1, ch[k][u][0], ch[k][u][1]);
+                } else {
+                    put(0, cl[k][u][0], cl[k][u][1]);
+                    put(2, ch[k][u][0], ch[k][u][1]);
                 }
-                const int sb = pass == 0 ? 1 : 2;
-                *reinterpret_cast<float4 *>(&qb[(sb * NC + kr) * NC + 4 * cq]) =
-                    make_float4(rv && cv[0] ? hi4[0] * hi4[0] : 0.f, rv && cv[1] ? hi4[1] * hi4[1] : 0.f,
-                                rv && cv[2] ? hi4[2] * hi4[2] : 0.f, rv && cv[3] ? hi4[3] * hi4[3] : 0.f);
-                if (core)
-                    *reinterpret_cast<float4 *>(&cb[(sb * TT + kr - HALO) * TT + 4 * cq - HALO]) =
-                        make_float4(hi4[0], hi4[1], hi4[2], hi4[3]);
             }
         }
     }
     __syncthreads();
 
     // Wiener shrinkage of the TT x TT core of each detail band: one thread per
-    // (band, core column, WS-th part of the core rows), WS as large as the
-    // workgroup's threads allow up to four.  Band s of q/cb is lh, hl, hh for
-    // s = 0, 1, 2, stored as subbands 1, 2, 3.
-    constexpr int WS = WIENER_SPLIT * 3 * TT <= NTH ? WIENER_SPLIT : 2;
+    // (band, core column, WS-th part of the core rows).  Band s of q/cb is lh,
+    // hl, hh for s = 0, 1, 2, stored as subbands 1, 2, 3.
+    constexpr int WS = WIENER_SPLIT;
+    static_assert(3 * WS * TT <= NTH, "one Wiener column part per thread");
     if (tid < 3 * WS * TT) {
         const int s = tid / (WS * TT), part = (tid / TT) % WS, kcl = tid & (TT - 1);
         const float *Q = qb + s * NC * NC;
@@ -301,14 +332,19 @@ __device__ __forceinline__ void fwd_compute(const FwdArgs &a, int tile, int plan
         PRNU_GLOBAL float *cp = a.ckpt ? gmem(a.ckpt) + (int64_t)plane * a.ckpt_stride + (int64_t)s * band : nullptr;
         const int gco = k0c + kcl;
         const float s2 = a.s2;
+        // this thread's outputs: core rows part*TT/WS + i of column kcl
+        const int grow0 = k0r + part * (TT / WS);
+        PRNU_GLOBAL float *orow = ob + (int64_t)grow0 * wk + gco;
+        PRNU_GLOBAL float *crow = cp ? cp + (int64_t)grow0 * wk + gco : nullptr;
+        const float *ccol = Cc + part * (TT / WS) * TT + kcl;
         auto load = [&](int kr, int kc) { return Q[kr * NC + kc]; };
         auto emit = [&](int ko, float rho, float den) {
-            const int gro = gr0 + ko;
-            if (gro < hk && gco < wk) {
-                const float c = Cc[(ko - HALO) * TT + kcl];
-                ob[(int64_t)gro * wk + gco] = c * rho;
+            const int i = ko - HALO - part * (TT / WS);
+            if (grow0 + i < hk && gco < wk) {
+                const float c = ccol[i * TT];
+                orow[i * wk] = c * rho;
                 // sensitivity dr/ds = c / m where the window mean m exceeds s2, else 0
-                if (cp) cp[(int64_t)gro * wk + gco] = den > s2 ? c * __builtin_amdgcn_rcpf(den) : 0.f;
+                if (crow) crow[i * wk] = den > s2 ? c * __builtin_amdgcn_rcpf(den) : 0.f;
             }
         };
         wiener_column<TT / WS>(part * (TT / WS), kcl, s2, load, emit);
@@ -319,7 +355,7 @@ __device__ __forceinline__ void fwd_compute(const FwdArgs &a, int tile, int plan
 template <int TAPS, int TT>
 __device__ __forceinline__ void fwd_body(const FwdArgs &a, int tile, int plane, float *lds, const Filter &f) {
     using G = FwdGeom<TAPS, TT>;
-    int *rmap = reinterpret_cast<int *>(lds + G::TILE + 2 * G::RL);
+    int *rmap = reinterpret_cast<int *>(lds + G::TILE);
     int *cmap = rmap + G::IN;
     const int tid = opaque_tid();
     FwdStage<TAPS, TT>::maps(a, tile, tid, rmap, cmap);
