@@ -438,31 +438,31 @@ __device__ __forceinline__ void inv_cols(int tid, const float *sb, float *lo1, f
     // item: column kc, quad of output rows n = 4pp .. 4pp+3 (coefficient rows 2pp .. 2pp+HT)
     for (int it = tid; it < NK * (TT / 2); it += inv_nt(TT)) {
         const int pp = it / NK, kc = it - (it / NK) * NK;
-        float a[HT + 1], lh[HT + 1], hl[HT + 1], hh[HT + 1];
 #pragma unroll
-        for (int t = 0; t <= HT; ++t) {
-            const int kr = 2 * pp + t;
-            a[t] = sb[(0 * NK + kr) * NKS + kc];
-            lh[t] = sb[(1 * NK + kr) * NKS + kc];
-            hl[t] = sb[(2 * NK + kr) * NKS + kc];
-            hh[t] = sb[(3 * NK + kr) * NKS + kc];
-        }
+        for (int half = 0; half < 2; ++half) {
+            // half 0: a and hl give lo1; half 1: lh and hh give hi1
+            const int s0 = half == 0 ? 0 : 1, s1 = half == 0 ? 2 : 3;
+            float p[HT + 1], q[HT + 1];
 #pragma unroll
-        for (int v = 0; v < 2; ++v)
-#pragma unroll
-            for (int par = 0; par < 2; ++par) {
-                float lo = 0.f, hi = 0.f;
-#pragma unroll
-                for (int i = 0; i < HT; ++i) {
-                    const int t = v - i + HT - 1;
-                    const float hj = f.h[2 * i + par], gj = f.g[2 * i + par];
-                    lo = fmaf(hj, a[t], fmaf(gj, hl[t], lo));
-                    hi = fmaf(hj, lh[t], fmaf(gj, hh[t], hi));
-                }
-                const int n = 4 * pp + 2 * v + par;
-                lo1[n * NKS + kc] = lo;
-                hi1[n * NKS + kc] = hi;
+            for (int t = 0; t <= HT; ++t) {
+                const int kr = 2 * pp + t;
+                p[t] = sb[(s0 * NK + kr) * NKS + kc];
+                q[t] = sb[(s1 * NK + kr) * NKS + kc];
             }
+            float *dst = half == 0 ? lo1 : hi1;
+#pragma unroll
+            for (int v = 0; v < 2; ++v)
+#pragma unroll
+                for (int par = 0; par < 2; ++par) {
+                    float acc = 0.f;
+#pragma unroll
+                    for (int i = 0; i < HT; ++i) {
+                        const int t = v - i + HT - 1;
+                        acc = fmaf(f.h[2 * i + par], p[t], fmaf(f.g[2 * i + par], q[t], acc));
+                    }
+                    dst[(4 * pp + 2 * v + par) * NKS + kc] = acc;
+                }
+        }
     }
 }
 
