@@ -150,13 +150,39 @@ __global__ __launch_bounds__(FNT) void fft_cols_power(const float2 *__restrict__
             return (c0 + v < Mc) ? sp[(int64_t)n * Mc + c0 + v] : make_float2(0.f, 0.f);
         },
         [&](int e, float2 z) { b0[e] = z; });
+    const int pid = p0 + pl;
+    const float *pq = DOT ? Px + (int64_t)(pid / ny) * plane : nullptr;
+    // With a compile-time length the power weights of this thread's elements
+    // are loaded now, so they arrive while the transform runs.
+    constexpr int PXN = (DOT && FN) ? (FN * FV + FNT - 1) / FNT : 1;
+    float pxr[PXN];
+    if constexpr (DOT && FN != 0) {
+#pragma unroll
+        for (int k = 0; k < PXN; ++k) {
+            const int e = threadIdx.x + k * FNT;
+            const int v = e & (nvec - 1), n = e >> lvec;
+            pxr[k] = (e < tot && c0 + v < Mc) ? pq[(int64_t)n * Mc + c0 + v] : 0.f;
+        }
+    }
     __syncthreads();
     const float2 *res = fft_run<FN, FV>(b0, b1, plan, twl, -1.f);
-    const int pid = p0 + pl;
     double acc = 0.0;
-    const float *pq = DOT ? Px + (int64_t)(pid / ny) * plane : nullptr;
+    if constexpr (DOT && FN != 0) {
+#pragma unroll
+        for (int k = 0; k < PXN; ++k) {
+            const int e = threadIdx.x + k * FNT;
+            const int v = e & (nvec - 1), n = e >> lvec;
+            const int col = c0 + v;
+            if (e >= tot || col >= Mc) continue;
+            const float2 z = res[e];
+            float pw = z.x * z.x + z.y * z.y;
+            if (n == 0 && col == 0) pw = 0.f;
+            const float wgt = (col == 0 || col == Mc - 1) ? 1.f : 2.f;
+            acc += (double)(wgt * pw) * (double)pxr[k];
+        }
+    }
     constexpr int KB = 8;  // the power weights of KB elements are loaded before they are used
-    for (int e0 = threadIdx.x; e0 < tot; e0 += KB * FNT) {
+    for (int e0 = threadIdx.x; e0 < ((DOT && FN) ? 0 : tot); e0 += KB * FNT) {
         float px[KB];
         if (DOT) {
 #pragma unroll
