@@ -5,12 +5,15 @@
 // buf[n * nvec + v].  Each pass is a Stockham (self-sorting) step: with Ns the
 // product of the radices already applied, butterfly j (k = j mod Ns) reads
 // x[j + r N/R] for r < R, multiplies by the twiddle W_N^{k r N/(Ns R)},
-// does an R-point DFT and writes y[(j / Ns) Ns R + k + r Ns].  Passes
-// ping-pong between two LDS buffers, so each thread only holds one
-// butterfly's values at a time.  Twiddles W_N^k = exp(-2 pi i k / N) are
-// rounded to float from double-precision sincospi once per size and staged
-// into LDS with the data, so a pass touches no global memory.  LDS is sized
-// per launch: two data buffers of N * nvec plus the twiddle table(s).
+// does an R-point DFT and writes y[(j / Ns) Ns R + k + r Ns].  For the
+// lengths compiled in (those of 1080p, 720p, 2160p and 512 x 512 planes) a
+// pass runs in place in one LDS buffer: a thread reads and transforms all of
+// its butterflies, and writes them back after a barrier.  Other lengths run
+// a plan read at run time whose passes ping-pong between two LDS buffers.
+// Twiddles W_N^k = exp(-2 pi i k / N) are rounded to float from
+// double-precision sincospi once per size and staged into LDS with the data,
+// so a pass touches no global memory.  LDS is sized per launch: one or two
+// data buffers of N * nvec plus the twiddle table(s).
 //
 // Kernels:
 //   fft_1d          complex transform of rows or columns, in place in HBM
@@ -46,7 +49,9 @@ __global__ __launch_bounds__(FNT) void fft_1d(float2 *__restrict__ data, int Nrt
     const int v0 = blk * nvec;
     float2 *base = data + (int64_t)pl * plane_stride;
     const int tot = N * nvec;
-    float2 *b0 = smem, *b1 = smem + tot, *twl = smem + 2 * tot;
+    // compile-time lengths transform in place (data, twiddles); the runtime
+    // plan ping-pongs between two data buffers
+    float2 *b0 = smem, *b1 = smem + tot, *twl = FN ? smem + tot : smem + 2 * tot;
     staged_copy<FNT, 4, float2>(threadIdx.x, N, [&](int e) { return tw[e]; }, [&](int e, float2 z) { twl[e] = z; });
     staged_copy<FNT, 8, float2>(
         threadIdx.x, tot,
@@ -82,7 +87,7 @@ __global__ __launch_bounds__(FNT) void rfft_rows(const float *__restrict__ Y, co
     const float *mp = mod ? mod + (int64_t)(pid / ny) * N : nullptr;
     const float mu = mean ? (float)mean[blockIdx.y] : 0.f;
     const int tot = M * nvec;
-    float2 *b0 = smem, *b1 = smem + tot, *twh = smem + 2 * tot, *twf = twh + M;
+    float2 *b0 = smem, *b1 = smem + tot, *twh = FN ? smem + tot : smem + 2 * tot, *twf = twh + M;
     staged_copy<FNT, 4, float2>(threadIdx.x, M, [&](int e) { return tw_half[e]; },
                                 [&](int e, float2 z) { twh[e] = z; });
     staged_copy<FNT, 4, float2>(threadIdx.x, M + 1, [&](int e) { return tw_full[e]; },
@@ -141,7 +146,7 @@ __global__ __launch_bounds__(FNT) void fft_cols_power(const float2 *__restrict__
     const int64_t plane = (int64_t)h * Mc;
     const float2 *sp = S + (int64_t)pl * plane;
     const int tot = h * nvec;
-    float2 *b0 = smem, *b1 = smem + tot, *twl = smem + 2 * tot;
+    float2 *b0 = smem, *b1 = smem + tot, *twl = FN ? smem + tot : smem + 2 * tot;
     staged_copy<FNT, 4, float2>(threadIdx.x, h, [&](int e) { return tw[e]; }, [&](int e, float2 z) { twl[e] = z; });
     staged_copy<FNT, 8, float2>(
         threadIdx.x, tot,
@@ -210,8 +215,9 @@ __global__ __launch_bounds__(FNT) void fft_cols_power(const float2 *__restrict__
         }
     }
     if (DOT) {
-        // the buffer not holding the result is free for the reduction
-        double *red = reinterpret_cast<double *>(res == b0 ? b1 : b0);
+        // the twiddles (compile-time lengths) or the buffer not holding the
+        // result are free for the reduction: the last pass ended in a barrier
+        double *red = reinterpret_cast<double *>(FN ? twl : (res == b0 ? b1 : b0));
         acc = block_sum_f64(acc, red);
         if (threadIdx.x == 0) part[(int64_t)pl * gridDim.x + blk] = acc;
     }
@@ -252,10 +258,11 @@ bool make_fft_plan(int n, FftPlan *p, bool columns) {
 
 size_t fft_twiddle_floats(int n) { return (size_t)2 * n; }
 
-// Dynamic LDS of a transform workgroup: two data buffers and `tw` twiddles
-// (at most 2 * 5120 + 5121 complex values, 123 KB, for one vector of 5120).
-unsigned fft_lds_bytes(const FftPlan &p, int tw) {
-    return (unsigned)(sizeof(float2) * ((size_t)2 * p.n * p.nvec + (size_t)tw));
+// Dynamic LDS of a transform workgroup: one data buffer (compile-time
+// lengths, in place) or two (runtime plan) and `tw` twiddles (at most
+// 2 * 5120 + 5121 complex values, 123 KB, for one vector of 5120).
+unsigned fft_lds_bytes(const FftPlan &p, int tw, bool in_place) {
+    return (unsigned)(sizeof(float2) * ((size_t)(in_place ? 1 : 2) * p.n * p.nvec + (size_t)tw));
 }
 
 // Allows a kernel the dynamic LDS of its launch.
@@ -312,8 +319,8 @@ hipError_t launch_fft2(float2 *data, int batch, int h, int w, const FftPlan &ph,
     dim3 gr((unsigned)((h + pw.nvec - 1) / pw.nvec), (unsigned)batch);
     {
         KernelTimer kt("fft_1d", bytes, s);
-        const unsigned lds = fft_lds_bytes(pw, pw.n);
         const Fft1dKernel k = pick_fft_1d(pw);
+        const unsigned lds = fft_lds_bytes(pw, pw.n, k != fft_1d<0, 0>);
         hipError_t e = allow_lds(k, lds);
         if (e != hipSuccess) return e;
         k<<<gr, FNT, lds, s>>>(data, w, h, 1, w, plane, pw, tw_w, sigma);
@@ -324,8 +331,8 @@ hipError_t launch_fft2(float2 *data, int batch, int h, int w, const FftPlan &ph,
     dim3 gc((unsigned)((w + ph.nvec - 1) / ph.nvec), (unsigned)batch);
     {
         KernelTimer kt("fft_1d", bytes, s);
-        const unsigned lds = fft_lds_bytes(ph, ph.n);
         const Fft1dKernel k = pick_fft_1d(ph);
+        const unsigned lds = fft_lds_bytes(ph, ph.n, k != fft_1d<0, 0>);
         e = allow_lds(k, lds);
         if (e != hipSuccess) return e;
         k<<<gc, FNT, lds, s>>>(data, h, w, w, 1, plane, ph, tw_h, sigma);
@@ -339,8 +346,8 @@ hipError_t launch_rfft_rows(const float *Y, const float *mod, int ny, int p0, in
     const double bytes = (double)n * h * ((mod ? 8.0 : 4.0) * w + 8.0 * (w / 2 + 1));
     KernelTimer kt("rfft_rows", bytes, s);
     dim3 g((unsigned)((h + phalf.nvec - 1) / phalf.nvec), (unsigned)n);
-    const unsigned lds = fft_lds_bytes(phalf, 2 * phalf.n + 1);
     const RowsKernel k = pick_rfft_rows(phalf);
+    const unsigned lds = fft_lds_bytes(phalf, 2 * phalf.n + 1, k != rfft_rows<0, 0>);
     const hipError_t e = allow_lds(k, lds);
     if (e != hipSuccess) return e;
     k<<<g, FNT, lds, s>>>(Y, mod, ny, p0, mean, h, w, phalf, tw_half, tw_full, out);
@@ -353,7 +360,7 @@ hipError_t launch_fft_cols_power(const float2 *S, int n, int h, int Mc, const Ff
                                  const float *Px, int ny, int p0, float *Pout, double *part, hipStream_t s) {
     const double bytes = (double)n * h * Mc * (8.0 + 4.0);
     dim3 g((unsigned)fft_cols_power_blocks(Mc, ph), (unsigned)n);
-    const unsigned lds = fft_lds_bytes(ph, ph.n);
+    const unsigned lds = fft_lds_bytes(ph, ph.n, pick_fft_cols<true>(ph) != fft_cols_power<true, 0, 0>);
     if (Px) {
         const ColsKernel k = pick_fft_cols<true>(ph);
         const hipError_t e = allow_lds(k, lds);

@@ -7,7 +7,7 @@
 
 namespace prnu {
 
-constexpr int FNT = 512;    // threads per FFT workgroup (LDS allows two or three per CU; 8 waves each hide LDS latency)
+constexpr int FNT = 512;    // threads per FFT workgroup (8 waves hide LDS latency; the in-place transforms of 1080p planes take 30-50 KB of LDS, three to five workgroups per CU)
 constexpr int FCAP = 5120;  // longest transform
 constexpr int FVEC = 2560;  // vectors per workgroup: as many as keep nvec * N within this
 
@@ -168,72 +168,69 @@ constexpr Radices radices_of(int N) {
 }
 constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
 
+// The passes run in place in one LDS buffer: every thread first takes all
+// of its butterflies' inputs into registers and transforms them, and writes
+// them back after a barrier, so a workgroup needs half the LDS of the
+// two-buffer passes of the runtime plan (more workgroups per CU).
 template <int N, int R, int NS, int NV>
-__device__ __forceinline__ void stockham_fixed(const float2 *__restrict__ src, float2 *__restrict__ dst,
-                                               const float2 *__restrict__ tw, float sigma) {
+__device__ __forceinline__ void stockham_inplace(float2 *buf, const float2 *__restrict__ tw, float sigma) {
     constexpr int NR = N / R, NB = NR * NV, TWS = N / (NS * R);
     constexpr int ITER = (NB + FNT - 1) / FNT;
-    constexpr int KB = R == 5 ? 3 : 4;
+    float2 v[ITER][R];
+    unsigned d0[ITER];
 #pragma unroll
-    for (int i0 = 0; i0 < ITER; i0 += KB) {
-        float2 v[KB][R];
-        unsigned kk[KB], d0[KB];
+    for (int i = 0; i < ITER; ++i) {
+        const unsigned idx = threadIdx.x + (unsigned)(i * FNT);
+        if ((i + 1) * FNT <= NB || idx < (unsigned)NB) {
+            const unsigned vv = idx % NV, j = idx / NV;
+            const unsigned k = j % NS, jq = j / NS;
+            d0[i] = (jq * (NS * R) + k) * NV + vv;
 #pragma unroll
-        for (int b = 0; b < KB; ++b) {
-            const int i = i0 + b;
-            const unsigned idx = threadIdx.x + (unsigned)(i * FNT);
-            if (i < ITER && ((i + 1) * FNT <= NB || idx < (unsigned)NB)) {
-                const unsigned vv = idx % NV, j = idx / NV;
-                const unsigned k = j % NS, jq = j / NS;
-                kk[b] = k;
-                d0[b] = (jq * (NS * R) + k) * NV + vv;
+            for (int r = 0; r < R; ++r) v[i][r] = buf[(j + r * NR) * NV + vv];
+            if (NS > 1) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[b][r] = src[(j + r * NR) * NV + vv];
-            }
-        }
-#pragma unroll
-        for (int b = 0; b < KB; ++b) {
-            const int i = i0 + b;
-            const unsigned idx = threadIdx.x + (unsigned)(i * FNT);
-            if (i < ITER && ((i + 1) * FNT <= NB || idx < (unsigned)NB)) {
-                if (NS > 1) {  // the first pass has k = 0: unit twiddles
-#pragma unroll
-                    for (int r = 1; r < R; ++r) {
-                        float2 w = tw[kk[b] * (r * TWS)];
-                        w.y *= -sigma;
-                        v[b][r] = cmul(v[b][r], w);
-                    }
+                for (int r = 1; r < R; ++r) {
+                    float2 w = tw[k * (r * TWS)];
+                    w.y *= -sigma;
+                    v[i][r] = cmul(v[i][r], w);
                 }
-                dft<R>(v[b], sigma);
-#pragma unroll
-                for (int r = 0; r < R; ++r) dst[d0[b] + r * NS * NV] = v[b][r];
             }
+            dft<R>(v[i], sigma);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITER; ++i) {
+        const unsigned idx = threadIdx.x + (unsigned)(i * FNT);
+        if ((i + 1) * FNT <= NB || idx < (unsigned)NB) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[d0[i] + r * NS * NV] = v[i][r];
         }
     }
     __syncthreads();
 }
 
 template <int N, int NV, int P = 0, int NS = 1>
-__device__ __forceinline__ const float2 *fft_fixed(float2 *src, float2 *dst, const float2 *__restrict__ tw,
-                                                   float sigma) {
+__device__ __forceinline__ void fft_fixed_inplace(float2 *buf, const float2 *__restrict__ tw, float sigma) {
     constexpr Radices L = radices_of(N);
-    if constexpr (P == L.n) {
-        return src;
-    } else {
+    if constexpr (P < L.n) {
         constexpr int R = L.r[P];
-        stockham_fixed<N, R, NS, NV>(src, dst, tw, sigma);
-        return fft_fixed<N, NV, P + 1, NS * R>(dst, src, tw, sigma);
+        stockham_inplace<N, R, NS, NV>(buf, tw, sigma);
+        fft_fixed_inplace<N, NV, P + 1, NS * R>(buf, tw, sigma);
     }
 }
 
-// Runtime plan for N = 0, the compile-time passes otherwise.
+// Runtime plan for N = 0 (two buffers, the result in either), the
+// compile-time passes in place in b0 otherwise (b1 unused).
 template <int N, int NV>
 __device__ __forceinline__ const float2 *fft_run(float2 *b0, float2 *b1, const FftPlan &plan,
                                                  const float2 *__restrict__ tw, float sigma) {
-    if constexpr (N == 0)
+    if constexpr (N == 0) {
         return fft_lds(b0, b1, plan, tw, sigma);
-    else
-        return fft_fixed<N, NV>(b0, b1, tw, sigma);
+    } else {
+        fft_fixed_inplace<N, NV>(b0, tw, sigma);
+        return b0;
+    }
 }
 
 __device__ __forceinline__ double wave_sum_f64(double v) {
