@@ -150,7 +150,7 @@ int plan_denoise(Carver &cv, int n_img, int H, int W, const prnu_denoise_params 
 
 int frames_per_batch(int g, int H, int W, int C) {
     const int64_t px = (int64_t)C * padded(H) * padded(W);
-    int64_t nb = kBatchPixels / px;
+    int64_t nb = kAccBatchPixels / px;
     if (nb < 1) nb = 1;
     if (nb > kMaxFramesPerMle) nb = kMaxFramesPerMle;
     if (nb > g) nb = g;

@@ -24,7 +24,11 @@ namespace prnu {
 
 constexpr size_t kAlign = 256;
 constexpr int64_t kBatchPixels = 48ll << 20;  // planes x padded pixels per denoise batch
-constexpr int kMaxFramesPerMle = 8;          // SDA frames folded per accumulator update
+// Fingerprint accumulation batches more: every batch ends in one read-modify-
+// write of the accumulators, and larger level launches leave shorter tails
+// (1080p RGB: 32 SDA frames, about 1.9 GB of workspace).
+constexpr int64_t kAccBatchPixels = 192ll << 20;  // frames x channels x padded pixels per batch
+constexpr int kMaxFramesPerMle = 32;               // SDA frames folded per accumulator update
 constexpr int kMaxDim = 1 << 15;
 
 // Bump allocator over the caller's workspace; with base == nullptr it only

@@ -67,7 +67,9 @@ def test_workspace_queries(lib):
     rc, n8 = _ws_size(lib.prnu_fingerprint_accumulate_workspace_size, 400, 1080, 1920, 3, 50, ctypes.byref(p))
     assert rc == 0 and n8 > 0
     rc, n1 = _ws_size(lib.prnu_fingerprint_accumulate_workspace_size, 400, 1080, 1920, 3, 1, ctypes.byref(p))
-    assert rc == 0 and n1 == n8  # 8 SDA frames per batch either way
+    assert rc == 0 and n1 == 4 * n8  # batches of 32 SDA frames at d = 1, all 8 at d = 50
+    rc, n12 = _ws_size(lib.prnu_fingerprint_accumulate_workspace_size, 400, 1080, 1920, 3, 12, ctypes.byref(p))
+    assert rc == 0 and n12 == n1  # 34 SDA frames: batches of 32 either way
     rc, n = _ws_size(lib.prnu_fingerprint_finalize_workspace_size, 3, 1080, 1920, 7)
     assert rc == 0 and n > 1080 * 1920 * 16
     rc, n = _ws_size(lib.prnu_pce_match_workspace_size, 50, 4, 1080, 1920, 1)
