@@ -505,7 +505,9 @@ struct TunePlan {
 // nb SDA frames of C planes, about 16 Mi padded pixels in all.
 void plan_tune(Carver &cv, int H, int W, int C, int levels, TunePlan *tp) {
     const int64_t px = (int64_t)C * padded(H) * padded(W);
-    tp->nb = (int)std::max<int64_t>(1, std::min<int64_t>(8, (16ll << 20) / px));
+    // trial launches as large as fingerprint accumulation's batches, so the
+    // tile chosen is the faster one at the size it will run
+    tp->nb = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxFramesPerMle, kAccBatchPixels / px));
     tp->planes = tp->nb * C;
     tp->means = cv.take<float>((size_t)tp->planes * H * W);
     for (int l = 1; l <= levels; ++l)
