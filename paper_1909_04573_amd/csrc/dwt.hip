@@ -28,6 +28,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 
 #include "internal.h"
 #include "stage_dev.h"
@@ -117,8 +118,8 @@ struct FwdStage {
 
     static __device__ __forceinline__ void maps(const FwdArgs &a, int tile, int tid, int *rmap, int *cmap) {
         const int tr = tile / a.tiles_c, tc = tile - (tile / a.tiles_c) * a.tiles_c;
-        if (tid < IN)
-            rmap[tid] = map_index(2 * (tr * TT - HALO) + tid, a.n_r, a.off_r, a.src_rows);
+        if (tid < IN)  // row offsets in elements (< 2^30: a plane has at most 2^15 x 2^15 samples)
+            rmap[tid] = map_index(2 * (tr * TT - HALO) + tid, a.n_r, a.off_r, a.src_rows) * a.src_cols;
         else if (tid < 2 * IN)
             cmap[tid - IN] = map_index(2 * (tc * TT - HALO) + tid - IN, a.n_c, a.off_c, a.src_cols);
     }
@@ -136,7 +137,7 @@ struct FwdStage {
             for (int i = 0; i < NRGF; ++i) {
                 const int r = ty + i * RYF;
                 if (tx < IN2 && r < IN) {
-                    const float2 t = ld2(cp0 + (int64_t)rmap[r] * a.src_cols);
+                    const float2 t = ld2(cp0 + (unsigned)rmap[r]);
                     v[2 * i] = t.x;
                     v[2 * i + 1] = t.y;
                 }
@@ -149,7 +150,7 @@ struct FwdStage {
 #pragma unroll
             for (int i = 0; i < NRGS; ++i) {
                 const int r = ty + i * RYS;
-                const PRNU_GLOBAL float *rp = sp + (int64_t)(r < IN ? rmap[r] : 0) * a.src_cols;
+                const PRNU_GLOBAL float *rp = sp + (unsigned)(r < IN ? rmap[r] : 0);
 #pragma unroll
                 for (int g = 0; g < NCGS; ++g)
                     if (r < IN && tx + g * CXS < IN) v[i * NCGS + g] = rp[coff[g]];
@@ -288,35 +289,45 @@ __device__ __forceinline__ void fwd_compute(const FwdArgs &a, int tile, int plan
         }
     }
     __syncthreads();
+    // Tiles whose margin lies inside the band (most of them) store the
+    // squares without the per-coefficient range masks.
+    const bool inside = gr0 >= 0 && gr0 + NC <= hk && gc0 >= 0 && gc0 + NC <= wk;
+    auto store_cols = [&](auto masked) {
 #pragma unroll
-    for (int k = 0; k < CIT; ++k) {
-        const int it = tid + k * NTH;
-        if (it < CITEMS) {
-            const int cp = it % NP, kp = (it / NP) % NP, pass = it / (NP * NP);
-            const bool cv0 = gc0 + 2 * cp >= 0 && gc0 + 2 * cp < wk;
-            const bool cv1 = gc0 + 2 * cp + 1 >= 0 && gc0 + 2 * cp + 1 < wk;
-            const bool core_c = cp >= HALO / 2 && cp < (HALO + TT) / 2;
+        for (int k = 0; k < CIT; ++k) {
+            const int it = tid + k * NTH;
+            if (it < CITEMS) {
+                const int cp = it % NP, kp = (it / NP) % NP, pass = it / (NP * NP);
+                const bool cv0 = !masked || (gc0 + 2 * cp >= 0 && gc0 + 2 * cp < wk);
+                const bool cv1 = !masked || (gc0 + 2 * cp + 1 >= 0 && gc0 + 2 * cp + 1 < wk);
+                const bool core_c = cp >= HALO / 2 && cp < (HALO + TT) / 2;
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int kr = 2 * kp + u;
-                const bool rv = gr0 + kr >= 0 && gr0 + kr < hk;
-                const bool core = core_c && kr >= HALO && kr < HALO + TT;
-                auto put = [&](int sb, float c0, float c1) {
-                    *reinterpret_cast<float2 *>(&qb[(sb * NC + kr) * NC + 2 * cp]) =
-                        make_float2(rv && cv0 ? c0 * c0 : 0.f, rv && cv1 ? c1 * c1 : 0.f);
-                    if (core)
-                        *reinterpret_cast<float2 *>(&cb[(sb * TT + kr - HALO) * TT + 2 * cp - HALO]) =
-                            make_float2(c0, c1);
-                };
-                if (pass == 0) {
-                    put(1, ch[k][u][0], ch[k][u][1]);
-                } else {
-                    put(0, cl[k][u][0], cl[k][u][1]);
-                    put(2, ch[k][u][0], ch[k][u][1]);
+                for (int u = 0; u < 2; ++u) {
+                    const int kr = 2 * kp + u;
+                    const bool rv = !masked || (gr0 + kr >= 0 && gr0 + kr < hk);
+                    const bool core = core_c && kr >= HALO && kr < HALO + TT;
+                    auto put = [&](int sb, float c0, float c1) {
+                        float2 q2 = make_float2(c0 * c0, c1 * c1);
+                        if (masked) q2 = make_float2(rv && cv0 ? q2.x : 0.f, rv && cv1 ? q2.y : 0.f);
+                        *reinterpret_cast<float2 *>(&qb[(sb * NC + kr) * NC + 2 * cp]) = q2;
+                        if (core)
+                            *reinterpret_cast<float2 *>(&cb[(sb * TT + kr - HALO) * TT + 2 * cp - HALO]) =
+                                make_float2(c0, c1);
+                    };
+                    if (pass == 0) {
+                        put(1, ch[k][u][0], ch[k][u][1]);
+                    } else {
+                        put(0, cl[k][u][0], cl[k][u][1]);
+                        put(2, ch[k][u][0], ch[k][u][1]);
+                    }
                 }
             }
         }
-    }
+    };
+    if (inside)
+        store_cols(std::false_type{});
+    else
+        store_cols(std::true_type{});
     __syncthreads();
 
     // Wiener shrinkage of the TT x TT core of each detail band: one thread per
