@@ -310,15 +310,17 @@ __global__ __launch_bounds__(NT) void pce_direct(const float *__restrict__ X, co
 // the centred query tile in LDS, read through per-lane shift offsets) by
 // 4 pixels x 16 fingerprints (B: the modulated fingerprint tile in LDS); eight
 // such products per pixel quad cover 128 rows: the 121 shifts, an all-ones row
-// (giving sum y) and 6 unused rows.  Lane layout (checked on the device):
-// A[i][k] and B[k][n] at lane 16 k + i / 16 k + n, C[4 (l / 16) + r][l % 16]
-// in slot r of lane l.  Each tile's fp32 products are added to FP64
-// accumulators; sum y^2 and sum xc are plain FP64 sums.
+// (giving sum y) and 6 unused rows; each of the four waves owns two of the
+// eight shift blocks for every pixel of the tile.  Lane layout (checked on
+// the device): A[i][k] and B[k][n] at lane 16 k + i / 16 k + n,
+// C[4 (l / 16) + r][l % 16] in slot r of lane l.  Each tile's fp32 products
+// are added to FP64 accumulators; sum y^2 and sum xc are plain FP64 sums.
 constexpr int MTY = 8, MTX = 64;                              // pixel tile
 constexpr int MXH = MTY + 2 * DRAD, MXW = MTX + 2 * DRAD, MXWS = 76;  // query tile with the shift halo
 constexpr int MNJ = 16, MNS = 8;                              // fingerprints, shift blocks of 16
 constexpr int MYS = MTY * MTX + 4;                            // fingerprint stride in LDS (bank offset 4)
 constexpr int MONES = DNS * DNS;                              // row 121: all ones
+constexpr int SBW = MNS / (NT / 64);                          // shift blocks per wave
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(NT) void pce_direct_mfma(const float *__restrict__ X, const double *__restrict__ xmean,
@@ -327,7 +329,7 @@ __global__ __launch_bounds__(NT) void pce_direct_mfma(const float *__restrict__ 
                                                       double *__restrict__ part) {
     __shared__ float xs[MXH * MXWS];
     __shared__ float ms[MTY * MTX];                // modulation per tile pixel, 0 outside the image
-    __shared__ __align__(16) float ys[MNJ * MYS];  // reused for the FP64 reduction (32 KB)
+    __shared__ __align__(16) float ys[MNJ * MYS];
     __shared__ double sred[NT / 64];
     __shared__ double yred[NT / 64][MNJ];
     const int q = q0 + (int)blockIdx.y;
@@ -342,23 +344,27 @@ __global__ __launch_bounds__(NT) void pce_direct_mfma(const float *__restrict__ 
     // ones row read shift (0,0) and are dropped), column k = lane / 16 is pixel k of the quad.
     // The modulation belongs to the pixel t, so it scales A: xc(t + s) * mod(t); the
     // fingerprint tile (B) is then the same for every query.
-    int aoff[MNS];
+    // Wave wv computes shift blocks SBW wv .. SBW wv + SBW - 1 over all the
+    // tile's pixels, so it holds complete sums for its shifts (no cross-wave
+    // reduction, a quarter of the accumulators).
+    int aoff[SBW];
 #pragma unroll
-    for (int sb = 0; sb < MNS; ++sb) {
-        const int m = 16 * sb + (lane & 15);
+    for (int i = 0; i < SBW; ++i) {
+        const int m = 16 * (SBW * wv + i) + (lane & 15);
         const int mm = m < DNS * DNS ? m : (DNS * DNS) / 2;
-        aoff[sb] = (mm / DNS) * MXWS + (mm % DNS) + (lane >> 4);
+        aoff[i] = (mm / DNS) * MXWS + (mm % DNS) + (lane >> 4);
     }
-    const bool ones_lane = (lane & 15) == MONES - 16 * (MNS - 1);
+    // the all-ones row: lane 9 of the last block of the last wave
+    const bool ones_lane = wv == NT / 64 - 1 && (lane & 15) == MONES - 16 * (MNS - 1);
     const int boff = (lane & 15) * MYS + (lane >> 4);  // B: fingerprint n = lane % 16, pixel k = lane / 16
     // staging of the fingerprint tile: thread -> fingerprint sn, columns sc + 16 u
     const int sn = tid >> 4, sc = tid & 15;
     const PRNU_GLOBAL float *yp = j0 + sn < ny ? gmem(Y) + (int64_t)(j0 + sn) * N : nullptr;
-    double acc[MNS][4];
+    double acc[SBW][4];
 #pragma unroll
-    for (int sb = 0; sb < MNS; ++sb)
+    for (int i = 0; i < SBW; ++i)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc[sb][r] = 0.0;
+        for (int r = 0; r < 4; ++r) acc[i][r] = 0.0;
     double syy = 0.0, sx = 0.0;
 
     // The next tile's global loads are issued before the current tile's
@@ -418,66 +424,45 @@ __global__ __launch_bounds__(NT) void pce_direct_mfma(const float *__restrict__ 
             const int t = tid + u * NT, r = t / MTX, c = t % MTX;
             if (ty0 + r < h && tx0 + c < w) sx += (double)xs[(r + DRAD) * MXWS + c + DRAD];
         }
-        // wave wv: pixel rows 2 wv, 2 wv + 1, sixteen quads each
-        v4f cacc[MNS];
+        // every pixel row, sixteen quads each; sum y^2 of rows wv and wv + 4
+        v4f cacc[SBW];
 #pragma unroll
-        for (int sb = 0; sb < MNS; ++sb) cacc[sb] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int i = 0; i < SBW; ++i) cacc[i] = v4f{0.f, 0.f, 0.f, 0.f};
         float ssq = 0.f;
-        for (int g = 0; g < 32; ++g) {
-            const int r = 2 * wv + (g >> 4), c4 = (g & 15) * 4;
+#pragma unroll 16
+        for (int g = 0; g < MTY * 16; ++g) {
+            const int r = g >> 4, c4 = (g & 15) * 4;
             const float b = ys[boff + r * MTX + c4];
             const float m = ms[r * MTX + c4 + (lane >> 4)];
-            const float mb = m * b;
-            ssq = fmaf(mb, mb, ssq);
+            if ((r & 3) == wv) {
+                const float mb = m * b;
+                ssq = fmaf(mb, mb, ssq);
+            }
             const int xb = r * MXWS + c4;
 #pragma unroll
-            for (int sb = 0; sb < MNS; ++sb) {
-                float a = xs[xb + aoff[sb]] * m;
-                if (sb == MNS - 1 && ones_lane) a = m;
-                cacc[sb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, cacc[sb], 0, 0, 0);
+            for (int i = 0; i < SBW; ++i) {
+                float a = xs[xb + aoff[i]] * m;
+                if (i == SBW - 1 && ones_lane) a = m;
+                cacc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, cacc[i], 0, 0, 0);
             }
         }
         syy += (double)ssq;
 #pragma unroll
-        for (int sb = 0; sb < MNS; ++sb)
+        for (int i = 0; i < SBW; ++i)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) acc[sb][r] += (double)cacc[sb][r];
+            for (int r = 0; r < 4; ++r) acc[i][r] += (double)cacc[i][r];
     }
-    // reduce the four waves' accumulators in a fixed order (waves 2, 3 into 0, 1; then 1 into 0)
-    double *dred = reinterpret_cast<double *>(ys);  // [2][64][32]
-    __syncthreads();
-    if (wv >= 2) {
-#pragma unroll
-        for (int sb = 0; sb < MNS; ++sb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) dred[((wv - 2) * 64 + lane) * 32 + sb * 4 + r] = acc[sb][r];
-    }
-    __syncthreads();
-    if (wv < 2) {
-#pragma unroll
-        for (int sb = 0; sb < MNS; ++sb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) acc[sb][r] += dred[(wv * 64 + lane) * 32 + sb * 4 + r];
-    }
-    __syncthreads();
-    if (wv == 1) {
-#pragma unroll
-        for (int sb = 0; sb < MNS; ++sb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) dred[lane * 32 + sb * 4 + r] = acc[sb][r];
-    }
-    __syncthreads();
     const int64_t prow = (int64_t)(q - q0) * ny;
-    if (wv == 0) {
+    {
         const int n = lane & 15;
         if (j0 + n < ny) {
             double *dst = part + ((prow + j0 + n) * nblk + blk) * DSTAT;
 #pragma unroll
-            for (int sb = 0; sb < MNS; ++sb)
+            for (int i = 0; i < SBW; ++i)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int m = 16 * sb + 4 * (lane >> 4) + r;
-                    if (m <= MONES) dst[m] = acc[sb][r] + dred[lane * 32 + sb * 4 + r];
+                    const int m = 16 * (SBW * wv + i) + 4 * (lane >> 4) + r;
+                    if (m <= MONES) dst[m] = acc[i][r];
                 }
         }
     }
