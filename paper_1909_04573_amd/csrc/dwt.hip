@@ -47,7 +47,7 @@ constexpr int fwd_nt(int tt) { return tt == 32 ? FWD_NT32 : NT; }
 // re-reads eight halo rows, so few long parts beat many short ones once other
 // workgroups on the CU cover the idle threads.
 constexpr int WIENER_SPLIT = 2;
-// Inverse levels with 32 x 32 tiles: three workgroups per CU, 512 threads each.
+// Inverse levels with 32 x 32 tiles run 512 threads per workgroup.
 constexpr int INV_NT32 = 512;
 constexpr int inv_nt(int tt) { return tt == 32 ? INV_NT32 : NT; }
 
