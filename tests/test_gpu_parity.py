@@ -109,7 +109,7 @@ ACC_CASES = [
     ("tiny d=4", 8, 256, 256, 1, 4),
     ("rgb ragged remainder", 10, 72, 104, 3, 4),
     ("d=3", 9, 64, 80, 1, 3),
-    ("many batches", 40, 48, 48, 1, 2),
+    ("many batches", 80, 48, 48, 1, 2),  # 40 SDA frames: a batch of 32 and a ragged one of 8
 ]
 
 
