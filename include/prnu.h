@@ -353,8 +353,10 @@ int prnu_fingerprint_batch(const prnu_camera *cams, int n_cams, int dtype, const
  * prnu_set_tile: tile 16 or 32, 0 restores the default.
  * prnu_autotune: for frames of H x W x C and the denoiser `p`, times both
  *   tiles of every forward level, inverse level 2..L and the MLE fold on
- *   synthetic planes in `ws` (events on `stream`, waits for them; not under
- *   graph capture) and keeps the faster; `tiles` (nullable, 12 ints) receives
+ *   synthetic planes in `ws`, as many as one fingerprint-accumulation batch
+ *   holds (up to 32 frames: the tile is chosen at the size it runs; events
+ *   on `stream`, waits for them; not under graph capture) and keeps the
+ *   faster; `tiles` (nullable, 12 ints) receives
  *   the choices: [0..3] forward levels 1..4, [4..7] inverse levels 1..4
  *   ([4], level 1, is the MLE fold's), [8] the MLE fold; unused entries 0.
  */
