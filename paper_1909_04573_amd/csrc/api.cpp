@@ -61,7 +61,8 @@ size_t ckpt_level_offset(int H, int W, int lvl) {
 }
 
 int run_pyramid(const Filter &f, const prnu_denoise_params *p, const float *src, int planes, int H,
-                int W, const Pyramid &py, hipStream_t s, float *ckpt = nullptr) {
+                int W, const Pyramid &py, hipStream_t s, float *ckpt = nullptr, const unsigned char *src8 = nullptr,
+                int src8_c = 0) {
     const int Hp = padded(H), Wp = padded(W), L = p->levels;
     const float s0 = p->sigma0 * p->sigma0;
     const int64_t cstride = (int64_t)ckpt_level_offset(H, W, L + 1);
@@ -70,7 +71,7 @@ int run_pyramid(const Filter &f, const prnu_denoise_params *p, const float *src,
         float *ck = ckpt ? ckpt + ckpt_level_offset(H, W, l) : nullptr;
         if (l == 1) {
             PRNU_HIP(launch_dwt_fwd(p->taps, f, src, (int64_t)H * W, H, W, Hp, Wp, pad_before(H),
-                                    pad_before(W), py.lvl[1], planes, s2, L > 1, s, ck, cstride));
+                                    pad_before(W), py.lvl[1], planes, s2, L > 1, s, ck, cstride, src8, src8_c));
         } else {
             const int nr = Hp >> (l - 1), nc = Wp >> (l - 1);
             PRNU_HIP(launch_dwt_fwd(p->taps, f, py.lvl[l - 1], (int64_t)level_floats(Hp, Wp, l - 1), nr,
@@ -546,13 +547,18 @@ int prnu_fingerprint_accumulate(const void *frames, int dtype, int n_frames, int
     hipStream_t s = (hipStream_t)stream;
     const int g = (n_frames + group - 1) / group;
     const int Hp = padded(H), Wp = padded(W);
+    // SDA depth 1 on u8 frames: the means are the frames themselves (exact in
+    // float), so the level-1 forward and the MLE fold read the frames directly
+    const bool direct = group == 1 && dtype == PRNU_U8;
     for (int g0 = 0; g0 < g; g0 += ap.nb) {
         const int g1 = g0 + ap.nb < g ? g0 + ap.nb : g;
         const int nb = g1 - g0;
-        PRNU_HIP(launch_sda(frames, dtype, n_frames, H, W, C, group, g0, g1, nullptr, ap.means, s));
-        PRNU_TRY(run_pyramid(f, p, ap.means, nb * C, H, W, ap.py, s));
+        const unsigned char *f8 =
+            direct ? static_cast<const unsigned char *>(frames) + (int64_t)g0 * H * W * C : nullptr;
+        if (!direct) PRNU_HIP(launch_sda(frames, dtype, n_frames, H, W, C, group, g0, g1, nullptr, ap.means, s));
+        PRNU_TRY(run_pyramid(f, p, ap.means, nb * C, H, W, ap.py, s, nullptr, f8, C));
         PRNU_HIP(launch_dwt_inv_mle(p->taps, f, ap.py.lvl[1], Hp / 2, Wp / 2, p->levels == 1, nb, C,
-                                    ap.means, H, W, pad_before(H), pad_before(W), acc_mode, A, B, s));
+                                    ap.means, H, W, pad_before(H), pad_before(W), acc_mode, A, B, s, f8));
     }
     return PRNU_OK;
 }

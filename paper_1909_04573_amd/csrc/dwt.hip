@@ -128,8 +128,8 @@ struct FwdStage {
         const int tc = tile - (tile / a.tiles_c) * a.tiles_c;
         const PRNU_GLOBAL float *sp = gmem(a.src) + (int64_t)plane * a.src_stride;
         const int c_src0 = 2 * (tc * TT - HALO) - a.off_c;
-        fast = c_src0 >= 0 && c_src0 + IN <= a.src_cols && (c_src0 & 1) == 0 && (a.src_cols & 1) == 0 &&
-               (a.src_stride & 1) == 0;
+        fast = !a.src8 && c_src0 >= 0 && c_src0 + IN <= a.src_cols && (c_src0 & 1) == 0 &&
+               (a.src_cols & 1) == 0 && (a.src_stride & 1) == 0;
         if (fast) {
             const int tx = tid % CXF, ty = tid / CXF;
             const PRNU_GLOBAL float *cp0 = sp + c_src0 + 2 * tx;
@@ -147,13 +147,28 @@ struct FwdStage {
             int coff[NCGS];
 #pragma unroll
             for (int g = 0; g < NCGS; ++g) coff[g] = tx + g * CXS < IN ? cmap[tx + g * CXS] : 0;
+            if (a.src8) {
+                // one channel of interleaved u8 frames (exact in float)
+                const int C8 = a.src8_c;
+                const PRNU_GLOBAL unsigned char *bp =
+                    gmem(a.src8) + (int64_t)(plane / C8) * a.src_rows * a.src_cols * C8 + plane % C8;
 #pragma unroll
-            for (int i = 0; i < NRGS; ++i) {
-                const int r = ty + i * RYS;
-                const PRNU_GLOBAL float *rp = sp + (unsigned)(r < IN ? rmap[r] : 0);
+                for (int i = 0; i < NRGS; ++i) {
+                    const int r = ty + i * RYS;
+                    const unsigned ro = r < IN ? (unsigned)rmap[r] : 0u;
 #pragma unroll
-                for (int g = 0; g < NCGS; ++g)
-                    if (r < IN && tx + g * CXS < IN) v[i * NCGS + g] = rp[coff[g]];
+                    for (int g = 0; g < NCGS; ++g)
+                        if (r < IN && tx + g * CXS < IN) v[i * NCGS + g] = (float)bp[(ro + (unsigned)coff[g]) * (unsigned)C8];
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < NRGS; ++i) {
+                    const int r = ty + i * RYS;
+                    const PRNU_GLOBAL float *rp = sp + (unsigned)(r < IN ? rmap[r] : 0);
+#pragma unroll
+                    for (int g = 0; g < NCGS; ++g)
+                        if (r < IN && tx + g * CXS < IN) v[i * NCGS + g] = rp[coff[g]];
+                }
             }
         }
     }
@@ -548,7 +563,7 @@ __device__ __forceinline__ void inv_body(const InvArgs &a, int tile, int plane, 
 
 // Level 1 with the MLE epilogue over the a.nb SDA frames of channel c
 // (planes [nb][C], means [nb][C][H][W]).
-template <int TAPS, int TT, int ACC>
+template <int TAPS, int TT, int ACC, bool U8I = false>
 __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, float *lds, const Filter &f) {
     using G = InvGeom<TAPS, TT>;
     constexpr int NO = G::NO;
@@ -584,6 +599,14 @@ __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, floa
         // this frame's SDA means, loaded ahead of the subband staging (kept
         // in registers only where a thread owns a single row quad)
         const PRNU_GLOBAL float *Ip = gmem(a.means) + (int64_t)(fr * C + c) * npx;
+        // U8I: SDA depth 1, the means are the u8 frames (a.means8) themselves
+        const PRNU_GLOBAL unsigned char *I8 = U8I ? gmem(a.means8) + (int64_t)fr * npx * C + c : nullptr;
+        auto load_I = [&](int y, int xx) {
+            if constexpr (U8I)
+                return (float)I8[((int64_t)y * W + xx) * C];
+            else
+                return Ip[(int64_t)y * W + xx];
+        };
         constexpr int PF = ITEMS == 1 ? 1 : 0;
         float Iv[PF ? ITEMS : 1][4];
 #pragma unroll
@@ -594,7 +617,7 @@ __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, floa
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int xx = 2 * k0c + 4 * mq + u - a.off_c;
-                Iv[k][u] = (y >= 0 && y < H && xx >= 0 && xx < W) ? Ip[(int64_t)y * W + xx] : 0.f;
+                Iv[k][u] = (y >= 0 && y < H && xx >= 0 && xx < W) ? load_I(y, xx) : 0.f;
             }
         }
         // The previous frame's column pass finished reading sb before the
@@ -618,7 +641,7 @@ __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, floa
             for (int u = 0; u < 4; ++u) {
                 const int xx = 2 * k0c + 4 * mq + u - a.off_c;
                 if (y >= 0 && y < H && xx >= 0 && xx < W) {
-                    const float I = PF ? Iv[PF ? k : 0][u] : Ip[(int64_t)y * W + xx];
+                    const float I = PF ? Iv[PF ? k : 0][u] : load_I(y, xx);
                     if (ACC == PRNU_ACC_KAHAN_F32) {
                         // two-sum accumulation of W*I and I*I
                         const float pa = x[u] * I, pb = I * I;
@@ -699,12 +722,12 @@ __global__ __launch_bounds__(inv_nt(TT)) void dwt_inv(InvArgs a, Filter f) {
     inv_body<TAPS, TT, EPI>(a, tile, plane, lds, f);
 }
 
-template <int TAPS, int TT, int ACC>
+template <int TAPS, int TT, int ACC, bool U8I>
 __global__ __launch_bounds__(inv_nt(TT)) void dwt_inv_mle(MleArgs a, Filter f) {
     __shared__ __align__(16) float lds[InvGeom<TAPS, TT>::LDS];
     int tile, c;
     grid_tile(tile, c);
-    mle_body<TAPS, TT, ACC>(a, tile, c, lds, f);
+    mle_body<TAPS, TT, ACC, U8I>(a, tile, c, lds, f);
 }
 
 // ---------------------------------------------------------------------------
@@ -834,14 +857,15 @@ void set_tile_choice(int kind, int taps, int hk, int wk, int tt) {
 
 hipError_t launch_dwt_fwd(int taps, const Filter &f, const float *src, int64_t src_stride, int src_rows,
                           int src_cols, int n_r, int n_c, int off_r, int off_c, float *out, int planes, float s2,
-                          bool write_ll, hipStream_t s, float *ckpt, int64_t ckpt_stride) {
+                          bool write_ll, hipStream_t s, float *ckpt, int64_t ckpt_stride, const unsigned char *src8,
+                          int src8_c) {
     const int hk = n_r / 2, wk = n_c / 2;
     const int tt = tile_choice(TK_FWD, taps, hk, wk);
     FwdArgs a{src, src_stride, src_rows, src_cols, n_r, n_c, off_r, off_c, out, s2,
-              ceil_div(wk, tt), write_ll ? 1 : 0, ckpt, ckpt_stride};
+              ceil_div(wk, tt), write_ll ? 1 : 0, ckpt, ckpt_stride, src8, src8_c};
     dim3 grid((unsigned)tiles_for(tt, hk, wk), (unsigned)planes);
-    const double bytes = (double)planes * 4.0 *
-                         ((double)src_rows * src_cols + (write_ll ? 4.0 : 3.0) * (double)hk * wk);
+    const double bytes = (double)planes * ((src8 ? 1.0 : 4.0) * (double)src_rows * src_cols +
+                                           4.0 * (write_ll ? 4.0 : 3.0) * (double)hk * wk);
     KernelTimer kt(taps == 16 ? "dwt_fwd_wiener<16>" : "dwt_fwd_wiener<8>", bytes, s,
                    (double)planes * n_r * n_c * fwd_flops_per_px(taps));
     if (taps == 16) {
@@ -881,21 +905,27 @@ hipError_t launch_dwt_inv(int taps, const Filter &f, const float *lvl, int hk, i
 
 hipError_t launch_dwt_inv_mle(int taps, const Filter &f, const float *lvl, int hk, int wk, bool zero_approx, int nb,
                               int C, const float *means, int H, int W, int off_r, int off_c, int acc_mode, void *A,
-                              void *B, hipStream_t s) {
+                              void *B, hipStream_t s, const unsigned char *means8) {
     const int tt = tile_choice(TK_MLE, taps, hk, wk);
-    MleArgs a{lvl, hk, wk, zero_approx ? 1 : 0, ceil_div(wk, tt), nb, C, means, H, W, off_r, off_c, A, B};
+    MleArgs a{lvl, hk, wk, zero_approx ? 1 : 0, ceil_div(wk, tt), nb, C, means, H, W, off_r, off_c, A, B, means8};
     dim3 grid((unsigned)tiles_for(tt, hk, wk), (unsigned)C);
     const double accb = acc_mode == PRNU_ACC_F32 ? 16.0 : 32.0;  // A and B, read + write
-    const double bytes = (double)nb * C * 4.0 * ((zero_approx ? 3.0 : 4.0) * (double)hk * wk + (double)H * W) +
+    const double bytes = (double)nb * C *
+                             (4.0 * (zero_approx ? 3.0 : 4.0) * (double)hk * wk + (means8 ? 1.0 : 4.0) * H * W) +
                          (double)C * H * W * accb;
     KernelTimer kt(taps == 16 ? "dwt_inv_mle<16>" : "dwt_inv_mle<8>", bytes, s,
                    (double)nb * C * (4.0 * hk * wk * inv_flops_per_px(taps) + 4.0 * H * W));
-#define PRNU_MLE(TP, T_)                                                                            \
-    do {                                                                                            \
-        if (acc_mode == PRNU_ACC_F64) dwt_inv_mle<TP, T_, PRNU_ACC_F64><<<grid, inv_nt(T_), 0, s>>>(a, f);  \
-        else if (acc_mode == PRNU_ACC_KAHAN_F32)                                                    \
-            dwt_inv_mle<TP, T_, PRNU_ACC_KAHAN_F32><<<grid, inv_nt(T_), 0, s>>>(a, f);                      \
-        else dwt_inv_mle<TP, T_, PRNU_ACC_F32><<<grid, inv_nt(T_), 0, s>>>(a, f);                           \
+#define PRNU_MLE_U(TP, T_, U)                                                                              \
+    do {                                                                                                   \
+        if (acc_mode == PRNU_ACC_F64) dwt_inv_mle<TP, T_, PRNU_ACC_F64, U><<<grid, inv_nt(T_), 0, s>>>(a, f); \
+        else if (acc_mode == PRNU_ACC_KAHAN_F32)                                                           \
+            dwt_inv_mle<TP, T_, PRNU_ACC_KAHAN_F32, U><<<grid, inv_nt(T_), 0, s>>>(a, f);                  \
+        else dwt_inv_mle<TP, T_, PRNU_ACC_F32, U><<<grid, inv_nt(T_), 0, s>>>(a, f);                       \
+    } while (0)
+#define PRNU_MLE(TP, T_)                        \
+    do {                                        \
+        if (means8) PRNU_MLE_U(TP, T_, true);   \
+        else PRNU_MLE_U(TP, T_, false);         \
     } while (0)
     if (taps == 16) {
         if (tt == 16) PRNU_MLE(16, 16); else PRNU_MLE(16, 32);
@@ -903,6 +933,7 @@ hipError_t launch_dwt_inv_mle(int taps, const Filter &f, const float *lvl, int h
         if (tt == 16) PRNU_MLE(8, 16); else PRNU_MLE(8, 32);
     }
 #undef PRNU_MLE
+#undef PRNU_MLE_U
     return hipGetLastError();
 }
 

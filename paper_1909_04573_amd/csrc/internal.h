@@ -62,6 +62,10 @@ struct FwdArgs {
     int write_ll;
     float *ckpt;
     int64_t ckpt_stride;
+    // u8 frames [.][src_rows][src_cols][src8_c] read in place of `src` (plane
+    // p = channel p % src8_c of frame p / src8_c), or null
+    const unsigned char *src8;
+    int src8_c;
 };
 struct InvArgs {
     const float *lvl;
@@ -75,6 +79,8 @@ struct MleArgs {
     const float *means;
     int H, W, off_r, off_c;
     void *A, *B;
+    // u8 frames [nb][H][W][C] read in place of `means` (SDA depth 1), or null
+    const unsigned char *means8;
 };
 // One entry of a batched launch: `blocks` virtual workgroups starting at block0.
 struct FwdDesc {
@@ -122,7 +128,8 @@ hipError_t launch_sda(const void *frames, int dtype, int n_frames, int H, int W,
 hipError_t launch_dwt_fwd(int taps, const Filter &f, const float *src, int64_t src_stride,
                           int src_rows, int src_cols, int n_r, int n_c, int off_r, int off_c,
                           float *out, int planes, float s2, bool write_ll, hipStream_t s,
-                          float *ckpt = nullptr, int64_t ckpt_stride = 0);
+                          float *ckpt = nullptr, int64_t ckpt_stride = 0, const unsigned char *src8 = nullptr,
+                          int src8_c = 0);
 
 enum InvEpilogue { INV_PLANE = 0, INV_RESID = 1, INV_MLE = 2 };
 
@@ -139,7 +146,8 @@ hipError_t launch_dwt_inv(int taps, const Filter &f, const float *lvl, int hk, i
 // means[f][c] ([nb][C][H][W]).
 hipError_t launch_dwt_inv_mle(int taps, const Filter &f, const float *lvl, int hk, int wk,
                               bool zero_approx, int nb, int C, const float *means, int H, int W,
-                              int off_r, int off_c, int acc_mode, void *A, void *B, hipStream_t s);
+                              int off_r, int off_c, int acc_mode, void *A, void *B, hipStream_t s,
+                              const unsigned char *means8 = nullptr);
 
 // Batched (work-queue) launches of one tile size tt: every workgroup of a
 // grid of `grid` takes virtual blocks from *ctr until `total`; *ctr must be
