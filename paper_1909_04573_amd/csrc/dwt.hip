@@ -710,7 +710,10 @@ template <int TAPS, int TT>
 __global__ __launch_bounds__(fwd_nt(TT)) void dwt_fwd_wiener(FwdArgs a, Filter f) {
     __shared__ __align__(16) float lds[FwdGeom<TAPS, TT>::LDS];
     int tile, plane;
-    grid_tile(tile, plane);
+    if (a.src8 && a.src8_c > 1)
+        grid_tile_channels(tile, plane, a.src8_c);
+    else
+        grid_tile(tile, plane);
     fwd_body<TAPS, TT>(a, tile, plane, lds, f);
 }
 

@@ -53,6 +53,16 @@ __device__ __forceinline__ void grid_tile(int &tile, int &plane) {
     plane = v / tiles;
     tile = v - plane * tiles;
 }
+// The same for planes that are the C interleaved channels of frames: the C
+// channels of one tile are consecutive virtual blocks (same XCD, close in
+// time), so the frame bytes they share come from one L2 fill.
+__device__ __forceinline__ void grid_tile_channels(int &tile, int &plane, int C) {
+    const int tiles = (int)gridDim.x;
+    const int v = xcd_order((int)(blockIdx.x + blockIdx.y * gridDim.x), (int)(gridDim.x * gridDim.y));
+    const int frame = v / (tiles * C), r = v - frame * (tiles * C);
+    tile = r / C;
+    plane = frame * C + (r - tile * C);
+}
 
 template <int NTH, int KB, typename T, typename Load, typename Store>
 __device__ __forceinline__ void staged_copy(int tid, int count, Load load, Store store) {
