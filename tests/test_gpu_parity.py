@@ -108,6 +108,7 @@ ACC_CASES = [
     ("tiny d=1", 8, 256, 256, 1, 1),
     ("tiny d=4", 8, 256, 256, 1, 4),
     ("rgb ragged remainder", 10, 72, 104, 3, 4),
+    ("rgb d=1 frames read in place", 10, 72, 104, 3, 1),
     ("d=3", 9, 64, 80, 1, 3),
     ("many batches", 80, 48, 48, 1, 2),  # 40 SDA frames: a batch of 32 and a ragged one of 8
 ]
@@ -164,6 +165,19 @@ def test_streaming_calls_add_up(dev):
     prnu.fingerprint_accumulate(t[8:].contiguous(), 4, A2, B2)
     np.testing.assert_allclose(down(A2), down(A1), rtol=0, atol=1e-12 * float(np.abs(down(A1)).max()))
     np.testing.assert_array_equal(down(B2), down(B1))
+
+
+def test_depth_one_u8_frames_read_in_place(dev):
+    """At d = 1 the u8 frames are read in place (no means written); the same
+    frames as float32 go through the SDA kernel: identical accumulators."""
+    _log("d=1 u8 in place vs f32 frames")
+    fr = _frames_for(7, 72, 104, 3, 11)
+    A8, B8 = prnu.new_accumulators(3, 72, 104, device=dev)
+    prnu.fingerprint_accumulate(up(fr, dev), 1, A8, B8)
+    Af, Bf = prnu.new_accumulators(3, 72, 104, device=dev)
+    prnu.fingerprint_accumulate(up(fr.astype(np.float32), dev), 1, Af, Bf)
+    np.testing.assert_array_equal(down(A8), down(Af))
+    np.testing.assert_array_equal(down(B8), down(Bf))
 
 
 def test_depth_one_equals_per_frame_residuals(dev):
