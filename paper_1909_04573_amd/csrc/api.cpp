@@ -132,12 +132,13 @@ int run_post(const float *in, int nf, int C, int H, int W, int flags, float sigm
         PRNU_HIP(launch_twiddles(W, pw.tw_w, s));
     }
     if (sigma_wf < 0.f) PRNU_HIP(launch_plane_variance(dst, nout, N, pw.var, pw.red, s));
-    PRNU_HIP(launch_real_to_complex(dst, nout, N, pw.Z, s));
-    PRNU_HIP(launch_fft2(pw.Z, nout, H, W, ph, pwl, pw.tw_h, pw.tw_w, -1, s));
+    // the forward rows pass reads the real planes, the inverse columns pass
+    // stores the real part, scaled by 1/N
+    PRNU_HIP(launch_fft2(pw.Z, nout, H, W, ph, pwl, pw.tw_h, pw.tw_w, -1, s, dst));
     PRNU_HIP(launch_spectral_wiener(pw.Z, nout, H, W, pw.var, sigma_wf < 0.f ? -1.f : sigma_wf * sigma_wf,
                                     pw.G, s));
-    PRNU_HIP(launch_fft2(pw.G, nout, H, W, ph, pwl, pw.tw_h, pw.tw_w, +1, s));
-    PRNU_HIP(launch_complex_real(pw.G, nout, N, (float)(1.0 / (double)N), out, s));
+    PRNU_HIP(launch_fft2(pw.G, nout, H, W, ph, pwl, pw.tw_h, pw.tw_w, +1, s, nullptr, out,
+                         (float)(1.0 / (double)N)));
     return PRNU_OK;
 }
 

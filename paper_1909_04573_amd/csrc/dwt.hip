@@ -11,14 +11,19 @@
 //       var = min_{w=3,5,7,9} max(0, box_w(c^2)/w^2 - s2)
 //       r   = c * s2 / (var + s2)
 //   It writes the approximation (input of the next level) and the residual
-//   detail coefficients r; the shrunk coefficients never touch HBM.
+//   detail coefficients r; the shrunk coefficients never touch HBM.  One LDS
+//   area holds in turn the input samples, the row-filtered bands and the
+//   squares, each pass keeping its results in registers across a barrier.
+//   Level 1 reads float planes or, at SDA depth 1, one channel of the u8
+//   frames themselves.
 //
 // Inverse level (synthesis): a workgroup owns a 2TT x 2TT output tile, stages
 //   the (TT+L/2-1)^2 coefficients of the four subbands it needs, synthesises
 //   columns then rows in LDS and either stores the plane (next level up),
 //   stores the cropped residual, or (level 1 of the fingerprint path) folds
 //   the MLE sums  A += W*I, B += I^2  over a batch of SDA frames in registers
-//   before one read-modify-write of the accumulators.
+//   (I the SDA means, or the u8 frames at depth 1) before one
+//   read-modify-write of the accumulators.
 //
 // Each level body is a device function of (tile, plane) working in an LDS
 // area handed to it, so the per-plane kernels (tile and plane from blockIdx)

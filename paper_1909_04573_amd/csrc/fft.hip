@@ -36,11 +36,15 @@ namespace {
 // One batch of 1-D transforms: vectors v0 .. v0+nvec-1 of `count`, element n
 // of vector v at base[v * vs + n * es].
 // FN, FV: length and vectors per workgroup fixed at compile time (FN = 0: the
-// runtime plan).
+// runtime plan).  With rin the input is real (rin at the same element
+// offsets, imaginary part 0); with rout only the real part, times rscale, is
+// stored, to rout at the same offsets.
 template <int FN, int FV>
 __global__ __launch_bounds__(FNT) void fft_1d(float2 *__restrict__ data, int Nrt, int count, int64_t es,
                                               int64_t vs, int64_t plane_stride, FftPlan plan,
-                                              const float2 *__restrict__ tw, float sigma) {
+                                              const float2 *__restrict__ tw, float sigma,
+                                              const float *__restrict__ rin, float *__restrict__ rout,
+                                              float rscale) {
     extern __shared__ float2 smem[];
     int blk, pl;
     grid_tile(blk, pl);  // neighbouring vector groups on one XCD: they share cache lines
@@ -57,14 +61,22 @@ __global__ __launch_bounds__(FNT) void fft_1d(float2 *__restrict__ data, int Nrt
         threadIdx.x, tot,
         [&](int e) {
             const int v = e & (nvec - 1), n = e >> lvec;
-            return (v0 + v < count) ? base[(int64_t)(v0 + v) * vs + (int64_t)n * es] : make_float2(0.f, 0.f);
+            const int64_t o = (int64_t)(v0 + v) * vs + (int64_t)n * es;
+            if (v0 + v >= count) return make_float2(0.f, 0.f);
+            return rin ? make_float2(rin[(int64_t)pl * plane_stride + o], 0.f) : base[o];
         },
         [&](int e, float2 z) { b0[e] = z; });
     __syncthreads();
     const float2 *res = fft_run<FN, FV>(b0, b1, plan, twl, sigma);
     for (int e = threadIdx.x; e < tot; e += FNT) {
         const int v = e & (nvec - 1), n = e >> lvec;
-        if (v0 + v < count) base[(int64_t)(v0 + v) * vs + (int64_t)n * es] = res[e];
+        const int64_t o = (int64_t)(v0 + v) * vs + (int64_t)n * es;
+        if (v0 + v < count) {
+            if (rout)
+                rout[(int64_t)pl * plane_stride + o] = res[e].x * rscale;
+            else
+                base[o] = res[e];
+        }
     }
 }
 
@@ -311,31 +323,34 @@ hipError_t launch_twiddles(int n, float2 *tw, hipStream_t s) {
 }
 
 hipError_t launch_fft2(float2 *data, int batch, int h, int w, const FftPlan &ph, const FftPlan &pw,
-                       const float2 *tw_h, const float2 *tw_w, int dir, hipStream_t s) {
+                       const float2 *tw_h, const float2 *tw_w, int dir, hipStream_t s, const float *rin,
+                       float *rout, float rscale) {
     const float sigma = dir < 0 ? -1.f : 1.f;
     const int64_t plane = (int64_t)h * w;
-    const double bytes = 16.0 * (double)batch * plane;  // read + write every complex element
+    // read + write every element: complex 8 B, real input or output 4 B
+    const double bytes_rows = (rin ? 12.0 : 16.0) * (double)batch * plane;
+    const double bytes_cols = (rout ? 12.0 : 16.0) * (double)batch * plane;
     // rows: h vectors of length w
     dim3 gr((unsigned)((h + pw.nvec - 1) / pw.nvec), (unsigned)batch);
     {
-        KernelTimer kt("fft_1d", bytes, s);
+        KernelTimer kt("fft_1d", bytes_rows, s);
         const Fft1dKernel k = pick_fft_1d(pw);
         const unsigned lds = fft_lds_bytes(pw, pw.n, k != fft_1d<0, 0>);
         hipError_t e = allow_lds(k, lds);
         if (e != hipSuccess) return e;
-        k<<<gr, FNT, lds, s>>>(data, w, h, 1, w, plane, pw, tw_w, sigma);
+        k<<<gr, FNT, lds, s>>>(data, w, h, 1, w, plane, pw, tw_w, sigma, rin, nullptr, 1.f);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // columns: w vectors of length h
     dim3 gc((unsigned)((w + ph.nvec - 1) / ph.nvec), (unsigned)batch);
     {
-        KernelTimer kt("fft_1d", bytes, s);
+        KernelTimer kt("fft_1d", bytes_cols, s);
         const Fft1dKernel k = pick_fft_1d(ph);
         const unsigned lds = fft_lds_bytes(ph, ph.n, k != fft_1d<0, 0>);
         e = allow_lds(k, lds);
         if (e != hipSuccess) return e;
-        k<<<gc, FNT, lds, s>>>(data, h, w, w, 1, plane, ph, tw_h, sigma);
+        k<<<gc, FNT, lds, s>>>(data, h, w, w, 1, plane, ph, tw_h, sigma, nullptr, rout, rscale);
     }
     return hipGetLastError();
 }

@@ -207,10 +207,12 @@ bool make_fft_plan(int n, FftPlan *p, bool columns = false);
 size_t fft_twiddle_floats(int n);  // complex table of n entries, 2 floats each
 hipError_t launch_twiddles(int n, float2 *tw, hipStream_t s);
 // In-place 2-D complex FFT on `batch` planes [h][w] (plane stride h*w).
-// dir = -1 forward, +1 inverse (unnormalised).
+// dir = -1 forward, +1 inverse (unnormalised).  With rin the rows pass reads
+// the real planes rin [batch][h][w] instead of data; with rout the columns
+// pass stores only rscale * the real part, to rout [batch][h][w].
 hipError_t launch_fft2(float2 *data, int batch, int h, int w, const FftPlan &ph,
                        const FftPlan &pw, const float2 *tw_h, const float2 *tw_w, int dir,
-                       hipStream_t s);
+                       hipStream_t s, const float *rin = nullptr, float *rout = nullptr, float rscale = 1.f);
 
 // Real rows -> half spectra [n][h][w/2+1] (w even, phalf planned for w/2).
 // Plane p is Y[(p0+p) % ny], times mod[(p0+p) / ny] when mod is given, minus
@@ -231,8 +233,6 @@ hipError_t launch_fft_cols_power(const float2 *S, int n, int h, int Mc, const Ff
 size_t reduce_scratch_doubles(int n, int64_t N);
 hipError_t launch_plane_variance(const float *x, int n, int64_t N, double *var, double *scratch,
                                  hipStream_t s);
-// Real planes [n][h][w] -> complex [n][h][w] (imaginary part 0).
-hipError_t launch_real_to_complex(const float *x, int n, int64_t N, float2 *z, hipStream_t s);
 // G = F * rho with rho the Wiener residual factor of |F|/sqrt(hw); noise
 // variance var[p] (per plane, device) or sigma2 >= 0 (host constant).
 // Bilinear resampling of n planes [n][H][W] to [n][oh][ow] (pixel centres,
@@ -243,9 +243,6 @@ hipError_t launch_resample_bilinear(const float *src, int n, int H, int W, doubl
 hipError_t launch_extract_blocks(const float *src, int n, int H, int W, int b, float *out, hipStream_t s);
 hipError_t launch_spectral_wiener(const float2 *F, int n, int h, int w, const double *var,
                                   float sigma2, float2 *G, hipStream_t s);
-// out[p][i] = Re(z[p][i]) * scale
-hipError_t launch_complex_real(const float2 *z, int n, int64_t N, float scale, float *out,
-                               hipStream_t s);
 
 // ---- PCE -------------------------------------------------------------------
 // Chunk plane p (0 <= p < n) is Y[(p0+p) % ny], times mod[(p0+p) / ny] when mod

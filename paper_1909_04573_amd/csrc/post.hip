@@ -184,18 +184,6 @@ __global__ void plane_finish_kernel(const double *__restrict__ part, int n, int6
     out[p] = s / (double)N;
 }
 
-__global__ __launch_bounds__(NT) void r2c_kernel(const float *__restrict__ x, int64_t n,
-                                                 float2 *__restrict__ z) {
-    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (i < n) z[i] = make_float2(x[i], 0.f);
-}
-
-__global__ __launch_bounds__(NT) void c2r_kernel(const float2 *__restrict__ z, int64_t n, float scale,
-                                                 float *__restrict__ x) {
-    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (i < n) x[i] = z[i].x * scale;
-}
-
 // DFT-domain Wiener: tile of T x T bins with a 4-bin margin; q = |F|^2 / N
 // (zero outside the array), G = F * rho.
 constexpr int WT = 32, WH = 4, WNC = WT + 2 * WH, WNCS = WNC + 1;
@@ -301,18 +289,6 @@ hipError_t launch_plane_variance(const float *x, int n, int64_t N, double *var, 
     plane_finish_kernel<<<(n + 63) / 64, 64, 0, s>>>(part, n, N, mean);
     plane_partial_kernel<<<g, NT, 0, s>>>(x, N, mean, part);
     plane_finish_kernel<<<(n + 63) / 64, 64, 0, s>>>(part, n, N, var);
-    return hipGetLastError();
-}
-
-hipError_t launch_real_to_complex(const float *x, int n, int64_t N, float2 *z, hipStream_t s) {
-    KernelTimer kt("real_to_complex", 12.0 * (double)n * N, s);
-    r2c_kernel<<<blocks((int64_t)n * N), NT, 0, s>>>(x, (int64_t)n * N, z);
-    return hipGetLastError();
-}
-
-hipError_t launch_complex_real(const float2 *z, int n, int64_t N, float scale, float *out, hipStream_t s) {
-    KernelTimer kt("complex_real", 12.0 * (double)n * N, s);
-    c2r_kernel<<<blocks((int64_t)n * N), NT, 0, s>>>(z, (int64_t)n * N, scale, out);
     return hipGetLastError();
 }
 
