@@ -8,6 +8,13 @@ summaries of PCE values the library computed; no method arithmetic.
   (0, 0) to (1, 1);
 * auc(matched, unmatched): area under that curve, equal to the probability
   that a same-camera PCE exceeds a different-camera one (ties count 1/2).
+
+Stabilised video (Sec. V-F), orchestration of library calls:
+
+* segment_shifts(W, I, K_ref): per SDA frame, the translation of a reference
+  fingerprint with the largest fixed-peak PCE;
+* aligned_fingerprint(means, shifts, A, B): MLE over the SDA frames
+  translated back by their shifts.
 """
 from __future__ import annotations
 
@@ -51,3 +58,134 @@ def auc(matched, unmatched) -> float:
     below = np.searchsorted(us, m, side="left")
     equal = np.searchsorted(us, m, side="right") - below
     return float((below.sum() + 0.5 * equal.sum()) / (m.size * u.size))
+
+
+# ---------------------------------------------------------------- stabilised video (Sec. V-F)
+def smooth_floor(n: int) -> int:
+    """Largest m <= n with no prime factor above 5 (a size the DFT Wiener
+    step of the fingerprint post-processing accepts)."""
+    for m in range(int(n), 0, -1):
+        r = m
+        for q in (2, 3, 5):
+            while r % q == 0:
+                r //= q
+        if r == 1:
+            return m
+    raise ValueError("n must be >= 1")
+
+
+def aligned_window(H: int, W: int, M: int):
+    """Size (h, w) of aligned fingerprints of H x W frames whose shifts are
+    within M: the largest 5-smooth sizes inside [M, H - M) x [M, W - M)."""
+    return smooth_floor(H - 2 * M), smooth_floor(W - 2 * M)
+
+
+def segment_shifts(W, I, K_ref, max_shift: int = 8, margin: int = 60, origin: int = 0):
+    """Per-segment alignment search for stabilised video (Sec. V-F): the
+    sensor pattern of SDA frame j (residual W[j], intensity I[j], planes
+    [g][H][W] float32 on the GPU) is compared with every integer translation
+    (dy, dx), |dy|, |dx| <= max_shift, of the reference fingerprint K_ref,
+    whose pixel (0, 0) sits at frame pixel (origin, origin):
+    candidate(y, x) = K_ref(y - origin + dy, x - origin + dx), cut out by
+    prnu_resample_bilinear at scale 1, and the fixed-peak PCE of W[j] against
+    I[j] * candidate picks the translation.  A `margin` is left out of the
+    correlations (the denoiser's boundary pattern) and must cover the search:
+    margin >= origin + max_shift.  Every step runs in the library (the
+    cut-outs and one pce_match call); the argmax is on the host.  Returns
+    (shifts int [g][2], pce float64 [g][(2 max_shift + 1)^2]) with candidate
+    k = (dy, dx) = divmod(k, 2 max_shift + 1) - max_shift."""
+    import torch
+
+    from . import prnu
+
+    g, H, Wd = (int(v) for v in W.shape)
+    n = 2 * max_shift + 1
+    h, w = H - 2 * margin, Wd - 2 * margin
+    o = margin - origin
+    if o - max_shift < 0 or o + max_shift + h > K_ref.shape[-2] or o + max_shift + w > K_ref.shape[-1]:
+        raise ValueError("the search window leaves the reference fingerprint")
+    cands = torch.empty((n * n, h, w), dtype=torch.float32, device=W.device)
+    for k in range(n * n):
+        dy, dx = k // n - max_shift, k % n - max_shift
+        cands[k] = prnu.resample_bilinear(K_ref, 1.0, h, w, o + dy, o + dx)
+    Wc = W[:, margin:H - margin, margin:Wd - margin].contiguous()
+    Ic = I[:, margin:H - margin, margin:Wd - margin].contiguous()
+    P, _, _ = prnu.pce_match(Wc, cands, Ic, peak_mode=prnu.PEAK_FIXED_00, want_ncc=False, want_peak=False)
+    P = P.cpu().numpy()
+    best = np.argmax(P, axis=1)
+    shifts = np.stack([best // n - max_shift, best % n - max_shift], axis=1).astype(np.int64)
+    return shifts, P
+
+
+def self_aligned_shifts(means, W, params=None, ws=None, max_shift: int = 8, margin: int = 60):
+    """Per-segment translations of a stabilised video found with no reference
+    from outside it (Sec. V-F).  A frame's own residual must not be in the
+    fingerprint it is searched against: its noise would match itself at zero
+    shift far above the sensor pattern.  So the SDA frames (means, residuals W
+    [g][H][W] float32) are split into interleaved halves a and b: b is
+    searched against a's MLE fingerprint (its dominant pose), then a against
+    b's fingerprint aligned that way, then b again against a's aligned
+    fingerprint, so both halves end in one common frame.  That frame is moved
+    onto the most common estimated translation, the pose of the uncorrected
+    frames when those are the most frequent.  The reference fingerprints
+    cover aligned_window(H, W, max_shift) from frame pixel (max_shift,
+    max_shift), and the searched area must lie inside them.  Returns (shifts
+    int [g][2] in the convention of segment_shifts, ok bool [g]): a segment
+    whose shift after the move leaves the searched range is not ok (its pose
+    disagrees with the others; it is left out of an aligned fingerprint)."""
+    import torch
+
+    from . import prnu
+
+    g, H, Wd = (int(v) for v in means.shape)
+    M = max_shift
+    est = np.zeros((g, 2), dtype=np.int64)
+    if g < 2:
+        return est, np.ones(g, dtype=bool)
+    a, b = np.arange(0, g, 2), np.arange(1, g, 2)
+    A, B = prnu.new_accumulators(1, *aligned_window(H, Wd, M), device=means.device)
+
+    def ref(idx):
+        A.zero_()
+        B.zero_()
+        aligned_fingerprint(means[torch.as_tensor(idx, device=means.device)], est[idx], A, B, M, params, ws)
+        return prnu.fingerprint_finalize(A, B)
+
+    def search(idx, K):
+        t = torch.as_tensor(idx, device=means.device)
+        est[idx] = segment_shifts(W[t], means[t], K, max_shift, margin, origin=M)[0]
+
+    search(b, ref(a))
+    search(a, ref(b))
+    search(b, ref(a))
+    u, cnt = np.unique(est, axis=0, return_counts=True)
+    top = u[cnt == cnt.max()]  # ties: the smallest move from the anchor half's pose
+    m = top[np.lexsort((np.abs(top).sum(axis=1), np.abs(top).max(axis=1)))[0]]
+    est = est - m
+    return est, np.abs(est).max(axis=1) <= max_shift
+
+
+def aligned_fingerprint(means, shifts, A, B, M: int, params=None, ws=None):
+    """MLE over SDA frames after alignment: SDA frame j (means [g][H][W]
+    float32) is translated back by its segment's shift (dy, dx), |dy|, |dx|
+    <= M, and cut to a window of h x w frame pixels starting at (M, M):
+    aligned(y, x) = mean(y + M - dy, x + M - dx), so its sensor pattern lines
+    up with the reference pose; the windows are accumulated as frames of
+    depth 1 into A, B of [1][h][w] (updated in place; h <= H - 2M,
+    w <= W - 2M, normally aligned_window(H, W, M))."""
+    import torch
+
+    from . import prnu
+
+    g, H, Wd = (int(v) for v in means.shape)
+    if np.abs(np.asarray(shifts)).max(initial=0) > M:
+        raise ValueError("a shift exceeds the window margin M")
+    h, w = (int(v) for v in A.shape[-2:])
+    if h > H - 2 * M or w > Wd - 2 * M:
+        raise ValueError("the accumulators exceed the window inside the margin M")
+    al = torch.empty((g, h, w, 1), dtype=torch.float32, device=means.device)
+    for j in range(g):
+        dy, dx = int(shifts[j, 0]), int(shifts[j, 1])
+        al[j, :, :, 0] = prnu.resample_bilinear(means[j], 1.0, h, w, M - dy, M - dx)
+    prnu.fingerprint_accumulate(al, 1, A, B, params, ws=ws)
+    return A, B

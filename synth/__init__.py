@@ -366,14 +366,18 @@ def mixed_media_camera_torch(cam: int, n_video: int, n_still: int, Hs: int = 225
 
 def stabilized_video_torch(cam: int, vid: int, n: int, H: int = 1080, W: int = 1920, k_std: float = 0.0004,
                            p_still: float = 0.3, max_shift: int = 8, noise_std: float = 2.0, device="cuda",
-                           cfg: int = CFG_EVAL):
+                           cfg: int = CFG_EVAL, segment: int = 0):
     """A digitally stabilised gray video: the scene is a random-walk crop of a
     per-video texture (as in the video generator); each frame's sensor
     pattern reaches the output translated by the stabiliser, by (0, 0) with
     probability p_still and otherwise by an integer shift uniform in
     [-max_shift, max_shift]^2 (a translation-only stand-in for the in-camera
-    warps).  I = I0 (1 + K shifted) + N(0, noise_std^2), rounded.  Returns
-    (uint8 [n][H][W][1] on device, K float64 [H][W], shifts int [n][2])."""
+    warps).  With segment > 0 the translation is drawn once per run of
+    `segment` frames (a stabiliser whose correction holds over a segment),
+    from a stream of its own, so the per-frame draws are unchanged.
+    I = I0 (1 + K shifted) + N(0, noise_std^2), rounded; the pattern of a
+    frame with shift (sy, sx) is K rolled by (sy, sx).  Returns (uint8
+    [n][H][W][1] on device, K float64 [H][W], shifts int [n][2])."""
     import torch
 
     K = camera_prnu((H, W), k_std, cfg, cam, 0x57AB)
@@ -386,6 +390,13 @@ def stabilized_video_torch(cam: int, vid: int, n: int, H: int = 1080, W: int = 1
     still = g.uniform(size=n) < p_still
     shifts = g.integers(-max_shift, max_shift + 1, size=(n, 2))
     shifts[still] = 0
+    if segment > 0:
+        gs = rng(cfg, cam, 0x57AB, vid, 0x5E6)
+        nseg = (n + segment - 1) // segment
+        sstill = gs.uniform(size=nseg) < p_still
+        ss = gs.integers(-max_shift, max_shift + 1, size=(nseg, 2))
+        ss[sstill] = 0
+        shifts = np.repeat(ss, segment, axis=0)[:n]
     gen = torch.Generator(device=device)
     gen.manual_seed((MASTER_SEED * 17 + cfg * 7919 + cam * 104729 + vid * 131) % (2**63))
     out = torch.empty((n, H, W, 1), dtype=torch.uint8, device=device)

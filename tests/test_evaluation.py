@@ -34,3 +34,17 @@ def test_auc_extremes_and_ties():
     assert ev.auc([3, 4], [1, 2]) == 1.0
     assert ev.auc([1, 2], [3, 4]) == 0.0
     assert ev.auc([1, 1], [1, 1]) == 0.5
+
+
+def test_smooth_floor_and_aligned_window():
+    """Brute force: the largest size <= n whose prime factors are 2, 3 and 5."""
+    def smooth(m):
+        for q in (2, 3, 5):
+            while m % q == 0:
+                m //= q
+        return m == 1
+    for n in range(1, 400):
+        m = ev.smooth_floor(n)
+        assert m <= n and smooth(m) and not any(smooth(k) for k in range(m + 1, n + 1))
+    assert ev.aligned_window(1080, 1920, 8) == (1024, 1875)
+    assert ev.aligned_window(256, 256, 3) == (250, 250)

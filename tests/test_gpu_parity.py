@@ -487,3 +487,42 @@ def test_video_1080p_rgb_sample(dev):
         ref.append(correlate.pce(Wr, Ir * Kr)["pce"])
     assert_pce(down(pce)[:, 0], ref)
     _log(f"1080p pce gpu {down(pce)[:, 0]} oracle {ref}")
+
+
+def test_stabilised_segments_aligned(dev):
+    """Segment-constant stabiliser (Sec. V-F): the alignment search finds each
+    segment's translation against the camera's pattern, and the aligned MLE
+    fingerprint correlates with K better than the unaligned one."""
+    from paper_1909_04573_amd import evaluation as ev
+
+    _log("stabilised segments: alignment search")
+    H = W = 256
+    fr, K, sh = synth.stabilized_video_torch(1, 0, 80, H, W, k_std=0.02, max_shift=3, device=dev,
+                                             cfg=synth.CFG_TEST, segment=10)
+    seg = sh[::10]
+    assert np.any(seg != 0) and np.any(np.all(seg == 0, axis=1))
+    _, means = prnu.sda_average(fr, 10, want_sums=False)
+    means = means[:, 0].contiguous()
+    Wr = prnu.denoise_residual(means)
+    Kt = torch.from_numpy(K.astype(np.float32)).to(dev)
+    est, P = ev.segment_shifts(Wr, means, Kt, max_shift=3, margin=8)
+    # the pattern of a frame shifted by (sy, sx) is K rolled by (sy, sx): candidate (-sy, -sx)
+    np.testing.assert_array_equal(est, -seg)
+    M = 3
+    assert ev.aligned_window(H, W, M) == (250, 250)
+    A, B = prnu.new_accumulators(1, 250, 250, device=dev)
+    ev.aligned_fingerprint(means, est, A, B, M)
+    Ka = down(prnu.fingerprint_finalize(A, B, flags=0))  # pixel (0, 0) is frame pixel (M, M)
+    A0, B0 = prnu.new_accumulators(1, H, W, device=dev)
+    prnu.fingerprint_accumulate(fr, 10, A0, B0)
+    K0 = down(prnu.fingerprint_finalize(A0, B0, flags=0))
+    c, ca = slice(8, H - 8), slice(8 - M, H - 8 - M)
+    corr = lambda a, s: float(np.corrcoef(a[s, s].ravel(), K[c, c].ravel())[0, 1])
+    print(f"corr aligned {corr(Ka, ca):.3f} unaligned {corr(K0, c):.3f}", flush=True)
+    assert corr(Ka, ca) > corr(K0, c) + 0.1
+    # no outside reference: halves searched against each other, then put on the
+    # most common pose (three of the eight segments of this seed are uncorrected)
+    assert np.sum(np.all(seg == 0, axis=1)) == 3
+    est2, ok = ev.self_aligned_shifts(means, Wr, max_shift=3, margin=8)
+    np.testing.assert_array_equal(est2, -seg)
+    assert ok.all()
