@@ -80,7 +80,8 @@ def aligned_window(H: int, W: int, M: int):
     return smooth_floor(H - 2 * M), smooth_floor(W - 2 * M)
 
 
-def segment_shifts(W, I, K_ref, max_shift: int = 8, margin: int = 60, origin: int = 0):
+def segment_shifts(W, I, K_ref, max_shift: int = 8, margin: int = 60, origin: int = 0,
+                   pce_min: float | None = None):
     """Per-segment alignment search for stabilised video (Sec. V-F): the
     sensor pattern of SDA frame j (residual W[j], intensity I[j], planes
     [g][H][W] float32 on the GPU) is compared with every integer translation
@@ -90,8 +91,14 @@ def segment_shifts(W, I, K_ref, max_shift: int = 8, margin: int = 60, origin: in
     prnu_resample_bilinear at scale 1, and the fixed-peak PCE of W[j] against
     I[j] * candidate picks the translation.  A `margin` is left out of the
     correlations (the denoiser's boundary pattern) and must cover the search:
-    margin >= origin + max_shift.  Every step runs in the library (the
-    cut-outs and one pce_match call); the argmax is on the host.  Returns
+    margin >= origin + max_shift.  With pce_min, a frame whose best PCE stays
+    below it keeps the zero shift: a frame of another camera would otherwise
+    take the translation that best matches the reference's noise, and those
+    choices add up in the aligned fingerprint's PCE against the reference
+    (pce_min = 25 is a 5-sigma peak; the chance that one of (2 max_shift +
+    1)^2 noise candidates reaches it is about 1e-4 per frame at max_shift 8).
+    Every step runs in the library (the cut-outs and one pce_match call); the
+    argmax is on the host.  Returns
     (shifts int [g][2], pce float64 [g][(2 max_shift + 1)^2]) with candidate
     k = (dy, dx) = divmod(k, 2 max_shift + 1) - max_shift."""
     import torch
@@ -114,55 +121,9 @@ def segment_shifts(W, I, K_ref, max_shift: int = 8, margin: int = 60, origin: in
     P = P.cpu().numpy()
     best = np.argmax(P, axis=1)
     shifts = np.stack([best // n - max_shift, best % n - max_shift], axis=1).astype(np.int64)
+    if pce_min is not None:
+        shifts[P[np.arange(g), best] < pce_min] = 0
     return shifts, P
-
-
-def self_aligned_shifts(means, W, params=None, ws=None, max_shift: int = 8, margin: int = 60):
-    """Per-segment translations of a stabilised video found with no reference
-    from outside it (Sec. V-F).  A frame's own residual must not be in the
-    fingerprint it is searched against: its noise would match itself at zero
-    shift far above the sensor pattern.  So the SDA frames (means, residuals W
-    [g][H][W] float32) are split into interleaved halves a and b: b is
-    searched against a's MLE fingerprint (its dominant pose), then a against
-    b's fingerprint aligned that way, then b again against a's aligned
-    fingerprint, so both halves end in one common frame.  That frame is moved
-    onto the most common estimated translation, the pose of the uncorrected
-    frames when those are the most frequent.  The reference fingerprints
-    cover aligned_window(H, W, max_shift) from frame pixel (max_shift,
-    max_shift), and the searched area must lie inside them.  Returns (shifts
-    int [g][2] in the convention of segment_shifts, ok bool [g]): a segment
-    whose shift after the move leaves the searched range is not ok (its pose
-    disagrees with the others; it is left out of an aligned fingerprint)."""
-    import torch
-
-    from . import prnu
-
-    g, H, Wd = (int(v) for v in means.shape)
-    M = max_shift
-    est = np.zeros((g, 2), dtype=np.int64)
-    if g < 2:
-        return est, np.ones(g, dtype=bool)
-    a, b = np.arange(0, g, 2), np.arange(1, g, 2)
-    A, B = prnu.new_accumulators(1, *aligned_window(H, Wd, M), device=means.device)
-
-    def ref(idx):
-        A.zero_()
-        B.zero_()
-        aligned_fingerprint(means[torch.as_tensor(idx, device=means.device)], est[idx], A, B, M, params, ws)
-        return prnu.fingerprint_finalize(A, B)
-
-    def search(idx, K):
-        t = torch.as_tensor(idx, device=means.device)
-        est[idx] = segment_shifts(W[t], means[t], K, max_shift, margin, origin=M)[0]
-
-    search(b, ref(a))
-    search(a, ref(b))
-    search(b, ref(a))
-    u, cnt = np.unique(est, axis=0, return_counts=True)
-    top = u[cnt == cnt.max()]  # ties: the smallest move from the anchor half's pose
-    m = top[np.lexsort((np.abs(top).sum(axis=1), np.abs(top).max(axis=1)))[0]]
-    est = est - m
-    return est, np.abs(est).max(axis=1) <= max_shift
 
 
 def aligned_fingerprint(means, shifts, A, B, M: int, params=None, ws=None):
