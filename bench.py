@@ -1345,7 +1345,9 @@ def stab_main(args):
         log(f"segment stabiliser L={L}: shifts recovered on matched pairs {recov[str(L)]:.3f}")
     res = {"metric": "TPR at PCE > 60 between fingerprints of stabilised videos of the same camera",
            "workload": f"{ncam} gray cameras x {nvid} stabilised videos x {nmax} frames {W}x{H}; K ~ N(0, 0.0004^2); "
-                       "translation-only stabilisation (still with p = 0.3, else up to 8 px)",
+                       "translation-only stabilisation (still with p = 0.3, else up to 8 px); the segment "
+                       "stabiliser holds one translation per 30 frames, and its aligned type searches each SDA "
+                       "frame against the other video's fingerprint",
            "types": out,
            "segment_stabiliser": {"segment_frames": S, "types": seg_out,
                                   "shifts_recovered_on_matched_pairs": recov}}
