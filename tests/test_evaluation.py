@@ -48,3 +48,44 @@ def test_smooth_floor_and_aligned_window():
         assert m <= n and smooth(m) and not any(smooth(k) for k in range(m + 1, n + 1))
     assert ev.aligned_window(1080, 1920, 8) == (1024, 1875)
     assert ev.aligned_window(256, 256, 3) == (250, 250)
+
+
+def test_segment_stabiliser_draws():
+    """Synthetic segment stabiliser: one translation per run of frames, drawn
+    from a stream of its own (the per-frame stabiliser's draws and the frames
+    of still segments are unchanged), and a frame's pattern is K rolled by its
+    translation."""
+    import synth
+    import torch
+
+    n, H, W = 25, 24, 32
+    fr0, K, sh0 = synth.stabilized_video_torch(0, 1, n, H, W, k_std=0.02, max_shift=3, device="cpu",
+                                                cfg=synth.CFG_TEST)
+    fr1, K1, sh1 = synth.stabilized_video_torch(0, 1, n, H, W, k_std=0.02, max_shift=3, device="cpu",
+                                                cfg=synth.CFG_TEST, segment=10)
+    np.testing.assert_array_equal(K, K1)
+    assert sh1.shape == (n, 2) and np.abs(sh1).max() <= 3
+    for s in range(0, n, 10):
+        assert (sh1[s:s + 10] == sh1[s]).all()
+    assert len({tuple(r) for r in sh1[::10]}) > 1 or not sh1.any()
+    # frames with the same translation under both models are identical (same scene, noise draws)
+    for i in range(n):
+        if (sh0[i] == sh1[i]).all():
+            assert torch.equal(fr0[i], fr1[i])
+
+
+def test_alignment_helpers_refuse_windows_outside_the_reference():
+    """Argument checks of the alignment search run on the host before any
+    device work."""
+    import torch
+
+    W = torch.zeros((2, 64, 64))
+    with pytest.raises(ValueError, match="leaves the reference"):
+        ev.segment_shifts(W, W, torch.zeros((64, 64)), max_shift=8, margin=4)
+    with pytest.raises(ValueError, match="leaves the reference"):
+        ev.segment_shifts(W, W, torch.zeros((56, 56)), max_shift=4, margin=8, origin=2)  # 6 + 4 + 48 > 56
+    A = torch.zeros((1, 50, 50), dtype=torch.float64)
+    with pytest.raises(ValueError, match="exceeds the window margin"):
+        ev.aligned_fingerprint(W, np.array([[0, 0], [5, 0]]), A, A, 4)
+    with pytest.raises(ValueError, match="exceed the window"):
+        ev.aligned_fingerprint(W, np.zeros((2, 2), dtype=np.int64), torch.zeros((1, 60, 56)), A, 4)
