@@ -1296,7 +1296,7 @@ def stab_main(args):
             segsh.append(shv[::S])
     iu = np.triu_indices(nv, 1)
     same = vcam[iu[0]] == vcam[iu[1]]
-    seg_out, recov = {"sda30": {}, "sda30-aligned": {}}, {}
+    seg_out, recov = {}, {}
     for L in lengths:
         g = L // S
         K = torch.empty((nv, H, W), dtype=torch.float32, device=dev)
@@ -1313,36 +1313,42 @@ def stab_main(args):
         Kc = K[:, 60:H - 60, 60:W - 60].contiguous()
         P, _, _ = prnu.pce_match(Kc, Kc, None, peak_mode=prnu.PEAK_FIXED_00, want_ncc=False, want_peak=False)
         Pn = P.cpu().numpy()[iu]
-        Pa, rec, pair_ms = np.zeros(len(iu[0])), [], 0.0
+        search = {"sda30-aligned": ev.segment_shifts, "sda30-aligned-plane": ev.segment_shifts_plane}
+        Pa = {k: np.zeros(len(iu[0])) for k in search}
+        rec = {k: [] for k in search}
+        pair_ms = {k: 0.0 for k in search}
+        o = 60 - M  # aligned fingerprints: the same frame pixels [60, H - 60) x [60, W - 60)
         for k, (u, v) in enumerate(zip(*iu)):
-            e0.record(stream)
-            _, means = prnu.sda_average(segv[v, :L], S, want_sums=False)
-            means = means[:, 0].contiguous()
-            Wr = prnu.denoise_residual(means, p)
-            est, _ = ev.segment_shifts(Wr, means, K[u], max_shift=M, margin=60, pce_min=25.0)
-            Aa.zero_()
-            Ba.zero_()
-            ev.aligned_fingerprint(means, est, Aa, Ba, M, p, ws=ws)
-            Kal = prnu.fingerprint_finalize(Aa, Ba)
-            o = 60 - M  # the same frame pixels [60, H - 60) x [60, W - 60)
-            Pk, _, _ = prnu.pce_match(Kal[None, o:o + H - 120, o:o + W - 120].contiguous(), Kc[u:u + 1], None,
-                                      peak_mode=prnu.PEAK_FIXED_00, want_ncc=False, want_peak=False)
-            e1.record(stream)
-            Pa[k] = float(Pk.cpu()[0, 0])
-            pair_ms += e0.elapsed_time(e1)
-            if same[k]:
-                rec.append(float(np.mean(np.all(est == -segsh[v][:g], axis=1))))
-        recov[str(L)] = float(np.mean(rec))
-        for name, Pv, ms in (("sda30", Pn, naive_ms), ("sda30-aligned", Pa, pair_ms / len(Pa))):
+            for name, fn in search.items():
+                e0.record(stream)
+                _, means = prnu.sda_average(segv[v, :L], S, want_sums=False)
+                means = means[:, 0].contiguous()
+                Wr = prnu.denoise_residual(means, p)
+                est, _ = fn(Wr, means, K[u], max_shift=M, margin=60, pce_min=25.0)
+                Aa.zero_()
+                Ba.zero_()
+                ev.aligned_fingerprint(means, est, Aa, Ba, M, p, ws=ws)
+                Kal = prnu.fingerprint_finalize(Aa, Ba)
+                Pk, _, _ = prnu.pce_match(Kal[None, o:o + H - 120, o:o + W - 120].contiguous(), Kc[u:u + 1], None,
+                                          peak_mode=prnu.PEAK_FIXED_00, want_ncc=False, want_peak=False)
+                e1.record(stream)
+                Pa[name][k] = float(Pk.cpu()[0, 0])
+                pair_ms[name] += e0.elapsed_time(e1)
+                if same[k]:
+                    rec[name].append(float(np.mean(np.all(est == -segsh[v][:g], axis=1))))
+        for name in search:
+            recov.setdefault(name, {})[str(L)] = float(np.mean(rec[name]))
+        for name, Pv, ms in [("sda30", Pn, naive_ms)] + [(n, Pa[n], pair_ms[n] / len(iu[0])) for n in search]:
             matched, unmatched = Pv[same], Pv[~same]
-            seg_out[name][str(L)] = {
+            seg_out.setdefault(name, {})[str(L)] = {
                 "tpr": ev.tpr(matched), "fpr": ev.fpr(unmatched), "auc": ev.auc(matched, unmatched),
                 "matched_pce_median": float(np.median(matched)),
                 "unmatched_abs_pce_max": float(np.abs(unmatched).max()),
                 ("fingerprint_ms_per_video" if name == "sda30" else "ms_per_pair"): round(ms, 2)}
             log(f"segment stabiliser {name} L={L}: TPR {seg_out[name][str(L)]['tpr']:.3f} "
-                f"FPR {seg_out[name][str(L)]['fpr']:.3f} median PCE {seg_out[name][str(L)]['matched_pce_median']:.1f}")
-        log(f"segment stabiliser L={L}: shifts recovered on matched pairs {recov[str(L)]:.3f}")
+                f"FPR {seg_out[name][str(L)]['fpr']:.3f} median PCE {seg_out[name][str(L)]['matched_pce_median']:.1f}"
+                + ("" if name == "sda30" else f", shifts recovered on matched pairs {recov[name][str(L)]:.3f}, "
+                                              f"{seg_out[name][str(L)]['ms_per_pair']:.1f} ms per pair"))
     res = {"metric": "TPR at PCE > 60 between fingerprints of stabilised videos of the same camera",
            "workload": f"{ncam} gray cameras x {nvid} stabilised videos x {nmax} frames {W}x{H}; K ~ N(0, 0.0004^2); "
                        "translation-only stabilisation (still with p = 0.3, else up to 8 px); the segment "

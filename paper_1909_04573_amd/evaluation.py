@@ -126,6 +126,41 @@ def segment_shifts(W, I, K_ref, max_shift: int = 8, margin: int = 60, origin: in
     return shifts, P
 
 
+def segment_shifts_plane(W, I, K_ref, max_shift: int = 8, margin: int = 60, origin: int = 0,
+                         pce_min: float | None = None):
+    """The search of segment_shifts from one correlation plane per SDA frame.
+    With the reference cut to the frame's window as the query and the frame's
+    intensity as the modulation of its residual, the plane is
+    C(s) = sum_t K_ref(t + s) I[j](t) W[j](t) (circular over the window),
+    which is the candidate sum of segment_shifts at (dy, dx) = s, so one
+    pce_match call with the argmax peak per frame replaces the
+    (2 max_shift + 1)^2 candidates.  The peak is the largest C over the whole
+    plane; a frame keeps the zero shift where that peak lies outside
+    |dy|, |dx| <= max_shift or (with pce_min) its PCE stays below pce_min.
+    The window wraps at its edges (max_shift of its rows and columns).
+    Returns (shifts int [g][2], pce float64 [g] at the peak)."""
+    from . import prnu
+
+    g, H, Wd = (int(v) for v in W.shape)
+    h, w = H - 2 * margin, Wd - 2 * margin
+    o = margin - origin
+    if o < 0 or o + h > K_ref.shape[-2] or o + w > K_ref.shape[-1]:
+        raise ValueError("the search window leaves the reference fingerprint")
+    Kc = K_ref[None, o:o + h, o:o + w].contiguous()
+    Wc = W[:, margin:H - margin, margin:Wd - margin].contiguous()
+    Ic = I[:, margin:H - margin, margin:Wd - margin].contiguous()
+    shifts = np.zeros((g, 2), dtype=np.int64)
+    pce = np.zeros(g)
+    for j in range(g):
+        P, _, pk = prnu.pce_match(Kc, Wc[j:j + 1], Ic[j:j + 1], peak_mode=prnu.PEAK_ARGMAX, want_ncc=False)
+        r, c = (int(v) for v in pk.cpu()[0, 0])
+        dy, dx = (r - h if r > h // 2 else r), (c - w if c > w // 2 else c)
+        pce[j] = float(P.cpu()[0, 0])
+        if max(abs(dy), abs(dx)) <= max_shift and (pce_min is None or pce[j] >= pce_min):
+            shifts[j] = (dy, dx)
+    return shifts, pce
+
+
 def aligned_fingerprint(means, shifts, A, B, M: int, params=None, ws=None):
     """MLE over SDA frames after alignment: SDA frame j (means [g][H][W]
     float32) is translated back by its segment's shift (dy, dx), |dy|, |dx|

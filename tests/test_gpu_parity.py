@@ -508,6 +508,10 @@ def test_stabilised_segments_aligned(dev):
     est, P = ev.segment_shifts(Wr, means, Kt, max_shift=3, margin=8)
     # the pattern of a frame shifted by (sy, sx) is K rolled by (sy, sx): candidate (-sy, -sx)
     np.testing.assert_array_equal(est, -seg)
+    est_p, pce_p = ev.segment_shifts_plane(Wr, means, Kt, max_shift=3, margin=8)
+    np.testing.assert_array_equal(est_p, -seg)
+    # the same peak; the planes differ in which side carries the modulation and the mean
+    assert np.all(pce_p > 0.5 * P.max(axis=1)) and np.all(pce_p < 2.0 * P.max(axis=1))
     M = 3
     assert ev.aligned_window(H, W, M) == (250, 250)
     A, B = prnu.new_accumulators(1, 250, 250, device=dev)
