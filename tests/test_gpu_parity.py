@@ -370,7 +370,7 @@ def test_pce_blocks_vs_oracle(dev):
 
 @pytest.mark.parametrize("n,H,W,scale,oh,ow,oy,ox", [
     (2, 64, 96, 0.5, 32, 48, 0, 0), (1, 37, 53, 1.37, 60, 70, 3, 5), (3, 120, 200, 0.73, 80, 140, 2, 1),
-    (1, 2200, 3900, 0.5, 1080, 1920, 37, 61), (1, 17, 19, 2.0, 40, 40, 0, 0)])
+    (1, 2200, 3900, 0.5, 1080, 1920, 37, 61), (1, 17, 19, 2.0, 40, 40, 0, 0), (2, 40, 56, 1.0, 36, 50, 6, 9)])
 def test_resample_bilinear_vs_oracle(dev, n, H, W, scale, oh, ow, oy, ox):
     """Resizing and cropping of a query for mixed-media matching: downsampling,
     upsampling, crop offsets and clamped edges against the oracle."""

@@ -10,6 +10,18 @@ def test_identity_at_scale_one():
     np.testing.assert_array_equal(resample.bilinear(X, 1.0, 13, 17), X)
 
 
+def test_integer_offsets_at_scale_one_are_crops_with_edge_replication():
+    """What the translation search of stabilised video relies on: at scale 1 an
+    integer offset (oy, ox) reads X(y + oy, x + ox) exactly, clamped to the
+    plane beyond its edges."""
+    X = np.random.default_rng(4).normal(size=(15, 19))
+    np.testing.assert_array_equal(resample.bilinear(X, 1.0, 9, 11, 3, 5), X[3:12, 5:16])
+    Y = resample.bilinear(X, 1.0, 15, 19, 4, 2)
+    rows = np.minimum(np.arange(15) + 4, 14)
+    cols = np.minimum(np.arange(19) + 2, 18)
+    np.testing.assert_array_equal(Y, X[np.ix_(rows, cols)])
+
+
 def test_half_scale_is_the_two_by_two_mean():
     X = np.random.default_rng(2).normal(size=(12, 20))
     Y = resample.bilinear(X, 0.5, 6, 10)
