@@ -61,6 +61,23 @@ def test_wiener_dft_keeps_white_noise_and_kills_periodic_pattern():
     assert proj_in > 0.95 and abs(proj_out) < 0.1
 
 
+@pytest.mark.parametrize("sigma2", [None, 0.2])
+def test_wiener_dft_single_cosine_closed_form(sigma2):
+    """A cosine with whole periods has two isolated DFT bins of magnitude
+    |F| = a HW / 2, so M^2 = a^2 HW / 4 there and 0 elsewhere.  The largest
+    window (9 x 9) gives the smallest local mean M^2 / 81, so var_hat =
+    M^2 / 81 - s2 and rho = s2 / (M^2 / 81).  The output is rho times the
+    input.  s2 defaults to the cosine's population variance a^2 / 2."""
+    H, W, a = 48, 60, 1.7
+    yy, xx = np.mgrid[0:H, 0:W]
+    K = a * np.cos(2 * np.pi * (5 * yy / H + 9 * xx / W))
+    s2 = a * a / 2 if sigma2 is None else sigma2
+    M2 = a * a * H * W / 4
+    assert M2 / 81 > s2
+    rho = s2 / (M2 / 81)
+    np.testing.assert_allclose(pipeline.wiener_dft(K, sigma2=sigma2), rho * K, rtol=0, atol=1e-12)
+
+
 def test_postprocess_order_for_colour():
     P = np.stack([_f((16, 24), 8 + c) for c in range(3)])
     got = pipeline.postprocess(P, pipeline.FIN_ZM | pipeline.FIN_LUMA)
