@@ -126,6 +126,12 @@ def segment_shifts(W, I, K_ref, max_shift: int = 8, margin: int = 60, origin: in
     return shifts, P
 
 
+def signed_lag(i: int, n: int) -> int:
+    """Lag of index i of a circular correlation of length n, in
+    (-n/2, n/2]: i for i <= n // 2, else i - n."""
+    return i - n if i > n // 2 else i
+
+
 def segment_shifts_plane(W, I, K_ref, max_shift: int = 8, margin: int = 60, origin: int = 0,
                          pce_min: float | None = None):
     """The search of segment_shifts from one correlation plane per SDA frame.
@@ -154,7 +160,7 @@ def segment_shifts_plane(W, I, K_ref, max_shift: int = 8, margin: int = 60, orig
     for j in range(g):
         P, _, pk = prnu.pce_match(Kc, Wc[j:j + 1], Ic[j:j + 1], peak_mode=prnu.PEAK_ARGMAX, want_ncc=False)
         r, c = (int(v) for v in pk.cpu()[0, 0])
-        dy, dx = (r - h if r > h // 2 else r), (c - w if c > w // 2 else c)
+        dy, dx = signed_lag(r, h), signed_lag(c, w)
         pce[j] = float(P.cpu()[0, 0])
         if max(abs(dy), abs(dx)) <= max_shift and (pce_min is None or pce[j] >= pce_min):
             shifts[j] = (dy, dx)

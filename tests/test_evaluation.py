@@ -89,3 +89,18 @@ def test_alignment_helpers_refuse_windows_outside_the_reference():
         ev.aligned_fingerprint(W, np.array([[0, 0], [5, 0]]), A, A, 4)
     with pytest.raises(ValueError, match="exceed the window"):
         ev.aligned_fingerprint(W, np.zeros((2, 2), dtype=np.int64), torch.zeros((1, 60, 56)), A, 4)
+
+
+def test_signed_lag_of_a_circular_correlation():
+    """Index i of a circular correlation of length n is the lag i or i - n; a
+    brute-force circular correlation of a shifted copy peaks at its shift."""
+    assert [ev.signed_lag(i, 8) for i in range(8)] == [0, 1, 2, 3, 4, -3, -2, -1]
+    assert ev.signed_lag(952, 960) == -8 and ev.signed_lag(480, 960) == 480 and ev.signed_lag(481, 960) == -479
+    rng = np.random.default_rng(3)
+    y = rng.normal(size=(12, 15))
+    for sy, sx in [(3, -4), (-5, 2), (0, 7)]:
+        x = np.roll(y, (-sy, -sx), axis=(0, 1))  # x(t) = y(t + s)
+        # C(l) = sum_t x(t + l) y(t) peaks where t + l + s = t, at l = -s
+        C = np.array([[np.sum(np.roll(x, (-a, -b), axis=(0, 1)) * y) for b in range(15)] for a in range(12)])
+        r, c = np.unravel_index(np.argmax(C), C.shape)
+        assert (ev.signed_lag(r, 12), ev.signed_lag(c, 15)) == (-sy, -sx)
