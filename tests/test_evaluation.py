@@ -104,3 +104,78 @@ def test_signed_lag_of_a_circular_correlation():
         C = np.array([[np.sum(np.roll(x, (-a, -b), axis=(0, 1)) * y) for b in range(15)] for a in range(12)])
         r, c = np.unravel_index(np.argmax(C), C.shape)
         assert (ev.signed_lag(r, 12), ev.signed_lag(c, 15)) == (-sy, -sx)
+
+
+def _oracle_library(monkeypatch):
+    """Stand-ins for the two library calls of the segment searches, computed
+    by the oracle on host tensors: the host logic around them (cut-out
+    offsets, sign of the shifts, lag wrap, gate) is what these tests check."""
+    import torch
+
+    from oracle import correlate, resample
+    from paper_1909_04573_amd import prnu
+
+    def resample_bilinear(x, scale, oh, ow, oy=0, ox=0):
+        a = x.double().numpy()
+        out = [resample.bilinear(p, scale, oh, ow, oy, ox) for p in (a[None] if a.ndim == 2 else a)]
+        t = torch.from_numpy(np.stack(out)).float()
+        return t[0] if a.ndim == 2 else t
+
+    def pce_match(X, Y, modulate=None, peak_mode=0, nbhd=11, want_ncc=True, want_peak=True):
+        nx, ny = X.shape[0], Y.shape[0]
+        P = np.zeros((nx, ny))
+        pk = np.zeros((nx, ny, 2), dtype=np.int32)
+        for q in range(nx):
+            for j in range(ny):
+                y = Y[j].double().numpy() * (modulate[q].double().numpy() if modulate is not None else 1.0)
+                r = correlate.pce(X[q].double().numpy(), y, peak_mode, nbhd)
+                P[q, j], pk[q, j] = r["pce"], r["peak"]
+        return torch.from_numpy(P), None, torch.from_numpy(pk)
+
+    monkeypatch.setattr(prnu, "resample_bilinear", resample_bilinear)
+    monkeypatch.setattr(prnu, "pce_match", pce_match)
+
+
+def _shifted_frames(shifts, H=40, W=40, seed=11):
+    """Residuals whose sensor pattern is K rolled by each frame's shift."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    K = rng.normal(size=(H, W))
+    I = rng.uniform(50, 200, size=(len(shifts), H, W))
+    Wr = np.stack([I[j] * np.roll(K, tuple(s), axis=(0, 1)) + rng.normal(0, 5.0, size=(H, W))
+                   for j, s in enumerate(shifts)])
+    return torch.from_numpy(Wr).float(), torch.from_numpy(I).float(), torch.from_numpy(K).float()
+
+
+def test_segment_search_conventions_on_the_host(monkeypatch):
+    _oracle_library(monkeypatch)
+    true = np.array([[0, 0], [2, -1], [-2, 2], [1, 0]])
+    Wr, I, K = _shifted_frames(true)
+    est, P = ev.segment_shifts(Wr, I, K, max_shift=2, margin=6)
+    np.testing.assert_array_equal(est, -true)
+    assert P.shape == (4, 25) and P.max(axis=1).min() > 60
+    # a reference whose pixel (0, 0) is frame pixel (3, 3)
+    est_o, P_o = ev.segment_shifts(Wr, I, K[3:, 3:].contiguous(), max_shift=2, margin=6, origin=3)
+    np.testing.assert_array_equal(est_o, -true)
+    np.testing.assert_allclose(P_o, P)
+    # the plane search finds the same translations from one correlation per frame
+    est_p, pce_p = ev.segment_shifts_plane(Wr, I, K, max_shift=2, margin=6)
+    np.testing.assert_array_equal(est_p, -true)
+    assert pce_p.min() > 60
+
+
+def test_segment_search_gate_keeps_the_zero_shift(monkeypatch):
+    """Frames of another camera: no peak reaches the gate, every frame keeps
+    the zero shift; without the gate the argmax moves them."""
+    import torch
+
+    _oracle_library(monkeypatch)
+    Wr, I, _ = _shifted_frames(np.array([[1, 1], [-2, 0], [0, 2]]))
+    other = torch.from_numpy(np.random.default_rng(99).normal(size=(40, 40))).float()
+    est, P = ev.segment_shifts(Wr, I, other, max_shift=2, margin=6, pce_min=25.0)
+    assert P.max() < 25 and not est.any()
+    est_p, _ = ev.segment_shifts_plane(Wr, I, other, max_shift=2, margin=6, pce_min=25.0)
+    assert not est_p.any()
+    est_free, _ = ev.segment_shifts(Wr, I, other, max_shift=2, margin=6)
+    assert est_free.any()
