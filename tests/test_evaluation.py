@@ -179,3 +179,25 @@ def test_segment_search_gate_keeps_the_zero_shift(monkeypatch):
     assert not est_p.any()
     est_free, _ = ev.segment_shifts(Wr, I, other, max_shift=2, margin=6)
     assert est_free.any()
+
+
+def test_aligned_fingerprint_lines_patterns_up(monkeypatch):
+    """Frames whose pattern is K rolled by s_j, with their shifts estimated as
+    -s_j, are all translated onto K's window from (M, M) before the MLE (the
+    accumulation call is captured instead of run)."""
+    import torch
+
+    from paper_1909_04573_amd import prnu
+
+    _oracle_library(monkeypatch)
+    seen = {}
+    monkeypatch.setattr(prnu, "fingerprint_accumulate", lambda fr, d, A, B, p=None, ws=None: seen.update(fr=fr, d=d))
+    K = np.random.default_rng(5).normal(size=(30, 36))
+    s = np.array([[0, 0], [2, -3], [-3, 1]])
+    means = torch.from_numpy(np.stack([np.roll(K, tuple(v), axis=(0, 1)) for v in s])).float()
+    M = 3
+    A = torch.zeros((1, 24, 27), dtype=torch.float64)
+    ev.aligned_fingerprint(means, -s, A, A, M)
+    assert seen["d"] == 1 and tuple(seen["fr"].shape) == (3, 24, 27, 1)
+    for j in range(3):
+        np.testing.assert_array_equal(seen["fr"][j, :, :, 0].numpy(), K[M:M + 24, M:M + 27].astype(np.float32))
