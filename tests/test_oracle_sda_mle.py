@@ -125,3 +125,46 @@ def test_flat_vs_textured_depth_trend():
     assert abs(res[False, 32] / res[False, 1] - 1) < 0.03
     assert res[True, 1] > res[True, 4] > res[True, 32]
     assert res[True, 32] / res[True, 1] < 0.95
+
+
+def _sda_mle_error_var(g, K, levels, d, s1, s2):
+    """Empirical error variance of the SDA-d MLE when every frame of a group
+    has the constant level of that group, the frame noise psi_i (variance s1^2)
+    is averaged by the SDA, and each SDA frame's residual carries an error of
+    its own (variance s2^2, the denoising error of the model)."""
+    frames = np.concatenate([np.full((d,) + K.shape + (1,), v) for v in levels])
+    psi = g.normal(0, s1, size=frames.shape)
+    I = sda.sda_means(frames, d)[:, 0]  # [g][C][H][W] -> [g][H][W]
+    P = sda.sda_means(psi, d)[:, 0]
+    res = [I[j] * K + P[j] + g.normal(0, s2, size=K.shape) for j in range(len(levels))]
+    A, B = pipeline.mle_accumulate(res, list(I))
+    return np.var(pipeline.mle_ratio(A, B) - K), I
+
+
+@pytest.mark.parametrize("d", [1, 3, 8])
+def test_sda_mle_variance_form(d):
+    """Sec. III-B: Var(K_hat) = (s1^2 / d + s2^2) / sum_j (I_j^SDA)^2."""
+    g = synth.rng(synth.CFG_TEST, 3010 + d)
+    K = g.normal(0, 0.02, size=(64, 64))
+    s1, s2 = 3.0, 1.5
+    levels = np.array([60.0, 140.0, 200.0, 90.0, 170.0])
+    v, I = _sda_mle_error_var(g, K, levels, d, s1, s2)
+    expect = (s1 ** 2 / d + s2 ** 2) / np.sum(levels ** 2)
+    assert abs(v / expect - 1) < 0.08
+
+
+def test_sda_frame_budget_for_equal_variance():
+    """Sec. III-B: n conventional frames and m = n (s1^2 + d s2^2) / (s1^2 +
+    s2^2) frames in SDA-d groups give the same error variance.  With s1^2 = 6,
+    s2^2 = 2, d = 3 and n = 20 that is m = 30, ten SDA frames; a third as many
+    SDA frames as the budget gives a larger variance."""
+    g = synth.rng(synth.CFG_TEST, 3020)
+    K = g.normal(0, 0.02, size=(96, 96))
+    s1, s2, d, n = np.sqrt(6.0), np.sqrt(2.0), 3, 20
+    m = n * (s1 ** 2 + d * s2 ** 2) / (s1 ** 2 + s2 ** 2)
+    assert m == 30
+    v_conv, _ = _sda_mle_error_var(g, K, np.full(n, 120.0), 1, s1, s2)
+    v_sda, _ = _sda_mle_error_var(g, K, np.full(int(m) // d, 120.0), d, s1, s2)
+    assert abs(v_sda / v_conv - 1) < 0.08
+    v_short, _ = _sda_mle_error_var(g, K, np.full(int(m) // d // 3, 120.0), d, s1, s2)
+    assert v_short > 2.0 * v_conv
