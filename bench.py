@@ -404,14 +404,72 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def _oracle_plane(args):
-    """Worker of the oracle's process-pool run: residual and MLE terms of one
-    plane (float64), as the oracle computes them for an SDA frame."""
+def _oracle_pool_worker(folder: str, idx: list) -> None:
+    """Child process of the oracle's multi-core run: loads its planes, says
+    "ready", waits for one line on stdin, then computes the residual (and for
+    an SDA frame the MLE terms) of each plane as the oracle does, and prints
+    the sums as one JSON line."""
+    import numpy as np
+
     from oracle import pipeline
 
-    I, kind = args
-    Wr = pipeline.denoise_residual(I)
-    return float((Wr * I).sum()) if kind == "sda" else float(Wr.sum())
+    with open(os.path.join(folder, "kinds.json")) as fh:
+        kinds = json.load(fh)
+    planes = [np.load(os.path.join(folder, f"p{i}.npy")) for i in idx]
+    print("ready", flush=True)
+    sys.stdin.readline()
+    out = []
+    for i, I in zip(idx, planes):
+        Wr = pipeline.denoise_residual(I)
+        out.append(float((Wr * I).sum()) if kinds[i] == "sda" else float(Wr.sum()))
+    print(json.dumps(out), flush=True)
+
+
+def oracle_pool_seconds(jobs, workers: int) -> float:
+    """Wall time of the oracle's plane denoises spread over `workers` child
+    processes (fresh interpreters: the parent holds the GPU).  Plain child
+    processes, started and joined here, so nothing of the run outlives it;
+    their start-up and imports are not timed."""
+    import shutil
+    import subprocess
+    import tempfile
+
+    import numpy as np
+
+    folder = tempfile.mkdtemp(prefix="oracle_pool_")
+    procs = []
+    try:
+        for i, (I, _) in enumerate(jobs):
+            np.save(os.path.join(folder, f"p{i}.npy"), I)
+        with open(os.path.join(folder, "kinds.json"), "w") as fh:
+            json.dump([k for _, k in jobs], fh)
+        env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+        code = ("import sys; sys.path.insert(0, sys.argv[1]); import bench; "
+                "bench._oracle_pool_worker(sys.argv[2], [int(v) for v in sys.argv[3:]])")
+        for w in range(workers):
+            idx = [str(i) for i in range(w, len(jobs), workers)]
+            if not idx:
+                break
+            procs.append(subprocess.Popen([sys.executable, "-c", code, ROOT, folder, *idx], stdin=subprocess.PIPE,
+                                          stdout=subprocess.PIPE, text=True, env=env))
+        for pr in procs:
+            if pr.stdout.readline().strip() != "ready":
+                raise RuntimeError("oracle pool worker failed to start")
+        t0 = time.perf_counter()
+        for pr in procs:
+            pr.stdin.write("go\n")
+            pr.stdin.flush()
+        for pr in procs:
+            json.loads(pr.stdout.readline())
+            if pr.wait() != 0:
+                raise RuntimeError("oracle pool worker failed")
+        return time.perf_counter() - t0
+    finally:
+        for pr in procs:
+            if pr.poll() is None:
+                pr.kill()
+                pr.wait()
+        shutil.rmtree(folder, ignore_errors=True)
 
 
 def cpu_baseline(frames, queries, ncam, nq, nfp, depths, H, W, C, dev, p):
@@ -424,9 +482,6 @@ def cpu_baseline(frames, queries, ncam, nq, nfp, depths, H, W, C, dev, p):
     denoises are then timed in a process pool over the host's cores.  The GPU
     path runs the sample through the C ABI; its errors against the oracle are
     returned."""
-    import concurrent.futures
-    import multiprocessing
-
     import numpy as np
     import torch
 
@@ -473,12 +528,7 @@ def cpu_baseline(frames, queries, ncam, nq, nfp, depths, H, W, C, dev, p):
     workers = max(1, min(16, os.cpu_count() or 1))
     jobs = [(means[i, c], "sda") for i in range(g) for c in range(C)]
     jobs += [(np.ascontiguousarray(q[:, :, c], dtype=np.float64), "query") for q in qs for c in range(C)]
-    ctx = multiprocessing.get_context("spawn")
-    with concurrent.futures.ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as pool:
-        list(pool.map(_oracle_plane, jobs[:workers]))  # start-up and imports, untimed
-        tp = time.perf_counter()
-        list(pool.map(_oracle_plane, jobs))
-        t_pool = time.perf_counter() - tp
+    t_pool = oracle_pool_seconds(jobs, workers)
     log(f"cpu baseline: {len(jobs)} plane denoises in {t_pool:.1f} s on {workers} processes")
 
     # the same sample on the GPU
@@ -1091,7 +1141,7 @@ def eval_main(args):
 
 
 def mixed_main(args):
-    """Mixed-media matching (Sec. V-D, "train on videos, test on images") on
+    """Mixed-media matching (Sec. V-B, "train on videos, test on images") on
     synthetic cameras: the sensor (2250 x 4000, PRNU K ~ N(0, 0.001^2)) takes
     full-resolution stills and video reduced 2 x 2 and cropped at a
     camera-specific offset to 1920 x 1080.  Video fingerprints at several SDA
@@ -1212,7 +1262,7 @@ def mixed_main(args):
 
 
 def stab_main(args):
-    """Matching two stabilised videos (Sec. V-F) on synthetic cameras: each
+    """Matching two stabilised videos (Sec. V-E) on synthetic cameras: each
     frame's sensor pattern is translated by the stabiliser (still with
     probability 0.3, otherwise up to 8 px).  Fingerprint estimates of every
     video (all frames, SDA-30/50/200, an I-frame proxy) over the first L
@@ -1277,7 +1327,7 @@ def stab_main(args):
     # A stabiliser whose correction holds over 30-frame segments: each SDA-30
     # frame has one pose.  Matching video v against video u, v's SDA frames are
     # searched against u's fingerprint for their translations and v's aligned
-    # fingerprint is correlated with u's (Sec. V-F).  u's fingerprint holds the
+    # fingerprint is correlated with u's (Sec. V-E).  u's fingerprint holds the
     # uncorrected pose most strongly; the scene content that v's own SDA
     # frames share (the moving texture) never enters the reference.  A frame
     # takes a translation only on a 5-sigma peak (PCE >= 25), so frames of

@@ -198,7 +198,7 @@ int prnu_query_residual(const void *frames, int dtype, int n, int H, int W, int 
  */
 int prnu_extract_blocks(const float *src, int n, int H, int W, int b, float *out, void *stream);
 
-/* Bilinear resampling for mixed-media matching (Sec. V-D: the query image is
+/* Bilinear resampling for mixed-media matching (Sec. V-B: the query image is
  * resized and cropped to the geometry of the video fingerprint before its
  * PRNU is matched).
  *

@@ -1,6 +1,6 @@
 """Bilinear resampling for mixed-media matching (test infrastructure only).
 
-Sec. V-D matches a still image against a video fingerprint after resizing
+Sec. V-B matches a still image against a video fingerprint after resizing
 and cropping the image's PRNU to the video's geometry.  Reading taken (the
 paper takes the parameters from its companion work and gives no kernel):
 output pixel (y, x) samples the input at ((y + oy + 0.5)/s - 0.5,

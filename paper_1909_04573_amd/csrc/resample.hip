@@ -1,6 +1,6 @@
 // Bilinear resampling for mixed-media matching: a still image's residual is
 // resized (and cropped) to the geometry of a video fingerprint before the two
-// are correlated (Sec. V-D).  Output pixel (y, x) samples the source at
+// are correlated (Sec. V-B).  Output pixel (y, x) samples the source at
 //   ((y + oy + 0.5) / scale - 0.5, (x + ox + 0.5) / scale - 0.5)
 // (pixel centres), with the coordinates clamped to the plane (edge
 // replication).  One thread per output pixel; pure gather (HBM / L2 bound).

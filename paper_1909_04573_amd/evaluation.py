@@ -9,7 +9,7 @@ summaries of PCE values the library computed; no method arithmetic.
 * auc(matched, unmatched): area under that curve, equal to the probability
   that a same-camera PCE exceeds a different-camera one (ties count 1/2).
 
-Stabilised video (Sec. V-F), orchestration of library calls:
+Stabilised video (Sec. V-E), orchestration of library calls:
 
 * segment_shifts(W, I, K_ref): per SDA frame, the translation of a reference
   fingerprint with the largest fixed-peak PCE;
@@ -60,7 +60,7 @@ def auc(matched, unmatched) -> float:
     return float((below.sum() + 0.5 * equal.sum()) / (m.size * u.size))
 
 
-# ---------------------------------------------------------------- stabilised video (Sec. V-F)
+# ---------------------------------------------------------------- stabilised video (Sec. V-E)
 def smooth_floor(n: int) -> int:
     """Largest m <= n with no prime factor above 5 (a size the DFT Wiener
     step of the fingerprint post-processing accepts)."""
@@ -82,7 +82,7 @@ def aligned_window(H: int, W: int, M: int):
 
 def segment_shifts(W, I, K_ref, max_shift: int = 8, margin: int = 60, origin: int = 0,
                    pce_min: float | None = None):
-    """Per-segment alignment search for stabilised video (Sec. V-F): the
+    """Per-segment alignment search for stabilised video (Sec. V-E): the
     sensor pattern of SDA frame j (residual W[j], intensity I[j], planes
     [g][H][W] float32 on the GPU) is compared with every integer translation
     (dy, dx), |dy|, |dx| <= max_shift, of the reference fingerprint K_ref,

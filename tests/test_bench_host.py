@@ -77,3 +77,17 @@ def test_more_than_one_gpu_is_refused(repo_root):
                        text=True, env=env, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_oracle_pool_leaves_no_process():
+    """The oracle's multi-core leg runs plain child processes and joins them:
+    no worker, tracker or helper process outlives the call."""
+    import numpy as np
+    import psutil
+
+    rng = np.random.default_rng(3)
+    jobs = [(rng.uniform(0, 255, (48, 64)), "sda" if i % 2 else "query") for i in range(5)]
+    before = {p.pid for p in psutil.Process().children(recursive=True)}
+    assert bench.oracle_pool_seconds(jobs, 3) > 0
+    after = {p.pid for p in psutil.Process().children(recursive=True)}
+    assert after <= before

@@ -490,7 +490,7 @@ def test_video_1080p_rgb_sample(dev):
 
 
 def test_stabilised_segments_aligned(dev):
-    """Segment-constant stabiliser (Sec. V-F): the alignment search finds each
+    """Segment-constant stabiliser (Sec. V-E): the alignment search finds each
     segment's translation against the camera's pattern, and the aligned MLE
     fingerprint correlates with K better than the unaligned one."""
     from paper_1909_04573_amd import evaluation as ev

@@ -78,6 +78,36 @@ def test_wiener_dft_single_cosine_closed_form(sigma2):
     np.testing.assert_allclose(pipeline.wiener_dft(K, sigma2=sigma2), rho * K, rtol=0, atol=1e-12)
 
 
+@pytest.mark.parametrize("axis", [0, 1])
+@pytest.mark.parametrize("sigma2", [None, 0.2])
+def test_wiener_dft_edge_bins_closed_form(axis, sigma2):
+    """Windows cut by the edge of the frequency array (zero extension there).
+
+    K = b + a cos(2 pi t / n) along `axis` has three non-zero DFT bins: DC with
+    M^2 = b^2 N, and bins 1 and n-1 of that axis with M^2 = a^2 N / 4 each
+    (N = H W).  With zero extension every window (3..9) centred on DC or on
+    bin 1 holds DC and bin 1 but not bin n-1, so all window sums there are
+    S = b^2 N + a^2 N / 4 and the smallest mean is S / 81; every window on
+    bin n-1 holds only that bin, smallest mean a^2 N / 4 / 81.  (A periodic
+    wrap would put bin n-1 in the windows of DC and bin 1 and vice versa.)
+    With rho = s2 / max(s2, smallest mean), the real part of the inverse is
+    b rho_0 + (a/2)(rho_1 + rho_{n-1}) cos(2 pi t / n).  s2 defaults to the
+    population variance a^2 / 2."""
+    H, W, a, b = 48, 60, 1.7, 0.9
+    N = H * W
+    yy, xx = np.mgrid[0:H, 0:W]
+    t, n = (yy, H) if axis == 0 else (xx, W)
+    cosine = np.cos(2 * np.pi * t / n)
+    K = b + a * cosine
+    s2 = a * a / 2 if sigma2 is None else sigma2
+    S = b * b * N + a * a * N / 4
+    rho_0 = rho_1 = s2 / max(s2, S / 81)
+    rho_last = s2 / max(s2, a * a * N / 4 / 81)
+    assert rho_1 != rho_last
+    want = b * rho_0 + 0.5 * a * (rho_1 + rho_last) * cosine
+    np.testing.assert_allclose(pipeline.wiener_dft(K, sigma2=sigma2), want, rtol=0, atol=1e-12)
+
+
 def test_postprocess_order_for_colour():
     P = np.stack([_f((16, 24), 8 + c) for c in range(3)])
     got = pipeline.postprocess(P, pipeline.FIN_ZM | pipeline.FIN_LUMA)

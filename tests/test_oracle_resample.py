@@ -1,4 +1,4 @@
-"""Pins of the oracle's bilinear resampling (mixed-media matching, Sec. V-D)."""
+"""Pins of the oracle's bilinear resampling (mixed-media matching, Sec. V-B)."""
 import numpy as np
 from scipy import ndimage
 
