@@ -123,13 +123,16 @@ def pce_vjp(x, y, nbhd=11):
     return float(val), gx - gx.mean(), gy - gy.mean()
 
 
-def gap_loss(theta, cam_frames, queries, query_cam, d=8, taps=16, nbhd=11, want_grad=True):
+def gap_loss(theta, cam_frames, queries, query_cam, d=8, taps=16, nbhd=11, want_grad=True, want_mag=False):
     """Matched-minus-unmatched mean PCE and its gradient w.r.t. theta.
 
     cam_frames: list over cameras of [m][H][W] float arrays (fingerprint
     patches); queries: [nq][H][W]; query_cam[q] is the camera of query q.
     Fingerprints use SDA depth d and zero-mean; queries use zero-mean; the
     matched statistic modulates the fingerprint by the query intensity.
+    With want_mag a fourth value holds, per gradient component, the sum of
+    the magnitudes of the per-coefficient terms it adds up (the scale of the
+    rounding error of any finite-precision evaluation of the same sums).
     """
     theta = np.asarray(theta, dtype=np.float64)
     sigma0, lam = float(theta[0]), tuple(float(v) for v in theta[1:5])
@@ -160,18 +163,27 @@ def gap_loss(theta, cam_frames, queries, query_cam, d=8, taps=16, nbhd=11, want_
     L = float(np.sum(wgt * P))
     if not want_grad:
         return L, None, P
-    dLds = np.zeros(4)
+    dLds, mag = np.zeros(4), np.zeros(4)
     for j, (means, B, _, sens) in enumerate(fp):
         gKraw = pipeline.zero_mean(gK[j])  # zero-mean is self-adjoint
         for i, I in enumerate(means):
             gWi = np.where(B > 0, gKraw * I / np.where(B > 0, B, 1.0), 0.0)
-            dLds[:len(sens[i])] += residual_vjp_ds(gWi, sens[i], taps)
+            v, a = residual_vjp_ds(gWi, sens[i], taps, want_abs=True)
+            dLds[:len(sens[i])] += v
+            mag[:len(sens[i])] += a
     for q, (_, _, sq) in enumerate(qs):
-        dLds[:len(sq)] += residual_vjp_ds(pipeline.zero_mean(gx[q]), sq, taps)
+        v, a = residual_vjp_ds(pipeline.zero_mean(gx[q]), sq, taps, want_abs=True)
+        dLds[:len(sq)] += v
+        mag[:len(sq)] += a
     grad = np.zeros(5)
     grad[0] = float(np.sum(dLds * 2.0 * np.array(lam) * sigma0))
     grad[1:5] = dLds * sigma0 * sigma0
-    return L, grad, P
+    if not want_mag:
+        return L, grad, P
+    gmag = np.zeros(5)
+    gmag[0] = float(np.sum(mag * 2.0 * np.abs(np.array(lam)) * abs(sigma0)))
+    gmag[1:5] = mag * sigma0 * sigma0
+    return L, grad, P, gmag
 
 
 def kink_masks(theta, cam_frames, queries, d=8, taps=16):

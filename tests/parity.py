@@ -6,6 +6,8 @@ the scale is the reference's largest magnitude: every element must satisfy
 per-element relative error where it crosses zero), and the whole array
 |got - ref|_2 <= rtol * |ref|_2.  PCE values use 1e-4 relative where
 |ref| >= 1 and 1e-4 absolute below (an unmatched PCE sits near 0).
+Gradient components are checked one by one, each against its own bound
+(its own magnitude, or the sum of the magnitudes of the terms it adds up).
 """
 import numpy as np
 
@@ -32,3 +34,18 @@ def assert_pce(got, ref, rtol=RTOL, what="pce"):
     for g, r in zip(got, ref):
         tol = rtol * abs(r) if abs(r) >= 1.0 else rtol
         assert abs(g - r) <= tol, f"{what}: gpu {g!r} oracle {r!r}"
+
+
+def components_ok(got, ref, bound, rtol=RTOL):
+    """True where |got - ref| <= rtol * bound, component by component."""
+    got = np.asarray(got, dtype=np.float64).ravel()
+    ref = np.asarray(ref, dtype=np.float64).ravel()
+    bound = np.asarray(bound, dtype=np.float64).ravel()
+    return np.abs(got - ref) <= rtol * bound
+
+
+def assert_components(got, ref, bound, rtol=RTOL, what="gradient"):
+    ok = components_ok(got, ref, bound, rtol)
+    rel = np.abs(np.asarray(got, np.float64).ravel() - np.asarray(ref, np.float64).ravel()) / np.maximum(
+        np.asarray(bound, np.float64).ravel(), 1e-300)
+    assert np.all(ok), f"{what}: gpu {np.asarray(got)} oracle {np.asarray(ref)} err/bound {rel} (rtol {rtol:g})"

@@ -95,3 +95,48 @@ def test_level_weight_scale_identity():
     lhs = theta[0] * g[0]
     rhs = 2.0 * float(np.dot(theta[1:], g[1:]))
     assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1e-300) + 1e-300
+
+
+def test_residual_cotangent_gives_positive_closed_form():
+    """With the residual itself as cotangent (dL/dW = W) on a plane whose
+    sides are multiples of 16 (no padding, so the DWT of W returns its
+    residual coefficients r = c s / max(s, m)), every term of dL/ds_l is
+    r [m > s] c / m = s (c / m)^2 [m > s] >= 0: dL/ds_l = s_l * sum of the
+    squared sensitivities, and the sum of the terms' magnitudes equals it."""
+    x = synth.patch_camera(1, 1, 96, 128)[0][0]
+    lw = (1.0, 0.7, 1.3, 1.0)
+    W, sens = adjoint.residual_with_sensitivity(x, 3.0, lw)
+    ds, mag = adjoint.residual_vjp_ds(W, sens, want_abs=True)
+    want = np.array([9.0 * lw[l] * sum(float(np.sum(v * v)) for v in sens[l].values()) for l in range(4)])
+    np.testing.assert_allclose(ds, want, rtol=1e-12)
+    np.testing.assert_allclose(mag, ds, rtol=1e-12)
+    assert np.all(ds > 0)
+
+
+def test_planted_level_one_error_is_caught_by_the_non_cancelling_check():
+    """A level-1 sensitivity 1% off (the size of a mistake once seen in a
+    GPU run) fails the per-level check of the residual cotangent
+    (1e-4 of each level's own sum of term magnitudes), while every level of
+    the correct sensitivities passes it."""
+    from parity import components_ok
+
+    x = synth.patch_camera(2, 1, 96, 128)[0][0]
+    W, sens = adjoint.residual_with_sensitivity(x, 3.0)
+    ref, mag = adjoint.residual_vjp_ds(W, sens, want_abs=True)
+    assert np.all(components_ok(adjoint.residual_vjp_ds(W, sens), ref, mag))
+    wrong = [dict(s) for s in sens]
+    wrong[0] = {k: 1.01 * v for k, v in sens[0].items()}
+    ok = components_ok(adjoint.residual_vjp_ds(W, wrong), ref, mag)
+    assert not ok[0] and np.all(ok[1:])
+
+
+def test_gap_loss_term_magnitudes_bound_the_gradient():
+    """The per-component sums of term magnitudes bound the gradient's
+    components (triangle inequality) and follow the same chain rule."""
+    cams, qs, qc = _diff_problem(H=48, W=48, nfp=4, nq=1)
+    theta = np.array([2.5, 0.8, 1.3, 1.0, 0.6])
+    L, g, _, mag = adjoint.gap_loss(theta, cams, qs, qc, d=2, want_mag=True)
+    L2, g2, _ = adjoint.gap_loss(theta, cams, qs, qc, d=2)
+    assert L == L2 and np.array_equal(g, g2)
+    assert np.all(mag >= np.abs(g))
+    assert abs(theta[0] * mag[0] - 2.0 * float(np.dot(theta[1:], mag[1:]))) <= 1e-12 * theta[0] * mag[0]
