@@ -345,14 +345,24 @@ int prnu_fingerprint_batch(const prnu_camera *cams, int n_cams, int dtype, const
 /* ---------------------------------------------------------------------------
  * Tile shapes of the wavelet level kernels (host state, process-wide).
  *
- * A forward level with shrinkage, an inverse level, or inverse level 1 with
- * the MLE fold (kind PRNU_TILE_FWD / _INV / _MLE) works on square tiles of
- * `tile` subband coefficients per side, 16 or 32 (default 32), chosen per
- * filter length and subband size hk x wk; the Wiener margin around a forward
- * tile is fixed at 4 coefficients by the largest (9 x 9) window.
- * prnu_set_tile: tile 16 or 32, 0 restores the default.
+ * This table is the library's one piece of global state: a host-side map,
+ * guarded by a mutex, from (kind, filter length, subband size) to a tile
+ * width.  It holds no device memory and changes only the launch shapes,
+ * never the results (every tile width computes the same values).
+ *
+ * A forward level with shrinkage (kind PRNU_TILE_FWD) streams strips of
+ * `tile` subband columns, 64 or 32 (default 64), down the plane in steps of
+ * 16 coefficient rows; the segment of rows a workgroup walks is sized from
+ * the level and the batch so that each launch holds about six workgroups per
+ * CU.  The Wiener margin around a strip is fixed at 4 coefficients by the
+ * largest (9 x 9) window.  An inverse level or inverse level 1 with the MLE
+ * fold (kind PRNU_TILE_INV / _MLE) works on square tiles of `tile`
+ * coefficients per side, 32 or 16 (default 32).  Choices are kept per
+ * filter length and subband size hk x wk.
+ * prnu_set_tile: one of the kind's two widths, 0 restores the default;
+ *   PRNU_E_INVAL for any other width.
  * prnu_autotune: for frames of H x W x C and the denoiser `p`, times both
- *   tiles of every forward level, inverse level 2..L and the MLE fold on
+ *   widths of every forward level, inverse level 2..L and the MLE fold on
  *   synthetic planes in `ws`, as many as one fingerprint-accumulation batch
  *   holds (up to 32 frames: the tile is chosen at the size it runs; events
  *   on `stream`, waits for them; not under graph capture) and keeps the

@@ -130,14 +130,15 @@ struct Layout {
 };
 
 // Descriptor tables per round: SDA, forward levels 1..L, inverse levels L..2,
-// MLE; every level stage split by tile size (32 first, then 16).
+// MLE; every level stage split by tile width (the kind's default first, then
+// its small one).
 struct StageCount {
-    int n32 = 0, n16 = 0;
+    int nbig = 0, nsmall = 0;
 };
 
-int stage_tt(int kind, int taps, int hk, int wk) { return tile_choice(kind, taps, hk, wk) == 16 ? 16 : 32; }
+int stage_tt(int kind, int taps, int hk, int wk) { return tile_choice(kind, taps, hk, wk); }
 
-void count_stage(StageCount *sc, int tt) { (tt == 16 ? sc->n16 : sc->n32)++; }
+void count_stage(StageCount *sc, int kind, int tt) { (tt == tile_small(kind) ? sc->nsmall : sc->nbig)++; }
 
 Layout plan_layout(const prnu_camera *cams, int n, const prnu_denoise_params *p, size_t budget) {
     Layout L;
@@ -163,15 +164,15 @@ Layout plan_layout(const prnu_camera *cams, int n, const prnu_denoise_params *p,
                     kind = TK_MLE;
                     l = 1;
                 }
-                count_stage(&sc, stage_tt(kind, p->taps, Hp >> l, Wp >> l));
+                count_stage(&sc, kind, stage_tt(kind, p->taps, Hp >> l, Wp >> l));
             }
             const size_t dsz = s < lv ? sizeof(FwdDesc) : s < 2 * lv - 1 ? sizeof(InvDesc) : sizeof(MleDesc);
-            if (sc.n32) {
-                L.tables += align_up(sc.n32 * dsz);
+            if (sc.nbig) {
+                L.tables += align_up(sc.nbig * dsz);
                 ++L.counters;
             }
-            if (sc.n16) {
-                L.tables += align_up(sc.n16 * dsz);
+            if (sc.nsmall) {
+                L.tables += align_up(sc.nsmall * dsz);
                 ++L.counters;
             }
         }
@@ -262,7 +263,7 @@ int build(const prnu_camera *cams, int n, int dtype, const prnu_denoise_params *
         }
         // a level stage: descriptors of one tile size, virtual blocks tile-fastest
         auto emit_stage = [&](auto make, size_t dsz, int kind_tk, int level, Launch::Kind kind) -> int {
-            for (int tt : {32, 16}) {
+            for (int tt : {tile_default(kind_tk), tile_small(kind_tk)}) {
                 int cnt = 0;
                 for (int k = 0; k < nj; ++k) {
                     const prnu_camera &c = cams[r[k].cam];
@@ -280,8 +281,8 @@ int build(const prnu_camera *cams, int n, int dtype, const prnu_denoise_params *
                     const int Hp = padded(c.H), Wp = padded(c.W);
                     const int hk = Hp >> level, wk = Wp >> level;
                     if (stage_tt(kind_tk, taps, hk, wk) != tt || nd == cnt) continue;
-                    const int tiles = tiles_for(tt, hk, wk);
-                    const int planes = make(k, tt, tab + nd * dsz, blk, &bytes, &flops);
+                    int tiles = 0;
+                    const int planes = make(k, tt, tab + nd * dsz, blk, &bytes, &flops, &tiles);
                     blk += (int64_t)tiles * planes;
                     ++nd;
                 }
@@ -308,21 +309,24 @@ int build(const prnu_camera *cams, int n, int dtype, const prnu_denoise_params *
         };
         for (int l = 1; l <= lv; ++l) {
             const float s2 = p->level_weight[l - 1] * s0;
-            auto mk = [&](int k, int tt, char *dst, int64_t blk0, double *bytes, double *flops) {
+            auto mk = [&](int k, int tt, char *dst, int64_t blk0, double *bytes, double *flops, int *ntiles) {
                 const prnu_camera &c = cams[r[k].cam];
                 const int Hp = padded(c.H), Wp = padded(c.W);
                 const int planes = r[k].ng * c.C;
                 FwdDesc d{};
+                int strips = 0, seg = 0, tiles = 0;
+                fwd_layout(tt, Hp >> l, Wp >> l, planes, &strips, &seg, &tiles);
                 if (l == 1)
                     d.a = FwdArgs{means[k], (int64_t)c.H * c.W, c.H, c.W, Hp, Wp, pad_before(c.H), pad_before(c.W),
-                                  lvl[k][1], s2, ((Wp >> 1) + tt - 1) / tt, lv > 1 ? 1 : 0, nullptr, 0};
+                                  lvl[k][1], s2, strips, lv > 1 ? 1 : 0, nullptr, 0, nullptr, 0, seg};
                 else {
                     const int nr = Hp >> (l - 1), nc = Wp >> (l - 1);
                     d.a = FwdArgs{lvl[k][l - 1], (int64_t)level_floats(Hp, Wp, l - 1), nr, nc, nr, nc, 0, 0,
-                                  lvl[k][l], s2, ((nc >> 1) + tt - 1) / tt, l < lv ? 1 : 0, nullptr, 0};
+                                  lvl[k][l], s2, strips, l < lv ? 1 : 0, nullptr, 0, nullptr, 0, seg};
                 }
                 d.tt = tt;
-                d.tiles = tiles_for(tt, Hp >> l, Wp >> l);
+                d.tiles = tiles;
+                *ntiles = tiles;
                 d.planes = planes;
                 d.block0 = blk0;
                 std::memcpy(dst, &d, sizeof d);
@@ -334,7 +338,7 @@ int build(const prnu_camera *cams, int n, int dtype, const prnu_denoise_params *
             PRNU_TRY(emit_stage(mk, sizeof(FwdDesc), TK_FWD, l, Launch::FWD));
         }
         for (int l = lv; l >= 2; --l) {
-            auto mk = [&](int k, int tt, char *dst, int64_t blk0, double *bytes, double *flops) {
+            auto mk = [&](int k, int tt, char *dst, int64_t blk0, double *bytes, double *flops, int *ntiles) {
                 const prnu_camera &c = cams[r[k].cam];
                 const int Hp = padded(c.H), Wp = padded(c.W);
                 const int planes = r[k].ng * c.C;
@@ -343,6 +347,7 @@ int build(const prnu_camera *cams, int n, int dtype, const prnu_denoise_params *
                 d.a = InvArgs{lvl[k][l], hk, wk, l == lv ? 1 : 0, (wk + tt - 1) / tt, lvl[k][l - 1], 0, 0, 0, 0};
                 d.tt = tt;
                 d.tiles = tiles_for(tt, hk, wk);
+                *ntiles = d.tiles;
                 d.planes = planes;
                 d.block0 = blk0;
                 std::memcpy(dst, &d, sizeof d);
@@ -353,7 +358,7 @@ int build(const prnu_camera *cams, int n, int dtype, const prnu_denoise_params *
             PRNU_TRY(emit_stage(mk, sizeof(InvDesc), TK_INV, l, Launch::INV));
         }
         {
-            auto mk = [&](int k, int tt, char *dst, int64_t blk0, double *bytes, double *flops) {
+            auto mk = [&](int k, int tt, char *dst, int64_t blk0, double *bytes, double *flops, int *ntiles) {
                 const prnu_camera &c = cams[r[k].cam];
                 const int Hp = padded(c.H), Wp = padded(c.W);
                 const int hk = Hp >> 1, wk = Wp >> 1;
@@ -362,6 +367,7 @@ int build(const prnu_camera *cams, int n, int dtype, const prnu_denoise_params *
                               c.W, pad_before(c.H), pad_before(c.W), c.A, c.B};
                 d.tt = tt;
                 d.tiles = tiles_for(tt, hk, wk);
+                *ntiles = d.tiles;
                 d.block0 = blk0;
                 std::memcpy(dst, &d, sizeof d);
                 const double accb = acc_mode == PRNU_ACC_F32 ? 16.0 : 32.0;  // A and B, read + write
@@ -383,7 +389,7 @@ int build(const prnu_camera *cams, int n, int dtype, const prnu_denoise_params *
 
 int enqueue(const prnu_batch *b, hipStream_t s) {
     using Launch = prnu_batch::Launch;
-    static const char *fwd_names[2] = {"batch_fwd_wiener<16>", "batch_fwd_wiener<32>"};
+    static const char *fwd_names[2] = {"batch_fwd_wiener<32>", "batch_fwd_wiener<64>"};
     static const char *inv_names[2] = {"batch_inv<16>", "batch_inv<32>"};
     static const char *mle_names[2] = {"batch_inv_mle<16>", "batch_inv_mle<32>"};
     for (const Launch &la : b->launches) {
@@ -398,7 +404,7 @@ int enqueue(const prnu_batch *b, hipStream_t s) {
                 break;
             }
             case Launch::FWD: {
-                KernelTimer kt(fwd_names[t32], la.bytes, s, la.flops);
+                KernelTimer kt(fwd_names[la.tt == 64], la.bytes, s, la.flops);
                 e = launch_fwd_multi(b->taps, la.tt, b->f, static_cast<const FwdDesc *>(la.desc), la.nd,
                                      (int)la.total, la.ctr, la.grid, s);
                 break;
@@ -595,8 +601,10 @@ int prnu_set_tile(int kind, int taps, int hk, int wk, int tile) {
     if (kind < PRNU_TILE_FWD || kind > PRNU_TILE_MLE) return fail(PRNU_E_INVAL, "prnu_set_tile: unknown kind");
     if (taps != 8 && taps != 16) return fail(PRNU_E_UNSUPPORTED, "prnu_set_tile: taps must be 8 or 16");
     if (hk < 1 || wk < 1) return fail(PRNU_E_INVAL, "prnu_set_tile: bad subband size");
-    if (tile != 0 && tile != 16 && tile != 32) return fail(PRNU_E_INVAL, "prnu_set_tile: tile must be 0, 16 or 32");
-    set_tile_choice(kind, taps, hk, wk, tile == 0 ? 32 : tile);
+    if (tile != 0 && !tile_valid(kind, tile))
+        return fail(PRNU_E_INVAL, "prnu_set_tile: tile must be 0, %d or %d for this kind", tile_default(kind),
+                    tile_small(kind));
+    set_tile_choice(kind, taps, hk, wk, tile == 0 ? tile_default(kind) : tile);
     return PRNU_OK;
 }
 
@@ -664,8 +672,8 @@ int prnu_autotune(int H, int W, int C, const prnu_denoise_params *p, void *ws, s
     auto tune = [&](int kind, int l, auto run) -> int {
         const int hk = Hp >> l, wk = Wp >> l;
         float best_ms = 0.f;
-        int best = 32;
-        for (int tt : {32, 16}) {
+        int best = tile_default(kind);
+        for (int tt : {tile_default(kind), tile_small(kind)}) {
             set_tile_choice(kind, taps, hk, wk, tt);
             if (run(l) != hipSuccess) return 0;  // warm-up
             if (hipEventRecord(e0, s) != hipSuccess) return 0;
@@ -674,7 +682,7 @@ int prnu_autotune(int H, int W, int C, const prnu_denoise_params *p, void *ws, s
             if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return 0;
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return 0;
-            if (tt == 32 || ms < best_ms) {
+            if (tt == tile_default(kind) || ms < best_ms) {
                 best_ms = ms;
                 best = tt;
             }

@@ -2,20 +2,22 @@
 // with F the locally adaptive wavelet denoiser named in Sec. IV.
 //
 // Forward level (analysis + Wiener shrinkage, one launch per level):
-//   a workgroup owns a TT x TT tile of every subband (TT = 16 or 32).  It
-//   stages the (2(TT+2*HALO)+L-2)^2 input samples the tile and a HALO-wide
-//   Wiener margin need into LDS (periodic wrap, plus symmetric padding at
-//   level 1), filters rows then columns in LDS with register-blocked taps held
-//   in scalar registers, keeps the squares of the three detail bands over the
-//   (TT+2*HALO)^2 region (zero outside the band) in LDS, and shrinks the core:
+//   a workgroup owns a strip of TC = 64 (or 32) subband columns of one plane
+//   and walks down a segment of its rows, 16 coefficient rows per step.  Per
+//   step it stages 32 new input rows in LDS (periodic wrap, plus symmetric
+//   padding at level 1), filters them along the rows into a ring of
+//   row-filtered rows (the last TAPS - 2 rows carry over to the next step),
+//   filters the ring along the columns into 16 new coefficient rows of the
+//   four subbands over the strip and a 4-column Wiener margin each side, and
+//   advances the Wiener window sums of every detail column, held in
+//   registers across steps:
 //       var = min_{w=3,5,7,9} max(0, box_w(c^2)/w^2 - s2)
 //       r   = c * s2 / (var + s2)
 //   It writes the approximation (input of the next level) and the residual
-//   detail coefficients r; the shrunk coefficients never touch HBM.  One LDS
-//   area holds in turn the input samples, the row-filtered bands and the
-//   squares, each pass keeping its results in registers across a barrier.
-//   Level 1 reads float planes or, at SDA depth 1, one channel of the u8
-//   frames themselves.
+//   detail coefficients r; the shrunk coefficients never touch HBM.  Along
+//   the streamed direction nothing is filtered twice: the halo is paid once
+//   per segment, not once per tile.  Level 1 reads float planes or, at SDA
+//   depth 1, one channel of the u8 frames themselves.
 //
 // Inverse level (synthesis): a workgroup owns a 2TT x 2TT output tile, stages
 //   the (TT+L/2-1)^2 coefficients of the four subbands it needs, synthesises
@@ -44,32 +46,9 @@ namespace {
 
 constexpr int HALO = 4;  // half of the largest Wiener window (9)
 constexpr int NT = 256;  // threads per workgroup
-// Forward-level workgroups with 32 x 32 tiles take 36 KB of LDS (four per
-// CU); 512 threads give each of them eight waves.
-constexpr int FWD_NT32 = 512;
-constexpr int fwd_nt(int tt) { return tt == 32 ? FWD_NT32 : NT; }
-// Row parts per core column in the forward level's Wiener stage: each part
-// re-reads eight halo rows, so few long parts beat many short ones once other
-// workgroups on the CU cover the idle threads.
-constexpr int WIENER_SPLIT = 2;
 // Inverse levels with 32 x 32 tiles run 512 threads per workgroup.
 constexpr int INV_NT32 = 512;
 constexpr int inv_nt(int tt) { return tt == 32 ? INV_NT32 : NT; }
-
-template <int TAPS, int TT>
-struct FwdGeom {
-    static constexpr int NC = TT + 2 * HALO;              // coefficients per side incl. margin
-    static constexpr int IN = 2 * NC + TAPS - 2;          // input samples per side
-    static constexpr int INS = (IN + 3) / 4 * 4;          // LDS row stride, 16-byte aligned rows
-    static constexpr int QSZ = 3 * NC * NC + 3 * TT * TT;  // masked squares + core coefficients
-    static constexpr int RL = IN * NC;                    // one row-filtered band
-    // One area holds, in turn, the input samples, the two row-filtered bands
-    // and the squares + core coefficients: each pass keeps its results in
-    // registers until every thread has read its inputs.
-    static constexpr int TILE = IN * INS > QSZ ? (IN * INS > 2 * RL ? IN * INS : 2 * RL) : (QSZ > 2 * RL ? QSZ : 2 * RL);
-    static constexpr int LDS = TILE + 2 * IN;             // floats; the two index maps at the end
-    static_assert(TILE % 4 == 0 && RL % 4 == 0 && NC % 4 == 0, "16-byte aligned LDS areas");
-};
 
 template <int TAPS, int TT>
 struct InvGeom {
@@ -102,131 +81,202 @@ __device__ __forceinline__ int map_index(int p, int n, int off, int stored) {
 }
 
 // ---------------------------------------------------------------------------
-// Forward level: staging of a tile's input samples.  maps() writes the
-// periodic/reflected source row and column of every tile sample to LDS;
-// fetch() issues the tile's global loads into registers (pairs of contiguous
-// samples where the tile's columns need neither the periodic wrap nor the
-// reflection, single samples otherwise); put() stores them to LDS.  Threads
-// form CX columns x RY rows: a thread looks up its column offsets once and one
-// row offset per row it reads, so each load costs an address add, and every
-// load of a thread is issued before the first LDS store.  Splitting fetch and
-// put keeps the register staging separate from the LDS layout.
-template <int TAPS, int TT>
-struct FwdStage {
-    using G = FwdGeom<TAPS, TT>;
-    static constexpr int NTH = fwd_nt(TT), IN = G::IN, INS = G::INS, IN2 = IN / 2;
-    static constexpr int CXF = IN2 <= 32 ? 32 : 64, RYF = NTH / CXF, NRGF = (IN + RYF - 1) / RYF;
-    static constexpr int CXS = 32, RYS = NTH / CXS, NCGS = (IN + CXS - 1) / CXS, NRGS = (IN + RYS - 1) / RYS;
-    static constexpr int NV = 2 * NRGF > NRGS * NCGS ? 2 * NRGF : NRGS * NCGS;
-    float v[NV];
-    bool fast;
+// Forward level, streamed by strips.  A workgroup owns a strip of TC subband
+// columns of one plane and walks down a segment of its rows, SR coefficient
+// rows per step.  Per step it
+//   P  stores the 2 SR input rows it prefetched into registers to LDS,
+//   R  filters them along the rows (low and high pass, NC = TC + 2 HALO
+//      coefficient columns: the strip and its Wiener margins) into a ring of
+//      row-filtered rows, and issues the next step's input loads,
+//   C  filters the ring along the columns: SR new coefficient rows of the four
+//      subbands; the approximation goes straight to HBM, the squares of the
+//      three detail bands (zero outside the band) and the strip's detail
+//      coefficients to LDS,
+//   W  advances each detail column's Wiener window sums by SR rows: one thread
+//      per (band, strip column) keeps the horizontal 3/5/7/9 sums of the last
+//      rows and their pair sums in registers across steps and shrinks the
+//      coefficient four rows behind the newest square row; meanwhile the
+//      remaining threads move the last TAPS - 2 ring rows to the ring's start
+//      for the next step's column pass.
+// Nothing is filtered twice along the streamed direction: the vertical halo
+// is paid once per segment instead of once per tile.
+constexpr int SR = 16;  // coefficient rows per step; also the period of the Wiener register ring (>= 9)
 
-    static __device__ __forceinline__ void maps(const FwdArgs &a, int tile, int tid, int *rmap, int *cmap) {
-        const int tr = tile / a.tiles_c, tc = tile - (tile / a.tiles_c) * a.tiles_c;
-        if (tid < IN)  // row offsets in elements (< 2^30: a plane has at most 2^15 x 2^15 samples)
-            rmap[tid] = map_index(2 * (tr * TT - HALO) + tid, a.n_r, a.off_r, a.src_rows) * a.src_cols;
-        else if (tid < 2 * IN)
-            cmap[tid - IN] = map_index(2 * (tc * TT - HALO) + tid - IN, a.n_c, a.off_c, a.src_cols);
+template <int TAPS, int TC>
+struct StripGeom {
+    static constexpr int NTH = 4 * TC;             // threads: 3 TC Wiener columns + TC helpers
+    static constexpr int NW = 3 * TC;              // Wiener threads
+    static constexpr int NEW = 2 * SR;             // input rows staged per step
+    static constexpr int CARRY = TAPS - 2;         // row-filtered rows the next step's column pass reuses
+    static constexpr int RR = NEW + CARRY;         // rows of the row-filtered ring
+    static constexpr int NC = TC + 2 * HALO;       // coefficient columns incl. the Wiener margins
+    static constexpr int NP = NC / 2;              // column pairs
+    static constexpr int INC = 2 * NC + TAPS - 2;  // input columns
+    static constexpr int INCQ = (INC + 3) / 4 * 4; // input columns read (whole 16-byte quads)
+    // LDS row stride of the staged input: 4 (mod 32) floats, so the row pass's
+    // 16-byte reads by consecutive rows fall in distinct banks
+    static constexpr int INCS = (INCQ + 27) / 32 * 32 + 4;
+    static constexpr int NQ4 = INCQ / 4;
+    static constexpr int RING = 2 * RR * NC;       // [row band lo, hi][RR][NC]
+    static constexpr int QF = 3 * SR * NC;         // squares [3][SR][NC]
+    static constexpr int CF = 3 * SR * TC;         // strip coefficients [3][SR][TC]
+    static constexpr int SF = NEW * INCS;          // staged input [NEW][INCS]
+    // the staged input and the squares + coefficients share one area: the row
+    // pass has read the input before the column pass writes the squares
+    static constexpr int AREA = QF + CF > SF ? QF + CF : SF;
+    static constexpr int LDS = RING + AREA + 2 * NEW + INCS;  // floats, then two row maps and the column map
+    static_assert(INCQ >= INC + 2 && INCS >= INCQ && INCS % 32 == 4, "staged row layout");
+    static_assert(NC % 4 == 0 && RING % 4 == 0 && QF % 4 == 0 && AREA % 4 == 0, "16-byte aligned LDS areas");
+    static_assert(NTH - NW >= 32, "helper threads for the ring move");
+};
+
+// Strips per plane, segment rows and virtual blocks of a forward level of
+// hk x wk coefficients with strips of tc columns over `planes` planes: long
+// segments keep the vertical halo small, short ones keep enough workgroups
+// (about six per CU per launch) to fill the chip and shorten its tail.
+__host__ __device__ inline void strip_layout(int tc, int hk, int wk, int64_t planes, int cus, int *strips, int *seg,
+                                             int *tiles) {
+    const int ns = (wk + tc - 1) / tc;
+    const int64_t base = (int64_t)ns * (planes > 0 ? planes : 1);
+    const int64_t want = 6ll * (cus > 0 ? cus : 256);
+    int64_t nseg = (want + base - 1) / base;
+    const int max_seg = hk / 64 > 1 ? hk / 64 : 1;  // segments of at least 64 rows
+    if (nseg > max_seg) nseg = max_seg;
+    if (nseg < (hk + 503) / 504) nseg = (hk + 503) / 504;  // and at most about 500
+    int S = (int)((hk + nseg - 1) / nseg);
+    S = ((S + 2 * HALO + SR - 1) / SR) * SR - 2 * HALO;  // whole steps: S + 2 HALO rows computed
+    if (S < 1) S = 1;
+    *strips = ns;
+    *seg = S;
+    *tiles = ns * ((hk + S - 1) / S);
+}
+
+__device__ __forceinline__ float4 ld4(const PRNU_GLOBAL float *p) {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    const v4 t = *(const PRNU_GLOBAL v4 *)p;
+    return make_float4(t.x, t.y, t.z, t.w);
+}
+
+// Staging modes of a strip's input rows (uniform per strip): float planes
+// whose strip needs neither the periodic wrap nor the reflection in its
+// columns are read as 16-byte quads; other float planes and u8 frames one
+// sample per load through the column map.
+enum StageMode { ST_QUAD = 0, ST_F32 = 1, ST_U8 = 2 };
+
+// Staging of NR input rows of a strip: fetch() issues the global loads into
+// registers, put() stores them to the LDS rows.  Quads: slot e = row-major
+// quad index; samples: threads form 32 columns x NTH/32 rows (u8 frames: one
+// channel of interleaved frames, kept as bytes until put(), exact in float).
+// Neither branches on the slot: slots past the end repeat the last valid one
+// (the same value lands in the same LDS word twice), so every thread issues
+// the same loads and the compiler can count the memory operations in flight.
+template <int TAPS, int TC, int NR, int MODE>
+struct StripStage {
+    using G = StripGeom<TAPS, TC>;
+    static constexpr int NTH = G::NTH, INC = G::INC, INCS = G::INCS, NQ4 = G::NQ4;
+    static constexpr int NVF = (NR * NQ4 + NTH - 1) / NTH;
+    static constexpr int CX = 32, RY = NTH / CX;
+    static constexpr int NCG = (INC + CX - 1) / CX, NRG = (NR + RY - 1) / RY;
+    static constexpr int NV = MODE == ST_QUAD ? 4 * NVF : NRG * NCG;
+    using V = typename std::conditional<MODE == ST_U8, unsigned, float>::type;
+    V v[NV];
+
+    static __device__ __forceinline__ int slot(int tid, int k) {
+        const int e = tid + k * NTH;
+        return e < NR * NQ4 ? e : NR * NQ4 - 1;
     }
-    __device__ __forceinline__ void fetch(const FwdArgs &a, int tile, int plane, int tid, const int *rmap,
+    static __device__ __forceinline__ int srow(int ty, int i) {
+        const int r = ty + i * RY;
+        return r < NR ? r : NR - 1;
+    }
+    static __device__ __forceinline__ int scol(int tx, int g) {
+        const int x = tx + g * CX;
+        return x < INC ? x : INC - 1;
+    }
+
+    __device__ __forceinline__ void fetch(const FwdArgs &a, int plane, int tid, int c_src0, const int *rmap,
                                           const int *cmap) {
-        const int tc = tile - (tile / a.tiles_c) * a.tiles_c;
-        const PRNU_GLOBAL float *sp = gmem(a.src) + (int64_t)plane * a.src_stride;
-        const int c_src0 = 2 * (tc * TT - HALO) - a.off_c;
-        fast = !a.src8 && c_src0 >= 0 && c_src0 + IN <= a.src_cols && (c_src0 & 1) == 0 &&
-               (a.src_cols & 1) == 0 && (a.src_stride & 1) == 0;
-        if (fast) {
-            const int tx = tid % CXF, ty = tid / CXF;
-            const PRNU_GLOBAL float *cp0 = sp + c_src0 + 2 * tx;
+        if constexpr (MODE == ST_QUAD) {
+            const PRNU_GLOBAL float *sp = gmem(a.src) + (int64_t)plane * a.src_stride + c_src0;
 #pragma unroll
-            for (int i = 0; i < NRGF; ++i) {
-                const int r = ty + i * RYF;
-                if (tx < IN2 && r < IN) {
-                    const float2 t = ld2(cp0 + (unsigned)rmap[r]);
-                    v[2 * i] = t.x;
-                    v[2 * i + 1] = t.y;
-                }
+            for (int k = 0; k < NVF; ++k) {
+                const int e = slot(tid, k);
+                const int r = e / NQ4, q = e - (e / NQ4) * NQ4;
+                const float4 t = ld4(sp + (unsigned)(rmap[r] + 4 * q));
+                v[4 * k] = t.x;
+                v[4 * k + 1] = t.y;
+                v[4 * k + 2] = t.z;
+                v[4 * k + 3] = t.w;
             }
         } else {
-            const int tx = tid % CXS, ty = tid / CXS;
-            int coff[NCGS];
+            const int tx = tid % CX, ty = tid / CX;
+            int coff[NCG];
 #pragma unroll
-            for (int g = 0; g < NCGS; ++g) coff[g] = tx + g * CXS < IN ? cmap[tx + g * CXS] : 0;
-            if (a.src8) {
-                // one channel of interleaved u8 frames (exact in float)
+            for (int g = 0; g < NCG; ++g) coff[g] = cmap[scol(tx, g)];
+            if constexpr (MODE == ST_U8) {
                 const int C8 = a.src8_c;
                 const PRNU_GLOBAL unsigned char *bp =
                     gmem(a.src8) + (int64_t)(plane / C8) * a.src_rows * a.src_cols * C8 + plane % C8;
 #pragma unroll
-                for (int i = 0; i < NRGS; ++i) {
-                    const int r = ty + i * RYS;
-                    const unsigned ro = r < IN ? (unsigned)rmap[r] : 0u;
+                for (int g = 0; g < NCG; ++g) coff[g] *= C8;
 #pragma unroll
-                    for (int g = 0; g < NCGS; ++g)
-                        if (r < IN && tx + g * CXS < IN) v[i * NCGS + g] = (float)bp[(ro + (unsigned)coff[g]) * (unsigned)C8];
+                for (int i = 0; i < NRG; ++i) {
+                    const unsigned ro = (unsigned)rmap[srow(ty, i)] * (unsigned)C8;
+#pragma unroll
+                    for (int g = 0; g < NCG; ++g) v[i * NCG + g] = bp[ro + (unsigned)coff[g]];
                 }
             } else {
+                const PRNU_GLOBAL float *sp = gmem(a.src) + (int64_t)plane * a.src_stride;
 #pragma unroll
-                for (int i = 0; i < NRGS; ++i) {
-                    const int r = ty + i * RYS;
-                    const PRNU_GLOBAL float *rp = sp + (unsigned)(r < IN ? rmap[r] : 0);
+                for (int i = 0; i < NRG; ++i) {
+                    const PRNU_GLOBAL float *rp = sp + (unsigned)rmap[srow(ty, i)];
 #pragma unroll
-                    for (int g = 0; g < NCGS; ++g)
-                        if (r < IN && tx + g * CXS < IN) v[i * NCGS + g] = rp[coff[g]];
+                    for (int g = 0; g < NCG; ++g) v[i * NCG + g] = rp[coff[g]];
                 }
             }
         }
     }
-    __device__ __forceinline__ void put(float *tbuf, int tid) const {
-        if (fast) {
-            const int tx = tid % CXF, ty = tid / CXF;
+    __device__ __forceinline__ void put(float *S, int tid) const {
+        if constexpr (MODE == ST_QUAD) {
 #pragma unroll
-            for (int i = 0; i < NRGF; ++i) {
-                const int r = ty + i * RYF;
-                if (tx < IN2 && r < IN)
-                    *reinterpret_cast<float2 *>(&tbuf[r * INS + 2 * tx]) = make_float2(v[2 * i], v[2 * i + 1]);
+            for (int k = 0; k < NVF; ++k) {
+                const int e = slot(tid, k);
+                const int r = e / NQ4, q = e - (e / NQ4) * NQ4;
+                *reinterpret_cast<float4 *>(&S[r * INCS + 4 * q]) =
+                    make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
             }
         } else {
-            const int tx = tid % CXS, ty = tid / CXS;
+            const int tx = tid % CX, ty = tid / CX;
 #pragma unroll
-            for (int i = 0; i < NRGS; ++i)
+            for (int i = 0; i < NRG; ++i)
 #pragma unroll
-                for (int g = 0; g < NCGS; ++g) {
-                    const int r = ty + i * RYS;
-                    if (r < IN && tx + g * CXS < IN) tbuf[r * INS + tx + g * CXS] = v[i * NCGS + g];
-                }
+                for (int g = 0; g < NCG; ++g) S[srow(ty, i) * INCS + scol(tx, g)] = (float)v[i * NCG + g];
         }
     }
 };
 
-// Forward level work on a staged tile (`tile` of plane `plane`, input samples
-// in LDS): row pass, column pass, Wiener shrinkage of the detail bands.
-template <int TAPS, int TT>
-__device__ __forceinline__ void fwd_compute(const FwdArgs &a, int tile, int plane, float *lds, const Filter &f) {
-    using G = FwdGeom<TAPS, TT>;
-    constexpr int NTH = fwd_nt(TT);
-    constexpr int IN = G::IN, INS = G::INS, NC = G::NC;
-    float *tbuf = lds;             // input samples, then the row bands, then squares + core coefficients
-    float *rlo = lds;              // row low-pass
-    float *rhi = lds + G::RL;      // row high-pass
-    const int hk = a.n_r >> 1, wk = a.n_c >> 1;
-    const int tr = tile / a.tiles_c, tc = tile - (tile / a.tiles_c) * a.tiles_c;
-    const int k0r = tr * TT, k0c = tc * TT;
-    PRNU_GLOBAL float *op = gmem(a.out) + (int64_t)plane * 4 * hk * wk;
-    const int64_t band = (int64_t)hk * wk;
-    const int tid = opaque_tid();
+// Staging mode of the strip whose input starts at column c_src0 of the source.
+__device__ __forceinline__ int strip_mode(const FwdArgs &a, int c_src0, int incq) {
+    if (a.src8) return ST_U8;
+    const bool quad = c_src0 >= 0 && c_src0 + incq <= a.src_cols && (c_src0 & 3) == 0 && (a.src_cols & 3) == 0 &&
+                      (a.src_stride & 3) == 0 && (reinterpret_cast<uintptr_t>(a.src) & 15) == 0;
+    return quad ? ST_QUAD : ST_F32;
+}
 
-    // Rows: lo/hi along axis 1, four coefficients per item, 16-byte LDS traffic.
-    constexpr int NQ = NC / 4;
-    constexpr int NX = TAPS + 8;  // TAPS + 6 samples, rounded up to whole float4s
-    constexpr int RITEMS = IN * NQ, RIT = (RITEMS + NTH - 1) / NTH;
-    float rl[RIT][4], rh[RIT][4];
-#pragma unroll
-    for (int k = 0; k < RIT; ++k) {
-        const int it = tid + k * NTH;
-        if (it < RITEMS) {
-            const int i = it / NQ, kq = it - (it / NQ) * NQ;
-            const float4 *row = reinterpret_cast<const float4 *>(&tbuf[i * INS + 8 * kq]);
+// Row pass over NR staged rows: low and high pass of four consecutive
+// coefficient columns of one row per item into ring rows row0 .. row0 + NR - 1.
+template <int TAPS, int TC, int NR>
+__device__ __forceinline__ void strip_rows(int tid, const float *S, float *ring, int row0, const Filter &f) {
+    using G = StripGeom<TAPS, TC>;
+    constexpr int NC = G::NC, NQ = NC / 4, NX = TAPS + 8, ITEMS = NR * NQ;
+    float *rlo = ring, *rhi = ring + G::RR * NC;
+#pragma unroll 1
+    for (int k = 0; k < (ITEMS + G::NTH - 1) / G::NTH; ++k) {
+        const int it = tid + k * G::NTH;
+        if (it < ITEMS) {
+            // consecutive lanes filter consecutive rows (distinct LDS banks)
+            const int i = it % NR, kq = it / NR;
+            const float4 *row = reinterpret_cast<const float4 *>(&S[i * G::INCS + 8 * kq]);
             float x[NX];
 #pragma unroll
             for (int t = 0; t < NX / 4; ++t) {
@@ -236,166 +286,254 @@ __device__ __forceinline__ void fwd_compute(const FwdArgs &a, int tile, int plan
                 x[4 * t + 2] = v.z;
                 x[4 * t + 3] = v.w;
             }
+            float rl[4], rh[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                rl[k][u] = 0.f;
-                rh[k][u] = 0.f;
+                rl[u] = 0.f;
+                rh[u] = 0.f;
 #pragma unroll
                 for (int j = 0; j < TAPS; ++j) {
-                    rl[k][u] = fmaf(f.h[j], x[2 * u + j], rl[k][u]);
-                    rh[k][u] = fmaf(f.g[j], x[2 * u + j], rh[k][u]);
+                    rl[u] = fmaf(f.h[j], x[2 * u + j], rl[u]);
+                    rh[u] = fmaf(f.g[j], x[2 * u + j], rh[u]);
                 }
             }
+            *reinterpret_cast<float4 *>(&rlo[(row0 + i) * NC + 4 * kq]) = make_float4(rl[0], rl[1], rl[2], rl[3]);
+            *reinterpret_cast<float4 *>(&rhi[(row0 + i) * NC + 4 * kq]) = make_float4(rh[0], rh[1], rh[2], rh[3]);
         }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < RIT; ++k) {
-        const int it = tid + k * NTH;
-        if (it < RITEMS) {
-            const int i = it / NQ, kq = it - (it / NQ) * NQ;
-            *reinterpret_cast<float4 *>(&rlo[i * NC + 4 * kq]) = make_float4(rl[k][0], rl[k][1], rl[k][2], rl[k][3]);
-            *reinterpret_cast<float4 *>(&rhi[i * NC + 4 * kq]) = make_float4(rh[k][0], rh[k][1], rh[k][2], rh[k][3]);
-        }
-    }
-    __syncthreads();
-
-    // Columns: a pair of coefficient columns by a pair of coefficient rows of
-    // one row band per item.  Every detail coefficient's square goes to q
-    // (zero outside the band: the Wiener windows' zero extension); the core
-    // coefficients to cb.  Row band 0 (low-pass) gives ll (stored at once)
-    // and hl (q band 1); row band 1 gives lh (q band 0) and hh (q band 2).
-    float *qb = tbuf;                // [3][NC][NC]
-    float *cb = tbuf + 3 * NC * NC;  // [3][TT][TT]
-    const int gr0 = k0r - HALO, gc0 = k0c - HALO;
-    constexpr int NP = NC / 2;
-    constexpr int CITEMS = 2 * NP * NP, CIT = (CITEMS + NTH - 1) / NTH;
-    float cl[CIT][2][2], ch[CIT][2][2];  // [item][row][column]
-#pragma unroll
-    for (int k = 0; k < CIT; ++k) {
-        const int it = tid + k * NTH;
-        if (it < CITEMS) {
-            const int cp = it % NP, kp = (it / NP) % NP, pass = it / (NP * NP);
-            const float *rb = pass == 0 ? rlo : rhi;
-            float2 xv[TAPS + 2];
-#pragma unroll
-            for (int t = 0; t < TAPS + 2; ++t)
-                xv[t] = *reinterpret_cast<const float2 *>(&rb[(4 * kp + t) * NC + 2 * cp]);
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                float l0 = 0.f, l1 = 0.f, h0 = 0.f, h1 = 0.f;
-#pragma unroll
-                for (int j = 0; j < TAPS; ++j) {
-                    const float2 v = xv[2 * u + j];
-                    l0 = fmaf(f.h[j], v.x, l0);
-                    l1 = fmaf(f.h[j], v.y, l1);
-                    h0 = fmaf(f.g[j], v.x, h0);
-                    h1 = fmaf(f.g[j], v.y, h1);
-                }
-                cl[k][u][0] = l0;
-                cl[k][u][1] = l1;
-                ch[k][u][0] = h0;
-                ch[k][u][1] = h1;
-                const int kr = 2 * kp + u;
-                const bool core = cp >= HALO / 2 && cp < (HALO + TT) / 2 && kr >= HALO && kr < HALO + TT;
-                if (pass == 0 && a.write_ll && core) {
-                    const int gr = gr0 + kr, gc = gc0 + 2 * cp;
-                    if (gr < hk) {
-                        if (gc < wk) op[(int64_t)gr * wk + gc] = l0;
-                        if (gc + 1 < wk) op[(int64_t)gr * wk + gc + 1] = l1;
-                    }
-                }
-            }
-        }
-    }
-    __syncthreads();
-    // Tiles whose margin lies inside the band (most of them) store the
-    // squares without the per-coefficient range masks.
-    const bool inside = gr0 >= 0 && gr0 + NC <= hk && gc0 >= 0 && gc0 + NC <= wk;
-    auto store_cols = [&](auto masked) {
-#pragma unroll
-        for (int k = 0; k < CIT; ++k) {
-            const int it = tid + k * NTH;
-            if (it < CITEMS) {
-                const int cp = it % NP, kp = (it / NP) % NP, pass = it / (NP * NP);
-                const bool cv0 = !masked || (gc0 + 2 * cp >= 0 && gc0 + 2 * cp < wk);
-                const bool cv1 = !masked || (gc0 + 2 * cp + 1 >= 0 && gc0 + 2 * cp + 1 < wk);
-                const bool core_c = cp >= HALO / 2 && cp < (HALO + TT) / 2;
-#pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const int kr = 2 * kp + u;
-                    const bool rv = !masked || (gr0 + kr >= 0 && gr0 + kr < hk);
-                    const bool core = core_c && kr >= HALO && kr < HALO + TT;
-                    auto put = [&](int sb, float c0, float c1) {
-                        float2 q2 = make_float2(c0 * c0, c1 * c1);
-                        if (masked) q2 = make_float2(rv && cv0 ? q2.x : 0.f, rv && cv1 ? q2.y : 0.f);
-                        *reinterpret_cast<float2 *>(&qb[(sb * NC + kr) * NC + 2 * cp]) = q2;
-                        if (core)
-                            *reinterpret_cast<float2 *>(&cb[(sb * TT + kr - HALO) * TT + 2 * cp - HALO]) =
-                                make_float2(c0, c1);
-                    };
-                    if (pass == 0) {
-                        put(1, ch[k][u][0], ch[k][u][1]);
-                    } else {
-                        put(0, cl[k][u][0], cl[k][u][1]);
-                        put(2, ch[k][u][0], ch[k][u][1]);
-                    }
-                }
-            }
-        }
-    };
-    if (inside)
-        store_cols(std::false_type{});
-    else
-        store_cols(std::true_type{});
-    __syncthreads();
-
-    // Wiener shrinkage of the TT x TT core of each detail band: one thread per
-    // (band, core column, WS-th part of the core rows).  Band s of q/cb is lh,
-    // hl, hh for s = 0, 1, 2, stored as subbands 1, 2, 3.
-    constexpr int WS = WIENER_SPLIT;
-    static_assert(3 * WS * TT <= NTH, "one Wiener column part per thread");
-    if (tid < 3 * WS * TT) {
-        const int s = tid / (WS * TT), part = (tid / TT) % WS, kcl = tid & (TT - 1);
-        const float *Q = qb + s * NC * NC;
-        const float *Cc = cb + s * TT * TT;
-        PRNU_GLOBAL float *ob = op + (int64_t)(s + 1) * band;
-        PRNU_GLOBAL float *cp = a.ckpt ? gmem(a.ckpt) + (int64_t)plane * a.ckpt_stride + (int64_t)s * band : nullptr;
-        const int gco = k0c + kcl;
-        const float s2 = a.s2;
-        // this thread's outputs: core rows part*TT/WS + i of column kcl
-        const int grow0 = k0r + part * (TT / WS);
-        PRNU_GLOBAL float *orow = ob + (int64_t)grow0 * wk + gco;
-        PRNU_GLOBAL float *crow = cp ? cp + (int64_t)grow0 * wk + gco : nullptr;
-        const float *ccol = Cc + part * (TT / WS) * TT + kcl;
-        auto load = [&](int kr, int kc) { return Q[kr * NC + kc]; };
-        auto emit = [&](int ko, float rho, float den) {
-            const int i = ko - HALO - part * (TT / WS);
-            if (grow0 + i < hk && gco < wk) {
-                const float c = ccol[i * TT];
-                orow[i * wk] = c * rho;
-                // sensitivity dr/ds = c / m where the window mean m exceeds s2, else 0
-                if (crow) crow[i * wk] = den > s2 ? c * __builtin_amdgcn_rcpf(den) : 0.f;
-            }
-        };
-        wiener_column<TT / WS>(part * (TT / WS), kcl, s2, load, emit);
     }
 }
 
-// Forward level body: subband tile `tile` of plane `plane`.
-template <int TAPS, int TT>
-__device__ __forceinline__ void fwd_body(const FwdArgs &a, int tile, int plane, float *lds, const Filter &f) {
-    using G = FwdGeom<TAPS, TT>;
-    int *rmap = reinterpret_cast<int *>(lds + G::TILE);
-    int *cmap = rmap + G::IN;
+// Wiener state of one (band, strip column): horizontal window sums h of the
+// last rows and the pair sums p of consecutive rows, ring index = row mod SR.
+struct WienerRing {
+    float h3[SR], h5[SR], h7[SR], h9[SR];
+    float p3[SR], p5[SR], p7[SR], p9[SR];
+    float c[SR];  // the column's coefficients, shrunk four rows later
+};
+
+// Forward level body: strip tile % tiles_c, segment tile / tiles_c of plane
+// `plane`, in the LDS area `lds` (StripGeom::LDS floats).  CK: also store the
+// sensitivity checkpoint (a.ckpt).
+template <int TAPS, int TC, bool CK, int MODE>
+__device__ __forceinline__ void fwd_strip(const FwdArgs &a, int tile, int plane, float *lds, const Filter &f) {
+    using G = StripGeom<TAPS, TC>;
+    constexpr int NTH = G::NTH, NC = G::NC, NP = G::NP, RR = G::RR, NEW = G::NEW, CARRY = G::CARRY;
+    float *ring = lds;
+    float *S = lds + G::RING;           // staged input rows ...
+    float *Q = S;                       // ... later the squares [3][SR][NC]
+    float *Cb = S + G::QF;              // and the strip coefficients [3][SR][TC]
+    int *rmap = reinterpret_cast<int *>(lds + G::RING + G::AREA);  // [2][NEW] row offsets (elements)
+    int *cmap = rmap + 2 * NEW;                                     // [INC] source columns
     const int tid = opaque_tid();
-    FwdStage<TAPS, TT>::maps(a, tile, tid, rmap, cmap);
+    const int hk = a.n_r >> 1, wk = a.n_c >> 1;
+    const int sc = tile % a.tiles_c, sg = tile / a.tiles_c;
+    const int C0 = sc * TC, R0 = sg * a.seg_rows;
+    const int K0 = R0 - HALO, J0 = C0 - HALO;
+    const int oend = min(R0 + a.seg_rows, hk);
+    const int T = (oend - R0 + 2 * HALO + SR - 1) / SR;
+    float *op = a.out + (int64_t)plane * 4 * hk * wk;
+    const int64_t band = (int64_t)hk * wk;
+    // Outputs go through buffer stores whose out-of-range lanes the hardware
+    // drops: every thread issues the same stores each step (no branches around
+    // them), so the wait for the next step's input loads counts exactly the
+    // stores behind them instead of draining them.  Byte ranges: subband 0,
+    // then the three detail bands (and the checkpoint's three bands).
+    const unsigned ll_bytes = (unsigned)(band * 4), det_bytes = (unsigned)(3 * band * 4);
+    const __amdgpu_buffer_rsrc_t ll_rs = __builtin_amdgcn_make_buffer_rsrc(op, 0, (int)ll_bytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t det_rs = __builtin_amdgcn_make_buffer_rsrc(op + band, 0, (int)det_bytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t ck_rs = __builtin_amdgcn_make_buffer_rsrc(
+        CK ? a.ckpt + (int64_t)plane * a.ckpt_stride : op, 0, (int)det_bytes, 0x00020000);
+    const int c_src0 = 2 * J0 - a.off_c;
+    auto row_of = [&](int y) { return map_index(y, a.n_r, a.off_r, a.src_rows) * a.src_cols; };
+
+    // prologue: the first CARRY row-filtered rows go straight to the ring's
+    // start, then step 0's rows are staged
+    if (tid < G::INC) cmap[tid] = map_index(2 * J0 + tid, a.n_c, a.off_c, a.src_cols);
+    if (tid < CARRY) rmap[NEW + tid] = row_of(2 * K0 + tid);
     __syncthreads();
-    FwdStage<TAPS, TT> st;
-    st.fetch(a, tile, plane, tid, rmap, cmap);
-    st.put(lds, tid);
+    {
+        StripStage<TAPS, TC, CARRY, MODE> pro;
+        pro.fetch(a, plane, tid, c_src0, rmap + NEW, cmap);
+        pro.put(S, tid);
+    }
+    if (tid < NEW) rmap[tid] = row_of(2 * K0 + CARRY + tid);
     __syncthreads();
-    fwd_compute<TAPS, TT>(a, tile, plane, lds, f);
+    strip_rows<TAPS, TC, CARRY>(tid, S, ring, 0, f);
+    StripStage<TAPS, TC, NEW, MODE> st;
+    st.fetch(a, plane, tid, c_src0, rmap, cmap);
+    __syncthreads();
+    st.put(S, tid);
+    if (tid < NEW) rmap[NEW + tid] = row_of(2 * K0 + 2 * SR + CARRY + tid);
+    __syncthreads();
+
+    const bool cols_in = J0 >= 0 && J0 + NC <= wk;
+    WienerRing wr;
+#pragma unroll
+    for (int i = 0; i < SR; ++i) {
+        wr.h3[i] = wr.h5[i] = wr.h7[i] = wr.h9[i] = 0.f;
+        wr.p3[i] = wr.p5[i] = wr.p7[i] = wr.p9[i] = 0.f;
+        wr.c[i] = 0.f;
+    }
+    // Step t: R (row pass of the staged rows; the next step's loads issued),
+    // C, W (with this step's stores), then P: the next step's rows to LDS.
+    // The last step fetches and stages one more step of rows it does not
+    // use (valid rows): the loads stay unconditional.
+    for (int t = 0; t < T; ++t) {
+        strip_rows<TAPS, TC, NEW>(tid, S, ring, CARRY, f);
+        st.fetch(a, plane, tid, c_src0, rmap + ((t + 1) & 1) * NEW, cmap);
+        __syncthreads();
+        // C: column pass, coefficient rows kb .. kb + SR - 1
+        const int kb = K0 + SR * t;
+        const bool inside = cols_in && kb >= 0 && kb + SR <= hk;
+        auto cols = [&](auto masked) {
+            constexpr int ITEMS = 2 * NP * (SR / 2);
+#pragma unroll 1
+            for (int k = 0; k < (ITEMS + NTH - 1) / NTH; ++k) {
+                const int it = tid + k * NTH;
+                if (it >= ITEMS) continue;
+                const int cp = it % NP, kp = (it / NP) % (SR / 2), b = it / (NP * (SR / 2));
+                const float *rb = ring + b * RR * NC;
+                float2 xv[TAPS + 2];
+#pragma unroll
+                for (int u = 0; u < TAPS + 2; ++u) xv[u] = *reinterpret_cast<const float2 *>(&rb[(4 * kp + u) * NC + 2 * cp]);
+                const int gc = J0 + 2 * cp;
+                const bool core_c = cp >= HALO / 2 && cp < (HALO + TC) / 2;
+                const bool cv0 = !masked || (gc >= 0 && gc < wk), cv1 = !masked || (gc + 1 >= 0 && gc + 1 < wk);
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    float l0 = 0.f, l1 = 0.f, h0 = 0.f, h1 = 0.f;
+#pragma unroll
+                    for (int j = 0; j < TAPS; ++j) {
+                        const float2 v = xv[2 * u + j];
+                        l0 = fmaf(f.h[j], v.x, l0);
+                        l1 = fmaf(f.h[j], v.y, l1);
+                        h0 = fmaf(f.g[j], v.x, h0);
+                        h1 = fmaf(f.g[j], v.y, h1);
+                    }
+                    const int ur = 2 * kp + u, kr = kb + ur;
+                    const bool rv = !masked || (kr >= 0 && kr < hk);
+                    auto put = [&](int s, float c0, float c1) {
+                        float2 q2 = make_float2(c0 * c0, c1 * c1);
+                        if (masked) q2 = make_float2(rv && cv0 ? q2.x : 0.f, rv && cv1 ? q2.y : 0.f);
+                        *reinterpret_cast<float2 *>(&Q[(s * SR + ur) * NC + 2 * cp]) = q2;
+                        if (core_c)
+                            *reinterpret_cast<float2 *>(&Cb[(s * SR + ur) * TC + 2 * cp - HALO]) = make_float2(c0, c1);
+                    };
+                    // approximation rows of the segment (row low-pass items, strip columns) to HBM
+                    const bool llr = b == 0 && a.write_ll && core_c && kr >= R0 && kr < oend;
+                    const unsigned lo = (unsigned)((int64_t)kr * wk + gc) * 4u;
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(l0), ll_rs, llr && gc < wk ? lo : ll_bytes,
+                                                          0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(l1), ll_rs,
+                                                          llr && gc + 1 < wk ? lo + 4u : ll_bytes, 0, 0);
+                    if (b == 0) {
+                        // row low-pass: hl (band 1)
+                        put(1, h0, h1);
+                    } else {
+                        // row high-pass: lh (band 0) and hh (band 2)
+                        put(0, l0, l1);
+                        put(2, h0, h1);
+                    }
+                }
+            }
+        };
+        if (inside)
+            cols(std::false_type{});
+        else
+            cols(std::true_type{});
+        __syncthreads();
+        // W: Wiener shrinkage of the strip's detail columns, four rows behind
+        float res[SR], sen[CK ? SR : 1];
+        unsigned okm = 0u;  // bit i: the step's output row i is stored
+        const int ob = R0 + SR * t - 2 * HALO;  // output row of the step's row i is ob + i (from row R0 on)
+        unsigned obase = 0u;                    // byte offset of output row ob in the detail bands
+        if (tid < G::NW) {
+            const int s = tid / TC, jc = tid - (tid / TC) * TC;
+            const float *Qs = Q + s * SR * NC + jc;
+            const float *Cs = Cb + s * SR * TC + jc;
+            const float s2 = a.s2;
+            const bool col_ok = C0 + jc < wk;
+            obase = (unsigned)((int64_t)s * band + (int64_t)ob * wk + C0 + jc) * 4u;
+#pragma unroll
+            for (int i = 0; i < SR; ++i) {
+                float q[9];
+#pragma unroll
+                for (int dx = 0; dx < 9; ++dx) q[dx] = Qs[i * NC + dx];
+                const float a3 = q[3] + q[4] + q[5];
+                const float a5 = a3 + q[2] + q[6];
+                const float a7 = a5 + q[1] + q[7];
+                const float a9 = a7 + q[0] + q[8];
+                const int ip = (i + SR - 1) % SR;
+                wr.p3[i] = wr.h3[ip] + a3;
+                wr.p5[i] = wr.h5[ip] + a5;
+                wr.p7[i] = wr.h7[ip] + a7;
+                wr.p9[i] = wr.h9[ip] + a9;
+                wr.h3[i] = a3;
+                wr.h5[i] = a5;
+                wr.h7[i] = a7;
+                wr.h9[i] = a9;
+                wr.c[i] = Cs[i * TC];
+                // output ring row o = i - 4: window rows o-r .. o+r as pairs
+                constexpr int M = SR;
+                const int o = (i + M - 4) % M;
+                const float v3 = wr.p3[o] + wr.h3[(o + 1) % M];
+                const float v5 = wr.p5[(o + M - 1) % M] + wr.p5[(o + 1) % M] + wr.h5[(o + 2) % M];
+                const float v7 = wr.p7[(o + M - 2) % M] + wr.p7[o] + wr.p7[(o + 2) % M] + wr.h7[(o + 3) % M];
+                const float v9 = wr.p9[(o + M - 3) % M] + wr.p9[(o + M - 1) % M] + wr.p9[(o + 1) % M] +
+                                 wr.p9[(o + 3) % M] + wr.h9[i];
+                float m = fminf(v3 * (1.f / 9.f), v5 * (1.f / 25.f));
+                m = fminf(m, v7 * (1.f / 49.f));
+                m = fminf(m, v9 * (1.f / 81.f));
+                const float den = fmaxf(s2, m);
+                const float rcp = __builtin_amdgcn_rcpf(den);
+                const float c = wr.c[o];
+                res[i] = c * (den > 0.f ? s2 * rcp : 0.f);
+                // sensitivity dr/ds = c / m where the window mean m exceeds s2, else 0
+                if (CK) sen[CK ? i : 0] = den > s2 ? c * rcp : 0.f;
+                const int orw = ob + i;  // absolute output row
+                if ((t > 0 || i >= 2 * HALO) && orw < oend && col_ok) okm |= 1u << i;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < SR; ++i) {
+                res[i] = 0.f;
+                if (CK) sen[CK ? i : 0] = 0.f;
+            }
+            // the last CARRY ring rows become the first ones of the next step
+            constexpr int N4 = CARRY * NC / 4;
+            for (int e = tid - G::NW; e < 2 * N4; e += NTH - G::NW) {
+                const int b = e / N4, r4 = e - (e / N4) * N4;
+                float *base = ring + b * RR * NC;
+                *reinterpret_cast<float4 *>(&base[4 * r4]) = *reinterpret_cast<const float4 *>(&base[NEW * NC + 4 * r4]);
+            }
+        }
+        const unsigned row_bytes = (unsigned)wk * 4u;
+#pragma unroll
+        for (int i = 0; i < SR; ++i) {
+            const unsigned o = (okm >> i) & 1u ? obase + (unsigned)i * row_bytes : det_bytes;
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(res[i]), det_rs, o, 0, 0);
+            if (CK) __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(sen[CK ? i : 0]), ck_rs, o, 0, 0);
+        }
+        __syncthreads();
+        // P: the next step's rows to LDS (over the squares); row offsets of the step after
+        st.put(S, tid);
+        if (tid < NEW) rmap[(t & 1) * NEW + tid] = row_of(2 * K0 + 2 * SR * (t + 2) + CARRY + tid);
+        __syncthreads();
+    }
+}
+
+// Forward level body: picks the staging mode of the strip (uniform across
+// the workgroup) and runs the strip.
+template <int TAPS, int TC, bool CK>
+__device__ __forceinline__ void fwd_body(const FwdArgs &a, int tile, int plane, float *lds, const Filter &f) {
+    const int C0 = (tile % a.tiles_c) * TC;
+    const int mode = strip_mode(a, 2 * (C0 - HALO) - a.off_c, StripGeom<TAPS, TC>::INCQ);
+    if (mode == ST_QUAD)
+        fwd_strip<TAPS, TC, CK, ST_QUAD>(a, tile, plane, lds, f);
+    else if (mode == ST_U8)
+        fwd_strip<TAPS, TC, CK, ST_U8>(a, tile, plane, lds, f);
+    else
+        fwd_strip<TAPS, TC, CK, ST_F32>(a, tile, plane, lds, f);
 }
 
 // ---------------------------------------------------------------------------
@@ -711,15 +849,16 @@ __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, floa
 
 // ---------------------------------------------------------------------------
 // Per-plane kernels.
-template <int TAPS, int TT>
-__global__ __launch_bounds__(fwd_nt(TT)) void dwt_fwd_wiener(FwdArgs a, Filter f) {
-    __shared__ __align__(16) float lds[FwdGeom<TAPS, TT>::LDS];
+template <int TAPS, int TC, bool CK>
+__global__ __launch_bounds__(4 * TC) __attribute__((amdgpu_waves_per_eu(3))) void dwt_fwd_wiener(FwdArgs a,
+                                                                                                Filter f) {
+    __shared__ __align__(16) float lds[StripGeom<TAPS, TC>::LDS];
     int tile, plane;
     if (a.src8 && a.src8_c > 1)
         grid_tile_channels(tile, plane, a.src8_c);
     else
         grid_tile(tile, plane);
-    fwd_body<TAPS, TT>(a, tile, plane, lds, f);
+    fwd_body<TAPS, TC, CK>(a, tile, plane, lds, f);
 }
 
 template <int TAPS, int TT, int EPI>
@@ -766,17 +905,17 @@ __device__ __forceinline__ int next_block(int *ctr, int *slot) {
     return __builtin_amdgcn_readfirstlane(*slot);  // uniform: descriptor fields go to scalar registers
 }
 
-template <int TAPS, int TT>
-__global__ __launch_bounds__(fwd_nt(TT)) void dwt_fwd_multi(const FwdDesc *__restrict__ d, int nd, int total, int *ctr,
-                                                    Filter f) {
-    __shared__ __align__(16) float lds[FwdGeom<TAPS, TT>::LDS];
+template <int TAPS, int TC>
+__global__ __launch_bounds__(4 * TC) __attribute__((amdgpu_waves_per_eu(3))) void dwt_fwd_multi(const FwdDesc *__restrict__ d, int nd,
+                                                                        int total, int *ctr, Filter f) {
+    __shared__ __align__(16) float lds[StripGeom<TAPS, TC>::LDS];
     __shared__ int slot;
     for (;;) {
         const int vb = next_block(ctr, &slot);
         if (vb >= total) break;
         const FwdDesc &D = d[find_desc(d, nd, vb)];
         const int local = vb - (int)D.block0;
-        fwd_body<TAPS, TT>(D.a, local % D.tiles, local / D.tiles, lds, f);
+        fwd_body<TAPS, TC, false>(D.a, local % D.tiles, local / D.tiles, lds, f);
     }
 }
 
@@ -855,12 +994,16 @@ int device_cus() {
 int tile_choice(int kind, int taps, int hk, int wk) {
     std::lock_guard<std::mutex> lk(g_tile_mu);
     auto it = g_tile.find(std::make_tuple(kind, taps, hk, wk));
-    return it == g_tile.end() ? 32 : it->second;
+    return it == g_tile.end() ? tile_default(kind) : it->second;
 }
 
 void set_tile_choice(int kind, int taps, int hk, int wk, int tt) {
     std::lock_guard<std::mutex> lk(g_tile_mu);
-    g_tile[std::make_tuple(kind, taps, hk, wk)] = tt == 16 ? 16 : 32;
+    g_tile[std::make_tuple(kind, taps, hk, wk)] = tile_valid(kind, tt) ? tt : tile_default(kind);
+}
+
+void fwd_layout(int tc, int hk, int wk, int64_t planes, int *strips, int *seg_rows, int *tiles) {
+    strip_layout(tc, hk, wk, planes, device_cus(), strips, seg_rows, tiles);
 }
 
 hipError_t launch_dwt_fwd(int taps, const Filter &f, const float *src, int64_t src_stride, int src_rows,
@@ -868,21 +1011,27 @@ hipError_t launch_dwt_fwd(int taps, const Filter &f, const float *src, int64_t s
                           bool write_ll, hipStream_t s, float *ckpt, int64_t ckpt_stride, const unsigned char *src8,
                           int src8_c) {
     const int hk = n_r / 2, wk = n_c / 2;
-    const int tt = tile_choice(TK_FWD, taps, hk, wk);
+    const int tc = tile_choice(TK_FWD, taps, hk, wk);
+    int strips = 0, seg = 0, tiles = 0;
+    fwd_layout(tc, hk, wk, planes, &strips, &seg, &tiles);
     FwdArgs a{src, src_stride, src_rows, src_cols, n_r, n_c, off_r, off_c, out, s2,
-              ceil_div(wk, tt), write_ll ? 1 : 0, ckpt, ckpt_stride, src8, src8_c};
-    dim3 grid((unsigned)tiles_for(tt, hk, wk), (unsigned)planes);
+              strips, write_ll ? 1 : 0, ckpt, ckpt_stride, src8, src8_c, seg};
+    dim3 grid((unsigned)tiles, (unsigned)planes);
     const double bytes = (double)planes * ((src8 ? 1.0 : 4.0) * (double)src_rows * src_cols +
                                            4.0 * (write_ll ? 4.0 : 3.0) * (double)hk * wk);
     KernelTimer kt(taps == 16 ? "dwt_fwd_wiener<16>" : "dwt_fwd_wiener<8>", bytes, s,
                    (double)planes * n_r * n_c * fwd_flops_per_px(taps));
+#define PRNU_FWD(TP, T_)                                                                                   \
+    do {                                                                                                   \
+        if (ckpt) dwt_fwd_wiener<TP, T_, true><<<grid, StripGeom<TP, T_>::NTH, 0, s>>>(a, f);              \
+        else dwt_fwd_wiener<TP, T_, false><<<grid, StripGeom<TP, T_>::NTH, 0, s>>>(a, f);                 \
+    } while (0)
     if (taps == 16) {
-        if (tt == 16) dwt_fwd_wiener<16, 16><<<grid, fwd_nt(16), 0, s>>>(a, f);
-        else dwt_fwd_wiener<16, 32><<<grid, fwd_nt(32), 0, s>>>(a, f);
+        if (tc == 32) PRNU_FWD(16, 32); else PRNU_FWD(16, 64);
     } else {
-        if (tt == 16) dwt_fwd_wiener<8, 16><<<grid, fwd_nt(16), 0, s>>>(a, f);
-        else dwt_fwd_wiener<8, 32><<<grid, fwd_nt(32), 0, s>>>(a, f);
+        if (tc == 32) PRNU_FWD(8, 32); else PRNU_FWD(8, 64);
     }
+#undef PRNU_FWD
     return hipGetLastError();
 }
 
@@ -949,11 +1098,11 @@ hipError_t launch_fwd_multi(int taps, int tt, const Filter &f, const FwdDesc *d,
                             int grid, hipStream_t s) {
     if (total <= 0 || nd <= 0) return hipSuccess;
     if (taps == 16) {
-        if (tt == 16) dwt_fwd_multi<16, 16><<<grid, fwd_nt(16), 0, s>>>(d, nd, total, ctr, f);
-        else dwt_fwd_multi<16, 32><<<grid, fwd_nt(32), 0, s>>>(d, nd, total, ctr, f);
+        if (tt == 32) dwt_fwd_multi<16, 32><<<grid, StripGeom<16, 32>::NTH, 0, s>>>(d, nd, total, ctr, f);
+        else dwt_fwd_multi<16, 64><<<grid, StripGeom<16, 64>::NTH, 0, s>>>(d, nd, total, ctr, f);
     } else {
-        if (tt == 16) dwt_fwd_multi<8, 16><<<grid, fwd_nt(16), 0, s>>>(d, nd, total, ctr, f);
-        else dwt_fwd_multi<8, 32><<<grid, fwd_nt(32), 0, s>>>(d, nd, total, ctr, f);
+        if (tt == 32) dwt_fwd_multi<8, 32><<<grid, StripGeom<8, 32>::NTH, 0, s>>>(d, nd, total, ctr, f);
+        else dwt_fwd_multi<8, 64><<<grid, StripGeom<8, 64>::NTH, 0, s>>>(d, nd, total, ctr, f);
     }
     return hipGetLastError();
 }
@@ -1006,9 +1155,10 @@ hipError_t launch_fill_pattern(float *x, int64_t n, hipStream_t s) {
 
 int fwd_multi_occupancy(int taps, int tt) {
     if (taps == 16)
-        return tt == 16 ? occupancy_of(dwt_fwd_multi<16, 16>, fwd_nt(16))
-                        : occupancy_of(dwt_fwd_multi<16, 32>, fwd_nt(32));
-    return tt == 16 ? occupancy_of(dwt_fwd_multi<8, 16>, fwd_nt(16)) : occupancy_of(dwt_fwd_multi<8, 32>, fwd_nt(32));
+        return tt == 32 ? occupancy_of(dwt_fwd_multi<16, 32>, StripGeom<16, 32>::NTH)
+                        : occupancy_of(dwt_fwd_multi<16, 64>, StripGeom<16, 64>::NTH);
+    return tt == 32 ? occupancy_of(dwt_fwd_multi<8, 32>, StripGeom<8, 32>::NTH)
+                    : occupancy_of(dwt_fwd_multi<8, 64>, StripGeom<8, 64>::NTH);
 }
 int inv_multi_occupancy(int taps, int tt) {
     if (taps == 16)

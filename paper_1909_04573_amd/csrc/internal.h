@@ -66,6 +66,9 @@ struct FwdArgs {
     // p = channel p % src8_c of frame p / src8_c), or null
     const unsigned char *src8;
     int src8_c;
+    // forward levels run by strips: tiles_c strips of the tile width across,
+    // segments of seg_rows coefficient rows down (see fwd_layout)
+    int seg_rows;
 };
 struct InvArgs {
     const float *lvl;
@@ -106,12 +109,19 @@ struct SdaDesc {
     int64_t block0;
 };
 
-// Tile side (16 or 32 subband coefficients) per kernel kind and level size;
-// 32 unless prnu_autotune measured otherwise.
+// Tile width per kernel kind and level size: the forward level runs strips
+// of 64 or 32 subband columns (64 unless prnu_autotune measured otherwise),
+// the inverse and MLE levels square tiles of 32 or 16 (32 by default).
 enum TileKind { TK_FWD = 0, TK_INV = 1, TK_MLE = 2 };
+inline int tile_default(int kind) { return kind == TK_FWD ? 64 : 32; }
+inline int tile_small(int kind) { return kind == TK_FWD ? 32 : 16; }
+inline bool tile_valid(int kind, int tt) { return tt == tile_default(kind) || tt == tile_small(kind); }
 int tile_choice(int kind, int taps, int hk, int wk);
 void set_tile_choice(int kind, int taps, int hk, int wk, int tt);
 inline int tiles_for(int tt, int hk, int wk) { return ((hk + tt - 1) / tt) * ((wk + tt - 1) / tt); }
+// Forward level of hk x wk coefficients over `planes` planes in strips of tc
+// columns: strips per plane, rows per segment and virtual blocks per plane.
+void fwd_layout(int tc, int hk, int wk, int64_t planes, int *strips, int *seg_rows, int *tiles);
 
 // ---- kernel launchers (all enqueue on `s`, return the launch status) -------
 // SDA: groups [g0, g1) of `group` frames; outputs indexed from g0.

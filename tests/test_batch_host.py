@@ -113,14 +113,21 @@ def test_batch_validation(lib):
 
 
 def test_tile_state(lib):
+    """Forward levels take strips of 64 (default) or 32 columns, inverse and
+    MLE levels tiles of 32 (default) or 16, per kind, filter length and size."""
+    assert prnu.get_tile(prnu.TILE_FWD, 16, 1000, 999) == 64
+    prnu.set_tile(prnu.TILE_FWD, 16, 1000, 999, 32)
     assert prnu.get_tile(prnu.TILE_FWD, 16, 1000, 999) == 32
-    prnu.set_tile(prnu.TILE_FWD, 16, 1000, 999, 16)
-    assert prnu.get_tile(prnu.TILE_FWD, 16, 1000, 999) == 16
     assert prnu.get_tile(prnu.TILE_INV, 16, 1000, 999) == 32  # per kind
-    assert prnu.get_tile(prnu.TILE_FWD, 8, 1000, 999) == 32  # per filter length
+    prnu.set_tile(prnu.TILE_INV, 16, 1000, 999, 16)
+    assert prnu.get_tile(prnu.TILE_INV, 16, 1000, 999) == 16
+    assert prnu.get_tile(prnu.TILE_FWD, 8, 1000, 999) == 64  # per filter length
     prnu.set_tile(prnu.TILE_FWD, 16, 1000, 999, 0)
-    assert prnu.get_tile(prnu.TILE_FWD, 16, 1000, 999) == 32
-    for args in [(3, 16, 8, 8, 16), (0, 6, 8, 8, 16), (0, 16, 0, 8, 16), (0, 16, 8, 8, 24)]:
+    prnu.set_tile(prnu.TILE_INV, 16, 1000, 999, 0)
+    assert prnu.get_tile(prnu.TILE_FWD, 16, 1000, 999) == 64
+    assert prnu.get_tile(prnu.TILE_INV, 16, 1000, 999) == 32
+    for args in [(3, 16, 8, 8, 16), (0, 6, 8, 8, 32), (0, 16, 0, 8, 32), (0, 16, 8, 8, 24), (0, 16, 8, 8, 16),
+                 (1, 16, 8, 8, 64), (2, 16, 8, 8, 64)]:
         with pytest.raises(prnu.PrnuError):
             prnu.set_tile(*args)
 
@@ -137,7 +144,7 @@ def test_autotune_workspace(lib):
 
 def test_set_tiles_layout(lib):
     """set_tiles applies autotune's layout: forward levels 1..4, inverse 2..4, MLE."""
-    tiles = [16, 32, 16, 32, 0, 32, 16, 32, 16, 0, 0, 0]
+    tiles = [32, 64, 32, 64, 0, 32, 16, 32, 16, 0, 0, 0]
     try:
         prnu.set_tiles(1080, 1920, tiles)
         Hp, Wp = 1088, 1920

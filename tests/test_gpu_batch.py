@@ -126,15 +126,19 @@ def _all_geometries(taps=16, levels=4):
     return geo
 
 
-@pytest.mark.parametrize("tile", [16, 32])
+# tile widths per kind: forward strips 64 / 32 columns, inverse and MLE tiles 32 / 16
+WIDTHS = {prnu.TILE_FWD: (64, 32), prnu.TILE_INV: (32, 16), prnu.TILE_MLE: (32, 16)}
+
+
+@pytest.mark.parametrize("tile", ["default", "small"])
 def test_batch_tile_sizes(dev, data, tile):
-    _log(f"batch and per-camera path with {tile}x{tile} tiles")
+    _log(f"batch and per-camera path with the {tile} tile widths")
     frames, refs = data
     geo = _all_geometries()
     try:
         for kind in (prnu.TILE_FWD, prnu.TILE_INV, prnu.TILE_MLE):
             for hk, wk in geo:
-                prnu.set_tile(kind, 16, hk, wk, tile)
+                prnu.set_tile(kind, 16, hk, wk, WIDTHS[kind][tile == "small"])
         cams = _cams(frames, dev)
         b = prnu.Batch(cams)
         b.launch()
@@ -163,7 +167,7 @@ def test_mixed_tile_sizes_in_one_stage(dev, data):
     try:
         for i, (hk, wk) in enumerate(geo):
             for kind in (prnu.TILE_FWD, prnu.TILE_INV, prnu.TILE_MLE):
-                prnu.set_tile(kind, 16, hk, wk, 16 if (i + kind) % 2 else 32)
+                prnu.set_tile(kind, 16, hk, wk, WIDTHS[kind][(i + kind) % 2])
         cams = _cams(frames, dev)
         b = prnu.Batch(cams)
         b.launch()
@@ -228,7 +232,7 @@ def test_autotune_then_batch(dev, data):
     frames, refs = data
     n, H, W, C, d = CAMS[3]
     tiles = prnu.autotune(H, W, C)
-    assert all(t in (16, 32) for t in tiles[0:4]), tiles
+    assert all(t in WIDTHS[prnu.TILE_FWD] for t in tiles[0:4]), tiles
     assert all(t in (16, 32) for t in tiles[5:8]) and tiles[8] in (16, 32), tiles
     try:
         cams = _cams(frames, dev)
