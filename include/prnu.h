@@ -134,6 +134,28 @@ int prnu_denoise_residual(const float *img, int n_img, int H, int W, const prnu_
                           float *resid, void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Noise residuals without any allocation, for callers that cannot allocate
+ * device memory or pass a workspace: code under HIP graph / stream capture,
+ * tight serving loops, and hosts that forbid allocation.
+ *
+ * Same arguments, results and errors as prnu_denoise_residual minus the
+ * workspace: the scratch (the wavelet pyramid of a batch of planes) is a
+ * file-scope device array of PRNU_STATIC_SCRATCH_BYTES (64 MiB) that each GPU
+ * the library runs on holds until the process ends; its address is looked up
+ * on the first call on each device.  Planes are processed in batches that fit
+ * it; PRNU_E_INVAL if the pyramid of one padded H x W plane does not (the
+ * limit lies between 4000 x 3000 and 4096 x 4096 at 4 levels).  Nothing in the
+ * scratch needs to start at zero: every call overwrites what it reads.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time on
+ * one GPU (other streams or host threads) race and must be serialised by the
+ * caller.  The call allocates nothing (no hipMalloc / hipFree) and only
+ * enqueues kernels on `stream`.
+ */
+#define PRNU_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int prnu_denoise_residual_noalloc(const float *img, int n_img, int H, int W, const prnu_denoise_params *p,
+                                  float *resid, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Fused SDA -> residual -> MLE accumulation (Sec. III-B: the SDA frames are
  * denoised and combined with the MLE; group = 1 is the conventional
  * per-frame estimator of Sec. III-A).

@@ -144,8 +144,9 @@ int run_post(const float *in, int nf, int C, int H, int W, int flags, float sigm
 
 // ---- entry point plans ---------------------------------------------------
 int plan_denoise(Carver &cv, int n_img, int H, int W, const prnu_denoise_params *p, Pyramid *py,
-                 int *nb) {
+                 int *nb, int max_nb = 0) {
     *nb = batch_planes(n_img, H, W);
+    if (max_nb > 0 && *nb > max_nb) *nb = max_nb;
     carve_pyramid(cv, *nb, H, W, p->levels, py);
     return PRNU_OK;
 }
@@ -455,12 +456,9 @@ int prnu_denoise_residual_workspace_size(int n_img, int H, int W, const prnu_den
     return PRNU_OK;
 }
 
-static int denoise_impl(const char *fn, const float *img, int n_img, int H, int W, const prnu_denoise_params *p,
-                        float *resid, float *ckpt, void *ws, size_t ws_bytes, void *stream);
-
 int prnu_denoise_residual(const float *img, int n_img, int H, int W, const prnu_denoise_params *p,
                           float *resid, void *ws, size_t ws_bytes, void *stream) {
-    return denoise_impl("prnu_denoise_residual", img, n_img, H, W, p, resid, nullptr, ws, ws_bytes, stream);
+    return denoise_run("prnu_denoise_residual", img, n_img, H, W, p, resid, nullptr, ws, ws_bytes, stream);
 }
 
 int prnu_denoise_ckpt_floats(int H, int W, int levels, size_t *floats) {
@@ -475,11 +473,15 @@ int prnu_denoise_ckpt_floats(int H, int W, int levels, size_t *floats) {
 int prnu_denoise_residual_ckpt(const float *img, int n_img, int H, int W, const prnu_denoise_params *p,
                                float *resid, float *ckpt, void *ws, size_t ws_bytes, void *stream) {
     if (!ckpt) return fail(PRNU_E_INVAL, "prnu_denoise_residual_ckpt: null checkpoint");
-    return denoise_impl("prnu_denoise_residual_ckpt", img, n_img, H, W, p, resid, ckpt, ws, ws_bytes, stream);
+    return denoise_run("prnu_denoise_residual_ckpt", img, n_img, H, W, p, resid, ckpt, ws, ws_bytes, stream);
 }
 
-static int denoise_impl(const char *fn, const float *img, int n_img, int H, int W, const prnu_denoise_params *p,
-                        float *resid, float *ckpt, void *ws, size_t ws_bytes, void *stream) {
+}  // extern "C"
+
+namespace prnu {
+
+int denoise_run(const char *fn, const float *img, int n_img, int H, int W, const prnu_denoise_params *p,
+                float *resid, float *ckpt, void *ws, size_t ws_bytes, void *stream, int max_nb) {
     set_error("");
     if (!img || !resid) return fail(PRNU_E_INVAL, "%s: null pointer", fn);
     if (img == resid) return fail(PRNU_E_INVAL, "%s: resid may not alias img", fn);
@@ -489,10 +491,10 @@ static int denoise_impl(const char *fn, const float *img, int n_img, int H, int 
     Carver cv(nullptr);
     Pyramid py;
     int nb;
-    plan_denoise(cv, n_img, H, W, p, &py, &nb);
+    plan_denoise(cv, n_img, H, W, p, &py, &nb, max_nb);
     PRNU_TRY(check_ws(cv, ws, ws_bytes, fn));
     Carver real(ws);
-    plan_denoise(real, n_img, H, W, p, &py, &nb);
+    plan_denoise(real, n_img, H, W, p, &py, &nb, max_nb);
     Filter f;
     make_filter(p->taps, &f);
     hipStream_t s = (hipStream_t)stream;
@@ -507,6 +509,28 @@ static int denoise_impl(const char *fn, const float *img, int n_img, int H, int 
     }
     return PRNU_OK;
 }
+
+int denoise_planes_fitting(int H, int W, const prnu_denoise_params *p, size_t bytes) {
+    // the pyramid of nb planes, each level 256-byte aligned, must fit `bytes`
+    const int Hp = padded(H), Wp = padded(W);
+    size_t per = 0;
+    for (int l = 1; l <= p->levels; ++l) per += level_floats(Hp, Wp, l) * sizeof(float);
+    const size_t slack = (size_t)p->levels * kAlign;
+    if (bytes <= slack || per > bytes - slack) return 0;
+    int64_t nb = (int64_t)((bytes - slack) / per);
+    if (nb > 0x7fffffff) nb = 0x7fffffff;
+    for (; nb > 0; --nb) {
+        Carver cv(nullptr);
+        Pyramid py;
+        carve_pyramid(cv, (int)nb, H, W, p->levels, &py);
+        if (cv.off <= bytes) break;
+    }
+    return (int)nb;
+}
+
+}  // namespace prnu
+
+extern "C" {
 
 int prnu_fingerprint_accumulate_workspace_size(int n_frames, int H, int W, int C, int group,
                                                const prnu_denoise_params *p, size_t *bytes) {

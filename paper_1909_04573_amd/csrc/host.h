@@ -90,4 +90,11 @@ inline int check_flags(int flags, const char *fn) {
 
 inline size_t elem_bytes(int dtype) { return dtype == PRNU_U8 ? 1 : dtype == PRNU_BF16 ? 2 : 4; }
 
+// Residuals of float planes in batches of at most max_nb planes (0: the
+// default batch) through the workspace ws; optional sensitivity checkpoint.
+int denoise_run(const char *fn, const float *img, int n_img, int H, int W, const prnu_denoise_params *p,
+                float *resid, float *ckpt, void *ws, size_t ws_bytes, void *stream, int max_nb = 0);
+// Planes of H x W whose wavelet pyramid (the denoise workspace) fits `bytes`.
+int denoise_planes_fitting(int H, int W, const prnu_denoise_params *p, size_t bytes);
+
 }  // namespace prnu

@@ -27,7 +27,7 @@ _DT = {torch.uint8: U8, torch.bfloat16: BF16, torch.float32: F32}
 EXPORTS = (
     "prnu_last_error", "prnu_version", "prnu_default_denoise_params", "prnu_filter_coefficients",
     "prnu_sda_average",
-    "prnu_denoise_residual_workspace_size", "prnu_denoise_residual",
+    "prnu_denoise_residual_workspace_size", "prnu_denoise_residual", "prnu_denoise_residual_noalloc",
     "prnu_fingerprint_accumulate_workspace_size", "prnu_fingerprint_accumulate",
     "prnu_fingerprint_finalize_workspace_size", "prnu_fingerprint_finalize",
     "prnu_query_residual_workspace_size", "prnu_query_residual",
@@ -92,6 +92,7 @@ def lib() -> ctypes.CDLL:
     L.prnu_sda_average.argtypes = [_P, _I, _I, _I, _I, _I, _I, _P, _P, _P]
     L.prnu_denoise_residual_workspace_size.argtypes = [_I, _I, _I, _DP, ctypes.POINTER(_S)]
     L.prnu_denoise_residual.argtypes = [_P, _I, _I, _I, _DP, _P, _P, _S, _P]
+    L.prnu_denoise_residual_noalloc.argtypes = [_P, _I, _I, _I, _DP, _P, _P]
     L.prnu_fingerprint_accumulate_workspace_size.argtypes = [_I, _I, _I, _I, _I, _DP, ctypes.POINTER(_S)]
     L.prnu_fingerprint_accumulate.argtypes = [_P, _I, _I, _I, _I, _I, _I, _DP, _I, _P, _P, _P, _S, _P]
     L.prnu_fingerprint_finalize_workspace_size.argtypes = [_I, _I, _I, _I, ctypes.POINTER(_S)]
@@ -216,6 +217,19 @@ def denoise_residual(img: torch.Tensor, params: DenoiseParams | None = None) -> 
     _check(lib().prnu_denoise_residual(_ptr(x), n, H, W, ctypes.byref(p), _ptr(out), _ptr(ws),
                                        ws.numel(), _stream(x.device)))
     return out[0] if squeeze else out
+
+
+def denoise_residual_noalloc(img: torch.Tensor, out: torch.Tensor, params: DenoiseParams | None = None):
+    """W = I - F(I) of float planes [n][H][W] into `out`, with the library's
+    static per-GPU scratch (no workspace, nothing allocated by the call)."""
+    _cuda(img, "img")
+    _cuda(out, "out")
+    if img.dtype != torch.float32 or img.dim() != 3 or out.shape != img.shape or out.dtype != torch.float32:
+        raise ValueError("img and out must be float32 [n][H][W] of one shape")
+    n, H, W = img.shape
+    p = params or denoise_params()
+    _check(lib().prnu_denoise_residual_noalloc(_ptr(img), n, H, W, ctypes.byref(p), _ptr(out), _stream(img.device)))
+    return out
 
 
 def new_accumulators(C: int, H: int, W: int, acc_mode: int = ACC_F64, device="cuda"):

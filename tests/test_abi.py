@@ -148,3 +148,22 @@ def test_resample_validation(lib):
     ]
     for args in bad:
         assert lib.prnu_resample_bilinear(*args) == prnu.PRNU_E_INVAL, args
+
+
+def test_noalloc_validation(lib):
+    """The no-allocation residual call rejects bad arguments, and a plane whose
+    wavelet pyramid exceeds the static scratch, on the host before any device
+    work."""
+    p = prnu.denoise_params()
+    P = ctypes.byref(p)
+    fake = ctypes.c_void_p(0x100000)
+    out = ctypes.c_void_p(0x200000)
+    f = lib.prnu_denoise_residual_noalloc
+    assert f(None, 1, 64, 64, P, out, None) == prnu.PRNU_E_INVAL
+    assert f(fake, 1, 64, 64, P, fake, None) == prnu.PRNU_E_INVAL  # resid aliases img
+    assert f(fake, 0, 64, 64, P, out, None) == prnu.PRNU_E_INVAL
+    assert f(fake, 1, 15, 64, P, out, None) == prnu.PRNU_E_INVAL
+    bad = prnu.denoise_params(taps=6)
+    assert f(fake, 1, 64, 64, ctypes.byref(bad), out, None) == prnu.PRNU_E_UNSUPPORTED
+    assert f(fake, 1, 4096, 4096, P, out, None) == prnu.PRNU_E_INVAL
+    assert "static scratch" in lib.prnu_last_error().decode()
