@@ -9,6 +9,15 @@ summaries of PCE values the library computed; no method arithmetic.
 * auc(matched, unmatched): area under that curve, equal to the probability
   that a same-camera PCE exceeds a different-camera one (ties count 1/2).
 
+Fingerprint equivalence and the variance model (Sec. III-B, Sec. IV-B):
+
+* equal_variance_images(n, s1_sq, s2_sq, d): the image count m whose SDA-d
+  fingerprint has the error variance of a conventional one of n images;
+* variance_components(W, prnu_term): the noise (s1^2) and scene (s2^2)
+  variances of the residual model from R residuals of one scene;
+* equivalent_images(conv, sda): per conventional image count, the fewest
+  images an SDA fingerprint needs to reach at least its TPR.
+
 Stabilised video (Sec. V-E), orchestration of library calls:
 
 * segment_shifts(W, I, K_ref): per SDA frame, the translation of a reference
@@ -58,6 +67,44 @@ def auc(matched, unmatched) -> float:
     below = np.searchsorted(us, m, side="left")
     equal = np.searchsorted(us, m, side="right") - below
     return float((below.sum() + 0.5 * equal.sum()) / (m.size * u.size))
+
+
+# ---------------------------------------------------------------- equivalence and variance model
+def equal_variance_images(n: float, s1_sq: float, s2_sq: float, d: int) -> float:
+    """Sec. III-B: with the residual of a frame modelled as I K + psi + xi,
+    psi the noise term (variance s1^2, averaged down by d in an SDA frame)
+    and xi the scene term (variance s2^2, not averaged), n conventional
+    images and m = n (s1^2 + d s2^2) / (s1^2 + s2^2) images in SDA-d frames
+    give fingerprints of equal error variance.  s2^2 = 0 gives m = n."""
+    if s1_sq < 0 or s2_sq < 0 or s1_sq + s2_sq <= 0 or d < 1:
+        raise ValueError("variances must be >= 0, not both 0, and d >= 1")
+    return float(n) * (s1_sq + d * s2_sq) / (s1_sq + s2_sq)
+
+
+def variance_components(W, prnu_term):
+    """(s1^2, s2^2) of the residual model from R >= 2 residuals W[r] of one
+    scene that share the scene and the PRNU term and differ only in their
+    noise: s1^2 is the unbiased variance across the R residuals, averaged
+    over pixels; the mean residual minus the PRNU term then holds the scene
+    term plus the noise averaged over R, so s2^2 = mean((mean_r W - prnu)^2)
+    - s1^2 / R, clipped at 0."""
+    W = np.asarray(W, dtype=np.float64)
+    P = np.asarray(prnu_term, dtype=np.float64)
+    R = W.shape[0]
+    if R < 2 or W.shape[1:] != P.shape:
+        raise ValueError("need R >= 2 residuals of the PRNU term's shape")
+    mean = W.mean(axis=0)
+    s1 = float(((W - mean) ** 2).sum(axis=0).mean() / (R - 1))
+    s2 = max(float(((mean - P) ** 2).mean()) - s1 / R, 0.0)
+    return s1, s2
+
+
+def equivalent_images(conv: dict, sda: dict) -> dict:
+    """{n: m}: for each conventional image count n (TPR conv[n]) the smallest
+    m among sda's image counts whose TPR sda[m] is at least conv[n]; None if
+    none reaches it (Sec. IV-B, Fig. 5: the fingerprint-equivalence search)."""
+    ms = sorted(sda)
+    return {n: next((m for m in ms if sda[m] >= t), None) for n, t in sorted(conv.items())}
 
 
 # ---------------------------------------------------------------- stabilised video (Sec. V-E)

@@ -201,3 +201,58 @@ def test_aligned_fingerprint_lines_patterns_up(monkeypatch):
     assert seen["d"] == 1 and tuple(seen["fr"].shape) == (3, 24, 27, 1)
     for j in range(3):
         np.testing.assert_array_equal(seen["fr"][j, :, :, 0].numpy(), K[M:M + 24, M:M + 27].astype(np.float32))
+
+
+# ---------------------------------------------------------------- equivalence and variance model
+def test_equal_variance_images_budget():
+    """The SDA frame budget of Sec. III-B: no scene term gives m = n; the
+    values of the simulated budget pin (s1^2 = 6, s2^2 = 2, d = 3, n = 20 ->
+    m = 30); m grows linearly in d with slope n s2^2 / (s1^2 + s2^2)."""
+    assert ev.equal_variance_images(50, 4.0, 0.0, 10) == 50.0
+    assert ev.equal_variance_images(20, 6.0, 2.0, 3) == 30.0
+    assert ev.equal_variance_images(20, 6.0, 2.0, 1) == 20.0
+    a, b = ev.equal_variance_images(40, 3.0, 1.0, 5), ev.equal_variance_images(40, 3.0, 1.0, 6)
+    assert abs((b - a) - 40 * 1.0 / 4.0) < 1e-12
+    for bad in [(10, -1.0, 1.0, 2), (10, 0.0, 0.0, 2), (10, 1.0, 1.0, 0)]:
+        with pytest.raises(ValueError):
+            ev.equal_variance_images(*bad)
+
+
+@pytest.mark.parametrize("s1,s2", [(4.0, 0.0), (3.25, 0.6), (1.0, 2.0)])
+def test_variance_components_recover_generator_variances(s1, s2):
+    """R residuals W_r = P + xi + psi_r with a scene term xi ~ N(0, s2) shared
+    by all r and noise psi_r ~ N(0, s1) drawn per r: the estimator returns
+    (s1, s2) within the sampling error of 256 x 256 pixels."""
+    g = np.random.default_rng(1909)
+    R, shape = 16, (256, 256)
+    P = g.normal(0, 0.5, size=shape)
+    xi = g.normal(0, np.sqrt(s2), size=shape)
+    W = P + xi + g.normal(0, np.sqrt(s1), size=(R,) + shape)
+    e1, e2 = ev.variance_components(W, P)
+    assert abs(e1 / s1 - 1) < 0.02
+    assert abs(e2 - s2) < 0.03 * max(s2, 1.0)
+
+
+def test_variance_components_exact_cases():
+    """No noise: s1 = 0 and s2 is the scene term's mean square exactly; the
+    PRNU term itself contributes nothing; too few residuals are refused."""
+    P = np.arange(12.0).reshape(3, 4)
+    xi = np.array([[1.0, -1.0, 2.0, 0.0]] * 3)
+    W = np.stack([P + xi] * 4)
+    s1, s2 = ev.variance_components(W, P)
+    assert s1 == 0.0 and s2 == pytest.approx(np.mean(xi ** 2))
+    assert ev.variance_components(np.stack([P, P]), P) == (0.0, 0.0)
+    with pytest.raises(ValueError):
+        ev.variance_components(W[:1], P)
+    with pytest.raises(ValueError):
+        ev.variance_components(W, P[:2])
+
+
+def test_equivalent_images_search():
+    conv = {40: 0.26, 50: 0.5, 60: 0.7, 80: 0.95, 100: 0.99}
+    sda = {50: 0.3, 75: 0.71, 100: 0.95, 125: 0.99}
+    got = ev.equivalent_images(conv, sda)
+    assert got == {40: 50, 50: 75, 60: 75, 80: 100, 100: 125}
+    assert ev.equivalent_images({10: 1.0}, {50: 0.99, 100: 0.999}) == {10: None}
+    assert ev.equivalent_images({10: 0.5}, {100: 0.5, 50: 0.5}) == {10: 50}  # ties reach, smallest m
+    assert ev.equivalent_images({}, {50: 1.0}) == {}
