@@ -53,7 +53,9 @@ constexpr int inv_nt(int tt) { return tt == 32 ? INV_NT32 : NT; }
 template <int TAPS, int TT>
 struct InvGeom {
     static constexpr int NK = TT + TAPS / 2 - 1;  // coefficients per side
-    static constexpr int NKS = NK + 1;
+    // odd row stride: the row pass's lanes read every other column of two
+    // consecutive rows, which then fall in banks of opposite parity
+    static constexpr int NKS = NK | 1;
     static constexpr int NO = 2 * TT;             // outputs per side
     static constexpr int SB = 4 * NK * NKS;
     static constexpr int L1 = NO * NKS;
@@ -102,6 +104,14 @@ __device__ __forceinline__ int map_index(int p, int n, int off, int stored) {
 // is paid once per segment instead of once per tile.
 constexpr int SR = 16;  // coefficient rows per step; also the period of the Wiener register ring (>= 9)
 
+// High-pass tap j as the quadrature mirror of the low-pass, g[j] =
+// (-1)^j h[TAPS-1-j] (exactly the host's g): the sign becomes a source
+// modifier of the FMA, so only the TAPS low-pass taps occupy scalar registers.
+template <int TAPS>
+__device__ __forceinline__ float qmf_g(const Filter &f, int j) {
+    return (j & 1) ? -f.h[TAPS - 1 - j] : f.h[TAPS - 1 - j];
+}
+
 template <int TAPS, int TC>
 struct StripGeom {
     static constexpr int NTH = 4 * TC;             // threads: 3 TC Wiener columns + TC helpers
@@ -128,6 +138,7 @@ struct StripGeom {
     static_assert(INCQ >= INC + 2 && INCS >= INCQ && INCS % 32 == 4, "staged row layout");
     static_assert(NC % 4 == 0 && RING % 4 == 0 && QF % 4 == 0 && AREA % 4 == 0, "16-byte aligned LDS areas");
     static_assert(NTH - NW >= 32, "helper threads for the ring move");
+    static_assert((SR & (SR - 1)) == 0, "SR a power of two");
 };
 
 // Strips per plane, segment rows and virtual blocks of a forward level of
@@ -294,7 +305,7 @@ __device__ __forceinline__ void strip_rows(int tid, const float *S, float *ring,
 #pragma unroll
                 for (int j = 0; j < TAPS; ++j) {
                     rl[u] = fmaf(f.h[j], x[2 * u + j], rl[u]);
-                    rh[u] = fmaf(f.g[j], x[2 * u + j], rh[u]);
+                    rh[u] = fmaf(qmf_g<TAPS>(f, j), x[2 * u + j], rh[u]);
                 }
             }
             *reinterpret_cast<float4 *>(&rlo[(row0 + i) * NC + 4 * kq]) = make_float4(rl[0], rl[1], rl[2], rl[3]);
@@ -367,6 +378,31 @@ __device__ __forceinline__ void fwd_strip(const FwdArgs &a, int tile, int plane,
     __syncthreads();
 
     const bool cols_in = J0 >= 0 && J0 + NC <= wk;
+    // Column-pass items of this thread, the same every step: (row band b,
+    // coefficient row pair kp, column pair cp) -> LDS addresses of its ring
+    // reads and of its square / coefficient writes, and its approximation
+    // offset relative to the step's first row.  Kept in registers.
+    typedef __attribute__((address_space(3))) float lds_rw;
+    typedef float v2f __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(3))) v2f lds_rw2;
+    constexpr int CITEMS = 2 * NP * (SR / 2), NCI = (CITEMS + NTH - 1) / NTH;
+    lds_rw *ci_rd[NCI], *ci_qh[NCI], *ci_ql[NCI], *ci_ch[NCI], *ci_cl[NCI];
+    int ci_ll[NCI], ci_meta[NCI];  // meta: bit 0 valid, 1 b, 2 core column, 3 col 0 in band, 4 col 1 in band; kp << 8
+#pragma unroll
+    for (int k = 0; k < NCI; ++k) {
+        const int it = tid + k * NTH;
+        const int q8 = it / NP, cp = it - (it / NP) * NP, kp = q8 & (SR / 2 - 1), b = (q8 / (SR / 2)) & 1;
+        const int gc = J0 + 2 * cp;
+        const bool core_c = cp >= HALO / 2 && cp < (HALO + TC) / 2;
+        ci_rd[k] = (lds_rw *)(ring + b * RR * NC + 4 * kp * NC + 2 * cp);
+        ci_qh[k] = (lds_rw *)(Q + ((1 + b) * SR + 2 * kp) * NC + 2 * cp);
+        ci_ql[k] = (lds_rw *)(Q + (2 * kp) * NC + 2 * cp);
+        ci_ch[k] = (lds_rw *)(Cb + ((1 + b) * SR + 2 * kp) * TC + 2 * cp - HALO);
+        ci_cl[k] = (lds_rw *)(Cb + (2 * kp) * TC + 2 * cp - HALO);
+        ci_ll[k] = 2 * kp * wk + gc;
+        ci_meta[k] = (it < CITEMS ? 1 : 0) | (b << 1) | (core_c ? 4 : 0) | (gc >= 0 && gc < wk ? 8 : 0) |
+                     (gc + 1 >= 0 && gc + 1 < wk ? 16 : 0) | (kp << 8);
+    }
     WienerRing wr;
 #pragma unroll
     for (int i = 0; i < SR; ++i) {
@@ -384,21 +420,30 @@ __device__ __forceinline__ void fwd_strip(const FwdArgs &a, int tile, int plane,
         __syncthreads();
         // C: column pass, coefficient rows kb .. kb + SR - 1
         const int kb = K0 + SR * t;
+        const int kbwk = kb * wk;
         const bool inside = cols_in && kb >= 0 && kb + SR <= hk;
         auto cols = [&](auto masked) {
-            constexpr int ITEMS = 2 * NP * (SR / 2);
-#pragma unroll 1
-            for (int k = 0; k < (ITEMS + NTH - 1) / NTH; ++k) {
-                const int it = tid + k * NTH;
-                if (it >= ITEMS) continue;
-                const int cp = it % NP, kp = (it / NP) % (SR / 2), b = it / (NP * (SR / 2));
-                const float *rb = ring + b * RR * NC;
+#pragma unroll
+            for (int k = 0; k < NCI; ++k) {
+                __builtin_amdgcn_sched_barrier(0);  // one item at a time: registers
+                const int meta = ci_meta[k];
+                if (!(meta & 1)) continue;
+                const int b = (meta >> 1) & 1, kp = meta >> 8;
+                const bool core_c = (meta & 4) != 0;
+                const bool cv0 = !masked || (meta & 8), cv1 = !masked || (meta & 16);
+                const lds_rw *rb = ci_rd[k];
                 float2 xv[TAPS + 2];
 #pragma unroll
-                for (int u = 0; u < TAPS + 2; ++u) xv[u] = *reinterpret_cast<const float2 *>(&rb[(4 * kp + u) * NC + 2 * cp]);
-                const int gc = J0 + 2 * cp;
-                const bool core_c = cp >= HALO / 2 && cp < (HALO + TC) / 2;
-                const bool cv0 = !masked || (gc >= 0 && gc < wk), cv1 = !masked || (gc + 1 >= 0 && gc + 1 < wk);
+                for (int u = 0; u < TAPS + 2; ++u) {
+                    const v2f t2 = *(const lds_rw2 *)(&rb[u * NC]);
+                    xv[u] = make_float2(t2.x, t2.y);
+                }
+                // approximation (row low-pass items, strip columns, the segment's rows) to HBM
+                const bool llc = b == 0 && a.write_ll && core_c;
+                const unsigned ll0 = llc ? (unsigned)(kbwk + ci_ll[k]) * 4u : ll_bytes;
+                // the high-pass output goes to band 1 (hl) from row low-pass items, band 2 (hh)
+                // from row high-pass ones; the low-pass output of row high-pass items to band 0 (lh)
+                lds_rw *qh = ci_qh[k], *ql = ci_ql[k], *ch = ci_ch[k], *cl = ci_cl[k];
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
                     float l0 = 0.f, l1 = 0.f, h0 = 0.f, h1 = 0.f;
@@ -407,32 +452,26 @@ __device__ __forceinline__ void fwd_strip(const FwdArgs &a, int tile, int plane,
                         const float2 v = xv[2 * u + j];
                         l0 = fmaf(f.h[j], v.x, l0);
                         l1 = fmaf(f.h[j], v.y, l1);
-                        h0 = fmaf(f.g[j], v.x, h0);
-                        h1 = fmaf(f.g[j], v.y, h1);
+                        h0 = fmaf(qmf_g<TAPS>(f, j), v.x, h0);
+                        h1 = fmaf(qmf_g<TAPS>(f, j), v.y, h1);
                     }
-                    const int ur = 2 * kp + u, kr = kb + ur;
+                    const int kr = kb + 2 * kp + u;
                     const bool rv = !masked || (kr >= 0 && kr < hk);
-                    auto put = [&](int s, float c0, float c1) {
-                        float2 q2 = make_float2(c0 * c0, c1 * c1);
-                        if (masked) q2 = make_float2(rv && cv0 ? q2.x : 0.f, rv && cv1 ? q2.y : 0.f);
-                        *reinterpret_cast<float2 *>(&Q[(s * SR + ur) * NC + 2 * cp]) = q2;
-                        if (core_c)
-                            *reinterpret_cast<float2 *>(&Cb[(s * SR + ur) * TC + 2 * cp - HALO]) = make_float2(c0, c1);
+                    auto sq = [&](float c0, float c1) {
+                        v2f q2 = v2f{c0 * c0, c1 * c1};
+                        if (masked) q2 = v2f{rv && cv0 ? q2.x : 0.f, rv && cv1 ? q2.y : 0.f};
+                        return q2;
                     };
-                    // approximation rows of the segment (row low-pass items, strip columns) to HBM
-                    const bool llr = b == 0 && a.write_ll && core_c && kr >= R0 && kr < oend;
-                    const unsigned lo = (unsigned)((int64_t)kr * wk + gc) * 4u;
-                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(l0), ll_rs, llr && gc < wk ? lo : ll_bytes,
+                    const bool llr = kr >= R0 && kr < oend;
+                    const unsigned lo = ll0 + (unsigned)u * (unsigned)wk * 4u;
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(l0), ll_rs, llr && cv0 ? lo : ll_bytes, 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(l1), ll_rs, llr && cv1 ? lo + 4u : ll_bytes,
                                                           0, 0);
-                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(l1), ll_rs,
-                                                          llr && gc + 1 < wk ? lo + 4u : ll_bytes, 0, 0);
-                    if (b == 0) {
-                        // row low-pass: hl (band 1)
-                        put(1, h0, h1);
-                    } else {
-                        // row high-pass: lh (band 0) and hh (band 2)
-                        put(0, l0, l1);
-                        put(2, h0, h1);
+                    *(lds_rw2 *)(&qh[u * NC]) = sq(h0, h1);
+                    if (core_c) *(lds_rw2 *)(&ch[u * TC]) = v2f{h0, h1};
+                    if (b == 1) {
+                        *(lds_rw2 *)(&ql[u * NC]) = sq(l0, l1);
+                        if (core_c) *(lds_rw2 *)(&cl[u * TC]) = v2f{l0, l1};
                     }
                 }
             }
@@ -444,16 +483,22 @@ __device__ __forceinline__ void fwd_strip(const FwdArgs &a, int tile, int plane,
         __syncthreads();
         // W: Wiener shrinkage of the strip's detail columns, four rows behind
         float res[SR], sen[CK ? SR : 1];
-        unsigned okm = 0u;  // bit i: the step's output row i is stored
         const int ob = R0 + SR * t - 2 * HALO;  // output row of the step's row i is ob + i (from row R0 on)
-        unsigned obase = 0u;                    // byte offset of output row ob in the detail bands
+        // byte offset of output row ob of this thread's column in the detail
+        // bands; out of range for helper threads and columns past the band
+        unsigned obase = det_bytes;
         if (tid < G::NW) {
             const int s = tid / TC, jc = tid - (tid / TC) * TC;
-            const float *Qs = Q + s * SR * NC + jc;
-            const float *Cs = Cb + s * SR * TC + jc;
+            // the column's LDS addresses as opaque registers: every load is
+            // then that register plus an immediate offset (the compiler would
+            // otherwise rebuild the area's base address for each pair of loads)
+            typedef __attribute__((address_space(3))) const float lds_f32;
+            lds_f32 *Qs = (lds_f32 *)(Q + s * SR * NC + jc);
+            lds_f32 *Cs = (lds_f32 *)(Cb + s * SR * TC + jc);
+            asm volatile("" : "+v"(Qs), "+v"(Cs));
             const float s2 = a.s2;
             const bool col_ok = C0 + jc < wk;
-            obase = (unsigned)((int64_t)s * band + (int64_t)ob * wk + C0 + jc) * 4u;
+            if (col_ok) obase = (unsigned)((int64_t)s * band + (int64_t)ob * wk + C0 + jc) * 4u;
 #pragma unroll
             for (int i = 0; i < SR; ++i) {
                 float q[9];
@@ -490,8 +535,6 @@ __device__ __forceinline__ void fwd_strip(const FwdArgs &a, int tile, int plane,
                 res[i] = c * (den > 0.f ? s2 * rcp : 0.f);
                 // sensitivity dr/ds = c / m where the window mean m exceeds s2, else 0
                 if (CK) sen[CK ? i : 0] = den > s2 ? c * rcp : 0.f;
-                const int orw = ob + i;  // absolute output row
-                if ((t > 0 || i >= 2 * HALO) && orw < oend && col_ok) okm |= 1u << i;
             }
         } else {
 #pragma unroll
@@ -510,7 +553,9 @@ __device__ __forceinline__ void fwd_strip(const FwdArgs &a, int tile, int plane,
         const unsigned row_bytes = (unsigned)wk * 4u;
 #pragma unroll
         for (int i = 0; i < SR; ++i) {
-            const unsigned o = (okm >> i) & 1u ? obase + (unsigned)i * row_bytes : det_bytes;
+            // rows before the segment's first output row or past its end (uniform)
+            const bool rok = (t > 0 || i >= 2 * HALO) && ob + i < oend;
+            const unsigned o = rok ? obase + (unsigned)i * row_bytes : det_bytes;
             __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(res[i]), det_rs, o, 0, 0);
             if (CK) __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(sen[CK ? i : 0]), ck_rs, o, 0, 0);
         }
