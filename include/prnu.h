@@ -107,20 +107,33 @@ void prnu_default_denoise_params(prnu_denoise_params *p);
  * double.  taps in {2,4,...,20}.  Enqueues nothing. */
 int prnu_filter_coefficients(int taps, double *h);
 
+/* Status bits a call ORs into a caller-zeroed device word */
+#define PRNU_STATUS_NONFINITE 1u /* a BF16/F32 frame sample was NaN or +-Inf */
+
 /* ---------------------------------------------------------------------------
- * SDA frames (Sec. III-B: the mean of d consecutive frames).
+ * SDA frames (Sec. III-B: the mean of d consecutive frames; the group sizes
+ * n_i of the last group's shorter run).
  *
- * frames  [n_frames][H][W][C] of `dtype`.
+ * frames  n_frames frames of H x W x C interleaved samples of `dtype`; frame f
+ *         starts at frames + f * frame_stride_bytes.  frame_stride_bytes = 0
+ *         means dense (H*W*C*element size); otherwise it must be at least that
+ *         and a multiple of the element size (frames that sit inside larger
+ *         decoder surfaces, or every k-th frame of a buffer).
  * group   d >= 1: group i holds frames i*d .. min((i+1)*d, n_frames) - 1;
  *         g = ceil(n_frames / d) groups.
  * sums    PRNU_U8 only (else must be NULL), nullable: uint32 [g][C][H][W],
  *         exact integer sums (n_frames <= 16843009 so 255*d fits).
  * means   nullable: float [g][C][H][W] = sum / count, correctly rounded
  *         (U8: the exact integer sum divided once; BF16/F32: sum in double).
+ * counts  nullable: int32 [g], the number of frames in each group.
+ * status  nullable device word; PRNU_STATUS_NONFINITE is ORed in when a
+ *         BF16/F32 group sum is NaN or infinite (a NaN or infinite sample;
+ *         u8 frames never set it).  The caller clears it.
  * At least one of sums/means must be given.
  */
-int prnu_sda_average(const void *frames, int dtype, int n_frames, int H, int W, int C, int group,
-                     uint32_t *sums, float *means, void *stream);
+int prnu_sda_average(const void *frames, int dtype, int n_frames, int H, int W, int C,
+                     int64_t frame_stride_bytes, int group, uint32_t *sums, float *means, int *counts,
+                     uint32_t *status, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Noise residual W = I - F(I) of float planes (Sec. II-A; denoiser of Sec. IV).
@@ -160,18 +173,37 @@ int prnu_denoise_residual_noalloc(const float *img, int n_img, int H, int W, con
  * denoised and combined with the MLE; group = 1 is the conventional
  * per-frame estimator of Sec. III-A).
  *
- * frames   [n_frames][H][W][C] of `dtype`; SDA groups of `group` frames are
- *          formed inside this call (the last may be shorter).
+ * frames   n_frames frames of H x W x C samples of `dtype`, frame f at
+ *          frames + f * frame_stride_bytes (0 = dense, as prnu_sda_average);
+ *          SDA groups of `group` frames are formed inside this call (the last
+ *          may be shorter).  Depth-1 u8 frames are read in place when dense;
+ *          strided ones are first gathered by the SDA kernel.
  * A, B     accumulators in the layout of `acc_mode` (see PRNU_ACC_*), per
  *          channel: A += sum_i W_i * I_i, B += sum_i I_i^2 over this call's SDA
  *          frames I_i.  The caller zeroes them once; calling again with more
  *          frames continues the same sums (streaming / resume).
+ * state    nullable device prnu_acc_state kept beside A and B (zeroed with
+ *          them): after each internal batch's MLE fold, on the same stream,
+ *          `frames` and `sda_frames` grow by that batch's counts, and
+ *          PRNU_STATUS_NONFINITE is ORed into `status` when a BF16/F32 frame
+ *          holds a NaN or infinity.  (A, B, state) is the checkpoint of a
+ *          streamed fingerprint: a run that stopped part-way shows fewer
+ *          frames than were submitted.  With group > 1 a call's groups are
+ *          its own: resuming mid-group is the caller's split of the frames.
  */
+typedef struct prnu_acc_state {
+    int64_t frames;     /* frames folded into A, B                          */
+    int64_t sda_frames; /* SDA frames (groups) folded into A, B             */
+    uint32_t status;    /* PRNU_STATUS_* bits                               */
+    uint32_t reserved;
+} prnu_acc_state;
+
 int prnu_fingerprint_accumulate_workspace_size(int n_frames, int H, int W, int C, int group,
                                                const prnu_denoise_params *p, size_t *bytes);
 int prnu_fingerprint_accumulate(const void *frames, int dtype, int n_frames, int H, int W, int C,
-                                int group, const prnu_denoise_params *p, int acc_mode, void *A,
-                                void *B, void *ws, size_t ws_bytes, void *stream);
+                                int64_t frame_stride_bytes, int group, const prnu_denoise_params *p,
+                                int acc_mode, void *A, void *B, prnu_acc_state *state, void *ws,
+                                size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Fingerprint finalisation: K = A / B per channel (0 where B = 0), then the
@@ -234,6 +266,24 @@ int prnu_extract_blocks(const float *src, int n, int H, int W, int b, float *out
  */
 int prnu_resample_bilinear(const float *src, int n, int H, int W, double scale, int oy, int ox, int oh, int ow,
                            float *out, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Affine bilinear warp for stabilised video (Sec. II-B: digital stabilisers
+ * shift, rotate, shear or zoom each frame, so frames' sensor patterns are
+ * misaligned; Sec. V-E matches stabilised videos).
+ *
+ * out[k][y][x] = bilinear sample of src[k % n_src] at column
+ *   u = m0 x + m1 y + m2 and row v = m3 x + m4 y + m5 (pixel indices),
+ * m = affine + 6 k: a DEVICE array of n * 6 doubles (one matrix per output
+ * plane); u and v are computed in double and clamped to the plane (edge
+ * replication).  src [n_src][H][W] fp32, out [n][oh][ow] fp32 (may not alias
+ * src).  With m = (1/s, 0, (ox + 0.5)/s - 0.5, 0, 1/s, (oy + 0.5)/s - 0.5)
+ * it is prnu_resample_bilinear.  PRNU_E_INVAL for null pointers, n_src < 1,
+ * n outside [1, 65535], or sizes outside [1, 32768].  Enqueued on `stream`;
+ * nothing is allocated.
+ */
+int prnu_warp_affine(const float *src, int n_src, int H, int W, const double *affine, int n, int oh, int ow,
+                     float *out, void *stream);
 
 /* ---------------------------------------------------------------------------
  * PCE / NCC matching (Sec. II-A correlation; Sec. IV uses PCE > 60).

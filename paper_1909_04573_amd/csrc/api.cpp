@@ -2,14 +2,19 @@
 // and the launch sequences of every entry point.  Nothing here allocates
 // device memory; every buffer comes from the caller.
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <climits>
 
 #include "host.h"
 #include "internal.h"
+
+// The Python binding views prnu_acc_state as int64 [3].
+static_assert(sizeof(prnu_acc_state) == 24 && offsetof(prnu_acc_state, status) == 16, "prnu_acc_state layout");
 
 namespace prnu {
 
@@ -425,18 +430,21 @@ void prnu_default_denoise_params(prnu_denoise_params *p) {
     for (int l = 0; l < 4; ++l) p->level_weight[l] = 1.0f;
 }
 
-int prnu_sda_average(const void *frames, int dtype, int n_frames, int H, int W, int C, int group,
-                     uint32_t *sums, float *means, void *stream) {
+int prnu_sda_average(const void *frames, int dtype, int n_frames, int H, int W, int C, int64_t frame_stride_bytes,
+                     int group, uint32_t *sums, float *means, int *counts, uint32_t *status, void *stream) {
     const char *fn = "prnu_sda_average";
     set_error("");
     PRNU_TRY(check_frames(frames, dtype, n_frames, C, fn));
     if (H < 1 || W < 1 || H > kMaxDim || W > kMaxDim) return fail(PRNU_E_INVAL, "%s: bad H x W", fn);
+    int64_t fstride;
+    PRNU_TRY(check_frame_stride(frame_stride_bytes, dtype, n_frames, H, W, C, fn, &fstride));
     if (group < 1) return fail(PRNU_E_INVAL, "%s: group must be >= 1", fn);
     if (!sums && !means) return fail(PRNU_E_INVAL, "%s: need sums or means", fn);
     if (sums && dtype != PRNU_U8) return fail(PRNU_E_INVAL, "%s: integer sums need u8 frames", fn);
     if (n_frames > 16843009) return fail(PRNU_E_INVAL, "%s: too many frames for u32 sums", fn);
     const int g = (n_frames + group - 1) / group;
-    PRNU_HIP(launch_sda(frames, dtype, n_frames, H, W, C, group, 0, g, sums, means, (hipStream_t)stream));
+    PRNU_HIP(launch_sda(frames, fstride, dtype, n_frames, H, W, C, group, 0, g, sums, means, counts, status,
+                        (hipStream_t)stream));
     return PRNU_OK;
 }
 
@@ -549,12 +557,14 @@ int prnu_fingerprint_accumulate_workspace_size(int n_frames, int H, int W, int C
 }
 
 int prnu_fingerprint_accumulate(const void *frames, int dtype, int n_frames, int H, int W, int C,
-                                int group, const prnu_denoise_params *p, int acc_mode, void *A, void *B,
-                                void *ws, size_t ws_bytes, void *stream) {
+                                int64_t frame_stride_bytes, int group, const prnu_denoise_params *p, int acc_mode,
+                                void *A, void *B, prnu_acc_state *state, void *ws, size_t ws_bytes, void *stream) {
     const char *fn = "prnu_fingerprint_accumulate";
     set_error("");
     PRNU_TRY(check_frames(frames, dtype, n_frames, C, fn));
     PRNU_TRY(check_dims(H, W, fn));
+    int64_t fstride;
+    PRNU_TRY(check_frame_stride(frame_stride_bytes, dtype, n_frames, H, W, C, fn, &fstride));
     PRNU_TRY(check_params(p, fn));
     if (group < 1) return fail(PRNU_E_INVAL, "%s: group must be >= 1", fn);
     if (acc_mode != PRNU_ACC_F64 && acc_mode != PRNU_ACC_KAHAN_F32 && acc_mode != PRNU_ACC_F32)
@@ -572,18 +582,25 @@ int prnu_fingerprint_accumulate(const void *frames, int dtype, int n_frames, int
     hipStream_t s = (hipStream_t)stream;
     const int g = (n_frames + group - 1) / group;
     const int Hp = padded(H), Wp = padded(W);
-    // SDA depth 1 on u8 frames: the means are the frames themselves (exact in
-    // float), so the level-1 forward and the MLE fold read the frames directly
-    const bool direct = group == 1 && dtype == PRNU_U8;
+    // SDA depth 1 on dense u8 frames: the means are the frames themselves
+    // (exact in float), so the level-1 forward and the MLE fold read the
+    // frames directly
+    const bool direct = group == 1 && dtype == PRNU_U8 && fstride == (int64_t)H * W * C;
+    uint32_t *status = state ? &state->status : nullptr;
     for (int g0 = 0; g0 < g; g0 += ap.nb) {
         const int g1 = g0 + ap.nb < g ? g0 + ap.nb : g;
         const int nb = g1 - g0;
-        const unsigned char *f8 =
-            direct ? static_cast<const unsigned char *>(frames) + (int64_t)g0 * H * W * C : nullptr;
-        if (!direct) PRNU_HIP(launch_sda(frames, dtype, n_frames, H, W, C, group, g0, g1, nullptr, ap.means, s));
+        const unsigned char *f8 = direct ? static_cast<const unsigned char *>(frames) + (int64_t)g0 * fstride : nullptr;
+        if (!direct)
+            PRNU_HIP(launch_sda(frames, fstride, dtype, n_frames, H, W, C, group, g0, g1, nullptr, ap.means, nullptr,
+                                status, s));
         PRNU_TRY(run_pyramid(f, p, ap.means, nb * C, H, W, ap.py, s, nullptr, f8, C));
         PRNU_HIP(launch_dwt_inv_mle(p->taps, f, ap.py.lvl[1], Hp / 2, Wp / 2, p->levels == 1, nb, C,
                                     ap.means, H, W, pad_before(H), pad_before(W), acc_mode, A, B, s, f8));
+        if (state) {
+            const int64_t fr = std::min<int64_t>(n_frames, (int64_t)g1 * group) - (int64_t)g0 * group;
+            PRNU_HIP(launch_acc_state_add(state, fr, nb, s));
+        }
     }
     return PRNU_OK;
 }
@@ -678,7 +695,8 @@ int prnu_query_residual(const void *frames, int dtype, int n, int H, int W, int 
     for (int f0 = 0; f0 < n; f0 += qp.nb) {
         const int f1 = f0 + qp.nb < n ? f0 + qp.nb : n;
         const int nb = f1 - f0;
-        PRNU_HIP(launch_sda(frames, dtype, n, H, W, C, 1, f0, f1, nullptr, qp.means, s));
+        PRNU_HIP(launch_sda(frames, (int64_t)H * W * C * (int64_t)elem_bytes(dtype), dtype, n, H, W, C, 1, f0, f1,
+                            nullptr, qp.means, nullptr, nullptr, s));
         PRNU_TRY(run_pyramid(f, p, qp.means, nb * C, H, W, qp.py, s));
         PRNU_HIP(launch_dwt_inv(p->taps, f, qp.py.lvl[1], Hp / 2, Wp / 2, p->levels == 1, nb * C, INV_RESID,
                                 qp.resid, H, W, pad_before(H), pad_before(W), s));
@@ -717,6 +735,18 @@ int prnu_resample_bilinear(const float *src, int n, int H, int W, double scale, 
     if (!std::isfinite(scale) || scale <= 0.0) return fail(PRNU_E_INVAL, "%s: scale must be finite and > 0", fn);
     if (oy < 0 || ox < 0 || oy > kMaxDim || ox > kMaxDim) return fail(PRNU_E_INVAL, "%s: bad crop offset", fn);
     PRNU_HIP(launch_resample_bilinear(src, n, H, W, scale, oy, ox, oh, ow, out, (hipStream_t)stream));
+    return PRNU_OK;
+}
+
+int prnu_warp_affine(const float *src, int n_src, int H, int W, const double *affine, int n, int oh, int ow,
+                     float *out, void *stream) {
+    const char *fn = "prnu_warp_affine";
+    set_error("");
+    if (!src || !affine || !out) return fail(PRNU_E_INVAL, "%s: null pointer", fn);
+    if (n_src < 1 || n < 1 || n > 65535) return fail(PRNU_E_INVAL, "%s: need n_src >= 1 and n in [1, 65535]", fn);
+    if (H < 1 || W < 1 || H > kMaxDim || W > kMaxDim) return fail(PRNU_E_INVAL, "%s: bad H x W", fn);
+    if (oh < 1 || ow < 1 || oh > kMaxDim || ow > kMaxDim) return fail(PRNU_E_INVAL, "%s: bad output size", fn);
+    PRNU_HIP(launch_warp_affine(src, n_src, H, W, affine, n, oh, ow, out, (hipStream_t)stream));
     return PRNU_OK;
 }
 

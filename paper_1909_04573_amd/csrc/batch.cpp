@@ -237,7 +237,7 @@ int build(const prnu_camera *cams, int n, int dtype, const prnu_denoise_params *
             for (int k = 0; k < nj; ++k) {
                 const prnu_camera &c = cams[r[k].cam];
                 const int64_t npx = (int64_t)c.H * c.W;
-                const bool quad = sda_quad_ok(c.frames, dtype, npx, c.C, nullptr, means[k]);
+                const bool quad = sda_quad_ok(c.frames, npx * c.C * elem_bytes(dtype), dtype, npx, c.C, nullptr, means[k]);
                 d[k] = SdaDesc{c.frames, npx, dtype, c.n_frames, c.C, c.group, r[k].g0, r[k].ng, quad ? 1 : 0,
                                sda_blocks_per_group(quad, npx), means[k], blk};
                 blk += (int64_t)d[k].bpg * r[k].ng;

@@ -90,6 +90,22 @@ inline int check_flags(int flags, const char *fn) {
 
 inline size_t elem_bytes(int dtype) { return dtype == PRNU_U8 ? 1 : dtype == PRNU_BF16 ? 2 : 4; }
 
+// Bytes from one frame to the next: 0 asks for dense frames; otherwise at
+// least a dense frame, a multiple of the sample size, and small enough that
+// the last frame's offset fits in int64.  Call after check_frames.
+inline int check_frame_stride(int64_t stride, int dtype, int n, int H, int W, int C, const char *fn, int64_t *out) {
+    const int64_t esz = (int64_t)elem_bytes(dtype), dense = (int64_t)H * W * C * esz;
+    if (stride == 0) {
+        *out = dense;
+        return PRNU_OK;
+    }
+    if (stride < dense || stride % esz != 0 || stride > INT64_MAX / n)
+        return fail(PRNU_E_INVAL, "%s: frame_stride_bytes %lld must be 0 or a multiple of %lld that is >= %lld", fn,
+                    (long long)stride, (long long)esz, (long long)dense);
+    *out = stride;
+    return PRNU_OK;
+}
+
 // Residuals of float planes in batches of at most max_nb planes (0: the
 // default batch) through the workspace ws; optional sensitivity checkpoint.
 int denoise_run(const char *fn, const float *img, int n_img, int H, int W, const prnu_denoise_params *p,

@@ -125,8 +125,10 @@ void fwd_layout(int tc, int hk, int wk, int64_t planes, int *strips, int *seg_ro
 
 // ---- kernel launchers (all enqueue on `s`, return the launch status) -------
 // SDA: groups [g0, g1) of `group` frames; outputs indexed from g0.
-hipError_t launch_sda(const void *frames, int dtype, int n_frames, int H, int W, int C, int group,
-                      int g0, int g1, uint32_t *sums, float *means, hipStream_t s);
+hipError_t launch_sda(const void *frames, int64_t fstride, int dtype, int n_frames, int H, int W, int C, int group,
+                      int g0, int g1, uint32_t *sums, float *means, int *counts, uint32_t *status, hipStream_t s);
+// state->frames += frames, state->sda_frames += sda_frames (one thread, in stream order).
+hipError_t launch_acc_state_add(prnu_acc_state *st, int64_t frames, int64_t sda_frames, hipStream_t s);
 
 // Forward level with fused Wiener shrinkage.  src plane p at src + p*src_stride,
 // stored src_rows x src_cols; the level input is the n_r x n_c plane obtained
@@ -186,7 +188,8 @@ int mle_multi_occupancy(int taps, int tt, int acc_mode);
 // Batched SDA means (no sums): a 1-D grid of `total` blocks over the
 // descriptors; quad = sda_quad_ok(...) for the descriptor's buffers, bpg =
 // sda_blocks_per_group(quad, npx), means [ng][C][H][W] of groups g0 .. g0+ng-1.
-bool sda_quad_ok(const void *frames, int dtype, int64_t npx, int C, const void *sums, const void *means);
+bool sda_quad_ok(const void *frames, int64_t fstride, int dtype, int64_t npx, int C, const void *sums,
+                 const void *means);
 int sda_blocks_per_group(bool quad, int64_t npx);
 hipError_t launch_sda_multi(const SdaDesc *d, int nd, int64_t total, hipStream_t s);
 
@@ -249,6 +252,10 @@ hipError_t launch_plane_variance(const float *x, int n, int64_t N, double *var, 
 // scale = output / input size, crop offset (oy, ox) in output pixels).
 hipError_t launch_resample_bilinear(const float *src, int n, int H, int W, double scale, int oy, int ox, int oh,
                                     int ow, float *out, hipStream_t s);
+// Affine bilinear warp: plane k of out [n][oh][ow] samples src [k % n_src][H][W]
+// at column m0 x + m1 y + m2, row m3 x + m4 y + m5 (m = affine + 6k, device).
+hipError_t launch_warp_affine(const float *src, int n_src, int H, int W, const double *affine, int n, int oh, int ow,
+                              float *out, hipStream_t s);
 // Disjoint b x b blocks of n planes [n][H][W], block-major [k][n][b][b].
 hipError_t launch_extract_blocks(const float *src, int n, int H, int W, int b, float *out, hipStream_t s);
 hipError_t launch_spectral_wiener(const float2 *F, int n, int h, int w, const double *var,

@@ -23,7 +23,12 @@ Stabilised video (Sec. V-E), orchestration of library calls:
 * segment_shifts(W, I, K_ref): per SDA frame, the translation of a reference
   fingerprint with the largest fixed-peak PCE;
 * aligned_fingerprint(means, shifts, A, B): MLE over the SDA frames
-  translated back by their shifts.
+  translated back by their shifts;
+* segment_poses(W, I, K_ref, angles): the same search over rotations about
+  the frame centre (one warped reference per angle, the translation from the
+  argmax of one correlation plane per angle);
+* aligned_fingerprint_affine(means, poses, A, B): MLE over the SDA frames
+  rotated and translated back by their poses.
 """
 from __future__ import annotations
 
@@ -237,4 +242,86 @@ def aligned_fingerprint(means, shifts, A, B, M: int, params=None, ws=None):
         dy, dx = int(shifts[j, 0]), int(shifts[j, 1])
         al[j, :, :, 0] = prnu.resample_bilinear(means[j], 1.0, h, w, M - dy, M - dx)
     prnu.fingerprint_accumulate(al, 1, A, B, params, ws=ws)
+    return A, B
+
+
+# ---------------------------------------------------------------- rotations (stabilised video, Sec. II-B / V-E)
+def reference_pose_matrix(theta: float, H: int, W: int, margin: int, origin: int = 0):
+    """Affine matrix (prnu_warp_affine layout) of the reference cut-out for
+    rotation theta: window pixel q of an H x W frame (frame pixel q + margin)
+    samples the reference fingerprint at c + R(theta) (q + margin - c) - origin,
+    c the frame centre; R rotates (column, row) coordinates."""
+    ca, sa = np.cos(theta), np.sin(theta)
+    cx, cy = (W - 1) / 2.0, (H - 1) / 2.0
+    return [ca, -sa, ca * (margin - cx) - sa * (margin - cy) + cx - origin,
+            sa, ca, sa * (margin - cx) + ca * (margin - cy) + cy - origin]
+
+
+def alignment_matrix(theta: float, dy: float, dx: float, H: int, W: int, M: int):
+    """Affine matrix that brings an H x W frame of pose (theta, dy, dx) (its
+    pattern at frame pixel p is the reference at c + R(theta) (p - c) + d) to
+    the reference pose: window pixel q samples the frame at
+    c + R(-theta) (q + M - d - c).  theta = 0 is the translation of
+    aligned_fingerprint."""
+    ca, sa = np.cos(theta), np.sin(theta)
+    cx, cy = (W - 1) / 2.0, (H - 1) / 2.0
+    ax, ay = M - dx - cx, M - dy - cy
+    return [ca, sa, cx + ca * ax + sa * ay, -sa, ca, cy - sa * ax + ca * ay]
+
+
+def segment_poses(W, I, K_ref, angles, max_shift: int = 8, margin: int = 60, origin: int = 0,
+                  pce_min: float | None = None):
+    """Per-segment pose search for stabilised video whose stabiliser also
+    rotates frames (Sec. II-B): for every candidate angle the reference
+    fingerprint is warped onto the frames' window (reference_pose_matrix,
+    one prnu_warp_affine call for all angles), and each SDA frame j runs one
+    pce_match call with the argmax peak against all of them: the plane of
+    angle a is C_a(s) = sum_t ref_a(t + s) I[j](t) W[j](t), whose peak gives
+    the translation for that angle (as in segment_shifts_plane).  The frame
+    takes the angle with the largest PCE; it keeps the zero pose where that
+    peak lies outside |dy|, |dx| <= max_shift or (with pce_min) its PCE stays
+    below pce_min.  The margin must cover the rotated window inside the
+    reference, and the window (H - 2 margin) x (W - 2 margin) must be a size
+    the PCE's DFT takes (prime factors up to 5).  Returns (poses float64 [g][3] = (theta, dy, dx),
+    pce float64 [g][len(angles)] at each angle's peak)."""
+    import torch
+
+    from . import prnu
+
+    g, H, Wd = (int(v) for v in W.shape)
+    h, w = H - 2 * margin, Wd - 2 * margin
+    mats = np.array([reference_pose_matrix(a, H, Wd, margin, origin) for a in angles])
+    refs = prnu.warp_affine(K_ref, mats, h, w)
+    Wc = W[:, margin:H - margin, margin:Wd - margin].contiguous()
+    Ic = I[:, margin:H - margin, margin:Wd - margin].contiguous()
+    na = len(angles)
+    poses = np.zeros((g, 3))
+    pce = np.zeros((g, na))
+    for j in range(g):
+        mod = Ic[j:j + 1].expand(na, h, w).contiguous()
+        P, _, pk = prnu.pce_match(refs, Wc[j:j + 1], mod, peak_mode=prnu.PEAK_ARGMAX, want_ncc=False)
+        P, pk = P.cpu().numpy()[:, 0], pk.cpu().numpy()[:, 0]
+        pce[j] = P
+        a = int(np.argmax(P))
+        dy, dx = signed_lag(int(pk[a, 0]), h), signed_lag(int(pk[a, 1]), w)
+        if max(abs(dy), abs(dx)) <= max_shift and (pce_min is None or P[a] >= pce_min):
+            poses[j] = (angles[a], dy, dx)
+    return poses, pce
+
+
+def aligned_fingerprint_affine(means, poses, A, B, M: int, params=None, ws=None):
+    """MLE over SDA frames brought to the reference pose: frame j (means
+    [g][H][W] float32) is warped by alignment_matrix(pose j) onto the window
+    of h x w frame pixels from (M, M) (prnu_warp_affine, one call for all
+    frames) and the windows are accumulated as frames of depth 1 into A, B of
+    [1][h][w]."""
+    from . import prnu
+
+    g, H, Wd = (int(v) for v in means.shape)
+    h, w = (int(v) for v in A.shape[-2:])
+    if h > H - 2 * M or w > Wd - 2 * M:
+        raise ValueError("the accumulators exceed the window inside the margin M")
+    mats = np.array([alignment_matrix(float(t), float(dy), float(dx), H, Wd, M) for t, dy, dx in poses])
+    al = prnu.warp_affine(means.contiguous(), mats, h, w)
+    prnu.fingerprint_accumulate(al.unsqueeze(-1).contiguous(), 1, A, B, params, ws=ws)
     return A, B

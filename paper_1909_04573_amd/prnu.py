@@ -19,6 +19,7 @@ PRNU_OK, PRNU_E_INVAL, PRNU_E_UNSUPPORTED, PRNU_E_WORKSPACE, PRNU_E_HIP = 0, -1,
 U8, BF16, F32 = 0, 1, 2
 ACC_F64, ACC_KAHAN_F32, ACC_F32 = 0, 1, 2
 ZM, LUMA, WIENER = 1, 2, 4
+STATUS_NONFINITE = 1
 PEAK_FIXED_00, PEAK_ARGMAX = 0, 1
 
 _DT = {torch.uint8: U8, torch.bfloat16: BF16, torch.float32: F32}
@@ -32,6 +33,7 @@ EXPORTS = (
     "prnu_fingerprint_finalize_workspace_size", "prnu_fingerprint_finalize",
     "prnu_query_residual_workspace_size", "prnu_query_residual",
     "prnu_pce_match_workspace_size", "prnu_pce_match", "prnu_extract_blocks", "prnu_resample_bilinear",
+    "prnu_warp_affine",
     "prnu_timing_enable", "prnu_timing_report",
     "prnu_postprocess_workspace_size", "prnu_postprocess",
     "prnu_denoise_ckpt_floats", "prnu_denoise_residual_ckpt",
@@ -73,7 +75,7 @@ class BatchInfo(ctypes.Structure):
 
 
 _lib = None
-_P, _I, _F, _S = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_size_t
+_P, _I, _F, _S, _L = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_size_t, ctypes.c_int64
 _DP = ctypes.POINTER(DenoiseParams)
 
 
@@ -89,12 +91,12 @@ def lib() -> ctypes.CDLL:
     L.prnu_version.restype = ctypes.c_char_p
     L.prnu_default_denoise_params.argtypes = [_DP]
     L.prnu_filter_coefficients.argtypes = [_I, ctypes.POINTER(ctypes.c_double)]
-    L.prnu_sda_average.argtypes = [_P, _I, _I, _I, _I, _I, _I, _P, _P, _P]
+    L.prnu_sda_average.argtypes = [_P, _I, _I, _I, _I, _I, _L, _I, _P, _P, _P, _P, _P]
     L.prnu_denoise_residual_workspace_size.argtypes = [_I, _I, _I, _DP, ctypes.POINTER(_S)]
     L.prnu_denoise_residual.argtypes = [_P, _I, _I, _I, _DP, _P, _P, _S, _P]
     L.prnu_denoise_residual_noalloc.argtypes = [_P, _I, _I, _I, _DP, _P, _P]
     L.prnu_fingerprint_accumulate_workspace_size.argtypes = [_I, _I, _I, _I, _I, _DP, ctypes.POINTER(_S)]
-    L.prnu_fingerprint_accumulate.argtypes = [_P, _I, _I, _I, _I, _I, _I, _DP, _I, _P, _P, _P, _S, _P]
+    L.prnu_fingerprint_accumulate.argtypes = [_P, _I, _I, _I, _I, _I, _L, _I, _DP, _I, _P, _P, _P, _P, _S, _P]
     L.prnu_fingerprint_finalize_workspace_size.argtypes = [_I, _I, _I, _I, ctypes.POINTER(_S)]
     L.prnu_fingerprint_finalize.argtypes = [_P, _P, _I, _I, _I, _I, _I, _F, _P, _P, _S, _P]
     L.prnu_query_residual_workspace_size.argtypes = [_I, _I, _I, _I, _DP, _I, ctypes.POINTER(_S)]
@@ -104,6 +106,7 @@ def lib() -> ctypes.CDLL:
                                  _S, _P]
     L.prnu_extract_blocks.argtypes = [_P, _I, _I, _I, _I, _P, _P]
     L.prnu_resample_bilinear.argtypes = [_P, _I, _I, _I, ctypes.c_double, _I, _I, _I, _I, _P, _P]
+    L.prnu_warp_affine.argtypes = [_P, _I, _I, _I, _P, _I, _I, _I, _P, _P]
     L.prnu_postprocess_workspace_size.argtypes = [_I, _I, _I, _I, _I, ctypes.POINTER(_S)]
     L.prnu_postprocess.argtypes = [_P, _I, _I, _I, _I, _I, _F, _P, _P, _S, _P]
     L.prnu_denoise_ckpt_floats.argtypes = [_I, _I, _I, ctypes.POINTER(_S)]
@@ -158,8 +161,13 @@ def _cuda(t: torch.Tensor, name: str) -> torch.Tensor:
     return t
 
 
-def _frames(frames: torch.Tensor):
-    _cuda(frames, "frames")
+def _frames(frames: torch.Tensor, strided: bool = False):
+    """(frames [n][H][W][C], dtype code, n, H, W, C[, frame stride in bytes]).
+    With strided=True the frames may be a view whose frames are dense but
+    spaced further apart (e.g. big[::k] or the first frames of a padded
+    buffer); the stride is 0 when the frames are dense."""
+    if not frames.is_cuda:
+        raise ValueError("frames must be a device tensor")
     if frames.dtype not in _DT:
         raise ValueError("frames must be uint8, bfloat16 or float32")
     if frames.dim() == 3:
@@ -167,7 +175,17 @@ def _frames(frames: torch.Tensor):
     if frames.dim() != 4:
         raise ValueError("frames must be [n][H][W] or [n][H][W][C]")
     n, H, W, C = frames.shape
-    return frames, _DT[frames.dtype], n, H, W, C
+    if not strided:
+        _cuda(frames, "frames")
+        return frames, _DT[frames.dtype], n, H, W, C
+    if not frames[0].is_contiguous():
+        raise ValueError("each frame must be contiguous")
+    dense = H * W * C
+    s0 = frames.stride(0) if n > 1 else dense
+    if s0 < dense:
+        raise ValueError("frames overlap")
+    stride = 0 if s0 == dense else s0 * frames.element_size()
+    return frames, _DT[frames.dtype], n, H, W, C, stride
 
 
 def workspace(nbytes: int, device) -> torch.Tensor:
@@ -187,18 +205,27 @@ def filter_coefficients(taps: int):
     return list(buf)
 
 
-def sda_average(frames: torch.Tensor, group: int, want_sums: bool = True, want_means: bool = True):
-    """SDA frames: returns (sums int64 [g][C][H][W] or None, means f32 [g][C][H][W] or None)."""
-    frames, dt, n, H, W, C = _frames(frames)
+def sda_average(frames: torch.Tensor, group: int, want_sums: bool = True, want_means: bool = True,
+                want_counts: bool = False, status: torch.Tensor | None = None):
+    """SDA frames: returns (sums int64 [g][C][H][W] or None, means f32
+    [g][C][H][W] or None), plus counts int32 [g] with want_counts.  Frames
+    may be spaced apart (a view with dense frames).  ``status``: optional
+    int32 device word that PRNU_STATUS_NONFINITE is ORed into."""
+    frames, dt, n, H, W, C, stride = _frames(frames, strided=True)
     g = (n + group - 1) // group
     dev = frames.device
     sums = torch.empty((g, C, H, W), dtype=torch.int32, device=dev) if want_sums and dt == U8 else None
     means = torch.empty((g, C, H, W), dtype=torch.float32, device=dev) if want_means else None
-    _check(lib().prnu_sda_average(_ptr(frames), dt, n, H, W, C, int(group), _ptr(sums), _ptr(means),
-                                  _stream(dev)))
+    counts = torch.empty(g, dtype=torch.int32, device=dev) if want_counts else None
+    if status is not None:
+        _cuda(status, "status")
+        if status.dtype != torch.int32 or status.numel() != 1:
+            raise ValueError("status must be one int32 device word")
+    _check(lib().prnu_sda_average(_ptr(frames), dt, n, H, W, C, stride, int(group), _ptr(sums), _ptr(means),
+                                  _ptr(counts), _ptr(status), _stream(dev)))
     if sums is not None:
         sums = sums.to(torch.int64) & 0xFFFFFFFF
-    return sums, means
+    return (sums, means, counts) if want_counts else (sums, means)
 
 
 def denoise_residual(img: torch.Tensor, params: DenoiseParams | None = None) -> torch.Tensor:
@@ -243,21 +270,34 @@ def new_accumulators(C: int, H: int, W: int, acc_mode: int = ACC_F64, device="cu
     return torch.zeros(shape, dtype=dt, device=device), torch.zeros(shape, dtype=dt, device=device)
 
 
+def new_acc_state(device) -> torch.Tensor:
+    """Zeroed prnu_acc_state as int64 [3]: frames, SDA frames, status bits
+    (the low 32 bits of the third word)."""
+    return torch.zeros(3, dtype=torch.int64, device=device)
+
+
 def fingerprint_accumulate(frames: torch.Tensor, group: int, A: torch.Tensor, B: torch.Tensor,
                            params: DenoiseParams | None = None, acc_mode: int = ACC_F64,
-                           ws: torch.Tensor | None = None):
-    """A += sum W*I, B += sum I^2 over the SDA frames of ``frames`` (in place)."""
-    frames, dt, n, H, W, C = _frames(frames)
+                           ws: torch.Tensor | None = None, state: torch.Tensor | None = None):
+    """A += sum W*I, B += sum I^2 over the SDA frames of ``frames`` (in place).
+    Frames may be spaced apart (a view with dense frames).  ``state`` (from
+    new_acc_state) counts the frames and SDA frames folded in and collects
+    the non-finite-input flag."""
+    frames, dt, n, H, W, C, stride = _frames(frames, strided=True)
     _cuda(A, "A")
     _cuda(B, "B")
+    if state is not None:
+        _cuda(state, "state")
+        if state.dtype != torch.int64 or state.numel() != 3:
+            raise ValueError("state must be int64 [3] (new_acc_state)")
     p = params or denoise_params()
     nbytes = _S()
     _check(lib().prnu_fingerprint_accumulate_workspace_size(n, H, W, C, int(group), ctypes.byref(p),
                                                             ctypes.byref(nbytes)))
     if ws is None or ws.numel() < nbytes.value:
         ws = workspace(nbytes.value, frames.device)
-    _check(lib().prnu_fingerprint_accumulate(_ptr(frames), dt, n, H, W, C, int(group), ctypes.byref(p),
-                                             int(acc_mode), _ptr(A), _ptr(B), _ptr(ws), ws.numel(),
+    _check(lib().prnu_fingerprint_accumulate(_ptr(frames), dt, n, H, W, C, stride, int(group), ctypes.byref(p),
+                                             int(acc_mode), _ptr(A), _ptr(B), _ptr(state), _ptr(ws), ws.numel(),
                                              _stream(frames.device)))
     return A, B
 
@@ -361,6 +401,24 @@ def extract_blocks(x: torch.Tensor, b: int) -> torch.Tensor:
     nb = (H // b) * (W // b) if b > 0 else 0
     out = torch.empty((max(nb, 1), n, max(b, 1), max(b, 1)), dtype=torch.float32, device=x.device)
     _check(lib().prnu_extract_blocks(_ptr(x), n, H, W, int(b), _ptr(out), _stream(x.device)))
+    return out
+
+
+def warp_affine(x: torch.Tensor, matrices, out_h: int, out_w: int) -> torch.Tensor:
+    """Planes [n_src][H][W] (or [H][W]) warped by n affine matrices (rows of 6:
+    column = m0 x + m1 y + m2, row = m3 x + m4 y + m5 of output pixel (y, x);
+    a float64 tensor or array [n][6], or one matrix) into [n][out_h][out_w];
+    output plane k samples source plane k % n_src."""
+    _cuda(x, "x")
+    if x.dtype != torch.float32:
+        raise ValueError("x must be float32")
+    x = (x.unsqueeze(0) if x.dim() == 2 else x).contiguous()
+    m = torch.as_tensor(matrices, dtype=torch.float64).reshape(-1, 6).to(x.device).contiguous()
+    n_src, H, W = (int(v) for v in x.shape)
+    n = int(m.shape[0])
+    out = torch.empty((n, int(out_h), int(out_w)), dtype=torch.float32, device=x.device)
+    _check(lib().prnu_warp_affine(_ptr(x), n_src, H, W, _ptr(m), n, int(out_h), int(out_w), _ptr(out),
+                                  _stream(x.device)))
     return out
 
 

@@ -364,6 +364,64 @@ def mixed_media_camera_torch(cam: int, n_video: int, n_still: int, Hs: int = 225
     return video, stills, K
 
 
+def stabilized_video_affine_torch(cam: int, vid: int, n: int, H: int = 1080, W: int = 1920,
+                                  k_std: float = 0.0004, p_still: float = 0.3, max_shift: int = 8,
+                                  angles_deg=(-1.0, -0.5, 0.5, 1.0), segment: int = 30, noise_std: float = 2.0,
+                                  device="cuda", cfg: int = CFG_EVAL, K=None):
+    """A stabilised gray video whose stabiliser holds one pose per run of
+    `segment` frames: with probability p_still none, otherwise a rotation
+    about the frame centre by an angle drawn from `angles_deg` and an integer
+    translation uniform in [-max_shift, max_shift]^2 (Sec. II-B: stabilisers
+    shift, rotate and zoom frames).  A frame with pose (theta, sy, sx) sees
+    the sensor pattern at frame pixel p as K(c + R(theta) (p - c) - s), c the
+    frame centre, sampled bilinearly (torch grid_sample, edges clamped); the
+    scene is the video generator's random-walk crop of a per-video texture.
+    I = I0 (1 + pattern) + N(0, noise_std^2), rounded.  K defaults to the
+    camera's PRNU of the stabilised workload.  Returns (uint8 [n][H][W][1]
+    on device, K float64 [H][W], poses float64 [n][3] = (theta in radians,
+    sy, sx))."""
+    import torch
+    import torch.nn.functional as F
+
+    if K is None:
+        K = camera_prnu((H, W), k_std, cfg, cam, 0x57AB)
+    Kt = torch.from_numpy(np.asarray(K)).to(device=device, dtype=torch.float32)[None, None]
+    g = rng(cfg, cam, 0x57AB, vid)
+    tex = torch.from_numpy(stretch(gaussian_blur(g.uniform(0.0, 1.0, size=(2 * H, 2 * W)), 2.0))).to(
+        device=device, dtype=torch.float32)
+    offs = crop_walk(n, H, W, g)
+    bright = g.uniform(0.7, 1.3, size=n)
+    gs = rng(cfg, cam, 0x57AB, vid, 0xAFF)
+    nseg = (n + segment - 1) // segment
+    still = gs.uniform(size=nseg) < p_still
+    th = np.deg2rad(np.asarray(angles_deg, dtype=np.float64))[gs.integers(0, len(angles_deg), size=nseg)]
+    sh = gs.integers(-max_shift, max_shift + 1, size=(nseg, 2)).astype(np.float64)
+    th[still] = 0.0
+    sh[still] = 0.0
+    poses = np.repeat(np.concatenate([th[:, None], sh], axis=1), segment, axis=0)[:n]
+    gen = torch.Generator(device=device)
+    gen.manual_seed((MASTER_SEED * 19 + cfg * 7919 + cam * 104729 + vid * 131) % (2**63))
+    yy, xx = torch.meshgrid(torch.arange(H, dtype=torch.float64, device=device),
+                            torch.arange(W, dtype=torch.float64, device=device), indexing="ij")
+    cy, cx = (H - 1) / 2.0, (W - 1) / 2.0
+    out = torch.empty((n, H, W, 1), dtype=torch.uint8, device=device)
+    pat = None
+    for i in range(n):
+        if i % segment == 0:
+            t, sy, sx = (float(v) for v in poses[i])
+            u = cx + np.cos(t) * (xx - cx) - np.sin(t) * (yy - cy) - sx
+            v = cy + np.sin(t) * (xx - cx) + np.cos(t) * (yy - cy) - sy
+            u = u.clamp(0, W - 1) / (W - 1) * 2 - 1  # grid_sample's [-1, 1] with corner alignment
+            v = v.clamp(0, H - 1) / (H - 1) * 2 - 1
+            grid = torch.stack([u, v], dim=-1)[None].to(torch.float32)
+            pat = F.grid_sample(Kt, grid, mode="bilinear", padding_mode="border", align_corners=True)[0, 0]
+        y, x = int(offs[i, 0]), int(offs[i, 1])
+        I = tex[y:y + H, x:x + W] * float(bright[i]) * (1.0 + pat)
+        I = I + noise_std * torch.randn((H, W), generator=gen, device=device)
+        out[i, :, :, 0] = torch.round(I).clamp_(0, 255).to(torch.uint8)
+    return out, K, poses
+
+
 def stabilized_video_torch(cam: int, vid: int, n: int, H: int = 1080, W: int = 1920, k_std: float = 0.0004,
                            p_still: float = 0.3, max_shift: int = 8, noise_std: float = 2.0, device="cuda",
                            cfg: int = CFG_EVAL, segment: int = 0):

@@ -18,6 +18,28 @@ def repo_root():
     return ROOT
 
 
+@pytest.fixture(scope="session")
+def host_check():
+    """Run the sanitized host-check program (built once per session): the
+    library's host sources under AddressSanitizer and UndefinedBehaviorSanitizer.
+    Returns run(mode) -> (exit status, combined output)."""
+    import shutil
+    import subprocess
+
+    if shutil.which("hipcc") is None and not os.path.exists("/opt/rocm/bin/hipcc"):
+        pytest.skip("hipcc is needed to build the sanitized host check")
+    from paper_1909_04573_amd import build
+
+    exe = build.build_host_check()
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1", UBSAN_OPTIONS="print_stacktrace=1")
+
+    def run(mode):
+        r = subprocess.run([exe, mode], capture_output=True, text=True, timeout=300, env=env)
+        return r.returncode, r.stdout + r.stderr
+
+    return run
+
+
 def pytest_collection_modifyitems(config, items):
     try:
         import torch

@@ -83,11 +83,19 @@ def test_validation_rejects_before_enqueue(lib):
     P = ctypes.byref(p)
     fake = ctypes.c_void_p(0x100000)  # never dereferenced: every call below fails validation
     out = ctypes.c_void_p(0x200000)
-    assert lib.prnu_sda_average(None, 0, 8, 16, 16, 1, 1, fake, fake, None) == prnu.PRNU_E_INVAL
-    assert lib.prnu_sda_average(fake, 0, 8, 16, 16, 2, 1, None, fake, None) == prnu.PRNU_E_INVAL
-    assert lib.prnu_sda_average(fake, 0, 8, 16, 16, 1, 0, None, fake, None) == prnu.PRNU_E_INVAL
-    assert lib.prnu_sda_average(fake, 1, 8, 16, 16, 1, 1, fake, None, None) == prnu.PRNU_E_INVAL
-    assert lib.prnu_sda_average(fake, 9, 8, 16, 16, 1, 1, None, fake, None) == prnu.PRNU_E_INVAL
+    sda = lambda fr, dt, n, C, stride, d, sums, means: lib.prnu_sda_average(fr, dt, n, 16, 16, C, stride, d, sums,
+                                                                             means, None, None, None)
+    assert sda(None, 0, 8, 1, 0, 1, fake, fake) == prnu.PRNU_E_INVAL
+    assert sda(fake, 0, 8, 2, 0, 1, None, fake) == prnu.PRNU_E_INVAL
+    assert sda(fake, 0, 8, 1, 0, 0, None, fake) == prnu.PRNU_E_INVAL
+    assert sda(fake, 1, 8, 1, 0, 1, fake, None) == prnu.PRNU_E_INVAL
+    assert sda(fake, 9, 8, 1, 0, 1, None, fake) == prnu.PRNU_E_INVAL
+    # frame strides: shorter than a frame, not a multiple of the sample size, negative, overflowing
+    assert sda(fake, 0, 8, 1, 255, 1, None, fake) == prnu.PRNU_E_INVAL
+    assert sda(fake, 2, 8, 1, 16 * 16 * 4 + 2, 1, None, fake) == prnu.PRNU_E_INVAL
+    assert sda(fake, 0, 8, 1, -256, 1, None, fake) == prnu.PRNU_E_INVAL
+    assert sda(fake, 0, 8, 1, (1 << 62), 1, None, fake) == prnu.PRNU_E_INVAL
+    assert "frame_stride_bytes" in lib.prnu_last_error().decode()
     assert lib.prnu_denoise_residual(fake, 1, 15, 64, P, fake, fake, 1 << 30, None) == prnu.PRNU_E_INVAL
     assert lib.prnu_denoise_residual(fake, 1, 64, 64, P, out, fake, 16, None) == prnu.PRNU_E_WORKSPACE
     assert lib.prnu_denoise_residual(fake, 0, 64, 64, P, fake, fake, 1 << 30, None) == prnu.PRNU_E_INVAL
@@ -103,10 +111,12 @@ def test_validation_rejects_before_enqueue(lib):
     misaligned = ctypes.c_void_p(0x100010)
     assert lib.prnu_denoise_residual(fake, 1, 64, 64, P, out, misaligned, 1 << 30, None) == \
         prnu.PRNU_E_WORKSPACE
-    assert lib.prnu_fingerprint_accumulate(fake, 0, 8, 64, 64, 1, 1, P, 7, fake, fake, fake, 1 << 30,
+    assert lib.prnu_fingerprint_accumulate(fake, 0, 8, 64, 64, 1, 0, 1, P, 7, fake, fake, None, fake, 1 << 30,
                                            None) == prnu.PRNU_E_INVAL
-    assert lib.prnu_fingerprint_accumulate(fake, 0, 8, 64, 64, 1, 1, P, 0, None, fake, fake, 1 << 30,
+    assert lib.prnu_fingerprint_accumulate(fake, 0, 8, 64, 64, 1, 0, 1, P, 0, None, fake, None, fake, 1 << 30,
                                            None) == prnu.PRNU_E_INVAL
+    assert lib.prnu_fingerprint_accumulate(fake, 0, 8, 64, 64, 1, 64 * 64 - 1, 1, P, 0, fake, fake, None, fake,
+                                           1 << 30, None) == prnu.PRNU_E_INVAL
     assert lib.prnu_fingerprint_finalize(fake, fake, 0, 1, 17, 64, 4, -1.0, fake, fake, 1 << 30,
                                          None) == prnu.PRNU_E_UNSUPPORTED  # 17 is not 5-smooth
     assert lib.prnu_fingerprint_finalize(fake, fake, 0, 1, 64, 64, 8, -1.0, fake, fake, 1 << 30,
@@ -167,3 +177,38 @@ def test_noalloc_validation(lib):
     assert f(fake, 1, 64, 64, ctypes.byref(bad), out, None) == prnu.PRNU_E_UNSUPPORTED
     assert f(fake, 1, 4096, 4096, P, out, None) == prnu.PRNU_E_INVAL
     assert "static scratch" in lib.prnu_last_error().decode()
+
+
+def test_warp_affine_validation(lib):
+    """The affine warp rejects null pointers and bad sizes on the host."""
+    fake = ctypes.c_void_p(0x100000)
+    out = ctypes.c_void_p(0x200000)
+    m = ctypes.c_void_p(0x300000)
+    f = lib.prnu_warp_affine
+    assert f(None, 1, 16, 16, m, 1, 8, 8, out, None) == prnu.PRNU_E_INVAL
+    assert f(fake, 1, 16, 16, None, 1, 8, 8, out, None) == prnu.PRNU_E_INVAL
+    assert f(fake, 1, 16, 16, m, 1, 8, 8, None, None) == prnu.PRNU_E_INVAL
+    assert f(fake, 0, 16, 16, m, 1, 8, 8, out, None) == prnu.PRNU_E_INVAL
+    assert f(fake, 1, 16, 16, m, 0, 8, 8, out, None) == prnu.PRNU_E_INVAL
+    assert f(fake, 1, 16, 16, m, 70000, 8, 8, out, None) == prnu.PRNU_E_INVAL
+    assert f(fake, 1, 0, 16, m, 1, 8, 8, out, None) == prnu.PRNU_E_INVAL
+    assert f(fake, 1, 16, 16, m, 1, 8, 40000, out, None) == prnu.PRNU_E_INVAL
+
+
+def test_host_sources_under_sanitizers(host_check):
+    """The validation, workspace carving, filter design and error text of the
+    host sources run clean under ASan + UBSan (the same rejections as above,
+    from C), and the sanitizers are live: a planted heap over-read and a
+    planted signed overflow in the check program are reported."""
+    from paper_1909_04573_amd import build
+
+    rc, out = host_check("abi")
+    assert rc == 0 and "0 failed" in out, out
+    assert "Sanitizer" not in out and "runtime error" not in out, out
+    syms = subprocess.run(["nm", os.path.join(os.path.dirname(build.HOST_CHECK), "api.cpp.o")],
+                          capture_output=True, text=True).stdout
+    assert "__asan_report_load" in syms and "__ubsan_handle" in syms
+    rc, out = host_check("plant-heap")
+    assert rc != 0 and "AddressSanitizer: heap-buffer-overflow" in out, out
+    rc, out = host_check("plant-ub")
+    assert rc != 0 and "runtime error: signed integer overflow" in out, out

@@ -156,3 +156,11 @@ def test_set_tiles_layout(lib):
         for l in range(1, 5):
             for kind in (prnu.TILE_FWD, prnu.TILE_INV, prnu.TILE_MLE):
                 prnu.set_tile(kind, 16, 1088 >> l, 1920 >> l, 0)
+
+
+def test_batch_planning_under_sanitizers(host_check):
+    """Round packing of 40 mixed cameras under shrinking budgets, the batch
+    validation and the tile table run clean under ASan + UBSan."""
+    rc, out = host_check("batch")
+    assert rc == 0 and "0 failed" in out, out
+    assert "Sanitizer" not in out and "runtime error" not in out, out

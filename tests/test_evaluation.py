@@ -256,3 +256,109 @@ def test_equivalent_images_search():
     assert ev.equivalent_images({10: 1.0}, {50: 0.99, 100: 0.999}) == {10: None}
     assert ev.equivalent_images({10: 0.5}, {100: 0.5, 50: 0.5}) == {10: 50}  # ties reach, smallest m
     assert ev.equivalent_images({}, {50: 1.0}) == {}
+
+
+# ---------------------------------------------------------------- rotations (stabilised video)
+def _oracle_warp(monkeypatch):
+    """Stand-in for prnu_warp_affine computed by the oracle on host tensors."""
+    import torch
+
+    from oracle import resample
+    from paper_1909_04573_amd import prnu
+
+    def warp_affine(x, mats, oh, ow):
+        a = x.double().numpy()
+        a = a[None] if a.ndim == 2 else a
+        m = np.asarray(mats, dtype=np.float64).reshape(-1, 6)
+        return torch.from_numpy(np.stack([resample.affine(a[k % len(a)], m[k], oh, ow) for k in range(len(m))])).float()
+
+    monkeypatch.setattr(prnu, "warp_affine", warp_affine)
+
+
+def _posed_frames(poses, H=56, W=56, seed=21):
+    """Residuals whose pattern at frame pixel p is K(c + R(theta)(p - c) + d)."""
+    import torch
+
+    from oracle import resample
+
+    rng = np.random.default_rng(seed)
+    K = rng.normal(size=(H, W))
+    I = rng.uniform(50, 200, size=(len(poses), H, W))
+    Wr = []
+    for j, (t, dy, dx) in enumerate(poses):
+        m = ev.reference_pose_matrix(t, H, W, 0, 0)
+        m[2] += dx
+        m[5] += dy
+        Wr.append(I[j] * resample.affine(K, m, H, W) + rng.normal(0, 5.0, size=(H, W)))
+    return torch.from_numpy(np.stack(Wr)).float(), torch.from_numpy(I).float(), torch.from_numpy(K).float()
+
+
+def test_pose_matrices_reduce_to_translations():
+    """At angle 0 the reference cut-out is the crop from (margin - origin) and
+    the alignment the translation of aligned_fingerprint; a pose and its
+    alignment compose to the window's offset."""
+    np.testing.assert_allclose(ev.reference_pose_matrix(0.0, 40, 50, 6, 2), [1, 0, 4, 0, 1, 4], atol=1e-12)
+    np.testing.assert_allclose(ev.alignment_matrix(0.0, 2, -3, 40, 50, 5), [1, 0, 8, 0, 1, 3], atol=1e-12)
+    t, dy, dx, H, W, M = 0.03, 2.0, -1.0, 60, 80, 7
+    R = np.array(ev.reference_pose_matrix(t, H, W, 0, 0)).reshape(2, 3)
+    R[:, 2] += (dx, dy)
+    A = np.array(ev.alignment_matrix(t, dy, dx, H, W, M)).reshape(2, 3)
+    comp = R[:, :2] @ A[:, :2], R[:, :2] @ A[:, 2] + R[:, 2]
+    np.testing.assert_allclose(comp[0], np.eye(2), atol=1e-12)
+    np.testing.assert_allclose(comp[1], [M, M], atol=1e-9)
+
+
+def test_pose_search_recovers_rotations_and_translations(monkeypatch):
+    """Frames rotated by angles of the candidate grid and translated by
+    integers: every pose comes back exactly (on 56 x 56 frames neighbouring
+    angles still correlate, so only the winner is checked); frames of
+    another camera keep the zero pose under the gate."""
+    _oracle_library(monkeypatch)
+    _oracle_warp(monkeypatch)
+    angles = [-0.08, -0.04, 0.0, 0.04, 0.08]
+    true = np.array([[0.0, 0, 0], [0.04, 2, -1], [-0.08, -2, 2], [0.08, 1, 0], [-0.04, 0, -2]])
+    Wr, I, K = _posed_frames(true)
+    est, P = ev.segment_poses(Wr, I, K, angles, max_shift=3, margin=8)
+    np.testing.assert_allclose(est, true, atol=1e-12)
+    for j in range(len(true)):
+        a = angles.index(true[j, 0])
+        assert P[j, a] > 60 and P[j, a] == P[j].max()
+    other = np.random.default_rng(77).normal(size=K.shape)
+    import torch
+    est_o, _ = ev.segment_poses(Wr, I, torch.from_numpy(other).float(), angles, max_shift=3, margin=8,
+                                pce_min=25.0)
+    assert not est_o.any()
+
+
+def test_affine_alignment_lines_rotated_patterns_up(monkeypatch):
+    """Smooth patterns posed by (theta, d) and aligned back with their poses
+    match the reference window from (M, M) (interpolated twice: correlation
+    above 0.999 on a smooth field); the accumulation call is captured."""
+    import torch
+    from scipy import ndimage
+
+    from oracle import resample
+    from paper_1909_04573_amd import prnu
+
+    _oracle_warp(monkeypatch)
+    seen = {}
+    monkeypatch.setattr(prnu, "fingerprint_accumulate", lambda fr, d, A, B, p=None, ws=None: seen.update(fr=fr, d=d))
+    H = W = 64
+    K = ndimage.gaussian_filter(np.random.default_rng(9).normal(size=(H, W)), 3.0)
+    poses = np.array([[0.0, 0, 0], [0.05, 2, -3], [-0.06, -3, 1]])
+    frames = []
+    for t, dy, dx in poses:
+        m = ev.reference_pose_matrix(t, H, W, 0, 0)
+        m[2] += dx
+        m[5] += dy
+        frames.append(resample.affine(K, m, H, W))
+    M, h, w = 8, 48, 48
+    A = torch.zeros((1, h, w), dtype=torch.float64)
+    ev.aligned_fingerprint_affine(torch.from_numpy(np.stack(frames)).float(), poses, A, A, M)
+    assert seen["d"] == 1 and tuple(seen["fr"].shape) == (3, h, w, 1)
+    ref = K[M:M + h, M:M + w]
+    np.testing.assert_allclose(seen["fr"][0, :, :, 0].numpy(), ref, atol=1e-6)
+    for j in (1, 2):
+        got = seen["fr"][j, :, :, 0].numpy().astype(np.float64)
+        c = np.corrcoef(got[4:-4, 4:-4].ravel(), ref[4:-4, 4:-4].ravel())[0, 1]
+        assert c > 0.999, c

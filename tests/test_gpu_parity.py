@@ -68,6 +68,68 @@ def test_sda_float_frames(dev, dtype):
     np.testing.assert_array_equal(down(means).view(np.uint32), ref.view(np.uint32))
 
 
+def _spaced(fr, layout, dev):
+    """The frames fr [n][H][W][C] (numpy or a device tensor) as a device view
+    whose frames are dense but spaced apart: every other frame of a buffer,
+    or one frame per slot of H*W*C + pad samples."""
+    t = fr if isinstance(fr, torch.Tensor) else up(fr, dev)
+    n, H, W, C = t.shape
+    hwc = H * W * C
+    if layout == "every_other":
+        buf = torch.zeros((2 * n, H, W, C), dtype=t.dtype, device=dev)
+        buf[::2] = t
+        return buf[::2]
+    pad = {"slot_pad64": 64, "slot_pad3": 3}[layout]
+    buf = torch.zeros((n, hwc + pad), dtype=t.dtype, device=dev)
+    buf[:, :hwc] = t.reshape(n, -1)
+    return buf.as_strided((n, H, W, C), (hwc + pad, W * C, C, 1))
+
+
+@pytest.mark.parametrize("layout", ["every_other", "slot_pad64", "slot_pad3"])
+@pytest.mark.parametrize("C", [1, 3])
+def test_sda_spaced_frames_and_counts(dev, layout, C):
+    """Frames spaced apart in memory (frame_stride_bytes) give the oracle's
+    exact sums and means; counts[g] are the group sizes n_i (Sec. III-B),
+    the last group shorter.  slot_pad3 makes the stride odd: the one-pixel
+    path instead of the dword-quad path."""
+    n, H, W, d = 11, 40, 56, 4
+    _log(f"sda spaced {layout} C={C}")
+    fr = _u8((n, H, W, C), 70 + C)
+    sums, means, counts = prnu.sda_average(_spaced(fr, layout, dev), d, want_counts=True)
+    rs, rc = sda.sda_sums(fr, d)
+    np.testing.assert_array_equal(down(sums), rs)
+    np.testing.assert_array_equal(down(means).view(np.uint32), sda.sda_means_f32(fr, d).view(np.uint32))
+    np.testing.assert_array_equal(down(counts), rc)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_sda_nonfinite_flag(dev, dtype):
+    """A NaN or infinite sample sets PRNU_STATUS_NONFINITE (its group's mean
+    is not finite, the others are unchanged); finite frames leave the word
+    clear.  Spaced float frames give the dense result."""
+    _log(f"sda non-finite {dtype}")
+    g = synth.rng(synth.CFG_TEST, 5200)
+    fr = g.uniform(0, 255, size=(9, 24, 40, 3)).astype(np.float32)
+    tdt = torch.float32 if dtype == "f32" else torch.bfloat16
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    t = up(fr, dev).to(tdt)
+    _, m0 = prnu.sda_average(t, 4, want_sums=False, status=st)
+    assert int(down(st)[0]) == 0
+    _, m1 = prnu.sda_average(_spaced(t, "slot_pad3", dev), 4, want_sums=False)
+    np.testing.assert_array_equal(down(m1).view(np.uint32), down(m0).view(np.uint32))
+    for bad in (float("nan"), float("inf"), -float("inf")):
+        st.zero_()
+        t2 = t.clone()
+        t2[5, 7, 11, 2] = bad
+        _, m2 = prnu.sda_average(t2, 4, want_sums=False, status=st)
+        assert int(down(st)[0]) == prnu.STATUS_NONFINITE
+        m2, m0h = down(m2), down(m0)
+        assert not np.isfinite(m2[1, 2, 7, 11])
+        mask = np.ones(m2.shape, bool)
+        mask[1, 2, 7, 11] = False
+        np.testing.assert_array_equal(m2[mask], m0h[mask])
+
+
 # ------------------------------------------------------------------ denoiser
 DENOISE_CASES = [
     (256, 256, 16, 4, (1, 1, 1, 1)),
@@ -165,6 +227,44 @@ def test_streaming_calls_add_up(dev):
     prnu.fingerprint_accumulate(t[8:].contiguous(), 4, A2, B2)
     np.testing.assert_allclose(down(A2), down(A1), rtol=0, atol=1e-12 * float(np.abs(down(A1)).max()))
     np.testing.assert_array_equal(down(B2), down(B1))
+
+
+@pytest.mark.parametrize("layout,d", [("every_other", 1), ("slot_pad3", 1), ("slot_pad64", 3)])
+def test_accumulate_spaced_frames(dev, layout, d):
+    """Spaced frames accumulate exactly as the same frames packed densely
+    (at d = 1 the spaced u8 frames go through the SDA kernel instead of being
+    read in place: same values, same arithmetic)."""
+    _log(f"accumulate spaced {layout} d={d}")
+    fr = _frames_for(7, 72, 104, 3, 12)
+    A0, B0 = prnu.new_accumulators(3, 72, 104, device=dev)
+    prnu.fingerprint_accumulate(up(fr, dev), d, A0, B0)
+    A1, B1 = prnu.new_accumulators(3, 72, 104, device=dev)
+    prnu.fingerprint_accumulate(_spaced(fr, layout, dev), d, A1, B1)
+    np.testing.assert_array_equal(down(A1), down(A0))
+    np.testing.assert_array_equal(down(B1), down(B0))
+
+
+def test_accumulator_state_counts_and_flag(dev):
+    """The accumulator state counts the frames and SDA frames folded in, over
+    calls and over the call's internal batches (40 SDA frames at d = 1 cross
+    a batch), and collects the non-finite-input flag of float frames."""
+    _log("accumulator state")
+    fr = _frames_for(57, 64, 64, 1, 13)
+    t = up(fr, dev)
+    A, B = prnu.new_accumulators(1, 64, 64, device=dev)
+    st = prnu.new_acc_state(dev)
+    prnu.fingerprint_accumulate(t[:40], 1, A, B, state=st)
+    assert down(st).tolist() == [40, 40, 0]
+    prnu.fingerprint_accumulate(t[40:], 5, A, B, state=st)
+    assert down(st).tolist() == [57, 44, 0]  # 17 frames in groups of 5: 4 SDA frames
+    ff = up(fr.astype(np.float32), dev)
+    st2 = prnu.new_acc_state(dev)
+    A2, B2 = prnu.new_accumulators(1, 64, 64, device=dev)
+    prnu.fingerprint_accumulate(ff[:10], 2, A2, B2, state=st2)
+    assert down(st2).tolist() == [10, 5, 0]
+    ff[3, 5, 6, 0] = float("nan")
+    prnu.fingerprint_accumulate(ff[:10], 2, A2, B2, state=st2)
+    assert down(st2).tolist() == [20, 10, prnu.STATUS_NONFINITE]
 
 
 def test_depth_one_u8_frames_read_in_place(dev):
@@ -383,6 +483,29 @@ def test_resample_bilinear_vs_oracle(dev, n, H, W, scale, oh, ow, oy, ox):
         np.testing.assert_allclose(got[p], ref, rtol=0, atol=2e-6 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("n_src,H,W,oh,ow", [(1, 64, 96, 50, 70), (2, 120, 200, 120, 200), (1, 1080, 1920, 960, 1800)])
+def test_warp_affine_vs_oracle(dev, n_src, H, W, oh, ow):
+    """The affine warp of stabilised video against the oracle: rotations by
+    small and large angles, zooms, shear, translations (some leave the plane:
+    clamped edges), each output plane with its own matrix; plane k samples
+    source k % n_src.  Bilinear weights in float32 from double coordinates:
+    2e-6 of the plane's scale."""
+    _log(f"warp affine {n_src}x{H}x{W} -> {oh}x{ow}")
+    g = synth.rng(synth.CFG_TEST, 6300 + H)
+    x = g.normal(0, 1, size=(n_src, H, W)).astype(np.float32)
+    mats = [resample.rotation(0.0, 1.0, H, W, oh, ow),
+            resample.rotation(0.0175, 1.0, H, W, oh, ow, 2.5, -3.0),
+            resample.rotation(-0.3, 1.07, H, W, oh, ow),
+            resample.rotation(1.2, 0.8, H, W, oh, ow, -7.0, 11.0),
+            [0.95, 0.12, 3.3, -0.08, 1.04, -2.1],
+            resample.rotation(np.pi / 2, 1.0, H, W, oh, ow)]
+    got = down(prnu.warp_affine(up(x, dev), np.array(mats), oh, ow))
+    assert got.shape == (len(mats), oh, ow)
+    for k, M in enumerate(mats):
+        ref = resample.affine(x[k % n_src].astype(np.float64), M, oh, ow)
+        np.testing.assert_allclose(got[k], ref, rtol=0, atol=2e-6 * np.abs(ref).max())
+
+
 def test_pce_fixed_query_chunks(dev):
     """Enough pairs that the direct sums run in several chunks of queries."""
     _log("pce query chunks")
@@ -521,6 +644,42 @@ def test_stabilised_segments_aligned(dev):
     prnu.fingerprint_accumulate(fr, 10, A0, B0)
     K0 = down(prnu.fingerprint_finalize(A0, B0, flags=0))
     c, ca = slice(8, H - 8), slice(8 - M, H - 8 - M)
+    corr = lambda a, s: float(np.corrcoef(a[s, s].ravel(), K[c, c].ravel())[0, 1])
+    print(f"corr aligned {corr(Ka, ca):.3f} unaligned {corr(K0, c):.3f}", flush=True)
+    assert corr(Ka, ca) > corr(K0, c) + 0.1
+
+
+def test_stabilised_rotations_aligned(dev):
+    """Stabiliser that rotates and translates each segment (Sec. II-B, V-E):
+    the pose search finds every segment's angle (from the candidate grid) and
+    translation against the camera's pattern, and the MLE over the frames
+    warped back correlates with K better than the unaligned fingerprint."""
+    from paper_1909_04573_amd import evaluation as ev
+
+    _log("stabilised rotations: pose search")
+    H = W = 256
+    degs = (-2.0, -1.0, 1.0, 2.0)
+    fr, K, poses = synth.stabilized_video_affine_torch(1, 0, 80, H, W, k_std=0.02, max_shift=3, angles_deg=degs,
+                                                       segment=10, device=dev, cfg=synth.CFG_TEST)
+    seg = poses[::10]
+    assert np.any(seg[:, 0] != 0) and np.any(np.all(seg == 0, axis=1))
+    _, means = prnu.sda_average(fr, 10, want_sums=False)
+    means = means[:, 0].contiguous()
+    Wr = prnu.denoise_residual(means)
+    Kt = torch.from_numpy(K.astype(np.float32)).to(dev)
+    angles = list(np.deg2rad((-2.0, -1.0, 0.0, 1.0, 2.0)))
+    est, P = ev.segment_poses(Wr, means, Kt, angles, max_shift=3, margin=28)  # 200 x 200 DFT window
+    # pattern at p is K(c + R(theta)(p - c) - s): the pose search reports (theta, -sy, -sx)
+    np.testing.assert_allclose(est[:, 0], seg[:, 0], atol=1e-12)
+    np.testing.assert_array_equal(est[:, 1:], -seg[:, 1:])
+    M, h = 12, 225
+    A, B = prnu.new_accumulators(1, h, h, device=dev)
+    ev.aligned_fingerprint_affine(means, est, A, B, M)
+    Ka = down(prnu.fingerprint_finalize(A, B, flags=0))  # pixel (0, 0) is frame pixel (M, M)
+    A0, B0 = prnu.new_accumulators(1, H, W, device=dev)
+    prnu.fingerprint_accumulate(fr, 10, A0, B0)
+    K0 = down(prnu.fingerprint_finalize(A0, B0, flags=0))
+    c, ca = slice(16, 16 + 200), slice(16 - M, 16 - M + 200)
     corr = lambda a, s: float(np.corrcoef(a[s, s].ravel(), K[c, c].ravel())[0, 1])
     print(f"corr aligned {corr(Ka, ca):.3f} unaligned {corr(K0, c):.3f}", flush=True)
     assert corr(Ka, ca) > corr(K0, c) + 0.1
