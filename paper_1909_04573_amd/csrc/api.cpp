@@ -548,6 +548,7 @@ int prnu_fingerprint_accumulate_workspace_size(int n_frames, int H, int W, int C
     if (n_frames < 1 || group < 1) return fail(PRNU_E_INVAL, "%s: n_frames and group must be >= 1", fn);
     if (C != 1 && C != 3) return fail(PRNU_E_INVAL, "%s: C must be 1 or 3", fn);
     PRNU_TRY(check_dims(H, W, fn));
+    PRNU_TRY(check_mle_pixels(H, W, fn));
     PRNU_TRY(check_params(p, fn));
     Carver cv(nullptr);
     AccPlan ap;
@@ -563,6 +564,7 @@ int prnu_fingerprint_accumulate(const void *frames, int dtype, int n_frames, int
     set_error("");
     PRNU_TRY(check_frames(frames, dtype, n_frames, C, fn));
     PRNU_TRY(check_dims(H, W, fn));
+    PRNU_TRY(check_mle_pixels(H, W, fn));
     int64_t fstride;
     PRNU_TRY(check_frame_stride(frame_stride_bytes, dtype, n_frames, H, W, C, fn, &fstride));
     PRNU_TRY(check_params(p, fn));

@@ -116,6 +116,8 @@ int check_cameras(const prnu_camera *cams, int n, const char *fn) {
         if (check_dims(c.H, c.W, fn) != PRNU_OK)
             return fail(PRNU_E_INVAL, "%s: camera %d: H and W must be in [16, %d] (got %d x %d)", fn, j, kMaxDim,
                         c.H, c.W);
+        if ((int64_t)c.H * c.W >= kMleMaxPixels)
+            return fail(PRNU_E_INVAL, "%s: camera %d: frames of %d x %d exceed 2^28 pixels", fn, j, c.H, c.W);
     }
     return PRNU_OK;
 }

@@ -602,7 +602,10 @@ __device__ __forceinline__ void inv_maps(int tid, int hk, int wk, int k0r, int k
 // subband, so each load costs one address add; a wave's lanes read
 // consecutive columns of two rows.  fetch() issues a plane's loads into
 // registers, put() stores them to LDS, so a caller can have the next plane's
-// loads in flight while it works on the current one.
+// loads in flight while it works on the current one.  Neither branches:
+// slots past the last row or column repeat the last one (the same value
+// lands in the same LDS word twice), so the compiler can count the loads in
+// flight and wait only for the ones a put needs.
 template <int TAPS, int TT>
 struct InvStage {
     static constexpr int NK = InvGeom<TAPS, TT>::NK, NKS = InvGeom<TAPS, TT>::NKS;
@@ -611,14 +614,17 @@ struct InvStage {
     int tx, ty, coff[NCG], roff[NRG];
     float v[4][NRG][NCG];
 
+    static __device__ __forceinline__ int col(int tx, int g) { return min(tx + g * CX, NK - 1); }
+    static __device__ __forceinline__ int row(int ty, int i) { return min(ty + i * RY, NK - 1); }
+
     // rmap/cmap must be in LDS (after the barrier that follows inv_maps)
     __device__ __forceinline__ void offsets(int tid, int wk, const int *rmap, const int *cmap) {
         tx = tid % CX;
         ty = tid / CX;
 #pragma unroll
-        for (int g = 0; g < NCG; ++g) coff[g] = tx + g * CX < NK ? cmap[tx + g * CX] : 0;
+        for (int g = 0; g < NCG; ++g) coff[g] = cmap[col(tx, g)];
 #pragma unroll
-        for (int i = 0; i < NRG; ++i) roff[i] = ty + i * RY < NK ? rmap[ty + i * RY] * wk : 0;
+        for (int i = 0; i < NRG; ++i) roff[i] = rmap[row(ty, i)] * wk;
     }
     __device__ __forceinline__ void fetch(const float *__restrict__ lpp, int64_t band, bool zero_approx) {
         const PRNU_GLOBAL float *lp = gmem(lpp);
@@ -628,9 +634,8 @@ struct InvStage {
             for (int i = 0; i < NRG; ++i)
 #pragma unroll
                 for (int g = 0; g < NCG; ++g) {
-                    v[sbd][i][g] = 0.f;
-                    if (ty + i * RY < NK && tx + g * CX < NK && !(sbd == 0 && zero_approx))
-                        v[sbd][i][g] = lp[sbd * band + roff[i] + coff[g]];
+                    const float t = lp[sbd * band + roff[i] + coff[g]];
+                    v[sbd][i][g] = sbd == 0 && zero_approx ? 0.f : t;
                 }
     }
     __device__ __forceinline__ void put(float *sb) const {
@@ -639,18 +644,50 @@ struct InvStage {
 #pragma unroll
             for (int i = 0; i < NRG; ++i)
 #pragma unroll
-                for (int g = 0; g < NCG; ++g)
-                    if (ty + i * RY < NK && tx + g * CX < NK)
-                        sb[(sbd * NK + ty + i * RY) * NKS + tx + g * CX] = v[sbd][i][g];
+                for (int g = 0; g < NCG; ++g) sb[(sbd * NK + row(ty, i)) * NKS + col(tx, g)] = v[sbd][i][g];
     }
 };
 
 // Columns (axis 0): lo1/hi1[n][kc] for the 2TT output rows.
+//
+// Piece (kc, pp, half, v) of the column pass: output rows 4pp + 2v and
+// 4pp + 2v + 1 of column kc of lo1 (half 0: from a and hl) or hi1 (half 1:
+// from lh and hh), from coefficient rows 2pp + v .. 2pp + v + HT - 1.
+template <int TAPS, int TT>
+__device__ __forceinline__ void inv_col_piece(const float *sb, float *lo1, float *hi1, const Filter &f, int kc,
+                                              int pp, int half, int v) {
+    constexpr int NK = InvGeom<TAPS, TT>::NK, NKS = InvGeom<TAPS, TT>::NKS, HT = TAPS / 2;
+    const int s0 = half == 0 ? 0 : 1, s1 = half == 0 ? 2 : 3;
+    float p[HT], q[HT];
+#pragma unroll
+    for (int t = 0; t < HT; ++t) {
+        const int kr = 2 * pp + v + t;
+        p[t] = sb[(s0 * NK + kr) * NKS + kc];
+        q[t] = sb[(s1 * NK + kr) * NKS + kc];
+    }
+    float *dst = half == 0 ? lo1 : hi1;
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+        float acc = 0.f;
+#pragma unroll
+        for (int i = 0; i < HT; ++i) {
+            const int t = HT - 1 - i;
+            acc = fmaf(f.h[2 * i + par], p[t], fmaf(f.g[2 * i + par], q[t], acc));
+        }
+        dst[(4 * pp + 2 * v + par) * NKS + kc] = acc;
+    }
+}
+
+// Items (column kc, output row quad pp): the first rounds give every thread
+// whole items (both halves and both row pairs share their loads); the
+// remainder, fewer than the threads, is cut into quarter items (half, v) so
+// that no wave reaches the next barrier with a whole extra item.  Every
+// output sums the same products in the same order either way.
 template <int TAPS, int TT>
 __device__ __forceinline__ void inv_cols(int tid, const float *sb, float *lo1, float *hi1, const Filter &f) {
-    constexpr int NK = InvGeom<TAPS, TT>::NK, NKS = InvGeom<TAPS, TT>::NKS, HT = TAPS / 2;
-    // item: column kc, quad of output rows n = 4pp .. 4pp+3 (coefficient rows 2pp .. 2pp+HT)
-    for (int it = tid; it < NK * (TT / 2); it += inv_nt(TT)) {
+    constexpr int NK = InvGeom<TAPS, TT>::NK, NKS = InvGeom<TAPS, TT>::NKS, HT = TAPS / 2, NTH = inv_nt(TT);
+    constexpr int ITEMS = NK * (TT / 2), FULL = ITEMS / NTH * NTH, REST = ITEMS - FULL;
+    for (int it = tid; it < FULL; it += NTH) {
         const int pp = it / NK, kc = it - (it / NK) * NK;
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
@@ -677,6 +714,12 @@ __device__ __forceinline__ void inv_cols(int tid, const float *sb, float *lo1, f
                     dst[(4 * pp + 2 * v + par) * NKS + kc] = acc;
                 }
         }
+    }
+    // quarter e: item FULL + e % REST (consecutive lanes, consecutive items), piece e / REST
+    for (int e = tid; e < 4 * REST; e += NTH) {
+        const int qtr = e / REST, it = FULL + (e - qtr * REST);
+        const int pp = it / NK, kc = it - (it / NK) * NK;
+        inv_col_piece<TAPS, TT>(sb, lo1, hi1, f, kc, pp, qtr >> 1, qtr & 1);
     }
 }
 
@@ -750,7 +793,11 @@ __device__ __forceinline__ void inv_body(const InvArgs &a, int tile, int plane, 
 }
 
 // Level 1 with the MLE epilogue over the a.nb SDA frames of channel c
-// (planes [nb][C], means [nb][C][H][W]).
+// (planes [nb][C], means [nb][C][H][W]).  The intensities I of frame fr + 1
+// are loaded with its subbands, one frame ahead; they and the accumulators
+// go through buffer loads and stores whose out-of-image offsets read 0 and
+// write nothing, so no load sits behind a per-pixel branch (a pixel outside
+// the image adds W * 0 to its partial sums, which leaves them unchanged).
 template <int TAPS, int TT, int ACC, bool U8I = false>
 __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, float *lds, const Filter &f) {
     using G = InvGeom<TAPS, TT>;
@@ -766,6 +813,39 @@ __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, floa
     const int H = a.H, W = a.W, C = a.C;
     inv_maps<TAPS, TT>(tid, a.hk, a.wk, k0r, k0c, rmap, cmap);
     const int64_t npx = (int64_t)H * W;
+    // byte offset of each owned pixel within one intensity plane (a frame's
+    // channel c for U8I), or the plane's size where the pixel lies outside
+    const unsigned esz = U8I ? (unsigned)C : 4u;
+    const unsigned plane_bytes = U8I ? (unsigned)(npx * C - c) : (unsigned)(npx * 4);
+    unsigned ioff[ITEMS][4];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const int it = tid + k * inv_nt(TT);
+        const int n = it / (NO / 4), mq = it - (it / (NO / 4)) * (NO / 4);
+        const int y = 2 * k0r + n - a.off_r;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int xx = 2 * k0c + 4 * mq + u - a.off_c;
+            ioff[k][u] = (y >= 0 && y < H && xx >= 0 && xx < W) ? (unsigned)(y * W + xx) * esz : plane_bytes;
+        }
+    }
+    auto i_rsrc = [&](int fr) {
+        const void *base = U8I ? (const void *)(a.means8 + (int64_t)fr * npx * C + c)
+                               : (const void *)(a.means + (int64_t)(fr * C + c) * npx);
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)plane_bytes, 0x00020000);
+    };
+    auto load_i = [&](int fr, float (&Iv)[ITEMS][4]) {
+        const __amdgpu_buffer_rsrc_t rs = i_rsrc(fr);
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if constexpr (U8I)
+                    Iv[k][u] = (float)__builtin_amdgcn_raw_buffer_load_b8(rs, ioff[k][u], 0, 0);
+                else
+                    Iv[k][u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, ioff[k][u], 0, 0));
+            }
+    };
     double sa[ITEMS][4], sbb[ITEMS][4];  // ACC_F64 partials
     float ka[ITEMS][4], kc_[ITEMS][4];   // float partial of A (+ compensation for KAHAN)
     float kb[ITEMS][4], kbc[ITEMS][4];   // ... and of B
@@ -777,44 +857,30 @@ __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, floa
             sbb[k][u] = 0.0;
             ka[k][u] = kc_[k][u] = kb[k][u] = kbc[k][u] = 0.f;
         }
-    // subband loads of frame fr + 1 are in flight while frame fr is transformed
+    // subband loads and intensities of frame fr + 1 are in flight while frame fr is transformed
     __syncthreads();  // maps ready
     InvStage<TAPS, TT> st;
     st.offsets(tid, a.wk, rmap, cmap);
     const int64_t band = (int64_t)a.hk * a.wk;
     st.fetch(a.lvl + (int64_t)c * 4 * band, band, a.zero_approx != 0);
+    float In[ITEMS][4];
+    load_i(0, In);
     for (int fr = 0; fr < a.nb; ++fr) {
-        // this frame's SDA means, loaded ahead of the subband staging (kept
-        // in registers only where a thread owns a single row quad)
-        const PRNU_GLOBAL float *Ip = gmem(a.means) + (int64_t)(fr * C + c) * npx;
-        // U8I: SDA depth 1, the means are the u8 frames (a.means8) themselves
-        const PRNU_GLOBAL unsigned char *I8 = U8I ? gmem(a.means8) + (int64_t)fr * npx * C + c : nullptr;
-        auto load_I = [&](int y, int xx) {
-            if constexpr (U8I)
-                return (float)I8[((int64_t)y * W + xx) * C];
-            else
-                return Ip[(int64_t)y * W + xx];
-        };
-        constexpr int PF = ITEMS == 1 ? 1 : 0;
-        float Iv[PF ? ITEMS : 1][4];
+        float Iv[ITEMS][4];
 #pragma unroll
-        for (int k = 0; k < (PF ? ITEMS : 0); ++k) {
-            const int it = tid + k * inv_nt(TT);
-            const int n = it / (NO / 4), mq = it - (it / (NO / 4)) * (NO / 4);
-            const int y = 2 * k0r + n - a.off_r;
+        for (int k = 0; k < ITEMS; ++k)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int xx = 2 * k0c + 4 * mq + u - a.off_c;
-                Iv[k][u] = (y >= 0 && y < H && xx >= 0 && xx < W) ? load_I(y, xx) : 0.f;
-            }
-        }
+            for (int u = 0; u < 4; ++u) Iv[k][u] = In[k][u];
         // The previous frame's column pass finished reading sb before the
         // barrier that precedes its row pass, and this frame's column pass
         // writes lo1/hi1 only after the next barrier, which every thread
         // reaches after its row pass: one barrier per hand-over suffices.
         st.put(sb);
         __syncthreads();
-        if (fr + 1 < a.nb) st.fetch(a.lvl + (int64_t)((fr + 1) * C + c) * 4 * band, band, a.zero_approx != 0);
+        if (fr + 1 < a.nb) {
+            st.fetch(a.lvl + (int64_t)((fr + 1) * C + c) * 4 * band, band, a.zero_approx != 0);
+            load_i(fr + 1, In);
+        }
         const int tf = opaque_tid();  // index arithmetic per frame, not live across the frame loop
         inv_cols<TAPS, TT>(tf, sb, lo1, hi1, f);
         __syncthreads();
@@ -824,71 +890,106 @@ __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, floa
             const int n = it / (NO / 4), mq = it - (it / (NO / 4)) * (NO / 4);
             float x[4];
             inv_row_quad<TAPS, TT>(lo1, hi1, n, mq, f, x);
-            const int y = 2 * k0r + n - a.off_r;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int xx = 2 * k0c + 4 * mq + u - a.off_c;
-                if (y >= 0 && y < H && xx >= 0 && xx < W) {
-                    const float I = PF ? Iv[PF ? k : 0][u] : load_I(y, xx);
-                    if (ACC == PRNU_ACC_KAHAN_F32) {
-                        // two-sum accumulation of W*I and I*I
-                        const float pa = x[u] * I, pb = I * I;
-                        float t = ka[k][u] + pa;
-                        float z = t - ka[k][u];
-                        kc_[k][u] += (ka[k][u] - (t - z)) + (pa - z);
-                        ka[k][u] = t;
-                        t = kb[k][u] + pb;
-                        z = t - kb[k][u];
-                        kbc[k][u] += (kb[k][u] - (t - z)) + (pb - z);
-                        kb[k][u] = t;
-                    } else if (ACC == PRNU_ACC_F32) {
-                        ka[k][u] = fmaf(x[u], I, ka[k][u]);
-                        kb[k][u] = fmaf(I, I, kb[k][u]);
-                    } else {
-                        sa[k][u] = fma((double)x[u], (double)I, sa[k][u]);
-                        sbb[k][u] = fma((double)I, (double)I, sbb[k][u]);
-                    }
+                const float I = Iv[k][u];
+                if (ACC == PRNU_ACC_KAHAN_F32) {
+                    // two-sum accumulation of W*I and I*I
+                    const float pa = x[u] * I, pb = I * I;
+                    float t = ka[k][u] + pa;
+                    float z = t - ka[k][u];
+                    kc_[k][u] += (ka[k][u] - (t - z)) + (pa - z);
+                    ka[k][u] = t;
+                    t = kb[k][u] + pb;
+                    z = t - kb[k][u];
+                    kbc[k][u] += (kb[k][u] - (t - z)) + (pb - z);
+                    kb[k][u] = t;
+                } else if (ACC == PRNU_ACC_F32) {
+                    ka[k][u] = fmaf(x[u], I, ka[k][u]);
+                    kb[k][u] = fmaf(I, I, kb[k][u]);
+                } else {
+                    sa[k][u] = fma((double)x[u], (double)I, sa[k][u]);
+                    sbb[k][u] = fma((double)I, (double)I, sbb[k][u]);
                 }
             }
         }
     }
-    // one read-modify-write of the accumulators per pixel
+    // one read-modify-write of the accumulators per pixel: every load first,
+    // then the sums, then the stores (out-of-image offsets read 0, store nothing)
+    const unsigned ab = (unsigned)(npx * (ACC == PRNU_ACC_F64 ? 8 : 4));
+    unsigned aoff[ITEMS][4];
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-        const int it = tid + k * inv_nt(TT);
-        const int n = it / (NO / 4), mq = it - (it / (NO / 4)) * (NO / 4);
-        const int y = 2 * k0r + n - a.off_r;
-        if (y < 0 || y >= H) continue;
+    for (int k = 0; k < ITEMS; ++k)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int xx = 2 * k0c + 4 * mq + u - a.off_c;
-            if (xx < 0 || xx >= W) continue;
-            const int64_t o = (int64_t)c * npx + (int64_t)y * W + xx;
-            if (ACC == PRNU_ACC_F64) {
-                PRNU_GLOBAL double *A = gmem(static_cast<double *>(a.A));
-                PRNU_GLOBAL double *B = gmem(static_cast<double *>(a.B));
-                A[o] += sa[k][u];
-                B[o] += sbb[k][u];
-            } else if (ACC == PRNU_ACC_F32) {
-                PRNU_GLOBAL float *A = gmem(static_cast<float *>(a.A));
-                PRNU_GLOBAL float *B = gmem(static_cast<float *>(a.B));
-                A[o] += ka[k][u];
-                B[o] += kb[k][u];
-            } else {
-                // value plane [0], compensation plane [1]
-                PRNU_GLOBAL float *A = gmem(static_cast<float *>(a.A));
-                PRNU_GLOBAL float *B = gmem(static_cast<float *>(a.B));
-                const int64_t cs = (int64_t)C * npx;
-                float s = A[o], t = s + ka[k][u], z = t - s;
-                A[o + cs] += kc_[k][u] + ((s - (t - z)) + (ka[k][u] - z));
-                A[o] = t;
-                s = B[o];
-                t = s + kb[k][u];
-                z = t - s;
-                B[o + cs] += kbc[k][u] + ((s - (t - z)) + (kb[k][u] - z));
-                B[o] = t;
+        for (int u = 0; u < 4; ++u)
+            aoff[k][u] = ioff[k][u] == plane_bytes ? ab : ioff[k][u] / esz * (ACC == PRNU_ACC_F64 ? 8u : 4u);
+    if constexpr (ACC == PRNU_ACC_F64) {
+        const __amdgpu_buffer_rsrc_t ra =
+            __builtin_amdgcn_make_buffer_rsrc(static_cast<double *>(a.A) + (int64_t)c * npx, 0, (int)ab, 0x00020000);
+        const __amdgpu_buffer_rsrc_t rb =
+            __builtin_amdgcn_make_buffer_rsrc(static_cast<double *>(a.B) + (int64_t)c * npx, 0, (int)ab, 0x00020000);
+        double va[ITEMS][4], vb[ITEMS][4];
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const auto la = __builtin_amdgcn_raw_buffer_load_b64(ra, aoff[k][u], 0, 0);
+                const auto lb = __builtin_amdgcn_raw_buffer_load_b64(rb, aoff[k][u], 0, 0);
+                __builtin_memcpy(&va[k][u], &la, 8);
+                __builtin_memcpy(&vb[k][u], &lb, 8);
             }
-        }
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double na = va[k][u] + sa[k][u], nb = vb[k][u] + sbb[k][u];
+                decltype(__builtin_amdgcn_raw_buffer_load_b64(ra, 0, 0, 0)) wa, wb;
+                __builtin_memcpy(&wa, &na, 8);
+                __builtin_memcpy(&wb, &nb, 8);
+                __builtin_amdgcn_raw_buffer_store_b64(wa, ra, aoff[k][u], 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b64(wb, rb, aoff[k][u], 0, 0);
+            }
+    } else {
+        // F32: A, B planes; KAHAN: value plane [0] then compensation plane [1] of each
+        const int64_t cs = (int64_t)C * npx;
+        float *A0 = static_cast<float *>(a.A) + (int64_t)c * npx, *B0 = static_cast<float *>(a.B) + (int64_t)c * npx;
+        const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(A0, 0, (int)ab, 0x00020000);
+        const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(B0, 0, (int)ab, 0x00020000);
+        const __amdgpu_buffer_rsrc_t rac = __builtin_amdgcn_make_buffer_rsrc(A0 + cs, 0, (int)ab, 0x00020000);
+        const __amdgpu_buffer_rsrc_t rbc = __builtin_amdgcn_make_buffer_rsrc(B0 + cs, 0, (int)ab, 0x00020000);
+        float va[ITEMS][4], vb[ITEMS][4], vac[ITEMS][4], vbc[ITEMS][4];
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                va[k][u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ra, aoff[k][u], 0, 0));
+                vb[k][u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rb, aoff[k][u], 0, 0));
+                if (ACC == PRNU_ACC_KAHAN_F32) {
+                    vac[k][u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rac, aoff[k][u], 0, 0));
+                    vbc[k][u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rbc, aoff[k][u], 0, 0));
+                }
+            }
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const unsigned o = aoff[k][u];
+                if (ACC == PRNU_ACC_F32) {
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(va[k][u] + ka[k][u]), ra, o, 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(vb[k][u] + kb[k][u]), rb, o, 0, 0);
+                } else {
+                    float s = va[k][u], t = s + ka[k][u], z = t - s;
+                    __builtin_amdgcn_raw_buffer_store_b32(
+                        __float_as_uint(vac[k][u] + (kc_[k][u] + ((s - (t - z)) + (ka[k][u] - z)))), rac, o, 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(t), ra, o, 0, 0);
+                    s = vb[k][u];
+                    t = s + kb[k][u];
+                    z = t - s;
+                    __builtin_amdgcn_raw_buffer_store_b32(
+                        __float_as_uint(vbc[k][u] + (kbc[k][u] + ((s - (t - z)) + (kb[k][u] - z)))), rbc, o, 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(t), rb, o, 0, 0);
+                }
+            }
     }
 }
 
@@ -915,7 +1016,7 @@ __global__ __launch_bounds__(inv_nt(TT)) void dwt_inv(InvArgs a, Filter f) {
 }
 
 template <int TAPS, int TT, int ACC, bool U8I>
-__global__ __launch_bounds__(inv_nt(TT)) void dwt_inv_mle(MleArgs a, Filter f) {
+__global__ __launch_bounds__(inv_nt(TT)) __attribute__((amdgpu_waves_per_eu(4))) void dwt_inv_mle(MleArgs a, Filter f) {
     __shared__ __align__(16) float lds[InvGeom<TAPS, TT>::LDS];
     int tile, c;
     grid_tile(tile, c);
@@ -1108,6 +1209,9 @@ hipError_t launch_dwt_inv(int taps, const Filter &f, const float *lvl, int hk, i
 hipError_t launch_dwt_inv_mle(int taps, const Filter &f, const float *lvl, int hk, int wk, bool zero_approx, int nb,
                               int C, const float *means, int H, int W, int off_r, int off_c, int acc_mode, void *A,
                               void *B, hipStream_t s, const unsigned char *means8) {
+    // the fold addresses one channel plane of A or B (8 bytes a pixel) and a
+    // frame (C bytes a pixel) with 32-bit buffer offsets
+    if ((int64_t)H * W >= kMleMaxPixels) return hipErrorInvalidValue;
     const int tt = tile_choice(TK_MLE, taps, hk, wk);
     MleArgs a{lvl, hk, wk, zero_approx ? 1 : 0, ceil_div(wk, tt), nb, C, means, H, W, off_r, off_c, A, B, means8};
     dim3 grid((unsigned)tiles_for(tt, hk, wk), (unsigned)C);

@@ -70,6 +70,13 @@ inline int check_frames(const void *frames, int dtype, int n, int C, const char 
     return PRNU_OK;
 }
 
+// MLE accumulation: a frame below 2^28 pixels (the fold's 32-bit offsets).
+inline int check_mle_pixels(int H, int W, const char *fn) {
+    if ((int64_t)H * W >= kMleMaxPixels)
+        return fail(PRNU_E_INVAL, "%s: frames of %d x %d are too large to accumulate (limit 2^28 pixels)", fn, H, W);
+    return PRNU_OK;
+}
+
 inline int check_params(const prnu_denoise_params *p, const char *fn) {
     if (!p) return fail(PRNU_E_INVAL, "%s: null denoise params", fn);
     if (!std::isfinite(p->sigma0) || p->sigma0 < 0.f)

@@ -76,6 +76,9 @@ struct InvArgs {
     float *out;
     int H, W, off_r, off_c;
 };
+// Frames of at least this many pixels are refused by the MLE fold (its
+// buffer offsets into an FP64 accumulator plane are 32-bit).
+constexpr int64_t kMleMaxPixels = (int64_t)1 << 28;
 struct MleArgs {
     const float *lvl;
     int hk, wk, zero_approx, tiles_c, nb, C;

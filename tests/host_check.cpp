@@ -144,6 +144,10 @@ void check_validation() {
     EXPECT_RC(prnu_fingerprint_accumulate(fr, PRNU_U8, 8, 64, 64, 1, 0, 1, &p, 0, nullptr, out, nullptr, ws, big,
                                           nullptr),
               PRNU_E_INVAL);
+    EXPECT_RC(prnu_fingerprint_accumulate(fr, PRNU_U8, 8, 16384, 16384, 1, 0, 1, &p, 0, out, out, nullptr, ws, big,
+                                          nullptr),
+              PRNU_E_INVAL);  // 2^28 pixels: beyond the fold's 32-bit offsets
+    EXPECT(error_mentions("2^28"));
     EXPECT_RC(prnu_fingerprint_accumulate(fr, PRNU_U8, 8, 64, 64, 1, 64 * 64 - 1, 1, &p, 0, out, out, nullptr, ws, big,
                                           nullptr),
               PRNU_E_INVAL);
