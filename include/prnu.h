@@ -355,6 +355,36 @@ int prnu_pce_vjp(const float *X, int nx, const float *Y, int ny, int h, int w, c
                  size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * FP64 mode of the differentiated chain (checking mode): the matched-minus-
+ * unmatched fixed-peak PCE gap and its gradient with respect to
+ * theta = (sigma0, lambda_1..lambda_4), s_l = lambda_l sigma0^2, every step in
+ * double precision on the GPU (Sec. III-B SDA frames and MLE, Sec. II-A
+ * residual and correlation, Sec. IV PCE; the same chain the FP32 entry points
+ * above differentiate, with 4 wavelet levels).
+ *
+ * cam_frames  float [ncam][m][H][W]: each camera's frames, grouped by `group`
+ *             into SDA frames (the last group may be shorter).
+ * queries     float [nq][H][W]; query_cam int [nq] (device): the camera of
+ *             each query (matched pair) or any other value (no match).
+ * theta       HOST doubles [5], finite and >= 0.
+ * out         device doubles [6]: loss = mean PCE of matched pairs - mean PCE
+ *             of unmatched pairs, then dL/dsigma0, dL/dlambda_1..4.
+ * pce         nullable device doubles [nq][ncam].
+ * H and W need prime factors <= 5 (the DFT); nbhd odd, below H and W.
+ * The kernels are plain (one thread per value, direct window sums, a
+ * radix-2..5 FFT, reductions in a fixed order): results are deterministic;
+ * the mode is for checking gradients at full sizes, not for speed.
+ * Workspace: about (6 + 2 * 3/4) * (ncam * ceil(m / group) + nq) padded
+ * planes of doubles.
+ */
+int prnu_pce_gap_f64_workspace_size(int ncam, int m, int nq, int H, int W, int group, int taps, int nbhd,
+                                    size_t *bytes);
+int prnu_pce_gap_f64(const float *cam_frames, int ncam, int m, const float *queries, int nq,
+                     const int *query_cam, int H, int W, int group, int taps, int nbhd,
+                     const double *theta, double *out, double *pce, void *ws, size_t ws_bytes,
+                     void *stream);
+
+/* ---------------------------------------------------------------------------
  * Batched fingerprint accumulation: many cameras of different sizes, frame
  * counts and SDA group lengths in one sequence of persistent launches (the
  * SDA -> residual -> MLE chain of prnu_fingerprint_accumulate, Sec. III-B,

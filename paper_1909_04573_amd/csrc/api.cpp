@@ -943,6 +943,71 @@ int prnu_pce_vjp(const float *X, int nx, const float *Y, int ny, int h, int w, c
     return PRNU_OK;
 }
 
+// ---- FP64 mode of the differentiated chain -----------------------------------
+static int gap64_dims(int ncam, int m, int nq, int H, int W, int group, int taps, int nbhd, const char *fn,
+                      prnu::Gap64Dims *D) {
+    using namespace prnu;
+    if (ncam < 1 || m < 1 || nq < 1) return fail(PRNU_E_INVAL, "%s: ncam, m and nq must be >= 1", fn);
+    if (group < 1) return fail(PRNU_E_INVAL, "%s: group must be >= 1", fn);
+    PRNU_TRY(check_dims(H, W, fn));
+    if (taps != 8 && taps != 16) return fail(PRNU_E_UNSUPPORTED, "%s: taps must be 8 or 16", fn);
+    if (nbhd < 1 || !(nbhd & 1) || nbhd >= H || nbhd >= W)
+        return fail(PRNU_E_INVAL, "%s: nbhd must be odd, >= 1 and below H and W", fn);
+    if (!gap64_fft_length_ok(H) || !gap64_fft_length_ok(W))
+        return fail(PRNU_E_UNSUPPORTED, "%s: H and W need prime factors <= 5 (got %d x %d)", fn, H, W);
+    D->ncam = ncam;
+    D->m = m;
+    D->d = group;
+    D->g = (m + group - 1) / group;
+    D->nq = nq;
+    D->H = H;
+    D->W = W;
+    D->Hp = padded(H);
+    D->Wp = padded(W);
+    D->t = pad_before(H);
+    D->l = pad_before(W);
+    D->levels = 4;
+    D->taps = taps;
+    D->nbhd = nbhd;
+    D->ssz = 0;
+    for (int l = 1; l <= D->levels; ++l) D->ssz += 3 * (int64_t)(D->Hp >> l) * (D->Wp >> l);
+    const int64_t planes = (int64_t)ncam * D->g + nq;
+    if (planes > 65535 || planes * D->Hp * (int64_t)D->Wp > ((int64_t)1 << 31))
+        return fail(PRNU_E_INVAL, "%s: at most 65535 planes and 2^31 padded pixels over all planes", fn);
+    return PRNU_OK;
+}
+
+int prnu_pce_gap_f64_workspace_size(int ncam, int m, int nq, int H, int W, int group, int taps, int nbhd,
+                                    size_t *bytes) {
+    const char *fn = "prnu_pce_gap_f64_workspace_size";
+    set_error("");
+    if (!bytes) return fail(PRNU_E_INVAL, "%s: null output", fn);
+    Gap64Dims D;
+    PRNU_TRY(gap64_dims(ncam, m, nq, H, W, group, taps, nbhd, fn, &D));
+    *bytes = gap64_workspace_bytes(D);
+    return PRNU_OK;
+}
+
+int prnu_pce_gap_f64(const float *cam_frames, int ncam, int m, const float *queries, int nq, const int *query_cam,
+                     int H, int W, int group, int taps, int nbhd, const double *theta, double *out, double *pce,
+                     void *ws, size_t ws_bytes, void *stream) {
+    const char *fn = "prnu_pce_gap_f64";
+    set_error("");
+    if (!cam_frames || !queries || !query_cam || !theta || !out) return fail(PRNU_E_INVAL, "%s: null pointer", fn);
+    Gap64Dims D;
+    PRNU_TRY(gap64_dims(ncam, m, nq, H, W, group, taps, nbhd, fn, &D));
+    for (int k = 0; k < 5; ++k)
+        if (!std::isfinite(theta[k]) || theta[k] < 0.0)
+            return fail(PRNU_E_INVAL, "%s: theta must be finite and >= 0", fn);
+    const size_t need = gap64_workspace_bytes(D);
+    if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255))
+        return fail(PRNU_E_WORKSPACE, "%s: workspace needs %zu bytes, 256-byte aligned", fn, need);
+    Filter64 f;
+    if (!make_filter64(taps, &f)) return fail(PRNU_E_UNSUPPORTED, "%s: filter design failed", fn);
+    PRNU_HIP(gap64_run(D, f, theta, cam_frames, queries, query_cam, ws, out, pce, (hipStream_t)stream));
+    return PRNU_OK;
+}
+
 int prnu_postprocess_workspace_size(int n, int C, int H, int W, int flags, size_t *bytes) {
     const char *fn = "prnu_postprocess_workspace_size";
     set_error("");

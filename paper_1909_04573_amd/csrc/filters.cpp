@@ -125,6 +125,19 @@ bool make_filter(int taps, Filter *f) {
     return true;
 }
 
+bool make_filter64(int taps, Filter64 *f) {
+    if (taps != 8 && taps != 16) return false;
+    long double h[20];
+    if (!daubechies_lowpass(taps, h)) return false;
+    std::memset(f, 0, sizeof(*f));
+    f->taps = taps;
+    for (int k = 0; k < taps; ++k) {
+        f->h[k] = (double)h[k];
+        f->g[k] = (double)((k & 1 ? -1.0L : 1.0L) * h[taps - 1 - k]);
+    }
+    return true;
+}
+
 }  // namespace prnu
 
 extern "C" int prnu_filter_coefficients(int taps, double *h) {

@@ -38,6 +38,13 @@ struct Filter {
 // Daubechies extremal-phase low-pass, long-double spectral factorisation.
 bool daubechies_lowpass(int taps, long double *h);
 bool make_filter(int taps, Filter *f);
+// The same filters rounded to double, for the FP64 mode of the differentiated chain.
+struct Filter64 {
+    double h[kMaxTaps];
+    double g[kMaxTaps];
+    int taps;
+};
+bool make_filter64(int taps, Filter64 *f);
 
 // ---- geometry --------------------------------------------------------------
 constexpr int kPadMult = 16;
@@ -324,5 +331,18 @@ hipError_t launch_pvjp(float2 *Z, float2 *V, float2 *T1, float2 *T2, const float
                        const float2 *tw_w, void *coef, const double *wts, const float *mod, double *pce, float *gX,
                        float *gY, hipStream_t s);
 hipError_t launch_fill_zero(float *x, int64_t n, hipStream_t s);
+
+// ---- FP64 mode of the differentiated chain ---------------------------------
+constexpr int kRedBlocks64 = 64;  // partial sums per plane of an FP64 reduction
+struct Gap64Dims {
+    int ncam, m, g, d, nq, H, W, Hp, Wp, t, l, levels, taps, nbhd;
+    int64_t ssz;  // checkpoint doubles per plane: 3 bands of each level
+};
+bool gap64_fft_length_ok(int n);
+size_t gap64_workspace_bytes(const Gap64Dims &D);
+// Forward and backward of the PCE gap in FP64; out (device) = loss, dL/dsigma0,
+// dL/dlambda_1..4; pce_out (device, nullable) [nq][ncam].
+hipError_t gap64_run(const Gap64Dims &D, const Filter64 &f, const double *theta, const float *cams,
+                     const float *queries, const int *qcam, void *ws, double *out, double *pce_out, hipStream_t s);
 
 }  // namespace prnu

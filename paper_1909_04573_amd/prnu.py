@@ -39,6 +39,7 @@ EXPORTS = (
     "prnu_denoise_ckpt_floats", "prnu_denoise_residual_ckpt",
     "prnu_denoise_residual_vjp_workspace_size", "prnu_denoise_residual_vjp",
     "prnu_pce_vjp_workspace_size", "prnu_pce_vjp",
+    "prnu_pce_gap_f64_workspace_size", "prnu_pce_gap_f64",
     "prnu_batch_workspace_size", "prnu_batch_create", "prnu_batch_launch", "prnu_batch_info_get",
     "prnu_batch_destroy", "prnu_fingerprint_batch",
     "prnu_get_tile", "prnu_set_tile", "prnu_autotune_workspace_size", "prnu_autotune",
@@ -115,6 +116,9 @@ def lib() -> ctypes.CDLL:
     L.prnu_denoise_residual_vjp.argtypes = [_P, ctypes.c_int64, _P, _P, _I, _I, _I, _DP, _P, _P, _P, _S, _P]
     L.prnu_pce_vjp_workspace_size.argtypes = [_I, _I, _I, _I, ctypes.POINTER(_S)]
     L.prnu_pce_vjp.argtypes = [_P, _I, _P, _I, _I, _I, _P, _I, _P, _P, _P, _P, _P, _S, _P]
+    L.prnu_pce_gap_f64_workspace_size.argtypes = [_I, _I, _I, _I, _I, _I, _I, _I, ctypes.POINTER(_S)]
+    L.prnu_pce_gap_f64.argtypes = [_P, _I, _I, _P, _I, _P, _I, _I, _I, _I, _I, ctypes.POINTER(ctypes.c_double),
+                                   _P, _P, _P, _S, _P]
     _CP = ctypes.POINTER(Camera)
     L.prnu_batch_workspace_size.argtypes = [_CP, _I, _DP, _S, ctypes.POINTER(_S)]
     L.prnu_batch_create.argtypes = [_CP, _I, _I, _DP, _I, _I, _S, _P, _S, _P, ctypes.POINTER(_P)]
@@ -531,6 +535,37 @@ def denoise_residual_vjp(gW: torch.Tensor, ckpt: torch.Tensor, params: DenoisePa
     _check(lib().prnu_denoise_residual_vjp(_ptr(gW), stride, _ptr(mul), _ptr(div), n, H, W, ctypes.byref(p),
                                            _ptr(ckpt), _ptr(dLds), _ptr(ws), ws.numel(), _stream(gW.device)))
     return dLds
+
+
+def pce_gap_f64(theta, cam_frames: torch.Tensor, queries: torch.Tensor, query_cam, d: int = 8, nbhd: int = 11,
+                taps: int = 16):
+    """FP64 mode of the differentiated chain: (loss, dL/dtheta [5], PCE [nq][ncam])
+    of the matched-minus-unmatched PCE gap, everything in double on the GPU.
+    theta = (sigma0, lambda_1..4); cam_frames float32 [ncam][m][H][W];
+    queries float32 [nq][H][W]; query_cam: camera of each query."""
+    _cuda(cam_frames, "cam_frames")
+    _cuda(queries, "queries")
+    if cam_frames.dtype != torch.float32 or queries.dtype != torch.float32:
+        raise ValueError("cam_frames and queries must be float32")
+    if cam_frames.dim() != 4 or queries.dim() != 3 or tuple(queries.shape[1:]) != tuple(cam_frames.shape[2:]):
+        raise ValueError("cam_frames [ncam][m][H][W] and queries [nq][H][W] of one frame size")
+    ncam, m, H, W = (int(v) for v in cam_frames.shape)
+    nq = int(queries.shape[0])
+    dev = queries.device
+    qc = torch.as_tensor(list(query_cam), dtype=torch.int32).to(dev)
+    if qc.numel() != nq:
+        raise ValueError("query_cam needs one camera per query")
+    th = (ctypes.c_double * 5)(*[float(v) for v in theta])
+    nbytes = _S()
+    _check(lib().prnu_pce_gap_f64_workspace_size(ncam, m, nq, H, W, int(d), int(taps), int(nbhd),
+                                                 ctypes.byref(nbytes)))
+    ws = workspace(nbytes.value, dev)
+    out = torch.zeros(6, dtype=torch.float64, device=dev)
+    pce = torch.zeros((nq, ncam), dtype=torch.float64, device=dev)
+    _check(lib().prnu_pce_gap_f64(_ptr(cam_frames), ncam, m, _ptr(queries), nq, _ptr(qc), H, W, int(d), int(taps),
+                                  int(nbhd), th, _ptr(out), _ptr(pce), _ptr(ws), ws.numel(), _stream(dev)))
+    o = out.cpu().numpy()
+    return float(o[0]), o[1:6].copy(), pce.cpu().numpy()
 
 
 def pce_vjp(X: torch.Tensor, Y: torch.Tensor, weights: torch.Tensor, modulate: torch.Tensor | None = None,

@@ -177,6 +177,16 @@ void check_validation() {
     const double *M = static_cast<const double *>(fake(0x300000));
     EXPECT_RC(prnu_warp_affine(X, 1, 16, 16, M, 70000, 8, 8, o, nullptr), PRNU_E_INVAL);
     EXPECT_RC(prnu_warp_affine(X, 1, 16, 16, nullptr, 1, 8, 8, o, nullptr), PRNU_E_INVAL);
+    // FP64 gap: sizes, DFT lengths, theta
+    size_t gn = 0;
+    EXPECT_RC(prnu_pce_gap_f64_workspace_size(8, 32, 64, 512, 512, 8, 16, 11, &gn), PRNU_OK);
+    EXPECT(gn > (size_t)88 * 512 * 512 * 8);
+    EXPECT_RC(prnu_pce_gap_f64_workspace_size(2, 8, 4, 64, 70, 4, 16, 11, &gn), PRNU_E_UNSUPPORTED);
+    EXPECT_RC(prnu_pce_gap_f64_workspace_size(70000, 1, 1, 64, 64, 1, 16, 11, &gn), PRNU_E_INVAL);
+    const double th_bad[5] = {3.0, 1.0, NAN, 1.0, 1.0};
+    EXPECT_RC(prnu_pce_gap_f64(X, 2, 8, X, 4, static_cast<const int *>(fake(0x300000)), 64, 64, 4, 16, 11, th_bad,
+                               pce, nullptr, ws, big, nullptr),
+              PRNU_E_INVAL);
     // long argument values reach the error text formatting
     EXPECT_RC(prnu_sda_average(fr, PRNU_F32, 16843009, 16, 16, 3, INT64_MAX, 1, nullptr, o, nullptr, nullptr, nullptr),
               PRNU_E_INVAL);

@@ -212,3 +212,25 @@ def test_host_sources_under_sanitizers(host_check):
     assert rc != 0 and "AddressSanitizer: heap-buffer-overflow" in out, out
     rc, out = host_check("plant-ub")
     assert rc != 0 and "runtime error: signed integer overflow" in out, out
+
+
+def test_gap_f64_validation(lib):
+    """The FP64 gap rejects bad sizes, a DFT size with a factor 7, even
+    neighbourhoods, negative theta and a short workspace on the host."""
+    fake = ctypes.c_void_p(0x100000)
+    out = ctypes.c_void_p(0x200000)
+    qc = ctypes.c_void_p(0x300000)
+    n = ctypes.c_size_t(0)
+    ws_size = lib.prnu_pce_gap_f64_workspace_size
+    assert ws_size(2, 8, 4, 64, 64, 4, 16, 11, ctypes.byref(n)) == 0 and n.value > 0
+    assert ws_size(0, 8, 4, 64, 64, 4, 16, 11, ctypes.byref(n)) == prnu.PRNU_E_INVAL
+    assert ws_size(2, 8, 4, 64, 70, 4, 16, 11, ctypes.byref(n)) == prnu.PRNU_E_UNSUPPORTED  # 7 divides 70
+    assert ws_size(2, 8, 4, 64, 64, 4, 16, 10, ctypes.byref(n)) == prnu.PRNU_E_INVAL
+    assert ws_size(2, 8, 4, 64, 64, 4, 6, 11, ctypes.byref(n)) == prnu.PRNU_E_UNSUPPORTED
+    th = (ctypes.c_double * 5)(3.0, 1.0, 1.0, 1.0, 1.0)
+    f = lib.prnu_pce_gap_f64
+    assert f(None, 2, 8, fake, 4, qc, 64, 64, 4, 16, 11, th, out, None, fake, 1 << 30, None) == prnu.PRNU_E_INVAL
+    assert f(fake, 2, 8, fake, 4, qc, 64, 64, 4, 16, 11, th, out, None, fake, 16, None) == prnu.PRNU_E_WORKSPACE
+    bad = (ctypes.c_double * 5)(3.0, -1.0, 1.0, 1.0, 1.0)
+    assert f(fake, 2, 8, fake, 4, qc, 64, 64, 4, 16, 11, bad, out, None, fake, 1 << 30, None) == prnu.PRNU_E_INVAL
+    assert "theta" in lib.prnu_last_error().decode()
