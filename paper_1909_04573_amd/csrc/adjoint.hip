@@ -72,17 +72,14 @@ __global__ __launch_bounds__(NT) void dwt_vjp(const float *__restrict__ src, int
         [&](int e) {
             const int i = e / IN, j = e - (e / IN) * IN;
             const int r = rmap[i], c = cmap[j];
-            float v = 0.f;
-            if (r >= 0 && c >= 0) {
-                const int64_t o = (int64_t)r * src_cols + c;
-                v = sp[o];
-                if (mp) v *= mp[o];
-                if (div) {
-                    const float d = div[o];
-                    v = d > 0.f ? v / d : 0.f;
-                }
+            const int64_t o = (int64_t)max(r, 0) * src_cols + max(c, 0);
+            float v = sp[o];
+            if (mp) v *= mp[o];
+            if (div) {
+                const float d = div[o];
+                v = d > 0.f ? v / d : 0.f;
             }
-            return v;
+            return r >= 0 && c >= 0 ? v : 0.f;
         },
         [&](int e, float v) { tile[(e / IN) * INS + e - (e / IN) * IN] = v; });
     __syncthreads();

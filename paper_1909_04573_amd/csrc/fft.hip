@@ -57,15 +57,20 @@ __global__ __launch_bounds__(FNT) void fft_1d(float2 *__restrict__ data, int Nrt
     // plan ping-pongs between two data buffers
     float2 *b0 = smem, *b1 = smem + tot, *twl = FN ? smem + tot : smem + 2 * tot;
     staged_copy<FNT, 4, float2>(threadIdx.x, N, [&](int e) { return tw[e]; }, [&](int e, float2 z) { twl[e] = z; });
-    staged_copy<FNT, 8, float2>(
-        threadIdx.x, tot,
-        [&](int e) {
-            const int v = e & (nvec - 1), n = e >> lvec;
-            const int64_t o = (int64_t)(v0 + v) * vs + (int64_t)n * es;
-            if (v0 + v >= count) return make_float2(0.f, 0.f);
-            return rin ? make_float2(rin[(int64_t)pl * plane_stride + o], 0.f) : base[o];
-        },
-        [&](int e, float2 z) { b0[e] = z; });
+    // vector groups inside the batch (all but a ragged last one) stage without
+    // a bounds select, which the compiler would turn into a branch around the loads
+    auto elem = [&](int e, bool in) {
+        const int v = e & (nvec - 1), n = e >> lvec;
+        const int64_t o = (int64_t)min(v0 + v, count - 1) * vs + (int64_t)n * es;
+        const float2 z = rin ? make_float2(rin[(int64_t)pl * plane_stride + o], 0.f) : base[o];
+        return in || v0 + v < count ? z : make_float2(0.f, 0.f);
+    };
+    if (v0 + nvec <= count)
+        staged_copy<FNT, 8, float2>(threadIdx.x, tot, [&](int e) { return elem(e, true); },
+                                    [&](int e, float2 z) { b0[e] = z; });
+    else
+        staged_copy<FNT, 8, float2>(threadIdx.x, tot, [&](int e) { return elem(e, false); },
+                                    [&](int e, float2 z) { b0[e] = z; });
     __syncthreads();
     const float2 *res = fft_run<FN, FV>(b0, b1, plan, twl, sigma);
     for (int e = threadIdx.x; e < tot; e += FNT) {
@@ -83,7 +88,7 @@ __global__ __launch_bounds__(FNT) void fft_1d(float2 *__restrict__ data, int Nrt
 // Real rows -> half spectra.  Plane p of the batch is y = Y[(p0+p) % ny]
 // (times mod[(p0+p) / ny] if given, minus `mean[p]` if given).  Row r, bins
 // k = 0 .. w/2 at out[p][r][k] (row stride w/2 + 1).
-template <int FN, int FV>
+template <int FN, int FV, bool MOD>
 __global__ __launch_bounds__(FNT) void rfft_rows(const float *__restrict__ Y, const float *__restrict__ mod,
                                                  int ny, int p0, const double *__restrict__ mean, int h,
                                                  int wrt, FftPlan plan, const float2 *__restrict__ tw_half,
@@ -96,7 +101,7 @@ __global__ __launch_bounds__(FNT) void rfft_rows(const float *__restrict__ Y, co
     const int pid = p0 + (int)blockIdx.y;
     const int64_t N = (int64_t)h * w;
     const float *yp = Y + (int64_t)(pid % ny) * N;
-    const float *mp = mod ? mod + (int64_t)(pid / ny) * N : nullptr;
+    const float *mp = MOD ? mod + (int64_t)(pid / ny) * N : nullptr;
     const float mu = mean ? (float)mean[blockIdx.y] : 0.f;
     const int tot = M * nvec;
     float2 *b0 = smem, *b1 = smem + tot, *twh = FN ? smem + tot : smem + 2 * tot, *twf = twh + M;
@@ -104,23 +109,25 @@ __global__ __launch_bounds__(FNT) void rfft_rows(const float *__restrict__ Y, co
                                 [&](int e, float2 z) { twh[e] = z; });
     staged_copy<FNT, 4, float2>(threadIdx.x, M + 1, [&](int e) { return tw_full[e]; },
                                 [&](int e, float2 z) { twf[e] = z; });
-    staged_copy<FNT, 8, float2>(
-        threadIdx.x, tot,
-        [&](int e) {
-            const int v = e & (nvec - 1), n = e >> lvec;
-            float2 z = make_float2(0.f, 0.f);
-            if (r0 + v < h) {
-                const int64_t o = (int64_t)(r0 + v) * w + 2 * n;
-                float a = yp[o], b = yp[o + 1];
-                if (mp) {
-                    a *= mp[o];
-                    b *= mp[o + 1];
-                }
-                z = make_float2(a - mu, b - mu);
-            }
-            return z;
-        },
-        [&](int e, float2 z) { b0[e] = z; });
+    // rows of a block inside the plane (all but a ragged last block) stage
+    // without a bounds select: the compiler would turn it into a branch
+    // around the loads and wait for each pair of loads in turn
+    auto row_pair = [&](int e, bool in) {
+        const int v = e & (nvec - 1), n = e >> lvec;
+        const int64_t o = (int64_t)min(r0 + v, h - 1) * w + 2 * n;
+        float a = yp[o], b = yp[o + 1];
+        if constexpr (MOD) {  // a separate instantiation: no branch around the loads
+            a *= mp[o];
+            b *= mp[o + 1];
+        }
+        return in || r0 + v < h ? make_float2(a - mu, b - mu) : make_float2(0.f, 0.f);
+    };
+    if (r0 + nvec <= h)
+        staged_copy<FNT, 8, float2>(threadIdx.x, tot, [&](int e) { return row_pair(e, true); },
+                                    [&](int e, float2 z) { b0[e] = z; });
+    else
+        staged_copy<FNT, 8, float2>(threadIdx.x, tot, [&](int e) { return row_pair(e, false); },
+                                    [&](int e, float2 z) { b0[e] = z; });
     __syncthreads();
     const float2 *res = fft_run<FN, FV>(b0, b1, plan, twh, -1.f);
     // Split the even/odd-sample spectra: Y[k] = E[k] + W_w^k O[k].
@@ -160,13 +167,19 @@ __global__ __launch_bounds__(FNT) void fft_cols_power(const float2 *__restrict__
     const int tot = h * nvec;
     float2 *b0 = smem, *b1 = smem + tot, *twl = FN ? smem + tot : smem + 2 * tot;
     staged_copy<FNT, 4, float2>(threadIdx.x, h, [&](int e) { return tw[e]; }, [&](int e, float2 z) { twl[e] = z; });
-    staged_copy<FNT, 8, float2>(
-        threadIdx.x, tot,
-        [&](int e) {
-            const int v = e & (nvec - 1), n = e >> lvec;
-            return (c0 + v < Mc) ? sp[(int64_t)n * Mc + c0 + v] : make_float2(0.f, 0.f);
-        },
-        [&](int e, float2 z) { b0[e] = z; });
+    // column groups inside the half spectrum (all but the last) stage without a
+    // bounds select, which the compiler would turn into a branch around the loads
+    auto col_elem = [&](int e, bool in) {
+        const int v = e & (nvec - 1), n = e >> lvec;
+        const float2 z = sp[(int64_t)n * Mc + min(c0 + v, Mc - 1)];
+        return in || c0 + v < Mc ? z : make_float2(0.f, 0.f);
+    };
+    if (c0 + nvec <= Mc)
+        staged_copy<FNT, 8, float2>(threadIdx.x, tot, [&](int e) { return col_elem(e, true); },
+                                    [&](int e, float2 z) { b0[e] = z; });
+    else
+        staged_copy<FNT, 8, float2>(threadIdx.x, tot, [&](int e) { return col_elem(e, false); },
+                                    [&](int e, float2 z) { b0[e] = z; });
     const int pid = p0 + pl;
     const float *pq = DOT ? Px + (int64_t)(pid / ny) * plane : nullptr;
     // With a compile-time length the power weights of this thread's elements
@@ -178,7 +191,8 @@ __global__ __launch_bounds__(FNT) void fft_cols_power(const float2 *__restrict__
         for (int k = 0; k < PXN; ++k) {
             const int e = threadIdx.x + k * FNT;
             const int v = e & (nvec - 1), n = e >> lvec;
-            pxr[k] = (e < tot && c0 + v < Mc) ? pq[(int64_t)n * Mc + c0 + v] : 0.f;
+            // clamped to a valid element (read only where e and the column are in range)
+            pxr[k] = pq[(int64_t)min(n, h - 1) * Mc + min(c0 + v, Mc - 1)];
         }
     }
     __syncthreads();
@@ -288,7 +302,7 @@ hipError_t allow_lds(K kernel, unsigned bytes) {
 // gets: full rows, half rows and columns of 1920x1080, 1280x720, 3840x2160
 // and 512x512 planes.  Every other length runs the runtime plan.
 using Fft1dKernel = decltype(&fft_1d<0, 0>);
-using RowsKernel = decltype(&rfft_rows<0, 0>);
+using RowsKernel = decltype(&rfft_rows<0, 0, false>);
 using ColsKernel = decltype(&fft_cols_power<true, 0, 0>);
 
 static Fft1dKernel pick_fft_1d(const FftPlan &p) {
@@ -300,12 +314,12 @@ static Fft1dKernel pick_fft_1d(const FftPlan &p) {
     return fft_1d<0, 0>;
 }
 
-static RowsKernel pick_rfft_rows(const FftPlan &p) {
+static RowsKernel pick_rfft_rows(const FftPlan &p, bool mod) {
 #define PRNU_CASE(N, V) \
-    if (p.n == N && p.nvec == V) return rfft_rows<N, V>;
+    if (p.n == N && p.nvec == V) return mod ? rfft_rows<N, V, true> : rfft_rows<N, V, false>;
     PRNU_CASE(960, 2) PRNU_CASE(640, 4) PRNU_CASE(1920, 1) PRNU_CASE(256, 8)
 #undef PRNU_CASE
-    return rfft_rows<0, 0>;
+    return mod ? rfft_rows<0, 0, true> : rfft_rows<0, 0, false>;
 }
 
 template <bool DOT>
@@ -361,8 +375,9 @@ hipError_t launch_rfft_rows(const float *Y, const float *mod, int ny, int p0, in
     const double bytes = (double)n * h * ((mod ? 8.0 : 4.0) * w + 8.0 * (w / 2 + 1));
     KernelTimer kt("rfft_rows", bytes, s);
     dim3 g((unsigned)((h + phalf.nvec - 1) / phalf.nvec), (unsigned)n);
-    const RowsKernel k = pick_rfft_rows(phalf);
-    const unsigned lds = fft_lds_bytes(phalf, 2 * phalf.n + 1, k != rfft_rows<0, 0>);
+    const RowsKernel k = pick_rfft_rows(phalf, mod != nullptr);
+    const unsigned lds =
+        fft_lds_bytes(phalf, 2 * phalf.n + 1, k != rfft_rows<0, 0, false> && k != rfft_rows<0, 0, true>);
     const hipError_t e = allow_lds(k, lds);
     if (e != hipSuccess) return e;
     k<<<g, FNT, lds, s>>>(Y, mod, ny, p0, mean, h, w, phalf, tw_half, tw_full, out);

@@ -204,12 +204,9 @@ __global__ __launch_bounds__(NT) void spectral_wiener_kernel(const float2 *__res
         [&](int e) {
             const int i = e / WNC, j = e - (e / WNC) * WNC;
             const int gr = r0 + i, gc = c0 + j;
-            float v = 0.f;
-            if (gr >= 0 && gr < h && gc >= 0 && gc < w) {
-                const float2 z = Fp[(int64_t)gr * w + gc];
-                v = (z.x * z.x + z.y * z.y) * invN;
-            }
-            return v;
+            const float2 z = Fp[(int64_t)min(max(gr, 0), h - 1) * w + min(max(gc, 0), w - 1)];
+            const float v = (z.x * z.x + z.y * z.y) * invN;
+            return gr >= 0 && gr < h && gc >= 0 && gc < w ? v : 0.f;
         },
         [&](int e, float v) { q[(e / WNC) * WNCS + e - (e / WNC) * WNC] = v; });
     __syncthreads();

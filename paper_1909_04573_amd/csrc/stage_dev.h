@@ -3,7 +3,9 @@
 // staged_copy: cooperative staging of global data into LDS.  Thread `tid` of
 // a group of NTH threads handles elements tid, tid + NTH, ... of `count`; it
 // issues up to KB loads before storing them, so a batch of global loads is in
-// flight at once instead of one load per round trip.
+// flight at once instead of one load per round trip.  The load callbacks must
+// not branch around their loads either: they clamp indices to valid elements
+// and select zero afterwards.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -68,15 +70,19 @@ template <int NTH, int KB, typename T, typename Load, typename Store>
 __device__ __forceinline__ void staged_copy(int tid, int count, Load load, Store store) {
     for (int e0 = tid; e0 < count; e0 += KB * NTH) {
         T v[KB];
+        // neither loads nor stores sit behind a per-lane branch (elements
+        // past the end load the last one again and store it to the same
+        // place): the compiler then waits for each load only where its value
+        // is stored, not for every load in flight after each one
 #pragma unroll
         for (int k = 0; k < KB; ++k) {
             const int e = e0 + k * NTH;
-            if (e < count) v[k] = load(e);
+            v[k] = load(e < count ? e : count - 1);
         }
 #pragma unroll
         for (int k = 0; k < KB; ++k) {
             const int e = e0 + k * NTH;
-            if (e < count) store(e, v[k]);
+            store(e < count ? e : count - 1, v[k]);
         }
     }
 }
