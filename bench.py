@@ -68,8 +68,8 @@ def parse():
     ap.add_argument("--no-equal-accuracy", action="store_true",
                     help="video: skip the untimed SDA-vs-conventional equal-TPR block on weak-PRNU cameras")
     ap.add_argument("--tiles", type=str, default="auto",
-                    help="video: 'auto' (time both tile sizes per level kernel) or the 12 values autotune "
-                         "reports, e.g. to profile the configuration a bench run chose")
+                    help="video: 'auto' (time the tile sizes and strip segment targets per level kernel) or "
+                         "the 16 values autotune reports, e.g. to profile the configuration a bench run chose")
     ap.add_argument("--curve-step", type=int, default=25,
                     help="video: frame-count grid of the conventional accuracy curve (0: skip it)")
     ap.add_argument("--block", type=int, default=500, help="evaluation: block side of the block-wise PCE")

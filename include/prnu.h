@@ -454,27 +454,32 @@ int prnu_fingerprint_batch(const prnu_camera *cams, int n_cams, int dtype, const
  *
  * A forward level with shrinkage (kind PRNU_TILE_FWD) streams strips of
  * `tile` subband columns, 64 or 32 (default 64), down the plane in steps of
- * 16 coefficient rows; the segment of rows a workgroup walks is sized from
- * the level and the batch so that each launch holds about six workgroups per
- * CU.  The Wiener margin around a strip is fixed at 4 coefficients by the
- * largest (9 x 9) window.  An inverse level or inverse level 1 with the MLE
- * fold (kind PRNU_TILE_INV / _MLE) works on square tiles of `tile`
- * coefficients per side, 32 or 16 (default 32).  Choices are kept per
- * filter length and subband size hk x wk.
- * prnu_set_tile: one of the kind's two widths, 0 restores the default;
- *   PRNU_E_INVAL for any other width.
+ * 16 coefficient rows.  The segment of rows a workgroup walks (kind
+ * PRNU_TILE_SEG, the halo's amortisation) is sized from the level and the
+ * batch so that each launch holds about `tile` workgroups per CU: 3, 6 or 12
+ * (default 6); longer segments recompute the 4-coefficient Wiener margin
+ * and the row-filter carry at segment ends less often, shorter ones fill
+ * the chip more evenly.  The Wiener margin around a strip is fixed at 4
+ * coefficients by the largest (9 x 9) window.  An inverse level or inverse
+ * level 1 with the MLE fold (kind PRNU_TILE_INV / _MLE) works on square
+ * tiles of `tile` coefficients per side, 32 or 16 (default 32).  Choices are
+ * kept per filter length and subband size hk x wk.
+ * prnu_set_tile: one of the kind's values, 0 restores the default;
+ *   PRNU_E_INVAL for any other value.
  * prnu_autotune: for frames of H x W x C and the denoiser `p`, times both
- *   widths of every forward level, inverse level 2..L and the MLE fold on
- *   synthetic planes in `ws`, as many as one fingerprint-accumulation batch
- *   holds (up to 32 frames: the tile is chosen at the size it runs; events
- *   on `stream`, waits for them; not under graph capture) and keeps the
- *   faster; `tiles` (nullable, 12 ints) receives
- *   the choices: [0..3] forward levels 1..4, [4..7] inverse levels 1..4
- *   ([4], level 1, is the MLE fold's), [8] the MLE fold; unused entries 0.
+ *   widths of every forward level, then the three segment targets at the
+ *   chosen width, inverse level 2..L and the MLE fold on synthetic planes in
+ *   `ws`, as many as one fingerprint-accumulation batch holds (up to 32
+ *   frames: the tile is chosen at the size it runs; events on `stream`,
+ *   waits for them; not under graph capture) and keeps the fastest; `tiles`
+ *   (nullable, 16 ints) receives the choices: [0..3] forward levels 1..4,
+ *   [4..7] inverse levels 1..4 ([4], level 1, is the MLE fold's), [8] the
+ *   MLE fold, [12..15] the forward levels' segment targets; unused entries 0.
  */
 #define PRNU_TILE_FWD 0
 #define PRNU_TILE_INV 1
 #define PRNU_TILE_MLE 2
+#define PRNU_TILE_SEG 3
 int prnu_get_tile(int kind, int taps, int hk, int wk);
 int prnu_set_tile(int kind, int taps, int hk, int wk, int tile);
 int prnu_autotune_workspace_size(int H, int W, int C, const prnu_denoise_params *p, size_t *bytes);

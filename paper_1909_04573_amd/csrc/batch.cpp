@@ -317,7 +317,7 @@ int build(const prnu_camera *cams, int n, int dtype, const prnu_denoise_params *
                 const int planes = r[k].ng * c.C;
                 FwdDesc d{};
                 int strips = 0, seg = 0, tiles = 0;
-                fwd_layout(tt, Hp >> l, Wp >> l, planes, &strips, &seg, &tiles);
+                fwd_layout(p->taps, tt, Hp >> l, Wp >> l, planes, &strips, &seg, &tiles);
                 if (l == 1)
                     d.a = FwdArgs{means[k], (int64_t)c.H * c.W, c.H, c.W, Hp, Wp, pad_before(c.H), pad_before(c.W),
                                   lvl[k][1], s2, strips, lv > 1 ? 1 : 0, nullptr, 0, nullptr, 0, seg};
@@ -594,18 +594,20 @@ int prnu_fingerprint_batch(const prnu_camera *cams, int n_cams, int dtype, const
 }
 
 int prnu_get_tile(int kind, int taps, int hk, int wk) {
-    if (kind < PRNU_TILE_FWD || kind > PRNU_TILE_MLE) return 0;
+    if (kind < PRNU_TILE_FWD || kind > PRNU_TILE_SEG) return 0;
     return tile_choice(kind, taps, hk, wk);
 }
 
 int prnu_set_tile(int kind, int taps, int hk, int wk, int tile) {
     set_error("");
-    if (kind < PRNU_TILE_FWD || kind > PRNU_TILE_MLE) return fail(PRNU_E_INVAL, "prnu_set_tile: unknown kind");
+    if (kind < PRNU_TILE_FWD || kind > PRNU_TILE_SEG) return fail(PRNU_E_INVAL, "prnu_set_tile: unknown kind");
     if (taps != 8 && taps != 16) return fail(PRNU_E_UNSUPPORTED, "prnu_set_tile: taps must be 8 or 16");
     if (hk < 1 || wk < 1) return fail(PRNU_E_INVAL, "prnu_set_tile: bad subband size");
-    if (tile != 0 && !tile_valid(kind, tile))
+    if (tile != 0 && !tile_valid(kind, tile)) {
+        if (kind == PRNU_TILE_SEG) return fail(PRNU_E_INVAL, "prnu_set_tile: segment target must be 0, 3, 6 or 12");
         return fail(PRNU_E_INVAL, "prnu_set_tile: tile must be 0, %d or %d for this kind", tile_default(kind),
                     tile_small(kind));
+    }
     set_tile_choice(kind, taps, hk, wk, tile == 0 ? tile_default(kind) : tile);
     return PRNU_OK;
 }
@@ -692,11 +694,34 @@ int prnu_autotune(int H, int W, int C, const prnu_denoise_params *p, void *ws, s
         set_tile_choice(kind, taps, hk, wk, best);
         return best;
     };
-    int out[12] = {0};
+    // the forward strip's segment target, timed with the chosen width
+    auto tune_seg = [&](int l) -> int {
+        const int hk = Hp >> l, wk = Wp >> l;
+        float best_ms = 0.f;
+        int best = tile_default(TK_SEG);
+        for (int k : {tile_default(TK_SEG), tile_small(TK_SEG), 12}) {
+            set_tile_choice(TK_SEG, taps, hk, wk, k);
+            if (fwd(l) != hipSuccess) return 0;  // warm-up
+            if (hipEventRecord(e0, s) != hipSuccess) return 0;
+            for (int r = 0; r < 3; ++r)
+                if (fwd(l) != hipSuccess) return 0;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return 0;
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return 0;
+            if (k == tile_default(TK_SEG) || ms < best_ms) {
+                best_ms = ms;
+                best = k;
+            }
+        }
+        set_tile_choice(TK_SEG, taps, hk, wk, best);
+        return best;
+    };
+    int out[16] = {0};
     // the pyramid must hold every level before the inverse stages are timed
     for (int l = 1; l <= lv && rc == PRNU_OK; ++l) {
         out[l - 1] = tune(TK_FWD, l, fwd);
-        if (!out[l - 1]) rc = fail(PRNU_E_HIP, "%s: forward level %d failed", fn, l);
+        if (out[l - 1]) out[12 + l - 1] = tune_seg(l);
+        if (!out[l - 1] || !out[12 + l - 1]) rc = fail(PRNU_E_HIP, "%s: forward level %d failed", fn, l);
     }
     for (int l = lv; l >= 2 && rc == PRNU_OK; --l) {
         out[4 + l - 1] = tune(TK_INV, l, inv);

@@ -145,11 +145,11 @@ struct StripGeom {
 // hk x wk coefficients with strips of tc columns over `planes` planes: long
 // segments keep the vertical halo small, short ones keep enough workgroups
 // (about six per CU per launch) to fill the chip and shorten its tail.
-__host__ __device__ inline void strip_layout(int tc, int hk, int wk, int64_t planes, int cus, int *strips, int *seg,
-                                             int *tiles) {
+__host__ __device__ inline void strip_layout(int tc, int hk, int wk, int64_t planes, int cus, int per_cu,
+                                             int *strips, int *seg, int *tiles) {
     const int ns = (wk + tc - 1) / tc;
     const int64_t base = (int64_t)ns * (planes > 0 ? planes : 1);
-    const int64_t want = 6ll * (cus > 0 ? cus : 256);
+    const int64_t want = (int64_t)per_cu * (cus > 0 ? cus : 256);
     int64_t nseg = (want + base - 1) / base;
     const int max_seg = hk / 64 > 1 ? hk / 64 : 1;  // segments of at least 64 rows
     if (nseg > max_seg) nseg = max_seg;
@@ -1148,8 +1148,8 @@ void set_tile_choice(int kind, int taps, int hk, int wk, int tt) {
     g_tile[std::make_tuple(kind, taps, hk, wk)] = tile_valid(kind, tt) ? tt : tile_default(kind);
 }
 
-void fwd_layout(int tc, int hk, int wk, int64_t planes, int *strips, int *seg_rows, int *tiles) {
-    strip_layout(tc, hk, wk, planes, device_cus(), strips, seg_rows, tiles);
+void fwd_layout(int taps, int tc, int hk, int wk, int64_t planes, int *strips, int *seg_rows, int *tiles) {
+    strip_layout(tc, hk, wk, planes, device_cus(), tile_choice(TK_SEG, taps, hk, wk), strips, seg_rows, tiles);
 }
 
 hipError_t launch_dwt_fwd(int taps, const Filter &f, const float *src, int64_t src_stride, int src_rows,
@@ -1159,7 +1159,7 @@ hipError_t launch_dwt_fwd(int taps, const Filter &f, const float *src, int64_t s
     const int hk = n_r / 2, wk = n_c / 2;
     const int tc = tile_choice(TK_FWD, taps, hk, wk);
     int strips = 0, seg = 0, tiles = 0;
-    fwd_layout(tc, hk, wk, planes, &strips, &seg, &tiles);
+    fwd_layout(taps, tc, hk, wk, planes, &strips, &seg, &tiles);
     FwdArgs a{src, src_stride, src_rows, src_cols, n_r, n_c, off_r, off_c, out, s2,
               strips, write_ll ? 1 : 0, ckpt, ckpt_stride, src8, src8_c, seg};
     dim3 grid((unsigned)tiles, (unsigned)planes);

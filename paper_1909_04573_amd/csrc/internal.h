@@ -122,16 +122,22 @@ struct SdaDesc {
 // Tile width per kernel kind and level size: the forward level runs strips
 // of 64 or 32 subband columns (64 unless prnu_autotune measured otherwise),
 // the inverse and MLE levels square tiles of 32 or 16 (32 by default).
-enum TileKind { TK_FWD = 0, TK_INV = 1, TK_MLE = 2 };
-inline int tile_default(int kind) { return kind == TK_FWD ? 64 : 32; }
-inline int tile_small(int kind) { return kind == TK_FWD ? 32 : 16; }
-inline bool tile_valid(int kind, int tt) { return tt == tile_default(kind) || tt == tile_small(kind); }
+// TK_SEG is the forward strip's segment length, stored as the number of
+// workgroups per CU a launch aims at (3, 6 or 12, default 6): fewer, longer
+// segments pay the vertical halo and the row-filter carry less often, more
+// and shorter ones fill the chip more evenly.
+enum TileKind { TK_FWD = 0, TK_INV = 1, TK_MLE = 2, TK_SEG = 3 };
+inline int tile_default(int kind) { return kind == TK_FWD ? 64 : kind == TK_SEG ? 6 : 32; }
+inline int tile_small(int kind) { return kind == TK_FWD ? 32 : kind == TK_SEG ? 3 : 16; }
+inline bool tile_valid(int kind, int tt) {
+    return tt == tile_default(kind) || tt == tile_small(kind) || (kind == TK_SEG && tt == 12);
+}
 int tile_choice(int kind, int taps, int hk, int wk);
 void set_tile_choice(int kind, int taps, int hk, int wk, int tt);
 inline int tiles_for(int tt, int hk, int wk) { return ((hk + tt - 1) / tt) * ((wk + tt - 1) / tt); }
 // Forward level of hk x wk coefficients over `planes` planes in strips of tc
 // columns: strips per plane, rows per segment and virtual blocks per plane.
-void fwd_layout(int tc, int hk, int wk, int64_t planes, int *strips, int *seg_rows, int *tiles);
+void fwd_layout(int taps, int tc, int hk, int wk, int64_t planes, int *strips, int *seg_rows, int *tiles);
 
 // ---- kernel launchers (all enqueue on `s`, return the launch status) -------
 // SDA: groups [g0, g1) of `group` frames; outputs indexed from g0.

@@ -44,7 +44,7 @@ EXPORTS = (
     "prnu_batch_destroy", "prnu_fingerprint_batch",
     "prnu_get_tile", "prnu_set_tile", "prnu_autotune_workspace_size", "prnu_autotune",
 )
-TILE_FWD, TILE_INV, TILE_MLE = 0, 1, 2
+TILE_FWD, TILE_INV, TILE_MLE, TILE_SEG = 0, 1, 2, 3
 BATCH_ZERO_ACC, BATCH_GRAPH = 1, 2
 
 
@@ -678,12 +678,16 @@ def set_tile(kind: int, taps: int, hk: int, wk: int, tile: int):
 
 
 def set_tiles(H: int, W: int, tiles, taps: int = 16, levels: int = 4):
-    """Applies a list in autotune's layout (forward 1..4, -, inverse 2..4, MLE)
-    to the level geometries of H x W frames; 0 entries are left as they are."""
+    """Applies a list in autotune's layout (forward 1..4, -, inverse 2..4, MLE,
+    and from entry 12 on the forward levels' segment targets) to the level
+    geometries of H x W frames; 0 entries and a missing tail are left as they
+    are."""
     Hp, Wp = -(-int(H) // 16) * 16, -(-int(W) // 16) * 16
     for l in range(1, levels + 1):
         if tiles[l - 1]:
             set_tile(TILE_FWD, taps, Hp >> l, Wp >> l, tiles[l - 1])
+        if len(tiles) > 12 + l - 1 and tiles[12 + l - 1]:
+            set_tile(TILE_SEG, taps, Hp >> l, Wp >> l, tiles[12 + l - 1])
     for l in range(2, levels + 1):
         if tiles[4 + l - 1]:
             set_tile(TILE_INV, taps, Hp >> l, Wp >> l, tiles[4 + l - 1])
@@ -692,13 +696,15 @@ def set_tiles(H: int, W: int, tiles, taps: int = 16, levels: int = 4):
 
 
 def autotune(H: int, W: int, C: int = 1, params: DenoiseParams | None = None, device="cuda"):
-    """Times both tile sizes of every level kernel for H x W x C frames and keeps
-    the faster; returns the 12 choices (forward 1..4, inverse 1..4, MLE)."""
+    """Times both tile sizes of every level kernel (and the forward levels'
+    segment targets) for H x W x C frames and keeps the fastest; returns the
+    16 choices (forward 1..4, inverse 1..4, MLE, -, -, -, segment targets of
+    forward 1..4)."""
     p = params or denoise_params()
     nbytes = _S()
     _check(lib().prnu_autotune_workspace_size(int(H), int(W), int(C), ctypes.byref(p), ctypes.byref(nbytes)))
     dev = torch.device(device)
     ws = workspace(nbytes.value, dev)
-    out = (ctypes.c_int * 12)()
+    out = (ctypes.c_int * 16)()
     _check(lib().prnu_autotune(int(H), int(W), int(C), ctypes.byref(p), _ptr(ws), ws.numel(), _stream(dev), out))
     return list(out)

@@ -267,6 +267,12 @@ void check_batch() {
     EXPECT_RC(prnu_set_tile(1, 16, 540, 960, 64), PRNU_E_INVAL);
     EXPECT_RC(prnu_set_tile(0, 16, 540, 960, 0), PRNU_OK);  // back to the default
     EXPECT(prnu_get_tile(0, 16, 540, 960) == t0);
+    EXPECT(prnu_get_tile(PRNU_TILE_SEG, 16, 540, 960) == 6);
+    EXPECT_RC(prnu_set_tile(PRNU_TILE_SEG, 16, 540, 960, 12), PRNU_OK);
+    EXPECT(prnu_get_tile(PRNU_TILE_SEG, 16, 540, 960) == 12);
+    EXPECT_RC(prnu_set_tile(PRNU_TILE_SEG, 16, 540, 960, 5), PRNU_E_INVAL);
+    EXPECT_RC(prnu_set_tile(PRNU_TILE_SEG, 16, 540, 960, 0), PRNU_OK);
+    EXPECT_RC(prnu_set_tile(4, 16, 540, 960, 0), PRNU_E_INVAL);
     EXPECT_RC(prnu_autotune_workspace_size(1080, 1920, 1, &p, &n), PRNU_OK);
     EXPECT_RC(prnu_autotune_workspace_size(1080, 1920, 2, &p, &n), PRNU_E_INVAL);
     EXPECT_RC(prnu_autotune(1080, 1920, 1, &p, ws, 16, nullptr, nullptr), PRNU_E_WORKSPACE);

@@ -126,6 +126,15 @@ def test_tile_state(lib):
     prnu.set_tile(prnu.TILE_INV, 16, 1000, 999, 0)
     assert prnu.get_tile(prnu.TILE_FWD, 16, 1000, 999) == 64
     assert prnu.get_tile(prnu.TILE_INV, 16, 1000, 999) == 32
+    # the forward strip's segment target: 6 workgroups per CU by default, 3 or 12
+    assert prnu.get_tile(prnu.TILE_SEG, 16, 1000, 999) == 6
+    for k in (3, 12):
+        prnu.set_tile(prnu.TILE_SEG, 16, 1000, 999, k)
+        assert prnu.get_tile(prnu.TILE_SEG, 16, 1000, 999) == k
+    prnu.set_tile(prnu.TILE_SEG, 16, 1000, 999, 0)
+    assert prnu.get_tile(prnu.TILE_SEG, 16, 1000, 999) == 6
+    with pytest.raises(prnu.PrnuError, match="segment target"):
+        prnu.set_tile(prnu.TILE_SEG, 16, 1000, 999, 32)
     for args in [(3, 16, 8, 8, 16), (0, 6, 8, 8, 32), (0, 16, 0, 8, 32), (0, 16, 8, 8, 24), (0, 16, 8, 8, 16),
                  (1, 16, 8, 8, 64), (2, 16, 8, 8, 64)]:
         with pytest.raises(prnu.PrnuError):
@@ -143,8 +152,9 @@ def test_autotune_workspace(lib):
 
 
 def test_set_tiles_layout(lib):
-    """set_tiles applies autotune's layout: forward levels 1..4, inverse 2..4, MLE."""
-    tiles = [32, 64, 32, 64, 0, 32, 16, 32, 16, 0, 0, 0]
+    """set_tiles applies autotune's layout: forward levels 1..4, inverse 2..4,
+    MLE, and the forward levels' segment targets from entry 12 on."""
+    tiles = [32, 64, 32, 64, 0, 32, 16, 32, 16, 0, 0, 0, 3, 12, 0, 6]
     try:
         prnu.set_tiles(1080, 1920, tiles)
         Hp, Wp = 1088, 1920
@@ -152,9 +162,10 @@ def test_set_tiles_layout(lib):
         assert [prnu.get_tile(prnu.TILE_INV, 16, Hp >> l, Wp >> l) for l in range(2, 5)] == tiles[5:8]
         assert prnu.get_tile(prnu.TILE_MLE, 16, Hp >> 1, Wp >> 1) == 16
         assert prnu.get_tile(prnu.TILE_INV, 16, Hp >> 1, Wp >> 1) == 32  # untouched: entry 4 is unused
+        assert [prnu.get_tile(prnu.TILE_SEG, 16, Hp >> l, Wp >> l) for l in range(1, 5)] == [3, 12, 6, 6]
     finally:
         for l in range(1, 5):
-            for kind in (prnu.TILE_FWD, prnu.TILE_INV, prnu.TILE_MLE):
+            for kind in (prnu.TILE_FWD, prnu.TILE_INV, prnu.TILE_MLE, prnu.TILE_SEG):
                 prnu.set_tile(kind, 16, 1088 >> l, 1920 >> l, 0)
 
 

@@ -234,12 +234,13 @@ def test_autotune_then_batch(dev, data):
     tiles = prnu.autotune(H, W, C)
     assert all(t in WIDTHS[prnu.TILE_FWD] for t in tiles[0:4]), tiles
     assert all(t in (16, 32) for t in tiles[5:8]) and tiles[8] in (16, 32), tiles
+    assert len(tiles) == 16 and all(t in (3, 6, 12) for t in tiles[12:16]), tiles
     try:
         cams = _cams(frames, dev)
         prnu.fingerprint_batch(cams)
         _check_oracle(cams, refs, what="autotuned")
     finally:
-        for kind in (prnu.TILE_FWD, prnu.TILE_INV, prnu.TILE_MLE):
+        for kind in (prnu.TILE_FWD, prnu.TILE_INV, prnu.TILE_MLE, prnu.TILE_SEG):
             for hk, wk in _all_geometries():
                 prnu.set_tile(kind, 16, hk, wk, 0)
 
