@@ -1471,14 +1471,96 @@ def stab_main(args):
                 f"FPR {seg_out[name][str(L)]['fpr']:.3f} median PCE {seg_out[name][str(L)]['matched_pce_median']:.1f}"
                 + ("" if name == "sda30" else f", shifts recovered on matched pairs {recov[name][str(L)]:.3f}, "
                                               f"{seg_out[name][str(L)]['ms_per_pair']:.1f} ms per pair"))
+    # A stabiliser that also rotates (Sec. II-B): one pose per 30-frame segment,
+    # still with p = 0.3, else a rotation about the frame centre by +-0.5 or
+    # +-1 degree and a translation up to 8 px.  The pose search warps u's
+    # fingerprint to every candidate angle and takes each of v's SDA frames'
+    # best angle and translation (evaluation.segment_poses); v's frames are
+    # warped back (evaluation.aligned_fingerprint_affine) onto the window of
+    # frame pixels [60, H - 60) x [60, W - 60), the same pixels as Kc.
+    del segv
+    torch.cuda.empty_cache()
+    angles_deg = (-1.0, -0.5, 0.5, 1.0)
+    cand = list(np.deg2rad((-1.0, -0.5, 0.0, 0.5, 1.0)))
+    Ma = 60
+    ha2, wa2 = ev.aligned_window(H, W, Ma)
+    Ar, Br = prnu.new_accumulators(1, ha2, wa2, device=dev)
+    rotv = torch.empty((nv, nmax, H, W, 1), dtype=torch.uint8, device=dev)
+    rposes = []
+    for c in range(ncam):
+        for v in range(nvid):
+            rotv[c * nvid + v], _, pv = synth.stabilized_video_affine_torch(c, v, nmax, H, W, angles_deg=angles_deg,
+                                                                          segment=S, device=dev)
+            rposes.append(pv[::S])
+    rot_out, rot_rec = {}, {}
+    for L in [x for x in lengths if x in (300, 600)]:
+        g = L // S
+        K = torch.empty((nv, H, W), dtype=torch.float32, device=dev)
+        for v in range(nv):
+            A.zero_()
+            B.zero_()
+            prnu.fingerprint_accumulate(rotv[v, :L], S, A, B, p, ws=ws)
+            prnu.fingerprint_finalize(A, B, out=K[v])
+        torch.cuda.synchronize()
+        Kc = K[:, 60:H - 60, 60:W - 60].contiguous()
+        P, _, _ = prnu.pce_match(Kc, Kc, None, peak_mode=prnu.PEAK_FIXED_00, want_ncc=False, want_peak=False)
+        Pn = P.cpu().numpy()[iu]
+        Pt, Pr = np.zeros(len(iu[0])), np.zeros(len(iu[0]))
+        rec_t, rec_r, ms_r = [], [], 0.0
+        for k, (u, v) in enumerate(zip(*iu)):
+            _, means = prnu.sda_average(rotv[v, :L], S, want_sums=False)
+            means = means[:, 0].contiguous()
+            Wr = prnu.denoise_residual(means, p)
+            # translations only (the search of the translation stabiliser)
+            est_t, _ = ev.segment_shifts_plane(Wr, means, K[u], max_shift=M, margin=60, pce_min=25.0)
+            Aa.zero_()
+            Ba.zero_()
+            ev.aligned_fingerprint(means, est_t, Aa, Ba, M, p, ws=ws)
+            Kal = prnu.fingerprint_finalize(Aa, Ba)
+            Pk, _, _ = prnu.pce_match(Kal[None, o:o + H - 120, o:o + W - 120].contiguous(), Kc[u:u + 1], None,
+                                      peak_mode=prnu.PEAK_FIXED_00, want_ncc=False, want_peak=False)
+            Pt[k] = float(Pk.cpu()[0, 0])
+            # angles and translations
+            e0.record(stream)
+            est, _ = ev.segment_poses(Wr, means, K[u], cand, max_shift=M, margin=60, pce_min=25.0)
+            Ar.zero_()
+            Br.zero_()
+            ev.aligned_fingerprint_affine(means, est, Ar, Br, Ma, p, ws=ws)
+            Kar = prnu.fingerprint_finalize(Ar, Br)
+            Pk, _, _ = prnu.pce_match(Kar[None].contiguous(), Kc[u:u + 1], None, peak_mode=prnu.PEAK_FIXED_00,
+                                      want_ncc=False, want_peak=False)
+            e1.record(stream)
+            Pr[k] = float(Pk.cpu()[0, 0])
+            ms_r += e0.elapsed_time(e1)
+            if same[k]:
+                truth = rposes[v][:g]
+                rec_t.append(float(np.mean(np.all(est_t == -truth[:, 1:], axis=1) & (truth[:, 0] == 0))))
+                rec_r.append(float(np.mean((np.abs(est[:, 0] - truth[:, 0]) < 1e-9)
+                                           & np.all(est[:, 1:] == -truth[:, 1:], axis=1))))
+        rot_rec[str(L)] = {"sda30-aligned-plane": float(np.mean(rec_t)), "sda30-poses": float(np.mean(rec_r))}
+        for name, Pv in (("sda30", Pn), ("sda30-aligned-plane", Pt), ("sda30-poses", Pr)):
+            matched, unmatched = Pv[same], Pv[~same]
+            rot_out.setdefault(name, {})[str(L)] = {
+                "tpr": ev.tpr(matched), "fpr": ev.fpr(unmatched), "auc": ev.auc(matched, unmatched),
+                "matched_pce_median": float(np.median(matched)),
+                "unmatched_abs_pce_max": float(np.abs(unmatched).max())}
+            if name == "sda30-poses":
+                rot_out[name][str(L)]["ms_per_pair"] = round(ms_r / len(iu[0]), 2)
+            log(f"rotating stabiliser {name} L={L}: TPR {rot_out[name][str(L)]['tpr']:.3f} "
+                f"FPR {rot_out[name][str(L)]['fpr']:.3f} median PCE {rot_out[name][str(L)]['matched_pce_median']:.1f}"
+                + (f", poses recovered {rot_rec[str(L)].get(name, float('nan')):.3f}" if name != "sda30" else ""))
     res = {"metric": "TPR at PCE > 60 between fingerprints of stabilised videos of the same camera",
            "workload": f"{ncam} gray cameras x {nvid} stabilised videos x {nmax} frames {W}x{H}; K ~ N(0, 0.0004^2); "
                        "translation-only stabilisation (still with p = 0.3, else up to 8 px); the segment "
                        "stabiliser holds one translation per 30 frames, and its aligned type searches each SDA "
-                       "frame against the other video's fingerprint",
+                       "frame against the other video's fingerprint; the rotating segment stabiliser also turns "
+                       "each segment by +-0.5 or +-1 degree",
            "types": out,
            "segment_stabiliser": {"segment_frames": S, "types": seg_out,
-                                  "shifts_recovered_on_matched_pairs": recov}}
+                                  "shifts_recovered_on_matched_pairs": recov},
+           "rotating_segment_stabiliser": {"segment_frames": S, "angles_deg": list(angles_deg),
+                                           "candidate_angles_deg": [-1.0, -0.5, 0.0, 0.5, 1.0], "types": rot_out,
+                                           "poses_recovered_on_matched_pairs": rot_rec}}
     print(json.dumps(res), flush=True)
 
 
