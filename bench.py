@@ -918,7 +918,6 @@ def batched_main(args):
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "equal_accuracy": equal_acc,
         "detail": {
             "denoised_px_per_step": denoised_px,
             "fingerprints_per_s": ncam / (ms_per_step / 1e3),
