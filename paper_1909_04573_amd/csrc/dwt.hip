@@ -596,55 +596,49 @@ __device__ __forceinline__ void inv_maps(int tid, int hk, int wk, int k0r, int k
 }
 
 // Staging of the (TT+L/2-1)^2 coefficients of the four subbands (subband 0
-// as zeros with zero_approx).  Threads form 32 columns x (threads/32) rows: a
-// thread looks up its column and row offsets once (they are the same for
-// every plane of a level) and then reads the same positions of every
-// subband, so each load costs one address add; a wave's lanes read
-// consecutive columns of two rows.  fetch() issues a plane's loads into
-// registers, put() stores them to LDS, so a caller can have the next plane's
-// loads in flight while it works on the current one.  Neither branches:
-// slots past the last row or column repeat the last one (the same value
-// lands in the same LDS word twice), so the compiler can count the loads in
-// flight and wait only for the ones a put needs.
+// as zeros with zero_approx).  Thread t takes elements t, t + threads, ...
+// of the NK x NK window in row-major order (the last slots repeat the last
+// element): consecutive lanes read consecutive columns of a row, and write
+// consecutive LDS words (the row stride NKS equals NK for odd NK).  The
+// element offsets in a subband plane and in LDS depend only on the tile, so
+// offsets() computes them once; every plane's fetch is then one load per
+// element and subband.  fetch() issues a plane's loads into registers, put()
+// stores them to LDS, so a caller can have the next plane's loads in flight
+// while it works on the current one.  Neither branches, so the compiler can
+// count the loads in flight and wait only for the ones a put needs.
 template <int TAPS, int TT>
 struct InvStage {
     static constexpr int NK = InvGeom<TAPS, TT>::NK, NKS = InvGeom<TAPS, TT>::NKS;
-    static constexpr int CX = 32, RY = inv_nt(TT) / CX;
-    static constexpr int NCG = (NK + CX - 1) / CX, NRG = (NK + RY - 1) / RY;
-    int tx, ty, coff[NCG], roff[NRG];
-    float v[4][NRG][NCG];
-
-    static __device__ __forceinline__ int col(int tx, int g) { return min(tx + g * CX, NK - 1); }
-    static __device__ __forceinline__ int row(int ty, int i) { return min(ty + i * RY, NK - 1); }
+    static constexpr int NTH = inv_nt(TT), PER = (NK * NK + NTH - 1) / NTH;
+    unsigned goff[PER];  // element offset within a subband plane
+    int loff[PER];       // LDS offset within subband 0's rows
+    float v[4][PER];
 
     // rmap/cmap must be in LDS (after the barrier that follows inv_maps)
     __device__ __forceinline__ void offsets(int tid, int wk, const int *rmap, const int *cmap) {
-        tx = tid % CX;
-        ty = tid / CX;
 #pragma unroll
-        for (int g = 0; g < NCG; ++g) coff[g] = cmap[col(tx, g)];
-#pragma unroll
-        for (int i = 0; i < NRG; ++i) roff[i] = rmap[row(ty, i)] * wk;
+        for (int k = 0; k < PER; ++k) {
+            const int e = min(tid + k * NTH, NK * NK - 1);
+            const int r = e / NK, c = e - (e / NK) * NK;
+            goff[k] = (unsigned)(rmap[r] * wk + cmap[c]);
+            loff[k] = r * NKS + c;
+        }
     }
     __device__ __forceinline__ void fetch(const float *__restrict__ lpp, int64_t band, bool zero_approx) {
         const PRNU_GLOBAL float *lp = gmem(lpp);
 #pragma unroll
         for (int sbd = 0; sbd < 4; ++sbd)
 #pragma unroll
-            for (int i = 0; i < NRG; ++i)
-#pragma unroll
-                for (int g = 0; g < NCG; ++g) {
-                    const float t = lp[sbd * band + roff[i] + coff[g]];
-                    v[sbd][i][g] = sbd == 0 && zero_approx ? 0.f : t;
-                }
+            for (int k = 0; k < PER; ++k) {
+                const float t = lp[sbd * band + goff[k]];
+                v[sbd][k] = sbd == 0 && zero_approx ? 0.f : t;
+            }
     }
     __device__ __forceinline__ void put(float *sb) const {
 #pragma unroll
         for (int sbd = 0; sbd < 4; ++sbd)
 #pragma unroll
-            for (int i = 0; i < NRG; ++i)
-#pragma unroll
-                for (int g = 0; g < NCG; ++g) sb[(sbd * NK + row(ty, i)) * NKS + col(tx, g)] = v[sbd][i][g];
+            for (int k = 0; k < PER; ++k) sb[sbd * NK * NKS + loff[k]] = v[sbd][k];
     }
 };
 
