@@ -613,6 +613,7 @@ struct InvStage {
     unsigned goff[PER];  // element offset within a subband plane
     int loff[PER];       // LDS offset within subband 0's rows
     float v[4][PER];
+    bool za;             // approximation band read as zero
 
     // rmap/cmap must be in LDS (after the barrier that follows inv_maps)
     __device__ __forceinline__ void offsets(int tid, int wk, const int *rmap, const int *cmap) {
@@ -624,21 +625,21 @@ struct InvStage {
             loff[k] = r * NKS + c;
         }
     }
+    // The zeroed approximation band is applied by put(): a select on a
+    // loaded value right after fetch() would wait for that load.
     __device__ __forceinline__ void fetch(const float *__restrict__ lpp, int64_t band, bool zero_approx) {
         const PRNU_GLOBAL float *lp = gmem(lpp);
 #pragma unroll
         for (int sbd = 0; sbd < 4; ++sbd)
 #pragma unroll
-            for (int k = 0; k < PER; ++k) {
-                const float t = lp[sbd * band + goff[k]];
-                v[sbd][k] = sbd == 0 && zero_approx ? 0.f : t;
-            }
+            for (int k = 0; k < PER; ++k) v[sbd][k] = lp[sbd * band + goff[k]];
+        za = zero_approx;
     }
     __device__ __forceinline__ void put(float *sb) const {
 #pragma unroll
         for (int sbd = 0; sbd < 4; ++sbd)
 #pragma unroll
-            for (int k = 0; k < PER; ++k) sb[sbd * NK * NKS + loff[k]] = v[sbd][k];
+            for (int k = 0; k < PER; ++k) sb[sbd * NK * NKS + loff[k]] = sbd == 0 && za ? 0.f : v[sbd][k];
     }
 };
 
