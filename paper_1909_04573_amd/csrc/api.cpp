@@ -386,7 +386,7 @@ int pce_fixed_fast(const float *X, int nx, const float *Y, int ny, int h, int w,
         const int qc = mfma_query_chunk(nx, ny, nbm);
         for (int q0 = 0; q0 < nx; q0 += qc) {
             const int nq = nx - q0 < qc ? nx - q0 : qc;
-            PRNU_HIP(launch_pce_direct_mfma(X, pl.xmean, Y, mod, ny, q0, nq, h, w, nbm, pl.dpart, s));
+            PRNU_HIP(launch_pce_direct_mfma(X, pl.xmean, Y, mod, ny, q0, nq, h, w, nbm, ncc != nullptr, pl.dpart, s));
             const int64_t pa = (int64_t)q0 * ny, pb = (int64_t)(q0 + nq) * ny;
             for (int64_t p0 = pa; p0 < pb; p0 += pl.P) {
                 const int n = (int)(pb - p0 < pl.P ? pb - p0 : pl.P);

@@ -310,8 +310,10 @@ constexpr int kPceDirectStats = 124;
 // The same direct sums on the matrix cores for every fingerprint of queries
 // q0 .. q0+nq-1: part [(q - q0) * ny + j][nblk][124] doubles.
 int pce_mfma_blocks(int nq, int ny, int h, int w);
+// syy: also the sums of y^2 (the NCC's fingerprint norms); without it their
+// partial slots are left unwritten.
 hipError_t launch_pce_direct_mfma(const float *X, const double *xmean, const float *Y, const float *mod, int ny,
-                                  int q0, int nq, int h, int w, int nblk, double *part, hipStream_t s);
+                                  int q0, int nq, int h, int w, int nblk, bool syy, double *part, hipStream_t s);
 hipError_t launch_pce_finish_fixed(const double *dpart, int nblk_d, const double *spart, int nblk_s, int n,
                                    int h, int w, int nbhd, const double *xn2, int ny, int p0, double *pce,
                                    double *ncc, int32_t *peak, hipStream_t s);

@@ -315,6 +315,9 @@ __global__ __launch_bounds__(NT) void pce_direct(const float *__restrict__ X, co
 // the device): A[i][k] and B[k][n] at lane 16 k + i / 16 k + n,
 // C[4 (l / 16) + r][l % 16] in slot r of lane l.  Each tile's fp32 products
 // are added to FP64 accumulators; sum y^2 and sum xc are plain FP64 sums.
+// The all-ones row reads a block of ones kept in LDS below the query tile
+// (1 x mod is mod exactly), so the loop has no per-lane select; sum y^2,
+// which only the NCC needs, is formed only when SYY is set.
 constexpr int MTY = 8, MTX = 64;                              // pixel tile
 constexpr int MXH = MTY + 2 * DRAD, MXW = MTX + 2 * DRAD, MXWS = 76;  // query tile with the shift halo
 constexpr int MNJ = 16, MNS = 8;                              // fingerprints, shift blocks of 16
@@ -323,11 +326,12 @@ constexpr int MONES = DNS * DNS;                              // row 121: all on
 constexpr int SBW = MNS / (NT / 64);                          // shift blocks per wave
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+template <bool SYY>
 __global__ __launch_bounds__(NT) void pce_direct_mfma(const float *__restrict__ X, const double *__restrict__ xmean,
                                                       const float *__restrict__ Y, const float *__restrict__ mod,
                                                       int ny, int q0, int h, int w, int tiles_x, int ntiles,
                                                       double *__restrict__ part) {
-    __shared__ float xs[MXH * MXWS];
+    __shared__ float xs[(MXH + MTY) * MXWS];  // query tile, then MTY rows of ones
     __shared__ float ms[MTY * MTX];                // modulation per tile pixel, 0 outside the image
     __shared__ __align__(16) float ys[MNJ * MYS];
     __shared__ double sred[NT / 64];
@@ -352,10 +356,10 @@ __global__ __launch_bounds__(NT) void pce_direct_mfma(const float *__restrict__ 
     for (int i = 0; i < SBW; ++i) {
         const int m = 16 * (SBW * wv + i) + (lane & 15);
         const int mm = m < DNS * DNS ? m : (DNS * DNS) / 2;
-        aoff[i] = (mm / DNS) * MXWS + (mm % DNS) + (lane >> 4);
+        aoff[i] = m == MONES ? MXH * MXWS + (lane >> 4) : (mm / DNS) * MXWS + (mm % DNS) + (lane >> 4);
     }
-    // the all-ones row: lane 9 of the last block of the last wave
-    const bool ones_lane = wv == NT / 64 - 1 && (lane & 15) == MONES - 16 * (MNS - 1);
+    // the ones (tile staging writes only the rows above them)
+    for (int e = tid; e < MTY * MXWS; e += NT) xs[MXH * MXWS + e] = 1.f;
     const int boff = (lane & 15) * MYS + (lane >> 4);  // B: fingerprint n = lane % 16, pixel k = lane / 16
     // staging of the fingerprint tile: thread -> fingerprint sn, columns sc + 16 u
     const int sn = tid >> 4, sc = tid & 15;
@@ -434,15 +438,14 @@ __global__ __launch_bounds__(NT) void pce_direct_mfma(const float *__restrict__ 
             const int r = g >> 4, c4 = (g & 15) * 4;
             const float b = ys[boff + r * MTX + c4];
             const float m = ms[r * MTX + c4 + (lane >> 4)];
-            if ((r & 3) == wv) {
+            if (SYY && (r & 3) == wv) {
                 const float mb = m * b;
                 ssq = fmaf(mb, mb, ssq);
             }
             const int xb = r * MXWS + c4;
 #pragma unroll
             for (int i = 0; i < SBW; ++i) {
-                float a = xs[xb + aoff[i]] * m;
-                if (i == SBW - 1 && ones_lane) a = m;
+                const float a = xs[xb + aoff[i]] * m;
                 cacc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, cacc[i], 0, 0, 0);
             }
         }
@@ -631,15 +634,18 @@ int pce_mfma_blocks(int nq, int ny, int h, int w) {
 }
 
 hipError_t launch_pce_direct_mfma(const float *X, const double *xmean, const float *Y, const float *mod, int ny,
-                                  int q0, int nq, int h, int w, int nblk, double *part, hipStream_t s) {
+                                  int q0, int nq, int h, int w, int nblk, bool syy, double *part, hipStream_t s) {
     const int tiles_x = (w + MTX - 1) / MTX;
     const int ntiles = pce_mfma_tiles(h, w);
     const int ng = (ny + MNJ - 1) / MNJ;
     // algorithmic bytes: every query pixel once, every fingerprint (and modulation) pixel once per query
     KernelTimer kt("pce_direct_mfma", (double)nq * h * w * (4.0 + ny * (mod ? 8.0 : 4.0)), s,
                    2.0 * (DNS * DNS + 1) * (double)nq * ny * h * w);  // 121 shifted sums and the plain sum
-    pce_direct_mfma<<<dim3((unsigned)nblk, (unsigned)nq, (unsigned)ng), NT, 0, s>>>(X, xmean, Y, mod, ny, q0, h, w,
-                                                                                  tiles_x, ntiles, part);
+    const dim3 grid((unsigned)nblk, (unsigned)nq, (unsigned)ng);
+    if (syy)
+        pce_direct_mfma<true><<<grid, NT, 0, s>>>(X, xmean, Y, mod, ny, q0, h, w, tiles_x, ntiles, part);
+    else
+        pce_direct_mfma<false><<<grid, NT, 0, s>>>(X, xmean, Y, mod, ny, q0, h, w, tiles_x, ntiles, part);
     return hipGetLastError();
 }
 

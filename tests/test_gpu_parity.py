@@ -399,7 +399,11 @@ def test_pce_fixed_many_fingerprints(dev, nx, ny, h, w, modulated):
     pce, ncc, _ = prnu.pce_match(up(X, dev), up(Y, dev), up(mod, dev) if modulated else None, peak_mode=0)
     rp, rn, _, _ = _pce_ref(X.astype(np.float64), Y.astype(np.float64),
                             mod.astype(np.float64) if modulated else None, 0)
+    # without the NCC the matrix-core sums skip sum y^2 only: the PCE is bit-identical
+    pce_only, _, _ = prnu.pce_match(up(X, dev), up(Y, dev), up(mod, dev) if modulated else None, peak_mode=0,
+                                    want_ncc=False, want_peak=False)
     pce, ncc = down(pce), down(ncc)
+    np.testing.assert_array_equal(down(pce_only), pce)
     np.testing.assert_allclose(ncc, rn, rtol=0, atol=1e-5)
     for q in range(nx):
         for j in range(ny):
