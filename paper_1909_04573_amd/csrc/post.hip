@@ -57,7 +57,15 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
     return r;
 }
 
-// Row means: one wave per row of a plane.  rm[c*H + r] = mean of row r.
+// Both sums below add their terms one by one in a fixed order; the loads of
+// a batch of ZB terms are issued before the first add (a term past the end
+// reads element 0 and adds an exact 0.0), so each thread keeps ZB loads in
+// flight instead of waiting for every term in turn.
+constexpr int ZB = 8;
+
+// Row means: one wave per row of a plane.  rm[c*H + r] = mean of row r; lane
+// l adds elements l, l + 64, ... in order, then the lanes are added by a
+// fixed shuffle tree.
 __global__ __launch_bounds__(NT) void row_mean_kernel(const float *__restrict__ x, int rows, int W,
                                                       double *__restrict__ rm) {
     const int row = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
@@ -65,12 +73,22 @@ __global__ __launch_bounds__(NT) void row_mean_kernel(const float *__restrict__ 
     if (row >= rows) return;
     const float *p = x + (int64_t)row * W;
     double s = 0.0;
-    for (int i = lane; i < W; i += 64) s += (double)p[i];
+    for (int i0 = lane; i0 < W; i0 += 64 * ZB) {
+        float v[ZB];
+#pragma unroll
+        for (int k = 0; k < ZB; ++k) {
+            const int i = i0 + 64 * k;
+            v[k] = p[i < W ? i : 0];
+        }
+#pragma unroll
+        for (int k = 0; k < ZB; ++k) s += i0 + 64 * k < W ? (double)v[k] : 0.0;
+    }
     s = wave_sum(s);
     if (lane == 0) rm[row] = s / (double)W;
 }
 
-// Column partial sums over chunks of RCH rows: colpart[c][chunk][col].
+// Column partial sums over chunks of RCH rows: colpart[c][chunk][col], the
+// rows of a chunk added in order.
 constexpr int RCH = 64;
 __global__ __launch_bounds__(NT) void col_part_kernel(const float *__restrict__ x, int H, int W,
                                                       double *__restrict__ colpart) {
@@ -78,10 +96,19 @@ __global__ __launch_bounds__(NT) void col_part_kernel(const float *__restrict__ 
     const int chunk = blockIdx.y, c = blockIdx.z;
     if (col >= W) return;
     const int nch = gridDim.y;
-    const float *p = x + (int64_t)c * H * W;
+    const float *p = x + (int64_t)c * H * W + col;
     const int r0 = chunk * RCH, r1 = min(H, r0 + RCH);
     double s = 0.0;
-    for (int r = r0; r < r1; ++r) s += (double)p[(int64_t)r * W + col];
+    for (int rb = r0; rb < r1; rb += ZB) {
+        float v[ZB];
+#pragma unroll
+        for (int k = 0; k < ZB; ++k) {
+            const int r = rb + k;
+            v[k] = p[(int64_t)(r < r1 ? r : r0) * W];
+        }
+#pragma unroll
+        for (int k = 0; k < ZB; ++k) s += rb + k < r1 ? (double)v[k] : 0.0;
+    }
     colpart[((int64_t)c * nch + chunk) * W + col] = s;
 }
 
@@ -104,35 +131,44 @@ __global__ __launch_bounds__(NT) void col_finish_kernel(const double *__restrict
     adj[(int64_t)c * W + col] = t / (double)H - mu;
 }
 
-// out = x - rm[r] - adj[col] per channel, then luma (optional).
-__global__ __launch_bounds__(NT) void zm_apply_kernel(const float *__restrict__ x, int C, int H, int W,
+// out = x - rm[r] - adj[col] per channel, then luma (LUMA, C == 3).  Block
+// (column block, row group, frame): the row index comes from the grid (no
+// division per pixel) and the row means are uniform across the block.  CC:
+// the channel count when it is 1 or 3 (loops unrolled), else 0 (runtime C).
+template <int CC, bool LUMA, bool ZM>
+__global__ __launch_bounds__(NT) void zm_apply_kernel(const float *__restrict__ x, int Cr, int H, int W,
                                                       const double *__restrict__ rm,
-                                                      const double *__restrict__ adj, int luma,
+                                                      const double *__restrict__ adj,
                                                       float *__restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int C = CC > 0 ? CC : Cr;
+    const int col = blockIdx.x * NT + threadIdx.x;
+    if (col >= W) return;
     const int64_t N = (int64_t)H * W;
-    if (i >= N) return;
-    const int f = blockIdx.y;  // frame: planes f*C .. f*C + C-1
+    const int f = blockIdx.z;  // frame: planes f*C .. f*C + C-1
     x += (int64_t)f * C * N;
-    out += (int64_t)f * (luma ? 1 : C) * N;
-    if (rm) {
+    out += (int64_t)f * (LUMA ? 1 : C) * N;
+    if (ZM) {
         rm += (int64_t)f * C * H;
         adj += (int64_t)f * C * W;
     }
-    const int r = (int)(i / W), col = (int)(i - (int64_t)r * W);
-    if (luma) {
-        double acc = 0.0;
-        for (int c = 0; c < C; ++c) {
-            double v = (double)x[c * N + i];
-            if (rm) v -= rm[(int64_t)c * H + r] + adj[(int64_t)c * W + col];
-            acc += (double)kLuma[c] * v;
-        }
-        out[i] = (float)acc;
-    } else {
-        for (int c = 0; c < C; ++c) {
-            double v = (double)x[c * N + i];
-            if (rm) v -= rm[(int64_t)c * H + r] + adj[(int64_t)c * W + col];
-            out[c * N + i] = (float)v;
+    for (int r = blockIdx.y; r < H; r += gridDim.y) {
+        const int64_t i = (int64_t)r * W + col;
+        if (LUMA) {
+            double acc = 0.0;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                double v = (double)x[c * N + i];
+                if (ZM) v -= rm[(int64_t)c * H + r] + adj[(int64_t)c * W + col];
+                acc += (double)kLuma[c] * v;
+            }
+            out[i] = (float)acc;
+        } else {
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                double v = (double)x[c * N + i];
+                if (ZM) v -= rm[(int64_t)c * H + r] + adj[(int64_t)c * W + col];
+                out[c * N + i] = (float)v;
+            }
         }
     }
 }
@@ -258,8 +294,22 @@ hipError_t launch_zero_mean(const float *in, int nf, int C, int H, int W, bool z
         col_part_kernel<<<dim3(blocks(W), nch, P), NT, 0, s>>>(in, H, W, colpart);
         col_finish_kernel<<<dim3(blocks(W), P), NT, 0, s>>>(colpart, nch, rm, H, W, adj);
     }
-    zm_apply_kernel<<<dim3(blocks((int64_t)H * W), nf), NT, 0, s>>>(in, C, H, W, zm ? rm : nullptr, adj,
-                                                                    luma ? 1 : 0, out);
+    const dim3 g(blocks(W), (unsigned)(H < 65535 ? H : 65535), (unsigned)nf);
+#define PRNU_ZM_APPLY(CC, L, Z) zm_apply_kernel<CC, L, Z><<<g, NT, 0, s>>>(in, C, H, W, rm, adj, out)
+    if (luma) {  // C == 3
+        if (zm) PRNU_ZM_APPLY(3, true, true);
+        else PRNU_ZM_APPLY(3, true, false);
+    } else if (C == 1) {
+        if (zm) PRNU_ZM_APPLY(1, false, true);
+        else PRNU_ZM_APPLY(1, false, false);
+    } else if (C == 3) {
+        if (zm) PRNU_ZM_APPLY(3, false, true);
+        else PRNU_ZM_APPLY(3, false, false);
+    } else {
+        if (zm) PRNU_ZM_APPLY(0, false, true);
+        else PRNU_ZM_APPLY(0, false, false);
+    }
+#undef PRNU_ZM_APPLY
     return hipGetLastError();
 }
 
