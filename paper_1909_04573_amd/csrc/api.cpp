@@ -255,17 +255,20 @@ void plan_pce_fast(Carver &cv, int nx, int ny, int h, int w, bool modulated, Pce
     int mx = nx > ny ? nx : ny;
     pp->spart = cv.take<double>(stats_part_doubles(mx));
     size_t dpart = pce_direct_part_doubles((int)P, h, w);
+    int64_t cpairs = P;  // pairs whose energy partials are held at once
     if (ny >= kMfmaMinFingerprints) {
         const int nbm = pce_mfma_blocks(nx, ny, h, w);
-        const size_t m = (size_t)mfma_query_chunk(nx, ny, nbm) * ny * nbm * kPceDirectStats;
+        const int qc = mfma_query_chunk(nx, ny, nbm);
+        const size_t m = (size_t)qc * ny * nbm * kPceDirectStats;
         if (m > dpart) dpart = m;
+        if ((int64_t)qc * ny > cpairs) cpairs = (int64_t)qc * ny;  // a whole query chunk, finished at once
     }
     pp->dpart = cv.take<double>(dpart);
     FftPlan ph;
     make_fft_plan(h, &ph, true);
     const int ncb = fft_cols_power_blocks(Mc, ph);
     const int nsb = ncb > pce_dot_blocks() ? ncb : pce_dot_blocks();
-    pp->cpart = cv.take<double>((size_t)P * nsb);
+    pp->cpart = cv.take<double>((size_t)cpairs * nsb);
     (void)N;
 }
 
@@ -368,15 +371,15 @@ int pce_fixed_fast(const float *X, int nx, const float *Y, int ny, int h, int w,
                                            s));
         }
     }
-    // energy of the pairs p0 .. p0+n-1 into cpart; returns the partials per pair
-    auto energy = [&](int64_t p0, int n, int *nbs) -> int {
+    // energy partials per pair: nbs doubles each
+    const int nbs = mod ? fft_cols_power_blocks(Mc, ph) : pce_dot_blocks();
+    // energy of the pairs p0 .. p0+n-1 into cp [n][nbs]
+    auto energy = [&](int64_t p0, int n, double *cp) -> int {
         if (mod) {
             PRNU_HIP(launch_rfft_rows(Y, mod, ny, (int)p0, n, nullptr, h, w, phalf, pl.tw_half, pl.tw_w, pl.Z, s));
-            PRNU_HIP(launch_fft_cols_power(pl.Z, n, h, Mc, ph, pl.tw_h, pl.Px, ny, (int)p0, nullptr, pl.cpart, s));
-            *nbs = fft_cols_power_blocks(Mc, ph);
+            PRNU_HIP(launch_fft_cols_power(pl.Z, n, h, Mc, ph, pl.tw_h, pl.Px, ny, (int)p0, nullptr, cp, s));
         } else {
-            PRNU_HIP(launch_power_dot(pl.Px, pl.Py, ny, (int)p0, n, h, Mc, pl.cpart, s));
-            *nbs = pce_dot_blocks();
+            PRNU_HIP(launch_power_dot(pl.Px, pl.Py, ny, (int)p0, n, h, Mc, cp, s));
         }
         return PRNU_OK;
     };
@@ -388,13 +391,13 @@ int pce_fixed_fast(const float *X, int nx, const float *Y, int ny, int h, int w,
             const int nq = nx - q0 < qc ? nx - q0 : qc;
             PRNU_HIP(launch_pce_direct_mfma(X, pl.xmean, Y, mod, ny, q0, nq, h, w, nbm, ncc != nullptr, pl.dpart, s));
             const int64_t pa = (int64_t)q0 * ny, pb = (int64_t)(q0 + nq) * ny;
+            // the energies of the chunk's pairs, P at a time, then one finish for all of them
             for (int64_t p0 = pa; p0 < pb; p0 += pl.P) {
                 const int n = (int)(pb - p0 < pl.P ? pb - p0 : pl.P);
-                int nbs = 0;
-                PRNU_TRY(energy(p0, n, &nbs));
-                PRNU_HIP(launch_pce_finish_fixed(pl.dpart + (p0 - pa) * nbm * kPceDirectStats, nbm, pl.cpart, nbs, n,
-                                                 h, w, nbhd, pl.xn2, ny, (int)p0, pce, ncc, peak, s));
+                PRNU_TRY(energy(p0, n, pl.cpart + (p0 - pa) * nbs));
             }
+            PRNU_HIP(launch_pce_finish_fixed(pl.dpart, nbm, pl.cpart, nbs, (int)(pb - pa), h, w, nbhd, pl.xn2, ny,
+                                             (int)pa, pce, ncc, peak, s));
         }
         return PRNU_OK;
     }
@@ -402,8 +405,7 @@ int pce_fixed_fast(const float *X, int nx, const float *Y, int ny, int h, int w,
     const int nbd = pce_direct_blocks(h, w);
     for (int64_t p0 = 0; p0 < npairs; p0 += pl.P) {
         const int n = (int)(npairs - p0 < pl.P ? npairs - p0 : pl.P);
-        int nbs = 0;
-        PRNU_TRY(energy(p0, n, &nbs));
+        PRNU_TRY(energy(p0, n, pl.cpart));
         PRNU_HIP(launch_pce_direct(X, pl.xmean, Y, mod, ny, (int)p0, n, h, w, pl.dpart, s));
         PRNU_HIP(launch_pce_finish_fixed(pl.dpart, nbd, pl.cpart, nbs, n, h, w, nbhd, pl.xn2, ny, (int)p0, pce, ncc,
                                          peak, s));

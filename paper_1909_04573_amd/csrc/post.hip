@@ -192,6 +192,29 @@ __global__ __launch_bounds__(NT) void luma_frames_kernel(const void *__restrict_
     out[(int64_t)f * npx + i] = r;
 }
 
+// Interleaved u8 RGB frames, four pixels per thread: three aligned dwords in
+// (12 bytes), one float4 out, the luma formed as in luma_frames_kernel.
+// Needs npx % 4 == 0 and 4-byte aligned frames, 16-byte aligned out.
+__global__ __launch_bounds__(NT) void luma_u8x4_kernel(const uint32_t *__restrict__ frames, int64_t npx,
+                                                       float *__restrict__ out) {
+    const int64_t q = (int64_t)blockIdx.x * NT + threadIdx.x;  // pixel quad
+    const int f = blockIdx.y;
+    if (4 * q >= npx) return;
+    const uint32_t *src = frames + ((int64_t)f * npx / 4 + q) * 3;
+    const uint32_t w0 = src[0], w1 = src[1], w2 = src[2];
+    auto byte = [&](int b) {
+        const uint32_t w = b < 4 ? w0 : b < 8 ? w1 : w2;
+        return (float)((w >> (8 * (b & 3))) & 0xffu);
+    };
+    float r[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float v0 = byte(3 * k), v1 = byte(3 * k + 1), v2 = byte(3 * k + 2);
+        r[k] = (float)((double)kLuma[0] * v0 + (double)kLuma[1] * v1 + (double)kLuma[2] * v2);
+    }
+    *reinterpret_cast<float4 *>(out + (int64_t)f * npx + 4 * q) = make_float4(r[0], r[1], r[2], r[3]);
+}
+
 // ---- per-plane sums: partials[p][blk] -------------------------------------
 constexpr int RBLK = 64;  // blocks per plane
 
@@ -318,7 +341,12 @@ hipError_t launch_luma_frames(const void *frames, int dtype, int n, int H, int W
     const int64_t npx = (int64_t)H * W;
     dim3 g(blocks(npx), (unsigned)n);
     KernelTimer kt("luma_frames", (double)n * npx * (C * (dtype == PRNU_U8 ? 1.0 : dtype == PRNU_BF16 ? 2.0 : 4.0) + 4.0), s);
-    if (dtype == PRNU_U8) luma_frames_kernel<PRNU_U8><<<g, NT, 0, s>>>(frames, npx, C, out);
+    const bool quads = dtype == PRNU_U8 && C == 3 && npx % 4 == 0 &&
+                       (reinterpret_cast<uintptr_t>(frames) & 3) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0;
+    if (quads)
+        luma_u8x4_kernel<<<dim3(blocks(npx / 4), (unsigned)n), NT, 0, s>>>(static_cast<const uint32_t *>(frames), npx,
+                                                                          out);
+    else if (dtype == PRNU_U8) luma_frames_kernel<PRNU_U8><<<g, NT, 0, s>>>(frames, npx, C, out);
     else if (dtype == PRNU_BF16) luma_frames_kernel<PRNU_BF16><<<g, NT, 0, s>>>(frames, npx, C, out);
     else luma_frames_kernel<PRNU_F32><<<g, NT, 0, s>>>(frames, npx, C, out);
     return hipGetLastError();
