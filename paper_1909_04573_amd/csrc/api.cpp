@@ -353,8 +353,9 @@ int pce_fixed_fast(const float *X, int nx, const float *Y, int ny, int h, int w,
     PRNU_HIP(launch_twiddles(h, pl.tw_h, s));
     PRNU_HIP(launch_twiddles(w, pl.tw_w, s));
     PRNU_HIP(launch_twiddles(w / 2, pl.tw_half, s));
-    // query statistics and power spectra |X^|^2 of the centred queries
-    PRNU_HIP(launch_pair_stats(X, nullptr, INT_MAX, 0, nx, N, pl.xmean, pl.xn2, pl.spart, s));
+    // query statistics (the centred norms serve the NCC only) and power
+    // spectra |X^|^2 of the centred queries
+    PRNU_HIP(launch_pair_stats(X, nullptr, INT_MAX, 0, nx, N, pl.xmean, ncc ? pl.xn2 : nullptr, pl.spart, s));
     const int64_t S = (int64_t)h * Mc;
     for (int q0 = 0; q0 < nx; q0 += pl.P) {
         const int n = nx - q0 < pl.P ? nx - q0 : pl.P;

@@ -279,7 +279,8 @@ hipError_t launch_spectral_wiener(const float2 *F, int n, int h, int w, const do
 
 // ---- PCE -------------------------------------------------------------------
 // Chunk plane p (0 <= p < n) is Y[(p0+p) % ny], times mod[(p0+p) / ny] when mod
-// is given.  Plain planes: mod = nullptr and ny > p0 + n.
+// is given.  Plain planes: mod = nullptr and ny > p0 + n.  launch_pair_stats
+// skips the centred norms when nrm2 is null.
 size_t pce_part_bytes(int npairs);
 size_t stats_part_doubles(int n);
 hipError_t launch_pair_stats(const float *Y, const float *mod, int ny, int p0, int n, int64_t N,

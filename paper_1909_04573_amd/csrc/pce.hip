@@ -59,11 +59,22 @@ __global__ __launch_bounds__(NT) void stats_partial(PairSel sel, int64_t N, cons
     const float *y, *m;
     sel.planes(N, y, m);
     const double mu = mean ? mean[blockIdx.y] : 0.0;
+    // the thread's terms in order, SB loads in flight (a term past the end is 0)
+    constexpr int SB = 8;
+    constexpr int64_t STRIDE = (int64_t)RB * NT;
     double s = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < N; i += (int64_t)RB * NT) {
-        const float v = m ? m[i] * y[i] : y[i];
-        const double d = (double)v - mu;
-        s += mean ? d * d : d;
+    for (int64_t i0 = (int64_t)blockIdx.x * NT + threadIdx.x; i0 < N; i0 += SB * STRIDE) {
+        float v[SB];
+#pragma unroll
+        for (int k = 0; k < SB; ++k) {
+            const int64_t i = i0 + k * STRIDE < N ? i0 + k * STRIDE : 0;
+            v[k] = m ? m[i] * y[i] : y[i];
+        }
+#pragma unroll
+        for (int k = 0; k < SB; ++k) {
+            const double d = i0 + k * STRIDE < N ? (double)v[k] - mu : 0.0;
+            s += mean ? d * d : d;
+        }
     }
     s = block_sum(s, sh);
     if (threadIdx.x == 0) part[(int64_t)blockIdx.y * RB + blockIdx.x] = s;
@@ -565,8 +576,10 @@ hipError_t launch_pair_stats(const float *Y, const float *mod, int ny, int p0, i
     KernelTimer kt("pair_stats", 2.0 * (double)n * N * (mod ? 8.0 : 4.0), s);
     stats_partial<<<g, NT, 0, s>>>(sel, N, nullptr, part);
     stats_finish<<<(n + 63) / 64, 64, 0, s>>>(part, n, 1.0 / (double)N, mean);
-    stats_partial<<<g, NT, 0, s>>>(sel, N, mean, part);
-    stats_finish<<<(n + 63) / 64, 64, 0, s>>>(part, n, 1.0, nrm2);
+    if (nrm2) {
+        stats_partial<<<g, NT, 0, s>>>(sel, N, mean, part);
+        stats_finish<<<(n + 63) / 64, 64, 0, s>>>(part, n, 1.0, nrm2);
+    }
     return hipGetLastError();
 }
 

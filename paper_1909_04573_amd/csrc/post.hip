@@ -225,10 +225,18 @@ __global__ __launch_bounds__(NT) void plane_partial_kernel(const float *__restri
     const int p = blockIdx.y;
     const float *xp = x + (int64_t)p * N;
     const double mu = mean ? mean[p] : 0.0;
+    // the thread's terms in order, ZB loads in flight (a term past the end is 0)
+    constexpr int64_t STRIDE = (int64_t)RBLK * NT;
     double s = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < N; i += (int64_t)RBLK * NT) {
-        const double v = (double)xp[i] - mu;
-        s += mean ? v * v : v;
+    for (int64_t i0 = (int64_t)blockIdx.x * NT + threadIdx.x; i0 < N; i0 += ZB * STRIDE) {
+        float x[ZB];
+#pragma unroll
+        for (int k = 0; k < ZB; ++k) x[k] = xp[i0 + k * STRIDE < N ? i0 + k * STRIDE : 0];
+#pragma unroll
+        for (int k = 0; k < ZB; ++k) {
+            const double v = i0 + k * STRIDE < N ? (double)x[k] - mu : 0.0;
+            s += mean ? v * v : v;
+        }
     }
     s = block_sum(s, sh);
     if (threadIdx.x == 0) part[(int64_t)p * RBLK + blockIdx.x] = s;
