@@ -297,7 +297,8 @@ def test_depth_one_equals_per_frame_residuals(dev):
 @pytest.mark.parametrize("C,H,W,flags", [
     (1, 256, 256, prnu.ZM), (1, 256, 256, prnu.ZM | prnu.WIENER), (3, 120, 160, prnu.ZM | prnu.LUMA),
     (3, 120, 160, prnu.ZM | prnu.LUMA | prnu.WIENER), (3, 96, 128, prnu.ZM), (1, 100, 75, prnu.WIENER),
-    (1, 37, 53, prnu.ZM), (3, 1080, 1920, prnu.ZM | prnu.LUMA | prnu.WIENER)])
+    (1, 37, 53, prnu.ZM), (3, 1080, 1920, prnu.ZM | prnu.LUMA | prnu.WIENER), (3, 45, 75, prnu.LUMA),
+    (3, 45, 75, 0), (1, 45, 75, 0)])
 def test_fingerprint_finalize(dev, C, H, W, flags):
     _log(f"finalize C={C} {H}x{W} flags={flags}")
     g = synth.rng(synth.CFG_TEST, 5300 + H + C)
@@ -320,7 +321,7 @@ def test_finalize_fixed_sigma(dev):
 
 # ------------------------------------------------------------------ queries
 @pytest.mark.parametrize("n,H,W,C,flags", [(3, 120, 160, 3, 7), (2, 256, 256, 1, 7), (2, 72, 104, 3, 3),
-                                           (1, 64, 64, 1, 0)])
+                                           (1, 64, 64, 1, 0), (2, 45, 75, 3, 3), (2, 45, 75, 3, 2)])
 def test_query_residual(dev, n, H, W, C, flags):
     _log(f"query n={n} {H}x{W}x{C} flags={flags}")
     fr = _frames_for(n, H, W, C, 11)
