@@ -151,7 +151,9 @@ __host__ __device__ inline void strip_layout(int tc, int hk, int wk, int64_t pla
     const int64_t base = (int64_t)ns * (planes > 0 ? planes : 1);
     const int64_t want = (int64_t)per_cu * (cus > 0 ? cus : 256);
     int64_t nseg = (want + base - 1) / base;
-    const int max_seg = hk / 64 > 1 ? hk / 64 : 1;  // segments of at least 64 rows
+    // segments of at least 16 rows: the small levels (68 and 136 rows at
+    // 1080p) need several to give the chip enough workgroups
+    const int max_seg = hk / 16 > 1 ? hk / 16 : 1;
     if (nseg > max_seg) nseg = max_seg;
     if (nseg < (hk + 503) / 504) nseg = (hk + 503) / 504;  // and at most about 500
     int S = (int)((hk + nseg - 1) / nseg);
