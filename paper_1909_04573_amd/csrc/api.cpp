@@ -239,15 +239,18 @@ void plan_pce_fast(Carver &cv, int nx, int ny, int h, int w, bool modulated, Pce
     if (P > 64) P = 64;
     if (P > npairs) P = npairs;
     int64_t Pq = P;  // planes per chunk when preparing the query / fingerprint spectra
+    FftPlan pc;  // the column transform's plan fixes the column-group layout of the half spectra
+    make_fft_plan(h, &pc, true);
+    const int64_t Sg = half_plane_elems(h, Mc, pc);
     pp->fast = true;
     pp->P = (int)P;
     pp->Mc = Mc;
     pp->tw_h = cv.take<float2>((size_t)h);
     pp->tw_w = cv.take<float2>((size_t)w);
     pp->tw_half = cv.take<float2>((size_t)(w / 2));
-    pp->Px = cv.take<float>((size_t)nx * S);
-    pp->Py = modulated ? nullptr : cv.take<float>((size_t)ny * S);
-    pp->Z = cv.take<float2>((size_t)(P > Pq ? P : Pq) * S);
+    pp->Px = cv.take<float>((size_t)nx * Sg);
+    pp->Py = modulated ? nullptr : cv.take<float>((size_t)ny * Sg);
+    pp->Z = cv.take<float2>((size_t)(P > Pq ? P : Pq) * Sg);
     pp->xmean = cv.take<double>((size_t)nx);
     pp->xn2 = cv.take<double>((size_t)nx);
     pp->ymean = cv.take<double>((size_t)ny);
@@ -347,27 +350,30 @@ int pce_fixed_fast(const float *X, int nx, const float *Y, int ny, int h, int w,
                    double *pce, double *ncc, int32_t *peak, const PcePlan &pl, hipStream_t s) {
     const int64_t N = (int64_t)h * w;
     const int Mc = pl.Mc;
+    // the half-length row transforms take as many rows per workgroup as the
+    // column transforms take columns (up to twice the default): their stores
+    // into the column-group layout then fill whole cache lines
     FftPlan ph, phalf;
     make_fft_plan(h, &ph, true);
-    make_fft_plan(w / 2, &phalf);
+    make_fft_plan(w / 2, &phalf, true);
     PRNU_HIP(launch_twiddles(h, pl.tw_h, s));
     PRNU_HIP(launch_twiddles(w, pl.tw_w, s));
     PRNU_HIP(launch_twiddles(w / 2, pl.tw_half, s));
     // query statistics (the centred norms serve the NCC only) and power
     // spectra |X^|^2 of the centred queries
     PRNU_HIP(launch_pair_stats(X, nullptr, INT_MAX, 0, nx, N, pl.xmean, ncc ? pl.xn2 : nullptr, pl.spart, s));
-    const int64_t S = (int64_t)h * Mc;
+    const int64_t S = half_plane_elems(h, Mc, ph);  // column-group layout of ph
     for (int q0 = 0; q0 < nx; q0 += pl.P) {
         const int n = nx - q0 < pl.P ? nx - q0 : pl.P;
         PRNU_HIP(launch_rfft_rows(X, nullptr, INT_MAX, q0, n, pl.xmean + q0, h, w, phalf, pl.tw_half, pl.tw_w,
-                                  pl.Z, s));
+                                  ph, pl.Z, s));
         PRNU_HIP(launch_fft_cols_power(pl.Z, n, h, Mc, ph, pl.tw_h, nullptr, 1, 0, pl.Px + q0 * S, nullptr, s));
     }
     if (!mod) {
         for (int j0 = 0; j0 < ny; j0 += pl.P) {
             const int n = ny - j0 < pl.P ? ny - j0 : pl.P;
             PRNU_HIP(launch_rfft_rows(Y, nullptr, INT_MAX, j0, n, nullptr, h, w, phalf, pl.tw_half, pl.tw_w,
-                                      pl.Z, s));
+                                      ph, pl.Z, s));
             PRNU_HIP(launch_fft_cols_power(pl.Z, n, h, Mc, ph, pl.tw_h, nullptr, 1, 0, pl.Py + j0 * S, nullptr,
                                            s));
         }
@@ -377,10 +383,11 @@ int pce_fixed_fast(const float *X, int nx, const float *Y, int ny, int h, int w,
     // energy of the pairs p0 .. p0+n-1 into cp [n][nbs]
     auto energy = [&](int64_t p0, int n, double *cp) -> int {
         if (mod) {
-            PRNU_HIP(launch_rfft_rows(Y, mod, ny, (int)p0, n, nullptr, h, w, phalf, pl.tw_half, pl.tw_w, pl.Z, s));
+            PRNU_HIP(launch_rfft_rows(Y, mod, ny, (int)p0, n, nullptr, h, w, phalf, pl.tw_half, pl.tw_w, ph, pl.Z,
+                                      s));
             PRNU_HIP(launch_fft_cols_power(pl.Z, n, h, Mc, ph, pl.tw_h, pl.Px, ny, (int)p0, nullptr, cp, s));
         } else {
-            PRNU_HIP(launch_power_dot(pl.Px, pl.Py, ny, (int)p0, n, h, Mc, cp, s));
+            PRNU_HIP(launch_power_dot(pl.Px, pl.Py, ny, (int)p0, n, h, Mc, ph.lvec, cp, s));
         }
         return PRNU_OK;
     };

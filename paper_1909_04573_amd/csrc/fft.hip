@@ -23,6 +23,13 @@
 //   fft_cols_power  column transform of half spectra; the epilogue either
 //                   stores |Y_k|^2 or reduces sum_k |X_k|^2 |Y_k|^2 over the
 //                   full (Hermitian) spectrum without the DC bin
+//
+// Half spectra and power tables of h rows x Mc bins are held in column
+// groups of G = 2^lg bins, G being the column transform's vectors per
+// workgroup: bin (n, c) at ((c >> lg) h + n) G + (c & (G - 1)), a plane of
+// h * ceil(Mc / G) * G elements (bins past Mc are padding, never read as
+// values).  A column workgroup then stages one contiguous block instead of
+// G adjacent values from each of h rows.
 
 #include <cmath>
 
@@ -92,7 +99,8 @@ template <int FN, int FV, bool MOD>
 __global__ __launch_bounds__(FNT) void rfft_rows(const float *__restrict__ Y, const float *__restrict__ mod,
                                                  int ny, int p0, const double *__restrict__ mean, int h,
                                                  int wrt, FftPlan plan, const float2 *__restrict__ tw_half,
-                                                 const float2 *__restrict__ tw_full, float2 *__restrict__ out) {
+                                                 const float2 *__restrict__ tw_full, int lg,
+                                                 float2 *__restrict__ out) {
     extern __shared__ float2 smem[];
     const int w = FN ? 2 * FN : wrt;
     const int M = w / 2;
@@ -130,8 +138,10 @@ __global__ __launch_bounds__(FNT) void rfft_rows(const float *__restrict__ Y, co
                                     [&](int e, float2 z) { b0[e] = z; });
     __syncthreads();
     const float2 *res = fft_run<FN, FV>(b0, b1, plan, twh, -1.f);
-    // Split the even/odd-sample spectra: Y[k] = E[k] + W_w^k O[k].
-    float2 *op = out + (int64_t)blockIdx.y * h * (M + 1);
+    // Split the even/odd-sample spectra: Y[k] = E[k] + W_w^k O[k], stored in
+    // column groups of 2^lg bins.
+    const int G = 1 << lg;
+    float2 *op = out + (int64_t)blockIdx.y * h * ((M + G) >> lg << lg);
     const int tot2 = (M + 1) * nvec;
     for (int e = threadIdx.x; e < tot2; e += FNT) {
         const int v = e % nvec, k = e / nvec;
@@ -142,7 +152,7 @@ __global__ __launch_bounds__(FNT) void rfft_rows(const float *__restrict__ Y, co
         const float2 E = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
         const float2 O = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
         const float2 tO = cmul(twf[k], O);  // exp(-2 pi i k / w), k <= w/2
-        op[(int64_t)(r0 + v) * (M + 1) + k] = make_float2(E.x + tO.x, E.y + tO.y);
+        op[((int64_t)(k >> lg) * h + r0 + v) * G + (k & (G - 1))] = make_float2(E.x + tO.x, E.y + tO.y);
     }
 }
 
@@ -162,16 +172,18 @@ __global__ __launch_bounds__(FNT) void fft_cols_power(const float2 *__restrict__
     const int h = FN ? FN : hrt;
     const int nvec = FN ? FV : plan.nvec, lvec = FN ? ilog2c(FV) : plan.lvec;
     const int c0 = blk * nvec;
-    const int64_t plane = (int64_t)h * Mc;
-    const float2 *sp = S + (int64_t)pl * plane;
     const int tot = h * nvec;
+    // column groups of nvec bins: this workgroup's block is contiguous
+    const int64_t plane = (int64_t)gridDim.x * tot;
+    const float2 *sp = S + (int64_t)pl * plane + (int64_t)blk * tot;
     float2 *b0 = smem, *b1 = smem + tot, *twl = FN ? smem + tot : smem + 2 * tot;
     staged_copy<FNT, 4, float2>(threadIdx.x, h, [&](int e) { return tw[e]; }, [&](int e, float2 z) { twl[e] = z; });
     // column groups inside the half spectrum (all but the last) stage without a
-    // bounds select, which the compiler would turn into a branch around the loads
+    // bounds select, which the compiler would turn into a branch around the
+    // loads; the last group's padding bins are read and replaced by 0
     auto col_elem = [&](int e, bool in) {
-        const int v = e & (nvec - 1), n = e >> lvec;
-        const float2 z = sp[(int64_t)n * Mc + min(c0 + v, Mc - 1)];
+        const int v = e & (nvec - 1);
+        const float2 z = sp[e];
         return in || c0 + v < Mc ? z : make_float2(0.f, 0.f);
     };
     if (c0 + nvec <= Mc)
@@ -181,7 +193,7 @@ __global__ __launch_bounds__(FNT) void fft_cols_power(const float2 *__restrict__
         staged_copy<FNT, 8, float2>(threadIdx.x, tot, [&](int e) { return col_elem(e, false); },
                                     [&](int e, float2 z) { b0[e] = z; });
     const int pid = p0 + pl;
-    const float *pq = DOT ? Px + (int64_t)(pid / ny) * plane : nullptr;
+    const float *pq = DOT ? Px + (int64_t)(pid / ny) * plane + (int64_t)blk * tot : nullptr;
     // With a compile-time length the power weights of this thread's elements
     // are loaded now, so they arrive while the transform runs.
     constexpr int PXN = (DOT && FN) ? (FN * FV + FNT - 1) / FNT : 1;
@@ -190,9 +202,8 @@ __global__ __launch_bounds__(FNT) void fft_cols_power(const float2 *__restrict__
 #pragma unroll
         for (int k = 0; k < PXN; ++k) {
             const int e = threadIdx.x + k * FNT;
-            const int v = e & (nvec - 1), n = e >> lvec;
-            // clamped to a valid element (read only where e and the column are in range)
-            pxr[k] = pq[(int64_t)min(n, h - 1) * Mc + min(c0 + v, Mc - 1)];
+            // clamped to the block (used only where e and the column are in range)
+            pxr[k] = pq[min(e, tot - 1)];
         }
     }
     __syncthreads();
@@ -219,8 +230,7 @@ __global__ __launch_bounds__(FNT) void fft_cols_power(const float2 *__restrict__
 #pragma unroll
             for (int k = 0; k < KB; ++k) {
                 const int e = e0 + k * FNT;
-                const int v = e & (nvec - 1), n = e >> lvec;
-                px[k] = (e < tot && c0 + v < Mc) ? pq[(int64_t)n * Mc + c0 + v] : 0.f;
+                px[k] = pq[e < tot ? e : 0];  // read where e and the column are in range
             }
         }
 #pragma unroll
@@ -236,7 +246,7 @@ __global__ __launch_bounds__(FNT) void fft_cols_power(const float2 *__restrict__
                 const float wgt = (col == 0 || col == Mc - 1) ? 1.f : 2.f;
                 acc += (double)(wgt * pw) * (double)px[k];
             } else {
-                Pout[(int64_t)pl * plane + (int64_t)n * Mc + col] = pw;
+                Pout[(int64_t)pl * plane + (int64_t)blk * tot + e] = pw;
             }
         }
     }
@@ -317,7 +327,7 @@ static Fft1dKernel pick_fft_1d(const FftPlan &p) {
 static RowsKernel pick_rfft_rows(const FftPlan &p, bool mod) {
 #define PRNU_CASE(N, V) \
     if (p.n == N && p.nvec == V) return mod ? rfft_rows<N, V, true> : rfft_rows<N, V, false>;
-    PRNU_CASE(960, 2) PRNU_CASE(640, 4) PRNU_CASE(1920, 1) PRNU_CASE(256, 8)
+    PRNU_CASE(960, 4) PRNU_CASE(640, 8) PRNU_CASE(1920, 2) PRNU_CASE(256, 16)
 #undef PRNU_CASE
     return mod ? rfft_rows<0, 0, true> : rfft_rows<0, 0, false>;
 }
@@ -371,7 +381,7 @@ hipError_t launch_fft2(float2 *data, int batch, int h, int w, const FftPlan &ph,
 
 hipError_t launch_rfft_rows(const float *Y, const float *mod, int ny, int p0, int n, const double *mean,
                             int h, int w, const FftPlan &phalf, const float2 *tw_half, const float2 *tw_full,
-                            float2 *out, hipStream_t s) {
+                            const FftPlan &pcol, float2 *out, hipStream_t s) {
     const double bytes = (double)n * h * ((mod ? 8.0 : 4.0) * w + 8.0 * (w / 2 + 1));
     KernelTimer kt("rfft_rows", bytes, s);
     dim3 g((unsigned)((h + phalf.nvec - 1) / phalf.nvec), (unsigned)n);
@@ -380,11 +390,14 @@ hipError_t launch_rfft_rows(const float *Y, const float *mod, int ny, int p0, in
         fft_lds_bytes(phalf, 2 * phalf.n + 1, k != rfft_rows<0, 0, false> && k != rfft_rows<0, 0, true>);
     const hipError_t e = allow_lds(k, lds);
     if (e != hipSuccess) return e;
-    k<<<g, FNT, lds, s>>>(Y, mod, ny, p0, mean, h, w, phalf, tw_half, tw_full, out);
+    k<<<g, FNT, lds, s>>>(Y, mod, ny, p0, mean, h, w, phalf, tw_half, tw_full, pcol.lvec, out);
     return hipGetLastError();
 }
 
 int fft_cols_power_blocks(int Mc, const FftPlan &ph) { return (Mc + ph.nvec - 1) / ph.nvec; }
+int64_t half_plane_elems(int h, int Mc, const FftPlan &ph) {
+    return (int64_t)h * fft_cols_power_blocks(Mc, ph) * ph.nvec;
+}
 
 hipError_t launch_fft_cols_power(const float2 *S, int n, int h, int Mc, const FftPlan &ph, const float2 *tw_h,
                                  const float *Px, int ny, int p0, float *Pout, double *part, hipStream_t s) {

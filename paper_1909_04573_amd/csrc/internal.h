@@ -243,16 +243,21 @@ hipError_t launch_fft2(float2 *data, int batch, int h, int w, const FftPlan &ph,
                        const FftPlan &pw, const float2 *tw_h, const float2 *tw_w, int dir,
                        hipStream_t s, const float *rin = nullptr, float *rout = nullptr, float rscale = 1.f);
 
-// Real rows -> half spectra [n][h][w/2+1] (w even, phalf planned for w/2).
+// Real rows -> half spectra of h rows x w/2+1 bins (w even, phalf planned for
+// w/2), n planes of half_plane_elems(h, w/2+1, pcol) in the column-group
+// layout of the column plan pcol (groups of pcol.nvec bins; see fft.hip).
 // Plane p is Y[(p0+p) % ny], times mod[(p0+p) / ny] when mod is given, minus
 // mean[p] when mean is given.  tw_half: table for w/2; tw_full: table for w.
 hipError_t launch_rfft_rows(const float *Y, const float *mod, int ny, int p0, int n, const double *mean,
                             int h, int w, const FftPlan &phalf, const float2 *tw_half, const float2 *tw_full,
-                            float2 *out, hipStream_t s);
-// Column transforms of half spectra S [n][h][Mc]: with Px, reduce
-// sum wgt*Px[(p0+p)/ny]*|S|^2 (DC excluded) into part[p][blocks]; else
-// store |S|^2 into Pout [n][h][Mc].
+                            const FftPlan &pcol, float2 *out, hipStream_t s);
+// Column transforms of half spectra S (n planes in the column-group layout
+// of ph): with Px, reduce sum wgt*Px[(p0+p)/ny]*|S|^2 (DC excluded) into
+// part[p][blocks]; else store |S|^2 into Pout.  Px and Pout have the same
+// layout as S.
 int fft_cols_power_blocks(int Mc, const FftPlan &ph);
+// Elements of one half spectrum or power table in the column-group layout.
+int64_t half_plane_elems(int h, int Mc, const FftPlan &ph);
 hipError_t launch_fft_cols_power(const float2 *S, int n, int h, int Mc, const FftPlan &ph, const float2 *tw_h,
                                  const float *Px, int ny, int p0, float *Pout, double *part, hipStream_t s);
 
@@ -303,7 +308,8 @@ size_t pce_direct_part_doubles(int npairs, int h, int w);
 int pce_dot_blocks();
 hipError_t launch_pce_direct(const float *X, const double *xmean, const float *Y, const float *mod, int ny,
                              int p0, int n, int h, int w, double *part, hipStream_t s);
-hipError_t launch_power_dot(const float *Px, const float *Py, int ny, int p0, int n, int h, int Mc,
+// Px, Py in the column-group layout of groups of 2^lg bins.
+hipError_t launch_power_dot(const float *Px, const float *Py, int ny, int p0, int n, int h, int Mc, int lg,
                             double *part, hipStream_t s);
 // Doubles per (pair, block) of the direct-sum partials: 121 shifts, sum y,
 // sum y^2, sum xc.

@@ -500,19 +500,24 @@ __global__ __launch_bounds__(NT) void pce_direct_mfma(const float *__restrict__ 
     }
 }
 
-// part[p][blk] = sum over the half spectrum of wgt * Px[q] * Py[j] (DC excluded).
+// part[p][blk] = sum over the half spectrum of wgt * Px[q] * Py[j] (DC excluded),
+// the bins taken in row-major order; Px and Py are held in column groups of
+// 2^lg bins (planes of h * ceil(Mc / 2^lg) * 2^lg).
 __global__ __launch_bounds__(NT) void power_dot(const float *__restrict__ Px, const float *__restrict__ Py,
-                                                int ny, int p0, int h, int Mc, double *__restrict__ part) {
+                                                int ny, int p0, int h, int Mc, int lg, double *__restrict__ part) {
     __shared__ double sh[NT / 64];
     const int pid = p0 + (int)blockIdx.y;
     const int64_t M = (int64_t)h * Mc;
-    const float *a = Px + (int64_t)(pid / ny) * M;
-    const float *b = Py + (int64_t)(pid % ny) * M;
+    const int G = 1 << lg;
+    const int64_t Mg = (int64_t)h * ((Mc + G - 1) >> lg << lg);
+    const float *a = Px + (int64_t)(pid / ny) * Mg;
+    const float *b = Py + (int64_t)(pid % ny) * Mg;
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < M; i += (int64_t)gridDim.x * NT) {
-        const int col = (int)(i % Mc);
+        const int n = (int)(i / Mc), col = (int)(i - (int64_t)n * Mc);
+        const int64_t o = ((int64_t)(col >> lg) * h + n) * G + (col & (G - 1));
         const float wgt = (col == 0 || col == Mc - 1) ? 1.f : 2.f;
-        acc += (i == 0) ? 0.0 : (double)(wgt * a[i] * b[i]);
+        acc += (i == 0) ? 0.0 : (double)(wgt * a[o] * b[o]);
     }
     acc = block_sum(acc, sh);
     if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = acc;
@@ -662,10 +667,10 @@ hipError_t launch_pce_direct_mfma(const float *X, const double *xmean, const flo
     return hipGetLastError();
 }
 
-hipError_t launch_power_dot(const float *Px, const float *Py, int ny, int p0, int n, int h, int Mc,
+hipError_t launch_power_dot(const float *Px, const float *Py, int ny, int p0, int n, int h, int Mc, int lg,
                             double *part, hipStream_t s) {
     KernelTimer kt("power_dot", (double)n * h * Mc * 8.0, s);
-    power_dot<<<dim3((unsigned)pce_dot_blocks(), (unsigned)n), NT, 0, s>>>(Px, Py, ny, p0, h, Mc, part);
+    power_dot<<<dim3((unsigned)pce_dot_blocks(), (unsigned)n), NT, 0, s>>>(Px, Py, ny, p0, h, Mc, lg, part);
     return hipGetLastError();
 }
 
