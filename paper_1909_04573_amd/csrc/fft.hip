@@ -105,12 +105,16 @@ __global__ __launch_bounds__(FNT) void rfft_rows(const float *__restrict__ Y, co
     const int w = FN ? 2 * FN : wrt;
     const int M = w / 2;
     const int nvec = FN ? FV : plan.nvec, lvec = FN ? ilog2c(FV) : plan.lvec;
-    const int r0 = blockIdx.x * nvec;
-    const int pid = p0 + (int)blockIdx.y;
+    // the pairs of one row block run together on one XCD: the fingerprint and
+    // modulation rows they share are fetched into its L2 once
+    int rb, pl;
+    grid_plane_major(rb, pl);
+    const int r0 = rb * nvec;
+    const int pid = p0 + pl;
     const int64_t N = (int64_t)h * w;
     const float *yp = Y + (int64_t)(pid % ny) * N;
     const float *mp = MOD ? mod + (int64_t)(pid / ny) * N : nullptr;
-    const float mu = mean ? (float)mean[blockIdx.y] : 0.f;
+    const float mu = mean ? (float)mean[pl] : 0.f;
     const int tot = M * nvec;
     float2 *b0 = smem, *b1 = smem + tot, *twh = FN ? smem + tot : smem + 2 * tot, *twf = twh + M;
     staged_copy<FNT, 4, float2>(threadIdx.x, M, [&](int e) { return tw_half[e]; },
@@ -141,7 +145,7 @@ __global__ __launch_bounds__(FNT) void rfft_rows(const float *__restrict__ Y, co
     // Split the even/odd-sample spectra: Y[k] = E[k] + W_w^k O[k], stored in
     // column groups of 2^lg bins.
     const int G = 1 << lg;
-    float2 *op = out + (int64_t)blockIdx.y * h * ((M + G) >> lg << lg);
+    float2 *op = out + (int64_t)pl * h * ((M + G) >> lg << lg);
     const int tot2 = (M + 1) * nvec;
     for (int e = threadIdx.x; e < tot2; e += FNT) {
         const int v = e % nvec, k = e / nvec;
@@ -156,10 +160,10 @@ __global__ __launch_bounds__(FNT) void rfft_rows(const float *__restrict__ Y, co
     }
 }
 
-// Column transforms of half spectra [p][h][Mc] (Mc = w/2 + 1).
+// Column transforms of half spectra (h rows x Mc = w/2 + 1 bins, column groups).
 //   POWER_STORE: Pout[p][k] = |S_k|^2 (DC bin 0)
-//   POWER_DOT:   part[p][blockIdx.x] = sum_k wgt(k) Px[q][k] |S_k|^2 over the
-//                strip (wgt = 1 on the first and the Nyquist column, 2 between;
+//   POWER_DOT:   part[p][b] = sum_k wgt(k) Px[q][k] |S_k|^2 over column group b
+//                (wgt = 1 on the first and the Nyquist column, 2 between;
 //                DC bin excluded), q = (p0 + p) / ny.
 template <bool DOT, int FN, int FV>
 __global__ __launch_bounds__(FNT) void fft_cols_power(const float2 *__restrict__ S, int hrt, int Mc, FftPlan plan,
@@ -168,7 +172,9 @@ __global__ __launch_bounds__(FNT) void fft_cols_power(const float2 *__restrict__
                                                       double *__restrict__ part) {
     extern __shared__ float2 smem[];
     int blk, pl;
-    grid_tile(blk, pl);  // neighbouring column groups on one XCD: they share cache lines
+    // the pairs of one column group run together on one XCD: a query's power
+    // weights of the group are fetched into its L2 once for all its pairs
+    grid_plane_major(blk, pl);
     const int h = FN ? FN : hrt;
     const int nvec = FN ? FV : plan.nvec, lvec = FN ? ilog2c(FV) : plan.lvec;
     const int c0 = blk * nvec;

@@ -55,6 +55,15 @@ __device__ __forceinline__ void grid_tile(int &tile, int &plane) {
     plane = v / tiles;
     tile = v - plane * tiles;
 }
+// Planes fastest: the planes of one tile are consecutive virtual blocks (same
+// XCD, close in time), for planes that read shared inputs at the same place
+// (a query's modulation and a fingerprint, each used by several pairs).
+__device__ __forceinline__ void grid_plane_major(int &tile, int &plane) {
+    const int planes = (int)gridDim.y;
+    const int v = xcd_order((int)(blockIdx.x + blockIdx.y * gridDim.x), (int)(gridDim.x * gridDim.y));
+    tile = v / planes;
+    plane = v - tile * planes;
+}
 // The same for planes that are the C interleaved channels of frames: the C
 // channels of one tile are consecutive virtual blocks (same XCD, close in
 // time), so the frame bytes they share come from one L2 fill.
