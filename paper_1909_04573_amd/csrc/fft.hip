@@ -93,8 +93,8 @@ __global__ __launch_bounds__(FNT) void fft_1d(float2 *__restrict__ data, int Nrt
 }
 
 // Real rows -> half spectra.  Plane p of the batch is y = Y[(p0+p) % ny]
-// (times mod[(p0+p) / ny] if given, minus `mean[p]` if given).  Row r, bins
-// k = 0 .. w/2 at out[p][r][k] (row stride w/2 + 1).
+// (times mod[(p0+p) / ny] if given, minus `mean[p]` if given); its bins
+// k = 0 .. w/2 go to out[p] in column groups of 2^lg bins.
 template <int FN, int FV, bool MOD>
 __global__ __launch_bounds__(FNT) void rfft_rows(const float *__restrict__ Y, const float *__restrict__ mod,
                                                  int ny, int p0, const double *__restrict__ mean, int h,
