@@ -326,9 +326,9 @@ __global__ __launch_bounds__(NT) void pce_direct(const float *__restrict__ X, co
 // the device): A[i][k] and B[k][n] at lane 16 k + i / 16 k + n,
 // C[4 (l / 16) + r][l % 16] in slot r of lane l.  Each tile's fp32 products
 // are added to FP64 accumulators; sum y^2 and sum xc are plain FP64 sums.
-// The all-ones row reads a block of ones kept in LDS below the query tile
-// (1 x mod is mod exactly), so the loop has no per-lane select; sum y^2,
-// which only the NCC needs, is formed only when SYY is set.
+// The all-ones row reads a block of ones kept in LDS below the query tile,
+// so the loop has no per-lane select; sum y^2, which only the NCC needs, is
+// formed only when SYY is set.
 constexpr int MTY = 8, MTX = 64;                              // pixel tile
 constexpr int MXH = MTY + 2 * DRAD, MXW = MTX + 2 * DRAD, MXWS = 76;  // query tile with the shift halo
 constexpr int MNJ = 16, MNS = 8;                              // fingerprints, shift blocks of 16
@@ -357,8 +357,9 @@ __global__ __launch_bounds__(NT) void pce_direct_mfma(const float *__restrict__ 
     const PRNU_GLOBAL float *mp = mod ? gmem(mod) + (int64_t)q * N : nullptr;
     // A operand: row i = lane % 16 of shift block sb is shift m = 16 sb + i (rows past the
     // ones row read shift (0,0) and are dropped), column k = lane / 16 is pixel k of the quad.
-    // The modulation belongs to the pixel t, so it scales A: xc(t + s) * mod(t); the
-    // fingerprint tile (B) is then the same for every query.
+    // The modulation belongs to the pixel t, so it scales B: y(t) = mod(t) * K(t), one
+    // multiply per lane and pixel quad shared by the lane's shift blocks (the pixel
+    // of A's column and of B's row is the same lane / 16).
     // Wave wv computes shift blocks SBW wv .. SBW wv + SBW - 1 over all the
     // tile's pixels, so it holds complete sums for its shifts (no cross-wave
     // reduction, a quarter of the accumulators).
@@ -447,18 +448,13 @@ __global__ __launch_bounds__(NT) void pce_direct_mfma(const float *__restrict__ 
 #pragma unroll 16
         for (int g = 0; g < MTY * 16; ++g) {
             const int r = g >> 4, c4 = (g & 15) * 4;
-            const float b = ys[boff + r * MTX + c4];
             const float m = ms[r * MTX + c4 + (lane >> 4)];
-            if (SYY && (r & 3) == wv) {
-                const float mb = m * b;
-                ssq = fmaf(mb, mb, ssq);
-            }
+            const float b = ys[boff + r * MTX + c4] * m;  // the modulated fingerprint y
+            if (SYY && (r & 3) == wv) ssq = fmaf(b, b, ssq);
             const int xb = r * MXWS + c4;
 #pragma unroll
-            for (int i = 0; i < SBW; ++i) {
-                const float a = xs[xb + aoff[i]] * m;
-                cacc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, cacc[i], 0, 0, 0);
-            }
+            for (int i = 0; i < SBW; ++i)
+                cacc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[xb + aoff[i]], b, cacc[i], 0, 0, 0);
         }
         syy += (double)ssq;
 #pragma unroll
