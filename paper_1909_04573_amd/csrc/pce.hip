@@ -357,9 +357,8 @@ __global__ __launch_bounds__(NT) void pce_direct_mfma(const float *__restrict__ 
     const PRNU_GLOBAL float *mp = mod ? gmem(mod) + (int64_t)q * N : nullptr;
     // A operand: row i = lane % 16 of shift block sb is shift m = 16 sb + i (rows past the
     // ones row read shift (0,0) and are dropped), column k = lane / 16 is pixel k of the quad.
-    // The modulation belongs to the pixel t, so it scales B: y(t) = mod(t) * K(t), one
-    // multiply per lane and pixel quad shared by the lane's shift blocks (the pixel
-    // of A's column and of B's row is the same lane / 16).
+    // The modulation belongs to the pixel t, so it scales B: y(t) = mod(t) * K(t),
+    // formed once per tile pixel and fingerprint when the tile is staged.
     // Wave wv computes shift blocks SBW wv .. SBW wv + SBW - 1 over all the
     // tile's pixels, so it holds complete sums for its shifts (no cross-wave
     // reduction, a quarter of the accumulators).
@@ -423,8 +422,13 @@ __global__ __launch_bounds__(NT) void pce_direct_mfma(const float *__restrict__ 
         }
 #pragma unroll
         for (int k = 0; k < KM; ++k) ms[tid + k * NT] = rm[k];
+        __syncthreads();  // the modulation of every tile pixel is in LDS
+        // the fingerprint tile goes to LDS already modulated: y = mod * K
 #pragma unroll
-        for (int k = 0; k < KY; ++k) ys[sn * MYS + (k >> 2) * MTX + sc + 16 * (k & 3)] = ry[k];
+        for (int k = 0; k < KY; ++k) {
+            const int o = (k >> 2) * MTX + sc + 16 * (k & 3);
+            ys[sn * MYS + o] = ry[k] * ms[o];
+        }
     };
 
     if (blk < ntiles) fetch(blk);
@@ -448,8 +452,7 @@ __global__ __launch_bounds__(NT) void pce_direct_mfma(const float *__restrict__ 
 #pragma unroll 16
         for (int g = 0; g < MTY * 16; ++g) {
             const int r = g >> 4, c4 = (g & 15) * 4;
-            const float m = ms[r * MTX + c4 + (lane >> 4)];
-            const float b = ys[boff + r * MTX + c4] * m;  // the modulated fingerprint y
+            const float b = ys[boff + r * MTX + c4];  // the modulated fingerprint y
             if (SYY && (r & 3) == wv) ssq = fmaf(b, b, ssq);
             const int xb = r * MXWS + c4;
 #pragma unroll
