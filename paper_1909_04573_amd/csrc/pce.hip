@@ -330,7 +330,9 @@ __global__ __launch_bounds__(NT) void pce_direct(const float *__restrict__ X, co
 // so the loop has no per-lane select; sum y^2, which only the NCC needs, is
 // formed only when SYY is set.
 constexpr int MTY = 8, MTX = 64;                              // pixel tile
-constexpr int MXH = MTY + 2 * DRAD, MXW = MTX + 2 * DRAD, MXWS = 76;  // query tile with the shift halo
+// query tile with the shift halo; row stride 16 banks (mod 64): the 16 shifts
+// of a block span at most three rows, whose reads then fall in disjoint banks
+constexpr int MXH = MTY + 2 * DRAD, MXW = MTX + 2 * DRAD, MXWS = 80;
 constexpr int MNJ = 16, MNS = 8;                              // fingerprints, shift blocks of 16
 constexpr int MYS = MTY * MTX + 4;                            // fingerprint stride in LDS (bank offset 4)
 constexpr int MONES = DNS * DNS;                              // row 121: all ones
@@ -367,7 +369,8 @@ __global__ __launch_bounds__(NT) void pce_direct_mfma(const float *__restrict__ 
     for (int i = 0; i < SBW; ++i) {
         const int m = 16 * (SBW * wv + i) + (lane & 15);
         const int mm = m < DNS * DNS ? m : (DNS * DNS) / 2;
-        aoff[i] = m == MONES ? MXH * MXWS + (lane >> 4) : (mm / DNS) * MXWS + (mm % DNS) + (lane >> 4);
+        // the ones row reads 16 columns in, in banks no shift of its block uses
+        aoff[i] = m == MONES ? MXH * MXWS + 16 + (lane >> 4) : (mm / DNS) * MXWS + (mm % DNS) + (lane >> 4);
     }
     // the ones (tile staging writes only the rows above them)
     for (int e = tid; e < MTY * MXWS; e += NT) xs[MXH * MXWS + e] = 1.f;
