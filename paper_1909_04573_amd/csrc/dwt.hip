@@ -831,14 +831,16 @@ __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, floa
                                : (const void *)(a.means + (int64_t)(fr * C + c) * npx);
         return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)plane_bytes, 0x00020000);
     };
-    auto load_i = [&](int fr, float (&Iv)[ITEMS][4]) {
+    // u8 intensities stay integers: I^2 is then summed exactly in 32 bits
+    using IT = typename std::conditional<U8I, unsigned, float>::type;
+    auto load_i = [&](int fr, IT (&Iv)[ITEMS][4]) {
         const __amdgpu_buffer_rsrc_t rs = i_rsrc(fr);
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k)
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 if constexpr (U8I)
-                    Iv[k][u] = (float)__builtin_amdgcn_raw_buffer_load_b8(rs, ioff[k][u], 0, 0);
+                    Iv[k][u] = __builtin_amdgcn_raw_buffer_load_b8(rs, ioff[k][u], 0, 0);
                 else
                     Iv[k][u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, ioff[k][u], 0, 0));
             }
@@ -846,6 +848,10 @@ __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, floa
     double sa[ITEMS][4], sbb[ITEMS][4];  // ACC_F64 partials
     float ka[ITEMS][4], kc_[ITEMS][4];   // float partial of A (+ compensation for KAHAN)
     float kb[ITEMS][4], kbc[ITEMS][4];   // ... and of B
+    // u8 intensities: sum I^2 of the batch as an integer.  With at most 32
+    // frames it stays below 2^24, so every accumulator mode's sum of these
+    // exact squares equals it exactly (the compensation stays 0).
+    unsigned iq[ITEMS][4];
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k)
 #pragma unroll
@@ -853,6 +859,7 @@ __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, floa
             sa[k][u] = 0.0;
             sbb[k][u] = 0.0;
             ka[k][u] = kc_[k][u] = kb[k][u] = kbc[k][u] = 0.f;
+            iq[k][u] = 0u;
         }
     // subband loads and intensities of frame fr + 1 are in flight while frame fr is transformed
     __syncthreads();  // maps ready
@@ -860,10 +867,10 @@ __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, floa
     st.offsets(tid, a.wk, rmap, cmap);
     const int64_t band = (int64_t)a.hk * a.wk;
     st.fetch(a.lvl + (int64_t)c * 4 * band, band, a.zero_approx != 0);
-    float In[ITEMS][4];
+    IT In[ITEMS][4];
     load_i(0, In);
     for (int fr = 0; fr < a.nb; ++fr) {
-        float Iv[ITEMS][4];
+        IT Iv[ITEMS][4];
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k)
 #pragma unroll
@@ -889,27 +896,42 @@ __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, floa
             inv_row_quad<TAPS, TT>(lo1, hi1, n, mq, f, x);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const float I = Iv[k][u];
+                if (U8I) iq[k][u] += Iv[k][u] * Iv[k][u];  // at most 255^2 a frame, 24-bit products
                 if (ACC == PRNU_ACC_KAHAN_F32) {
                     // two-sum accumulation of W*I and I*I
-                    const float pa = x[u] * I, pb = I * I;
+                    const float I = (float)Iv[k][u];
+                    const float pa = x[u] * I;
                     float t = ka[k][u] + pa;
                     float z = t - ka[k][u];
                     kc_[k][u] += (ka[k][u] - (t - z)) + (pa - z);
                     ka[k][u] = t;
-                    t = kb[k][u] + pb;
-                    z = t - kb[k][u];
-                    kbc[k][u] += (kb[k][u] - (t - z)) + (pb - z);
-                    kb[k][u] = t;
+                    if (!U8I) {
+                        const float pb = I * I;
+                        t = kb[k][u] + pb;
+                        z = t - kb[k][u];
+                        kbc[k][u] += (kb[k][u] - (t - z)) + (pb - z);
+                        kb[k][u] = t;
+                    }
                 } else if (ACC == PRNU_ACC_F32) {
+                    const float I = (float)Iv[k][u];
                     ka[k][u] = fmaf(x[u], I, ka[k][u]);
-                    kb[k][u] = fmaf(I, I, kb[k][u]);
+                    if (!U8I) kb[k][u] = fmaf(I, I, kb[k][u]);
                 } else {
-                    sa[k][u] = fma((double)x[u], (double)I, sa[k][u]);
-                    sbb[k][u] = fma((double)I, (double)I, sbb[k][u]);
+                    const double I = (double)Iv[k][u];
+                    sa[k][u] = fma((double)x[u], I, sa[k][u]);
+                    if (!U8I) sbb[k][u] = fma(I, I, sbb[k][u]);
                 }
             }
         }
+    }
+    if constexpr (U8I) {
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                sbb[k][u] = (double)iq[k][u];
+                kb[k][u] = (float)iq[k][u];
+            }
     }
     // one read-modify-write of the accumulators per pixel: every load first,
     // then the sums, then the stores (out-of-image offsets read 0, store nothing)
