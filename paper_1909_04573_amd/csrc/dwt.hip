@@ -637,6 +637,19 @@ struct InvStage {
             for (int k = 0; k < PER; ++k) v[sbd][k] = lp[sbd * band + goff[k]];
         za = zero_approx;
     }
+    // fetch() as buffer loads: one descriptor per subband in scalar registers
+    // and 32-bit byte offsets, for subbands of fewer than 2^29 coefficients
+    __device__ __forceinline__ void fetch_buf(const float *lpp, int64_t band, bool zero_approx) {
+#pragma unroll
+        for (int sbd = 0; sbd < 4; ++sbd) {
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<float *>(lpp + sbd * band), 0, (int)(band * 4), 0x00020000);
+#pragma unroll
+            for (int k = 0; k < PER; ++k)
+                v[sbd][k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, goff[k] * 4u, 0, 0));
+        }
+        za = zero_approx;
+    }
     __device__ __forceinline__ void put(float *sb) const {
 #pragma unroll
         for (int sbd = 0; sbd < 4; ++sbd)
@@ -866,7 +879,8 @@ __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, floa
     InvStage<TAPS, TT> st;
     st.offsets(tid, a.wk, rmap, cmap);
     const int64_t band = (int64_t)a.hk * a.wk;
-    st.fetch(a.lvl + (int64_t)c * 4 * band, band, a.zero_approx != 0);
+    // the fold's frames are below 2^28 pixels: 32-bit offsets reach every subband
+    st.fetch_buf(a.lvl + (int64_t)c * 4 * band, band, a.zero_approx != 0);
     IT In[ITEMS][4];
     load_i(0, In);
     for (int fr = 0; fr < a.nb; ++fr) {
@@ -882,7 +896,7 @@ __device__ __forceinline__ void mle_body(const MleArgs &a, int tile, int c, floa
         st.put(sb);
         __syncthreads();
         if (fr + 1 < a.nb) {
-            st.fetch(a.lvl + (int64_t)((fr + 1) * C + c) * 4 * band, band, a.zero_approx != 0);
+            st.fetch_buf(a.lvl + (int64_t)((fr + 1) * C + c) * 4 * band, band, a.zero_approx != 0);
             load_i(fr + 1, In);
         }
         const int tf = opaque_tid();  // index arithmetic per frame, not live across the frame loop
