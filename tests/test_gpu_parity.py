@@ -280,6 +280,23 @@ def test_depth_one_u8_frames_read_in_place(dev):
     np.testing.assert_array_equal(down(B8), down(Bf))
 
 
+@pytest.mark.parametrize("mode", [prnu.ACC_F64, prnu.ACC_KAHAN_F32, prnu.ACC_F32])
+def test_depth_one_u8_intensity_energy_exact(dev, mode):
+    """At d = 1 on u8 frames B = sum_i I_i^2 is a sum of integers below 2^24
+    (33 frames, across the 32-frame fold batch): every accumulator mode holds
+    it exactly (the compensation plane stays zero)."""
+    _log(f"d=1 u8 B exact mode {mode}")
+    fr = _frames_for(33, 40, 72, 3, 12)
+    A, B = prnu.new_accumulators(3, 40, 72, mode, device=dev)
+    prnu.fingerprint_accumulate(up(fr, dev), 1, A, B, acc_mode=mode)
+    ref = np.sum(fr.astype(np.int64) ** 2, axis=0).transpose(2, 0, 1).astype(np.float64)
+    b = down(B).astype(np.float64)
+    if mode == prnu.ACC_KAHAN_F32:
+        np.testing.assert_array_equal(b[1], 0.0)
+        b = b[0]
+    np.testing.assert_array_equal(b, ref)
+
+
 def test_depth_one_equals_per_frame_residuals(dev):
     """d = 1 is the conventional estimator: A equals sum_i W_i I_i built from
     the standalone residual call on each frame."""
